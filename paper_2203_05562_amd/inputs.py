@@ -1,0 +1,179 @@
+"""Seeded synthetic inputs: soil-column lattices and their set-up parameters.
+
+This module is shared by the GPU path and by the tests' CPU oracle, so it holds
+none of the method's arithmetic: no families, shape tensors, gradients, return
+mapping, retention curve or force states.  It only lays points on a jittered
+cubic lattice, draws the seeded random numbers, and derives problem set-up
+constants (geostatic total stress, solid grain density, Perzyna viscosity)
+from the workload description.
+
+Workloads (3D stand-ins for the paper's 2D column-collapse examples of
+Section 4.2; the paper's own geometry, experimental data and figures are not
+available, so every input here is synthetic):
+
+    C0  8 x 8 x 16     =     1,024 points, seed 0, suction 20 kPa, FP64
+    C1  40 x 40 x 80   =   128,000 points, seeds 1.., suction U(10, 40) kPa, FP64
+    C2  80 x 80 x 160  = 1,024,000 points, seed 2, suction 20 kPa, mixed precision
+    C3  24 x 24 x 48   =    27,648 points, seed 3, suction 20 kPa, adjoint
+    C4  128 x 128 x 256 = 4,194,304 points, seed 4, suction 20 kPa, mixed + adjoint
+
+Lattice: index = ix + nx*(iy + ny*iz), z vertical, spacing dx = 0.01 m,
+x = (ix, iy, iz)*dx + U(-0.05, 0.05)*dx per component (drawn first from
+numpy.random.default_rng(seed)); horizon delta = 3.015 dx; the bottom layer
+iz = 0 is fixed; lateral faces are free from t = 0.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional
+
+import numpy as np
+
+DX = 0.01
+DELTA_OVER_DX = 3.015
+
+
+@dataclasses.dataclass(frozen=True)
+class ColumnConfig:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    seed: int
+    suction_kpa: Optional[float]   # None -> drawn U(10, 40) kPa after the jitter
+    steps: int
+    precision: str                  # "fp64" or "mixed"
+    checkpoint_every: int = 0
+
+    @property
+    def n_points(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+CONFIGS: Dict[str, ColumnConfig] = {
+    "C0": ColumnConfig("C0", 8, 8, 16, 0, 20.0, 200, "fp64"),
+    "C1": ColumnConfig("C1", 40, 40, 80, 1, None, 2000, "fp64"),
+    "C2": ColumnConfig("C2", 80, 80, 160, 2, 20.0, 1000, "mixed"),
+    "C3": ColumnConfig("C3", 24, 24, 48, 3, 20.0, 1000, "fp64", checkpoint_every=50),
+    "C4": ColumnConfig("C4", 128, 128, 256, 4, 20.0, 500, "mixed", checkpoint_every=25),
+}
+
+# Material constants.  Critical-state values (M, lambda, kappa, e0, tau,
+# density, gravity) are those of the workload description; elastic moduli,
+# over-consolidation ratio and retention-curve constants are the ones printed
+# for the paper's column-collapse example (Section 4.2).
+MATERIAL = dict(
+    K=25.0e6,          # bulk modulus [Pa]
+    mu=15.0e6,         # shear modulus [Pa]
+    M=1.2,             # slope of the critical state line
+    lam=0.1,           # compression index (lambda tilde)
+    kap=0.02,          # swell index (kappa tilde)
+    e0=0.8,            # initial void ratio
+    tau=1.0e-3,        # Perzyna relaxation time [s]
+    rho_sat=2000.0,    # bulk density of the column [kg/m^3]
+    rho_w=1000.0,      # water density [kg/m^3]
+    g=9.81,            # gravity [m/s^2]
+    ocr=1.25,          # over-consolidation ratio
+    a1=0.038, a2=3.49, n_vg=1.25,   # retention-curve constants
+    b1=0.0, b2=1.0,    # apparent pre-consolidation exponents (Eq. 45)
+)
+
+
+def default_params(cfg: ColumnConfig, suction_pa: float, **over) -> dict:
+    """Problem set-up constants for one column.
+
+    Set-up readings (not the method):
+      * rho_s: the stated density is the saturated bulk density, so the grain
+        density follows from the mixture rule at S_r = 1:
+        rho_s = (rho_sat - rho_w*phi0) / (1 - phi0).
+      * eta: the Perzyna coefficient of Eq. 43 carries units Pa^3 s; the
+        stated viscosity is a relaxation time tau, so eta = tau*K*p_ref^2
+        with p_ref = rho_sat*g*H + s, a fixed stress scale of the column.
+    """
+    m = dict(MATERIAL)
+    m.update(over)
+    phi0 = m["e0"] / (1.0 + m["e0"])
+    height = cfg.nz * DX
+    p_ref = m["rho_sat"] * m["g"] * height + suction_pa
+    return dict(
+        delta=DELTA_OVER_DX * DX,
+        K=m["K"], mu=m["mu"], M=m["M"], lam=m["lam"], kap=m["kap"],
+        eta=m["tau"] * m["K"] * p_ref * p_ref,
+        b1=m["b1"], b2=m["b2"],
+        rho_s=(m["rho_sat"] - m["rho_w"] * phi0) / (1.0 - phi0),
+        rho_w=m["rho_w"], a1=m["a1"], a2=m["a2"], n_vg=m["n_vg"],
+        g=(0.0, 0.0, -m["g"]),
+        dt=0.0,
+        newton_tol=1e-13, newton_maxit=50,
+        ocr=m["ocr"],
+    )
+
+
+def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
+                suction_kpa: Optional[float] = None, jitter: float = 0.05,
+                dims=None) -> dict:
+    """Return the seeded column: arrays in caller (lattice) order plus params.
+
+    Arrays (float64 unless stated):
+      x0 (N,3), v0 (N,3) zeros, vol0 (N,), phi0 (N,), suction (N,) [Pa],
+      fixed (N,) uint8, sig_geo (N,6) total K0 geostatic stress in Voigt
+      order (xx, yy, zz, yz, xz, xy), tension positive.
+    """
+    nx, ny, nz = dims if dims is not None else (cfg.nx, cfg.ny, cfg.nz)
+    seed = cfg.seed if seed is None else seed
+    rng = np.random.default_rng(seed)
+    n = nx * ny * nz
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    lat = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    jit = rng.uniform(-jitter, jitter, (n, 3)) if jitter > 0 else np.zeros((n, 3))
+    x0 = (lat + jit) * DX
+    if suction_kpa is None:
+        suction_kpa = cfg.suction_kpa
+    if suction_kpa is None:
+        suction_kpa = float(rng.uniform(10.0, 40.0))
+    s = suction_kpa * 1e3
+    prm = default_params(cfg, s)
+    m = MATERIAL
+    phi0 = m["e0"] / (1.0 + m["e0"])
+    # K0 geostatic total stress: sigma_zz = -rho g depth, sigma_h = K0 sigma_zz,
+    # K0 = nu/(1-nu) from the elastic moduli.
+    nu = (3 * m["K"] - 2 * m["mu"]) / (2 * (3 * m["K"] + m["mu"]))
+    k0 = nu / (1 - nu)
+    top = (nz - 0.5) * DX
+    szz = -m["rho_sat"] * m["g"] * (top - lat[:, 2] * DX)
+    sig = np.zeros((n, 6))
+    sig[:, 0] = k0 * szz
+    sig[:, 1] = k0 * szz
+    sig[:, 2] = szz
+    return dict(
+        n=n, dims=(nx, ny, nz), lattice=lat.astype(np.int64),
+        x0=np.ascontiguousarray(x0),
+        v0=np.zeros((n, 3)),
+        vol0=np.full(n, DX ** 3),
+        phi0=np.full(n, phi0),
+        suction=np.full(n, s),
+        fixed=(lat[:, 2] == 0).astype(np.uint8),
+        sig_geo=sig,
+        params=prm,
+        suction_kpa=suction_kpa,
+    )
+
+
+def random_velocity(n: int, seed: int, scale: float = 1e-2) -> np.ndarray:
+    """Seeded velocity field U(-scale, scale) [m/s] for one-step checks."""
+    return np.random.default_rng(seed).uniform(-scale, scale, (n, 3))
+
+
+def subsample_ids(n: int, every: int = 64) -> np.ndarray:
+    """Every `every`-th caller id, the 1/64 subsample of the mixed column."""
+    return np.arange(0, n, every, dtype=np.int64)
+
+
+def runout_objective_weights(lattice: np.ndarray, dims) -> dict:
+    """Index sets for the runout + settlement objective: the initial top layer
+    and the column axis.  Pure bookkeeping."""
+    nx, ny, nz = dims
+    top = np.nonzero(lattice[:, 2] == nz - 1)[0]
+    axis = np.array([(nx - 1) * 0.5 * DX, (ny - 1) * 0.5 * DX])
+    return dict(top=top, axis=axis, height=(nz - 0.5) * DX)

@@ -1,0 +1,550 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: integer
+lattice enumeration, closed forms, invariants, limits of the constitutive
+model, an independent scalar solver, the paper's printed values.  Citations
+name the section / equation of arXiv 2203.05562.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2203_05562_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DX = inputs.DX
+DELTA = inputs.DELTA_OVER_DX * DX
+D2_LATTICE = inputs.DELTA_OVER_DX ** 2          # delta^2 in units of dx^2
+
+
+def lattice_family():
+    """Integer offsets n != 0 with |n| <= 3.015 (Eq. 1 on the unit lattice)."""
+    return [n for n in itertools.product(range(-4, 5), repeat=3)
+            if n != (0, 0, 0) and sum(c * c for c in n) <= D2_LATTICE]
+
+
+def column_state(olib, dims, seed=0, jitter=0.05, suction_kpa=20.0):
+    cfg = inputs.CONFIGS["C0"]
+    col = inputs.make_column(cfg, seed=seed, suction_kpa=suction_kpa, jitter=jitter, dims=dims)
+    prm = olib.make_params(col["params"])
+    S = olib.init_column(col, prm, col["params"]["ocr"])
+    return col, prm, S
+
+
+def set_uniform_stress(S, sig6, pc, s_pa):
+    S["sig"][:] = np.asarray(sig6, float)
+    S["pc"][:] = pc
+    S["s"][:] = s_pa
+
+
+# ------------------------------------------------------------------ families --
+
+@pytest.mark.parametrize("dims,jit", [((8, 8, 16), 0.05), ((12, 12, 12), 0.05), ((10, 9, 11), 0.0)])
+def test_family_cells_equal_bruteforce(olib, dims, jit):
+    """Eq. 1: the cell-list search equals the O(N^2) definition bit for bit."""
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=7, jitter=jit, dims=dims)
+    r1, c1 = olib.families(col["x0"], DELTA)
+    r2, c2 = olib.families(col["x0"], DELTA, brute=True)
+    assert np.array_equal(r1, r2) and np.array_equal(c1, c2)
+
+
+def test_family_symmetric_and_lattice_counts(olib):
+    """Eq. 1 on the unjittered lattice: interior |H| = 122 with the shell
+    populations of the integer lattice; j in H_i <=> i in H_j."""
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=0, jitter=0.0, dims=(12, 12, 12))
+    row, colx = olib.families(col["x0"], DELTA)
+    lat = col["lattice"]
+    fam = lattice_family()
+    assert len(fam) == 122
+    pairs = set()
+    for i in range(col["n"]):
+        for j in colx[row[i]:row[i + 1]]:
+            pairs.add((i, int(j)))
+    assert all((j, i) in pairs for (i, j) in pairs)
+    interior = np.all((lat >= 4) & (lat <= 7), axis=1)
+    cnt = np.diff(row)
+    assert np.all(cnt[interior] == 122)
+    i = int(np.nonzero(interior)[0][0])
+    got = sorted(tuple(int(c) for c in lat[j] - lat[i]) for j in colx[row[i]:row[i + 1]])
+    assert got == sorted(fam)
+
+
+def test_family_jittered_interior_range(olib):
+    """With +-0.05 dx jitter the interior family keeps 105..118 members."""
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=0, dims=(14, 14, 14))
+    row, _ = olib.families(col["x0"], DELTA)
+    lat = col["lattice"]
+    interior = np.all((lat >= 4) & (lat <= 9), axis=1)
+    cnt = np.diff(row)[interior]
+    assert cnt.min() >= 100 and cnt.max() <= 122
+    assert 105 <= cnt.mean() <= 118
+
+
+# ------------------------------------------------------------ sub-horizons --
+
+def test_subhorizon_sizes_and_shape_tensor_on_lattice(olib):
+    """Eqs. 22-23 on the unjittered lattice: |S_ij| and K_ij of an interior
+    point equal the integer-lattice counts and sums V dx^2 sum n n^T."""
+    col, prm, S = column_state(olib, (16, 16, 16), jitter=0.0)
+    out = olib.bond_fields(S, prm, 0.0)
+    lat = col["lattice"]
+    fam = lattice_family()
+    famset = set(fam)
+    i = int(np.nonzero(np.all(lat == 8, axis=1))[0][0])
+    V = DX ** 3
+    shells = {}
+    for s in range(out["row"][i], out["row"][i + 1]):
+        j = int(out["col"][s])
+        nj = tuple(int(c) for c in lat[j] - lat[i])
+        members = [nk for nk in fam if sum((a - b) ** 2 for a, b in zip(nk, nj)) <= D2_LATTICE]
+        assert nj in famset and out["nsub"][s] == len(members)
+        Kint = np.zeros((3, 3))
+        for nk in members:
+            Kint += np.outer(nk, nk)
+        Kexp = V * DX * DX * Kint
+        Kv = out["K"][s]
+        Kfull = np.array([[Kv[0], Kv[5], Kv[4]], [Kv[5], Kv[1], Kv[3]], [Kv[4], Kv[3], Kv[2]]])
+        assert np.allclose(Kfull, Kexp, rtol=0, atol=1e-13 * np.abs(Kexp).max())
+        shells.setdefault(sum(c * c for c in nj), set()).add(len(members))
+    # shell populations quoted for the unjittered interior
+    assert shells[1] == {93} and shells[2] == {79} and shells[3] == {67} and shells[4] == {68}
+    assert shells[5] == {59} and shells[6] == {51} and shells[8] == {44} and shells[9] == {37, 43}
+
+
+# ---------------------------------------------------------- velocity gradient --
+
+def test_linear_field_reproduced_exactly(olib):
+    """Eqs. 19/57: for v = A x + c, every non-degenerate sub-horizon gradient
+    L_ij equals A (boundary points included), and the full-horizon volume
+    increment equals 1/det(I - dt A)."""
+    col, prm, S = column_state(olib, (8, 8, 10), seed=3)
+    rng = np.random.default_rng(11)
+    A = rng.normal(size=(3, 3))
+    c = rng.normal(size=3)
+    x = S["x0"] + S["u"]
+    S["v"][:] = x @ A.T + c
+    dt = 1e-3
+    out = olib.bond_fields(S, prm, dt)
+    act = out["active"] == 1
+    assert act.mean() > 0.99
+    L = out["L"][act].reshape(-1, 3, 3)
+    assert np.abs(L - A).max() <= 1e-11 * np.abs(A).max()
+    jd = 1.0 / np.linalg.det(np.eye(3) - dt * A)
+    assert np.allclose(out["Jd"], jd, rtol=1e-12, atol=0)
+
+
+def test_checkerboard_mode_invisible_to_full_horizon(olib):
+    """Eqs. 20-21: the checkerboard velocity mode on the unjittered lattice
+    gives a zero full-horizon gradient at interior points (J increment = 1)
+    while sub-horizon gradients of lens-asymmetric bonds see it."""
+    col, prm, S = column_state(olib, (14, 14, 14), jitter=0.0)
+    lat = col["lattice"]
+    eps = 1e-3
+    S["v"][:] = 0.0
+    S["v"][:, 0] = eps * (-1.0) ** lat.sum(axis=1)
+    out = olib.bond_fields(S, prm, 1e-3)
+    interior = np.all((lat >= 4) & (lat <= 9), axis=1)
+    assert np.abs(out["Jd"][interior] - 1.0).max() < 1e-12
+    Lmax = np.abs(out["L"]).reshape(-1, 9).max(axis=1)
+    i = int(np.nonzero(np.all(lat == 7, axis=1))[0][0])
+    sl = slice(out["row"][i], out["row"][i + 1])
+    assert Lmax[sl].max() > 1e-2 * eps / DX
+
+
+def test_objectivity_rigid_rotation(olib):
+    """Objectivity: a rigid velocity field v = W x + c (W skew) gives
+    D_ij = sym(L_ij) = 0, so the bond stress equals the point stress."""
+    col, prm, S = column_state(olib, (8, 8, 8), seed=5)
+    w = np.array([0.3, -0.7, 0.5])
+    W = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    x = S["x0"] + S["u"]
+    S["v"][:] = x @ W.T + np.array([0.1, 0.2, -0.3])
+    set_uniform_stress(S, [-12e3, -11e3, -15e3, 500.0, -300.0, 200.0], -40e3, 20e3)
+    out = olib.bond_fields(S, prm, 1e-4)
+    act = out["active"] == 1
+    L = out["L"][act].reshape(-1, 3, 3)
+    D = 0.5 * (L + L.transpose(0, 2, 1))
+    assert np.abs(D).max() <= 1e-12 * np.abs(W).max()
+    assert np.abs(out["sig"][act] - S["sig"][0]).max() <= 1e-9 * 15e3
+
+
+def test_frame_indifference_lattice_rotation(olib):
+    """A 90-degree lattice rotation Q of the whole input rotates the nodal
+    forces (f -> Q f) and the updated point stresses (sigma -> Q sigma Q^T)."""
+    col, prm, S = column_state(olib, (8, 8, 8), seed=9)
+    rng = np.random.default_rng(3)
+    S["v"][:] = rng.uniform(-0.05, 0.05, S["v"].shape)
+    out = olib.bond_fields(S, prm, 2e-5)
+    Q = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    S2 = olib.copy_state(S)
+    S2["x0"] = np.ascontiguousarray(S["x0"] @ Q.T)
+    S2["u"] = np.ascontiguousarray(S["u"] @ Q.T)
+    S2["v"] = np.ascontiguousarray(S["v"] @ Q.T)
+
+    def rot6(s6):
+        full = np.stack([s6[:, [0, 5, 4]], s6[:, [5, 1, 3]], s6[:, [4, 3, 2]]], axis=1)
+        r = Q @ full @ Q.T
+        return np.stack([r[:, 0, 0], r[:, 1, 1], r[:, 2, 2], r[:, 1, 2], r[:, 0, 2], r[:, 0, 1]], axis=1)
+
+    S2["sig"] = np.ascontiguousarray(rot6(S["sig"]))
+    out2 = olib.bond_fields(S2, prm, 2e-5)
+    assert np.array_equal(out["row"], out2["row"]) and np.array_equal(out["col"], out2["col"])
+    fscale = np.abs(out["f"]).max()
+    assert np.abs(out2["f"] - out["f"] @ Q.T).max() <= 1e-11 * fscale
+    assert np.abs(out2["sig_pt"] - rot6(out["sig_pt"])).max() <= 1e-9 * np.abs(out["sig_pt"]).max()
+
+
+# ------------------------------------------------------------------ forces --
+
+def test_internal_forces_sum_to_zero(olib):
+    """Eqs. 49-50: the assembled internal force is a pair sum antisymmetric in
+    (i, j), so its total vanishes for any state."""
+    col, prm, S = column_state(olib, (8, 8, 12), seed=2)
+    rng = np.random.default_rng(5)
+    S["v"][:] = rng.uniform(-0.1, 0.1, S["v"].shape)
+    S["sig"][:] += rng.uniform(-2e3, 2e3, S["sig"].shape)
+    out = olib.bond_fields(S, prm, 2e-5)
+    f = out["f"]
+    assert np.abs(f.sum(axis=0)).max() <= 1e-13 * np.abs(f).sum()
+
+
+def test_interior_patch_uniform_stress(olib):
+    """A uniform stress on the unjittered lattice leaves points at least
+    2 delta inside the body force-free: sub-horizons of bonds n and -n are
+    point reflections of each other (Eq. 33 with central symmetry)."""
+    col, prm, S = column_state(olib, (16, 16, 16), jitter=0.0)
+    set_uniform_stress(S, [-20e3, -15e3, -25e3, 3e3, -2e3, 1e3], -60e3, 20e3)
+    out = olib.bond_fields(S, prm, 0.0)
+    lat = col["lattice"]
+    deep = np.all((lat >= 7) & (lat <= 8), axis=1)
+    V = DX ** 3
+    scale = np.abs(out["T"]).max() * V * V * 122
+    assert np.abs(out["f"][deep]).max() <= 1e-12 * scale
+    assert np.abs(out["f"][~deep]).max() > 1e-6 * scale      # boundaries do feel it
+
+
+# ------------------------------------------------------ constitutive model --
+
+def mat_params(olib, **over):
+    cfg = inputs.CONFIGS["C0"]
+    prm = dict(inputs.default_params(cfg, 20e3))
+    prm.update(over)
+    return olib.make_params(prm)
+
+
+def test_return_map_elastic_is_hooke(olib):
+    """Section 3.2.1: inside the yield surface the update is the trial state,
+    Hooke's law in Lame form sigma_n + lambda tr(de) 1 + 2 mu de."""
+    prm = mat_params(olib)
+    sig_n = np.array([-30e3, -28e3, -35e3, 1e3, -2e3, 500.0])
+    de = np.array([1e-5, -2e-5, 3e-6, 4e-6, -1e-6, 2e-6])     # tensor (not engineering) shear
+    out, pc, it = olib.return_map(prm, 1e-5, sig_n, -80e3, de)
+    assert it == 0
+    lam = prm.K - 2.0 * prm.mu / 3.0
+    tr = de[:3].sum()
+    exp = sig_n + 2.0 * prm.mu * de
+    exp[:3] += lam * tr
+    assert np.allclose(out, exp, rtol=0, atol=1e-9 * np.abs(exp).max())
+    assert pc == -80e3
+
+
+def test_return_map_jacobian_matches_fd(olib):
+    """The analytic Newton tangent equals central differences of the
+    residuals of Eqs. 73-75 (relative 1e-7)."""
+    prm = mat_params(olib, b1=0.1, b2=1.02)
+    c = 1e-14
+    x = np.array([-30e3, 25e3, -40e3])
+    r0, A = olib.rm_residual(prm, c, -28e3, 27e3, -38e3, x)
+    for k in range(3):
+        h = 1e-6 * abs(x[k])
+        xp, xm = x.copy(), x.copy()
+        xp[k] += h
+        xm[k] -= h
+        rp, _ = olib.rm_residual(prm, c, -28e3, 27e3, -38e3, xp)
+        rm, _ = olib.rm_residual(prm, c, -28e3, 27e3, -38e3, xm)
+        fd = (rp - rm) / (2 * h)
+        assert np.allclose(A[:, k], fd, rtol=1e-6, atol=1e-7 * np.abs(A).max())
+
+
+def test_return_map_isotropic_rate_independent_limit(olib):
+    """Isotropic compression from a state on the yield surface (q = 0,
+    b1 = 0, b2 = 1): as eta -> 0 the backward-Euler path reaches the
+    rate-independent closed form p = p_c, p - p0 = K (eps_v - eps_vp),
+    p_c = p_c0 exp(-eps_vp / (lam - kap)) (Eqs. 41, 45, 46), independently of
+    the number of steps, and the error shrinks linearly with eta."""
+    from scipy.optimize import brentq
+    p0 = -50e3
+    n_inc, deps_v = 20, -2e-4
+    base = mat_params(olib)
+    lk = base.lam - base.kap
+    ev = n_inc * deps_v
+    g = lambda x: p0 + base.K * (ev - x) - p0 * math.exp(-x / lk)
+    xvp = brentq(g, ev, 0.0, xtol=1e-18)
+    p_exact = p0 * math.exp(-xvp / lk)
+    errs = []
+    for eta in (1e15, 1e14):
+        prm = mat_params(olib, eta=eta)
+        sig = np.array([p0, p0, p0, 0.0, 0.0, 0.0])
+        pc = p0
+        for _ in range(n_inc):
+            de = np.array([deps_v / 3] * 3 + [0.0] * 3)
+            sig, pc, it = olib.return_map(prm, 1.0, sig, pc, de)
+            assert it > 0
+        assert abs(sig[0] - sig[2]) < 1e-9 * abs(p0)
+        errs.append(abs(sig[0] - p_exact) / abs(p_exact))
+    assert errs[1] < 5e-4 and 7.0 < errs[0] / errs[1] < 13.0
+
+
+def test_return_map_isochoric_shear_reaches_critical_state(olib):
+    """Drained isochoric shearing drives the state to the critical state line:
+    q/|p| -> M and the viscoplastic volume change vanishes (Eqs. 40, 43, 46)."""
+    prm = mat_params(olib, eta=1e11)
+    sig = np.array([-40e3, -40e3, -40e3, 0.0, 0.0, 0.0])
+    pc = -45e3
+    de = np.array([0.0, 0.0, 0.0, 0.0, 0.0, 2e-5])
+    pcs = []
+    for _ in range(1500):
+        sig, pc, it = olib.return_map(prm, 1e-3, sig, pc, de)
+        assert it >= 0
+        pcs.append(pc)
+    p = sig[:3].mean()
+    s = sig.copy()
+    s[:3] -= p
+    q = math.sqrt(1.5 * (s[:3] @ s[:3] + 2 * s[3:] @ s[3:]))
+    assert abs(q / abs(p) - prm.M) < 2e-3
+    assert abs(pcs[-1] - pcs[-2]) < 1e-6 * abs(pc)
+
+
+def test_return_map_independent_bisection_solver(olib):
+    """The Newton solution equals a different solver of the same equations:
+    q eliminated in closed form, then nested bisection on (p, p_c)."""
+    prm = mat_params(olib, eta=1e12, b1=0.0, b2=1.0)
+    sig_n = np.array([-30e3, -30e3, -34e3, 0.0, 0.0, 2e3])
+    pc_n = -36e3
+    de = np.array([-2e-4, 1e-4, -3e-4, 0.0, 5e-5, 2e-4])
+    dt = 1e-3
+    out, pc, it = olib.return_map(prm, dt, sig_n, pc_n, de)
+    assert it > 0
+    K, mu, M, lk, c = prm.K, prm.mu, prm.M, prm.lam - prm.kap, dt / prm.eta
+    tr = de[:3].sum()
+    st = sig_n.copy()
+    st[:3] += K * tr
+    dev = de.copy()
+    dev[:3] -= tr / 3
+    st += 2 * mu * dev
+    ptr = st[:3].mean()
+    s = st.copy()
+    s[:3] -= ptr
+    qtr = math.sqrt(1.5 * (s[:3] @ s[:3] + 2 * s[3:] @ s[3:]))
+
+    def q_of(p, P):
+        # r2 = 0 is a cubic in q for given (p, P); bisection on q in [0, qtr]
+        lo, hi = 0.0, qtr
+        for _ in range(200):
+            q = 0.5 * (lo + hi)
+            f = q * q / M ** 2 + p * (p - P)
+            val = q - qtr + 3 * mu * c * f * 2 * q / M ** 2
+            lo, hi = (q, hi) if val < 0 else (lo, q)
+        return 0.5 * (lo + hi)
+
+    def pc_of(p):
+        # r3 = 0 for p_c given p (q eliminated): bisection on log scale
+        lo, hi = pc_n * 4.0, pc_n * 0.25
+        for _ in range(200):
+            P = 0.5 * (lo + hi)
+            q = q_of(p, P)
+            f = q * q / M ** 2 + p * (p - P)
+            val = P - pc_n * math.exp(-c * f * (2 * p - P) / lk)
+            lo, hi = (P, hi) if val < 0 else (lo, P)
+        return 0.5 * (lo + hi)
+
+    def r1(p):
+        P = pc_of(p)
+        q = q_of(p, P)
+        f = q * q / M ** 2 + p * (p - P)
+        return p - ptr + K * c * f * (2 * p - P)
+
+    from scipy.optimize import brentq
+    p = brentq(r1, ptr * 3.0, 0.0, xtol=1e-10)
+    P = pc_of(p)
+    q = q_of(p, P)
+    pn = out[:3].mean()
+    sn = out.copy()
+    sn[:3] -= pn
+    qn = math.sqrt(1.5 * (sn[:3] @ sn[:3] + 2 * sn[3:] @ sn[3:]))
+    assert abs(pn - p) < 1e-9 * abs(p)
+    assert abs(qn - q) < 1e-8 * abs(p)
+    assert abs(pc - P) < 1e-9 * abs(P)
+
+
+# -------------------------------------------------------- retention curve --
+
+def test_swrc_printed_zero_suction_and_shape(olib):
+    """Eq. 15: S_r(s = 0) = 1 as printed (Section 4.2.2); S_r decreases with
+    suction, stays in (0, 1], and its log-slope tends to -(n - 1) at large
+    suction (this fixes the sign of the garbled exponent)."""
+    gold = json.load(open(os.path.join(HERE, "golden", "paper_values.json")))["swrc_pairs"]
+    prm = mat_params(olib)
+    phi = 0.8 / 1.8
+    assert olib.swrc(prm, 1.0, phi, gold["suction_kpa"][0] * 1e3) == gold["Sr"][0]
+    s = np.logspace(2, 9, 40)
+    sr = np.array([olib.swrc(prm, 1.0, phi, x) for x in s])
+    assert np.all(np.diff(sr) < 0) and np.all(sr > 0) and np.all(sr <= 1)
+    slope = math.log(sr[-1] / sr[-2]) / math.log(s[-1] / s[-2])
+    assert abs(slope + (prm.n_vg - 1.0)) < 1e-3
+    # wetter when compacted: smaller J -> smaller void ratio -> larger S_r
+    assert olib.swrc(prm, 0.9, 1 - (1 - phi) / 0.9, 20e3) > olib.swrc(prm, 1.0, phi, 20e3)
+
+
+# ---------------------------------------------------------------- Newmark --
+
+def test_free_fall_is_exact(olib):
+    """Central differences (beta1 = 1/2, beta2 = 0, Section 3.2) integrate a
+    constant acceleration exactly: isolated points fall as x0 + v0 t + g t^2/2."""
+    n = 27
+    g = np.stack(np.meshgrid(np.arange(3), np.arange(3), np.arange(3), indexing="ij"), -1).reshape(-1, 3)
+    S = olib.empty_state(n)
+    S["x0"][:] = g * 10 * DELTA
+    S["vol"][:] = DX ** 3
+    S["phi"][:] = 0.4
+    S["J"][:] = 1.0
+    S["Sr"][:] = 1.0
+    S["mass"][:] = 2000 * DX ** 3
+    S["pc"][:] = -1e4
+    v0 = np.random.default_rng(0).uniform(-1, 1, (n, 3))
+    S["v"][:] = v0
+    prm = mat_params(olib)
+    S["a"][:] = np.array(prm.g[:])
+    prm.dt = 1e-4
+    nsteps = 50
+    rc, E, st = olib.step(S, prm, nsteps)
+    assert rc == 0
+    t = nsteps * prm.dt
+    exp_u = v0 * t + 0.5 * np.array(prm.g[:]) * t * t
+    assert np.allclose(S["u"], exp_u, rtol=1e-12, atol=1e-15)
+    assert np.allclose(S["v"], v0 + np.array(prm.g[:]) * t, rtol=1e-12, atol=1e-15)
+
+
+def test_dt_crit_closed_form_on_lattice(olib):
+    """Eq. 65 with C/|zeta| and C = 18K/(pi delta^4): on the unjittered
+    lattice the minimum sits at interior points, sum_j 1/|n| = 56.8778..."""
+    col, prm, S = column_state(olib, (10, 10, 10), jitter=0.0)
+    s_inv = sum(1.0 / math.sqrt(sum(c * c for c in n)) for n in lattice_family())
+    C = 18 * prm.K / (math.pi * prm.delta ** 4)
+    V = DX ** 3
+    exp = math.sqrt(2 * (1 - S["phi"][0]) * prm.rho_s * DX / (V * C * s_inv))
+    assert abs(olib.dt_crit(S, prm) - exp) <= 1e-12 * exp
+
+
+def test_solid_mass_conserved_and_porosity_closed_form(olib):
+    """Eqs. 16 and 48: rho_s (1 - phi) V is constant point by point, and
+    phi follows 1 - (1 - phi0)/J."""
+    col, prm, S = column_state(olib, (6, 6, 10), seed=4)
+    prm.dt = 0.5 * olib.dt_crit(S, prm)
+    m0 = prm.rho_s * (1 - S["phi"]) * S["vol"]
+    phi0 = S["phi"].copy()
+    rc, E, st = olib.step(S, prm, 60)
+    assert rc == 0
+    m1 = prm.rho_s * (1 - S["phi"]) * S["vol"]
+    assert np.abs(m1 - m0).max() <= 1e-13 * m0.max()
+    assert np.allclose(S["phi"], 1 - (1 - phi0) / S["J"], rtol=0, atol=1e-14)
+    assert np.abs(S["J"] - 1).max() > 1e-6
+
+
+@pytest.mark.slow
+def test_energy_balance_and_trip(olib):
+    """Eq. 69 with eps = 1e-2 holds over the 200-step 8x8x16 column, and a
+    step five times the critical one violates it."""
+    col, prm, S = column_state(olib, (8, 8, 16), seed=0)
+    dtc = olib.dt_crit(S, prm)
+    prm.dt = 0.5 * dtc
+    S0 = olib.copy_state(S)
+    E = np.zeros(3)
+    for k in range(20):
+        rc, E, st = olib.step(S, prm, 10, E)
+        assert rc == 0
+        if k >= 1:
+            assert abs(E[0] + E[2] - E[1]) <= 1e-2 * np.abs(E).max()
+    prm.dt = 5.0 * dtc
+    S = S0
+    E = np.zeros(3)
+    tripped = False
+    for k in range(20):
+        rc, E, st = olib.step(S, prm, 10, E)
+        if rc != 0 or not np.all(np.isfinite(E)) or abs(E[0] + E[2] - E[1]) > 1e-2 * np.abs(E).max():
+            tripped = True
+            break
+    assert tripped
+
+
+def test_initial_state_on_scaled_yield_surface(olib):
+    """Set-up: effective stress = total - S_r0 s 1 (Eq. 2 with p_w = -s) and
+    the pre-consolidation pressure is OCR times that of the yield surface
+    through the initial stress (Eq. 40)."""
+    col, prm, S = column_state(olib, (4, 4, 6))
+    ocr = col["params"]["ocr"]
+    sig = S["sig"]
+    assert np.allclose(sig[:, :3] + (S["Sr"] * S["s"])[:, None], col["sig_geo"][:, :3], rtol=1e-14, atol=1e-9)
+    p = sig[:, :3].mean(axis=1)
+    dev = sig.copy()
+    dev[:, :3] -= p[:, None]
+    q2 = 1.5 * ((dev[:, :3] ** 2).sum(1) + 2 * (dev[:, 3:] ** 2).sum(1))
+    pcs = S["pc"] / ocr
+    f = q2 / prm.M ** 2 + p * (p - pcs)
+    assert np.abs(f).max() <= 1e-9 * (p ** 2).max()
+
+
+# ------------------------------------------------------- dual numbers --
+
+def test_dual_tangent_matches_central_differences(olib):
+    """The forward-mode (dual number) oracle is the derivative of the oracle:
+    central differences of 8 steps in M, eta and the initial velocity, taken
+    only where both perturbed runs keep identical families, sub-horizons and
+    elastic/plastic branches (the step map is piecewise smooth)."""
+    col, prm, S = column_state(olib, (6, 6, 8), seed=1)
+    prm.dt = 0.5 * olib.dt_crit(S, prm)
+    rng = np.random.default_rng(2)
+    S["v"][:] = rng.uniform(-0.02, 0.02, S["v"].shape)
+    S["v"][S["fixed"] == 1] = 0.0
+    dv = rng.normal(size=S["v"].shape)
+    dv[S["fixed"] == 1] = 0.0
+    # (name, dparam tangent, velocity tangent, relative step)
+    cases = [("M", np.array([1.0, 0, 0, 0]), None, 1e-4),
+             ("eta", np.array([0, 0, 0, prm.eta]), None, 1e-4),
+             ("v0", np.zeros(4), dv, 1e-6)]
+    nst = 8
+    for name, dpar, dvel, hs in cases:
+        dS = olib.empty_state(S["x0"].shape[0])
+        if dvel is not None:
+            dS["v"][:] = dvel
+        S1 = olib.copy_state(S)
+        rc, _, st0 = olib.step_dual(S1, dS, prm, dpar, nst)
+        assert rc == 0
+        res, sts = [], []
+        for sgn in (+1, -1):
+            S2 = olib.copy_state(S)
+            p2 = olib.make_params(olib.params_dict(prm))
+            if name == "M":      # tangent dM = 1
+                p2.M += sgn * hs * prm.M
+                scale = hs * prm.M
+            elif name == "eta":  # tangent d(eta) = eta, i.e. per unit relative change
+                p2.eta += sgn * hs * prm.eta
+                scale = hs
+            else:
+                S2["v"] += sgn * hs * dvel
+                scale = hs
+            rc, _, st = olib.step(S2, p2, nst)
+            assert rc == 0
+            res.append(S2)
+            sts.append(st)
+        for key in ("n_bonds", "n_triples", "n_plastic"):
+            assert sts[0][key] == sts[1][key] == st0[key], (name, key)
+        for fld in ("u", "v", "sig", "pc"):
+            fd = (res[0][fld] - res[1][fld]) / (2 * scale)
+            tan = dS[fld]
+            err = np.linalg.norm(fd - tan) / max(np.linalg.norm(tan), 1e-300)
+            assert err < 1e-5, (name, fld, err)
