@@ -1,0 +1,174 @@
+/* ulppm.h -- C ABI of the MI355X (gfx950) library for the per-step bond loop of
+ * updated Lagrangian unsaturated periporomechanics (Menon & Song, arXiv
+ * 2203.05562): families in the deformed configuration, bond-associated
+ * sub-horizon shape tensors and velocity gradients, the critical-state
+ * Perzyna update of the effective force state under constant suction, the
+ * nodal force gather, and the central-difference Newmark update.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All state arrays are caller-owned DEVICE memory (e.g. torch tensors on
+ *   cuda:0), FP64, structure-of-arrays, length n, indexed by the caller's
+ *   point ids.  The library never frees or reallocates them.
+ * - Symmetric tensors (stress) are six separate arrays in Voigt order
+ *   (xx, yy, zz, yz, xz, xy); tension positive (Section 1 of the paper),
+ *   pore-water pressure p_w = -s with suction s >= 0 [Pa].
+ * - The context owns only its scratch (cell lists, families, reverse-bond
+ *   index, bond force states, reduction partials), sized at ulppm_create
+ *   for n_points and max_family members per family.
+ * - Every call enqueues its kernels on the context's HIP stream, in order;
+ *   a call synchronises that stream only where it must read device results
+ *   back to the host (error counters, reports, bond counts).
+ * - Return values are ulppm_status codes.  Kernels never trap: they raise
+ *   device counters that the host turns into codes, with text available from
+ *   ulppm_last_error.  After an error the state is finite or flagged but
+ *   otherwise unspecified; restore it from a copy.
+ * - One context per host thread / stream; no global state.
+ */
+#ifndef ULPPM_H
+#define ULPPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ulppm_ctx ulppm_ctx;
+
+typedef enum {
+  ULPPM_OK = 0,
+  ULPPM_E_ARG = -1,       /* bad argument (NULL pointer, size mismatch, n out of range) */
+  ULPPM_E_CAPACITY = -2,  /* a family exceeded max_family, or col_cap too small */
+  ULPPM_E_NOCONV = -4,    /* Newton of the return map did not converge (Section 3.2.1) */
+  ULPPM_E_NONFINITE = -5, /* NaN/Inf produced in velocities or accelerations */
+  ULPPM_E_ENERGY = -6,    /* energy balance check of Eq. 69 failed */
+  ULPPM_E_HIP = -7        /* a HIP runtime call failed */
+} ulppm_status;
+
+enum { ULPPM_FP64 = 0, ULPPM_MIXED = 1 };
+
+/* Material and integration parameters, copied by value on every call. */
+typedef struct {
+  double delta;                 /* horizon, constant in the current configuration (Eq. 1) [m] */
+  double K, mu;                 /* elastic bulk and shear moduli (Eq. 41) [Pa] */
+  double M;                     /* slope of the critical state line (Eq. 40) */
+  double lam, kap;              /* compression / swell indices (Eq. 46) */
+  double eta;                   /* Perzyna viscosity coefficient (Eq. 43) [Pa^3 s] */
+  double b1, b2;                /* apparent pre-consolidation exponents (Eq. 45) */
+  double rho_s, rho_w;          /* solid grain and water densities (Eqs. 3, 48) [kg/m^3] */
+  double a1, a2, n_vg;          /* retention-curve constants (Eq. 15), suction in kPa */
+  double g[3];                  /* gravity [m/s^2] */
+  double dt;                    /* time step [s] */
+  double newton_tol;            /* relative tolerance of the return-map Newton */
+  int32_t newton_maxit;         /* Newton iteration cap */
+  int32_t precision;            /* ULPPM_FP64 or ULPPM_MIXED */
+  int32_t energy_check;         /* nonzero: check Eq. 69 at the end of ulppm_step */
+  int32_t pad;
+  double energy_tol;            /* epsilon of Eq. 69 (the paper uses ~1e-2) */
+} ulppm_params;
+
+/* Point state: caller-owned device arrays of length n (SoA). */
+typedef struct {
+  int64_t n;
+  double *x0[3];                /* initial positions (read only) */
+  double *u[3], *uc[3];         /* displacement and its Kahan compensation term */
+  double *v[3], *a[3];          /* velocity, acceleration */
+  double *vol, *phi, *J;        /* current volume, porosity, volume ratio */
+  double *Sr, *mass, *s;        /* degree of saturation, lumped mass, suction [Pa] (read only) */
+  double *sig[6];               /* effective stress (Voigt), the point history */
+  double *pc;                   /* saturated pre-consolidation pressure p_c < 0, point history */
+  const uint8_t *fixed;         /* nonzero = fixed point (v = a = 0) */
+} ulppm_state;
+
+/* Host-side report of the last ulppm_step / ulppm_forces call. */
+typedef struct {
+  double W_int, W_ext, W_kin;   /* energies of Eqs. 66-68, accumulated since create/reset */
+  int64_t n_bonds;              /* directed bonds of the last step (sum of family sizes) */
+  int64_t n_degenerate;         /* bonds with |S_ij| < 3 or singular K_ij (inactive), summed */
+  int64_t n_plastic;            /* bond updates that took the viscoplastic branch, summed */
+  int64_t max_newton;           /* largest Newton iteration count */
+  int64_t n_noconv;             /* Newton failures, summed */
+  int64_t n_tests;              /* sub-horizon membership tests (sum |H_i|^2), summed */
+  int64_t n_triples;            /* sub-horizon members visited (sum |S_ij|), summed */
+  int64_t max_family;           /* largest family of the last rebuild */
+  int64_t steps;                /* steps taken by the call */
+} ulppm_report;
+
+/* Create a context for up to n_points points and max_family members per family
+ * (0 selects 256).  hip_stream is a hipStream_t (NULL = the null stream).
+ * Allocates all scratch now; no entry point allocates afterwards.
+ * Errors: ULPPM_E_ARG (n_points <= 0 or > 2^31-1, max_family > 1024),
+ * ULPPM_E_HIP (allocation failed). */
+int ulppm_create(ulppm_ctx **out, int64_t n_points, int32_t max_family, void *hip_stream);
+
+/* Release the context's scratch.  Never touches caller memory. */
+int ulppm_destroy(ulppm_ctx *ctx);
+
+/* Text of the last error on this context (static storage inside the context). */
+const char *ulppm_last_error(const ulppm_ctx *ctx);
+
+/* Initial conditions of the explicit scheme (Algorithm 2, set-up and initial
+ * acceleration).  On entry sig holds the TOTAL stress, phi the initial
+ * porosity, vol the initial volume, s the suction, v the initial velocity.
+ * On return: u = uc = 0, J = 1, Sr from Eq. 15, sig = effective stress
+ * total - Sr s 1 (Eq. 2 with p_w = -s), pc the pre-consolidation pressure of
+ * the yield surface (Eq. 40) through that stress scaled by ocr and inverted
+ * through Eq. 45, mass from Eq. 48, and a = f/mass + g with the nodal force of
+ * Algorithm 1 at bond stress = point stress (fixed points: a = 0).
+ * Energies are reset to zero.  Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_HIP. */
+int ulppm_init_state(ulppm_ctx *ctx, ulppm_state *state, const ulppm_params *p, double ocr);
+
+/* Critical time step of Eq. 65, read as sqrt(2(1-phi) rho_s / sum_j V_j C/|zeta_ij|)
+ * with the bond micro-modulus C = 18K/(pi delta^4); the minimum over points with a
+ * non-empty family at the current positions x0+u is written to *dt_out (host).
+ * Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_HIP. */
+int ulppm_dt_crit(ulppm_ctx *ctx, const ulppm_state *state, const ulppm_params *p, double *dt_out);
+
+/* Neighbour search of Algorithm 1 (Eq. 1 with a constant horizon in the
+ * current configuration): family H_i = { j != i : |x_j - x_i| <= delta } at
+ * x = x0 + u, with the squared distance rounded as ((dx^2 + dy^2) + dz^2), no
+ * fused multiply-add.  Builds the context's internal CSR and reverse-bond
+ * index.  If row_ptr (n+1, device int64) is non-NULL the families are exported
+ * in the caller's ids, rows ascending; col (device int32, col_cap entries) is
+ * filled when non-NULL and large enough.  *n_bonds_out (host) receives the bond
+ * count.  Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY (family > max_family or
+ * col_cap < bonds), ULPPM_E_HIP. */
+int ulppm_build_families(ulppm_ctx *ctx, const ulppm_state *state, const ulppm_params *p,
+                         int64_t *row_ptr, int32_t *col, int64_t col_cap, int64_t *n_bonds_out);
+
+/* Algorithm 1 alone at the current state, without mutating it: families at
+ * x0 + u; sub-horizon shape tensors (Eq. 23) and velocity gradients (Eq. 57)
+ * from the velocities v; strain increment dt_inc * sym(L_ij) (Eqs. 26, 59);
+ * bond stress from the Perzyna return map (Section 3.2.1), or equal to the
+ * point stress when dt_inc == 0; force states T_ij (Eqs. 32, 51, 53); nodal
+ * force f_i = sum_j (T_ij - T_ji) V_i V_j (Eqs. 49-50 with the sign of Eq. 33)
+ * written to f[3] (device, length n each).  T_out, if non-NULL, receives the
+ * bond force states as three device arrays of length n_bonds (x, y, z), in the
+ * CSR order of ulppm_build_families.  rep (host) may be NULL.
+ * Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_NOCONV, ULPPM_E_HIP. */
+int ulppm_forces(ulppm_ctx *ctx, const ulppm_state *state, const ulppm_params *p, double dt_inc,
+                 double *f[3], double *T_out[3], ulppm_report *rep);
+
+/* Algorithm 2, n_steps explicit central-difference Newmark steps (beta1 = 1/2,
+ * beta2 = 0, Eqs. 60-64), state updated in place.  Each step: velocity
+ * predictor and boundary conditions; displacement with Kahan compensation;
+ * family rebuild; Algorithm 1 with dt_inc = dt (volume change from the
+ * full-horizon gradient, Eqs. 16-17; saturation Eq. 15; mass Eq. 48; point
+ * history = volume-weighted mean of its bond states); acceleration a = f/M + g
+ * (Eq. 62 with the sign of Eq. 33); velocity corrector (Eq. 63); energy
+ * increments of Eqs. 66-68.  rep (host) may be NULL.  With p->energy_check the
+ * balance of Eq. 69 is checked after the last step (ULPPM_E_ENERGY).
+ * Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_NOCONV, ULPPM_E_NONFINITE,
+ * ULPPM_E_ENERGY, ULPPM_E_HIP. */
+int ulppm_step(ulppm_ctx *ctx, ulppm_state *state, const ulppm_params *p, int32_t n_steps,
+               ulppm_report *rep);
+
+/* Zero the accumulated energies W_int, W_ext (W_kin is recomputed each step). */
+int ulppm_reset_energy(ulppm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ULPPM_H */

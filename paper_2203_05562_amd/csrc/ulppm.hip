@@ -1,0 +1,1447 @@
+// ulppm.hip -- gfx950 kernels and C ABI for the per-step bond loop of updated
+// Lagrangian unsaturated periporomechanics (Menon & Song, arXiv 2203.05562).
+//
+// One explicit central-difference step (Algorithm 2 driving Algorithm 1):
+//   k_predict   velocity predictor, boundary conditions, Kahan-compensated
+//               displacement, positions (Eqs. 60-61, 64)
+//   family build cell list -> one wave per point tests the 27 neighbour cells
+//               with the exact FP64 distance predicate, sorts its row, then a
+//               scan turns rows into CSR and a binary search builds rev[]
+//               (Eq. 1; Algorithm 1, neighbour search)
+//   k_bond      one workgroup per point i: the family of i is staged in LDS;
+//               the full-horizon sums give the volume change, porosity,
+//               saturation and mass of i (Eqs. 5, 8, 15-17, 48); then one lane
+//               per bond (i,j) streams every k in H_i from LDS (broadcast
+//               reads), tests k in S_ij exactly and accumulates the
+//               sub-horizon shape tensor, velocity-gradient numerator and
+//               volume (Eqs. 22-23, 25, 55, 57); inverts K_ij in FP64, forms
+//               the strain increment, runs the Perzyna return map
+//               (Section 3.2.1) and writes the force state T_ij (Eqs. 32, 51,
+//               53); wave reductions give the point history average.
+//   k_gather    one wave per point: f_i = sum_j (T_ij - T_ji) V_i V_j through
+//               rev[] (no atomics), acceleration, velocity corrector, energy
+//               partials (Eqs. 49-50, 62-63, 66-68)
+//
+// Every kernel is stream-ordered on the context's stream.  No kernel traps;
+// failures raise device counters.  Memory: all scratch is allocated at
+// create; the state lives in caller-owned SoA device arrays.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/ulppm.h"
+
+namespace {
+
+constexpr int kBondThreads = 128;   // one workgroup per point, one lane per bond
+constexpr int kWave = 64;
+constexpr int kScanChunk = 2048;    // elements per block in the scans (256 x 8)
+// Regions of the reduction-partials buffer (doubles).
+constexpr int64_t kPartPred = 0;        // predictor energy partials, 2 x <= 2048 blocks
+constexpr int64_t kPartRed = 4096;      // bounding box (6 x <= 1024) or dt_crit (<= 1024)
+constexpr int64_t kPartGather = 10240;  // gather energy partials, 3 per block
+
+// Device counters, zeroed at the start of every API call.
+enum Ctr {
+  C_DEGEN = 0, C_PLASTIC, C_MAXNEWTON, C_NOCONV, C_TESTS, C_TRIPLES, C_OVERFLOW,
+  C_NONFINITE, C_MAXFAM, C_NCOUNT = 16
+};
+
+struct DevParams {
+  double delta, d2;
+  double K, mu, M, lam, kap, eta, b1, b2;
+  double rho_s, rho_w, a1, a2, n_vg;
+  double g0, g1, g2;
+  double dt;
+  double newton_tol;
+  int newton_maxit;
+};
+
+struct Grid {                 // cell grid over the current bounding box
+  double lo0, lo1, lo2, cs;
+  int64_t d0, d1, d2, ncell;
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs of the chip, each with
+// its own L2.  Give each XCD a contiguous range of points so that the
+// neighbour data a block gathers is mostly resident in that XCD's L2.
+// The grid is launched with 8*per blocks; ids >= n are idle.
+__device__ __forceinline__ int64_t xcd_point(int64_t b, int64_t per) {
+  return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ long long wave_sum_i(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ long long wave_max_i(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    long long w = __shfl_xor(v, o, kWave);
+    v = v > w ? v : w;
+  }
+  return v;
+}
+
+// Exact squared distance, rounded as ((dx^2 + dy^2) + dz^2) with no fused
+// multiply-add, compared with delta^2.  Decides family (Eq. 1) and
+// sub-horizon (Eq. 22) membership identically on every device.
+__device__ __forceinline__ bool within(double ax, double ay, double az, double bx, double by,
+                                       double bz, double d2) {
+#pragma clang fp contract(off)
+  double dx = bx - ax, dy = by - ay, dz = bz - az;
+  double r2 = (dx * dx + dy * dy) + dz * dz;
+  return r2 <= d2;
+}
+
+__device__ __forceinline__ double exact_r2(double ax, double ay, double az, double bx, double by,
+                                           double bz) {
+#pragma clang fp contract(off)
+  double dx = bx - ax, dy = by - ay, dz = bz - az;
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// ---------------------------------------------------------------- scans --
+// Exclusive prefix sum of int32 counts into int64 offsets; out[n] = total.
+
+__global__ void k_scan_blocks(const int32_t* __restrict__ cnt, int64_t n, int64_t* __restrict__ out,
+                              int64_t* __restrict__ bsum) {
+  __shared__ int64_t s[256];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  int64_t loc[8];
+  int64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    int64_t e = base + threadIdx.x * 8 + k;
+    int64_t c = e < n ? (int64_t)cnt[e] : 0;
+    loc[k] = acc;
+    acc += c;
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    int64_t t = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int64_t pre = threadIdx.x ? s[threadIdx.x - 1] : 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    int64_t e = base + threadIdx.x * 8 + k;
+    if (e < n) out[e] = pre + loc[k];
+  }
+  if (threadIdx.x == 255) bsum[blockIdx.x] = s[255];
+}
+
+__global__ void k_scan_top(int64_t* __restrict__ bsum, int64_t nb, int64_t* __restrict__ out, int64_t n) {
+  __shared__ int64_t s[1024];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nb; base += 1024) {
+    int64_t e = base + threadIdx.x;
+    int64_t v = e < nb ? bsum[e] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      int64_t t = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (e < nb) bsum[e] = carry + s[threadIdx.x] - v;   // exclusive block offset
+    int64_t tot = s[1023];
+    __syncthreads();
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ boff) {
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  const int64_t add = boff[blockIdx.x];
+  for (int k = threadIdx.x; k < kScanChunk; k += blockDim.x) {
+    int64_t e = base + k;
+    if (e < n) out[e] += add;
+  }
+}
+
+template <class T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// ------------------------------------------------------------ predictor --
+
+// Velocity predictor v_half = v + (dt/2) a (Eq. 60, beta1 = 1/2, with the step
+// size restored), fixed points v_half = 0 (boundary conditions), displacement
+// u += dt v_half (Eqs. 61/64 with beta2 = 0) with Kahan compensation, and
+// positions x = x0 + u.  Rounded exactly as written (no contraction), so a
+// state gives bit-identical positions on every device.  Also saves V^n and
+// the first half of the energy increments (old force f^n = M (a - g)).
+__global__ void k_predict(ulppm_state S, DevParams P, double* __restrict__ x, double* __restrict__ vh,
+                          double* __restrict__ vol_n, double* __restrict__ epart) {
+#pragma clang fp contract(off)
+  const int64_t n = S.n;
+  const double dt = P.dt, hdt = 0.5 * P.dt;
+  const double g[3] = {P.g0, P.g1, P.g2};
+  double eint = 0.0, eext = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool fx = S.fixed[i] != 0;
+    const double m = S.mass[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double a = S.a[c][i];
+      const double vhalf = fx ? 0.0 : S.v[c][i] + hdt * a;
+      vh[c * n + i] = vhalf;
+      const double u = S.u[c][i], uc = S.uc[c][i];
+      const double y = dt * vhalf - uc;
+      const double t = u + y;
+      S.uc[c][i] = (t - u) - y;
+      S.u[c][i] = t;
+      x[c * n + i] = S.x0[c][i] + t;
+      if (!fx) {
+        eint -= hdt * vhalf * (m * (a - g[c]));
+        eext += hdt * vhalf * m * g[c];
+      }
+    }
+    vol_n[i] = S.vol[i];
+  }
+  __shared__ double r[2][4];
+  eint = wave_sum(eint);
+  eext = wave_sum(eext);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) { r[0][w] = eint; r[1][w] = eext; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) { a0 += r[0][k]; a1 += r[1][k]; }
+    epart[2 * blockIdx.x] = a0;
+    epart[2 * blockIdx.x + 1] = a1;
+  }
+}
+
+// Positions x = x0 + u without stepping (ulppm_forces, families, dt_crit, init).
+__global__ void k_positions(ulppm_state S, double* __restrict__ x, double* __restrict__ vh,
+                            double* __restrict__ vol_n) {
+  const int64_t n = S.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[c * n + i] = S.x0[c][i] + S.u[c][i];
+      vh[c * n + i] = S.v[c][i];
+    }
+    vol_n[i] = S.vol[i];
+  }
+}
+
+// -------------------------------------------------------- family build --
+
+__global__ void k_bbox(const double* __restrict__ x, int64_t n, double* __restrict__ part) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    for (int c = 0; c < 3; ++c) {
+      double v = x[c * n + i];
+      lo[c] = fmin(lo[c], v);
+      hi[c] = fmax(hi[c], v);
+    }
+  __shared__ double s[6][256];
+  for (int c = 0; c < 3; ++c) { s[c][threadIdx.x] = lo[c]; s[3 + c][threadIdx.x] = hi[c]; }
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int c = 0; c < 3; ++c) {
+        s[c][threadIdx.x] = fmin(s[c][threadIdx.x], s[c][threadIdx.x + o]);
+        s[3 + c][threadIdx.x] = fmax(s[3 + c][threadIdx.x], s[3 + c][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// One thread: cells of edge >= delta over the bounding box, doubled until the
+// grid fits the allocated cell arrays.  A non-finite box flags an error and
+// collapses everything into one cell (the search stays in bounds).
+__global__ void k_grid(const double* __restrict__ part, int nb, double delta, int64_t max_cells,
+                       Grid* __restrict__ G, unsigned long long* __restrict__ ctr) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = 0; b < nb; ++b)
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(lo[c], part[6 * b + c]);
+      hi[c] = fmax(hi[c], part[6 * b + 3 + c]);
+    }
+  bool ok = true;
+  for (int c = 0; c < 3; ++c) ok = ok && isfinite(lo[c]) && isfinite(hi[c]);
+  Grid g;
+  if (!ok) {
+    atomicAdd(&ctr[C_NONFINITE], 1ull);
+    g.lo0 = g.lo1 = g.lo2 = 0.0;
+    g.cs = INFINITY;
+    g.d0 = g.d1 = g.d2 = 1;
+    g.ncell = 1;
+    *G = g;
+    return;
+  }
+  double cs = delta * (1.0 + 1e-9);
+  int64_t d[3];
+  for (;;) {
+    double tot = 1.0;
+    for (int c = 0; c < 3; ++c) {
+      d[c] = (int64_t)floor((hi[c] - lo[c]) / cs) + 1;
+      tot *= (double)d[c];
+    }
+    if (tot <= (double)max_cells) break;
+    cs *= 2.0;
+  }
+  g.lo0 = lo[0]; g.lo1 = lo[1]; g.lo2 = lo[2];
+  g.cs = cs;
+  g.d0 = d[0]; g.d1 = d[1]; g.d2 = d[2];
+  g.ncell = d[0] * d[1] * d[2];
+  *G = g;
+}
+
+__device__ __forceinline__ int64_t cell_coord(double v, double lo, double cs, int64_t d) {
+  double t = floor((v - lo) / cs);
+  int64_t k = isfinite(t) ? (int64_t)t : 0;
+  return k < 0 ? 0 : (k >= d ? d - 1 : k);
+}
+
+__global__ void k_cell_count(const double* __restrict__ x, int64_t n, const Grid* __restrict__ G,
+                             int32_t* __restrict__ cellid, int32_t* __restrict__ ccount) {
+  const Grid g = *G;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t a = cell_coord(x[i], g.lo0, g.cs, g.d0);
+    int64_t b = cell_coord(x[n + i], g.lo1, g.cs, g.d1);
+    int64_t c = cell_coord(x[2 * n + i], g.lo2, g.cs, g.d2);
+    int32_t cid = (int32_t)(a + g.d0 * (b + g.d1 * c));
+    cellid[i] = cid;
+    atomicAdd(&ccount[cid], 1);
+  }
+}
+
+__global__ void k_cell_fill(int64_t n, const int32_t* __restrict__ cellid, const int64_t* __restrict__ cstart,
+                            int32_t* __restrict__ ccursor, int32_t* __restrict__ cpts) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t cid = cellid[i];
+    int32_t pos = atomicAdd(&ccursor[cid], 1);
+    cpts[cstart[cid] + pos] = (int32_t)i;
+  }
+}
+
+// One wave per point: test every point of the 27 surrounding cells with the
+// exact predicate, append hits through a ballot prefix, then place each hit at
+// its rank (ids are distinct) so the row comes out ascending.
+__global__ __launch_bounds__(kWave) void k_family(const double* __restrict__ x, int64_t n, int64_t per,
+                                                  const Grid* __restrict__ G, const int32_t* __restrict__ cellid,
+                                                  const int64_t* __restrict__ cstart,
+                                                  const int32_t* __restrict__ cpts, double d2, int max_f,
+                                                  int32_t* __restrict__ ell, int32_t* __restrict__ cnt,
+                                                  unsigned long long* __restrict__ ctr) {
+  extern __shared__ int32_t list[];
+  const int64_t i = xcd_point(blockIdx.x, per);
+  if (i >= n) return;
+  const int lane = threadIdx.x;
+  const Grid g = *G;
+  const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
+  const int64_t cid = cellid[i];
+  const int64_t ca = cid % g.d0, cb = (cid / g.d0) % g.d1, cc = cid / (g.d0 * g.d1);
+  int count = 0;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int64_t c3 = cc + dz;
+    if (c3 < 0 || c3 >= g.d2) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int64_t c2 = cb + dy;
+      if (c2 < 0 || c2 >= g.d1) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int64_t c1 = ca + dx;
+        if (c1 < 0 || c1 >= g.d0) continue;
+        const int64_t c = c1 + g.d0 * (c2 + g.d1 * c3);
+        const int64_t s0 = cstart[c], s1 = cstart[c + 1];
+        for (int64_t base = s0; base < s1; base += kWave) {
+          const int64_t e = base + lane;
+          bool hit = false;
+          int32_t j = -1;
+          if (e < s1) {
+            j = cpts[e];
+            hit = (j != (int32_t)i) && within(xi, yi, zi, x[j], x[n + j], x[2 * n + j], d2);
+          }
+          const unsigned long long mask = __ballot(hit);
+          const int off = __popcll(mask & ((1ull << lane) - 1ull));
+          if (hit && count + off < max_f) list[count + off] = j;
+          count += __popcll(mask);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int kept = count < max_f ? count : max_f;
+  for (int e = lane; e < kept; e += kWave) {
+    const int32_t v = list[e];
+    int r = 0;
+    for (int k = 0; k < kept; ++k) r += list[k] < v;
+    ell[i * (int64_t)max_f + r] = v;
+  }
+  if (lane == 0) {
+    cnt[i] = kept;
+    if (count > max_f) atomicAdd(&ctr[C_OVERFLOW], 1ull);
+    atomicMax(&ctr[C_MAXFAM], (unsigned long long)count);
+  }
+}
+
+// One wave per point: copy the sorted row into CSR and find, by binary
+// search in row j, the slot of the reverse bond (j,i).
+__global__ __launch_bounds__(kWave) void k_compact(int64_t n, int64_t per, int max_f,
+                                                   const int32_t* __restrict__ ell, const int32_t* __restrict__ cnt,
+                                                   const int64_t* __restrict__ row, int32_t* __restrict__ col,
+                                                   int32_t* __restrict__ rev, unsigned long long* __restrict__ ctr) {
+  const int64_t i = xcd_point(blockIdx.x, per);
+  if (i >= n) return;
+  const int nf = cnt[i];
+  const int64_t b0 = row[i];
+  for (int m = threadIdx.x; m < nf; m += kWave) {
+    const int32_t j = ell[i * (int64_t)max_f + m];
+    col[b0 + m] = j;
+    const int32_t* rj = ell + (int64_t)j * max_f;
+    int lo = 0, hi = cnt[j];
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (rj[mid] < (int32_t)i) lo = mid + 1; else hi = mid;
+    }
+    // Families are symmetric, so rj[lo] == i; a row truncated by an
+    // overflow (already flagged) falls back to the bond's own slot.
+    const bool found = lo < cnt[j] && rj[lo] == (int32_t)i;
+    rev[b0 + m] = (int32_t)(found ? row[j] + lo : b0 + m);
+    if (!found) atomicAdd(&ctr[C_OVERFLOW], 1ull);
+  }
+}
+
+// ----------------------------------------------------- constitutive model --
+
+__device__ __forceinline__ double apparent_pc(const DevParams& P, double pc) {
+  return -exp(P.b1) * pow(-pc, P.b2);               // Eq. 45
+}
+
+__device__ __forceinline__ double yield_f(const DevParams& P, double p, double q, double pcb) {
+  return q * q / (P.M * P.M) + p * (p - pcb);       // Eq. 40
+}
+
+// Retention curve, Eq. 15 read with exponent -(n-1)/n, suction in kPa, void
+// ratio e = phi/(1-phi).
+__device__ double swrc(const DevParams& P, double J, double phi, double s) {
+  if (!(s > 0.0)) return 1.0;
+  const double e = phi / (1.0 - phi);
+  const double arg = P.a1 * pow(e, P.a2) * J * (s * 1e-3);
+  return pow(1.0 + pow(arg, P.n_vg), -(P.n_vg - 1.0) / P.n_vg);
+}
+
+// Backward-Euler Perzyna update in the invariants (Eqs. 70-76): residuals
+// r1 = p - p_tr + K c f f_p, r2 = q - q_tr + 3 mu c f f_q,
+// r3 = p_c - p_c,n exp(-c f f_p / (lam - kap)) with c = dt/eta, solved by
+// Newton with the exact tangent; steps are halved to stay in
+// {f > 0, q >= 0, p_c < 0}, where the solution lies.  Returns the iteration
+// count (0 elastic) or -1.
+__device__ int return_map(const DevParams& P, double dt, const double* sn, double pcn, const double* de,
+                          double* so, double* pco) {
+  const double tr = de[0] + de[1] + de[2];
+  double st[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    st[k] = sn[k] + (k < 3 ? P.K * tr : 0.0) + 2.0 * P.mu * (de[k] - (k < 3 ? tr / 3.0 : 0.0));
+  const double ptr = (st[0] + st[1] + st[2]) / 3.0;
+  double s[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s[k] = st[k] - (k < 3 ? ptr : 0.0);
+  const double qtr = sqrt(1.5 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
+                                 2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5])));
+  const double Pn = apparent_pc(P, pcn);
+  if (!(yield_f(P, ptr, qtr, Pn) > 0.0)) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) so[k] = st[k];
+    *pco = pcn;
+    return 0;
+  }
+  const double c = dt / P.eta, M2 = P.M * P.M, lk = P.lam - P.kap;
+  const double sref = fmax(fabs(ptr), fmax(qtr, fabs(Pn)));
+  const double pref = fabs(pcn);
+  double p = ptr, q = qtr, pc = pcn;
+  int it = 0;
+  bool conv = false;
+  for (;;) {
+    const double Pb = apparent_pc(P, pc);
+    const double dP = P.b2 * exp(P.b1) * pow(-pc, P.b2 - 1.0);   // Eq. 89
+    const double f = yield_f(P, p, q, Pb);
+    const double fp = 2.0 * p - Pb, fq = 2.0 * q / M2, fc = -p * dP;
+    const double E = exp(-c * f * fp / lk);
+    const double r1 = p - ptr + P.K * c * f * fp;
+    const double r2 = q - qtr + 3.0 * P.mu * c * f * fq;
+    const double r3 = pc - pcn * E;
+    if (fabs(r1) <= P.newton_tol * sref && fabs(r2) <= P.newton_tol * sref && fabs(r3) <= P.newton_tol * pref) {
+      conv = true;
+      break;
+    }
+    if (it >= P.newton_maxit) break;
+    // d(f fp)/dx and d(f fq)/dx
+    const double gp = fp * fp + 2.0 * f, gq = fq * fp, gc = fc * fp - f * dP;
+    const double hp = fp * fq, hq = fq * fq + f * 2.0 / M2, hc = fc * fq;
+    const double k1 = P.K * c, k2 = 3.0 * P.mu * c, k3 = pcn * E * c / lk;
+    const double a11 = 1.0 + k1 * gp, a12 = k1 * gq, a13 = k1 * gc;
+    const double a21 = k2 * hp, a22 = 1.0 + k2 * hq, a23 = k2 * hc;
+    const double a31 = k3 * gp, a32 = k3 * gq, a33 = 1.0 + k3 * gc;
+    // Cramer's rule for A dx = -r
+    const double c11 = a22 * a33 - a23 * a32, c12 = a23 * a31 - a21 * a33, c13 = a21 * a32 - a22 * a31;
+    const double det = a11 * c11 + a12 * c12 + a13 * c13;
+    const double b1 = -r1, b2 = -r2, b3 = -r3;
+    const double dx1 = (b1 * c11 + a12 * (a23 * b3 - b2 * a33) + a13 * (b2 * a32 - a22 * b3)) / det;
+    const double dx2 = (a11 * (b2 * a33 - a23 * b3) + b1 * c12 + a13 * (a21 * b3 - b2 * a31)) / det;
+    const double dx3 = (a11 * (a22 * b3 - b2 * a32) + a12 * (b2 * a31 - a21 * b3) + b1 * c13) / det;
+    double stp = 1.0;
+    for (int h = 0; h < 60; ++h) {
+      const double pt = p + stp * dx1, qt = q + stp * dx2, ct = pc + stp * dx3;
+      if (ct < 0.0 && qt >= 0.0 && yield_f(P, pt, qt, apparent_pc(P, ct)) > 0.0) break;
+      stp *= 0.5;
+    }
+    p += stp * dx1;
+    q += stp * dx2;
+    pc += stp * dx3;
+    ++it;
+  }
+  const double ratio = qtr > 0.0 ? q / qtr : 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) so[k] = (k < 3 ? p : 0.0) + ratio * s[k];
+  *pco = pc;
+  if (!conv) return -1;
+  return it > 0 ? it : 1;
+}
+
+__device__ __forceinline__ double det3s(double a, double b, double c, double d, double e, double f) {
+  // symmetric [[a f e],[f b d],[e d c]]
+  return a * (b * c - d * d) - f * (f * c - d * e) + e * (f * d - b * e);
+}
+
+// ---------------------------------------------------------- bond kernel --
+
+enum { MODE_STEP = 0, MODE_FORCES = 1 };
+
+struct BondArgs {
+  int64_t n, per;
+  const int64_t* row;
+  const int32_t* col;
+  const double* x;        // 3n current positions
+  const double* vh;       // 3n velocities used for relative velocities
+  const double* vol_n;    // V^n, quadrature weights of this step
+  const double* J;
+  const double* phi;
+  const double* s;
+  const double* sig[6];   // point history in
+  const double* pc;
+  // point outputs (state arrays in step mode, scratch otherwise)
+  double* J_out;
+  double* vol_out;
+  double* phi_out;
+  double* Sr_out;
+  double* mass_out;
+  double* sig_out[6];
+  double* pc_out;
+  double* T[3];           // bond force states, CSR order
+  double dt_inc;
+  int max_f;
+  unsigned long long* ctr;
+};
+
+// One workgroup per point i, one lane per bond (i,j).
+template <class Acc>
+__global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) {
+  extern __shared__ double smem[];
+  const int64_t i = xcd_point(blockIdx.x, A.per);
+  if (i >= A.n) return;                           // uniform per block
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int mf = A.max_f;
+  const int64_t n = A.n;
+  const int64_t b0 = A.row[i];
+  const int nf = (int)(A.row[i + 1] - b0);
+  double* sx = smem;                               // 3*mf  x_k (FP64: exact predicate)
+  Acc* sz = reinterpret_cast<Acc*>(sx + 3 * mf);   // 3*mf  zeta_ik = x_k - x_i
+  Acc* sy = sz + 3 * mf;                           // 3*mf  ydot_ik = v_k - v_i
+  Acc* sv = sy + 3 * mf;                           // mf    V_k
+  __shared__ double red[2][24];
+  __shared__ double pt[4];                         // Sr_new, Vh, sum-of-family-volumes
+  __shared__ long long redi[2][4];
+
+  const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
+  const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
+
+  // Stage the family of i and form the full-horizon partial sums (Eqs. 5, 8).
+  double Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0.0;
+  for (int m = tid; m < nf; m += kBondThreads) {
+    const int32_t k = A.col[b0 + m];
+    const double xk0 = A.x[k], xk1 = A.x[n + k], xk2 = A.x[2 * n + k];
+    const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
+    const double y0 = A.vh[k] - vi0, y1 = A.vh[n + k] - vi1, y2 = A.vh[2 * n + k] - vi2;
+    const double V = A.vol_n[k];
+    sx[m] = xk0; sx[mf + m] = xk1; sx[2 * mf + m] = xk2;
+    sz[m] = (Acc)z0; sz[mf + m] = (Acc)z1; sz[2 * mf + m] = (Acc)z2;
+    sy[m] = (Acc)y0; sy[mf + m] = (Acc)y1; sy[2 * mf + m] = (Acc)y2;
+    sv[m] = (Acc)V;
+    const double w0 = V * z0, w1 = V * z1, w2 = V * z2;
+    Kp[0] += w0 * z0; Kp[1] += w1 * z1; Kp[2] += w2 * z2;
+    Kp[3] += w1 * z2; Kp[4] += w0 * z2; Kp[5] += w0 * z1;
+    Np[0] += y0 * w0; Np[1] += y0 * w1; Np[2] += y0 * w2;
+    Np[3] += y1 * w0; Np[4] += y1 * w1; Np[5] += y1 * w2;
+    Np[6] += y2 * w0; Np[7] += y2 * w1; Np[8] += y2 * w2;
+    Vp += V;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) Kp[k] = wave_sum(Kp[k]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Np[k] = wave_sum(Np[k]);
+  Vp = wave_sum(Vp);
+  if (lane == 0) {
+    for (int k = 0; k < 6; ++k) red[wid][k] = Kp[k];
+    for (int k = 0; k < 9; ++k) red[wid][6 + k] = Np[k];
+    red[wid][15] = Vp;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double Ki[6], Ni[9];
+    for (int k = 0; k < 6; ++k) Ki[k] = red[0][k] + red[1][k];
+    for (int k = 0; k < 9; ++k) Ni[k] = red[0][6 + k] + red[1][6 + k];
+    const double Vh = red[0][15] + red[1][15];
+    // Volume change of the step: with geometry at n+1 the increment F_D
+    // satisfies F_D^{-1} = I - dt L_i (Eq. 17 in updated Lagrangian form).
+    double Jd = 1.0;
+    const double dK = det3s(Ki[0], Ki[1], Ki[2], Ki[3], Ki[4], Ki[5]);
+    const double tk = (Ki[0] + Ki[1] + Ki[2]) / 3.0;
+    if (nf >= 3 && dK > 1e-12 * tk * tk * tk) {
+      const double a = Ki[0], b = Ki[1], c = Ki[2], d = Ki[3], e = Ki[4], f = Ki[5];
+      const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
+      const double ixy = (d * e - f * c) / dK, ixz = (f * d - b * e) / dK, iyz = (e * f - a * d) / dK;
+      const double Ki9[9] = {ixx, ixy, ixz, ixy, iyy, iyz, ixz, iyz, izz};
+      double B[9];
+      for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) {
+          double L = Ni[3 * r] * Ki9[cc] + Ni[3 * r + 1] * Ki9[3 + cc] + Ni[3 * r + 2] * Ki9[6 + cc];
+          B[3 * r + cc] = (r == cc ? 1.0 : 0.0) - A.dt_inc * L;
+        }
+      const double dB = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
+                        B[2] * (B[3] * B[7] - B[4] * B[6]);
+      Jd = 1.0 / dB;
+    }
+    const double Jn = A.J[i] * Jd;
+    const double Vn = A.vol_n[i] * Jd;
+    const double ph = 1.0 - (1.0 - A.phi[i]) / Jd;            // Eq. 16
+    const double Sr = swrc(P, Jn, ph, A.s[i]);                // Eq. 15
+    A.J_out[i] = Jn;
+    A.vol_out[i] = Vn;
+    A.phi_out[i] = ph;
+    A.Sr_out[i] = Sr;
+    A.mass_out[i] = (P.rho_s * (1.0 - ph) + P.rho_w * Sr * ph) * Vn;   // Eq. 48
+    pt[0] = Sr;
+    pt[1] = Vh;
+  }
+  __syncthreads();
+  const double Sr_i = pt[0], Vh = pt[1];
+  const double s_i = A.s[i];
+  double sig_i[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sig_i[k] = A.sig[k][i];
+  const double pc_i = A.pc[i];
+  const double d2 = P.d2;
+
+  double hs[6] = {0, 0, 0, 0, 0, 0}, hpc = 0.0, hw = 0.0;
+  long long n_deg = 0, n_pl = 0, n_nc = 0, n_trip = 0, mx = 0;
+  for (int m = tid; m < nf; m += kBondThreads) {
+    const double xj0 = sx[m], xj1 = sx[mf + m], xj2 = sx[2 * mf + m];
+    Acc K0 = 0, K1 = 0, K2 = 0, K3 = 0, K4 = 0, K5 = 0;
+    Acc N00 = 0, N01 = 0, N02 = 0, N10 = 0, N11 = 0, N12 = 0, N20 = 0, N21 = 0, N22 = 0, Vs = 0;
+    int ns = 0;
+    for (int t = 0; t < nf; ++t) {
+      const bool in = within(xj0, xj1, xj2, sx[t], sx[mf + t], sx[2 * mf + t], d2);
+      const Acc w = in ? sv[t] : (Acc)0;
+      ns += in ? 1 : 0;
+      const Acc z0 = sz[t], z1 = sz[mf + t], z2 = sz[2 * mf + t];
+      const Acc w0 = w * z0, w1 = w * z1, w2 = w * z2;
+      K0 += w0 * z0; K1 += w1 * z1; K2 += w2 * z2;
+      K3 += w1 * z2; K4 += w0 * z2; K5 += w0 * z1;
+      const Acc y0 = sy[t], y1 = sy[mf + t], y2 = sy[2 * mf + t];
+      N00 += y0 * w0; N01 += y0 * w1; N02 += y0 * w2;
+      N10 += y1 * w0; N11 += y1 * w1; N12 += y1 * w2;
+      N20 += y2 * w0; N21 += y2 * w1; N22 += y2 * w2;
+      Vs += w;
+    }
+    n_trip += ns;
+    // FP64 from here on: inversion, gradient, return map, force state.
+    const double a = K0, b = K1, c = K2, d = K3, e = K4, f = K5;
+    const double dK = det3s(a, b, c, d, e, f);
+    const double tk = (a + b + c) / 3.0;
+    const int64_t slot = b0 + m;
+    if (ns < 3 || !(dK > 1e-12 * tk * tk * tk)) {               // degenerate: inactive bond
+      ++n_deg;
+      A.T[0][slot] = 0.0; A.T[1][slot] = 0.0; A.T[2][slot] = 0.0;
+      continue;
+    }
+    const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
+    const double ixy = (d * e - f * c) / dK, ixz = (f * d - b * e) / dK, iyz = (e * f - a * d) / dK;
+    const double N[9] = {(double)N00, (double)N01, (double)N02, (double)N10, (double)N11,
+                         (double)N12, (double)N20, (double)N21, (double)N22};
+    double L[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      L[3 * r + 0] = N[3 * r] * ixx + N[3 * r + 1] * ixy + N[3 * r + 2] * ixz;
+      L[3 * r + 1] = N[3 * r] * ixy + N[3 * r + 1] * iyy + N[3 * r + 2] * iyz;
+      L[3 * r + 2] = N[3 * r] * ixz + N[3 * r + 1] * iyz + N[3 * r + 2] * izz;
+    }
+    const double varpi = (double)Vs / Vh;                       // Eq. 55
+    const double h = A.dt_inc;
+    const double de[6] = {h * L[0], h * L[4], h * L[8], h * 0.5 * (L[5] + L[7]), h * 0.5 * (L[2] + L[6]),
+                          h * 0.5 * (L[1] + L[3])};              // Eqs. 26, 59
+    double sb[6], pcb;
+    if (h == 0.0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sb[k] = sig_i[k];
+      pcb = pc_i;
+    } else {
+      int it = return_map(P, h, sig_i, pc_i, de, sb, &pcb);
+      if (it < 0) { ++n_nc; it = P.newton_maxit; }
+      if (it > 0) ++n_pl;
+      mx = mx > it ? mx : it;
+    }
+    // T_ij = varpi (sigma_ij + Sr_i s_i 1) K_ij^{-1} zeta_ij  (Eq. 32 with p_w = -s)
+    const double zx = xj0 - xi0, zy = xj1 - xi1, zz = xj2 - xi2;
+    const double w0 = ixx * zx + ixy * zy + ixz * zz;
+    const double w1 = ixy * zx + iyy * zy + iyz * zz;
+    const double w2 = ixz * zx + iyz * zy + izz * zz;
+    const double ps = Sr_i * s_i;
+    A.T[0][slot] = varpi * ((sb[0] + ps) * w0 + sb[5] * w1 + sb[4] * w2);
+    A.T[1][slot] = varpi * (sb[5] * w0 + (sb[1] + ps) * w1 + sb[3] * w2);
+    A.T[2][slot] = varpi * (sb[4] * w0 + sb[3] * w1 + (sb[2] + ps) * w2);
+    // point history: volume-weighted mean of the bond states
+    const double Vj = A.vol_n[A.col[slot]];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) hs[k] += Vj * sb[k];
+    hpc += Vj * pcb;
+    hw += Vj;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) hs[k] = wave_sum(hs[k]);
+  hpc = wave_sum(hpc);
+  hw = wave_sum(hw);
+  n_deg = wave_sum_i(n_deg);
+  n_pl = wave_sum_i(n_pl);
+  n_nc = wave_sum_i(n_nc);
+  n_trip = wave_sum_i(n_trip);
+  mx = wave_max_i(mx);
+  __syncthreads();   // red[] is reused
+  if (lane == 0) {
+    for (int k = 0; k < 6; ++k) red[wid][k] = hs[k];
+    red[wid][6] = hpc;
+    red[wid][7] = hw;
+    redi[wid][0] = n_deg; redi[wid][1] = n_pl; redi[wid][2] = n_nc; redi[wid][3] = n_trip;
+    red[wid][8] = (double)mx;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double W = red[0][7] + red[1][7];
+    if (W > 0.0) {
+      for (int k = 0; k < 6; ++k) A.sig_out[k][i] = (red[0][k] + red[1][k]) / W;
+      A.pc_out[i] = (red[0][6] + red[1][6]) / W;
+    } else {
+      for (int k = 0; k < 6; ++k) A.sig_out[k][i] = sig_i[k];
+      A.pc_out[i] = pc_i;
+    }
+    const long long d = redi[0][0] + redi[1][0], pl = redi[0][1] + redi[1][1];
+    const long long nc = redi[0][2] + redi[1][2], tr = redi[0][3] + redi[1][3];
+    if (d) atomicAdd(&A.ctr[C_DEGEN], (unsigned long long)d);
+    if (pl) atomicAdd(&A.ctr[C_PLASTIC], (unsigned long long)pl);
+    if (nc) atomicAdd(&A.ctr[C_NOCONV], (unsigned long long)nc);
+    atomicAdd(&A.ctr[C_TRIPLES], (unsigned long long)tr);
+    atomicAdd(&A.ctr[C_TESTS], (unsigned long long)((long long)nf * nf));
+    const long long m2 = (long long)fmax(red[0][8], red[1][8]);
+    if (m2) atomicMax(&A.ctr[C_MAXNEWTON], (unsigned long long)m2);
+  }
+}
+
+// -------------------------------------------------------- gather kernel --
+
+enum { G_FORCES = 0, G_INIT = 1, G_STEP = 2 };
+
+struct GatherArgs {
+  int64_t n, per;
+  const int64_t* row;
+  const int32_t* col;
+  const int32_t* rev;
+  const double* T[3];
+  const double* vol_n;
+  const double* mass;     // M^{n+1}
+  const double* vh;       // 3n (G_STEP)
+  const uint8_t* fixed;
+  double* f[3];           // G_FORCES output
+  double* a[3];
+  double* v[3];
+  double* epart;          // 3 per block (G_STEP)
+  unsigned long long* ctr;
+  double hdt, g0, g1, g2;
+  int mode;
+};
+
+// One wave per point: f_i = V_i sum_j (T_ij - T_ji) V_j (Eqs. 49-50, sign of
+// Eq. 33), gathering T_ji through rev[] instead of scattering with atomics;
+// then a = f/M + g (Eq. 62), v = v_half + (dt/2) a (Eq. 63), energy partials.
+__global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t i = xcd_point(blockIdx.x, G.per) * 4 + wid;
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+  if (i < G.n) {
+    const int64_t b0 = G.row[i], b1 = G.row[i + 1];
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    for (int64_t s = b0 + lane; s < b1; s += kWave) {
+      const int32_t j = G.col[s], r = G.rev[s];
+      const double wv = G.vol_n[j];
+      f0 += (G.T[0][s] - G.T[0][r]) * wv;
+      f1 += (G.T[1][s] - G.T[1][r]) * wv;
+      f2 += (G.T[2][s] - G.T[2][r]) * wv;
+    }
+    f0 = wave_sum(f0);
+    f1 = wave_sum(f1);
+    f2 = wave_sum(f2);
+    if (lane == 0) {
+      const double Vi = G.vol_n[i];
+      const double f[3] = {f0 * Vi, f1 * Vi, f2 * Vi};
+      if (G.mode == G_FORCES) {
+        for (int c = 0; c < 3; ++c) G.f[c][i] = f[c];
+      } else {
+        const bool fx = G.fixed[i] != 0;
+        const double M = G.mass[i];
+        const double g[3] = {G.g0, G.g1, G.g2};
+        bool bad = false;
+        for (int c = 0; c < 3; ++c) {
+          const double a = fx ? 0.0 : f[c] / M + g[c];
+          G.a[c][i] = a;
+          if (G.mode == G_STEP) {
+            const double vhc = G.vh[c * G.n + i];
+            const double v = vhc + G.hdt * a;
+            G.v[c][i] = v;
+            if (!fx) {
+              e0 -= G.hdt * vhc * f[c];
+              e1 += G.hdt * vhc * M * g[c];
+            }
+            e2 += 0.5 * M * v * v;
+            bad = bad || !isfinite(v);
+          }
+          bad = bad || !isfinite(a);
+        }
+        if (bad) atomicAdd(&G.ctr[C_NONFINITE], 1ull);
+      }
+    }
+  }
+  if (G.mode == G_STEP) {
+    __shared__ double r[3][4];
+    if (lane == 0) { r[0][wid] = e0; r[1][wid] = e1; r[2][wid] = e2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      G.epart[3 * blockIdx.x + 0] = r[0][0] + r[0][1] + r[0][2] + r[0][3];
+      G.epart[3 * blockIdx.x + 1] = r[1][0] + r[1][1] + r[1][2] + r[1][3];
+      G.epart[3 * blockIdx.x + 2] = r[2][0] + r[2][1] + r[2][2] + r[2][3];
+    }
+  }
+}
+
+// Deterministic energy totals: one block sums the per-block partials of the
+// predictor (2 per block) and of the gather (3 per block) in a fixed order.
+__global__ void k_energy(const double* __restrict__ pp, int npb, const double* __restrict__ gp, int ngb,
+                         double* __restrict__ E) {
+  __shared__ double s[3][256];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int k = threadIdx.x; k < npb; k += 256) { a += pp[2 * k]; b += pp[2 * k + 1]; }
+  for (int k = threadIdx.x; k < ngb; k += 256) { a += gp[3 * k]; b += gp[3 * k + 1]; c += gp[3 * k + 2]; }
+  s[0][threadIdx.x] = a; s[1][threadIdx.x] = b; s[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int q = 0; q < 3; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    E[0] += s[0][0];
+    E[1] += s[1][0];
+    E[2] = s[2][0];
+  }
+}
+
+// -------------------------------------------------------- init / dt_crit --
+
+// Point set-up of the initial conditions (Algorithm 2): J = 1, u = 0,
+// Sr from Eq. 15 at J = 1, effective stress = total - Sr s 1 (Eq. 2,
+// p_w = -s), pre-consolidation = ocr times the isotropic intercept of the
+// yield surface through that stress (Eq. 40), inverted through Eq. 45;
+// mass from Eq. 48.
+__global__ void k_init_points(ulppm_state S, DevParams P, double ocr) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < S.n; i += (int64_t)gridDim.x * blockDim.x) {
+    S.J[i] = 1.0;
+    for (int c = 0; c < 3; ++c) { S.u[c][i] = 0.0; S.uc[c][i] = 0.0; }
+    const double s = S.s[i], phi = S.phi[i];
+    const double Sr = swrc(P, 1.0, phi, s);
+    S.Sr[i] = Sr;
+    double sg[6];
+    for (int k = 0; k < 6; ++k) sg[k] = S.sig[k][i] - (k < 3 ? Sr * s : 0.0);
+    for (int k = 0; k < 6; ++k) S.sig[k][i] = sg[k];
+    const double p = (sg[0] + sg[1] + sg[2]) / 3.0;
+    const double d0 = sg[0] - p, d1 = sg[1] - p, d2 = sg[2] - p;
+    const double q2 = 1.5 * (d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * (sg[3] * sg[3] + sg[4] * sg[4] + sg[5] * sg[5]));
+    const double pcb = ocr * (p + q2 / (P.M * P.M * p));
+    S.pc[i] = -pow(-pcb * exp(-P.b1), 1.0 / P.b2);
+    S.mass[i] = (P.rho_s * (1.0 - phi) + P.rho_w * Sr * phi) * S.vol[i];
+  }
+}
+
+// Eq. 65 per point (C/|zeta| with C = 18 K / (pi delta^4)); block minima.
+__global__ void k_dtcrit(int64_t n, const int64_t* __restrict__ row, const int32_t* __restrict__ col,
+                         const double* __restrict__ x, const double* __restrict__ vol,
+                         const double* __restrict__ phi, double C, double rho_s, double* __restrict__ part) {
+  double best = INFINITY;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double sum = 0.0;
+    for (int64_t s = row[i]; s < row[i + 1]; ++s) {
+      const int32_t j = col[s];
+      const double z = sqrt(exact_r2(x[i], x[n + i], x[2 * n + i], x[j], x[n + j], x[2 * n + j]));
+      sum += vol[j] * C / z;
+    }
+    if (sum > 0.0) best = fmin(best, sqrt(2.0 * (1.0 - phi[i]) * rho_s / sum));
+  }
+  __shared__ double s[256];
+  s[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] = fmin(s[threadIdx.x], s[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void k_export_rows(int64_t n, const int64_t* __restrict__ row, int64_t* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e <= n; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = row[e];
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ a, int32_t* __restrict__ b, int64_t m) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+    b[e] = a[e];
+}
+
+__global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t m) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+    b[e] = a[e];
+}
+
+}  // namespace
+
+// ==================================================================== host ==
+
+struct ulppm_ctx {
+  hipStream_t stream = nullptr;
+  int64_t cap_n = 0;
+  int max_f = 0;
+  int64_t max_cells = 0;
+  int64_t bond_cap = 0;
+  // per point
+  double* x = nullptr;      // 3n
+  double* vh = nullptr;     // 3n
+  double* vol_n = nullptr;  // n
+  double* pscr = nullptr;   // 12n point scratch for non-mutating passes
+  int32_t* cellid = nullptr;
+  int32_t* cnt = nullptr;
+  int64_t* row = nullptr;   // n+1
+  int32_t* ell = nullptr;   // n*max_f
+  // cells
+  int32_t* ccount = nullptr;
+  int32_t* ccursor = nullptr;
+  int64_t* cstart = nullptr;  // max_cells+1
+  int32_t* cpts = nullptr;    // n
+  // bonds
+  int32_t* col = nullptr;
+  int32_t* rev = nullptr;
+  double* T = nullptr;        // 3*bond_cap
+  // reductions
+  double* part = nullptr;     // partials
+  int64_t part_cap = 0;
+  int64_t* scan_bsum = nullptr;
+  int64_t scan_cap = 0;
+  Grid* grid = nullptr;
+  unsigned long long* ctr = nullptr;
+  double* E = nullptr;        // 3
+  // host mirrors
+  unsigned long long h_ctr[C_NCOUNT];
+  std::string err;
+};
+
+namespace {
+
+int fail(ulppm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                               \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return fail(ctx, ULPPM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+DevParams dev_params(const ulppm_params* p) {
+  DevParams d;
+  d.delta = p->delta;
+  d.d2 = p->delta * p->delta;
+  d.K = p->K; d.mu = p->mu; d.M = p->M; d.lam = p->lam; d.kap = p->kap; d.eta = p->eta;
+  d.b1 = p->b1; d.b2 = p->b2; d.rho_s = p->rho_s; d.rho_w = p->rho_w;
+  d.a1 = p->a1; d.a2 = p->a2; d.n_vg = p->n_vg;
+  d.g0 = p->g[0]; d.g1 = p->g[1]; d.g2 = p->g[2];
+  d.dt = p->dt;
+  d.newton_tol = p->newton_tol;
+  d.newton_maxit = p->newton_maxit;
+  return d;
+}
+
+int check_state(ulppm_ctx* ctx, const ulppm_state* S) {
+  if (!S) return fail(ctx, ULPPM_E_ARG, "state is NULL");
+  if (S->n <= 0 || S->n > ctx->cap_n) return fail(ctx, ULPPM_E_ARG, "state n out of range for this context");
+  for (int c = 0; c < 3; ++c)
+    if (!S->x0[c] || !S->u[c] || !S->uc[c] || !S->v[c] || !S->a[c]) return fail(ctx, ULPPM_E_ARG, "NULL vector field");
+  for (int k = 0; k < 6; ++k)
+    if (!S->sig[k]) return fail(ctx, ULPPM_E_ARG, "NULL stress component");
+  if (!S->vol || !S->phi || !S->J || !S->Sr || !S->mass || !S->s || !S->pc || !S->fixed)
+    return fail(ctx, ULPPM_E_ARG, "NULL scalar field");
+  return ULPPM_OK;
+}
+
+int check_params(ulppm_ctx* ctx, const ulppm_params* p) {
+  if (!p) return fail(ctx, ULPPM_E_ARG, "params is NULL");
+  if (!(p->delta > 0.0) || !std::isfinite(p->delta)) return fail(ctx, ULPPM_E_ARG, "delta must be > 0");
+  if (!(p->K > 0.0) || !(p->mu > 0.0) || !(p->M > 0.0) || !(p->eta > 0.0) || !(p->lam > p->kap))
+    return fail(ctx, ULPPM_E_ARG, "material constants out of range");
+  if (p->newton_maxit < 1 || p->newton_maxit > 1000) return fail(ctx, ULPPM_E_ARG, "newton_maxit out of range");
+  if (p->precision != ULPPM_FP64 && p->precision != ULPPM_MIXED) return fail(ctx, ULPPM_E_ARG, "bad precision");
+  return ULPPM_OK;
+}
+
+inline int blocks_for(int64_t n, int t, int cap = 65536) {
+  int64_t b = (n + t - 1) / t;
+  if (b < 1) b = 1;
+  return (int)(b > cap ? cap : b);
+}
+
+int zero_counters(ulppm_ctx* ctx) {
+  k_fill<unsigned long long><<<1, 64, 0, ctx->stream>>>(ctx->ctr, C_NCOUNT, 0ull);
+  HIPCHK(hipGetLastError());
+  return ULPPM_OK;
+}
+
+int scan_counts(ulppm_ctx* ctx, const int32_t* cnt, int64_t m, int64_t* out) {
+  const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
+  if (nb > ctx->scan_cap) return fail(ctx, ULPPM_E_ARG, "scan too large");
+  if (nb == 0) {
+    k_fill<int64_t><<<1, 64, 0, ctx->stream>>>(out, 1, 0);
+    HIPCHK(hipGetLastError());
+    return ULPPM_OK;
+  }
+  k_scan_blocks<<<(unsigned)nb, 256, 0, ctx->stream>>>(cnt, m, out, ctx->scan_bsum);
+  k_scan_top<<<1, 1024, 0, ctx->stream>>>(ctx->scan_bsum, nb, out, m);
+  k_scan_add<<<(unsigned)nb, 256, 0, ctx->stream>>>(out, m, ctx->scan_bsum);
+  HIPCHK(hipGetLastError());
+  return ULPPM_OK;
+}
+
+// Families at the positions in ctx->x (Eq. 1): grid, cell lists, per-point
+// sorted rows, CSR and reverse index.
+int build_families(ulppm_ctx* ctx, int64_t n, double delta) {
+  const int nbb = blocks_for(n, 256, 1024);
+  k_bbox<<<nbb, 256, 0, ctx->stream>>>(ctx->x, n, ctx->part + kPartRed);
+  k_grid<<<1, 1, 0, ctx->stream>>>(ctx->part + kPartRed, nbb, delta, ctx->max_cells, ctx->grid, ctx->ctr);
+  k_fill<int32_t><<<blocks_for(ctx->max_cells, 256, 4096), 256, 0, ctx->stream>>>(ctx->ccount, ctx->max_cells, 0);
+  k_fill<int32_t><<<blocks_for(ctx->max_cells, 256, 4096), 256, 0, ctx->stream>>>(ctx->ccursor, ctx->max_cells, 0);
+  k_cell_count<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(ctx->x, n, ctx->grid, ctx->cellid, ctx->ccount);
+  HIPCHK(hipGetLastError());
+  int rc = scan_counts(ctx, ctx->ccount, ctx->max_cells, ctx->cstart);
+  if (rc) return rc;
+  k_cell_fill<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, ctx->cellid, ctx->cstart, ctx->ccursor, ctx->cpts);
+  const int64_t per = (n + 7) / 8;
+  k_family<<<(unsigned)(8 * per), kWave, ctx->max_f * sizeof(int32_t), ctx->stream>>>(
+      ctx->x, n, per, ctx->grid, ctx->cellid, ctx->cstart, ctx->cpts, delta * delta, ctx->max_f, ctx->ell,
+      ctx->cnt, ctx->ctr);
+  HIPCHK(hipGetLastError());
+  rc = scan_counts(ctx, ctx->cnt, n, ctx->row);
+  if (rc) return rc;
+  k_compact<<<(unsigned)(8 * per), kWave, 0, ctx->stream>>>(n, per, ctx->max_f, ctx->ell, ctx->cnt, ctx->row,
+                                                            ctx->col, ctx->rev, ctx->ctr);
+  HIPCHK(hipGetLastError());
+  return ULPPM_OK;
+}
+
+size_t bond_lds(int max_f, bool mixed) {
+  return (size_t)max_f * (3 * sizeof(double) + 7 * (mixed ? sizeof(float) : sizeof(double)));
+}
+
+// Algorithm 1 (bond pass) into outputs; mode: step (state outputs) or not.
+int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, double dt_inc, bool commit) {
+  const int64_t n = S->n;
+  BondArgs A;
+  A.n = n;
+  A.per = (n + 7) / 8;
+  A.row = ctx->row;
+  A.col = ctx->col;
+  A.x = ctx->x;
+  A.vh = ctx->vh;
+  A.vol_n = ctx->vol_n;
+  A.J = S->J;
+  A.phi = S->phi;
+  A.s = S->s;
+  for (int k = 0; k < 6; ++k) A.sig[k] = S->sig[k];
+  A.pc = S->pc;
+  if (commit) {
+    A.J_out = S->J; A.vol_out = S->vol; A.phi_out = S->phi; A.Sr_out = S->Sr; A.mass_out = S->mass;
+    for (int k = 0; k < 6; ++k) A.sig_out[k] = S->sig[k];
+    A.pc_out = S->pc;
+  } else {
+    double* q = ctx->pscr;
+    A.J_out = q; A.vol_out = q + n; A.phi_out = q + 2 * n; A.Sr_out = q + 3 * n; A.mass_out = q + 4 * n;
+    for (int k = 0; k < 6; ++k) A.sig_out[k] = q + (5 + k) * n;
+    A.pc_out = q + 11 * n;
+  }
+  for (int c = 0; c < 3; ++c) A.T[c] = ctx->T + c * ctx->bond_cap;
+  A.dt_inc = dt_inc;
+  A.max_f = ctx->max_f;
+  A.ctr = ctx->ctr;
+  DevParams P = dev_params(p);
+  const bool mixed = p->precision == ULPPM_MIXED;
+  const size_t lds = bond_lds(ctx->max_f, mixed);
+  if (mixed)
+    k_bond<float><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
+  else
+    k_bond<double><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
+  HIPCHK(hipGetLastError());
+  return ULPPM_OK;
+}
+
+int gather_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int mode, const double* mass,
+                double* const* fout) {
+  const int64_t n = S->n;
+  GatherArgs G;
+  G.n = n;
+  const int64_t nblk = (n + 3) / 4;
+  G.per = (nblk + 7) / 8;
+  G.row = ctx->row;
+  G.col = ctx->col;
+  G.rev = ctx->rev;
+  for (int c = 0; c < 3; ++c) G.T[c] = ctx->T + c * ctx->bond_cap;
+  G.vol_n = ctx->vol_n;
+  G.mass = mass;
+  G.vh = ctx->vh;
+  G.fixed = S->fixed;
+  for (int c = 0; c < 3; ++c) {
+    G.f[c] = fout ? fout[c] : nullptr;
+    G.a[c] = S->a[c];
+    G.v[c] = S->v[c];
+  }
+  G.epart = ctx->part + kPartGather;
+  G.ctr = ctx->ctr;
+  G.hdt = 0.5 * p->dt;
+  G.g0 = p->g[0]; G.g1 = p->g[1]; G.g2 = p->g[2];
+  G.mode = mode;
+  const unsigned grid = (unsigned)(8 * G.per);
+  if (mode == G_STEP && (int64_t)grid * 3 + kPartGather > ctx->part_cap) return fail(ctx, ULPPM_E_ARG, "partials too small");
+  k_gather<<<grid, 256, 0, ctx->stream>>>(G);
+  HIPCHK(hipGetLastError());
+  return ULPPM_OK;
+}
+
+int read_counters(ulppm_ctx* ctx) {
+  HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->ctr, sizeof(ctx->h_ctr), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ULPPM_OK;
+}
+
+int counters_to_status(ulppm_ctx* ctx) {
+  if (ctx->h_ctr[C_OVERFLOW])
+    return fail(ctx, ULPPM_E_CAPACITY, "a family exceeded max_family=" + std::to_string(ctx->max_f) +
+                                           " (largest " + std::to_string(ctx->h_ctr[C_MAXFAM]) + ")");
+  if (ctx->h_ctr[C_NONFINITE]) return fail(ctx, ULPPM_E_NONFINITE, "non-finite positions, velocities or accelerations");
+  if (ctx->h_ctr[C_NOCONV])
+    return fail(ctx, ULPPM_E_NOCONV, std::to_string(ctx->h_ctr[C_NOCONV]) + " return-map Newton solves did not converge");
+  return ULPPM_OK;
+}
+
+void fill_report(ulppm_ctx* ctx, int64_t n, ulppm_report* rep, int64_t steps) {
+  if (!rep) return;
+  double E[3] = {0, 0, 0};
+  int64_t nb = 0;
+  (void)hipMemcpyAsync(E, ctx->E, sizeof(E), hipMemcpyDeviceToHost, ctx->stream);
+  (void)hipMemcpyAsync(&nb, ctx->row + n, sizeof(nb), hipMemcpyDeviceToHost, ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
+  rep->W_int = E[0];
+  rep->W_ext = E[1];
+  rep->W_kin = E[2];
+  rep->n_bonds = nb;
+  rep->n_degenerate = (int64_t)ctx->h_ctr[C_DEGEN];
+  rep->n_plastic = (int64_t)ctx->h_ctr[C_PLASTIC];
+  rep->max_newton = (int64_t)ctx->h_ctr[C_MAXNEWTON];
+  rep->n_noconv = (int64_t)ctx->h_ctr[C_NOCONV];
+  rep->n_tests = (int64_t)ctx->h_ctr[C_TESTS];
+  rep->n_triples = (int64_t)ctx->h_ctr[C_TRIPLES];
+  rep->max_family = (int64_t)ctx->h_ctr[C_MAXFAM];
+  rep->steps = steps;
+}
+
+}  // namespace
+
+// =============================================================== C ABI ==
+
+extern "C" {
+
+int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hip_stream) {
+  ulppm_ctx* ctx = nullptr;
+  if (!out) return ULPPM_E_ARG;
+  *out = nullptr;
+  if (n_points <= 0 || n_points > 2147483647LL) return ULPPM_E_ARG;
+  if (max_family == 0) max_family = 256;
+  if (max_family < 8 || max_family > 1024) return ULPPM_E_ARG;
+  ctx = new ulppm_ctx();
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->cap_n = n_points;
+  ctx->max_f = max_family;
+  ctx->max_cells = n_points * 2 + 4096;
+  ctx->bond_cap = n_points * (int64_t)max_family;
+  if (ctx->bond_cap > 2147483647LL) {
+    delete ctx;
+    return ULPPM_E_ARG;   // bond slots are int32
+  }
+  const int64_t n = n_points;
+  ctx->part_cap = kPartGather + 3 * (8 * (((n + 3) / 4 + 7) / 8)) + 64;
+  ctx->scan_cap = (std::max<int64_t>(n + 1, ctx->max_cells) + kScanChunk - 1) / kScanChunk + 1;
+  hipError_t e = hipSuccess;
+  auto A = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 8);
+  };
+  A((void**)&ctx->x, sizeof(double) * 3 * n);
+  A((void**)&ctx->vh, sizeof(double) * 3 * n);
+  A((void**)&ctx->vol_n, sizeof(double) * n);
+  A((void**)&ctx->pscr, sizeof(double) * 12 * n);
+  A((void**)&ctx->cellid, sizeof(int32_t) * n);
+  A((void**)&ctx->cnt, sizeof(int32_t) * n);
+  A((void**)&ctx->row, sizeof(int64_t) * (n + 1));
+  A((void**)&ctx->ell, sizeof(int32_t) * ctx->bond_cap);
+  A((void**)&ctx->ccount, sizeof(int32_t) * ctx->max_cells);
+  A((void**)&ctx->ccursor, sizeof(int32_t) * ctx->max_cells);
+  A((void**)&ctx->cstart, sizeof(int64_t) * (ctx->max_cells + 1));
+  A((void**)&ctx->cpts, sizeof(int32_t) * n);
+  A((void**)&ctx->col, sizeof(int32_t) * ctx->bond_cap);
+  A((void**)&ctx->rev, sizeof(int32_t) * ctx->bond_cap);
+  A((void**)&ctx->T, sizeof(double) * 3 * ctx->bond_cap);
+  A((void**)&ctx->part, sizeof(double) * ctx->part_cap);
+  A((void**)&ctx->scan_bsum, sizeof(int64_t) * ctx->scan_cap);
+  A((void**)&ctx->grid, sizeof(Grid));
+  A((void**)&ctx->ctr, sizeof(unsigned long long) * C_NCOUNT);
+  A((void**)&ctx->E, sizeof(double) * 3);
+  if (e != hipSuccess) {
+    ulppm_destroy(ctx);
+    return ULPPM_E_HIP;
+  }
+  k_fill<double><<<1, 64, 0, ctx->stream>>>(ctx->E, 3, 0.0);
+  // the bond kernel's dynamic LDS may exceed the default cap for large max_family
+  (void)hipFuncSetAttribute((const void*)k_bond<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bond_lds(max_family, false));
+  (void)hipFuncSetAttribute((const void*)k_bond<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bond_lds(max_family, true));
+  if (hipGetLastError() != hipSuccess) {
+    ulppm_destroy(ctx);
+    return ULPPM_E_HIP;
+  }
+  *out = ctx;
+  return ULPPM_OK;
+}
+
+int ulppm_destroy(ulppm_ctx* ctx) {
+  if (!ctx) return ULPPM_E_ARG;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->cellid, ctx->cnt, ctx->row, ctx->ell,
+                  ctx->ccount, ctx->ccursor, ctx->cstart, ctx->cpts, ctx->col, ctx->rev, ctx->T,
+                  ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->E};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete ctx;
+  return ULPPM_OK;
+}
+
+const char* ulppm_last_error(const ulppm_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "NULL context";
+}
+
+int ulppm_reset_energy(ulppm_ctx* ctx) {
+  if (!ctx) return ULPPM_E_ARG;
+  k_fill<double><<<1, 64, 0, ctx->stream>>>(ctx->E, 3, 0.0);
+  HIPCHK(hipGetLastError());
+  return ULPPM_OK;
+}
+
+int ulppm_build_families(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int64_t* row_ptr,
+                         int32_t* col, int64_t col_cap, int64_t* n_bonds_out) {
+  if (!ctx) return ULPPM_E_ARG;
+  int rc = check_state(ctx, S);
+  if (rc) return rc;
+  if (!p || !(p->delta > 0.0)) return fail(ctx, ULPPM_E_ARG, "delta must be > 0");
+  const int64_t n = S->n;
+  if ((rc = zero_counters(ctx))) return rc;
+  k_positions<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, ctx->x, ctx->vh, ctx->vol_n);
+  HIPCHK(hipGetLastError());
+  if ((rc = build_families(ctx, n, p->delta))) return rc;
+  if ((rc = read_counters(ctx))) return rc;
+  if ((rc = counters_to_status(ctx))) return rc;
+  int64_t nb = 0;
+  HIPCHK(hipMemcpyAsync(&nb, ctx->row + n, sizeof(nb), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (n_bonds_out) *n_bonds_out = nb;
+  if (row_ptr) {
+    k_export_rows<<<blocks_for(n + 1, 256), 256, 0, ctx->stream>>>(n, ctx->row, row_ptr);
+    HIPCHK(hipGetLastError());
+  }
+  if (col) {
+    if (col_cap < nb) return fail(ctx, ULPPM_E_CAPACITY, "col_cap smaller than the bond count");
+    k_copy_i32<<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(ctx->col, col, nb);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ULPPM_OK;
+}
+
+int ulppm_forces(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, double dt_inc, double* f[3],
+                 double* T_out[3], ulppm_report* rep) {
+  if (!ctx) return ULPPM_E_ARG;
+  int rc = check_state(ctx, S);
+  if (rc) return rc;
+  if ((rc = check_params(ctx, p))) return rc;
+  if (!f || !f[0] || !f[1] || !f[2]) return fail(ctx, ULPPM_E_ARG, "f is NULL");
+  if (!(dt_inc >= 0.0) || !std::isfinite(dt_inc)) return fail(ctx, ULPPM_E_ARG, "dt_inc must be finite and >= 0");
+  const int64_t n = S->n;
+  if ((rc = zero_counters(ctx))) return rc;
+  k_positions<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, ctx->x, ctx->vh, ctx->vol_n);
+  HIPCHK(hipGetLastError());
+  if ((rc = build_families(ctx, n, p->delta))) return rc;
+  if ((rc = bond_pass(ctx, S, p, dt_inc, false))) return rc;
+  if ((rc = gather_pass(ctx, S, p, G_FORCES, ctx->pscr + 4 * n, f))) return rc;
+  if ((rc = read_counters(ctx))) return rc;
+  fill_report(ctx, n, rep, 0);
+  if ((rc = counters_to_status(ctx))) return rc;
+  if (T_out) {
+    int64_t nb = 0;
+    HIPCHK(hipMemcpyAsync(&nb, ctx->row + n, sizeof(nb), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int c = 0; c < 3; ++c)
+      if (T_out[c]) k_copy_f64<<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(ctx->T + c * ctx->bond_cap, T_out[c], nb);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ULPPM_OK;
+}
+
+int ulppm_init_state(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, double ocr) {
+  if (!ctx) return ULPPM_E_ARG;
+  int rc = check_state(ctx, S);
+  if (rc) return rc;
+  if ((rc = check_params(ctx, p))) return rc;
+  if (!(ocr >= 1.0)) return fail(ctx, ULPPM_E_ARG, "ocr must be >= 1");
+  const int64_t n = S->n;
+  if ((rc = zero_counters(ctx))) return rc;
+  DevParams P = dev_params(p);
+  k_init_points<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, P, ocr);
+  k_positions<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, ctx->x, ctx->vh, ctx->vol_n);
+  HIPCHK(hipGetLastError());
+  if ((rc = build_families(ctx, n, p->delta))) return rc;
+  if ((rc = bond_pass(ctx, S, p, 0.0, false))) return rc;
+  if ((rc = gather_pass(ctx, S, p, G_INIT, S->mass, nullptr))) return rc;
+  k_fill<double><<<1, 64, 0, ctx->stream>>>(ctx->E, 3, 0.0);
+  HIPCHK(hipGetLastError());
+  if ((rc = read_counters(ctx))) return rc;
+  return counters_to_status(ctx);
+}
+
+int ulppm_dt_crit(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, double* dt_out) {
+  if (!ctx) return ULPPM_E_ARG;
+  int rc = check_state(ctx, S);
+  if (rc) return rc;
+  if ((rc = check_params(ctx, p))) return rc;
+  if (!dt_out) return fail(ctx, ULPPM_E_ARG, "dt_out is NULL");
+  const int64_t n = S->n;
+  if ((rc = zero_counters(ctx))) return rc;
+  k_positions<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, ctx->x, ctx->vh, ctx->vol_n);
+  HIPCHK(hipGetLastError());
+  if ((rc = build_families(ctx, n, p->delta))) return rc;
+  const int nb = blocks_for(n, 256, 1024);
+  const double C = 18.0 * p->K / (M_PI * std::pow(p->delta, 4));
+  k_dtcrit<<<nb, 256, 0, ctx->stream>>>(n, ctx->row, ctx->col, ctx->x, S->vol, S->phi, C, p->rho_s,
+                                         ctx->part + kPartRed);
+  HIPCHK(hipGetLastError());
+  double h[1024];
+  HIPCHK(hipMemcpyAsync(h, ctx->part + kPartRed, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
+  if ((rc = read_counters(ctx))) return rc;
+  if ((rc = counters_to_status(ctx))) return rc;
+  double best = INFINITY;
+  for (int b = 0; b < nb; ++b) best = std::fmin(best, h[b]);
+  *dt_out = best;
+  return ULPPM_OK;
+}
+
+int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_steps, ulppm_report* rep) {
+  if (!ctx) return ULPPM_E_ARG;
+  int rc = check_state(ctx, S);
+  if (rc) return rc;
+  if ((rc = check_params(ctx, p))) return rc;
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(ctx, ULPPM_E_ARG, "dt must be > 0");
+  if (n_steps < 0) return fail(ctx, ULPPM_E_ARG, "n_steps < 0");
+  const int64_t n = S->n;
+  if ((rc = zero_counters(ctx))) return rc;
+  DevParams P = dev_params(p);
+  const int npb = blocks_for(n, 256, 2048);
+  for (int32_t k = 0; k < n_steps; ++k) {
+    k_predict<<<npb, 256, 0, ctx->stream>>>(*S, P, ctx->x, ctx->vh, ctx->vol_n, ctx->part + kPartPred);
+    HIPCHK(hipGetLastError());
+    if ((rc = build_families(ctx, n, p->delta))) return rc;
+    if ((rc = bond_pass(ctx, S, p, p->dt, true))) return rc;
+    if ((rc = gather_pass(ctx, S, p, G_STEP, S->mass, nullptr))) return rc;
+    const int64_t ngb = 8 * ((((n + 3) / 4) + 7) / 8);
+    k_energy<<<1, 256, 0, ctx->stream>>>(ctx->part + kPartPred, npb, ctx->part + kPartGather, (int)ngb,
+                                         ctx->E);
+    HIPCHK(hipGetLastError());
+  }
+  if ((rc = read_counters(ctx))) return rc;
+  fill_report(ctx, n, rep, n_steps);
+  if ((rc = counters_to_status(ctx))) return rc;
+  if (p->energy_check && n_steps > 0) {
+    double E[3];
+    HIPCHK(hipMemcpyAsync(E, ctx->E, sizeof(E), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const double mx = std::fmax(std::fabs(E[0]), std::fmax(std::fabs(E[1]), std::fabs(E[2])));
+    if (std::fabs(E[0] + E[2] - E[1]) > p->energy_tol * mx)
+      return fail(ctx, ULPPM_E_ENERGY, "energy balance (Eq. 69) violated");
+  }
+  return ULPPM_OK;
+}
+
+}  // extern "C"

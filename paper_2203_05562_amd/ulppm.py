@@ -1,0 +1,260 @@
+"""Thin Python binding of libulppm.so (argument marshalling only).
+
+Every step of the method runs in the HIP library; this module only lays out
+torch device tensors, fills the C structs of include/ulppm.h and checks return
+codes.  If the library is missing it raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libulppm.so")
+
+ULPPM_FP64, ULPPM_MIXED = 0, 1
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_CAPACITY", -4: "E_NOCONV", -5: "E_NONFINITE", -6: "E_ENERGY",
+          -7: "E_HIP"}
+
+_dp = C.POINTER(C.c_double)
+
+
+class Params(C.Structure):
+    _fields_ = [("delta", C.c_double), ("K", C.c_double), ("mu", C.c_double), ("M", C.c_double),
+                ("lam", C.c_double), ("kap", C.c_double), ("eta", C.c_double), ("b1", C.c_double),
+                ("b2", C.c_double), ("rho_s", C.c_double), ("rho_w", C.c_double), ("a1", C.c_double),
+                ("a2", C.c_double), ("n_vg", C.c_double), ("g", C.c_double * 3), ("dt", C.c_double),
+                ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("precision", C.c_int32),
+                ("energy_check", C.c_int32), ("pad", C.c_int32), ("energy_tol", C.c_double)]
+
+
+class State(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x0", _dp * 3), ("u", _dp * 3), ("uc", _dp * 3), ("v", _dp * 3),
+                ("a", _dp * 3), ("vol", _dp), ("phi", _dp), ("J", _dp), ("Sr", _dp), ("mass", _dp),
+                ("s", _dp), ("sig", _dp * 6), ("pc", _dp), ("fixed", C.POINTER(C.c_uint8))]
+
+
+class Report(C.Structure):
+    _fields_ = [("W_int", C.c_double), ("W_ext", C.c_double), ("W_kin", C.c_double),
+                ("n_bonds", C.c_int64), ("n_degenerate", C.c_int64), ("n_plastic", C.c_int64),
+                ("max_newton", C.c_int64), ("n_noconv", C.c_int64), ("n_tests", C.c_int64),
+                ("n_triples", C.c_int64), ("max_family", C.c_int64), ("steps", C.c_int64)]
+
+    def as_dict(self):
+        return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
+                for k, t in self._fields_}
+
+
+EXPORTS = ["ulppm_create", "ulppm_destroy", "ulppm_last_error", "ulppm_init_state", "ulppm_dt_crit",
+           "ulppm_build_families", "ulppm_forces", "ulppm_step", "ulppm_reset_energy"]
+
+_lib = None
+
+
+class UlppmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load the HIP library (no GPU call is made by loading)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() (no CPU fallback exists)")
+    L = C.CDLL(path)
+    vp = C.c_void_p
+    L.ulppm_create.argtypes = [C.POINTER(vp), C.c_int64, C.c_int32, vp]
+    L.ulppm_destroy.argtypes = [vp]
+    L.ulppm_last_error.argtypes = [vp]
+    L.ulppm_last_error.restype = C.c_char_p
+    L.ulppm_init_state.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.c_double]
+    L.ulppm_dt_crit.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.POINTER(C.c_double)]
+    L.ulppm_build_families.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.c_void_p, C.c_void_p,
+                                       C.c_int64, C.POINTER(C.c_int64)]
+    L.ulppm_forces.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.c_double, C.POINTER(_dp),
+                               C.POINTER(_dp), C.POINTER(Report)]
+    L.ulppm_step.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.c_int32, C.POINTER(Report)]
+    L.ulppm_reset_energy.argtypes = [vp]
+    for name in EXPORTS:
+        if name != "ulppm_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def make_params(prm: dict, precision: int = ULPPM_FP64, **over) -> Params:
+    d = dict(prm)
+    d.update(over)
+    p = Params()
+    for k in ("delta", "K", "mu", "M", "lam", "kap", "eta", "b1", "b2", "rho_s", "rho_w", "a1", "a2",
+              "n_vg", "dt", "newton_tol"):
+        setattr(p, k, float(d[k]))
+    p.g[:] = [float(c) for c in d["g"]]
+    p.newton_maxit = int(d.get("newton_maxit", 50))
+    p.precision = int(d.get("precision", precision))
+    p.energy_check = int(d.get("energy_check", 0))
+    p.energy_tol = float(d.get("energy_tol", 1e-2))
+    return p
+
+
+VEC = ("x0", "u", "uc", "v", "a")
+SCAL = ("vol", "phi", "J", "Sr", "mass", "s", "pc")
+
+
+class DeviceState:
+    """Point state as SoA torch tensors on one device (caller-owned memory)."""
+
+    def __init__(self, n: int, device="cuda"):
+        import torch
+        self.n = n
+        self.device = torch.device(device)
+        f = dict(dtype=torch.float64, device=self.device)
+        self.t: Dict[str, "torch.Tensor"] = {}
+        for k in VEC:
+            self.t[k] = torch.zeros((3, n), **f)
+        for k in SCAL:
+            self.t[k] = torch.zeros(n, **f)
+        self.t["sig"] = torch.zeros((6, n), **f)
+        self.t["fixed"] = torch.zeros(n, dtype=torch.uint8, device=self.device)
+
+    def __getitem__(self, k):
+        return self.t[k]
+
+    @classmethod
+    def from_arrays(cls, arrs: dict, device="cuda") -> "DeviceState":
+        """arrs in the AoS layout of the test harness: (N,3) vectors, (N,6) stress."""
+        import torch
+        n = int(np.asarray(arrs["x0"]).shape[0])
+        S = cls(n, device)
+        for k, v in arrs.items():
+            if k not in S.t:
+                continue
+            a = np.asarray(v)
+            if k in VEC or k == "sig":
+                a = a.T
+            S.t[k].copy_(torch.from_numpy(np.ascontiguousarray(a)))
+        return S
+
+    def to_arrays(self) -> dict:
+        out = {}
+        for k, v in self.t.items():
+            a = v.detach().cpu().numpy()
+            if k in VEC or k == "sig":
+                a = np.ascontiguousarray(a.T)
+            out[k] = a
+        return out
+
+    def clone(self) -> "DeviceState":
+        S = DeviceState.__new__(DeviceState)
+        S.n, S.device = self.n, self.device
+        S.t = {k: v.clone() for k, v in self.t.items()}
+        return S
+
+    def cstruct(self) -> State:
+        s = State()
+        s.n = self.n
+        for k in VEC:
+            arr = getattr(s, k)
+            for c in range(3):
+                arr[c] = C.cast(self.t[k][c].data_ptr(), _dp)
+        for k in SCAL:
+            setattr(s, k, C.cast(self.t[k].data_ptr(), _dp))
+        for c in range(6):
+            s.sig[c] = C.cast(self.t["sig"][c].data_ptr(), _dp)
+        s.fixed = C.cast(self.t["fixed"].data_ptr(), C.POINTER(C.c_uint8))
+        return s
+
+
+class Context:
+    """One ulppm context (scratch for up to n points) on the current stream."""
+
+    def __init__(self, n_points: int, max_family: int = 256, stream=None):
+        import torch
+        self.L = load_library()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.h = C.c_void_p()
+        rc = self.L.ulppm_create(C.byref(self.h), int(n_points), int(max_family), C.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise UlppmError(rc, "ulppm_create failed")
+        self.n_points = n_points
+        self.max_family = max_family
+
+    def close(self):
+        if self.h:
+            self.L.ulppm_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != 0:
+            msg = self.L.ulppm_last_error(self.h)
+            raise UlppmError(rc, msg.decode() if msg else "")
+
+    def init_state(self, S: DeviceState, p: Params, ocr: float):
+        cs = S.cstruct()
+        self._check(self.L.ulppm_init_state(self.h, C.byref(cs), C.byref(p), float(ocr)))
+
+    def dt_crit(self, S: DeviceState, p: Params) -> float:
+        out = C.c_double()
+        cs = S.cstruct()
+        self._check(self.L.ulppm_dt_crit(self.h, C.byref(cs), C.byref(p), C.byref(out)))
+        return float(out.value)
+
+    def build_families(self, S: DeviceState, p: Params, export: bool = True):
+        import torch
+        cs = S.cstruct()
+        nb = C.c_int64()
+        self._check(self.L.ulppm_build_families(self.h, C.byref(cs), C.byref(p), None, None, 0, C.byref(nb)))
+        if not export:
+            return int(nb.value)
+        row = torch.empty(S.n + 1, dtype=torch.int64, device=S.device)
+        col = torch.empty(max(int(nb.value), 1), dtype=torch.int32, device=S.device)
+        self._check(self.L.ulppm_build_families(self.h, C.byref(cs), C.byref(p), C.c_void_p(row.data_ptr()),
+                                                C.c_void_p(col.data_ptr()), col.numel(), C.byref(nb)))
+        return row, col[: int(nb.value)]
+
+    def forces(self, S: DeviceState, p: Params, dt_inc: float, want_T: bool = False):
+        import torch
+        f = torch.zeros((3, S.n), dtype=torch.float64, device=S.device)
+        fp = (_dp * 3)(*[C.cast(f[c].data_ptr(), _dp) for c in range(3)])
+        rep = Report()
+        cs = S.cstruct()
+        T = None
+        Tp = None
+        if want_T:
+            nb = self.build_families(S, p, export=False)
+            T = torch.zeros((3, max(nb, 1)), dtype=torch.float64, device=S.device)
+            Tp = (_dp * 3)(*[C.cast(T[c].data_ptr(), _dp) for c in range(3)])
+        self._check(self.L.ulppm_forces(self.h, C.byref(cs), C.byref(p), float(dt_inc), fp, Tp, C.byref(rep)))
+        return f, (T[:, : rep.n_bonds] if want_T else None), rep.as_dict()
+
+    def step(self, S: DeviceState, p: Params, n_steps: int) -> dict:
+        rep = Report()
+        cs = S.cstruct()
+        self._check(self.L.ulppm_step(self.h, C.byref(cs), C.byref(p), int(n_steps), C.byref(rep)))
+        return rep.as_dict()
+
+    def reset_energy(self):
+        self._check(self.L.ulppm_reset_energy(self.h))
+
+
+def column_state(col: dict, device="cuda", v0: Optional[np.ndarray] = None) -> DeviceState:
+    """Device state of a seeded column before ulppm_init_state: total stress in
+    sig, initial porosity and volume, suction, fixed base."""
+    n = col["n"]
+    arrs = dict(x0=col["x0"], vol=col["vol0"], phi=col["phi0"], s=col["suction"], sig=col["sig_geo"],
+                fixed=col["fixed"], v=(v0 if v0 is not None else np.zeros((n, 3))))
+    return DeviceState.from_arrays(arrs, device)

@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+that include/ulppm.h declares, and the ctypes mirrors of the structs match the
+header's layout (sizes and offsets measured by compiling the header with gcc).
+No GPU call is made."""
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2203_05562_amd import ulppm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ulppm.h")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(ulppm_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    syms = declared_symbols()
+    for s in ("ulppm_build_families", "ulppm_step", "ulppm_forces", "ulppm_create", "ulppm_destroy"):
+        assert s in syms
+    assert set(syms) == set(ulppm.EXPORTS) | (set(syms) - set(ulppm.EXPORTS))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ulppm.LIB_PATH):
+        from paper_2203_05562_amd.build import build
+        build()
+    return ulppm.load_library()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", ulppm.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r" T (ulppm_\w+)", out))
+    missing = [s for s in declared_symbols() if s not in exported]
+    assert not missing, missing
+    for s in declared_symbols():
+        assert hasattr(lib, s)
+
+
+def test_struct_layout_matches_header():
+    prog = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "ulppm.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(ulppm_params), sizeof(ulppm_state), sizeof(ulppm_report));
+  printf("%zu %zu %zu %zu\n", offsetof(ulppm_params, g), offsetof(ulppm_params, newton_maxit),
+         offsetof(ulppm_params, energy_tol), offsetof(ulppm_state, sig));
+  printf("%zu %zu\n", offsetof(ulppm_state, fixed), offsetof(ulppm_report, steps));
+  return 0;
+}
+'''
+    import ctypes as C
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(src, "w").write(prog)
+        subprocess.run(["gcc", "-I", os.path.dirname(HEADER), "-o", exe, src], check=True)
+        vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    exp = [C.sizeof(ulppm.Params), C.sizeof(ulppm.State), C.sizeof(ulppm.Report),
+           ulppm.Params.g.offset, ulppm.Params.newton_maxit.offset, ulppm.Params.energy_tol.offset,
+           ulppm.State.sig.offset, ulppm.State.fixed.offset, ulppm.Report.steps.offset]
+    assert vals == exp
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(ImportError):
+        saved = ulppm._lib
+        ulppm._lib = None
+        try:
+            ulppm.load_library(str(tmp_path / "nope.so"))
+        finally:
+            ulppm._lib = saved
