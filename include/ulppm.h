@@ -48,6 +48,17 @@ typedef enum {
 
 enum { ULPPM_FP64 = 0, ULPPM_MIXED = 1 };
 
+/* How bond force states are formed from the sub-horizon stresses.
+ * ULPPM_FORCE_CONJUGATE (default): the force state of bond (i,k) collects the
+ *   sub-horizon force state (V_j/V_H)(sigma_ij + S_r s 1) K_ij^{-1} zeta_ik of
+ *   every sub-horizon S_ij that holds k (Eqs. 27, 31 and the double integral
+ *   of Eq. 35), so its power equals the volume-weighted mean of sigma_ij : L_ij
+ *   that also updates the point history.
+ * ULPPM_FORCE_EQ51: Eq. 51 as printed, T_ij = varpi_ij (sigma_ij + S_r s 1)
+ *   K_ij^{-1} zeta_ij, the bond's own term only.  With history stored on the
+ *   points this form is linearly unstable (flutter); kept for comparison. */
+enum { ULPPM_FORCE_CONJUGATE = 0, ULPPM_FORCE_EQ51 = 1 };
+
 /* Material and integration parameters, copied by value on every call. */
 typedef struct {
   double delta;                 /* horizon, constant in the current configuration (Eq. 1) [m] */
@@ -64,7 +75,7 @@ typedef struct {
   int32_t newton_maxit;         /* Newton iteration cap */
   int32_t precision;            /* ULPPM_FP64 or ULPPM_MIXED */
   int32_t energy_check;         /* nonzero: check Eq. 69 at the end of ulppm_step */
-  int32_t pad;
+  int32_t force_mode;           /* ULPPM_FORCE_CONJUGATE or ULPPM_FORCE_EQ51 */
   double energy_tol;            /* epsilon of Eq. 69 (the paper uses ~1e-2) */
 } ulppm_params;
 
@@ -96,7 +107,7 @@ typedef struct {
 } ulppm_report;
 
 /* Create a context for up to n_points points and max_family members per family
- * (0 selects 256).  hip_stream is a hipStream_t (NULL = the null stream).
+ * (0 selects 192).  hip_stream is a hipStream_t (NULL = the null stream).
  * Allocates all scratch now; no entry point allocates afterwards.
  * Errors: ULPPM_E_ARG (n_points <= 0 or > 2^31-1, max_family > 1024),
  * ULPPM_E_HIP (allocation failed). */
@@ -141,7 +152,8 @@ int ulppm_build_families(ulppm_ctx *ctx, const ulppm_state *state, const ulppm_p
  * x0 + u; sub-horizon shape tensors (Eq. 23) and velocity gradients (Eq. 57)
  * from the velocities v; strain increment dt_inc * sym(L_ij) (Eqs. 26, 59);
  * bond stress from the Perzyna return map (Section 3.2.1), or equal to the
- * point stress when dt_inc == 0; force states T_ij (Eqs. 32, 51, 53); nodal
+ * point stress when dt_inc == 0; force states T_ij (Eqs. 27, 31-32, 35, or
+ * Eqs. 51, 53 as printed, per p->force_mode); nodal
  * force f_i = sum_j (T_ij - T_ji) V_i V_j (Eqs. 49-50 with the sign of Eq. 33)
  * written to f[3] (device, length n each).  T_out, if non-NULL, receives the
  * bond force states as three device arrays of length n_bonds (x, y, z), in the

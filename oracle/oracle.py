@@ -31,7 +31,7 @@ class OracleParams(C.Structure):
                 ("lam", C.c_double), ("kap", C.c_double), ("eta", C.c_double), ("b1", C.c_double),
                 ("b2", C.c_double), ("rho_s", C.c_double), ("rho_w", C.c_double), ("a1", C.c_double),
                 ("a2", C.c_double), ("n_vg", C.c_double), ("g", C.c_double * 3), ("dt", C.c_double),
-                ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("pad", C.c_int32)]
+                ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("force_mode", C.c_int32)]
 
 
 class OracleState(C.Structure):
@@ -100,11 +100,12 @@ def make_params(prm: dict, **over) -> OracleParams:
         setattr(p, k, float(d[k]))
     p.g[:] = [float(c) for c in d["g"]]
     p.newton_maxit = int(d.get("newton_maxit", 50))
+    p.force_mode = int(d.get("force_mode", 0))
     return p
 
 
 def params_dict(p: OracleParams) -> dict:
-    d = {k: getattr(p, k) for k, _ in OracleParams._fields_ if k not in ("g", "pad")}
+    d = {k: getattr(p, k) for k, _ in OracleParams._fields_ if k != "g"}
     d["g"] = list(p.g)
     return d
 

@@ -28,7 +28,10 @@
 //   volume-weighted mean of the bond states; backward-Euler Perzyna return in
 //   (p, q, p_c) with the hardening exponent signed as Eq. 46 requires;
 //   retention exponent -(n-1)/n with suction in kPa; J increment
-//   1/det(I - dt L_i); EOM sign of Eq. 33.
+//   1/det(I - dt L_i); EOM sign of Eq. 33; the force state of bond (i,k)
+//   collects the sub-horizon force states of all sub-horizons holding k
+//   (Eqs. 27, 31, 35), since keeping only the bond's own term (Eq. 51) with
+//   point-stored history is linearly unstable (flutter).
 
 #include <algorithm>
 #include <cmath>
@@ -85,6 +88,7 @@ struct Params {             // mirrors OracleParams below, in scalar type R
   double dt;
   double newton_tol;
   int newton_maxit;
+  int force_mode;           // 0: conjugate force states (default), 1: Eq. 51 as printed
 };
 
 template <class R>
@@ -313,6 +317,79 @@ void solve3(const R* A0, const R* b0, R* y) {
   }
 }
 
+// The same backward-Euler equations (Eqs. 70-75) written with the
+// consistency parameter dg = c f >= 0 (c = dt/eta):
+//   q   = q_tr / (1 + 6 mu dg / M^2),
+//   p   = (p_tr + K dg P) / (1 + 2 K dg),       so 2p - P = (2 p_tr - P)/(1 + 2 K dg),
+//   p_c = p_c,n exp(-dg (2 p_tr - P) / ((lam - kap)(1 + 2 K dg))),  P = P(p_c) (Eq. 45),
+//   dg  = c f(p, q, P).
+// For fixed dg the p_c equation is strictly increasing in p_c (slope >= 1);
+// dg - c f changes sign on [0, inf).  Both are bracketed, so this solve
+// cannot stall; it is used where Newton on (p, q, p_c) does.
+struct Bracketed {
+  double K, mu, M, lk, b1, b2, c, ptr, qtr, pcn;
+  double P(double pc) const { return -std::exp(b1) * std::pow(-pc, b2); }
+  double dP(double pc) const { return b2 * std::exp(b1) * std::pow(-pc, b2 - 1.0); }
+  // p_c for a given dg: safeguarded Newton inside a bracket [lo, hi) with hi = 0.
+  double pc_of(double dg) const {
+    const double A = dg / (lk * (1.0 + 2.0 * K * dg));
+    auto h = [&](double x) { return x - pcn * std::exp(-A * (2.0 * ptr - P(x))); };
+    double lo = pcn, hi = 0.0;
+    for (int k = 0; k < 4000 && h(lo) > 0.0; ++k) { hi = lo; lo *= 2.0; }
+    double x = pcn;
+    if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+      const double hx = h(x);
+      if (hx == 0.0) return x;
+      if (hx > 0.0) hi = x; else lo = x;
+      const double E = std::exp(-A * (2.0 * ptr - P(x)));
+      const double d = 1.0 - pcn * E * A * dP(x);
+      double xn = x - hx / d;
+      if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+      if (std::fabs(xn - x) <= 1e-16 * std::fabs(x) || hi - lo <= 1e-16 * std::fabs(lo)) return xn;
+      x = xn;
+    }
+    return x;
+  }
+  void state(double dg, double* x) const {
+    const double pc = pc_of(dg);
+    const double Pb = P(pc);
+    x[0] = (ptr + K * dg * Pb) / (1.0 + 2.0 * K * dg);
+    x[1] = qtr / (1.0 + 6.0 * mu * dg / (M * M));
+    x[2] = pc;
+  }
+  double phi(double dg) const {
+    double x[3];
+    state(dg, x);
+    const double f = x[1] * x[1] / (M * M) + x[0] * (x[0] - P(x[2]));
+    return dg - c * f;
+  }
+  // Illinois false position on phi over a doubling bracket.
+  void solve(double ftr, double* x) const {
+    double lo = 0.0, flo = -c * ftr;
+    double hi = c * ftr, fhi = phi(hi);
+    for (int k = 0; k < 2000 && fhi < 0.0; ++k) { lo = hi; flo = fhi; hi *= 2.0; fhi = phi(hi); }
+    int side = 0;
+    double dg = hi;
+    for (int it = 0; it < 300; ++it) {
+      dg = (lo * fhi - hi * flo) / (fhi - flo);
+      if (!(dg > lo && dg < hi)) dg = 0.5 * (lo + hi);
+      const double fm = phi(dg);
+      if (fm == 0.0 || hi - lo <= 2e-16 * hi) break;
+      if (fm > 0.0) {
+        hi = dg; fhi = fm;
+        if (side == 1) flo *= 0.5;
+        side = 1;
+      } else {
+        lo = dg; flo = fm;
+        if (side == -1) fhi *= 0.5;
+        side = -1;
+      }
+    }
+    state(dg, x);
+  }
+};
+
 // Local constitutive update (Section 3.2.1): elastic trial stress from the
 // strain increment (linear elasticity in invariants, Eq. 41, applied to the
 // increment), then, if the trial state violates the yield condition (Eq. 40),
@@ -344,13 +421,27 @@ int return_map(const Mat<R>& m, const Params& P, R dt, const R* sig_n, R pc_n, c
   double sref = std::max(std::fabs(val(ptr)), std::max(val(qtr), std::fabs(val(apparent_pc(m, pc_n)))));
   double pref = std::fabs(val(pc_n));
   int it = 0;
+  bool stalled = false;
   for (;;) {
     R r[3];
     rm_residual(m, c, ptr, qtr, pc_n, x, r);
     bool ok = std::fabs(val(r[0])) <= P.newton_tol * sref && std::fabs(val(r[1])) <= P.newton_tol * sref &&
               std::fabs(val(r[2])) <= P.newton_tol * pref;
     if (ok) break;
-    if (it >= P.newton_maxit) return -1;
+    if (it >= P.newton_maxit || stalled) {
+      // Newton stalled: solve the same equations by bracketing (see Bracketed).
+      Bracketed B{val(m.K), val(m.mu), val(m.M), val(m.lam) - val(m.kap), val(m.b1), val(m.b2),
+                  val(c), val(ptr), val(qtr), val(pc_n)};
+      double xb[3];
+      B.solve(val(ftr), xb);
+      for (int k = 0; k < 3; ++k) x[k] = xb[k];
+      rm_residual(m, c, ptr, qtr, pc_n, x, r);
+      if (!(std::fabs(val(r[0])) <= 1e3 * P.newton_tol * sref && std::fabs(val(r[1])) <= 1e3 * P.newton_tol * sref &&
+            std::fabs(val(r[2])) <= 1e3 * P.newton_tol * pref))
+        return -1;
+      it = P.newton_maxit + 1;
+      break;
+    }
     R A[9], dx[3], nr[3] = {-r[0], -r[1], -r[2]};
     rm_jacobian(m, c, pc_n, x, A);
     solve3(A, nr, dx);
@@ -368,6 +459,7 @@ int return_map(const Mat<R>& m, const Params& P, R dt, const R* sig_n, R pc_n, c
     }
     for (int k = 0; k < 3; ++k) x[k] += step * dx[k];
     ++it;
+    stalled = val(step) < 1e-6;
   }
   if constexpr (std::is_same<R, Dual>::value) {
     // One more Newton step at the converged point: the value moves by
@@ -514,6 +606,7 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
     for (int64_t s = b0; s < b1; ++s) Vh += S.vol[F.col[s]];
     R hs[6] = {0, 0, 0, 0, 0, 0}, hpc = 0.0, hw = 0.0;
     const R* sig_i = &S.sig[6 * i];
+    std::vector<R> SKb(9 * (b1 - b0), R(0.0));   // (V_j/V_H) (sigma_ij + S_r s 1) K_ij^{-1}
     for (int64_t s = b0; s < b1; ++s) {
       const int64_t j = F.col[s];
       R Kij[6] = {0, 0, 0, 0, 0, 0}, Nij[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vs = 0.0;
@@ -568,20 +661,47 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
       }
       for (int k = 0; k < 6; ++k) O.sig[6 * s + k] = sb[k];
       O.pc[s] = pcb;
-      // Total force state: varpi (sigma + S_r s 1) K^{-1} zeta_ij.
-      R z[3], w[3];
-      for (int c = 0; c < 3; ++c) z[c] = x[3 * j + c] - x[3 * i + c];
-      for (int r = 0; r < 3; ++r) w[r] = Kinv[3 * r + 0] * z[0] + Kinv[3 * r + 1] * z[1] + Kinv[3 * r + 2] * z[2];
-      R sF[9];
+      // Total stress of the bond, sigma_ij + S_r s 1 (Eq. 32 with p_w = -s),
+      // times K_ij^{-1}.
+      R sF[9], SK[9];
       sym_to_full(sb, sF);
       R ps = O.Sr_new[i] * S.s[i];
-      for (int r = 0; r < 3; ++r)
-        O.T[3 * s + r] = varpi * (sF[3 * r + 0] * w[0] + sF[3 * r + 1] * w[1] + sF[3 * r + 2] * w[2] + ps * w[r]);
+      for (int k = 0; k < 3; ++k) sF[4 * k] += ps;
+      matmul3(sF, Kinv, SK);
+      if (P.force_mode == 1) {
+        // Eq. 51 as printed: T_ij = varpi (sigma + S_r s 1) K^{-1} zeta_ij.
+        R z[3];
+        for (int c = 0; c < 3; ++c) z[c] = x[3 * j + c] - x[3 * i + c];
+        for (int r = 0; r < 3; ++r)
+          O.T[3 * s + r] = varpi * (SK[3 * r + 0] * z[0] + SK[3 * r + 1] * z[1] + SK[3 * r + 2] * z[2]);
+      } else {
+        for (int k = 0; k < 9; ++k) SKb[9 * (s - b0) + k] = SK[k] * (S.vol[j] / Vh);
+      }
       // Point history: volume-weighted mean of the bond states.
       R Vj = S.vol[j];
       for (int k = 0; k < 6; ++k) hs[k] += Vj * sb[k];
       hpc += Vj * pcb;
       hw += Vj;
+    }
+    if (P.force_mode == 0) {
+      // Force state of bond (i,k): the sub-horizon force state of every
+      // sub-horizon S_ij that holds k, evaluated on bond ik (Eqs. 27, 31),
+      // summed over those sub-horizons as in the double integral of Eq. 35.
+      // Its power, sum_k V_k T_ik . Ydot_ik, is the volume-weighted mean of
+      // sigma_ij : L_ij over the bonds of i, the same mean that updates the
+      // point history.
+      for (int64_t t = b0; t < b1; ++t) {
+        const int64_t k = F.col[t];
+        R acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t s = b0; s < b1; ++s) {
+          const int64_t j = F.col[s];
+          if (!(r2(&xval[3 * j], &xval[3 * k]) <= d2)) continue;
+          for (int q = 0; q < 9; ++q) acc[q] += SKb[9 * (s - b0) + q];
+        }
+        R z[3];
+        for (int c = 0; c < 3; ++c) z[c] = x[3 * k + c] - x[3 * i + c];
+        for (int r = 0; r < 3; ++r) O.T[3 * t + r] = acc[3 * r] * z[0] + acc[3 * r + 1] * z[1] + acc[3 * r + 2] * z[2];
+      }
     }
     if (val(hw) > 0.0) {
       for (int k = 0; k < 6; ++k) O.sig_new[6 * i + k] = hs[k] / hw;
@@ -704,7 +824,7 @@ typedef struct {
   double dt;
   double newton_tol;
   int32_t newton_maxit;
-  int32_t pad;
+  int32_t force_mode;
 } OracleParams;
 
 typedef struct {             // host arrays, caller order
@@ -730,6 +850,7 @@ static Params to_params(const OracleParams* p) {
   P.dt = p->dt;
   P.newton_tol = p->newton_tol;
   P.newton_maxit = p->newton_maxit;
+  P.force_mode = p->force_mode;
   return P;
 }
 

@@ -60,6 +60,7 @@ struct DevParams {
   double dt;
   double newton_tol;
   int newton_maxit;
+  int force_mode;
 };
 
 struct Grid {                 // cell grid over the current bounding box
@@ -453,6 +454,62 @@ __device__ double swrc(const DevParams& P, double J, double phi, double s) {
   return pow(1.0 + pow(arg, P.n_vg), -(P.n_vg - 1.0) / P.n_vg);
 }
 
+// Where Newton stalls, the same backward-Euler equations are solved through
+// the consistency parameter g = c f >= 0.  With it q = q_tr/(1 + 6 mu g/M^2),
+// p = (p_tr + K g P)/(1 + 2 K g) (hence 2p - P = (2 p_tr - P)/(1 + 2 K g)) and
+// p_c solves p_c = p_c,n exp(-g (2 p_tr - P(p_c)) / ((lam - kap)(1 + 2 K g))),
+// a strictly increasing equation in p_c; g itself is the root of
+// g - c f(p, q, P) on [0, inf), where it changes sign once.
+struct ConsistencySolve {
+  double K, mu, M2, lk, b1, b2, c, ptr, qtr, pcn;
+  __device__ double Pb(double pc) const { return -exp(b1) * pow(-pc, b2); }
+  __device__ double pc_for(double g) const {
+    const double A = g / (lk * (1.0 + 2.0 * K * g));
+    double hi = 0.0, lo = pcn;
+    for (int k = 0; k < 4000; ++k) {             // bracket: h(lo) <= 0 < h(0-)
+      if (lo - pcn * exp(-A * (2.0 * ptr - Pb(lo))) <= 0.0) break;
+      hi = lo;
+      lo *= 2.0;
+    }
+    double x = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+      const double E = exp(-A * (2.0 * ptr - Pb(x)));
+      const double h = x - pcn * E;
+      if (h > 0.0) hi = x; else lo = x;
+      const double dh = 1.0 - pcn * E * A * b2 * exp(b1) * pow(-x, b2 - 1.0);
+      double xn = x - h / dh;
+      if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+      const bool done = fabs(xn - x) <= 1e-16 * fabs(x);
+      x = xn;
+      if (done || hi - lo <= 1e-16 * fabs(lo)) break;
+    }
+    return x;
+  }
+  __device__ void at(double g, double* x) const {
+    x[2] = pc_for(g);
+    x[0] = (ptr + K * g * Pb(x[2])) / (1.0 + 2.0 * K * g);
+    x[1] = qtr / (1.0 + 6.0 * mu * g / M2);
+  }
+  __device__ double resid(double g) const {
+    double x[3];
+    at(g, x);
+    return g - c * (x[1] * x[1] / M2 + x[0] * (x[0] - Pb(x[2])));
+  }
+  __device__ void solve(double ftr, double* x) const {
+    double lo = 0.0, hi = c * ftr, rlo = -c * ftr, rhi = resid(hi);
+    for (int k = 0; k < 2000 && rhi < 0.0; ++k) { lo = hi; rlo = rhi; hi *= 2.0; rhi = resid(hi); }
+    for (int it = 0; it < 400 && hi - lo > 2e-16 * hi; ++it) {
+      // secant inside the bracket once it is narrow, bisection before
+      double g = (hi - lo > 1e-3 * hi) ? 0.5 * (lo + hi) : lo - rlo * (hi - lo) / (rhi - rlo);
+      if (!(g > lo && g < hi)) g = 0.5 * (lo + hi);
+      const double r = resid(g);
+      if (r == 0.0) { lo = hi = g; break; }
+      if (r > 0.0) { hi = g; rhi = r; } else { lo = g; rlo = r; }
+    }
+    at(0.5 * (lo + hi), x);
+  }
+};
+
 // Backward-Euler Perzyna update in the invariants (Eqs. 70-76): residuals
 // r1 = p - p_tr + K c f f_p, r2 = q - q_tr + 3 mu c f f_q,
 // r3 = p_c - p_c,n exp(-c f f_p / (lam - kap)) with c = dt/eta, solved by
@@ -484,7 +541,7 @@ __device__ int return_map(const DevParams& P, double dt, const double* sn, doubl
   const double pref = fabs(pcn);
   double p = ptr, q = qtr, pc = pcn;
   int it = 0;
-  bool conv = false;
+  bool conv = false, stalled = false;
   for (;;) {
     const double Pb = apparent_pc(P, pc);
     const double dP = P.b2 * exp(P.b1) * pow(-pc, P.b2 - 1.0);   // Eq. 89
@@ -498,7 +555,23 @@ __device__ int return_map(const DevParams& P, double dt, const double* sn, doubl
       conv = true;
       break;
     }
-    if (it >= P.newton_maxit) break;
+    if (it >= P.newton_maxit || stalled) {
+      ConsistencySolve B{P.K, P.mu, M2, lk, P.b1, P.b2, c, ptr, qtr, pcn};
+      double xb[3];
+      B.solve(yield_f(P, ptr, qtr, Pn), xb);
+      p = xb[0];
+      q = xb[1];
+      pc = xb[2];
+      const double Pb2 = apparent_pc(P, pc);
+      const double f2 = yield_f(P, p, q, Pb2), fp2 = 2.0 * p - Pb2;
+      const double e1 = p - ptr + P.K * c * f2 * fp2;
+      const double e2 = q - qtr + 3.0 * P.mu * c * f2 * 2.0 * q / M2;
+      const double e3 = pc - pcn * exp(-c * f2 * fp2 / lk);
+      conv = fabs(e1) <= 1e3 * P.newton_tol * sref && fabs(e2) <= 1e3 * P.newton_tol * sref &&
+             fabs(e3) <= 1e3 * P.newton_tol * pref;
+      it = P.newton_maxit + 1;
+      break;
+    }
     // d(f fp)/dx and d(f fq)/dx
     const double gp = fp * fp + 2.0 * f, gq = fq * fp, gc = fc * fp - f * dP;
     const double hp = fp * fq, hq = fq * fq + f * 2.0 / M2, hc = fc * fq;
@@ -523,6 +596,7 @@ __device__ int return_map(const DevParams& P, double dt, const double* sn, doubl
     q += stp * dx2;
     pc += stp * dx3;
     ++it;
+    stalled = stp < 1e-6;
   }
   const double ratio = qtr > 0.0 ? q / qtr : 0.0;
 #pragma unroll
@@ -578,8 +652,11 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
   const int64_t n = A.n;
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
+  const int nw = (mf + 63) / 64;                   // membership words per row
   double* sx = smem;                               // 3*mf  x_k (FP64: exact predicate)
-  Acc* sz = reinterpret_cast<Acc*>(sx + 3 * mf);   // 3*mf  zeta_ik = x_k - x_i
+  double* sM = sx + 3 * mf;                        // 9*mf  (V_j/V_H)(sigma_ij + S_r s 1) K_ij^{-1}
+  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sM + 9 * mf);  // mf*nw S_ij rows
+  Acc* sz = reinterpret_cast<Acc*>(sb + (size_t)mf * nw);  // 3*mf  zeta_ik = x_k - x_i
   Acc* sy = sz + 3 * mf;                           // 3*mf  ydot_ik = v_k - v_i
   Acc* sv = sy + 3 * mf;                           // mf    V_k
   __shared__ double red[2][24];
@@ -673,10 +750,16 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
     Acc K0 = 0, K1 = 0, K2 = 0, K3 = 0, K4 = 0, K5 = 0;
     Acc N00 = 0, N01 = 0, N02 = 0, N10 = 0, N11 = 0, N12 = 0, N20 = 0, N21 = 0, N22 = 0, Vs = 0;
     int ns = 0;
+    unsigned long long word = 0ull;
     for (int t = 0; t < nf; ++t) {
       const bool in = within(xj0, xj1, xj2, sx[t], sx[mf + t], sx[2 * mf + t], d2);
       const Acc w = in ? sv[t] : (Acc)0;
       ns += in ? 1 : 0;
+      word |= (unsigned long long)in << (t & 63);
+      if ((t & 63) == 63 || t == nf - 1) {
+        sb[(size_t)m * nw + (t >> 6)] = word;
+        word = 0ull;
+      }
       const Acc z0 = sz[t], z1 = sz[mf + t], z2 = sz[2 * mf + t];
       const Acc w0 = w * z0, w1 = w * z1, w2 = w * z2;
       K0 += w0 * z0; K1 += w1 * z1; K2 += w2 * z2;
@@ -695,7 +778,9 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
     const int64_t slot = b0 + m;
     if (ns < 3 || !(dK > 1e-12 * tk * tk * tk)) {               // degenerate: inactive bond
       ++n_deg;
-      A.T[0][slot] = 0.0; A.T[1][slot] = 0.0; A.T[2][slot] = 0.0;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) sM[q * mf + m] = 0.0;
+      if (P.force_mode == ULPPM_FORCE_EQ51) { A.T[0][slot] = 0.0; A.T[1][slot] = 0.0; A.T[2][slot] = 0.0; }
       continue;
     }
     const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
@@ -713,32 +798,68 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
     const double h = A.dt_inc;
     const double de[6] = {h * L[0], h * L[4], h * L[8], h * 0.5 * (L[5] + L[7]), h * 0.5 * (L[2] + L[6]),
                           h * 0.5 * (L[1] + L[3])};              // Eqs. 26, 59
-    double sb[6], pcb;
+    double sgb[6], pcb;
     if (h == 0.0) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) sb[k] = sig_i[k];
+      for (int k = 0; k < 6; ++k) sgb[k] = sig_i[k];
       pcb = pc_i;
     } else {
-      int it = return_map(P, h, sig_i, pc_i, de, sb, &pcb);
+      int it = return_map(P, h, sig_i, pc_i, de, sgb, &pcb);
       if (it < 0) { ++n_nc; it = P.newton_maxit; }
       if (it > 0) ++n_pl;
       mx = mx > it ? mx : it;
     }
-    // T_ij = varpi (sigma_ij + Sr_i s_i 1) K_ij^{-1} zeta_ij  (Eq. 32 with p_w = -s)
-    const double zx = xj0 - xi0, zy = xj1 - xi1, zz = xj2 - xi2;
-    const double w0 = ixx * zx + ixy * zy + ixz * zz;
-    const double w1 = ixy * zx + iyy * zy + iyz * zz;
-    const double w2 = ixz * zx + iyz * zy + izz * zz;
+    // Total bond stress sigma_ij + Sr_i s_i 1 (Eq. 32 with p_w = -s) times K_ij^{-1}.
     const double ps = Sr_i * s_i;
-    A.T[0][slot] = varpi * ((sb[0] + ps) * w0 + sb[5] * w1 + sb[4] * w2);
-    A.T[1][slot] = varpi * (sb[5] * w0 + (sb[1] + ps) * w1 + sb[3] * w2);
-    A.T[2][slot] = varpi * (sb[4] * w0 + sb[3] * w1 + (sb[2] + ps) * w2);
-    // point history: volume-weighted mean of the bond states
+    const double S00 = sgb[0] + ps, S11 = sgb[1] + ps, S22 = sgb[2] + ps;
+    const double SK[9] = {S00 * ixx + sgb[5] * ixy + sgb[4] * ixz, S00 * ixy + sgb[5] * iyy + sgb[4] * iyz,
+                          S00 * ixz + sgb[5] * iyz + sgb[4] * izz, sgb[5] * ixx + S11 * ixy + sgb[3] * ixz,
+                          sgb[5] * ixy + S11 * iyy + sgb[3] * iyz, sgb[5] * ixz + S11 * iyz + sgb[3] * izz,
+                          sgb[4] * ixx + sgb[3] * ixy + S22 * ixz, sgb[4] * ixy + sgb[3] * iyy + S22 * iyz,
+                          sgb[4] * ixz + sgb[3] * iyz + S22 * izz};
     const double Vj = A.vol_n[A.col[slot]];
+    if (P.force_mode == ULPPM_FORCE_EQ51) {
+      // Eq. 51 as printed: T_ij = varpi (sigma_ij + Sr s 1) K_ij^{-1} zeta_ij.
+      const double zx = xj0 - xi0, zy = xj1 - xi1, zz = xj2 - xi2;
+      A.T[0][slot] = varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz);
+      A.T[1][slot] = varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz);
+      A.T[2][slot] = varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz);
+    } else {
+      const double wj = Vj / Vh;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) hs[k] += Vj * sb[k];
+      for (int q = 0; q < 9; ++q) sM[q * mf + m] = wj * SK[q];
+    }
+    // point history: volume-weighted mean of the bond states
+#pragma unroll
+    for (int k = 0; k < 6; ++k) hs[k] += Vj * sgb[k];
     hpc += Vj * pcb;
     hw += Vj;
+  }
+  if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
+    // Force state of bond (i,k): the sub-horizon force state of every
+    // sub-horizon S_ij holding k, evaluated on bond ik (Eqs. 27, 31), summed
+    // as in the double integral of Eq. 35.  Membership is symmetric, so lane
+    // k reads row k of the bit matrix written in the first pass.
+    __syncthreads();
+    for (int m = tid; m < nf; m += kBondThreads) {
+      double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0, a8 = 0;
+      for (int j0 = 0; j0 < nf; j0 += 64) {
+        unsigned long long word = sb[(size_t)m * nw + (j0 >> 6)];
+        const int jn = nf - j0 < 64 ? nf - j0 : 64;
+        for (int jj = 0; jj < jn; ++jj) {
+          const double w = (word >> jj) & 1ull ? 1.0 : 0.0;
+          const int j = j0 + jj;
+          a0 += w * sM[j]; a1 += w * sM[mf + j]; a2 += w * sM[2 * mf + j];
+          a3 += w * sM[3 * mf + j]; a4 += w * sM[4 * mf + j]; a5 += w * sM[5 * mf + j];
+          a6 += w * sM[6 * mf + j]; a7 += w * sM[7 * mf + j]; a8 += w * sM[8 * mf + j];
+        }
+      }
+      const double zx = sx[m] - xi0, zy = sx[mf + m] - xi1, zz = sx[2 * mf + m] - xi2;
+      const int64_t slot = b0 + m;
+      A.T[0][slot] = a0 * zx + a1 * zy + a2 * zz;
+      A.T[1][slot] = a3 * zx + a4 * zy + a5 * zz;
+      A.T[2][slot] = a6 * zx + a7 * zy + a8 * zz;
+    }
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) hs[k] = wave_sum(hs[k]);
@@ -1017,6 +1138,7 @@ DevParams dev_params(const ulppm_params* p) {
   d.dt = p->dt;
   d.newton_tol = p->newton_tol;
   d.newton_maxit = p->newton_maxit;
+  d.force_mode = p->force_mode;
   return d;
 }
 
@@ -1039,6 +1161,8 @@ int check_params(ulppm_ctx* ctx, const ulppm_params* p) {
     return fail(ctx, ULPPM_E_ARG, "material constants out of range");
   if (p->newton_maxit < 1 || p->newton_maxit > 1000) return fail(ctx, ULPPM_E_ARG, "newton_maxit out of range");
   if (p->precision != ULPPM_FP64 && p->precision != ULPPM_MIXED) return fail(ctx, ULPPM_E_ARG, "bad precision");
+  if (p->force_mode != ULPPM_FORCE_CONJUGATE && p->force_mode != ULPPM_FORCE_EQ51)
+    return fail(ctx, ULPPM_E_ARG, "bad force_mode");
   return ULPPM_OK;
 }
 
@@ -1096,7 +1220,9 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta) {
 }
 
 size_t bond_lds(int max_f, bool mixed) {
-  return (size_t)max_f * (3 * sizeof(double) + 7 * (mixed ? sizeof(float) : sizeof(double)));
+  const size_t nw = (size_t)(max_f + 63) / 64;
+  return (size_t)max_f * (12 * sizeof(double) + nw * sizeof(unsigned long long) +
+                          7 * (mixed ? sizeof(float) : sizeof(double)));
 }
 
 // Algorithm 1 (bond pass) into outputs; mode: step (state outputs) or not.
@@ -1220,7 +1346,7 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   if (!out) return ULPPM_E_ARG;
   *out = nullptr;
   if (n_points <= 0 || n_points > 2147483647LL) return ULPPM_E_ARG;
-  if (max_family == 0) max_family = 256;
+  if (max_family == 0) max_family = 192;
   if (max_family < 8 || max_family > 1024) return ULPPM_E_ARG;
   ctx = new ulppm_ctx();
   ctx->stream = (hipStream_t)hip_stream;

@@ -28,7 +28,7 @@ class Params(C.Structure):
                 ("b2", C.c_double), ("rho_s", C.c_double), ("rho_w", C.c_double), ("a1", C.c_double),
                 ("a2", C.c_double), ("n_vg", C.c_double), ("g", C.c_double * 3), ("dt", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("precision", C.c_int32),
-                ("energy_check", C.c_int32), ("pad", C.c_int32), ("energy_tol", C.c_double)]
+                ("energy_check", C.c_int32), ("force_mode", C.c_int32), ("energy_tol", C.c_double)]
 
 
 class State(C.Structure):
@@ -100,6 +100,7 @@ def make_params(prm: dict, precision: int = ULPPM_FP64, **over) -> Params:
     p.precision = int(d.get("precision", precision))
     p.energy_check = int(d.get("energy_check", 0))
     p.energy_tol = float(d.get("energy_tol", 1e-2))
+    p.force_mode = int(d.get("force_mode", 0))
     return p
 
 
@@ -174,7 +175,7 @@ class DeviceState:
 class Context:
     """One ulppm context (scratch for up to n points) on the current stream."""
 
-    def __init__(self, n_points: int, max_family: int = 256, stream=None):
+    def __init__(self, n_points: int, max_family: int = 192, stream=None):
         import torch
         self.L = load_library()
         if stream is None:

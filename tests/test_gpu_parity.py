@@ -218,3 +218,44 @@ def test_ragged_small_columns(olib, gpu):
         rc, E, st = olib.step(S, oprm, 5)
         ctx.step(G, gprm, 5)
         compare_states(G.to_arrays(), S, 1e-11, fields=("u", "v", "sig", "pc", "J"), label=str(dims))
+
+
+def test_stiff_return_map_fallback(olib, gpu):
+    """Uniform hardened stress and a linear velocity field whose strain
+    increment is large enough that Newton on (p, q, p_c) stalls at every bond:
+    both sides fall back to the bracketed consistency-parameter solve."""
+    say("stiff return map")
+    col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, (6, 6, 6), seed=6)
+    sig = np.array([-399233.9451, -525329.6268, -366804.7115, -15105.1289, -5572.4562, -85528.3165])
+    de = np.array([-1.08648554e-03, -4.39455193e-03, 6.53503415e-05, -2.07182754e-04, -5.49232006e-05,
+                   -2.15806964e-03])
+    dt = 2.8489275e-05
+    A = np.array([[de[0], de[5], de[4]], [de[5], de[1], de[3]], [de[4], de[3], de[2]]]) / dt
+    S["sig"][:] = sig
+    S["pc"][:] = -509704.8096
+    x = S["x0"] + S["u"]
+    S["v"][:] = x @ A.T
+    G = gpu.DeviceState.from_arrays(S)
+    out = olib.bond_fields(S, oprm, dt)
+    f, T, rep = ctx.forces(G, gprm, dt, want_T=True)
+    say("max newton", out["stats"]["max_newton"], rep["max_newton"], "noconv", rep["n_noconv"])
+    assert out["stats"]["max_newton"] > oprm.newton_maxit and rep["max_newton"] > gprm.newton_maxit
+    assert rep["n_noconv"] == 0 and out["stats"]["n_noconv"] == 0
+    Tg = T.cpu().numpy().T
+    assert np.abs(Tg - out["T"]).max() <= 1e-10 * np.abs(out["T"]).max()
+
+
+def test_eq51_force_mode_parity(olib, gpu):
+    """Eq. 51 as printed (the bond's own term only): same parity bar over a
+    short run, before its flutter grows."""
+    say("eq51 mode")
+    col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, (8, 8, 12), seed=1, vscale=0.1)
+    oprm.force_mode = 1
+    gprm.force_mode = 1
+    out = olib.bond_fields(S, oprm, oprm.dt)
+    f, T, rep = ctx.forces(G, gprm, oprm.dt, want_T=True)
+    assert np.abs(T.cpu().numpy().T - out["T"]).max() <= 1e-11 * np.abs(out["T"]).max()
+    rc, E, st = olib.step(S, oprm, 20)
+    assert rc == 0
+    ctx.step(G, gprm, 20)
+    compare_states(G.to_arrays(), S, 1e-11, fields=("u", "v", "sig", "pc", "J"), label="eq51 20 steps")
