@@ -1,0 +1,164 @@
+"""Throughput of the explicit UL-PPM step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C1] [--precision fp64|mixed]
+
+A step is one whole explicit Newmark step through the C ABI (predictor,
+family rebuild, bond kernel, gather/corrector, energies) on a seeded
+synthetic soil column whose state is resident in HBM.  The metric is
+bond-updates/s: directed bonds taken through one step, summed over the K
+timed steps, divided by the wall time of those steps (HIP events on the
+stream the library runs on).  Prints exactly one JSON line on stdout;
+progress goes to stderr.
+
+The roofline object describes the dominant kernel, k_bond, bound by the
+vector ALU: algorithmic FP64 flops per launch over its average launch
+duration, measured with HIP events around every launch in the timed region.
+Algorithmic flops per launch:
+    8  per sub-horizon membership test           (sum_i |H_i|^2)
+    43 per sub-horizon member                    (sum |S_ij|; 34 for the
+       shape tensor, gradient and volume sums, 9 for the force-state sum)
+    284 per bond                                 (34 full-horizon sums,
+       250 for inversion, gradient, trial stress, yield check, force state)
+Newton iterations of the return map are not counted.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOPS_PER_TEST = 8.0
+FLOPS_PER_MEMBER = 43.0
+FLOPS_PER_BOND = 284.0
+PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64 (and FP32 without packing)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    with open(os.path.join(ROOT, "paper_2203_05562_amd", "csrc", "ulppm.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(config, precision):
+    """HBM bytes per k_bond launch from the committed counter summary, if it
+    was taken on the current kernel source for this workload; else None."""
+    path = os.path.join(ROOT, "profiles", "k_bond_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    key = f"{config}_{precision}"
+    e = d.get(key)
+    if not e or e.get("source_sha") != kernel_source_sha():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg_name, steps, dt):
+    """The oracle as it stands, on the host cores, for a bounded sample."""
+    import numpy as np
+    import oracle
+    from paper_2203_05562_amd import inputs
+    cfg = inputs.CONFIGS[cfg_name]
+    col = inputs.make_column(cfg)
+    prm = oracle.make_params(col["params"])
+    t0 = time.time()
+    S = oracle.init_column(col, prm, col["params"]["ocr"])
+    log(f"[cpu] oracle initial state {time.time() - t0:.1f}s")
+    prm.dt = dt
+    t0 = time.perf_counter()
+    rc, E, st = oracle.step(S, prm, steps)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    log(f"[cpu] oracle {steps} steps {el:.1f}s rc={rc} bonds={st['n_bonds']}")
+    return dict(value=st["n_bonds"] / el, unit="bond-updates/s", cores=cores, kind="oracle",
+                sample=f"{steps} full explicit steps of the {cfg.nx}x{cfg.ny}x{cfg.nz} column "
+                       f"({col['n']} points, {st['n_bonds']} bond-updates) from its initial state",
+                seconds=round(el, 3))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="C1")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_05562_amd import inputs, ulppm
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = inputs.CONFIGS[args.config]
+    col = inputs.make_column(cfg)
+    n = col["n"]
+    log(f"[gpu] {args.config}: {cfg.nx}x{cfg.ny}x{cfg.nz} = {n} points, suction {col['suction_kpa']:.2f} kPa")
+    prec = ulppm.ULPPM_MIXED if args.precision == "mixed" else ulppm.ULPPM_FP64
+    G = ulppm.column_state(col, "cuda:0")
+    prm = ulppm.make_params(col["params"], precision=prec)
+    ctx = ulppm.Context(n)
+    ctx.init_state(G, prm, col["params"]["ocr"])
+    prm.dt = 0.5 * ctx.dt_crit(G, prm)
+    log(f"[gpu] dt = {prm.dt:.4e} s; warmup {args.warmup} steps")
+    if args.warmup:
+        ctx.step(G, prm, args.warmup)
+    torch.cuda.synchronize()
+    prm.timing = 1
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    rep = ctx.step(G, prm, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    log(f"[gpu] timed {args.steps} steps: {ms:.1f} ms; report {rep}")
+    bonds = rep["n_bond_updates"]
+    value = bonds / (ms * 1e-3)
+    launches = rep["timed_steps"]
+    t_bond = rep["t_bond_ms"] / max(launches, 1) * 1e-3
+    flops_per_launch = (FLOPS_PER_TEST * rep["n_tests"] + FLOPS_PER_MEMBER * rep["n_triples"] +
+                        FLOPS_PER_BOND * bonds) / args.steps
+    achieved = flops_per_launch / t_bond / 1e12
+    traffic = measured_traffic(args.config, args.precision)
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_VALU_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_FP64_VALU_TFLOPS, 4), traffic=traffic,
+                    kernel="k_bond", avg_launch_ms=round(t_bond * 1e3, 4),
+                    flops_per_launch=flops_per_launch)
+    phases = {k: round(rep[f"t_{k}_ms"] / max(launches, 1), 4) for k in ("predict", "family", "bond", "gather")}
+    out = dict(metric="bond-updates/s per Newmark step", value=value, unit="bond-updates/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f64" if args.precision == "fp64" else "f32+f64",
+               data="synthetic",
+               config=dict(workload=f"{args.config}: jittered soil column {cfg.nx}x{cfg.ny}x{cfg.nz}, "
+                                    f"{args.precision}", points=n, bonds_per_step=bonds / args.steps,
+                           dt=prm.dt, suction_kpa=col["suction_kpa"], seed=cfg.seed, precision=args.precision),
+               roofline=roofline, phase_ms=phases)
+    del ctx
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps, prm.dt)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

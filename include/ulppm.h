@@ -77,6 +77,8 @@ typedef struct {
   int32_t energy_check;         /* nonzero: check Eq. 69 at the end of ulppm_step */
   int32_t force_mode;           /* ULPPM_FORCE_CONJUGATE or ULPPM_FORCE_EQ51 */
   double energy_tol;            /* epsilon of Eq. 69 (the paper uses ~1e-2) */
+  int32_t timing;               /* nonzero: time each phase of ulppm_step with HIP events */
+  int32_t pad;
 } ulppm_params;
 
 /* Point state: caller-owned device arrays of length n (SoA). */
@@ -104,6 +106,12 @@ typedef struct {
   int64_t n_triples;            /* sub-horizon members visited (sum |S_ij|), summed */
   int64_t max_family;           /* largest family of the last rebuild */
   int64_t steps;                /* steps taken by the call */
+  int64_t n_bond_updates;       /* directed bonds summed over the call's steps */
+  int64_t timed_steps;          /* steps covered by the phase timings (p->timing) */
+  double t_predict_ms;          /* summed HIP-event durations per phase over timed steps */
+  double t_family_ms;
+  double t_bond_ms;
+  double t_gather_ms;
 } ulppm_report;
 
 /* Create a context for up to n_points points and max_family members per family

@@ -49,8 +49,10 @@ constexpr int64_t kPartGather = 10240;  // gather energy partials, 3 per block
 // Device counters, zeroed at the start of every API call.
 enum Ctr {
   C_DEGEN = 0, C_PLASTIC, C_MAXNEWTON, C_NOCONV, C_TESTS, C_TRIPLES, C_OVERFLOW,
-  C_NONFINITE, C_MAXFAM, C_NCOUNT = 16
+  C_NONFINITE, C_MAXFAM, C_BONDSUM, C_NCOUNT = 16
 };
+constexpr int kTimedSteps = 256;    // steps per call covered by phase timings
+constexpr int kPhases = 4;          // predict, family, bond, gather
 
 struct DevParams {
   double delta, d2;
@@ -988,7 +990,8 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
 // Deterministic energy totals: one block sums the per-block partials of the
 // predictor (2 per block) and of the gather (3 per block) in a fixed order.
 __global__ void k_energy(const double* __restrict__ pp, int npb, const double* __restrict__ gp, int ngb,
-                         double* __restrict__ E) {
+                         double* __restrict__ E, const int64_t* __restrict__ row, int64_t n,
+                         unsigned long long* __restrict__ ctr) {
   __shared__ double s[3][256];
   double a = 0.0, b = 0.0, c = 0.0;
   for (int k = threadIdx.x; k < npb; k += 256) { a += pp[2 * k]; b += pp[2 * k + 1]; }
@@ -1004,6 +1007,7 @@ __global__ void k_energy(const double* __restrict__ pp, int npb, const double* _
     E[0] += s[0][0];
     E[1] += s[1][0];
     E[2] = s[2][0];
+    ctr[C_BONDSUM] += (unsigned long long)row[n];   // single thread, stream-ordered
   }
 }
 
@@ -1108,6 +1112,9 @@ struct ulppm_ctx {
   Grid* grid = nullptr;
   unsigned long long* ctr = nullptr;
   double* E = nullptr;        // 3
+  // phase timing events, [step][phase][start/stop]
+  hipEvent_t ev[kTimedSteps][kPhases][2] = {};
+  bool have_events = false;
   // host mirrors
   unsigned long long h_ctr[C_NCOUNT];
   std::string err;
@@ -1333,6 +1340,25 @@ void fill_report(ulppm_ctx* ctx, int64_t n, ulppm_report* rep, int64_t steps) {
   rep->n_triples = (int64_t)ctx->h_ctr[C_TRIPLES];
   rep->max_family = (int64_t)ctx->h_ctr[C_MAXFAM];
   rep->steps = steps;
+  rep->n_bond_updates = (int64_t)ctx->h_ctr[C_BONDSUM];
+  rep->timed_steps = 0;
+  rep->t_predict_ms = rep->t_family_ms = rep->t_bond_ms = rep->t_gather_ms = 0.0;
+}
+
+// Sum the phase durations of the timed steps of the last ulppm_step call.
+void add_timings(ulppm_ctx* ctx, int64_t timed, ulppm_report* rep) {
+  if (!rep || timed <= 0) return;
+  double t[kPhases] = {0, 0, 0, 0};
+  for (int64_t k = 0; k < timed; ++k)
+    for (int ph = 0; ph < kPhases; ++ph) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ctx->ev[k][ph][0], ctx->ev[k][ph][1]) == hipSuccess) t[ph] += ms;
+    }
+  rep->timed_steps = timed;
+  rep->t_predict_ms = t[0];
+  rep->t_family_ms = t[1];
+  rep->t_bond_ms = t[2];
+  rep->t_gather_ms = t[3];
 }
 
 }  // namespace
@@ -1390,6 +1416,15 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
     return ULPPM_E_HIP;
   }
   k_fill<double><<<1, 64, 0, ctx->stream>>>(ctx->E, 3, 0.0);
+  ctx->have_events = true;
+  for (int k = 0; k < kTimedSteps && ctx->have_events; ++k)
+    for (int ph = 0; ph < kPhases; ++ph)
+      for (int b = 0; b < 2; ++b)
+        if (hipEventCreate(&ctx->ev[k][ph][b]) != hipSuccess) ctx->have_events = false;
+  if (!ctx->have_events) {
+    ulppm_destroy(ctx);
+    return ULPPM_E_HIP;
+  }
   // the bond kernel's dynamic LDS may exceed the default cap for large max_family
   (void)hipFuncSetAttribute((const void*)k_bond<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bond_lds(max_family, false));
@@ -1412,6 +1447,11 @@ int ulppm_destroy(ulppm_ctx* ctx) {
                   ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->E};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (ctx->have_events)
+    for (int k = 0; k < kTimedSteps; ++k)
+      for (int ph = 0; ph < kPhases; ++ph)
+        for (int b = 0; b < 2; ++b)
+          if (ctx->ev[k][ph][b]) (void)hipEventDestroy(ctx->ev[k][ph][b]);
   delete ctx;
   return ULPPM_OK;
 }
@@ -1545,19 +1585,32 @@ int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_
   if ((rc = zero_counters(ctx))) return rc;
   DevParams P = dev_params(p);
   const int npb = blocks_for(n, 256, 2048);
+  const int64_t timed = p->timing ? std::min<int64_t>(n_steps, kTimedSteps) : 0;
+  auto mark = [&](int64_t k, int ph, int b) {
+    if (k < timed) (void)hipEventRecord(ctx->ev[k][ph][b], ctx->stream);
+  };
   for (int32_t k = 0; k < n_steps; ++k) {
+    mark(k, 0, 0);
     k_predict<<<npb, 256, 0, ctx->stream>>>(*S, P, ctx->x, ctx->vh, ctx->vol_n, ctx->part + kPartPred);
     HIPCHK(hipGetLastError());
+    mark(k, 0, 1);
+    mark(k, 1, 0);
     if ((rc = build_families(ctx, n, p->delta))) return rc;
+    mark(k, 1, 1);
+    mark(k, 2, 0);
     if ((rc = bond_pass(ctx, S, p, p->dt, true))) return rc;
+    mark(k, 2, 1);
+    mark(k, 3, 0);
     if ((rc = gather_pass(ctx, S, p, G_STEP, S->mass, nullptr))) return rc;
+    mark(k, 3, 1);
     const int64_t ngb = 8 * ((((n + 3) / 4) + 7) / 8);
     k_energy<<<1, 256, 0, ctx->stream>>>(ctx->part + kPartPred, npb, ctx->part + kPartGather, (int)ngb,
-                                         ctx->E);
+                                         ctx->E, ctx->row, n, ctx->ctr);
     HIPCHK(hipGetLastError());
   }
   if ((rc = read_counters(ctx))) return rc;
   fill_report(ctx, n, rep, n_steps);
+  add_timings(ctx, timed, rep);
   if ((rc = counters_to_status(ctx))) return rc;
   if (p->energy_check && n_steps > 0) {
     double E[3];

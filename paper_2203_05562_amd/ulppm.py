@@ -28,7 +28,8 @@ class Params(C.Structure):
                 ("b2", C.c_double), ("rho_s", C.c_double), ("rho_w", C.c_double), ("a1", C.c_double),
                 ("a2", C.c_double), ("n_vg", C.c_double), ("g", C.c_double * 3), ("dt", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("precision", C.c_int32),
-                ("energy_check", C.c_int32), ("force_mode", C.c_int32), ("energy_tol", C.c_double)]
+                ("energy_check", C.c_int32), ("force_mode", C.c_int32), ("energy_tol", C.c_double),
+                ("timing", C.c_int32), ("pad", C.c_int32)]
 
 
 class State(C.Structure):
@@ -41,7 +42,9 @@ class Report(C.Structure):
     _fields_ = [("W_int", C.c_double), ("W_ext", C.c_double), ("W_kin", C.c_double),
                 ("n_bonds", C.c_int64), ("n_degenerate", C.c_int64), ("n_plastic", C.c_int64),
                 ("max_newton", C.c_int64), ("n_noconv", C.c_int64), ("n_tests", C.c_int64),
-                ("n_triples", C.c_int64), ("max_family", C.c_int64), ("steps", C.c_int64)]
+                ("n_triples", C.c_int64), ("max_family", C.c_int64), ("steps", C.c_int64),
+                ("n_bond_updates", C.c_int64), ("timed_steps", C.c_int64), ("t_predict_ms", C.c_double),
+                ("t_family_ms", C.c_double), ("t_bond_ms", C.c_double), ("t_gather_ms", C.c_double)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
@@ -101,6 +104,7 @@ def make_params(prm: dict, precision: int = ULPPM_FP64, **over) -> Params:
     p.energy_check = int(d.get("energy_check", 0))
     p.energy_tol = float(d.get("energy_tol", 1e-2))
     p.force_mode = int(d.get("force_mode", 0))
+    p.timing = int(d.get("timing", 0))
     return p
 
 

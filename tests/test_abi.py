@@ -54,7 +54,8 @@ int main(void) {
   printf("%zu %zu %zu\n", sizeof(ulppm_params), sizeof(ulppm_state), sizeof(ulppm_report));
   printf("%zu %zu %zu %zu\n", offsetof(ulppm_params, g), offsetof(ulppm_params, newton_maxit),
          offsetof(ulppm_params, energy_tol), offsetof(ulppm_state, sig));
-  printf("%zu %zu\n", offsetof(ulppm_state, fixed), offsetof(ulppm_report, steps));
+  printf("%zu %zu %zu %zu\n", offsetof(ulppm_state, fixed), offsetof(ulppm_report, steps),
+         offsetof(ulppm_params, timing), offsetof(ulppm_report, t_gather_ms));
   return 0;
 }
 '''
@@ -67,7 +68,8 @@ int main(void) {
         vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     exp = [C.sizeof(ulppm.Params), C.sizeof(ulppm.State), C.sizeof(ulppm.Report),
            ulppm.Params.g.offset, ulppm.Params.newton_maxit.offset, ulppm.Params.energy_tol.offset,
-           ulppm.State.sig.offset, ulppm.State.fixed.offset, ulppm.Report.steps.offset]
+           ulppm.State.sig.offset, ulppm.State.fixed.offset, ulppm.Report.steps.offset,
+           ulppm.Params.timing.offset, ulppm.Report.t_gather_ms.offset]
     assert vals == exp
 
 

@@ -212,10 +212,11 @@ def test_degenerate_and_isolated_points(olib, gpu):
 
 
 def test_ragged_small_columns(olib, gpu):
-    for dims in [(2, 2, 2), (3, 1, 4), (5, 7, 3)]:
+    for dims in [(2, 2, 2), (3, 2, 4), (5, 7, 3)]:
         say("ragged", dims)
         col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, dims, seed=5, vscale=0.2)
         rc, E, st = olib.step(S, oprm, 5)
+        assert rc == 0
         ctx.step(G, gprm, 5)
         compare_states(G.to_arrays(), S, 1e-11, fields=("u", "v", "sig", "pc", "J"), label=str(dims))
 
@@ -259,3 +260,16 @@ def test_eq51_force_mode_parity(olib, gpu):
     assert rc == 0
     ctx.step(G, gprm, 20)
     compare_states(G.to_arrays(), S, 1e-11, fields=("u", "v", "sig", "pc", "J"), label="eq51 20 steps")
+
+
+def test_single_plane_blows_up_on_both_sides(olib, gpu):
+    """A 3 x 1 x 4 column is one jittered plane: its sub-horizon shape tensors
+    are nonsingular but badly conditioned, the explicit step of Eq. 65 is not
+    stable for it, and both sides report non-finite motion within 5 steps."""
+    say("single plane")
+    col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, (3, 1, 4), seed=5, vscale=0.2)
+    rc, E, st = olib.step(S, oprm, 5)
+    assert rc == -5
+    with pytest.raises(gpu.UlppmError) as ei:
+        ctx.step(G, gprm, 5)
+    assert ei.value.code == -5
