@@ -38,7 +38,14 @@
 
 namespace {
 
-constexpr int kBondThreads = 128;   // one workgroup per point, one lane per bond
+#ifndef ULPPM_BOND_THREADS
+#define ULPPM_BOND_THREADS 128
+#endif
+#ifndef ULPPM_BOND_MIN_WAVES
+#define ULPPM_BOND_MIN_WAVES 1
+#endif
+constexpr int kBondThreads = ULPPM_BOND_THREADS;   // one workgroup per point, one lane per bond
+constexpr int kBondWaves = kBondThreads / 64;
 constexpr int kWave = 64;
 constexpr int kScanChunk = 2048;    // elements per block in the scans (256 x 8)
 // Regions of the reduction-partials buffer (doubles).
@@ -51,7 +58,9 @@ enum Ctr {
   C_DEGEN = 0, C_PLASTIC, C_MAXNEWTON, C_NOCONV, C_TESTS, C_TRIPLES, C_OVERFLOW,
   C_NONFINITE, C_MAXFAM, C_BONDSUM, C_NCOUNT = 16
 };
+constexpr int kStripes = 256;       // each device counter is striped over this many addresses
 constexpr int kTimedSteps = 256;    // steps per call covered by phase timings
+constexpr double kSkin = 0.1;       // candidate-list skin, as a fraction of delta
 constexpr int kPhases = 4;          // predict, family, bond, gather
 
 struct DevParams {
@@ -70,12 +79,38 @@ struct Grid {                 // cell grid over the current bounding box
   int64_t d0, d1, d2, ncell;
 };
 
+// Device counters are striped by block so that concurrent blocks rarely hit
+// the same address; k_reduce_counters folds the stripes once per call.
+__device__ __forceinline__ void ctr_add(unsigned long long* ctr, int k, unsigned long long v) {
+  atomicAdd(&ctr[k * kStripes + (blockIdx.x & (kStripes - 1))], v);
+}
+__device__ __forceinline__ void ctr_max(unsigned long long* ctr, int k, unsigned long long v) {
+  atomicMax(&ctr[k * kStripes + (blockIdx.x & (kStripes - 1))], v);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs of the chip, each with
 // its own L2.  Give each XCD a contiguous range of points so that the
 // neighbour data a block gathers is mostly resident in that XCD's L2.
 // The grid is launched with 8*per blocks; ids >= n are idle.
 __device__ __forceinline__ int64_t xcd_point(int64_t b, int64_t per) {
   return (b & 7) * per + (b >> 3);
+}
+
+// Points walked by one wave of a capped grid (a multiple of 8 blocks of
+// `wpb` waves): the waves of XCD x stride over that XCD's contiguous range.
+// Short per-point kernels use this so that the number of workgroups stays
+// small: their run time would otherwise be set by workgroup dispatch.
+struct XcdWalk {
+  int64_t first, stride, end;
+};
+__device__ __forceinline__ XcdWalk xcd_walk(int64_t n, int wpb) {
+  const int64_t per = (n + 7) / 8;
+  const int64_t x = blockIdx.x & 7, lb = blockIdx.x >> 3, nblk = gridDim.x >> 3;
+  XcdWalk w;
+  w.first = x * per + lb * wpb + threadIdx.x / kWave;
+  w.stride = nblk * wpb;
+  w.end = (x + 1) * per < n ? (x + 1) * per : n;
+  return w;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -127,7 +162,8 @@ __device__ __forceinline__ double exact_r2(double ax, double ay, double az, doub
 // Exclusive prefix sum of int32 counts into int64 offsets; out[n] = total.
 
 __global__ void k_scan_blocks(const int32_t* __restrict__ cnt, int64_t n, int64_t* __restrict__ out,
-                              int64_t* __restrict__ bsum) {
+                              int64_t* __restrict__ bsum, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ int64_t s[256];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   int64_t loc[8];
@@ -156,7 +192,9 @@ __global__ void k_scan_blocks(const int32_t* __restrict__ cnt, int64_t n, int64_
   if (threadIdx.x == 255) bsum[blockIdx.x] = s[255];
 }
 
-__global__ void k_scan_top(int64_t* __restrict__ bsum, int64_t nb, int64_t* __restrict__ out, int64_t n) {
+__global__ void k_scan_top(int64_t* __restrict__ bsum, int64_t nb, int64_t* __restrict__ out, int64_t n,
+                           const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ int64_t s[1024];
   int64_t carry = 0;
   for (int64_t base = 0; base < nb; base += 1024) {
@@ -178,7 +216,9 @@ __global__ void k_scan_top(int64_t* __restrict__ bsum, int64_t nb, int64_t* __re
   if (threadIdx.x == 0) out[n] = carry;
 }
 
-__global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ boff) {
+__global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ boff,
+                           const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   const int64_t add = boff[blockIdx.x];
   for (int k = threadIdx.x; k < kScanChunk; k += blockDim.x) {
@@ -188,7 +228,8 @@ __global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* 
 }
 
 template <class T>
-__global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
+__global__ void k_fill(T* __restrict__ p, int64_t n, T v, const int32_t* __restrict__ gate = nullptr) {
+  if (gate && *gate == 0) return;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     p[e] = v;
 }
@@ -259,7 +300,9 @@ __global__ void k_positions(ulppm_state S, double* __restrict__ x, double* __res
 
 // -------------------------------------------------------- family build --
 
-__global__ void k_bbox(const double* __restrict__ x, int64_t n, double* __restrict__ part) {
+__global__ void k_bbox(const double* __restrict__ x, int64_t n, double* __restrict__ part,
+                       const int32_t* __restrict__ gate) {
+  if (*gate == 0) return;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     for (int c = 0; c < 3; ++c) {
@@ -281,22 +324,38 @@ __global__ void k_bbox(const double* __restrict__ x, int64_t n, double* __restri
   if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = s[threadIdx.x][0];
 }
 
-// One thread: cells of edge >= delta over the bounding box, doubled until the
-// grid fits the allocated cell arrays.  A non-finite box flags an error and
-// collapses everything into one cell (the search stays in bounds).
-__global__ void k_grid(const double* __restrict__ part, int nb, double delta, int64_t max_cells,
-                       Grid* __restrict__ G, unsigned long long* __restrict__ ctr) {
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = 0; b < nb; ++b)
+// Cells of edge >= delta over the bounding box, doubled until the grid fits
+// the allocated cell arrays.  One block reduces the bounding-box partials; a
+// non-finite box flags an error and collapses everything into one cell (the
+// search stays in bounds).
+__global__ __launch_bounds__(256) void k_grid(const double* __restrict__ part, int nb, double delta,
+                                              int64_t max_cells, Grid* __restrict__ G,
+                                              unsigned long long* __restrict__ ctr, const int32_t* __restrict__ gate) {
+  if (*gate == 0) return;
+  __shared__ double s[6][256];
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < nb; b += 256)
     for (int c = 0; c < 3; ++c) {
-      lo[c] = fmin(lo[c], part[6 * b + c]);
-      hi[c] = fmax(hi[c], part[6 * b + 3 + c]);
+      v[c] = fmin(v[c], part[6 * b + c]);
+      v[3 + c] = fmax(v[3 + c], part[6 * b + 3 + c]);
     }
+  for (int c = 0; c < 6; ++c) s[c][threadIdx.x] = v[c];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int c = 0; c < 3; ++c) {
+        s[c][threadIdx.x] = fmin(s[c][threadIdx.x], s[c][threadIdx.x + o]);
+        s[3 + c][threadIdx.x] = fmax(s[3 + c][threadIdx.x], s[3 + c][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double lo[3] = {s[0][0], s[1][0], s[2][0]}, hi[3] = {s[3][0], s[4][0], s[5][0]};
   bool ok = true;
   for (int c = 0; c < 3; ++c) ok = ok && isfinite(lo[c]) && isfinite(hi[c]);
   Grid g;
   if (!ok) {
-    atomicAdd(&ctr[C_NONFINITE], 1ull);
+    ctr_add(ctr, C_NONFINITE, 1ull);
     g.lo0 = g.lo1 = g.lo2 = 0.0;
     g.cs = INFINITY;
     g.d0 = g.d1 = g.d2 = 1;
@@ -329,7 +388,9 @@ __device__ __forceinline__ int64_t cell_coord(double v, double lo, double cs, in
 }
 
 __global__ void k_cell_count(const double* __restrict__ x, int64_t n, const Grid* __restrict__ G,
-                             int32_t* __restrict__ cellid, int32_t* __restrict__ ccount) {
+                             int32_t* __restrict__ cellid, int32_t* __restrict__ ccount,
+                             const int32_t* __restrict__ gate) {
+  if (*gate == 0) return;
   const Grid g = *G;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     int64_t a = cell_coord(x[i], g.lo0, g.cs, g.d0);
@@ -342,7 +403,9 @@ __global__ void k_cell_count(const double* __restrict__ x, int64_t n, const Grid
 }
 
 __global__ void k_cell_fill(int64_t n, const int32_t* __restrict__ cellid, const int64_t* __restrict__ cstart,
-                            int32_t* __restrict__ ccursor, int32_t* __restrict__ cpts) {
+                            int32_t* __restrict__ ccursor, int32_t* __restrict__ cpts,
+                            const int32_t* __restrict__ gate) {
+  if (*gate == 0) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     int32_t cid = cellid[i];
     int32_t pos = atomicAdd(&ccursor[cid], 1);
@@ -350,90 +413,171 @@ __global__ void k_cell_fill(int64_t n, const int32_t* __restrict__ cellid, const
   }
 }
 
-// One wave per point: test every point of the 27 surrounding cells with the
-// exact predicate, append hits through a ballot prefix, then place each hit at
-// its rank (ids are distinct) so the row comes out ascending.
+// Candidate lists: every point within delta + skin, found with a cell list.
+// One wave per point tests the points of the 27 surrounding cells, appends
+// hits through a ballot prefix, then places each hit at its rank (ids are
+// distinct) so the row comes out ascending.  The three cells along x of a
+// (y, z) row are consecutive in cell order, so their points form one
+// contiguous range of the cell list: 9 ranges per point.  Runs only when the
+// gate is set (first build of a call, or a point moved more than skin/2).
 __global__ __launch_bounds__(kWave) void k_family(const double* __restrict__ x, int64_t n, int64_t per,
                                                   const Grid* __restrict__ G, const int32_t* __restrict__ cellid,
                                                   const int64_t* __restrict__ cstart,
                                                   const int32_t* __restrict__ cpts, double d2, int max_f,
                                                   int32_t* __restrict__ ell, int32_t* __restrict__ cnt,
-                                                  unsigned long long* __restrict__ ctr) {
+                                                  unsigned long long* __restrict__ ctr,
+                                                  const int32_t* __restrict__ gate) {
   extern __shared__ int32_t list[];
-  const int64_t i = xcd_point(blockIdx.x, per);
-  if (i >= n) return;
+  if (*gate == 0) return;
   const int lane = threadIdx.x;
   const Grid g = *G;
-  const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
-  const int64_t cid = cellid[i];
-  const int64_t ca = cid % g.d0, cb = (cid / g.d0) % g.d1, cc = cid / (g.d0 * g.d1);
-  int count = 0;
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int64_t c3 = cc + dz;
-    if (c3 < 0 || c3 >= g.d2) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int64_t c2 = cb + dy;
-      if (c2 < 0 || c2 >= g.d1) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int64_t c1 = ca + dx;
-        if (c1 < 0 || c1 >= g.d0) continue;
-        const int64_t c = c1 + g.d0 * (c2 + g.d1 * c3);
-        const int64_t s0 = cstart[c], s1 = cstart[c + 1];
-        for (int64_t base = s0; base < s1; base += kWave) {
-          const int64_t e = base + lane;
-          bool hit = false;
-          int32_t j = -1;
-          if (e < s1) {
-            j = cpts[e];
-            hit = (j != (int32_t)i) && within(xi, yi, zi, x[j], x[n + j], x[2 * n + j], d2);
-          }
-          const unsigned long long mask = __ballot(hit);
-          const int off = __popcll(mask & ((1ull << lane) - 1ull));
-          if (hit && count + off < max_f) list[count + off] = j;
-          count += __popcll(mask);
+  // Grid-stride over points with a capped grid (a multiple of 8, so each
+  // block stays on its XCD's contiguous range): cheap to launch when gated off.
+  for (int64_t b = blockIdx.x; b < 8 * per; b += gridDim.x) {
+    const int64_t i = xcd_point(b, per);
+    if (i >= n) continue;
+    const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
+    const int64_t cid = cellid[i];
+    const int64_t ca = cid % g.d0, cb = (cid / g.d0) % g.d1, cc = cid / (g.d0 * g.d1);
+    const int64_t a0 = ca > 0 ? ca - 1 : 0, a1 = ca + 1 < g.d0 ? ca + 1 : g.d0 - 1;
+    int count = 0;
+    for (int r = 0; r < 9; ++r) {
+      const int64_t c3 = cc + (r / 3) - 1, c2 = cb + (r % 3) - 1;
+      if (c3 < 0 || c3 >= g.d2 || c2 < 0 || c2 >= g.d1) continue;
+      const int64_t crow = g.d0 * (c2 + g.d1 * c3);
+      const int64_t s0 = cstart[crow + a0], s1 = cstart[crow + a1 + 1];
+      for (int64_t base = s0; base < s1; base += kWave) {
+        const int64_t e = base + lane;
+        bool hit = false;
+        int32_t j = -1;
+        if (e < s1) {
+          j = cpts[e];
+          hit = (j != (int32_t)i) && within(xi, yi, zi, x[j], x[n + j], x[2 * n + j], d2);
         }
+        const unsigned long long mask = __ballot(hit);
+        const int off = __popcll(mask & ((1ull << lane) - 1ull));
+        if (hit && count + off < max_f) list[count + off] = j;
+        count += __popcll(mask);
       }
     }
-  }
-  __syncthreads();
-  const int kept = count < max_f ? count : max_f;
-  for (int e = lane; e < kept; e += kWave) {
-    const int32_t v = list[e];
-    int r = 0;
-    for (int k = 0; k < kept; ++k) r += list[k] < v;
-    ell[i * (int64_t)max_f + r] = v;
-  }
-  if (lane == 0) {
-    cnt[i] = kept;
-    if (count > max_f) atomicAdd(&ctr[C_OVERFLOW], 1ull);
-    atomicMax(&ctr[C_MAXFAM], (unsigned long long)count);
+    __syncthreads();
+    const int kept = count < max_f ? count : max_f;
+    for (int e = lane; e < kept; e += kWave) {
+      const int32_t v = list[e];
+      int r = 0;
+      for (int k = 0; k < kept; ++k) r += list[k] < v;
+      ell[i * (int64_t)max_f + r] = v;
+    }
+    __syncthreads();
+    if (lane == 0) {
+      cnt[i] = kept;
+      if (count > max_f) ctr_add(ctr, C_OVERFLOW, 1ull);
+    }
   }
 }
 
-// One wave per point: copy the sorted row into CSR and find, by binary
-// search in row j, the slot of the reverse bond (j,i).
-__global__ __launch_bounds__(kWave) void k_compact(int64_t n, int64_t per, int max_f,
-                                                   const int32_t* __restrict__ ell, const int32_t* __restrict__ cnt,
-                                                   const int64_t* __restrict__ row, int32_t* __restrict__ col,
-                                                   int32_t* __restrict__ rev, unsigned long long* __restrict__ ctr) {
-  const int64_t i = xcd_point(blockIdx.x, per);
-  if (i >= n) return;
-  const int nf = cnt[i];
-  const int64_t b0 = row[i];
-  for (int m = threadIdx.x; m < nf; m += kWave) {
-    const int32_t j = ell[i * (int64_t)max_f + m];
-    col[b0 + m] = j;
-    const int32_t* rj = ell + (int64_t)j * max_f;
-    int lo = 0, hi = cnt[j];
+// Reverse candidate index: position of i in the (sorted) candidate row of j,
+// by binary search; candidates are symmetric, so it exists.  Gated.
+__global__ __launch_bounds__(256) void k_cand_rev(int64_t n, int max_c, const int32_t* __restrict__ cand,
+                                                  const int32_t* __restrict__ ccnt, int32_t* __restrict__ crev,
+                                                  unsigned long long* __restrict__ ctr,
+                                                  const int32_t* __restrict__ gate) {
+  if (*gate == 0) return;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * max_c;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / max_c;
+    const int m = (int)(e - i * max_c);
+    if (m >= ccnt[i]) continue;
+    const int32_t j = cand[e];
+    const int32_t* rj = cand + (int64_t)j * max_c;
+    int lo = 0, hi = ccnt[j];
     while (lo < hi) {
-      int mid = (lo + hi) >> 1;
+      const int mid = (lo + hi) >> 1;
       if (rj[mid] < (int32_t)i) lo = mid + 1; else hi = mid;
     }
-    // Families are symmetric, so rj[lo] == i; a row truncated by an
-    // overflow (already flagged) falls back to the bond's own slot.
-    const bool found = lo < cnt[j] && rj[lo] == (int32_t)i;
-    rev[b0 + m] = (int32_t)(found ? row[j] + lo : b0 + m);
-    if (!found) atomicAdd(&ctr[C_OVERFLOW], 1ull);
+    const bool found = lo < ccnt[j] && rj[lo] == (int32_t)i;
+    crev[e] = found ? lo : -1;
+    if (!found) ctr_add(ctr, C_OVERFLOW, 1ull);
+  }
+}
+
+__global__ void k_save_ref(const double* __restrict__ x, double* __restrict__ xref, int64_t m,
+                           const int32_t* __restrict__ gate) {
+  if (*gate == 0) return;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+    xref[e] = x[e];
+}
+
+// Sets the gate when some point moved more than skin/2 since the candidate
+// lists were built: then a pair within delta now was within delta + skin then.
+__global__ void k_check_skin(const double* __restrict__ x, const double* __restrict__ xref, int64_t n,
+                             double lim2, int32_t* __restrict__ gate) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double a = x[i] - xref[i], b = x[n + i] - xref[n + i], c = x[2 * n + i] - xref[2 * n + i];
+    const double d = a * a + b * b + c * c;
+    if (!(d <= lim2)) *gate = 1;
+  }
+}
+
+// Family of every point in the current configuration (Eq. 1): one wave per
+// point filters its candidate row with the exact predicate; the ballot
+// prefix gives each member its slot in the row, so rows stay ascending.
+__global__ __launch_bounds__(256) void k_filter(const double* __restrict__ x, int64_t n, int max_c, int max_f,
+                                                const int32_t* __restrict__ cand, const int32_t* __restrict__ ccnt,
+                                                double d2, int32_t* __restrict__ posmap, int32_t* __restrict__ cnt,
+                                                unsigned long long* __restrict__ ctr) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const XcdWalk W = xcd_walk(n, 4);
+  int wmax = 0;
+  for (int64_t i = W.first; i < W.end; i += W.stride) {
+    const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
+    const int nc = ccnt[i];
+    int count = 0;
+    for (int base = 0; base < nc; base += kWave) {
+      const int c = base + lane;
+      bool hit = false;
+      if (c < nc) {
+        const int32_t j = cand[i * (int64_t)max_c + c];
+        hit = within(xi, yi, zi, x[j], x[n + j], x[2 * n + j], d2);
+      }
+      const unsigned long long mask = __ballot(hit);
+      const int off = __popcll(mask & ((1ull << lane) - 1ull));
+      if (c < nc) posmap[i * (int64_t)max_c + c] = hit ? count + off : -1;
+      count += __popcll(mask);
+    }
+    if (lane == 0) {
+      cnt[i] = count < max_f ? count : max_f;
+      if (count > max_f) ctr_add(ctr, C_OVERFLOW, 1ull);
+    }
+    wmax = wmax > count ? wmax : count;
+  }
+  if (lane == 0 && wmax > 0) ctr_max(ctr, C_MAXFAM, (unsigned long long)wmax);
+}
+
+// One thread per candidate slot that is a family member: CSR column and the
+// reverse-bond slot rev[(i,j)] = slot of (j,i), read through the reverse
+// candidate index (no search).
+__global__ __launch_bounds__(256) void k_compact(int64_t n, int max_c, int max_f, const int32_t* __restrict__ cand,
+                                                 const int32_t* __restrict__ ccnt, const int32_t* __restrict__ crev,
+                                                 const int32_t* __restrict__ posmap, const int64_t* __restrict__ row,
+                                                 int32_t* __restrict__ col, int32_t* __restrict__ rev,
+                                                 unsigned long long* __restrict__ ctr) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * max_c;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / max_c;
+    const int m = (int)(e - i * max_c);
+    if (m >= ccnt[i]) continue;
+    const int pm = posmap[e];
+    if (pm < 0 || pm >= max_f) continue;
+    const int64_t s = row[i] + pm;
+    const int32_t j = cand[e];
+    col[s] = j;
+    const int cr = crev[e];
+    const int pr = cr >= 0 ? posmap[(int64_t)j * max_c + cr] : -1;
+    // The exact predicate is symmetric, so (j,i) is a member of row j.
+    const bool ok = pr >= 0 && pr < max_f;
+    rev[s] = (int32_t)(ok ? row[j] + pr : s);
+    if (!ok) ctr_add(ctr, C_OVERFLOW, 1ull);
   }
 }
 
@@ -637,16 +781,38 @@ struct BondArgs {
   double* mass_out;
   double* sig_out[6];
   double* pc_out;
-  double* T[3];           // bond force states, CSR order
+  void* T[3];             // bond force states, CSR order (double, or float in mixed precision)
   double dt_inc;
   int max_f;
   unsigned long long* ctr;
 };
 
-// One workgroup per point i, one lane per bond (i,j).
+// LDS records of one family member k of point i, 16-byte aligned so that
+// each is read with ds_read_b128: positions (FP64, for the exact predicate),
+// zeta_ik with V_k, and ydot_ik.  The sub-horizon force-state factors of
+// pass 2 are 9 values per bond, padded to a 16-byte multiple.
+template <class T>
+struct alignas(16) Quad {
+  T v[4];
+};
 template <class Acc>
-__global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) {
-  extern __shared__ double smem[];
+struct alignas(16) MRec {
+  Acc v[sizeof(Acc) == 8 ? 10 : 12];
+};
+
+template <class Acc>
+__host__ __device__ constexpr size_t bond_lds_bytes(int max_f) {
+  return (size_t)max_f * (sizeof(Quad<double>) + 2 * sizeof(Quad<Acc>) + sizeof(MRec<Acc>)) +
+         (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long);
+}
+
+// One workgroup per point i, one lane per bond (i,j).
+// Acc: type of the sub-horizon, full-horizon and force-state sums (and of
+// the force states written); double, or float for mixed precision.
+template <class Acc>
+__global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MIN_WAVES) void k_bond(BondArgs A, DevParams P) {
+  using TS = Acc;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t i = xcd_point(blockIdx.x, A.per);
   if (i >= A.n) return;                           // uniform per block
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
@@ -655,38 +821,39 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
   const int nw = (mf + 63) / 64;                   // membership words per row
-  double* sx = smem;                               // 3*mf  x_k (FP64: exact predicate)
-  double* sM = sx + 3 * mf;                        // 9*mf  (V_j/V_H)(sigma_ij + S_r s 1) K_ij^{-1}
-  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sM + 9 * mf);  // mf*nw S_ij rows
-  Acc* sz = reinterpret_cast<Acc*>(sb + (size_t)mf * nw);  // 3*mf  zeta_ik = x_k - x_i
-  Acc* sy = sz + 3 * mf;                           // 3*mf  ydot_ik = v_k - v_i
-  Acc* sv = sy + 3 * mf;                           // mf    V_k
-  __shared__ double red[2][24];
+  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);        // x_k
+  Quad<Acc>* sZ = reinterpret_cast<Quad<Acc>*>(sX + mf);               // zeta_ik, V_k
+  Quad<Acc>* sY = sZ + mf;                                              // ydot_ik
+  MRec<Acc>* sM = reinterpret_cast<MRec<Acc>*>(sY + mf);               // (V_j/V_H)(sigma_ij + S_r s 1) K_ij^{-1}
+  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sM + mf);  // mf*nw S_ij rows
+  TS** const Tout = reinterpret_cast<TS**>(A.T);
+  __shared__ double s_d2;
+  __shared__ double red[kBondWaves][24];
   __shared__ double pt[4];                         // Sr_new, Vh, sum-of-family-volumes
-  __shared__ long long redi[2][4];
+  __shared__ long long redi[kBondWaves][4];
 
   const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
   const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
 
   // Stage the family of i and form the full-horizon partial sums (Eqs. 5, 8).
-  double Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0.0;
+  Acc Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0;
   for (int m = tid; m < nf; m += kBondThreads) {
     const int32_t k = A.col[b0 + m];
     const double xk0 = A.x[k], xk1 = A.x[n + k], xk2 = A.x[2 * n + k];
     const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
     const double y0 = A.vh[k] - vi0, y1 = A.vh[n + k] - vi1, y2 = A.vh[2 * n + k] - vi2;
     const double V = A.vol_n[k];
-    sx[m] = xk0; sx[mf + m] = xk1; sx[2 * mf + m] = xk2;
-    sz[m] = (Acc)z0; sz[mf + m] = (Acc)z1; sz[2 * mf + m] = (Acc)z2;
-    sy[m] = (Acc)y0; sy[mf + m] = (Acc)y1; sy[2 * mf + m] = (Acc)y2;
-    sv[m] = (Acc)V;
-    const double w0 = V * z0, w1 = V * z1, w2 = V * z2;
-    Kp[0] += w0 * z0; Kp[1] += w1 * z1; Kp[2] += w2 * z2;
-    Kp[3] += w1 * z2; Kp[4] += w0 * z2; Kp[5] += w0 * z1;
-    Np[0] += y0 * w0; Np[1] += y0 * w1; Np[2] += y0 * w2;
-    Np[3] += y1 * w0; Np[4] += y1 * w1; Np[5] += y1 * w2;
-    Np[6] += y2 * w0; Np[7] += y2 * w1; Np[8] += y2 * w2;
-    Vp += V;
+    sX[m] = Quad<double>{{xk0, xk1, xk2, 0.0}};
+    sZ[m] = Quad<Acc>{{(Acc)z0, (Acc)z1, (Acc)z2, (Acc)V}};
+    sY[m] = Quad<Acc>{{(Acc)y0, (Acc)y1, (Acc)y2, (Acc)0}};
+    const Acc a0 = (Acc)z0, a1 = (Acc)z1, a2 = (Acc)z2, c0 = (Acc)y0, c1 = (Acc)y1, c2 = (Acc)y2, Va = (Acc)V;
+    const Acc w0 = Va * a0, w1 = Va * a1, w2 = Va * a2;
+    Kp[0] += w0 * a0; Kp[1] += w1 * a1; Kp[2] += w2 * a2;
+    Kp[3] += w1 * a2; Kp[4] += w0 * a2; Kp[5] += w0 * a1;
+    Np[0] += c0 * w0; Np[1] += c0 * w1; Np[2] += c0 * w2;
+    Np[3] += c1 * w0; Np[4] += c1 * w1; Np[5] += c1 * w2;
+    Np[6] += c2 * w0; Np[7] += c2 * w1; Np[8] += c2 * w2;
+    Vp += Va;
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) Kp[k] = wave_sum(Kp[k]);
@@ -694,16 +861,22 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
   for (int k = 0; k < 9; ++k) Np[k] = wave_sum(Np[k]);
   Vp = wave_sum(Vp);
   if (lane == 0) {
-    for (int k = 0; k < 6; ++k) red[wid][k] = Kp[k];
-    for (int k = 0; k < 9; ++k) red[wid][6 + k] = Np[k];
-    red[wid][15] = Vp;
+    for (int k = 0; k < 6; ++k) red[wid][k] = (double)Kp[k];
+    for (int k = 0; k < 9; ++k) red[wid][6 + k] = (double)Np[k];
+    red[wid][15] = (double)Vp;
   }
   __syncthreads();
   if (tid == 0) {
+    s_d2 = P.d2;
     double Ki[6], Ni[9];
-    for (int k = 0; k < 6; ++k) Ki[k] = red[0][k] + red[1][k];
-    for (int k = 0; k < 9; ++k) Ni[k] = red[0][6 + k] + red[1][6 + k];
-    const double Vh = red[0][15] + red[1][15];
+    double Vh = 0.0;
+    for (int k = 0; k < 6; ++k) Ki[k] = 0.0;
+    for (int k = 0; k < 9; ++k) Ni[k] = 0.0;
+    for (int w = 0; w < kBondWaves; ++w) {
+      for (int k = 0; k < 6; ++k) Ki[k] += red[w][k];
+      for (int k = 0; k < 9; ++k) Ni[k] += red[w][6 + k];
+      Vh += red[w][15];
+    }
     // Volume change of the step: with geometry at n+1 the increment F_D
     // satisfies F_D^{-1} = I - dt L_i (Eq. 17 in updated Lagrangian form).
     double Jd = 1.0;
@@ -743,34 +916,39 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
 #pragma unroll
   for (int k = 0; k < 6; ++k) sig_i[k] = A.sig[k][i];
   const double pc_i = A.pc[i];
-  const double d2 = P.d2;
+  const double d2 = s_d2;                          // from LDS: a VGPR, not a reloaded kernel argument
 
   double hs[6] = {0, 0, 0, 0, 0, 0}, hpc = 0.0, hw = 0.0;
   long long n_deg = 0, n_pl = 0, n_nc = 0, n_trip = 0, mx = 0;
   for (int m = tid; m < nf; m += kBondThreads) {
-    const double xj0 = sx[m], xj1 = sx[mf + m], xj2 = sx[2 * mf + m];
+    const Quad<double> xj = sX[m];
+    const double xj0 = xj.v[0], xj1 = xj.v[1], xj2 = xj.v[2];
     Acc K0 = 0, K1 = 0, K2 = 0, K3 = 0, K4 = 0, K5 = 0;
     Acc N00 = 0, N01 = 0, N02 = 0, N10 = 0, N11 = 0, N12 = 0, N20 = 0, N21 = 0, N22 = 0, Vs = 0;
     int ns = 0;
-    unsigned long long word = 0ull;
-    for (int t = 0; t < nf; ++t) {
-      const bool in = within(xj0, xj1, xj2, sx[t], sx[mf + t], sx[2 * mf + t], d2);
-      const Acc w = in ? sv[t] : (Acc)0;
-      ns += in ? 1 : 0;
-      word |= (unsigned long long)in << (t & 63);
-      if ((t & 63) == 63 || t == nf - 1) {
-        sb[(size_t)m * nw + (t >> 6)] = word;
-        word = 0ull;
+    for (int t0 = 0; t0 < nf; t0 += 64) {
+      const int tn = nf - t0 < 64 ? nf - t0 : 64;
+      unsigned long long word = 0ull;
+      for (int u = 0; u < tn; ++u) {
+        const int t = t0 + u;
+        const Quad<double> xk = sX[t];
+        const Quad<Acc> zk = sZ[t];
+        const Quad<Acc> yk = sY[t];
+        const bool in = within(xj0, xj1, xj2, xk.v[0], xk.v[1], xk.v[2], d2);
+        const Acc w = in ? zk.v[3] : (Acc)0;
+        ns += in ? 1 : 0;
+        word |= (unsigned long long)in << u;
+        const Acc z0 = zk.v[0], z1 = zk.v[1], z2 = zk.v[2];
+        const Acc w0 = w * z0, w1 = w * z1, w2 = w * z2;
+        K0 += w0 * z0; K1 += w1 * z1; K2 += w2 * z2;
+        K3 += w1 * z2; K4 += w0 * z2; K5 += w0 * z1;
+        const Acc y0 = yk.v[0], y1 = yk.v[1], y2 = yk.v[2];
+        N00 += y0 * w0; N01 += y0 * w1; N02 += y0 * w2;
+        N10 += y1 * w0; N11 += y1 * w1; N12 += y1 * w2;
+        N20 += y2 * w0; N21 += y2 * w1; N22 += y2 * w2;
+        Vs += w;
       }
-      const Acc z0 = sz[t], z1 = sz[mf + t], z2 = sz[2 * mf + t];
-      const Acc w0 = w * z0, w1 = w * z1, w2 = w * z2;
-      K0 += w0 * z0; K1 += w1 * z1; K2 += w2 * z2;
-      K3 += w1 * z2; K4 += w0 * z2; K5 += w0 * z1;
-      const Acc y0 = sy[t], y1 = sy[mf + t], y2 = sy[2 * mf + t];
-      N00 += y0 * w0; N01 += y0 * w1; N02 += y0 * w2;
-      N10 += y1 * w0; N11 += y1 * w1; N12 += y1 * w2;
-      N20 += y2 * w0; N21 += y2 * w1; N22 += y2 * w2;
-      Vs += w;
+      sb[(size_t)m * nw + (t0 >> 6)] = word;
     }
     n_trip += ns;
     // FP64 from here on: inversion, gradient, return map, force state.
@@ -780,9 +958,8 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
     const int64_t slot = b0 + m;
     if (ns < 3 || !(dK > 1e-12 * tk * tk * tk)) {               // degenerate: inactive bond
       ++n_deg;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) sM[q * mf + m] = 0.0;
-      if (P.force_mode == ULPPM_FORCE_EQ51) { A.T[0][slot] = 0.0; A.T[1][slot] = 0.0; A.T[2][slot] = 0.0; }
+      sM[m] = MRec<Acc>{};
+      if (P.force_mode == ULPPM_FORCE_EQ51) { Tout[0][slot] = (TS)0; Tout[1][slot] = (TS)0; Tout[2][slot] = (TS)0; }
       continue;
     }
     const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
@@ -823,13 +1000,15 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
     if (P.force_mode == ULPPM_FORCE_EQ51) {
       // Eq. 51 as printed: T_ij = varpi (sigma_ij + Sr s 1) K_ij^{-1} zeta_ij.
       const double zx = xj0 - xi0, zy = xj1 - xi1, zz = xj2 - xi2;
-      A.T[0][slot] = varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz);
-      A.T[1][slot] = varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz);
-      A.T[2][slot] = varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz);
+      Tout[0][slot] = (TS)(varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz));
+      Tout[1][slot] = (TS)(varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz));
+      Tout[2][slot] = (TS)(varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz));
     } else {
       const double wj = Vj / Vh;
+      MRec<Acc> r{};
 #pragma unroll
-      for (int q = 0; q < 9; ++q) sM[q * mf + m] = wj * SK[q];
+      for (int q = 0; q < 9; ++q) r.v[q] = (Acc)(wj * SK[q]);
+      sM[m] = r;
     }
     // point history: volume-weighted mean of the bond states
 #pragma unroll
@@ -844,23 +1023,24 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
     // k reads row k of the bit matrix written in the first pass.
     __syncthreads();
     for (int m = tid; m < nf; m += kBondThreads) {
-      double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0, a8 = 0;
+      Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0, a8 = 0;
       for (int j0 = 0; j0 < nf; j0 += 64) {
         unsigned long long word = sb[(size_t)m * nw + (j0 >> 6)];
         const int jn = nf - j0 < 64 ? nf - j0 : 64;
         for (int jj = 0; jj < jn; ++jj) {
-          const double w = (word >> jj) & 1ull ? 1.0 : 0.0;
-          const int j = j0 + jj;
-          a0 += w * sM[j]; a1 += w * sM[mf + j]; a2 += w * sM[2 * mf + j];
-          a3 += w * sM[3 * mf + j]; a4 += w * sM[4 * mf + j]; a5 += w * sM[5 * mf + j];
-          a6 += w * sM[6 * mf + j]; a7 += w * sM[7 * mf + j]; a8 += w * sM[8 * mf + j];
+          const Acc w = (word >> jj) & 1ull ? (Acc)1 : (Acc)0;
+          const MRec<Acc> r = sM[j0 + jj];
+          a0 += w * r.v[0]; a1 += w * r.v[1]; a2 += w * r.v[2];
+          a3 += w * r.v[3]; a4 += w * r.v[4]; a5 += w * r.v[5];
+          a6 += w * r.v[6]; a7 += w * r.v[7]; a8 += w * r.v[8];
         }
       }
-      const double zx = sx[m] - xi0, zy = sx[mf + m] - xi1, zz = sx[2 * mf + m] - xi2;
+      const Quad<Acc> zm = sZ[m];
+      const Acc zx = zm.v[0], zy = zm.v[1], zz = zm.v[2];
       const int64_t slot = b0 + m;
-      A.T[0][slot] = a0 * zx + a1 * zy + a2 * zz;
-      A.T[1][slot] = a3 * zx + a4 * zy + a5 * zz;
-      A.T[2][slot] = a6 * zx + a7 * zy + a8 * zz;
+      Tout[0][slot] = (TS)(a0 * zx + a1 * zy + a2 * zz);
+      Tout[1][slot] = (TS)(a3 * zx + a4 * zy + a5 * zz);
+      Tout[2][slot] = (TS)(a6 * zx + a7 * zy + a8 * zz);
     }
   }
 #pragma unroll
@@ -882,23 +1062,27 @@ __global__ __launch_bounds__(kBondThreads) void k_bond(BondArgs A, DevParams P) 
   }
   __syncthreads();
   if (tid == 0) {
-    const double W = red[0][7] + red[1][7];
+    double W = 0.0, hsum[7] = {0, 0, 0, 0, 0, 0, 0};
+    long long d = 0, pl = 0, nc = 0, tr = 0, m2 = 0;
+    for (int w = 0; w < kBondWaves; ++w) {
+      W += red[w][7];
+      for (int k = 0; k < 7; ++k) hsum[k] += red[w][k];
+      d += redi[w][0]; pl += redi[w][1]; nc += redi[w][2]; tr += redi[w][3];
+      m2 = m2 > (long long)red[w][8] ? m2 : (long long)red[w][8];
+    }
     if (W > 0.0) {
-      for (int k = 0; k < 6; ++k) A.sig_out[k][i] = (red[0][k] + red[1][k]) / W;
-      A.pc_out[i] = (red[0][6] + red[1][6]) / W;
+      for (int k = 0; k < 6; ++k) A.sig_out[k][i] = hsum[k] / W;
+      A.pc_out[i] = hsum[6] / W;
     } else {
       for (int k = 0; k < 6; ++k) A.sig_out[k][i] = sig_i[k];
       A.pc_out[i] = pc_i;
     }
-    const long long d = redi[0][0] + redi[1][0], pl = redi[0][1] + redi[1][1];
-    const long long nc = redi[0][2] + redi[1][2], tr = redi[0][3] + redi[1][3];
-    if (d) atomicAdd(&A.ctr[C_DEGEN], (unsigned long long)d);
-    if (pl) atomicAdd(&A.ctr[C_PLASTIC], (unsigned long long)pl);
-    if (nc) atomicAdd(&A.ctr[C_NOCONV], (unsigned long long)nc);
-    atomicAdd(&A.ctr[C_TRIPLES], (unsigned long long)tr);
-    atomicAdd(&A.ctr[C_TESTS], (unsigned long long)((long long)nf * nf));
-    const long long m2 = (long long)fmax(red[0][8], red[1][8]);
-    if (m2) atomicMax(&A.ctr[C_MAXNEWTON], (unsigned long long)m2);
+    if (d) ctr_add(A.ctr, C_DEGEN, (unsigned long long)d);
+    if (pl) ctr_add(A.ctr, C_PLASTIC, (unsigned long long)pl);
+    if (nc) ctr_add(A.ctr, C_NOCONV, (unsigned long long)nc);
+    ctr_add(A.ctr, C_TRIPLES, (unsigned long long)tr);
+    ctr_add(A.ctr, C_TESTS, (unsigned long long)((long long)nf * nf));
+    if (m2) ctr_max(A.ctr, C_MAXNEWTON, (unsigned long long)m2);
   }
 }
 
@@ -911,7 +1095,7 @@ struct GatherArgs {
   const int64_t* row;
   const int32_t* col;
   const int32_t* rev;
-  const double* T[3];
+  const void* T[3];       // double, or float in mixed precision
   const double* vol_n;
   const double* mass;     // M^{n+1}
   const double* vh;       // 3n (G_STEP)
@@ -928,26 +1112,32 @@ struct GatherArgs {
 // One wave per point: f_i = V_i sum_j (T_ij - T_ji) V_j (Eqs. 49-50, sign of
 // Eq. 33), gathering T_ji through rev[] instead of scattering with atomics;
 // then a = f/M + g (Eq. 62), v = v_half + (dt/2) a (Eq. 63), energy partials.
+// TS: storage and accumulation type of the force gather (float in mixed
+// precision); the Newmark update is FP64.
+template <class TS>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int64_t i = xcd_point(blockIdx.x, G.per) * 4 + wid;
+  const TS* T0 = reinterpret_cast<const TS*>(G.T[0]);
+  const TS* T1 = reinterpret_cast<const TS*>(G.T[1]);
+  const TS* T2 = reinterpret_cast<const TS*>(G.T[2]);
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-  if (i < G.n) {
+  const XcdWalk W = xcd_walk(G.n, 4);
+  for (int64_t i = W.first; i < W.end; i += W.stride) {
     const int64_t b0 = G.row[i], b1 = G.row[i + 1];
-    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    TS f0 = 0, f1 = 0, f2 = 0;
     for (int64_t s = b0 + lane; s < b1; s += kWave) {
       const int32_t j = G.col[s], r = G.rev[s];
-      const double wv = G.vol_n[j];
-      f0 += (G.T[0][s] - G.T[0][r]) * wv;
-      f1 += (G.T[1][s] - G.T[1][r]) * wv;
-      f2 += (G.T[2][s] - G.T[2][r]) * wv;
+      const TS wv = (TS)G.vol_n[j];
+      f0 += (T0[s] - T0[r]) * wv;
+      f1 += (T1[s] - T1[r]) * wv;
+      f2 += (T2[s] - T2[r]) * wv;
     }
     f0 = wave_sum(f0);
     f1 = wave_sum(f1);
     f2 = wave_sum(f2);
     if (lane == 0) {
       const double Vi = G.vol_n[i];
-      const double f[3] = {f0 * Vi, f1 * Vi, f2 * Vi};
+      const double f[3] = {(double)f0 * Vi, (double)f1 * Vi, (double)f2 * Vi};
       if (G.mode == G_FORCES) {
         for (int c = 0; c < 3; ++c) G.f[c][i] = f[c];
       } else {
@@ -971,7 +1161,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
           }
           bad = bad || !isfinite(a);
         }
-        if (bad) atomicAdd(&G.ctr[C_NONFINITE], 1ull);
+        if (bad) ctr_add(G.ctr, C_NONFINITE, 1ull);
       }
     }
   }
@@ -1007,7 +1197,7 @@ __global__ void k_energy(const double* __restrict__ pp, int npb, const double* _
     E[0] += s[0][0];
     E[1] += s[1][0];
     E[2] = s[2][0];
-    ctr[C_BONDSUM] += (unsigned long long)row[n];   // single thread, stream-ordered
+    ctr[C_BONDSUM * kStripes] += (unsigned long long)row[n];   // single thread, stream-ordered
   }
 }
 
@@ -1061,6 +1251,19 @@ __global__ void k_dtcrit(int64_t n, const int64_t* __restrict__ row, const int32
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
+// Folds the counter stripes: sums, except the maxima.
+__global__ void k_reduce_counters(const unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= C_NCOUNT) return;
+  unsigned long long a = 0;
+  const bool is_max = k == C_MAXNEWTON || k == C_MAXFAM;
+  for (int t = 0; t < kStripes; ++t) {
+    const unsigned long long v = ctr[k * kStripes + t];
+    a = is_max ? (a > v ? a : v) : a + v;
+  }
+  out[k] = a;
+}
+
 __global__ void k_export_rows(int64_t n, const int64_t* __restrict__ row, int64_t* __restrict__ out) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e <= n; e += (int64_t)gridDim.x * blockDim.x)
     out[e] = row[e];
@@ -1069,6 +1272,11 @@ __global__ void k_export_rows(int64_t n, const int64_t* __restrict__ row, int64_
 __global__ void k_copy_i32(const int32_t* __restrict__ a, int32_t* __restrict__ b, int64_t m) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
     b[e] = a[e];
+}
+
+__global__ void k_widen(const float* __restrict__ a, double* __restrict__ b, int64_t m) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+    b[e] = (double)a[e];
 }
 
 __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t m) {
@@ -1094,7 +1302,14 @@ struct ulppm_ctx {
   int32_t* cellid = nullptr;
   int32_t* cnt = nullptr;
   int64_t* row = nullptr;   // n+1
-  int32_t* ell = nullptr;   // n*max_f
+  // candidate lists (radius delta + skin), rebuilt only when needed
+  int max_c = 0;
+  int32_t* cand = nullptr;    // n*max_c, rows ascending
+  int32_t* ccnt = nullptr;    // n
+  int32_t* crev = nullptr;    // n*max_c, position of i in the candidate row of j
+  int32_t* posmap = nullptr;  // n*max_c, slot of the candidate in the family row, or -1
+  double* xref = nullptr;     // 3n positions at the last candidate build
+  int32_t* gate = nullptr;    // 1: rebuild candidates in this step
   // cells
   int32_t* ccount = nullptr;
   int32_t* ccursor = nullptr;
@@ -1110,7 +1325,8 @@ struct ulppm_ctx {
   int64_t* scan_bsum = nullptr;
   int64_t scan_cap = 0;
   Grid* grid = nullptr;
-  unsigned long long* ctr = nullptr;
+  unsigned long long* ctr = nullptr;      // C_NCOUNT x kStripes
+  unsigned long long* ctr_sum = nullptr;  // C_NCOUNT, folded
   double* E = nullptr;        // 3
   // phase timing events, [step][phase][start/stop]
   hipEvent_t ev[kTimedSteps][kPhases][2] = {};
@@ -1173,6 +1389,14 @@ int check_params(ulppm_ctx* ctx, const ulppm_params* p) {
   return ULPPM_OK;
 }
 
+// Grid for the per-point kernels that walk points with xcd_walk: 4 waves per
+// block, at most 2 points per wave per pass, a multiple of 8 blocks, capped.
+inline unsigned walk_grid(int64_t n) {
+  int64_t b = (n + 7) / 8;
+  b = std::min<int64_t>(std::max<int64_t>(b, 1), 512);
+  return (unsigned)(8 * b);
+}
+
 inline int blocks_for(int64_t n, int t, int cap = 65536) {
   int64_t b = (n + t - 1) / t;
   if (b < 1) b = 1;
@@ -1180,56 +1404,76 @@ inline int blocks_for(int64_t n, int t, int cap = 65536) {
 }
 
 int zero_counters(ulppm_ctx* ctx) {
-  k_fill<unsigned long long><<<1, 64, 0, ctx->stream>>>(ctx->ctr, C_NCOUNT, 0ull);
+  k_fill<unsigned long long><<<16, 256, 0, ctx->stream>>>(ctx->ctr, C_NCOUNT * kStripes, 0ull);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
 
-int scan_counts(ulppm_ctx* ctx, const int32_t* cnt, int64_t m, int64_t* out) {
+int scan_counts(ulppm_ctx* ctx, const int32_t* cnt, int64_t m, int64_t* out, const int32_t* gate = nullptr) {
   const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
   if (nb > ctx->scan_cap) return fail(ctx, ULPPM_E_ARG, "scan too large");
   if (nb == 0) {
-    k_fill<int64_t><<<1, 64, 0, ctx->stream>>>(out, 1, 0);
+    k_fill<int64_t><<<1, 64, 0, ctx->stream>>>(out, 1, 0, gate);
     HIPCHK(hipGetLastError());
     return ULPPM_OK;
   }
-  k_scan_blocks<<<(unsigned)nb, 256, 0, ctx->stream>>>(cnt, m, out, ctx->scan_bsum);
-  k_scan_top<<<1, 1024, 0, ctx->stream>>>(ctx->scan_bsum, nb, out, m);
-  k_scan_add<<<(unsigned)nb, 256, 0, ctx->stream>>>(out, m, ctx->scan_bsum);
+  k_scan_blocks<<<(unsigned)nb, 256, 0, ctx->stream>>>(cnt, m, out, ctx->scan_bsum, gate);
+  k_scan_top<<<1, 1024, 0, ctx->stream>>>(ctx->scan_bsum, nb, out, m, gate);
+  k_scan_add<<<(unsigned)nb, 256, 0, ctx->stream>>>(out, m, ctx->scan_bsum, gate);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
 
-// Families at the positions in ctx->x (Eq. 1): grid, cell lists, per-point
-// sorted rows, CSR and reverse index.
-int build_families(ulppm_ctx* ctx, int64_t n, double delta) {
+// Families at the positions in ctx->x (Eq. 1).  Candidate lists within
+// delta + skin are rebuilt on the device when the gate is set (force, or a
+// point moved more than skin/2 since the last build); every step then
+// filters the candidates with the exact predicate, so the families are
+// exactly those of the current positions.  Then CSR offsets and rev[].
+int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
+  const double skin = kSkin * delta;
+  const double rc = delta + skin;
+  const int32_t* gate = ctx->gate;
+  if (force) {
+    k_fill<int32_t><<<1, 64, 0, ctx->stream>>>(ctx->gate, 1, 1);
+  } else {
+    const double half = 0.5 * skin * (1.0 - 1e-6);
+    k_check_skin<<<blocks_for(n, 256, 2048), 256, 0, ctx->stream>>>(ctx->x, ctx->xref, n, half * half, ctx->gate);
+  }
   const int nbb = blocks_for(n, 256, 1024);
-  k_bbox<<<nbb, 256, 0, ctx->stream>>>(ctx->x, n, ctx->part + kPartRed);
-  k_grid<<<1, 1, 0, ctx->stream>>>(ctx->part + kPartRed, nbb, delta, ctx->max_cells, ctx->grid, ctx->ctr);
-  k_fill<int32_t><<<blocks_for(ctx->max_cells, 256, 4096), 256, 0, ctx->stream>>>(ctx->ccount, ctx->max_cells, 0);
-  k_fill<int32_t><<<blocks_for(ctx->max_cells, 256, 4096), 256, 0, ctx->stream>>>(ctx->ccursor, ctx->max_cells, 0);
-  k_cell_count<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(ctx->x, n, ctx->grid, ctx->cellid, ctx->ccount);
+  k_bbox<<<nbb, 256, 0, ctx->stream>>>(ctx->x, n, ctx->part + kPartRed, gate);
+  k_grid<<<1, 256, 0, ctx->stream>>>(ctx->part + kPartRed, nbb, rc, ctx->max_cells, ctx->grid, ctx->ctr, gate);
+  k_fill<int32_t><<<blocks_for(ctx->max_cells, 256, 4096), 256, 0, ctx->stream>>>(ctx->ccount, ctx->max_cells, 0, gate);
+  k_fill<int32_t><<<blocks_for(ctx->max_cells, 256, 4096), 256, 0, ctx->stream>>>(ctx->ccursor, ctx->max_cells, 0, gate);
+  k_cell_count<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(ctx->x, n, ctx->grid, ctx->cellid, ctx->ccount, gate);
   HIPCHK(hipGetLastError());
-  int rc = scan_counts(ctx, ctx->ccount, ctx->max_cells, ctx->cstart);
-  if (rc) return rc;
-  k_cell_fill<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, ctx->cellid, ctx->cstart, ctx->ccursor, ctx->cpts);
+  int rc2 = scan_counts(ctx, ctx->ccount, ctx->max_cells, ctx->cstart, gate);
+  if (rc2) return rc2;
+  k_cell_fill<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, ctx->cellid, ctx->cstart, ctx->ccursor, ctx->cpts, gate);
   const int64_t per = (n + 7) / 8;
-  k_family<<<(unsigned)(8 * per), kWave, ctx->max_f * sizeof(int32_t), ctx->stream>>>(
-      ctx->x, n, per, ctx->grid, ctx->cellid, ctx->cstart, ctx->cpts, delta * delta, ctx->max_f, ctx->ell,
-      ctx->cnt, ctx->ctr);
+  const unsigned fgrid = (unsigned)std::min<int64_t>(8 * per, 16384);
+  k_family<<<fgrid, kWave, ctx->max_c * sizeof(int32_t), ctx->stream>>>(
+      ctx->x, n, per, ctx->grid, ctx->cellid, ctx->cstart, ctx->cpts, rc * rc, ctx->max_c, ctx->cand, ctx->ccnt,
+      ctx->ctr, gate);
+  const unsigned cgrid = (unsigned)((n * ctx->max_c + 255) / 256);
+  k_cand_rev<<<std::min<unsigned>(cgrid, 8192u), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->cand, ctx->ccnt,
+                                                                       ctx->crev, ctx->ctr, gate);
+  k_save_ref<<<blocks_for(3 * n, 256, 4096), 256, 0, ctx->stream>>>(ctx->x, ctx->xref, 3 * n, gate);
+  k_fill<int32_t><<<1, 64, 0, ctx->stream>>>(ctx->gate, 1, 0);
   HIPCHK(hipGetLastError());
-  rc = scan_counts(ctx, ctx->cnt, n, ctx->row);
-  if (rc) return rc;
-  k_compact<<<(unsigned)(8 * per), kWave, 0, ctx->stream>>>(n, per, ctx->max_f, ctx->ell, ctx->cnt, ctx->row,
-                                                            ctx->col, ctx->rev, ctx->ctr);
+  k_filter<<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->x, n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
+                                                   delta * delta, ctx->posmap, ctx->cnt, ctx->ctr);
+  HIPCHK(hipGetLastError());
+  rc2 = scan_counts(ctx, ctx->cnt, n, ctx->row);
+  if (rc2) return rc2;
+  k_compact<<<std::min<unsigned>(cgrid, 16384u), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand,
+                                                                        ctx->ccnt, ctx->crev, ctx->posmap, ctx->row,
+                                                                        ctx->col, ctx->rev, ctx->ctr);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
 
 size_t bond_lds(int max_f, bool mixed) {
-  const size_t nw = (size_t)(max_f + 63) / 64;
-  return (size_t)max_f * (12 * sizeof(double) + nw * sizeof(unsigned long long) +
-                          7 * (mixed ? sizeof(float) : sizeof(double)));
+  return mixed ? bond_lds_bytes<float>(max_f) : bond_lds_bytes<double>(max_f);
 }
 
 // Algorithm 1 (bond pass) into outputs; mode: step (state outputs) or not.
@@ -1258,12 +1502,13 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
     for (int k = 0; k < 6; ++k) A.sig_out[k] = q + (5 + k) * n;
     A.pc_out = q + 11 * n;
   }
-  for (int c = 0; c < 3; ++c) A.T[c] = ctx->T + c * ctx->bond_cap;
+  const bool mixed = p->precision == ULPPM_MIXED;
+  for (int c = 0; c < 3; ++c)
+    A.T[c] = mixed ? (void*)(reinterpret_cast<float*>(ctx->T) + c * ctx->bond_cap) : (void*)(ctx->T + c * ctx->bond_cap);
   A.dt_inc = dt_inc;
   A.max_f = ctx->max_f;
   A.ctr = ctx->ctr;
   DevParams P = dev_params(p);
-  const bool mixed = p->precision == ULPPM_MIXED;
   const size_t lds = bond_lds(ctx->max_f, mixed);
   if (mixed)
     k_bond<float><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
@@ -1278,12 +1523,14 @@ int gather_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int
   const int64_t n = S->n;
   GatherArgs G;
   G.n = n;
-  const int64_t nblk = (n + 3) / 4;
-  G.per = (nblk + 7) / 8;
+  G.per = 0;
   G.row = ctx->row;
   G.col = ctx->col;
   G.rev = ctx->rev;
-  for (int c = 0; c < 3; ++c) G.T[c] = ctx->T + c * ctx->bond_cap;
+  const bool mixed = p->precision == ULPPM_MIXED;
+  for (int c = 0; c < 3; ++c)
+    G.T[c] = mixed ? (const void*)(reinterpret_cast<const float*>(ctx->T) + c * ctx->bond_cap)
+                   : (const void*)(ctx->T + c * ctx->bond_cap);
   G.vol_n = ctx->vol_n;
   G.mass = mass;
   G.vh = ctx->vh;
@@ -1298,15 +1545,20 @@ int gather_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int
   G.hdt = 0.5 * p->dt;
   G.g0 = p->g[0]; G.g1 = p->g[1]; G.g2 = p->g[2];
   G.mode = mode;
-  const unsigned grid = (unsigned)(8 * G.per);
+  const unsigned grid = walk_grid(n);
   if (mode == G_STEP && (int64_t)grid * 3 + kPartGather > ctx->part_cap) return fail(ctx, ULPPM_E_ARG, "partials too small");
-  k_gather<<<grid, 256, 0, ctx->stream>>>(G);
+  if (mixed)
+    k_gather<float><<<grid, 256, 0, ctx->stream>>>(G);
+  else
+    k_gather<double><<<grid, 256, 0, ctx->stream>>>(G);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
 
 int read_counters(ulppm_ctx* ctx) {
-  HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->ctr, sizeof(ctx->h_ctr), hipMemcpyDeviceToHost, ctx->stream));
+  k_reduce_counters<<<1, 64, 0, ctx->stream>>>(ctx->ctr, ctx->ctr_sum);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->ctr_sum, sizeof(ctx->h_ctr), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return ULPPM_OK;
 }
@@ -1380,12 +1632,13 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   ctx->max_f = max_family;
   ctx->max_cells = n_points * 2 + 4096;
   ctx->bond_cap = n_points * (int64_t)max_family;
-  if (ctx->bond_cap > 2147483647LL) {
+  ctx->max_c = ((max_family * 3 / 2) + 63) / 64 * 64;
+  if (ctx->bond_cap > 2147483647LL || n_points * (int64_t)ctx->max_c > 2147483647LL) {
     delete ctx;
     return ULPPM_E_ARG;   // bond slots are int32
   }
   const int64_t n = n_points;
-  ctx->part_cap = kPartGather + 3 * (8 * (((n + 3) / 4 + 7) / 8)) + 64;
+  ctx->part_cap = kPartGather + 3 * 4096 + 64;
   ctx->scan_cap = (std::max<int64_t>(n + 1, ctx->max_cells) + kScanChunk - 1) / kScanChunk + 1;
   hipError_t e = hipSuccess;
   auto A = [&](void** p, size_t bytes) {
@@ -1398,7 +1651,12 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   A((void**)&ctx->cellid, sizeof(int32_t) * n);
   A((void**)&ctx->cnt, sizeof(int32_t) * n);
   A((void**)&ctx->row, sizeof(int64_t) * (n + 1));
-  A((void**)&ctx->ell, sizeof(int32_t) * ctx->bond_cap);
+  A((void**)&ctx->cand, sizeof(int32_t) * n * ctx->max_c);
+  A((void**)&ctx->ccnt, sizeof(int32_t) * n);
+  A((void**)&ctx->crev, sizeof(int32_t) * n * ctx->max_c);
+  A((void**)&ctx->posmap, sizeof(int32_t) * n * ctx->max_c);
+  A((void**)&ctx->xref, sizeof(double) * 3 * n);
+  A((void**)&ctx->gate, sizeof(int32_t));
   A((void**)&ctx->ccount, sizeof(int32_t) * ctx->max_cells);
   A((void**)&ctx->ccursor, sizeof(int32_t) * ctx->max_cells);
   A((void**)&ctx->cstart, sizeof(int64_t) * (ctx->max_cells + 1));
@@ -1409,7 +1667,8 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   A((void**)&ctx->part, sizeof(double) * ctx->part_cap);
   A((void**)&ctx->scan_bsum, sizeof(int64_t) * ctx->scan_cap);
   A((void**)&ctx->grid, sizeof(Grid));
-  A((void**)&ctx->ctr, sizeof(unsigned long long) * C_NCOUNT);
+  A((void**)&ctx->ctr, sizeof(unsigned long long) * C_NCOUNT * kStripes);
+  A((void**)&ctx->ctr_sum, sizeof(unsigned long long) * C_NCOUNT);
   A((void**)&ctx->E, sizeof(double) * 3);
   if (e != hipSuccess) {
     ulppm_destroy(ctx);
@@ -1442,9 +1701,10 @@ int ulppm_destroy(ulppm_ctx* ctx) {
   if (!ctx) return ULPPM_E_ARG;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
-  void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->cellid, ctx->cnt, ctx->row, ctx->ell,
+  void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->cellid, ctx->cnt, ctx->row, ctx->cand,
+                  ctx->ccnt, ctx->crev, ctx->posmap, ctx->xref, ctx->gate,
                   ctx->ccount, ctx->ccursor, ctx->cstart, ctx->cpts, ctx->col, ctx->rev, ctx->T,
-                  ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->E};
+                  ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->ctr_sum, ctx->E};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ctx->have_events)
@@ -1477,7 +1737,7 @@ int ulppm_build_families(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_param
   if ((rc = zero_counters(ctx))) return rc;
   k_positions<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, ctx->x, ctx->vh, ctx->vol_n);
   HIPCHK(hipGetLastError());
-  if ((rc = build_families(ctx, n, p->delta))) return rc;
+  if ((rc = build_families(ctx, n, p->delta, true))) return rc;
   if ((rc = read_counters(ctx))) return rc;
   if ((rc = counters_to_status(ctx))) return rc;
   int64_t nb = 0;
@@ -1509,7 +1769,7 @@ int ulppm_forces(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, do
   if ((rc = zero_counters(ctx))) return rc;
   k_positions<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, ctx->x, ctx->vh, ctx->vol_n);
   HIPCHK(hipGetLastError());
-  if ((rc = build_families(ctx, n, p->delta))) return rc;
+  if ((rc = build_families(ctx, n, p->delta, true))) return rc;
   if ((rc = bond_pass(ctx, S, p, dt_inc, false))) return rc;
   if ((rc = gather_pass(ctx, S, p, G_FORCES, ctx->pscr + 4 * n, f))) return rc;
   if ((rc = read_counters(ctx))) return rc;
@@ -1519,8 +1779,15 @@ int ulppm_forces(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, do
     int64_t nb = 0;
     HIPCHK(hipMemcpyAsync(&nb, ctx->row + n, sizeof(nb), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    const bool mixed = p->precision == ULPPM_MIXED;
     for (int c = 0; c < 3; ++c)
-      if (T_out[c]) k_copy_f64<<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(ctx->T + c * ctx->bond_cap, T_out[c], nb);
+      if (T_out[c]) {
+        if (mixed)
+          k_widen<<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(reinterpret_cast<const float*>(ctx->T) + c * ctx->bond_cap,
+                                                                 T_out[c], nb);
+        else
+          k_copy_f64<<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(ctx->T + c * ctx->bond_cap, T_out[c], nb);
+      }
     HIPCHK(hipGetLastError());
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1539,7 +1806,7 @@ int ulppm_init_state(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, doub
   k_init_points<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, P, ocr);
   k_positions<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, ctx->x, ctx->vh, ctx->vol_n);
   HIPCHK(hipGetLastError());
-  if ((rc = build_families(ctx, n, p->delta))) return rc;
+  if ((rc = build_families(ctx, n, p->delta, true))) return rc;
   if ((rc = bond_pass(ctx, S, p, 0.0, false))) return rc;
   if ((rc = gather_pass(ctx, S, p, G_INIT, S->mass, nullptr))) return rc;
   k_fill<double><<<1, 64, 0, ctx->stream>>>(ctx->E, 3, 0.0);
@@ -1558,7 +1825,7 @@ int ulppm_dt_crit(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, d
   if ((rc = zero_counters(ctx))) return rc;
   k_positions<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, ctx->x, ctx->vh, ctx->vol_n);
   HIPCHK(hipGetLastError());
-  if ((rc = build_families(ctx, n, p->delta))) return rc;
+  if ((rc = build_families(ctx, n, p->delta, true))) return rc;
   const int nb = blocks_for(n, 256, 1024);
   const double C = 18.0 * p->K / (M_PI * std::pow(p->delta, 4));
   k_dtcrit<<<nb, 256, 0, ctx->stream>>>(n, ctx->row, ctx->col, ctx->x, S->vol, S->phi, C, p->rho_s,
@@ -1595,7 +1862,7 @@ int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_
     HIPCHK(hipGetLastError());
     mark(k, 0, 1);
     mark(k, 1, 0);
-    if ((rc = build_families(ctx, n, p->delta))) return rc;
+    if ((rc = build_families(ctx, n, p->delta, k == 0))) return rc;
     mark(k, 1, 1);
     mark(k, 2, 0);
     if ((rc = bond_pass(ctx, S, p, p->dt, true))) return rc;
@@ -1603,7 +1870,7 @@ int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_
     mark(k, 3, 0);
     if ((rc = gather_pass(ctx, S, p, G_STEP, S->mass, nullptr))) return rc;
     mark(k, 3, 1);
-    const int64_t ngb = 8 * ((((n + 3) / 4) + 7) / 8);
+    const int64_t ngb = walk_grid(n);
     k_energy<<<1, 256, 0, ctx->stream>>>(ctx->part + kPartPred, npb, ctx->part + kPartGather, (int)ngb,
                                          ctx->E, ctx->row, n, ctx->ctr);
     HIPCHK(hipGetLastError());

@@ -13,7 +13,7 @@ from typing import Dict, Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libulppm.so")
+LIB_PATH = os.environ.get("ULPPM_LIB") or os.path.join(HERE, "libulppm.so")
 
 ULPPM_FP64, ULPPM_MIXED = 0, 1
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_CAPACITY", -4: "E_NOCONV", -5: "E_NONFINITE", -6: "E_ENERGY",

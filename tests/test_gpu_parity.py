@@ -273,3 +273,47 @@ def test_single_plane_blows_up_on_both_sides(olib, gpu):
     with pytest.raises(gpu.UlppmError) as ei:
         ctx.step(G, gprm, 5)
     assert ei.value.code == -5
+
+
+def test_candidate_rebuilds_inside_a_call(olib, gpu):
+    """A column translating at several m/s moves more than half the candidate
+    skin every few steps, so the candidate lists are rebuilt inside one
+    ulppm_step call; the trajectory must still match the oracle, whose
+    families are searched from scratch every step."""
+    say("candidate rebuilds")
+    col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, (6, 6, 10), seed=7, vscale=0.1)
+    S["v"][:] += np.array([5.0, -3.0, 2.0])
+    S["fixed"][:] = 0
+    G = gpu.DeviceState.from_arrays(S)
+    rc, E, st = olib.step(S, oprm, 40)
+    assert rc == 0
+    rep = ctx.step(G, gprm, 40)
+    assert rep["n_bond_updates"] == st["n_bonds"]
+    compare_states(G.to_arrays(), S, 1e-10, fields=("u", "v", "sig", "pc", "J"), label="moving column")
+
+
+@pytest.mark.parametrize("nsteps", [200, 500])
+def test_mixed_precision_trajectory_C0(olib, gpu, nsteps):
+    """Mixed precision (FP32 sums, force states and gather; FP64 inversion,
+    return map, history and positions) against the FP64 oracle: within 1e-4
+    relative L2 after 200 and 500 steps."""
+    say("mixed trajectory", nsteps)
+    col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, (8, 8, 16), seed=0)
+    gprm.precision = gpu.ULPPM_MIXED
+    rc, E, st = olib.step(S, oprm, nsteps)
+    assert rc == 0
+    ctx.step(G, gprm, nsteps)
+    compare_states(G.to_arrays(), S, 1e-4, fields=("u", "v", "sig", "pc", "J"), label=f"mixed {nsteps}")
+
+
+def test_mixed_precision_force_states(olib, gpu):
+    say("mixed forces")
+    col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, (8, 8, 16), seed=2, vscale=0.05)
+    gprm.precision = gpu.ULPPM_MIXED
+    out = olib.bond_fields(S, oprm, oprm.dt)
+    f, T, rep = ctx.forces(G, gprm, oprm.dt, want_T=True)
+    assert rep["n_bonds"] == out["row"][-1] and rep["n_triples"] == out["stats"]["n_triples"]
+    Tg = T.cpu().numpy().T
+    e = rel_l2(Tg, out["T"])
+    say("mixed T rel L2", e)
+    assert e < 1e-5
