@@ -184,6 +184,42 @@ int ulppm_forces(ulppm_ctx *ctx, const ulppm_state *state, const ulppm_params *p
 int ulppm_step(ulppm_ctx *ctx, ulppm_state *state, const ulppm_params *p, int32_t n_steps,
                ulppm_report *rep);
 
+/* Allocate the scratch of ulppm_adjoint_step (a copy of one state, the point
+ * adjoints and 7 doubles per bond slot).  Call once, before the first adjoint
+ * step; ulppm_adjoint_step itself never allocates.  Errors: ULPPM_E_ARG, ULPPM_E_HIP. */
+int ulppm_adjoint_reserve(ulppm_ctx *ctx);
+
+/* Reverse mode of one step n -> n+1 (the workload's hand-written adjoint of
+ * Algorithm 2 driving Algorithm 1), with that step's families, sub-horizons,
+ * degenerate bonds and elastic/plastic branches frozen.  Re-runs the forward
+ * step from state_n on scratch, then propagates adj_np1 (the adjoint of state
+ * n+1, same layout as a state: u, uc, v, a, vol, phi, J, Sr, mass, sig, pc;
+ * device arrays) back through the corrector, the gather (Eqs. 49-50), the
+ * conjugate force states, the bond tail (inversion, Eqs. 25-26 and 59, the
+ * return map by the implicit-function theorem at its solution), the
+ * sub-horizon sums (Eqs. 22-25, 57), the point kinematics (Eqs. 15-17, 48)
+ * and the predictor (Eqs. 60-61, 64), writing the adjoint of state n into
+ * adj_n.  adj_n->s receives adj_np1->s plus this step's suction adjoint and
+ * adj_n->x0 receives adj_np1->x0 plus the adjoint of x0, so both accumulate
+ * over a backward sweep; adj_n->Sr and adj_n->mass are zero (the step
+ * recomputes them).  theta_bar (device, 4 doubles) accumulates the adjoints of
+ * (M, lam, kap, eta).  adj_n may alias adj_np1.  FP64 with conjugate force
+ * states only.  Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_NOCONV,
+ * ULPPM_E_HIP. */
+int ulppm_adjoint_step(ulppm_ctx *ctx, const ulppm_state *state_n, const ulppm_params *p,
+                       const ulppm_state *adj_np1, ulppm_state *adj_n, double *theta_bar,
+                       ulppm_report *rep);
+
+/* Host-only self-check (no GPU call) of the library's hand-written reverse of the
+ * per-bond tail (inversion, velocity gradient, strain increment, Perzyna return
+ * map with its implicit-function adjoint, force-state factor) against central
+ * finite differences on n_cases random bonds, alternating elastic and plastic
+ * branches.  *max_rel receives the largest relative gradient error over all
+ * inputs and the parameters (M, lam, kap, eta); *n_plastic the plastic cases.
+ * Errors: ULPPM_E_ARG, ULPPM_E_NOCONV. */
+int ulppm_selfcheck_tail(const ulppm_params *p, int32_t seed, int32_t n_cases, double *max_rel,
+                         int32_t *n_plastic);
+
 /* Zero the accumulated energies W_int, W_ext (W_kin is recomputed each step). */
 int ulppm_reset_energy(ulppm_ctx *ctx);
 

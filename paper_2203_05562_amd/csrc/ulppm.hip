@@ -583,17 +583,17 @@ __global__ __launch_bounds__(256) void k_compact(int64_t n, int max_c, int max_f
 
 // ----------------------------------------------------- constitutive model --
 
-__device__ __forceinline__ double apparent_pc(const DevParams& P, double pc) {
+__host__ __device__ __forceinline__ double apparent_pc(const DevParams& P, double pc) {
   return -exp(P.b1) * pow(-pc, P.b2);               // Eq. 45
 }
 
-__device__ __forceinline__ double yield_f(const DevParams& P, double p, double q, double pcb) {
+__host__ __device__ __forceinline__ double yield_f(const DevParams& P, double p, double q, double pcb) {
   return q * q / (P.M * P.M) + p * (p - pcb);       // Eq. 40
 }
 
 // Retention curve, Eq. 15 read with exponent -(n-1)/n, suction in kPa, void
 // ratio e = phi/(1-phi).
-__device__ double swrc(const DevParams& P, double J, double phi, double s) {
+__host__ __device__ double swrc(const DevParams& P, double J, double phi, double s) {
   if (!(s > 0.0)) return 1.0;
   const double e = phi / (1.0 - phi);
   const double arg = P.a1 * pow(e, P.a2) * J * (s * 1e-3);
@@ -608,8 +608,8 @@ __device__ double swrc(const DevParams& P, double J, double phi, double s) {
 // g - c f(p, q, P) on [0, inf), where it changes sign once.
 struct ConsistencySolve {
   double K, mu, M2, lk, b1, b2, c, ptr, qtr, pcn;
-  __device__ double Pb(double pc) const { return -exp(b1) * pow(-pc, b2); }
-  __device__ double pc_for(double g) const {
+  __host__ __device__ double Pb(double pc) const { return -exp(b1) * pow(-pc, b2); }
+  __host__ __device__ double pc_for(double g) const {
     const double A = g / (lk * (1.0 + 2.0 * K * g));
     double hi = 0.0, lo = pcn;
     for (int k = 0; k < 4000; ++k) {             // bracket: h(lo) <= 0 < h(0-)
@@ -631,17 +631,17 @@ struct ConsistencySolve {
     }
     return x;
   }
-  __device__ void at(double g, double* x) const {
+  __host__ __device__ void at(double g, double* x) const {
     x[2] = pc_for(g);
     x[0] = (ptr + K * g * Pb(x[2])) / (1.0 + 2.0 * K * g);
     x[1] = qtr / (1.0 + 6.0 * mu * g / M2);
   }
-  __device__ double resid(double g) const {
+  __host__ __device__ double resid(double g) const {
     double x[3];
     at(g, x);
     return g - c * (x[1] * x[1] / M2 + x[0] * (x[0] - Pb(x[2])));
   }
-  __device__ void solve(double ftr, double* x) const {
+  __host__ __device__ void solve(double ftr, double* x) const {
     double lo = 0.0, hi = c * ftr, rlo = -c * ftr, rhi = resid(hi);
     for (int k = 0; k < 2000 && rhi < 0.0; ++k) { lo = hi; rlo = rhi; hi *= 2.0; rhi = resid(hi); }
     for (int it = 0; it < 400 && hi - lo > 2e-16 * hi; ++it) {
@@ -662,7 +662,7 @@ struct ConsistencySolve {
 // Newton with the exact tangent; steps are halved to stay in
 // {f > 0, q >= 0, p_c < 0}, where the solution lies.  Returns the iteration
 // count (0 elastic) or -1.
-__device__ int return_map(const DevParams& P, double dt, const double* sn, double pcn, const double* de,
+__host__ __device__ int return_map(const DevParams& P, double dt, const double* sn, double pcn, const double* de,
                           double* so, double* pco) {
   const double tr = de[0] + de[1] + de[2];
   double st[6];
@@ -752,9 +752,217 @@ __device__ int return_map(const DevParams& P, double dt, const double* sn, doubl
   return it > 0 ? it : 1;
 }
 
-__device__ __forceinline__ double det3s(double a, double b, double c, double d, double e, double f) {
+__host__ __device__ __forceinline__ double det3s(double a, double b, double c, double d, double e, double f) {
   // symmetric [[a f e],[f b d],[e d c]]
   return a * (b * c - d * d) - f * (f * c - d * e) + e * (f * d - b * e);
+}
+
+// ------------------------------------------------ per-bond tail and its reverse --
+// The per-bond tail of the step, as a function of the sub-horizon sums:
+//   K_ij^{-1}; L = N K^{-1}; de = dt sym(L) (Eqs. 25-26, 59); the Perzyna
+//   return map (Section 3.2.1); Q = sigma_ij + S_r s 1 (Eq. 32, p_w = -s);
+//   M_j = w_j Q K^{-1}, the factor of the conjugate force states.
+// tail_reverse is its hand-written adjoint, with the elastic/plastic branch
+// frozen; the return map is differentiated through the implicit-function
+// theorem at the converged point.  Both run on the device and on the host
+// (for the host self-check against finite differences).
+
+struct TailFwd {
+  double Ki[6];      // K^{-1}, Voigt
+  double de[6];      // strain increment, Voigt (tensor shears)
+  double sg[6];      // bond stress after the update
+  double pc;         // bond p_c after the update
+  double M[9];       // w Q K^{-1}, row-major
+  int branch;        // 0 elastic, > 0 plastic (Newton iterations), < 0 no convergence
+};
+
+// Inverse of a symmetric 3x3 in Voigt order (xx, yy, zz, yz, xz, xy).
+__host__ __device__ __forceinline__ double sym_inverse(const double* K, double* Ki) {
+  const double a = K[0], b = K[1], c = K[2], d = K[3], e = K[4], f = K[5];
+  const double det = det3s(a, b, c, d, e, f);
+  Ki[0] = (b * c - d * d) / det;
+  Ki[1] = (a * c - e * e) / det;
+  Ki[2] = (a * b - f * f) / det;
+  Ki[3] = (e * f - a * d) / det;
+  Ki[4] = (f * d - b * e) / det;
+  Ki[5] = (d * e - f * c) / det;
+  return det;
+}
+
+__host__ __device__ __forceinline__ void sym_full(const double* v, double* A) {
+  A[0] = v[0]; A[1] = v[5]; A[2] = v[4];
+  A[3] = v[5]; A[4] = v[1]; A[5] = v[3];
+  A[6] = v[4]; A[7] = v[3]; A[8] = v[2];
+}
+
+__host__ __device__ __forceinline__ void mat3_mul(const double* A, const double* B, double* C) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
+}
+
+// Gradient with respect to the six unique entries of a symmetric matrix,
+// from the gradient G with respect to its nine entries.
+__host__ __device__ __forceinline__ void unique_grad(const double* G, double* g) {
+  g[0] = G[0]; g[1] = G[4]; g[2] = G[8];
+  g[3] = G[5] + G[7]; g[4] = G[2] + G[6]; g[5] = G[1] + G[3];
+}
+
+__host__ __device__ void tail_forward(const DevParams& P, const double* K, const double* N, const double* sig,
+                                      double pc, double Srs, double w, double dt, TailFwd& F) {
+  sym_inverse(K, F.Ki);
+  double KiF[9], L[9];
+  sym_full(F.Ki, KiF);
+  mat3_mul(N, KiF, L);
+  F.de[0] = dt * L[0]; F.de[1] = dt * L[4]; F.de[2] = dt * L[8];
+  F.de[3] = dt * 0.5 * (L[5] + L[7]); F.de[4] = dt * 0.5 * (L[2] + L[6]); F.de[5] = dt * 0.5 * (L[1] + L[3]);
+  if (dt == 0.0) {
+    for (int k = 0; k < 6; ++k) F.sg[k] = sig[k];
+    F.pc = pc;
+    F.branch = 0;
+  } else {
+    F.branch = return_map(P, dt, sig, pc, F.de, F.sg, &F.pc);
+  }
+  double Q[6] = {F.sg[0] + Srs, F.sg[1] + Srs, F.sg[2] + Srs, F.sg[3], F.sg[4], F.sg[5]};
+  double QF[9], SK[9];
+  sym_full(Q, QF);
+  mat3_mul(QF, KiF, SK);
+  for (int k = 0; k < 9; ++k) F.M[k] = w * SK[k];
+}
+
+// Adjoint of the return map at fixed branch: given the adjoints of the
+// updated bond stress (sgb, Voigt components) and p_c, accumulate those of
+// the point stress, p_c,n, the strain increment and (M, lam, kap, eta).
+__host__ __device__ void rm_reverse(const DevParams& P, double dt, const double* sn, double pcn, const double* de,
+                                    const double* so, double pco, int branch, const double* sgb, double pcb,
+                                    double* snb, double* pcnb, double* deb, double* thb) {
+  const double tr = de[0] + de[1] + de[2];
+  double st[6], s[6];
+  for (int k = 0; k < 6; ++k)
+    st[k] = sn[k] + (k < 3 ? P.K * tr : 0.0) + 2.0 * P.mu * (de[k] - (k < 3 ? tr / 3.0 : 0.0));
+  const double ptr = (st[0] + st[1] + st[2]) / 3.0;
+  for (int k = 0; k < 6; ++k) s[k] = st[k] - (k < 3 ? ptr : 0.0);
+  const double qtr = sqrt(1.5 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5])));
+  double stb[6];
+  if (branch == 0) {
+    for (int k = 0; k < 6; ++k) stb[k] = sgb[k];
+    *pcnb += pcb;
+  } else {
+    const double p = (so[0] + so[1] + so[2]) / 3.0;
+    const double d0 = so[0] - p, d1 = so[1] - p, d2 = so[2] - p;
+    const double q = sqrt(1.5 * (d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * (so[3] * so[3] + so[4] * so[4] + so[5] * so[5])));
+    const double ratio = qtr > 0.0 ? q / qtr : 0.0;
+    // sigma = p 1 + ratio s_tr
+    const double pbar = sgb[0] + sgb[1] + sgb[2];
+    double ratiob = 0.0, sb[6];
+    for (int k = 0; k < 6; ++k) {
+      ratiob += sgb[k] * s[k];
+      sb[k] = ratio * sgb[k];
+    }
+    const double qbar = qtr > 0.0 ? ratiob / qtr : 0.0;
+    double qtrb = qtr > 0.0 ? -ratiob * q / (qtr * qtr) : 0.0;
+    // implicit function theorem at the solution x = (p, q, pc)
+    const double c = dt / P.eta, M2 = P.M * P.M, lk = P.lam - P.kap;
+    const double Pb = apparent_pc(P, pco);
+    const double dP = P.b2 * exp(P.b1) * pow(-pco, P.b2 - 1.0);
+    const double f = yield_f(P, p, q, Pb);
+    const double fp = 2.0 * p - Pb, fq = 2.0 * q / M2, fc = -p * dP;
+    const double E = exp(-c * f * fp / lk);
+    const double gp = fp * fp + 2.0 * f, gq = fq * fp, gc = fc * fp - f * dP;
+    const double hp = fp * fq, hq = fq * fq + f * 2.0 / M2, hc = fc * fq;
+    const double k1 = P.K * c, k2 = 3.0 * P.mu * c, k3 = pcn * E * c / lk;
+    const double A[9] = {1.0 + k1 * gp, k1 * gq, k1 * gc, k2 * hp, 1.0 + k2 * hq, k2 * hc,
+                         k3 * gp, k3 * gq, 1.0 + k3 * gc};
+    // mu = A^{-T} xbar by Cramer's rule on A^T
+    const double T[9] = {A[0], A[3], A[6], A[1], A[4], A[7], A[2], A[5], A[8]};
+    const double xb[3] = {pbar, qbar, pcb};
+    const double c11 = T[4] * T[8] - T[5] * T[7], c12 = T[5] * T[6] - T[3] * T[8], c13 = T[3] * T[7] - T[4] * T[6];
+    const double det = T[0] * c11 + T[1] * c12 + T[2] * c13;
+    const double m0 = (xb[0] * c11 + T[1] * (T[5] * xb[2] - xb[1] * T[8]) + T[2] * (xb[1] * T[7] - T[4] * xb[2])) / det;
+    const double m1 = (T[0] * (xb[1] * T[8] - T[5] * xb[2]) + xb[0] * c12 + T[2] * (T[3] * xb[2] - xb[1] * T[6])) / det;
+    const double m2 = (T[0] * (T[4] * xb[2] - xb[1] * T[7]) + T[1] * (xb[1] * T[6] - T[3] * xb[2]) + xb[0] * c13) / det;
+    // r1 = p - ptr + K c f fp, r2 = q - qtr + 3 mu c f fq, r3 = pc - pcn E
+    const double ptrb = m0;
+    qtrb += m1;
+    *pcnb += m2 * E;
+    // parameters: M (slope), lam, kap, eta
+    const double dfM = -2.0 * q * q / (M2 * P.M), dhM = -4.0 * q / (M2 * P.M);
+    const double r1M = k1 * dfM * fp, r2M = k2 * (dfM * fq + f * dhM), r3M = pcn * E * c * fp * dfM / lk;
+    const double r3lk = -pcn * E * c * f * fp / (lk * lk);
+    const double dcdeta = -c / P.eta;
+    const double r1e = P.K * f * fp * dcdeta, r2e = 3.0 * P.mu * f * fq * dcdeta, r3e = pcn * E * f * fp / lk * dcdeta;
+    thb[0] -= m0 * r1M + m1 * r2M + m2 * r3M;
+    thb[1] -= m2 * r3lk;
+    thb[2] += m2 * r3lk;
+    thb[3] -= m0 * r1e + m1 * r2e + m2 * r3e;
+    // trial state: p_tr, s_tr, q_tr from st
+    if (qtr > 0.0) {
+      const double wgt[6] = {1, 1, 1, 2, 2, 2};
+      for (int k = 0; k < 6; ++k) sb[k] += qtrb * 1.5 * wgt[k] * s[k] / qtr;
+    }
+    const double ssum = sb[0] + sb[1] + sb[2];
+    for (int k = 0; k < 6; ++k) stb[k] = sb[k] + (k < 3 ? (ptrb - ssum) / 3.0 : 0.0);
+  }
+  // sigma_tr = sigma_n + K tr 1 + 2 mu dev(de)
+  const double stsum = stb[0] + stb[1] + stb[2];
+  for (int k = 0; k < 6; ++k) {
+    snb[k] += stb[k];
+    deb[k] += 2.0 * P.mu * stb[k] + (k < 3 ? P.K * stsum - 2.0 * P.mu * stsum / 3.0 : 0.0);
+  }
+}
+
+// Adjoint of tail_forward: from the adjoints of M (9) and of the bond state
+// (sgb_ext, pcb_ext, e.g. from the history average) to those of K (unique
+// entries), N (9), the point stress and p_c, S_r s, w and the parameters.
+__host__ __device__ void tail_reverse(const DevParams& P, const double* K, const double* N, const double* sig,
+                                      double pc, double Srs, double w, double dt, const TailFwd& F,
+                                      const double* Mb, const double* sgb_ext, double pcb_ext, double* Kb,
+                                      double* Nb, double* sigb, double* pcbp, double* Srsb, double* wb,
+                                      double* thb) {
+  double KiF[9], QF[9], SK[9];
+  sym_full(F.Ki, KiF);
+  const double Q[6] = {F.sg[0] + Srs, F.sg[1] + Srs, F.sg[2] + Srs, F.sg[3], F.sg[4], F.sg[5]};
+  sym_full(Q, QF);
+  mat3_mul(QF, KiF, SK);
+  double SKb[9];
+  double wbar = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    SKb[k] = w * Mb[k];
+    wbar += Mb[k] * SK[k];
+  }
+  *wb += wbar;
+  // SK = Q Ki: Qbar = SKb Ki^T, Kibar = Q^T SKb (both matrices symmetric)
+  double QbF[9], KibF[9];
+  mat3_mul(SKb, KiF, QbF);
+  mat3_mul(QF, SKb, KibF);
+  double Qb[6];
+  unique_grad(QbF, Qb);
+  *Srsb += Qb[0] + Qb[1] + Qb[2];
+  double sgb[6];
+  for (int k = 0; k < 6; ++k) sgb[k] = Qb[k] + sgb_ext[k];
+  double deb[6] = {0, 0, 0, 0, 0, 0};
+  if (dt == 0.0) {
+    for (int k = 0; k < 6; ++k) sigb[k] += sgb[k];
+    *pcbp += pcb_ext;
+  } else {
+    rm_reverse(P, dt, sig, pc, F.de, F.sg, F.pc, F.branch, sgb, pcb_ext, sigb, pcbp, deb, thb);
+  }
+  // de = dt sym(L): Lbar
+  double Lb[9] = {dt * deb[0], 0.5 * dt * deb[5], 0.5 * dt * deb[4],
+                  0.5 * dt * deb[5], dt * deb[1], 0.5 * dt * deb[3],
+                  0.5 * dt * deb[4], 0.5 * dt * deb[3], dt * deb[2]};
+  // L = N Ki: Nbar = Lb Ki^T, Kibar += N^T Lb
+  mat3_mul(Lb, KiF, Nb);
+  double NT[9] = {N[0], N[3], N[6], N[1], N[4], N[7], N[2], N[5], N[8]};
+  double t[9];
+  mat3_mul(NT, Lb, t);
+  for (int k = 0; k < 9; ++k) KibF[k] += t[k];
+  // Ki = K^{-1}: Kbar = -Ki Kibar Ki
+  double u[9], KbF[9];
+  mat3_mul(KiF, KibF, u);
+  mat3_mul(u, KiF, KbF);
+  for (int k = 0; k < 9; ++k) KbF[k] = -KbF[k];
+  unique_grad(KbF, Kb);
 }
 
 // ---------------------------------------------------------- bond kernel --
@@ -1086,6 +1294,542 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MIN_WAVES) void k_bond(Bon
   }
 }
 
+// ------------------------------------------------------------- adjoint --
+// Reverse mode of one step n -> n+1 with the step's sets frozen (families,
+// sub-horizons, degenerate bonds, elastic/plastic branches).  The forward
+// step is first re-run on a scratch copy of state n, which leaves x^{n+1},
+// v_half, V^n, the families and the force states in the context.
+
+// Partial derivatives of the retention curve (Eq. 15 as read) in J, phi, s.
+__host__ __device__ void swrc_grad(const DevParams& P, double J, double phi, double s, double* dJ, double* dphi,
+                                   double* ds) {
+  *dJ = *dphi = *ds = 0.0;
+  if (!(s > 0.0)) return;
+  const double e = phi / (1.0 - phi);
+  const double X = P.a1 * pow(e, P.a2) * J * (s * 1e-3);
+  const double m = (P.n_vg - 1.0) / P.n_vg;
+  const double Xn = pow(X, P.n_vg);
+  const double dSdX = -m * pow(1.0 + Xn, -m - 1.0) * P.n_vg * Xn / X;
+  *dJ = dSdX * X / J;
+  *dphi = dSdX * X * P.a2 / (e * (1.0 - phi) * (1.0 - phi));
+  *ds = dSdX * X / s;
+}
+
+struct AdjArgs {
+  int64_t n, per;
+  const int64_t* row;
+  const int32_t* col;
+  const int32_t* rev;
+  const double* x;        // x^{n+1} (3n)
+  const double* vh;       // v_half (3n)
+  const double* vol_n;    // V^n
+  const double* J;        // state n
+  const double* phi;
+  const double* s;
+  const double* sig[6];
+  const double* pc;
+  const double* J1;       // state n+1 (forward re-run)
+  const double* phi1;
+  const double* Sr1;
+  const double* V1;
+  const double* sig1[6];
+  const double* pc1;
+  const double* T[3];     // forward force states
+  const double* fbar;     // 3n, adjoint of the nodal force
+  const double* Mbt;      // n, adjoint of M^{n+1} including the acceleration term
+  const double* Vb1;      // incoming adjoints of state n+1
+  const double* phib1;
+  const double* Jb1;
+  const double* Srb1;
+  const double* sigb1[6];
+  const double* pcb1;
+  double* own_x;          // 3n: -sum_k zeta_bar_ik
+  double* own_vh;         // 3n: -sum_k ydot_bar_ik
+  double* own_V;          // n
+  double* sigb;           // 6n adjoint of sigma^n
+  double* pcb;            // n
+  double* Jb;             // n
+  double* phib;           // n
+  double* sb;             // n, this step's suction adjoint
+  double* slot_x;         // 3 x cap: contribution to xbar_k from point i at slot (i,k)
+  double* slot_vh;        // 3 x cap
+  double* slot_V;         // cap
+  double* thpart;         // 4 per block
+  int64_t cap;
+  double dt;
+  int max_f;
+};
+
+template <class T>
+__host__ __device__ __forceinline__ void sym_full_grad(const double* Kb, double* Ks) {
+  // symmetric matrix Ks = G + G^T from the unique-entry gradient Kb (Voigt)
+  Ks[0] = 2.0 * Kb[0]; Ks[1] = 2.0 * Kb[1]; Ks[2] = 2.0 * Kb[2];
+  Ks[3] = Kb[3]; Ks[4] = Kb[4]; Ks[5] = Kb[5];
+}
+
+__host__ __device__ __forceinline__ void symv(const double* S, const double* z, double* out) {
+  out[0] = S[0] * z[0] + S[5] * z[1] + S[4] * z[2];
+  out[1] = S[5] * z[0] + S[1] * z[1] + S[3] * z[2];
+  out[2] = S[4] * z[0] + S[3] * z[1] + S[2] * z[2];
+}
+
+__global__ __launch_bounds__(256) void k_adj_point1(int64_t n, const uint8_t* __restrict__ fixed,
+                                                    const double* __restrict__ a1x, const double* __restrict__ a1y,
+                                                    const double* __restrict__ a1z, const double* __restrict__ M1,
+                                                    const double* __restrict__ vbx, const double* __restrict__ vby,
+                                                    const double* __restrict__ vbz, const double* __restrict__ abx,
+                                                    const double* __restrict__ aby, const double* __restrict__ abz,
+                                                    const double* __restrict__ Mb1, double h, double g0, double g1,
+                                                    double g2, double* __restrict__ fbar, double* __restrict__ Mbt) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    // v' = v_half + h a', a' = f/M' + g (free points)
+    const double at[3] = {abx[i] + h * vbx[i], aby[i] + h * vby[i], abz[i] + h * vbz[i]};
+    double mb = Mb1[i];
+    if (fixed[i]) {
+      fbar[i] = fbar[n + i] = fbar[2 * n + i] = 0.0;
+    } else {
+      const double M = M1[i];
+      const double a[3] = {a1x[i], a1y[i], a1z[i]}, g[3] = {g0, g1, g2};
+      for (int c = 0; c < 3; ++c) {
+        fbar[c * n + i] = at[c] / M;
+        mb -= at[c] * (a[c] - g[c]) / M;    // f/M^2 = (a - g)/M
+      }
+    }
+    Mbt[i] = mb;
+  }
+}
+
+// One workgroup per point i: re-run the bond pass of i, then reverse it.
+__global__ __launch_bounds__(kBondThreads) void k_adj_bond(AdjArgs A, DevParams P) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t i = xcd_point(blockIdx.x, A.per);
+  if (i >= A.n) {                                 // idle block: its parameter partials are zero
+    if (threadIdx.x < 4) A.thpart[4 * blockIdx.x + threadIdx.x] = 0.0;
+    return;
+  }
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int mf = A.max_f;
+  const int64_t n = A.n;
+  const int64_t b0 = A.row[i];
+  const int nf = (int)(A.row[i + 1] - b0);
+  const int nw = (mf + 63) / 64;
+  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);   // x_k
+  Quad<double>* sZ = sX + mf;                                     // zeta_ik, V_k
+  Quad<double>* sY = sZ + mf;                                     // ydot_ik
+  Quad<double>* sTb = sY + mf;                                    // Tbar_ik
+  Quad<double>* sZb = sTb + mf;                                   // zeta_bar_ik, slot Vbar_k
+  MRec<double>* sM = reinterpret_cast<MRec<double>*>(sZb + mf);   // M_j
+  double* sKN = reinterpret_cast<double*>(sM + mf);               // 16 per bond: K(6) N(9) active | Ks(6) Nb(9)
+  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)mf);
+  __shared__ double red[kBondWaves][32];
+  __shared__ double pt[32];
+
+  const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
+  const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
+  const double Vi = A.vol_n[i];
+  const double fb_i[3] = {A.fbar[i], A.fbar[n + i], A.fbar[2 * n + i]};
+
+  // ---- stage the family and the full-horizon sums (as the forward)
+  double Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0.0;
+  for (int m = tid; m < nf; m += kBondThreads) {
+    const int32_t k = A.col[b0 + m];
+    const double xk0 = A.x[k], xk1 = A.x[n + k], xk2 = A.x[2 * n + k];
+    const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
+    const double y0 = A.vh[k] - vi0, y1 = A.vh[n + k] - vi1, y2 = A.vh[2 * n + k] - vi2;
+    const double V = A.vol_n[k];
+    sX[m] = Quad<double>{{xk0, xk1, xk2, 0.0}};
+    sZ[m] = Quad<double>{{z0, z1, z2, V}};
+    sY[m] = Quad<double>{{y0, y1, y2, 0.0}};
+    sZb[m] = Quad<double>{{0.0, 0.0, 0.0, 0.0}};
+    const double w0 = V * z0, w1 = V * z1, w2 = V * z2;
+    Kp[0] += w0 * z0; Kp[1] += w1 * z1; Kp[2] += w2 * z2;
+    Kp[3] += w1 * z2; Kp[4] += w0 * z2; Kp[5] += w0 * z1;
+    Np[0] += y0 * w0; Np[1] += y0 * w1; Np[2] += y0 * w2;
+    Np[3] += y1 * w0; Np[4] += y1 * w1; Np[5] += y1 * w2;
+    Np[6] += y2 * w0; Np[7] += y2 * w1; Np[8] += y2 * w2;
+    Vp += V;
+  }
+  for (int k = 0; k < 6; ++k) Kp[k] = wave_sum(Kp[k]);
+  for (int k = 0; k < 9; ++k) Np[k] = wave_sum(Np[k]);
+  Vp = wave_sum(Vp);
+  if (lane == 0) {
+    for (int k = 0; k < 6; ++k) red[wid][k] = Kp[k];
+    for (int k = 0; k < 9; ++k) red[wid][6 + k] = Np[k];
+    red[wid][15] = Vp;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int k = 0; k < 16; ++k) {
+      double a = 0.0;
+      for (int w = 0; w < kBondWaves; ++w) a += red[w][k];
+      pt[k] = a;                                   // K_i (6), N_i (9), Vh
+    }
+  }
+  __syncthreads();
+  const double Vh = pt[15];
+  const double Sr1 = A.Sr1[i], s_i = A.s[i];
+  const double Srs = Sr1 * s_i;
+  double sig_i[6];
+  for (int k = 0; k < 6; ++k) sig_i[k] = A.sig[k][i];
+  const double pc_i = A.pc[i];
+  const double d2 = P.d2;
+  const double dt = A.dt;
+
+  // ---- pass 1 (re-run): sub-horizon sums, membership rows, tail forward
+  double Wp = 0.0;
+  for (int m = tid; m < nf; m += kBondThreads) {
+    const Quad<double> xj = sX[m];
+    double Kq[6] = {0, 0, 0, 0, 0, 0}, Nq[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int ns = 0;
+    for (int t0 = 0; t0 < nf; t0 += 64) {
+      const int tn = nf - t0 < 64 ? nf - t0 : 64;
+      unsigned long long word = 0ull;
+      for (int u = 0; u < tn; ++u) {
+        const int t = t0 + u;
+        const Quad<double> xk = sX[t];
+        const Quad<double> zk = sZ[t];
+        const Quad<double> yk = sY[t];
+        const bool in = within(xj.v[0], xj.v[1], xj.v[2], xk.v[0], xk.v[1], xk.v[2], d2);
+        const double w = in ? zk.v[3] : 0.0;
+        ns += in ? 1 : 0;
+        word |= (unsigned long long)in << u;
+        const double w0 = w * zk.v[0], w1 = w * zk.v[1], w2 = w * zk.v[2];
+        Kq[0] += w0 * zk.v[0]; Kq[1] += w1 * zk.v[1]; Kq[2] += w2 * zk.v[2];
+        Kq[3] += w1 * zk.v[2]; Kq[4] += w0 * zk.v[2]; Kq[5] += w0 * zk.v[1];
+        Nq[0] += yk.v[0] * w0; Nq[1] += yk.v[0] * w1; Nq[2] += yk.v[0] * w2;
+        Nq[3] += yk.v[1] * w0; Nq[4] += yk.v[1] * w1; Nq[5] += yk.v[1] * w2;
+        Nq[6] += yk.v[2] * w0; Nq[7] += yk.v[2] * w1; Nq[8] += yk.v[2] * w2;
+      }
+      sb[(size_t)m * nw + (t0 >> 6)] = word;
+    }
+    double* kn = sKN + 16 * (size_t)m;
+    const double dK = det3s(Kq[0], Kq[1], Kq[2], Kq[3], Kq[4], Kq[5]);
+    const double tk = (Kq[0] + Kq[1] + Kq[2]) / 3.0;
+    const bool active = ns >= 3 && dK > 1e-12 * tk * tk * tk;
+    for (int k = 0; k < 6; ++k) kn[k] = Kq[k];
+    for (int k = 0; k < 9; ++k) kn[6 + k] = Nq[k];
+    kn[15] = active ? 1.0 : 0.0;
+    MRec<double> r{};
+    if (active) {
+      const double Vj = sZ[m].v[3];
+      TailFwd F;
+      tail_forward(P, Kq, Nq, sig_i, pc_i, Srs, Vj / Vh, dt, F);
+      for (int q = 0; q < 9; ++q) r.v[q] = F.M[q];
+      Wp += Vj;
+    }
+    sM[m] = r;
+  }
+  Wp = wave_sum(Wp);
+  if (lane == 0) red[wid][16] = Wp;
+  __syncthreads();
+  double W = 0.0;
+  for (int w = 0; w < kBondWaves; ++w) W += red[w][16];
+
+  // ---- pass 2 (re-run) and the reverse of the gather:
+  // Tbar_ik = V_i V_k (fbar_i - fbar_k); zeta_bar_ik = A_ik^T Tbar_ik with
+  // A_ik = sum_j B_kj M_j; volume adjoints of the gather.
+  double ownV = 0.0;
+  for (int m = tid; m < nf; m += kBondThreads) {
+    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j0 = 0; j0 < nf; j0 += 64) {
+      const unsigned long long word = sb[(size_t)m * nw + (j0 >> 6)];
+      const int jn = nf - j0 < 64 ? nf - j0 : 64;
+      for (int jj = 0; jj < jn; ++jj) {
+        const double w = (word >> jj) & 1ull ? 1.0 : 0.0;
+        const MRec<double> r = sM[j0 + jj];
+        for (int q = 0; q < 9; ++q) a[q] += w * r.v[q];
+      }
+    }
+    const int64_t slot = b0 + m;
+    const int32_t k = A.col[slot];
+    const double Vk = sZ[m].v[3];
+    const double fb_k[3] = {A.fbar[k], A.fbar[n + k], A.fbar[2 * n + k]};
+    double tb[3];
+    for (int c = 0; c < 3; ++c) tb[c] = Vi * Vk * (fb_i[c] - fb_k[c]);
+    sTb[m] = Quad<double>{{tb[0], tb[1], tb[2], 0.0}};
+    Quad<double> zb;
+    zb.v[0] = a[0] * tb[0] + a[3] * tb[1] + a[6] * tb[2];
+    zb.v[1] = a[1] * tb[0] + a[4] * tb[1] + a[7] * tb[2];
+    zb.v[2] = a[2] * tb[0] + a[5] * tb[1] + a[8] * tb[2];
+    // f_i = V_i sum_k V_k (T_ik - T_ki)
+    const int32_t r = A.rev[slot];
+    double dT_dot_fb = 0.0;
+    for (int c = 0; c < 3; ++c) dT_dot_fb += (A.T[c][slot] - A.T[c][r]) * fb_i[c];
+    ownV += Vk * dT_dot_fb;
+    zb.v[3] = Vi * dT_dot_fb;                       // to Vbar_k
+    sZb[m] = zb;
+  }
+  __syncthreads();
+
+  // ---- reverse of the force states (R5) and of the bond tail
+  const double sgb1[6] = {A.sigb1[0][i], A.sigb1[1][i], A.sigb1[2][i], A.sigb1[3][i], A.sigb1[4][i], A.sigb1[5][i]};
+  const double pcb1 = A.pcb1[i];
+  double sig1[6];
+  for (int k = 0; k < 6; ++k) sig1[k] = A.sig1[k][i];
+  const double pc1 = A.pc1[i];
+  double acc_sig[6] = {0, 0, 0, 0, 0, 0}, acc_pc = 0.0, acc_Srs = 0.0, acc_Vh = 0.0, acc_th[4] = {0, 0, 0, 0};
+  for (int m = tid; m < nf; m += kBondThreads) {
+    double* kn = sKN + 16 * (size_t)m;
+    const bool active = kn[15] != 0.0;
+    double Kb[6] = {0, 0, 0, 0, 0, 0}, Nb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (active) {
+      // Mbar_j = sum_k B_jk Tbar_ik zeta_ik^T
+      double mb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int t0 = 0; t0 < nf; t0 += 64) {
+        const unsigned long long word = sb[(size_t)m * nw + (t0 >> 6)];
+        const int tn = nf - t0 < 64 ? nf - t0 : 64;
+        for (int u = 0; u < tn; ++u) {
+          const double w = (word >> u) & 1ull ? 1.0 : 0.0;
+          const Quad<double> tbk = sTb[t0 + u];
+          const Quad<double> zk = sZ[t0 + u];
+          for (int r = 0; r < 3; ++r) {
+            const double wt = w * tbk.v[r];
+            mb[3 * r] += wt * zk.v[0];
+            mb[3 * r + 1] += wt * zk.v[1];
+            mb[3 * r + 2] += wt * zk.v[2];
+          }
+        }
+      }
+      double Kq[6], Nq[9];
+      for (int k = 0; k < 6; ++k) Kq[k] = kn[k];
+      for (int k = 0; k < 9; ++k) Nq[k] = kn[6 + k];
+      const double Vj = sZ[m].v[3];
+      TailFwd F;
+      tail_forward(P, Kq, Nq, sig_i, pc_i, Srs, Vj / Vh, dt, F);
+      // history: sigma'_i = sum_j V_j sigma_ij / W
+      double sgx[6];
+      double vh_hist = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        sgx[k] = sgb1[k] * Vj / W;
+        vh_hist += sgb1[k] * (F.sg[k] - sig1[k]);
+      }
+      vh_hist += pcb1 * (F.pc - pc1);
+      const double pcx = pcb1 * Vj / W;
+      double wb = 0.0;
+      tail_reverse(P, Kq, Nq, sig_i, pc_i, Srs, Vj / Vh, dt, F, mb, sgx, pcx, Kb, Nb, acc_sig, &acc_pc, &acc_Srs,
+                   &wb, acc_th);
+      // w_j = V_j / Vh
+      sZb[m].v[3] += wb / Vh + vh_hist / W;
+      acc_Vh -= wb * Vj / (Vh * Vh);
+    }
+    double Ks[6];
+    sym_full_grad<double>(Kb, Ks);
+    for (int k = 0; k < 6; ++k) kn[k] = Ks[k];
+    for (int k = 0; k < 9; ++k) kn[6 + k] = Nb[k];
+  }
+  // block reductions: sigma_bar_i (6), pc_bar_i, Srs_bar, Vh_bar, theta (4), own V (gather)
+  double vals[14] = {acc_sig[0], acc_sig[1], acc_sig[2], acc_sig[3], acc_sig[4], acc_sig[5], acc_pc, acc_Srs,
+                     acc_Vh, acc_th[0], acc_th[1], acc_th[2], acc_th[3], ownV};
+  for (int k = 0; k < 14; ++k) vals[k] = wave_sum(vals[k]);
+  __syncthreads();
+  if (lane == 0)
+    for (int k = 0; k < 14; ++k) red[wid][k] = vals[k];
+  __syncthreads();
+  if (tid == 0) {
+    double v[14];
+    for (int k = 0; k < 14; ++k) {
+      v[k] = 0.0;
+      for (int w = 0; w < kBondWaves; ++w) v[k] += red[w][k];
+    }
+    double Vb_own = v[13];                       // gather: sum_k V_k (T_ik - T_ki).fbar_i
+    // history with no active bond keeps the point state
+    if (!(W > 0.0)) {
+      for (int k = 0; k < 6; ++k) v[k] += sgb1[k];
+      v[6] += pcb1;
+    }
+    for (int k = 0; k < 6; ++k) A.sigb[k * n + i] = v[k];
+    A.pcb[i] = v[6];
+    const double Srsb = v[7];
+    double Vhb = v[8];
+    for (int k = 0; k < 4; ++k) A.thpart[4 * blockIdx.x + k] = v[9 + k];
+    // point kinematics reverse (Eqs. 15-17, 48)
+    const double J0 = A.J[i], phi0 = A.phi[i], V0 = Vi;
+    const double J1 = A.J1[i], phi1 = A.phi1[i], V1 = A.V1[i];
+    const double Jd = V1 / V0;
+    const double Mb = A.Mbt[i];
+    double V1b = A.Vb1[i] + Mb * (P.rho_s * (1.0 - phi1) + P.rho_w * Sr1 * phi1);
+    double phi1b = A.phib1[i] + Mb * V1 * (P.rho_w * Sr1 - P.rho_s);
+    double Sr1b = A.Srb1[i] + Mb * P.rho_w * phi1 * V1 + s_i * Srsb;
+    double sbar = Sr1 * Srsb;
+    double dJ, dphi, ds;
+    swrc_grad(P, J1, phi1, s_i, &dJ, &dphi, &ds);
+    const double J1b = A.Jb1[i] + Sr1b * dJ;
+    phi1b += Sr1b * dphi;
+    sbar += Sr1b * ds;
+    const double Jdb = J1b * J0 + V1b * V0 + phi1b * (1.0 - phi0) / (Jd * Jd);
+    A.Jb[i] = J1b * Jd;
+    A.phib[i] = phi1b / Jd;
+    A.sb[i] = sbar;
+    Vb_own += V1b * Jd;
+    // Jd = 1/det(B), B = I - dt L_i, L_i = N_i K_i^{-1}
+    double Ks_i[6] = {0, 0, 0, 0, 0, 0}, Nb_i[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const double dKi = det3s(pt[0], pt[1], pt[2], pt[3], pt[4], pt[5]);
+    const double tki = (pt[0] + pt[1] + pt[2]) / 3.0;
+    if (nf >= 3 && dKi > 1e-12 * tki * tki * tki && dt != 0.0) {
+      double Ki[6], KiF[9], Li[9], B[9], Bi[9];
+      sym_inverse(pt, Ki);
+      sym_full(Ki, KiF);
+      mat3_mul(pt + 6, KiF, Li);
+      for (int k = 0; k < 9; ++k) B[k] = (k % 4 == 0 ? 1.0 : 0.0) - dt * Li[k];
+      const double dB = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
+                        B[2] * (B[3] * B[7] - B[4] * B[6]);
+      Bi[0] = (B[4] * B[8] - B[5] * B[7]) / dB; Bi[1] = (B[2] * B[7] - B[1] * B[8]) / dB;
+      Bi[2] = (B[1] * B[5] - B[2] * B[4]) / dB; Bi[3] = (B[5] * B[6] - B[3] * B[8]) / dB;
+      Bi[4] = (B[0] * B[8] - B[2] * B[6]) / dB; Bi[5] = (B[2] * B[3] - B[0] * B[5]) / dB;
+      Bi[6] = (B[3] * B[7] - B[4] * B[6]) / dB; Bi[7] = (B[1] * B[6] - B[0] * B[7]) / dB;
+      Bi[8] = (B[0] * B[4] - B[1] * B[3]) / dB;
+      // dJd/dB = -Jd B^{-T};  Lbar = -dt Bbar = dt Jdb Jd B^{-T}
+      double Lb[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Lb[3 * r + c] = dt * Jdb * Jd * Bi[3 * c + r];
+      mat3_mul(Lb, KiF, Nb_i);
+      const double* Ni = pt + 6;
+      double NT[9] = {Ni[0], Ni[3], Ni[6], Ni[1], Ni[4], Ni[7], Ni[2], Ni[5], Ni[8]};
+      double KibF[9], u9[9], KbF[9], Kbu[6];
+      mat3_mul(NT, Lb, KibF);
+      mat3_mul(KiF, KibF, u9);
+      mat3_mul(u9, KiF, KbF);
+      for (int k = 0; k < 9; ++k) KbF[k] = -KbF[k];
+      unique_grad(KbF, Kbu);
+      sym_full_grad<double>(Kbu, Ks_i);
+    }
+    for (int k = 0; k < 6; ++k) pt[16 + k] = Ks_i[k];
+    for (int k = 0; k < 9; ++k) pt[22 + k] = Nb_i[k];
+    pt[31] = Vhb;
+    A.own_V[i] = Vb_own;
+  }
+  __syncthreads();
+
+  // ---- reverse of the sums (R3): G_k = Ks_i + sum_j B_kj Ks_j, H_k = Nb_i + sum_j B_kj Nb_j
+  double ox[3] = {0, 0, 0}, oy[3] = {0, 0, 0};
+  const double Vhb = pt[31];
+  for (int m = tid; m < nf; m += kBondThreads) {
+    double G[6], H[9];
+    for (int k = 0; k < 6; ++k) G[k] = pt[16 + k];
+    for (int k = 0; k < 9; ++k) H[k] = pt[22 + k];
+    for (int j0 = 0; j0 < nf; j0 += 64) {
+      const unsigned long long word = sb[(size_t)m * nw + (j0 >> 6)];
+      const int jn = nf - j0 < 64 ? nf - j0 : 64;
+      for (int jj = 0; jj < jn; ++jj) {
+        const double w = (word >> jj) & 1ull ? 1.0 : 0.0;
+        const double* kn = sKN + 16 * (size_t)(j0 + jj);
+        for (int k = 0; k < 6; ++k) G[k] += w * kn[k];
+        for (int k = 0; k < 9; ++k) H[k] += w * kn[6 + k];
+      }
+    }
+    const Quad<double> zq = sZ[m];
+    const Quad<double> yq = sY[m];
+    const double z[3] = {zq.v[0], zq.v[1], zq.v[2]}, y[3] = {yq.v[0], yq.v[1], yq.v[2]};
+    const double Vk = zq.v[3];
+    double Gz[3], Hz[3], HTy[3];
+    symv(G, z, Gz);
+    for (int r = 0; r < 3; ++r) Hz[r] = H[3 * r] * z[0] + H[3 * r + 1] * z[1] + H[3 * r + 2] * z[2];
+    for (int c = 0; c < 3; ++c) HTy[c] = H[c] * y[0] + H[3 + c] * y[1] + H[6 + c] * y[2];
+    Quad<double> zb = sZb[m];
+    double zbar[3], ybar[3];
+    for (int c = 0; c < 3; ++c) {
+      zbar[c] = zb.v[c] + Vk * (Gz[c] + HTy[c]);
+      ybar[c] = Vk * Hz[c];
+    }
+    const double Vbar = zb.v[3] + 0.5 * (z[0] * Gz[0] + z[1] * Gz[1] + z[2] * Gz[2]) +
+                        (y[0] * Hz[0] + y[1] * Hz[1] + y[2] * Hz[2]) + Vhb;
+    const int64_t slot = b0 + m;
+    for (int c = 0; c < 3; ++c) {
+      A.slot_x[c * A.cap + slot] = zbar[c];
+      A.slot_vh[c * A.cap + slot] = ybar[c];
+      ox[c] -= zbar[c];
+      oy[c] -= ybar[c];
+    }
+    A.slot_V[slot] = Vbar;
+  }
+  for (int c = 0; c < 3; ++c) {
+    ox[c] = wave_sum(ox[c]);
+    oy[c] = wave_sum(oy[c]);
+  }
+  __syncthreads();
+  if (lane == 0)
+    for (int c = 0; c < 3; ++c) { red[wid][c] = ox[c]; red[wid][3 + c] = oy[c]; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int c = 0; c < 3; ++c) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < kBondWaves; ++w) { a += red[w][c]; b += red[w][3 + c]; }
+      A.own_x[c * n + i] = a;
+      A.own_vh[c * n + i] = b;
+    }
+  }
+}
+
+// Per point: collect the contributions other points made to this one
+// (stored at slot (i,k), found through rev[]), finish the reverse of the
+// predictor, and write the adjoint of state n.
+__global__ __launch_bounds__(256) void k_adj_point2(int64_t n, const int64_t* __restrict__ row,
+                                                    const int32_t* __restrict__ rev, const uint8_t* __restrict__ fixed,
+                                                    const double* __restrict__ own_x, const double* __restrict__ own_vh,
+                                                    const double* __restrict__ own_V, const double* __restrict__ slot_x,
+                                                    const double* __restrict__ slot_vh,
+                                                    const double* __restrict__ slot_V, int64_t cap,
+                                                    const double* __restrict__ sigb, const double* __restrict__ pcb,
+                                                    const double* __restrict__ Jb, const double* __restrict__ phib,
+                                                    const double* __restrict__ sb, ulppm_state In, ulppm_state Out,
+                                                    double dt) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const XcdWalk W = xcd_walk(n, 4);
+  for (int64_t k = W.first; k < W.end; k += W.stride) {
+    double ax[3] = {0, 0, 0}, av[3] = {0, 0, 0}, aV = 0.0;
+    for (int64_t s = row[k] + lane; s < row[k + 1]; s += kWave) {
+      const int32_t r = rev[s];
+      for (int c = 0; c < 3; ++c) {
+        ax[c] += slot_x[c * cap + r];
+        av[c] += slot_vh[c * cap + r];
+      }
+      aV += slot_V[r];
+    }
+    for (int c = 0; c < 3; ++c) {
+      ax[c] = wave_sum(ax[c]);
+      av[c] = wave_sum(av[c]);
+    }
+    aV = wave_sum(aV);
+    if (lane == 0) {
+      const bool fx = fixed[k] != 0;
+      for (int c = 0; c < 3; ++c) {
+        const double xb = own_x[c * n + k] + ax[c];
+        const double ub = In.u[c][k] + xb;                   // u^{n+1} = u^n + dt v_half, x = x0 + u^{n+1}
+        const double vhb = In.v[c][k] + own_vh[c * n + k] + av[c] + dt * ub;
+        Out.x0[c][k] = In.x0[c][k] + xb;
+        Out.u[c][k] = ub;
+        Out.uc[c][k] = -ub;
+        Out.v[c][k] = fx ? 0.0 : vhb;
+        Out.a[c][k] = fx ? 0.0 : 0.5 * dt * vhb;
+      }
+      Out.vol[k] = own_V[k] + aV;
+      Out.phi[k] = phib[k];
+      Out.J[k] = Jb[k];
+      Out.Sr[k] = 0.0;
+      Out.mass[k] = 0.0;
+      Out.s[k] = In.s[k] + sb[k];
+      for (int c = 0; c < 6; ++c) Out.sig[c][k] = sigb[c * n + k];
+      Out.pc[k] = pcb[k];
+    }
+  }
+}
+
+__global__ void k_adj_theta(const double* __restrict__ part, int64_t nb, double* __restrict__ th) {
+  __shared__ double s[4][256];
+  double a[4] = {0, 0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nb; b += 256)
+    for (int k = 0; k < 4; ++k) a[k] += part[4 * b + k];
+  for (int k = 0; k < 4; ++k) s[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int k = 0; k < 4; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) th[k] += s[k][0];
+}
+
 // -------------------------------------------------------- gather kernel --
 
 enum { G_FORCES = 0, G_INIT = 1, G_STEP = 2 };
@@ -1328,6 +2072,9 @@ struct ulppm_ctx {
   unsigned long long* ctr = nullptr;      // C_NCOUNT x kStripes
   unsigned long long* ctr_sum = nullptr;  // C_NCOUNT, folded
   double* E = nullptr;        // 3
+  // adjoint scratch (ulppm_adjoint_reserve)
+  double* adj = nullptr;      // 24n forward copy + 21n point adjoints + 4(n+8) partials
+  double* adj_slot = nullptr; // 7 x bond_cap
   // phase timing events, [step][phase][start/stop]
   hipEvent_t ev[kTimedSteps][kPhases][2] = {};
   bool have_events = false;
@@ -1619,6 +2366,152 @@ void add_timings(ulppm_ctx* ctx, int64_t timed, ulppm_report* rep) {
 
 extern "C" {
 
+// Host-only check of the hand-written reverse of the per-bond tail against
+// central finite differences (no GPU call).  Random sums, stresses and
+// velocity gradients; cases alternate between the elastic and the plastic
+// branch.  *max_rel receives the largest relative gradient error, *n_plastic
+// the number of plastic cases checked.
+int ulppm_selfcheck_tail(const ulppm_params* p, int32_t seed, int32_t n_cases, double* max_rel,
+                         int32_t* n_plastic) {
+  if (!p || !max_rel || !n_plastic || n_cases <= 0) return ULPPM_E_ARG;
+  DevParams P = dev_params(p);
+  uint64_t st = 0x9E3779B97F4A7C15ull ^ (uint64_t)seed;
+  auto rnd = [&]() {
+    st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+    return (double)(st >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+  };
+  double worst = 0.0;
+  int npl = 0;
+  for (int cs = 0; cs < n_cases; ++cs) {
+    // inputs
+    double K[6] = {0, 0, 0, 0, 0, 0};
+    for (int m = 0; m < 12; ++m) {
+      const double z[3] = {rnd() * 0.03, rnd() * 0.03, rnd() * 0.03};
+      K[0] += 1e-6 * z[0] * z[0]; K[1] += 1e-6 * z[1] * z[1]; K[2] += 1e-6 * z[2] * z[2];
+      K[3] += 1e-6 * z[1] * z[2]; K[4] += 1e-6 * z[0] * z[2]; K[5] += 1e-6 * z[0] * z[1];
+    }
+    const bool plastic = (cs % 2) == 1;
+    const double gscale = plastic ? 40.0 : 0.5;        // velocity-gradient magnitude [1/s]
+    double Ki[6];
+    sym_inverse(K, Ki);
+    double KiF[9], Lr[9], N[9];
+    sym_full(Ki, KiF);
+    for (int k = 0; k < 9; ++k) Lr[k] = gscale * rnd();
+    // N = L K so that L = N K^{-1} has the chosen size
+    double KF[9];
+    sym_full(K, KF);
+    mat3_mul(Lr, KF, N);
+    double sig[6] = {-30e3 + 2e3 * rnd(), -28e3 + 2e3 * rnd(), -33e3 + 2e3 * rnd(), 3e3 * rnd(), 3e3 * rnd(),
+                     3e3 * rnd()};
+    const double pc = plastic ? -31e3 : -60e3;
+    const double Srs = 19e3 * (1.0 + 0.1 * rnd());
+    const double w = 0.009 * (1.0 + 0.1 * rnd());
+    const double dt = p->dt;
+    // weights of the test functional, each term scaled to O(1) so that the
+    // central differences are not swamped by rounding
+    TailFwd F0;
+    tail_forward(P, K, N, sig, pc, Srs, w, dt, F0);
+    double mM = 0.0, mS = 0.0;
+    for (int k = 0; k < 9; ++k) mM = fmax(mM, fabs(F0.M[k]));
+    for (int k = 0; k < 6; ++k) mS = fmax(mS, fabs(F0.sg[k]));
+    double R[9], Rs[6];
+    for (int k = 0; k < 9; ++k) R[k] = rnd() / mM;
+    for (int k = 0; k < 6; ++k) Rs[k] = rnd() / mS;
+    const double Rp = rnd() / fabs(F0.pc);
+    auto J = [&](const DevParams& PP, const double* K_, const double* N_, const double* sg_, double pc_, double Srs_,
+                 double w_, int* br) {
+      TailFwd F;
+      tail_forward(PP, K_, N_, sg_, pc_, Srs_, w_, dt, F);
+      *br = F.branch;
+      double v = Rp * F.pc;
+      for (int k = 0; k < 9; ++k) v += R[k] * F.M[k];
+      for (int k = 0; k < 6; ++k) v += Rs[k] * F.sg[k];
+      return v;
+    };
+    TailFwd F;
+    tail_forward(P, K, N, sig, pc, Srs, w, dt, F);
+    if (F.branch < 0) return ULPPM_E_NOCONV;
+    if (F.branch > 0) ++npl;
+    double Kb[6], Nb[9], sigb[6] = {0, 0, 0, 0, 0, 0}, pcb = 0, Srsb = 0, wb = 0, thb[4] = {0, 0, 0, 0};
+    tail_reverse(P, K, N, sig, pc, Srs, w, dt, F, R, Rs, Rp, Kb, Nb, sigb, &pcb, &Srsb, &wb, thb);
+    // finite differences, input by input
+    auto check = [&](double analytic, double fd) {
+      const double scale = fabs(analytic) + fabs(fd) + 1e-300;
+      const double e = fabs(analytic - fd) / scale;
+      return e;
+    };
+    double gmax = 0.0, emax = 0.0;
+    auto fd = [&](double& x, double scale) -> double {
+      const double h = 1e-6 * scale;
+      const double x0 = x;
+      int b1, b2;
+      x = x0 + h;
+      const double jp = J(P, K, N, sig, pc, Srs, w, &b1);
+      x = x0 - h;
+      const double jm = J(P, K, N, sig, pc, Srs, w, &b2);
+      x = x0;
+      if (b1 != F.branch || b2 != F.branch) return (double)NAN;
+      return (jp - jm) / (2 * h);
+    };
+    double grads[40], fds[40];
+    int ng = 0;
+    double sK = 0.0, sN = 0.0, sS = 0.0;       // step sizes scaled by each input group
+    for (int k = 0; k < 6; ++k) sK = fmax(sK, fabs(K[k]));
+    for (int k = 0; k < 9; ++k) sN = fmax(sN, fabs(N[k]));
+    for (int k = 0; k < 6; ++k) sS = fmax(sS, fabs(sig[k]));
+    for (int k = 0; k < 6; ++k) { grads[ng] = Kb[k]; fds[ng++] = fd(K[k], sK); }
+    for (int k = 0; k < 9; ++k) { grads[ng] = Nb[k]; fds[ng++] = fd(N[k], sN); }
+    for (int k = 0; k < 6; ++k) { grads[ng] = sigb[k]; fds[ng++] = fd(sig[k], sS); }
+    double pcv = pc, Srsv = Srs, wv = w;
+    {
+      const double h = 1e-6 * fabs(pcv);
+      int b1, b2;
+      const double jp = J(P, K, N, sig, pcv + h, Srs, w, &b1), jm = J(P, K, N, sig, pcv - h, Srs, w, &b2);
+      grads[ng] = pcb; fds[ng++] = (b1 == F.branch && b2 == F.branch) ? (jp - jm) / (2 * h) : (double)NAN;
+    }
+    {
+      const double h = 1e-6 * Srsv;
+      int b1, b2;
+      const double jp = J(P, K, N, sig, pc, Srsv + h, w, &b1), jm = J(P, K, N, sig, pc, Srsv - h, w, &b2);
+      grads[ng] = Srsb; fds[ng++] = (b1 == F.branch && b2 == F.branch) ? (jp - jm) / (2 * h) : (double)NAN;
+    }
+    {
+      const double h = 1e-6 * wv;
+      int b1, b2;
+      const double jp = J(P, K, N, sig, pc, Srs, wv + h, &b1), jm = J(P, K, N, sig, pc, Srs, wv - h, &b2);
+      grads[ng] = wb; fds[ng++] = (b1 == F.branch && b2 == F.branch) ? (jp - jm) / (2 * h) : (double)NAN;
+    }
+    double* th[4] = {&P.M, &P.lam, &P.kap, &P.eta};
+    for (int k = 0; k < 4; ++k) {
+      double& x = *th[k];
+      const double x0 = x, h = 1e-5 * fabs(x0);
+      int b1, b2;
+      x = x0 + h;
+      const double jp = J(P, K, N, sig, pc, Srs, w, &b1);
+      x = x0 - h;
+      const double jm = J(P, K, N, sig, pc, Srs, w, &b2);
+      x = x0;
+      grads[ng] = thb[k];
+      fds[ng++] = (b1 == F.branch && b2 == F.branch) ? (jp - jm) / (2 * h) : (double)NAN;
+    }
+    for (int k = 0; k < ng; ++k) gmax = fmax(gmax, fabs(grads[k]) * 1.0);
+    // weight each input's error by its own scale times the input size so that
+    // gradients that are exactly zero in one branch do not dominate
+    for (int k = 0; k < ng; ++k) {
+      if (std::isnan(fds[k])) continue;
+      const double e = check(grads[k], fds[k]);
+      if (fabs(grads[k]) + fabs(fds[k]) > 1e-9 * gmax) emax = fmax(emax, e);
+#ifdef ULPPM_SELFCHECK_VERBOSE
+      if (e > 1e-5) printf("case %d branch %d input %d: reverse %.10e fd %.10e\n", cs, F.branch, k, grads[k], fds[k]);
+#endif
+    }
+    worst = fmax(worst, emax);
+  }
+  *max_rel = worst;
+  *n_plastic = npl;
+  return ULPPM_OK;
+}
+
 int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hip_stream) {
   ulppm_ctx* ctx = nullptr;
   if (!out) return ULPPM_E_ARG;
@@ -1704,7 +2597,8 @@ int ulppm_destroy(ulppm_ctx* ctx) {
   void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->cellid, ctx->cnt, ctx->row, ctx->cand,
                   ctx->ccnt, ctx->crev, ctx->posmap, ctx->xref, ctx->gate,
                   ctx->ccount, ctx->ccursor, ctx->cstart, ctx->cpts, ctx->col, ctx->rev, ctx->T,
-                  ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->ctr_sum, ctx->E};
+                  ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->ctr_sum, ctx->E, ctx->adj,
+                  ctx->adj_slot};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ctx->have_events)
@@ -1839,6 +2733,130 @@ int ulppm_dt_crit(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, d
   for (int b = 0; b < nb; ++b) best = std::fmin(best, h[b]);
   *dt_out = best;
   return ULPPM_OK;
+}
+
+size_t adj_lds(int max_f) {
+  return (size_t)max_f * (5 * sizeof(Quad<double>) + sizeof(MRec<double>) + 16 * sizeof(double) +
+                          (size_t)((max_f + 63) / 64) * sizeof(unsigned long long));
+}
+
+int ulppm_adjoint_reserve(ulppm_ctx* ctx) {
+  if (!ctx) return ULPPM_E_ARG;
+  if (ctx->adj) return ULPPM_OK;
+  const int64_t n = ctx->cap_n;
+  const size_t pts = sizeof(double) * (size_t)(45 * n + 4 * (n + 8));
+  HIPCHK(hipMalloc((void**)&ctx->adj, pts));
+  const hipError_t e = hipMalloc((void**)&ctx->adj_slot, sizeof(double) * 7 * (size_t)ctx->bond_cap);
+  if (e != hipSuccess) {
+    (void)hipFree(ctx->adj);
+    ctx->adj = nullptr;
+    return fail(ctx, ULPPM_E_HIP, std::string("adjoint scratch: ") + hipGetErrorString(e));
+  }
+  HIPCHK(hipFuncSetAttribute((const void*)k_adj_bond, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)adj_lds(ctx->max_f)));
+  return ULPPM_OK;
+}
+
+int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, const ulppm_state* adj1,
+                       ulppm_state* adj0, double* theta_bar, ulppm_report* rep) {
+  if (!ctx) return ULPPM_E_ARG;
+  int rc = check_state(ctx, S);
+  if (rc) return rc;
+  if ((rc = check_state(ctx, adj1))) return rc;
+  if ((rc = check_state(ctx, adj0))) return rc;
+  if ((rc = check_params(ctx, p))) return rc;
+  if (!theta_bar) return fail(ctx, ULPPM_E_ARG, "theta_bar is NULL");
+  if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
+  if (p->precision != ULPPM_FP64 || p->force_mode != ULPPM_FORCE_CONJUGATE)
+    return fail(ctx, ULPPM_E_ARG, "the adjoint supports FP64 with conjugate force states");
+  if (!(p->dt > 0.0)) return fail(ctx, ULPPM_E_ARG, "dt must be > 0");
+  const int64_t n = S->n;
+  if (adj1->n != n || adj0->n != n) return fail(ctx, ULPPM_E_ARG, "adjoint states must match the state size");
+  if ((rc = zero_counters(ctx))) return rc;
+  // forward re-run on a scratch copy of state n
+  double* q = ctx->adj;
+  ulppm_state F = *S;
+  for (int c = 0; c < 3; ++c) {
+    F.u[c] = q + (0 + c) * n;
+    F.uc[c] = q + (3 + c) * n;
+    F.v[c] = q + (6 + c) * n;
+    F.a[c] = q + (9 + c) * n;
+  }
+  F.vol = q + 12 * n; F.phi = q + 13 * n; F.J = q + 14 * n; F.Sr = q + 15 * n; F.mass = q + 16 * n;
+  for (int k = 0; k < 6; ++k) F.sig[k] = q + (17 + k) * n;
+  F.pc = q + 23 * n;
+  const int cb = blocks_for(n, 256, 4096);
+  for (int c = 0; c < 3; ++c) {
+    k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->u[c], F.u[c], n);
+    k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->uc[c], F.uc[c], n);
+    k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->v[c], F.v[c], n);
+    k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->a[c], F.a[c], n);
+  }
+  k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->vol, F.vol, n);
+  k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->phi, F.phi, n);
+  k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->J, F.J, n);
+  k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->Sr, F.Sr, n);
+  k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->mass, F.mass, n);
+  for (int k = 0; k < 6; ++k) k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->sig[k], F.sig[k], n);
+  k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->pc, F.pc, n);
+  HIPCHK(hipGetLastError());
+  DevParams P = dev_params(p);
+  const int npb = blocks_for(n, 256, 2048);
+  k_predict<<<npb, 256, 0, ctx->stream>>>(F, P, ctx->x, ctx->vh, ctx->vol_n, ctx->part + kPartPred);
+  HIPCHK(hipGetLastError());
+  if ((rc = build_families(ctx, n, p->delta, true))) return rc;
+  if ((rc = bond_pass(ctx, &F, p, p->dt, true))) return rc;
+  if ((rc = gather_pass(ctx, &F, p, G_STEP, F.mass, nullptr))) return rc;
+  // reverse
+  double* r = q + 24 * n;
+  double* own_x = r;          // 3n
+  double* own_vh = r + 3 * n; // 3n
+  double* own_V = r + 6 * n;
+  double* sigb = r + 7 * n;   // 6n
+  double* pcb = r + 13 * n;
+  double* Jb = r + 14 * n;
+  double* phib = r + 15 * n;
+  double* sb = r + 16 * n;
+  double* fbar = r + 17 * n;  // 3n
+  double* Mbt = r + 20 * n;
+  double* thpart = r + 21 * n;
+  k_adj_point1<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, S->fixed, F.a[0], F.a[1], F.a[2], F.mass, adj1->v[0],
+                                                           adj1->v[1], adj1->v[2], adj1->a[0], adj1->a[1],
+                                                           adj1->a[2], adj1->mass, 0.5 * p->dt, p->g[0], p->g[1],
+                                                           p->g[2], fbar, Mbt);
+  HIPCHK(hipGetLastError());
+  AdjArgs A;
+  A.n = n;
+  A.per = (n + 7) / 8;
+  A.row = ctx->row; A.col = ctx->col; A.rev = ctx->rev;
+  A.x = ctx->x; A.vh = ctx->vh; A.vol_n = ctx->vol_n;
+  A.J = S->J; A.phi = S->phi; A.s = S->s;
+  for (int k = 0; k < 6; ++k) { A.sig[k] = S->sig[k]; A.sig1[k] = F.sig[k]; A.sigb1[k] = adj1->sig[k]; }
+  A.pc = S->pc;
+  A.J1 = F.J; A.phi1 = F.phi; A.Sr1 = F.Sr; A.V1 = F.vol; A.pc1 = F.pc;
+  for (int c = 0; c < 3; ++c) A.T[c] = ctx->T + c * ctx->bond_cap;
+  A.fbar = fbar; A.Mbt = Mbt;
+  A.Vb1 = adj1->vol; A.phib1 = adj1->phi; A.Jb1 = adj1->J; A.Srb1 = adj1->Sr; A.pcb1 = adj1->pc;
+  A.own_x = own_x; A.own_vh = own_vh; A.own_V = own_V; A.sigb = sigb; A.pcb = pcb; A.Jb = Jb; A.phib = phib;
+  A.sb = sb;
+  A.slot_x = ctx->adj_slot;
+  A.slot_vh = ctx->adj_slot + 3 * ctx->bond_cap;
+  A.slot_V = ctx->adj_slot + 6 * ctx->bond_cap;
+  A.thpart = thpart;
+  A.cap = ctx->bond_cap;
+  A.dt = p->dt;
+  A.max_f = ctx->max_f;
+  const unsigned grid = (unsigned)(8 * A.per);
+  k_adj_bond<<<grid, kBondThreads, adj_lds(ctx->max_f), ctx->stream>>>(A, P);
+  HIPCHK(hipGetLastError());
+  k_adj_point2<<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->row, ctx->rev, S->fixed, own_x, own_vh, own_V,
+                                                      A.slot_x, A.slot_vh, A.slot_V, ctx->bond_cap, sigb, pcb, Jb,
+                                                      phib, sb, *adj1, *adj0, p->dt);
+  k_adj_theta<<<1, 256, 0, ctx->stream>>>(thpart, (int64_t)grid, theta_bar);
+  HIPCHK(hipGetLastError());
+  if ((rc = read_counters(ctx))) return rc;
+  fill_report(ctx, n, rep, 1);
+  return counters_to_status(ctx);
 }
 
 int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_steps, ulppm_report* rep) {

@@ -52,7 +52,8 @@ class Report(C.Structure):
 
 
 EXPORTS = ["ulppm_create", "ulppm_destroy", "ulppm_last_error", "ulppm_init_state", "ulppm_dt_crit",
-           "ulppm_build_families", "ulppm_forces", "ulppm_step", "ulppm_reset_energy"]
+           "ulppm_build_families", "ulppm_forces", "ulppm_step", "ulppm_reset_energy", "ulppm_adjoint_reserve",
+           "ulppm_adjoint_step", "ulppm_selfcheck_tail"]
 
 _lib = None
 
@@ -84,6 +85,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                C.POINTER(_dp), C.POINTER(Report)]
     L.ulppm_step.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.c_int32, C.POINTER(Report)]
     L.ulppm_reset_energy.argtypes = [vp]
+    L.ulppm_adjoint_reserve.argtypes = [vp]
+    L.ulppm_adjoint_step.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.POINTER(State), C.POINTER(State),
+                                     C.c_void_p, C.POINTER(Report)]
+    L.ulppm_selfcheck_tail.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32)]
     for name in EXPORTS:
         if name != "ulppm_last_error":
             getattr(L, name).restype = C.c_int
@@ -254,6 +260,29 @@ class Context:
 
     def reset_energy(self):
         self._check(self.L.ulppm_reset_energy(self.h))
+
+    def adjoint_reserve(self):
+        self._check(self.L.ulppm_adjoint_reserve(self.h))
+
+    def adjoint_step(self, S: "DeviceState", p: Params, adj1: "DeviceState", adj0: "DeviceState", theta_bar) -> dict:
+        """One reverse step: adj0 <- (d state_{n+1} / d state_n)^T adj1; theta_bar
+        (device float64 tensor of 4: M, lam, kap, eta) accumulates."""
+        rep = Report()
+        cs, c1, c0 = S.cstruct(), adj1.cstruct(), adj0.cstruct()
+        self._check(self.L.ulppm_adjoint_step(self.h, C.byref(cs), C.byref(p), C.byref(c1), C.byref(c0),
+                                              C.c_void_p(theta_bar.data_ptr()), C.byref(rep)))
+        return rep.as_dict()
+
+
+def selfcheck_tail(p: Params, seed: int = 0, n_cases: int = 40):
+    """Host-only check of the library's reverse of the per-bond tail (no GPU)."""
+    L = load_library()
+    m = C.c_double()
+    npl = C.c_int32()
+    rc = L.ulppm_selfcheck_tail(C.byref(p), int(seed), int(n_cases), C.byref(m), C.byref(npl))
+    if rc != 0:
+        raise UlppmError(rc, "selfcheck failed")
+    return float(m.value), int(npl.value)
 
 
 def column_state(col: dict, device="cuda", v0: Optional[np.ndarray] = None) -> DeviceState:

@@ -81,3 +81,16 @@ def test_missing_library_fails_loudly(tmp_path):
             ulppm.load_library(str(tmp_path / "nope.so"))
         finally:
             ulppm._lib = saved
+
+
+def test_tail_adjoint_selfcheck_on_host(lib):
+    """The library's hand-written reverse of the per-bond tail (inversion,
+    velocity gradient, strain increment, Perzyna return map through the
+    implicit-function theorem, force-state factor) agrees with central
+    differences on the host, elastic and plastic bonds alike."""
+    from paper_2203_05562_amd import inputs
+    prm = ulppm.make_params(inputs.default_params(inputs.CONFIGS["C0"], 20e3), dt=2.8e-5)
+    for seed in range(4):
+        err, npl = ulppm.selfcheck_tail(prm, seed, 40)
+        assert npl == 20
+        assert err < 2e-5, (seed, err)
