@@ -86,6 +86,74 @@ def cpu_baseline(cfg_name, steps, dt):
                 seconds=round(el, 3))
 
 
+def run_column(ulppm, col, precision, warmup, steps, timed=True):
+    """Initial conditions, dt = dt_c / 2, `warmup` untimed steps, then
+    `steps` steps timed with HIP events on the library's stream."""
+    import torch
+    G = ulppm.column_state(col, "cuda:0")
+    prm = ulppm.make_params(col["params"], precision=precision)
+    ctx = ulppm.Context(col["n"])
+    ctx.init_state(G, prm, col["params"]["ocr"])
+    prm.dt = 0.5 * ctx.dt_crit(G, prm)
+    if warmup:
+        ctx.step(G, prm, warmup)
+    torch.cuda.synchronize()
+    prm.timing = 1 if timed else 0
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    rep = ctx.step(G, prm, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del ctx
+    return G, rep, ms, prm.dt
+
+
+def rel_l2(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def adjoint_cost(cfg_name, steps, every, precision):
+    """Forward and backward of the checkpointed differentiable column on a
+    seeded configuration, objective = runout + settlement."""
+    import torch
+    from paper_2203_05562_amd import adjoint, inputs
+    cfg = inputs.CONFIGS[cfg_name]
+    col = inputs.make_column(cfg)
+    spec = adjoint.ColumnSpec(col, steps, every, precision=precision)
+    spec.timing = True
+    w = inputs.runout_objective_weights(col["lattice"], col["dims"])
+    theta = spec.theta0().requires_grad_(True)
+    s = torch.tensor(col["suction"], dtype=torch.float64, device="cuda", requires_grad=True)
+    v = torch.zeros((col["n"], 3), dtype=torch.float64, device="cuda", requires_grad=True)
+    x0 = torch.tensor(col["x0"], dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    u = adjoint.ColumnRun.apply(theta, s, v, spec)
+    ev[1].record()
+    J = adjoint.runout_settlement(u, x0, w["top"], w["axis"], 0.1 * inputs.DX)
+    J.backward()
+    ev[2].record()
+    torch.cuda.synchronize()
+    fwd, bwd = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    t = spec.last_timing
+    out = dict(workload=f"{cfg_name}: {cfg.nx}x{cfg.ny}x{cfg.nz} column, {steps} steps, checkpoint every {every}, "
+                        f"{'mixed' if precision else 'fp64'} forward, objective runout + settlement",
+               points=col["n"], forward_ms=round(fwd, 2), backward_ms=round(bwd, 2),
+               recompute_ms=round(t["recompute"], 2), reverse_ms=round(t["reverse"], 2),
+               forward_ms_per_step=round(fwd / steps, 4), adjoint_ms_per_step=round(t["reverse"] / steps, 4),
+               adjoint_to_forward_step=round(t["reverse"] / fwd, 3), backward_to_forward=round(bwd / fwd, 3),
+               objective=float(J), grad_theta=[float(g) for g in theta.grad],
+               grad_suction_sum=float(s.grad.sum()), grad_v0_norm=float(torch.linalg.vector_norm(v.grad)))
+    del spec
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +163,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision companion run")
+    ap.add_argument("--adjoint-config", default="C3", help="configuration of the adjoint cost line ('' skips it)")
+    ap.add_argument("--adjoint-steps", type=int, default=1000)
+    ap.add_argument("--adjoint-every", type=int, default=50)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -111,26 +183,8 @@ def main():
     n = col["n"]
     log(f"[gpu] {args.config}: {cfg.nx}x{cfg.ny}x{cfg.nz} = {n} points, suction {col['suction_kpa']:.2f} kPa")
     prec = ulppm.ULPPM_MIXED if args.precision == "mixed" else ulppm.ULPPM_FP64
-    G = ulppm.column_state(col, "cuda:0")
-    prm = ulppm.make_params(col["params"], precision=prec)
-    ctx = ulppm.Context(n)
-    ctx.init_state(G, prm, col["params"]["ocr"])
-    prm.dt = 0.5 * ctx.dt_crit(G, prm)
-    log(f"[gpu] dt = {prm.dt:.4e} s; warmup {args.warmup} steps")
-    if args.warmup:
-        ctx.step(G, prm, args.warmup)
-    torch.cuda.synchronize()
-    prm.timing = 1
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    rep = ctx.step(G, prm, args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    log(f"[gpu] timed {args.steps} steps: {ms:.1f} ms; report {rep}")
+    G, rep, ms, dt = run_column(ulppm, col, prec, args.warmup, args.steps)
+    log(f"[gpu] dt = {dt:.4e} s; timed {args.steps} steps after {args.warmup}: {ms:.1f} ms; report {rep}")
     bonds = rep["n_bond_updates"]
     value = bonds / (ms * 1e-3)
     launches = rep["timed_steps"]
@@ -150,11 +204,25 @@ def main():
                data="synthetic",
                config=dict(workload=f"{args.config}: jittered soil column {cfg.nx}x{cfg.ny}x{cfg.nz}, "
                                     f"{args.precision}", points=n, bonds_per_step=bonds / args.steps,
-                           dt=prm.dt, suction_kpa=col["suction_kpa"], seed=cfg.seed, precision=args.precision),
+                           dt=dt, suction_kpa=col["suction_kpa"], seed=cfg.seed, precision=args.precision),
                roofline=roofline, phase_ms=phases)
-    del ctx
+    if args.precision == "fp64" and not args.no_mixed:
+        # the same run in mixed precision from the same initial state
+        Gm, repm, msm, _ = run_column(ulppm, col, ulppm.ULPPM_MIXED, args.warmup, args.steps)
+        vm = repm["n_bond_updates"] / (msm * 1e-3)
+        out["mixed"] = dict(value=vm, ms_per_step=msm / args.steps, speedup=round(vm / value, 3),
+                            steps_compared=args.warmup + args.steps,
+                            u_rel_l2=rel_l2(Gm["u"], G["u"]), sig_rel_l2=rel_l2(Gm["sig"], G["sig"]),
+                            v_rel_l2=rel_l2(Gm["v"], G["v"]))
+        log(f"[gpu] mixed: {out['mixed']}")
+        del Gm
+    del G
+    torch.cuda.empty_cache()
+    if args.adjoint_config:
+        out["adjoint"] = adjoint_cost(args.adjoint_config, args.adjoint_steps, args.adjoint_every, 0)
+        log(f"[gpu] adjoint: {out['adjoint']}")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps, prm.dt)
+        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps, dt)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

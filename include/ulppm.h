@@ -116,7 +116,7 @@ typedef struct {
 
 /* Create a context for up to n_points points and max_family members per family
  * (0 selects 192).  hip_stream is a hipStream_t (NULL = the null stream).
- * Allocates all scratch now; no entry point allocates afterwards.
+ * Allocates all scratch now; afterwards only ulppm_adjoint_reserve allocates.
  * Errors: ULPPM_E_ARG (n_points <= 0 or > 2^31-1, max_family > 1024),
  * ULPPM_E_HIP (allocation failed). */
 int ulppm_create(ulppm_ctx **out, int64_t n_points, int32_t max_family, void *hip_stream);
@@ -191,10 +191,13 @@ int ulppm_adjoint_reserve(ulppm_ctx *ctx);
 
 /* Reverse mode of one step n -> n+1 (the workload's hand-written adjoint of
  * Algorithm 2 driving Algorithm 1), with that step's families, sub-horizons,
- * degenerate bonds and elastic/plastic branches frozen.  Re-runs the forward
- * step from state_n on scratch, then propagates adj_np1 (the adjoint of state
- * n+1, same layout as a state: u, uc, v, a, vol, phi, J, Sr, mass, sig, pc;
- * device arrays) back through the corrector, the gather (Eqs. 49-50), the
+ * degenerate bonds and elastic/plastic branches frozen.  state_np1, if not
+ * NULL, must be the state ulppm_step produced from state_n with the same
+ * params (a checkpointed sweep has it); then only the positions, half-step
+ * velocities and families are rebuilt.  If NULL, the forward step is re-run
+ * from state_n on scratch.  Propagates adj_np1 (the adjoint of state n+1, same
+ * layout as a state: u, uc, v, a, vol, phi, J, Sr, mass, sig, pc; device
+ * arrays) back through the corrector, the gather (Eqs. 49-50), the
  * conjugate force states, the bond tail (inversion, Eqs. 25-26 and 59, the
  * return map by the implicit-function theorem at its solution), the
  * sub-horizon sums (Eqs. 22-25, 57), the point kinematics (Eqs. 15-17, 48)
@@ -203,12 +206,28 @@ int ulppm_adjoint_reserve(ulppm_ctx *ctx);
  * adj_n->x0 receives adj_np1->x0 plus the adjoint of x0, so both accumulate
  * over a backward sweep; adj_n->Sr and adj_n->mass are zero (the step
  * recomputes them).  theta_bar (device, 4 doubles) accumulates the adjoints of
- * (M, lam, kap, eta).  adj_n may alias adj_np1.  FP64 with conjugate force
- * states only.  Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_NOCONV,
- * ULPPM_E_HIP. */
-int ulppm_adjoint_step(ulppm_ctx *ctx, const ulppm_state *state_n, const ulppm_params *p,
-                       const ulppm_state *adj_np1, ulppm_state *adj_n, double *theta_bar,
-                       ulppm_report *rep);
+ * (M, lam, kap, eta).  adj_n may alias adj_np1.  p must be FP64 with
+ * conjugate force states; state_n and state_np1 may come from a
+ * mixed-precision run (the reverse is then taken about that run's states).
+ * Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_NOCONV, ULPPM_E_HIP. */
+int ulppm_adjoint_step(ulppm_ctx *ctx, const ulppm_state *state_n, const ulppm_state *state_np1,
+                       const ulppm_params *p, const ulppm_state *adj_np1, ulppm_state *adj_n,
+                       double *theta_bar, ulppm_report *rep);
+
+/* Reverse of ulppm_init_state (the initial conditions of Algorithm 2) at the
+ * state state0 it produced with the same p and ocr.  adj0 is the adjoint of
+ * that state (after a backward sweep of ulppm_adjoint_step, the adjoint of
+ * state 0).  Writes s_bar (device, n doubles): the adjoint of each point's
+ * suction through the initial saturation (Eq. 15), effective stress (Eq. 2),
+ * pre-consolidation (Eqs. 40, 45), mass (Eq. 48) and, through the mass, the
+ * initial acceleration (Eq. 62), plus adj0->s.  Adds the pre-consolidation's
+ * dependence on M to theta_bar[0] (device, 4 doubles as in
+ * ulppm_adjoint_step).  The initial nodal force depends on the total stress
+ * only (Eq. 32 at zero strain increment), so neither suction nor M reach it.
+ * The adjoint of the initial velocity is adj0->v unchanged.  Needs
+ * ulppm_adjoint_reserve.  Errors: ULPPM_E_ARG, ULPPM_E_HIP. */
+int ulppm_adjoint_init(ulppm_ctx *ctx, const ulppm_state *state0, const ulppm_params *p, double ocr,
+                       const ulppm_state *adj0, double *s_bar, double *theta_bar);
 
 /* Host-only self-check (no GPU call) of the library's hand-written reverse of the
  * per-bond tail (inversion, velocity gradient, strain increment, Perzyna return

@@ -44,6 +44,9 @@ namespace {
 #ifndef ULPPM_BOND_MIN_WAVES
 #define ULPPM_BOND_MIN_WAVES 1
 #endif
+#ifndef ULPPM_ADJ_MIN_WAVES
+#define ULPPM_ADJ_MIN_WAVES 2
+#endif
 constexpr int kBondThreads = ULPPM_BOND_THREADS;   // one workgroup per point, one lane per bond
 constexpr int kBondWaves = kBondThreads / 64;
 constexpr int kWave = 64;
@@ -808,14 +811,21 @@ __host__ __device__ __forceinline__ void unique_grad(const double* G, double* g)
   g[3] = G[5] + G[7]; g[4] = G[2] + G[6]; g[5] = G[1] + G[3];
 }
 
-__host__ __device__ void tail_forward(const DevParams& P, const double* K, const double* N, const double* sig,
-                                      double pc, double Srs, double w, double dt, TailFwd& F) {
+// K^{-1} and the strain increment dt sym(N K^{-1}) of a bond (Eqs. 25-26, 59).
+__host__ __device__ __forceinline__ void tail_kinematics(const double* K, const double* N, double dt, TailFwd& F) {
   sym_inverse(K, F.Ki);
   double KiF[9], L[9];
   sym_full(F.Ki, KiF);
   mat3_mul(N, KiF, L);
   F.de[0] = dt * L[0]; F.de[1] = dt * L[4]; F.de[2] = dt * L[8];
   F.de[3] = dt * 0.5 * (L[5] + L[7]); F.de[4] = dt * 0.5 * (L[2] + L[6]); F.de[5] = dt * 0.5 * (L[1] + L[3]);
+}
+
+__host__ __device__ void tail_forward(const DevParams& P, const double* K, const double* N, const double* sig,
+                                      double pc, double Srs, double w, double dt, TailFwd& F) {
+  tail_kinematics(K, N, dt, F);
+  double KiF[9];
+  sym_full(F.Ki, KiF);
   if (dt == 0.0) {
     for (int k = 0; k < 6; ++k) F.sg[k] = sig[k];
     F.pc = pc;
@@ -1328,13 +1338,12 @@ struct AdjArgs {
   const double* s;
   const double* sig[6];
   const double* pc;
-  const double* J1;       // state n+1 (forward re-run)
+  const double* J1;       // state n+1
   const double* phi1;
   const double* Sr1;
   const double* V1;
   const double* sig1[6];
   const double* pc1;
-  const double* T[3];     // forward force states
   const double* fbar;     // 3n, adjoint of the nodal force
   const double* Mbt;      // n, adjoint of M^{n+1} including the acceleration term
   const double* Vb1;      // incoming adjoints of state n+1
@@ -1373,6 +1382,24 @@ __host__ __device__ __forceinline__ void symv(const double* S, const double* z, 
   out[2] = S[4] * z[0] + S[3] * z[1] + S[2] * z[2];
 }
 
+// Positions x^{n+1} = x0 + u^{n+1} from state n+1 and v_half, V^n from state
+// n, exactly as the predictor formed them.
+__global__ void k_adj_kin(ulppm_state S, ulppm_state S1, DevParams P, double* __restrict__ x,
+                          double* __restrict__ vh, double* __restrict__ vol_n) {
+#pragma clang fp contract(off)
+  const int64_t n = S.n;
+  const double hdt = 0.5 * P.dt;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool fx = S.fixed[i] != 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      vh[c * n + i] = fx ? 0.0 : S.v[c][i] + hdt * S.a[c][i];
+      x[c * n + i] = S1.x0[c][i] + S1.u[c][i];
+    }
+    vol_n[i] = S.vol[i];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_adj_point1(int64_t n, const uint8_t* __restrict__ fixed,
                                                     const double* __restrict__ a1x, const double* __restrict__ a1y,
                                                     const double* __restrict__ a1z, const double* __restrict__ M1,
@@ -1400,7 +1427,7 @@ __global__ __launch_bounds__(256) void k_adj_point1(int64_t n, const uint8_t* __
 }
 
 // One workgroup per point i: re-run the bond pass of i, then reverse it.
-__global__ __launch_bounds__(kBondThreads) void k_adj_bond(AdjArgs A, DevParams P) {
+__global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(AdjArgs A, DevParams P) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t i = xcd_point(blockIdx.x, A.per);
   if (i >= A.n) {                                 // idle block: its parameter partials are zero
@@ -1413,14 +1440,15 @@ __global__ __launch_bounds__(kBondThreads) void k_adj_bond(AdjArgs A, DevParams 
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
   const int nw = (mf + 63) / 64;
-  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);   // x_k
+  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);   // x_k (pass 1), then Tbar_ik
+  Quad<double>* sTb = sX;
   Quad<double>* sZ = sX + mf;                                     // zeta_ik, V_k
   Quad<double>* sY = sZ + mf;                                     // ydot_ik
-  Quad<double>* sTb = sY + mf;                                    // Tbar_ik
-  Quad<double>* sZb = sTb + mf;                                   // zeta_bar_ik, slot Vbar_k
+  Quad<double>* sZb = sY + mf;                                    // zeta_bar_ik, slot Vbar_k
   MRec<double>* sM = reinterpret_cast<MRec<double>*>(sZb + mf);   // M_j
   double* sKN = reinterpret_cast<double*>(sM + mf);               // 16 per bond: K(6) N(9) active | Ks(6) Nb(9)
-  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)mf);
+  double* sR = sKN + 16 * (size_t)mf;                             // 8 per bond: sigma_ij (6), p_c,ij, branch
+  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sR + 8 * (size_t)mf);
   __shared__ double red[kBondWaves][32];
   __shared__ double pt[32];
 
@@ -1515,6 +1543,10 @@ __global__ __launch_bounds__(kBondThreads) void k_adj_bond(AdjArgs A, DevParams 
       TailFwd F;
       tail_forward(P, Kq, Nq, sig_i, pc_i, Srs, Vj / Vh, dt, F);
       for (int q = 0; q < 9; ++q) r.v[q] = F.M[q];
+      double* rr = sR + 8 * (size_t)m;
+      for (int k = 0; k < 6; ++k) rr[k] = F.sg[k];
+      rr[6] = F.pc;
+      rr[7] = (double)F.branch;
       Wp += Vj;
     }
     sM[m] = r;
@@ -1544,19 +1576,22 @@ __global__ __launch_bounds__(kBondThreads) void k_adj_bond(AdjArgs A, DevParams 
     const int32_t k = A.col[slot];
     const double Vk = sZ[m].v[3];
     const double fb_k[3] = {A.fbar[k], A.fbar[n + k], A.fbar[2 * n + k]};
+    const double df[3] = {fb_i[0] - fb_k[0], fb_i[1] - fb_k[1], fb_i[2] - fb_k[2]};
     double tb[3];
-    for (int c = 0; c < 3; ++c) tb[c] = Vi * Vk * (fb_i[c] - fb_k[c]);
+    for (int c = 0; c < 3; ++c) tb[c] = Vi * Vk * df[c];
     sTb[m] = Quad<double>{{tb[0], tb[1], tb[2], 0.0}};
     Quad<double> zb;
     zb.v[0] = a[0] * tb[0] + a[3] * tb[1] + a[6] * tb[2];
     zb.v[1] = a[1] * tb[0] + a[4] * tb[1] + a[7] * tb[2];
     zb.v[2] = a[2] * tb[0] + a[5] * tb[1] + a[8] * tb[2];
-    // f_i = V_i sum_k V_k (T_ik - T_ki)
-    const int32_t r = A.rev[slot];
-    double dT_dot_fb = 0.0;
-    for (int c = 0; c < 3; ++c) dT_dot_fb += (A.T[c][slot] - A.T[c][r]) * fb_i[c];
-    ownV += Vk * dT_dot_fb;
-    zb.v[3] = Vi * dT_dot_fb;                       // to Vbar_k
+    // With symmetric families, sum_i fbar_i . f_i = sum_i sum_k V_i V_k
+    // T_ik . (fbar_i - fbar_k): the volume adjoints need only this point's
+    // own force states T_ik = A_ik zeta_ik.
+    const Quad<double> zq = sZ[m];
+    double e = 0.0;
+    for (int c = 0; c < 3; ++c) e += (a[3 * c] * zq.v[0] + a[3 * c + 1] * zq.v[1] + a[3 * c + 2] * zq.v[2]) * df[c];
+    ownV += Vk * e;
+    zb.v[3] = Vi * e;                               // to Vbar_k
     sZb[m] = zb;
   }
   __syncthreads();
@@ -1594,8 +1629,12 @@ __global__ __launch_bounds__(kBondThreads) void k_adj_bond(AdjArgs A, DevParams 
       for (int k = 0; k < 6; ++k) Kq[k] = kn[k];
       for (int k = 0; k < 9; ++k) Nq[k] = kn[6 + k];
       const double Vj = sZ[m].v[3];
-      TailFwd F;
-      tail_forward(P, Kq, Nq, sig_i, pc_i, Srs, Vj / Vh, dt, F);
+      TailFwd F;                                   // the return map's solution from pass 1
+      tail_kinematics(Kq, Nq, dt, F);
+      const double* rr = sR + 8 * (size_t)m;
+      for (int k = 0; k < 6; ++k) F.sg[k] = rr[k];
+      F.pc = rr[6];
+      F.branch = (int)rr[7];
       // history: sigma'_i = sum_j V_j sigma_ij / W
       double sgx[6];
       double vh_hist = 0.0;
@@ -1828,6 +1867,54 @@ __global__ void k_adj_theta(const double* __restrict__ part, int64_t nb, double*
   }
   if (threadIdx.x == 0)
     for (int k = 0; k < 4; ++k) th[k] += s[k][0];
+}
+
+// Reverse of the point set-up (k_init_points) at the state it produced, S.
+// B is the adjoint of that state.  The set-up's nodal force is a function of
+// the total stress alone (at dt_inc = 0 the bond stress is the point's
+// effective stress, and Eq. 32 adds S_r s 1 back), so the initial
+// acceleration a = f/M + g depends on suction only through the mass.  The
+// suction adjoint runs through the mass (Eq. 48), the effective stress
+// (Eq. 2) and the pre-consolidation (Eqs. 40, 45) into S_r (Eq. 15) and s;
+// the pre-consolidation adds the M adjoint.  Four partials per block (M, 0, 0, 0).
+__global__ void k_adj_init(ulppm_state S, ulppm_state B, DevParams P, double ocr, double* __restrict__ sbar,
+                           double* __restrict__ part) {
+  double Mb = 0.0;
+  const double g[3] = {P.g0, P.g1, P.g2};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < S.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double s = S.s[i], phi = S.phi[i], Sr = S.Sr[i], m = S.mass[i];
+    double mb = B.mass[i];
+    if (S.fixed[i] == 0)
+      for (int c = 0; c < 3; ++c) mb -= B.a[c][i] * (S.a[c][i] - g[c]) / m;
+    double Srb = B.Sr[i] + mb * P.rho_w * phi * S.vol[i];
+    double sg[6];
+    for (int k = 0; k < 6; ++k) sg[k] = S.sig[k][i];
+    const double p = (sg[0] + sg[1] + sg[2]) / 3.0;
+    const double d[3] = {sg[0] - p, sg[1] - p, sg[2] - p};
+    const double q2 = 1.5 * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + 2.0 * (sg[3] * sg[3] + sg[4] * sg[4] + sg[5] * sg[5]));
+    const double M2p = P.M * P.M * p;
+    const double pcb = ocr * (p + q2 / M2p);
+    const double pcbb = B.pc[i] * S.pc[i] / (P.b2 * pcb);     // d pc / d pcb of Eq. 45 inverted
+    Mb += pcbb * ocr * (-2.0 * q2 / (M2p * P.M));
+    const double dp = ocr * (1.0 - q2 / (M2p * p)), dq = ocr / M2p;
+    double tr = 0.0;
+    for (int k = 0; k < 3; ++k) tr += B.sig[k][i] + pcbb * (dp / 3.0 + dq * 3.0 * d[k]);
+    double dJ, dphi, ds;
+    swrc_grad(P, 1.0, phi, s, &dJ, &dphi, &ds);
+    Srb -= s * tr;
+    sbar[i] = B.s[i] - Sr * tr + Srb * ds;
+  }
+  __shared__ double r[256];
+  r[threadIdx.x] = Mb;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) r[threadIdx.x] += r[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x] = r[0];
+    part[4 * blockIdx.x + 1] = part[4 * blockIdx.x + 2] = part[4 * blockIdx.x + 3] = 0.0;
+  }
 }
 
 // -------------------------------------------------------- gather kernel --
@@ -2735,8 +2822,10 @@ int ulppm_dt_crit(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, d
   return ULPPM_OK;
 }
 
+constexpr size_t kMaxLds = 160 * 1024 - 1024;   // dynamic LDS of one workgroup (CDNA4: 160 KB per CU)
+
 size_t adj_lds(int max_f) {
-  return (size_t)max_f * (5 * sizeof(Quad<double>) + sizeof(MRec<double>) + 16 * sizeof(double) +
+  return (size_t)max_f * (4 * sizeof(Quad<double>) + sizeof(MRec<double>) + 24 * sizeof(double) +
                           (size_t)((max_f + 63) / 64) * sizeof(unsigned long long));
 }
 
@@ -2753,29 +2842,38 @@ int ulppm_adjoint_reserve(ulppm_ctx* ctx) {
     return fail(ctx, ULPPM_E_HIP, std::string("adjoint scratch: ") + hipGetErrorString(e));
   }
   HIPCHK(hipFuncSetAttribute((const void*)k_adj_bond, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)adj_lds(ctx->max_f)));
+                             (int)std::min(adj_lds(ctx->max_f), kMaxLds)));
   return ULPPM_OK;
 }
 
-int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, const ulppm_state* adj1,
-                       ulppm_state* adj0, double* theta_bar, ulppm_report* rep) {
+int ulppm_adjoint_init(ulppm_ctx* ctx, const ulppm_state* S0, const ulppm_params* p, double ocr,
+                       const ulppm_state* adj0, double* s_bar, double* theta_bar) {
   if (!ctx) return ULPPM_E_ARG;
-  int rc = check_state(ctx, S);
+  int rc = check_state(ctx, S0);
   if (rc) return rc;
-  if ((rc = check_state(ctx, adj1))) return rc;
   if ((rc = check_state(ctx, adj0))) return rc;
   if ((rc = check_params(ctx, p))) return rc;
-  if (!theta_bar) return fail(ctx, ULPPM_E_ARG, "theta_bar is NULL");
+  if (!s_bar || !theta_bar) return fail(ctx, ULPPM_E_ARG, "s_bar or theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
-  if (p->precision != ULPPM_FP64 || p->force_mode != ULPPM_FORCE_CONJUGATE)
-    return fail(ctx, ULPPM_E_ARG, "the adjoint supports FP64 with conjugate force states");
-  if (!(p->dt > 0.0)) return fail(ctx, ULPPM_E_ARG, "dt must be > 0");
+  if (!(ocr >= 1.0)) return fail(ctx, ULPPM_E_ARG, "ocr must be >= 1");
+  const int64_t n = S0->n;
+  if (adj0->n != n) return fail(ctx, ULPPM_E_ARG, "adjoint state must match the state size");
+  const int nb = blocks_for(n, 256, 2048);
+  double* part = ctx->adj + 45 * n;     // 4 (n + 8) doubles, nb <= n + 8
+  k_adj_init<<<nb, 256, 0, ctx->stream>>>(*S0, *adj0, dev_params(p), ocr, s_bar, part);
+  k_adj_theta<<<1, 256, 0, ctx->stream>>>(part, (int64_t)nb, theta_bar);
+  HIPCHK(hipGetLastError());
+  return ULPPM_OK;
+}
+
+// Forward re-run of step n -> n+1 on a scratch copy F of state n (in the
+// adjoint scratch), leaving x^{n+1}, v_half, V^n, the families and F =
+// state n+1 in the context.
+static int adjoint_rerun(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, const DevParams& P,
+                         ulppm_state& F) {
   const int64_t n = S->n;
-  if (adj1->n != n || adj0->n != n) return fail(ctx, ULPPM_E_ARG, "adjoint states must match the state size");
-  if ((rc = zero_counters(ctx))) return rc;
-  // forward re-run on a scratch copy of state n
   double* q = ctx->adj;
-  ulppm_state F = *S;
+  int rc;
   for (int c = 0; c < 3; ++c) {
     F.u[c] = q + (0 + c) * n;
     F.uc[c] = q + (3 + c) * n;
@@ -2800,15 +2898,47 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params*
   for (int k = 0; k < 6; ++k) k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->sig[k], F.sig[k], n);
   k_copy_f64<<<cb, 256, 0, ctx->stream>>>(S->pc, F.pc, n);
   HIPCHK(hipGetLastError());
-  DevParams P = dev_params(p);
   const int npb = blocks_for(n, 256, 2048);
   k_predict<<<npb, 256, 0, ctx->stream>>>(F, P, ctx->x, ctx->vh, ctx->vol_n, ctx->part + kPartPred);
   HIPCHK(hipGetLastError());
   if ((rc = build_families(ctx, n, p->delta, true))) return rc;
   if ((rc = bond_pass(ctx, &F, p, p->dt, true))) return rc;
   if ((rc = gather_pass(ctx, &F, p, G_STEP, F.mass, nullptr))) return rc;
+  return ULPPM_OK;
+}
+
+int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* S1, const ulppm_params* p,
+                       const ulppm_state* adj1, ulppm_state* adj0, double* theta_bar, ulppm_report* rep) {
+  if (!ctx) return ULPPM_E_ARG;
+  int rc = check_state(ctx, S);
+  if (rc) return rc;
+  if (S1 && (rc = check_state(ctx, S1))) return rc;
+  if ((rc = check_state(ctx, adj1))) return rc;
+  if ((rc = check_state(ctx, adj0))) return rc;
+  if ((rc = check_params(ctx, p))) return rc;
+  if (!theta_bar) return fail(ctx, ULPPM_E_ARG, "theta_bar is NULL");
+  if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
+  if (p->precision != ULPPM_FP64 || p->force_mode != ULPPM_FORCE_CONJUGATE)
+    return fail(ctx, ULPPM_E_ARG, "the adjoint supports FP64 with conjugate force states");
+  if (!(p->dt > 0.0)) return fail(ctx, ULPPM_E_ARG, "dt must be > 0");
+  const int64_t n = S->n;
+  if (adj1->n != n || adj0->n != n || (S1 && S1->n != n))
+    return fail(ctx, ULPPM_E_ARG, "adjoint states must match the state size");
+  if ((rc = zero_counters(ctx))) return rc;
+  double* q = ctx->adj;
+  DevParams P = dev_params(p);
+  ulppm_state F = S1 ? *S1 : *S;
+  if (S1) {
+    // state n+1 given: positions, half-step velocities and families only
+    k_adj_kin<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, *S1, P, ctx->x, ctx->vh, ctx->vol_n);
+    HIPCHK(hipGetLastError());
+    if ((rc = build_families(ctx, n, p->delta, true))) return rc;
+  } else if ((rc = adjoint_rerun(ctx, S, p, P, F))) {
+    return rc;
+  }
   // reverse
   double* r = q + 24 * n;
+
   double* own_x = r;          // 3n
   double* own_vh = r + 3 * n; // 3n
   double* own_V = r + 6 * n;
@@ -2834,7 +2964,6 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params*
   for (int k = 0; k < 6; ++k) { A.sig[k] = S->sig[k]; A.sig1[k] = F.sig[k]; A.sigb1[k] = adj1->sig[k]; }
   A.pc = S->pc;
   A.J1 = F.J; A.phi1 = F.phi; A.Sr1 = F.Sr; A.V1 = F.vol; A.pc1 = F.pc;
-  for (int c = 0; c < 3; ++c) A.T[c] = ctx->T + c * ctx->bond_cap;
   A.fbar = fbar; A.Mbt = Mbt;
   A.Vb1 = adj1->vol; A.phib1 = adj1->phi; A.Jb1 = adj1->J; A.Srb1 = adj1->Sr; A.pcb1 = adj1->pc;
   A.own_x = own_x; A.own_vh = own_vh; A.own_V = own_V; A.sigb = sigb; A.pcb = pcb; A.Jb = Jb; A.phib = phib;
@@ -2845,9 +2974,16 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params*
   A.thpart = thpart;
   A.cap = ctx->bond_cap;
   A.dt = p->dt;
-  A.max_f = ctx->max_f;
+  // LDS for the largest family of this step, not of the context
+  if ((rc = read_counters(ctx))) return rc;
+  if ((rc = counters_to_status(ctx))) return rc;
+  A.max_f = std::max<int>(1, (int)ctx->h_ctr[C_MAXFAM]);
+  const size_t lds = adj_lds(A.max_f);
+  if (lds > kMaxLds)
+    return fail(ctx, ULPPM_E_CAPACITY, "adjoint: a family of " + std::to_string(A.max_f) +
+                                           " members exceeds the workgroup's LDS");
   const unsigned grid = (unsigned)(8 * A.per);
-  k_adj_bond<<<grid, kBondThreads, adj_lds(ctx->max_f), ctx->stream>>>(A, P);
+  k_adj_bond<<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   HIPCHK(hipGetLastError());
   k_adj_point2<<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->row, ctx->rev, S->fixed, own_x, own_vh, own_V,
                                                       A.slot_x, A.slot_vh, A.slot_V, ctx->bond_cap, sigb, pcb, Jb,

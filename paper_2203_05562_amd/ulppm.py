@@ -53,7 +53,7 @@ class Report(C.Structure):
 
 EXPORTS = ["ulppm_create", "ulppm_destroy", "ulppm_last_error", "ulppm_init_state", "ulppm_dt_crit",
            "ulppm_build_families", "ulppm_forces", "ulppm_step", "ulppm_reset_energy", "ulppm_adjoint_reserve",
-           "ulppm_adjoint_step", "ulppm_selfcheck_tail"]
+           "ulppm_adjoint_step", "ulppm_adjoint_init", "ulppm_selfcheck_tail"]
 
 _lib = None
 
@@ -86,8 +86,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.ulppm_step.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.c_int32, C.POINTER(Report)]
     L.ulppm_reset_energy.argtypes = [vp]
     L.ulppm_adjoint_reserve.argtypes = [vp]
-    L.ulppm_adjoint_step.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.POINTER(State), C.POINTER(State),
-                                     C.c_void_p, C.POINTER(Report)]
+    L.ulppm_adjoint_step.argtypes = [vp, C.POINTER(State), C.POINTER(State), C.POINTER(Params), C.POINTER(State),
+                                     C.POINTER(State), C.c_void_p, C.POINTER(Report)]
+    L.ulppm_adjoint_init.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.c_double, C.POINTER(State),
+                                     C.c_void_p, C.c_void_p]
     L.ulppm_selfcheck_tail.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32)]
     for name in EXPORTS:
@@ -264,14 +266,24 @@ class Context:
     def adjoint_reserve(self):
         self._check(self.L.ulppm_adjoint_reserve(self.h))
 
-    def adjoint_step(self, S: "DeviceState", p: Params, adj1: "DeviceState", adj0: "DeviceState", theta_bar) -> dict:
+    def adjoint_step(self, S: "DeviceState", p: Params, adj1: "DeviceState", adj0: "DeviceState", theta_bar,
+                     S1: Optional["DeviceState"] = None) -> dict:
         """One reverse step: adj0 <- (d state_{n+1} / d state_n)^T adj1; theta_bar
-        (device float64 tensor of 4: M, lam, kap, eta) accumulates."""
+        (device float64 tensor of 4: M, lam, kap, eta) accumulates.  S1, the
+        state the forward step produced from S, saves re-running that step."""
         rep = Report()
         cs, c1, c0 = S.cstruct(), adj1.cstruct(), adj0.cstruct()
-        self._check(self.L.ulppm_adjoint_step(self.h, C.byref(cs), C.byref(p), C.byref(c1), C.byref(c0),
+        n1 = C.byref(S1.cstruct()) if S1 is not None else None
+        self._check(self.L.ulppm_adjoint_step(self.h, C.byref(cs), n1, C.byref(p), C.byref(c1), C.byref(c0),
                                               C.c_void_p(theta_bar.data_ptr()), C.byref(rep)))
         return rep.as_dict()
+
+    def adjoint_init(self, S0: "DeviceState", p: Params, ocr: float, adj0: "DeviceState", s_bar, theta_bar):
+        """Reverse of init_state at its output S0: s_bar (device float64 (n,))
+        receives the suction adjoint; theta_bar[0] accumulates the M adjoint."""
+        c0, ca = S0.cstruct(), adj0.cstruct()
+        self._check(self.L.ulppm_adjoint_init(self.h, C.byref(c0), C.byref(p), float(ocr), C.byref(ca),
+                                              C.c_void_p(s_bar.data_ptr()), C.c_void_p(theta_bar.data_ptr())))
 
 
 def selfcheck_tail(p: Params, seed: int = 0, n_cases: int = 40):

@@ -184,3 +184,179 @@ def test_adjoint_matches_finite_differences(gpu, olib):
         fd = (Js[0] - Js[1]) / (2 * h)
         say(attr, fd, th[k])
         assert abs(fd - th[k]) <= 1e-5 * abs(th[k])
+
+
+# ---------------------------------------------------------------------------
+# The differentiable column (checkpointed autograd.Function + initial
+# conditions) against the oracle run end to end.
+
+def column_case(olib, dims=(6, 6, 8), seed=3, vscale=0.3):
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=seed, dims=dims)
+    v0 = inputs.random_velocity(col["n"], seed + 50, vscale)
+    v0[col["fixed"] == 1] = 0.0
+    oprm = olib.make_params(col["params"])
+    S = olib.init_column(col, oprm, col["params"]["ocr"], v0)
+    dt = 0.5 * olib.dt_crit(S, oprm)
+    w = inputs.runout_objective_weights(col["lattice"], dims)
+    return col, v0, dt, w
+
+
+def np_objective(u, x0, w, tau):
+    """Runout (smooth maximum of horizontal distances from the axis) plus
+    settlement of the initial top layer, in numpy."""
+    from scipy.special import logsumexp
+    x = x0 + u
+    r = np.hypot(x[:, 0] - w["axis"][0], x[:, 1] - w["axis"][1])
+    return tau * logsumexp(r / tau) + (x0[w["top"], 2].mean() - x[w["top"], 2].mean())
+
+
+def np_objective_grad(u, x0, w, tau):
+    """d objective / d u in closed form (softmax weights of the smooth
+    maximum times the radial unit vector; -1/|top| on the top layer's z)."""
+    from scipy.special import softmax
+    x = x0 + u
+    dx, dy = x[:, 0] - w["axis"][0], x[:, 1] - w["axis"][1]
+    r = np.hypot(dx, dy)
+    p = softmax(r / tau)
+    g = np.zeros_like(u)
+    g[:, 0] = p * dx / r
+    g[:, 1] = p * dy / r
+    g[w["top"], 2] -= 1.0 / len(w["top"])
+    return g
+
+
+def oracle_run(olib, col, dt, nsteps, theta=None, s=None, v0=None):
+    prm = dict(col["params"])
+    if theta is not None:
+        prm.update(dict(zip(("M", "lam", "kap", "eta"), theta)))
+    c2 = dict(col)
+    if s is not None:
+        c2["suction"] = s
+    oprm = olib.make_params(prm)
+    S = olib.init_column(c2, oprm, prm["ocr"], v0)
+    oprm.dt = dt
+    rc, _, st = olib.step(S, oprm, nsteps)
+    assert rc == 0
+    return S["u"], st
+
+
+def gpu_gradient(gpu, col, v0, dt, w, tau, nsteps, k, precision=None):
+    import torch
+    from paper_2203_05562_amd import adjoint
+    kw = {} if precision is None else {"precision": precision}
+    spec = adjoint.ColumnSpec(col, nsteps, k, dt=dt, **kw)
+    theta = spec.theta0().requires_grad_(True)
+    s = torch.tensor(col["suction"], dtype=torch.float64, device="cuda", requires_grad=True)
+    v = torch.tensor(v0, dtype=torch.float64, device="cuda", requires_grad=True)
+    x0 = torch.tensor(col["x0"], dtype=torch.float64, device="cuda")
+    u = adjoint.ColumnRun.apply(theta, s, v, spec)
+    J = adjoint.runout_settlement(u, x0, w["top"], w["axis"], tau)
+    J.backward()
+    return (float(J), theta.grad.numpy().copy(), s.grad.cpu().numpy(), v.grad.cpu().numpy(),
+            u.detach().cpu().numpy(), spec)
+
+
+def test_checkpointing_does_not_change_the_gradient(olib, gpu):
+    """Recomputation from checkpoints every k steps (k = 1, 4 with a ragged
+    last segment, and all 10 steps in one segment) gives the same gradient."""
+    say("checkpoint intervals")
+    col, v0, dt, w = column_case(olib)
+    tau = 0.1 * inputs.DX
+    ref = gpu_gradient(gpu, col, v0, dt, w, tau, 10, 1)
+    for k in (4, 10):
+        got = gpu_gradient(gpu, col, v0, dt, w, tau, 10, k)
+        say("k", k, got[1], ref[1])
+        assert abs(got[0] - ref[0]) <= 1e-14 * abs(ref[0])
+        for a, b in zip(got[1:4], ref[1:4]):
+            assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+
+
+def test_column_gradient_matches_oracle_finite_differences(olib, gpu):
+    """Objective = runout + settlement after 12 steps (checkpoints every 5)
+    from the column's initial conditions.  The GPU gradients in (M, lam, kap,
+    eta), uniform suction and a random initial-velocity direction against
+    central differences (h = 1e-6 relative) of the oracle run end to end,
+    counted only when both runs have the same sub-horizon and plastic counts.
+    The differences are taken of u^N and contracted with the objective's
+    closed-form gradient at the unperturbed u^N: the objective (about 0.04 m)
+    moves by as little as 1e-14 between the two runs, below its own rounding,
+    while u^N's differences are resolved.  The objective's gradient itself is
+    checked on the CPU."""
+    say("column gradient vs oracle FD")
+    col, v0, dt, w = column_case(olib)
+    tau = 0.1 * inputs.DX
+    nsteps = 12
+    J, gth, gs, gv, u, spec = gpu_gradient(gpu, col, v0, dt, w, tau, nsteps, 5)
+    u0, st0 = oracle_run(olib, col, dt, nsteps, v0=v0)
+    J0 = np_objective(u0, col["x0"], w, tau)
+    gu = np_objective_grad(u0, col["x0"], w, tau)
+    say("objective gpu", J, "oracle", J0, "plastic", st0["n_plastic"])
+    assert st0["n_plastic"] > 0
+    assert abs(J - J0) <= 1e-10 * abs(J0)
+    theta0 = np.array([col["params"][k] for k in ("M", "lam", "kap", "eta")])
+    rng = np.random.default_rng(21)
+    dv = np.where(col["fixed"][:, None] == 1, 0.0, rng.normal(size=v0.shape))
+    cases = []
+    for i, name in enumerate(("M", "lam", "kap", "eta")):
+        e = np.zeros(4)
+        e[i] = 1.0
+        cases.append((name, 1e-6 * theta0[i], dict(theta=lambda h, e=e: theta0 + h * e), gth[i]))
+    s0 = np.asarray(col["suction"], dtype=np.float64)
+    cases.append(("s", 1e-6 * float(np.mean(s0)), dict(s=lambda h: s0 + h), float(np.sum(gs))))
+    cases.append(("v0", 1e-6 * 0.3, dict(v0=lambda h: v0 + h * dv), float(np.sum(gv * dv))))
+    for name, h, mk, g in cases:
+        vals, sts = [], []
+        for sgn in (+1, -1):
+            kw = {k: f(sgn * h) for k, f in mk.items()}
+            if "v0" not in kw:
+                kw["v0"] = v0
+            u, st = oracle_run(olib, col, dt, nsteps, **kw)
+            vals.append(u)
+            sts.append(st)
+        assert sts[0]["n_triples"] == sts[1]["n_triples"] and sts[0]["n_plastic"] == sts[1]["n_plastic"], name
+        fd = float(np.sum(gu * (vals[0] - vals[1]))) / (2 * h)
+        say(name, "fd", fd, "adjoint", g)
+        assert abs(fd - g) <= 1e-5 * abs(g), (name, fd, g)
+
+
+def test_mixed_precision_gradient_error(olib, gpu):
+    """The gradient of a mixed-precision forward (FP32 sums and gathers),
+    reversed in FP64 about its own states, against the FP64 run's."""
+    from paper_2203_05562_amd import ulppm
+    say("mixed gradient")
+    col, v0, dt, w = column_case(olib)
+    tau = 0.1 * inputs.DX
+    ref = gpu_gradient(gpu, col, v0, dt, w, tau, 12, 5)
+    got = gpu_gradient(gpu, col, v0, dt, w, tau, 12, 5, precision=ulppm.ULPPM_MIXED)
+    errs = {"J": abs(got[0] - ref[0]) / abs(ref[0])}
+    for name, a, b in zip(("theta", "s", "v0"), got[1:4], ref[1:4]):
+        errs[name] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    say("mixed vs fp64 relative errors", errs)
+    assert errs["J"] <= 1e-5
+    for name in ("theta", "s", "v0"):
+        assert errs[name] <= 1e-2, (name, errs)
+
+
+def test_adjoint_given_next_state_matches_rerun(olib, gpu):
+    """Handing ulppm_adjoint_step the forward's state n+1 (no re-run of the
+    step) gives the adjoint of the re-run path, over 6 plastic steps."""
+    import torch
+    say("adjoint with state n+1")
+    col, oprm, gprm, S, ctx = start(olib, gpu)
+    n = col["n"]
+    rng = np.random.default_rng(17)
+    states = forward_states(ctx, gprm, dev(gpu, S), 6)
+    lamN = {k: rng.normal(size=S[k].shape) for k in FIELDS}
+    lamN["uc"][:] = 0.0
+    out = []
+    for fast in (False, True):
+        lam = dev(gpu, {**lamN, "x0": np.zeros((n, 3))})
+        th = torch.zeros(4, dtype=torch.float64, device="cuda")
+        for k in range(5, -1, -1):
+            ctx.adjoint_step(states[k], gprm, lam, lam, th, S1=states[k + 1] if fast else None)
+        out.append((lam.to_arrays(), th.cpu().numpy()))
+    for k in FIELDS + ("x0",):
+        a, b = out[1][0][k], out[0][0][k]
+        scale = max(np.max(np.abs(b)), 1e-300)
+        assert np.max(np.abs(a - b)) <= 1e-12 * scale, k
+    assert np.max(np.abs(out[1][1] - out[0][1])) <= 1e-12 * np.max(np.abs(out[0][1]))
