@@ -20,6 +20,13 @@ Algorithmic flops per launch:
     284 per bond                                 (34 full-horizon sums,
        250 for inversion, gradient, trial stress, yield check, force state)
 Newton iterations of the return map are not counted.
+
+Two more objects ride on the same line.  "mixed": the same workload in mixed
+precision from the same initial state (FP32 sums, gathers and force states),
+its throughput, speed-up and relative L2 errors of u, sigma and v against
+the FP64 run after warmup + steps steps.  "adjoint": the checkpointed
+differentiable column (24x24x48 by default, 1000 steps, checkpoint every 50),
+time per forward step, per reverse step (ulppm_adjoint_step) and their ratio.
 """
 import argparse
 import hashlib
@@ -116,44 +123,6 @@ def rel_l2(a, b):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
-def adjoint_cost(cfg_name, steps, every, precision):
-    """Forward and backward of the checkpointed differentiable column on a
-    seeded configuration, objective = runout + settlement."""
-    import torch
-    from paper_2203_05562_amd import adjoint, inputs
-    cfg = inputs.CONFIGS[cfg_name]
-    col = inputs.make_column(cfg)
-    spec = adjoint.ColumnSpec(col, steps, every, precision=precision)
-    spec.timing = True
-    w = inputs.runout_objective_weights(col["lattice"], col["dims"])
-    theta = spec.theta0().requires_grad_(True)
-    s = torch.tensor(col["suction"], dtype=torch.float64, device="cuda", requires_grad=True)
-    v = torch.zeros((col["n"], 3), dtype=torch.float64, device="cuda", requires_grad=True)
-    x0 = torch.tensor(col["x0"], dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    ev[0].record()
-    u = adjoint.ColumnRun.apply(theta, s, v, spec)
-    ev[1].record()
-    J = adjoint.runout_settlement(u, x0, w["top"], w["axis"], 0.1 * inputs.DX)
-    J.backward()
-    ev[2].record()
-    torch.cuda.synchronize()
-    fwd, bwd = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
-    t = spec.last_timing
-    out = dict(workload=f"{cfg_name}: {cfg.nx}x{cfg.ny}x{cfg.nz} column, {steps} steps, checkpoint every {every}, "
-                        f"{'mixed' if precision else 'fp64'} forward, objective runout + settlement",
-               points=col["n"], forward_ms=round(fwd, 2), backward_ms=round(bwd, 2),
-               recompute_ms=round(t["recompute"], 2), reverse_ms=round(t["reverse"], 2),
-               forward_ms_per_step=round(fwd / steps, 4), adjoint_ms_per_step=round(t["reverse"] / steps, 4),
-               adjoint_to_forward_step=round(t["reverse"] / fwd, 3), backward_to_forward=round(bwd / fwd, 3),
-               objective=float(J), grad_theta=[float(g) for g in theta.grad],
-               grad_suction_sum=float(s.grad.sum()), grad_v0_norm=float(torch.linalg.vector_norm(v.grad)))
-    del spec
-    torch.cuda.empty_cache()
-    return out
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,7 +188,8 @@ def main():
     del G
     torch.cuda.empty_cache()
     if args.adjoint_config:
-        out["adjoint"] = adjoint_cost(args.adjoint_config, args.adjoint_steps, args.adjoint_every, 0)
+        from paper_2203_05562_amd.measure import adjoint_cost
+        out["adjoint"] = adjoint_cost(args.adjoint_config, args.adjoint_steps, args.adjoint_every, "fp64")
         log(f"[gpu] adjoint: {out['adjoint']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps, dt)

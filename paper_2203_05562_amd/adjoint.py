@@ -26,15 +26,6 @@ import torch
 from . import ulppm
 
 THETA = ("M", "lam", "kap", "eta")
-_SHARED = ("x0", "fixed", "s")          # never written by a step
-
-
-def _snapshot(S: "ulppm.DeviceState") -> "ulppm.DeviceState":
-    """Copy of the fields a step writes; x0, fixed and s are shared."""
-    T = ulppm.DeviceState.__new__(ulppm.DeviceState)
-    T.n, T.device = S.n, S.device
-    T.t = {k: (v if k in _SHARED else v.clone()) for k, v in S.t.items()}
-    return T
 
 
 class _Clock:
@@ -126,14 +117,14 @@ class ColumnRun(torch.autograd.Function):
         th = theta.detach().cpu()
         S = spec.initial_state(th, s.detach(), v0.detach())
         p = spec.params_for(th)
-        ckpts = [_snapshot(S)]
+        ckpts = [S.snapshot()]
         reps = []
         done = 0
         while done < spec.n_steps:
             m = min(spec.k, spec.n_steps - done)
             reps.append(spec.ctx.step(S, p, m))
             done += m
-            ckpts.append(_snapshot(S))
+            ckpts.append(S.snapshot())
         ctx.spec = spec
         ctx.theta = th
         ctx.ckpts = ckpts
@@ -156,10 +147,10 @@ class ColumnRun(torch.autograd.Function):
             m = min(spec.k, spec.n_steps - starts[seg])
             clock.start("recompute")
             states = [ctx.ckpts[seg]]
-            S = _snapshot(ctx.ckpts[seg])
+            S = ctx.ckpts[seg].snapshot()
             for _ in range(m - 1):
                 spec.ctx.step(S, p, 1)
-                states.append(_snapshot(S))
+                states.append(S.snapshot())
             clock.stop("recompute")
             clock.start("reverse")
             states.append(ctx.ckpts[seg + 1])

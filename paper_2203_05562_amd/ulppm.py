@@ -118,26 +118,45 @@ def make_params(prm: dict, precision: int = ULPPM_FP64, **over) -> Params:
 
 VEC = ("x0", "u", "uc", "v", "a")
 SCAL = ("vol", "phi", "J", "Sr", "mass", "s", "pc")
+# rows of the block a step writes, then the rows it only reads
+_MUT = (("u", 3), ("uc", 3), ("v", 3), ("a", 3), ("vol", 1), ("phi", 1), ("J", 1), ("Sr", 1), ("mass", 1),
+        ("sig", 6), ("pc", 1))
+_RO = (("x0", 3), ("s", 1))
+N_MUT_ROWS = sum(r for _, r in _MUT)
 
 
 class DeviceState:
-    """Point state as SoA torch tensors on one device (caller-owned memory)."""
+    """Point state as SoA torch tensors on one device (caller-owned memory).
+    The fields a step writes are views into one (24, n) float64 block, so a
+    snapshot of them is a single copy; x0 and s sit in a second block."""
 
     def __init__(self, n: int, device="cuda"):
         import torch
         self.n = n
         self.device = torch.device(device)
         f = dict(dtype=torch.float64, device=self.device)
+        self._bind(torch.zeros((N_MUT_ROWS, n), **f), torch.zeros((4, n), **f),
+                   torch.zeros(n, dtype=torch.uint8, device=self.device))
+
+    def _bind(self, mut, ro, fixed):
+        self.mut, self.ro = mut, ro
         self.t: Dict[str, "torch.Tensor"] = {}
-        for k in VEC:
-            self.t[k] = torch.zeros((3, n), **f)
-        for k in SCAL:
-            self.t[k] = torch.zeros(n, **f)
-        self.t["sig"] = torch.zeros((6, n), **f)
-        self.t["fixed"] = torch.zeros(n, dtype=torch.uint8, device=self.device)
+        for block, rows in ((mut, _MUT), (ro, _RO)):
+            r0 = 0
+            for k, r in rows:
+                self.t[k] = block[r0:r0 + r] if r > 1 else block[r0]
+                r0 += r
+        self.t["fixed"] = fixed
 
     def __getitem__(self, k):
         return self.t[k]
+
+    def snapshot(self) -> "DeviceState":
+        """Copy of the fields a step writes; x0, s and fixed are shared."""
+        S = DeviceState.__new__(DeviceState)
+        S.n, S.device = self.n, self.device
+        S._bind(self.mut.clone(), self.ro, self.t["fixed"])
+        return S
 
     @classmethod
     def from_arrays(cls, arrs: dict, device="cuda") -> "DeviceState":
@@ -166,7 +185,7 @@ class DeviceState:
     def clone(self) -> "DeviceState":
         S = DeviceState.__new__(DeviceState)
         S.n, S.device = self.n, self.device
-        S.t = {k: v.clone() for k, v in self.t.items()}
+        S._bind(self.mut.clone(), self.ro.clone(), self.t["fixed"].clone())
         return S
 
     def cstruct(self) -> State:

@@ -317,3 +317,33 @@ def test_mixed_precision_force_states(olib, gpu):
     e = rel_l2(Tg, out["T"])
     say("mixed T rel L2", e)
     assert e < 1e-5
+
+
+def test_C2_full_size_one_step_subsample(olib, gpu):
+    """80 x 80 x 160 = 1,024,000 points: one FP64 step and one mixed step on
+    the GPU against one oracle step from the same initial state, compared on
+    every 64th point (the oracle computes the whole column; the comparison
+    reads the subsample)."""
+    import time
+    say("C2 full size, one step, 1/64 subsample")
+    cfg = inputs.CONFIGS["C2"]
+    col = inputs.make_column(cfg)
+    oprm = olib.make_params(col["params"])
+    t0 = time.time()
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    say(f"oracle set-up {time.time() - t0:.1f}s")
+    S0 = olib.copy_state(S)
+    t0 = time.time()
+    rc, _, st = olib.step(S, oprm, 1)
+    assert rc == 0
+    say(f"oracle step {time.time() - t0:.1f}s, bonds {st['n_bonds']}, plastic {st['n_plastic']}")
+    ids = inputs.subsample_ids(col["n"], 64)
+    sub = lambda D: {k: D[k][ids] for k in FIELDS}
+    ctx = gpu.Context(col["n"])
+    for prec, tol in ((gpu.ULPPM_FP64, 1e-11), (gpu.ULPPM_MIXED, 1e-4)):
+        gprm = gpu.make_params(olib.params_dict(oprm), precision=prec)
+        G = gpu.DeviceState.from_arrays(S0)
+        rep = ctx.step(G, gprm, 1)
+        assert rep["n_bonds"] == st["n_bonds"]
+        compare_states(sub(G.to_arrays()), sub(S), tol, label=f"C2 precision {prec}")
