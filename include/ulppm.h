@@ -115,7 +115,9 @@ typedef struct {
 } ulppm_report;
 
 /* Create a context for up to n_points points and max_family members per family
- * (0 selects 192).  hip_stream is a hipStream_t (NULL = the null stream).
+ * (0 selects 152: a jittered cubic lattice with delta = 3.015 dx has at most
+ * about 125, and 152 lets four FP64 bond workgroups share a CU).  hip_stream
+ * is a hipStream_t (NULL = the null stream).
  * Allocates all scratch now; afterwards only ulppm_adjoint_reserve allocates.
  * Errors: ULPPM_E_ARG (n_points <= 0 or > 2^31-1, max_family > 1024),
  * ULPPM_E_HIP (allocation failed). */

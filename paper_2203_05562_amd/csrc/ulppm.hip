@@ -44,6 +44,12 @@ namespace {
 #ifndef ULPPM_BOND_MIN_WAVES
 #define ULPPM_BOND_MIN_WAVES 1
 #endif
+#ifndef ULPPM_BOND_MFMA
+#define ULPPM_BOND_MFMA 1       // masked sums of the bond kernel on the matrix cores
+#endif
+#ifndef ULPPM_BOND_MX_MIN_WAVES
+#define ULPPM_BOND_MX_MIN_WAVES 2
+#endif
 #ifndef ULPPM_ADJ_MIN_WAVES
 #define ULPPM_ADJ_MIN_WAVES 2
 #endif
@@ -75,6 +81,7 @@ struct DevParams {
   double newton_tol;
   int newton_maxit;
   int force_mode;
+  double iM2;                 // 1 / M^2
 };
 
 struct Grid {                 // cell grid over the current bounding box
@@ -591,7 +598,7 @@ __host__ __device__ __forceinline__ double apparent_pc(const DevParams& P, doubl
 }
 
 __host__ __device__ __forceinline__ double yield_f(const DevParams& P, double p, double q, double pcb) {
-  return q * q / (P.M * P.M) + p * (p - pcb);       // Eq. 40
+  return q * q * P.iM2 + p * (p - pcb);             // Eq. 40
 }
 
 // Retention curve, Eq. 15 read with exponent -(n-1)/n, suction in kPa, void
@@ -665,20 +672,22 @@ struct ConsistencySolve {
 // Newton with the exact tangent; steps are halved to stay in
 // {f > 0, q >= 0, p_c < 0}, where the solution lies.  Returns the iteration
 // count (0 elastic) or -1.
-__host__ __device__ int return_map(const DevParams& P, double dt, const double* sn, double pcn, const double* de,
-                          double* so, double* pco) {
+// Pn: the apparent pre-consolidation of pcn (Eq. 45), the same for every
+// bond of a point.
+__host__ __device__ int return_map_pn(const DevParams& P, double dt, const double* sn, double pcn, double Pn,
+                                      const double* de, double* so, double* pco) {
+  constexpr double kThird = 1.0 / 3.0;
   const double tr = de[0] + de[1] + de[2];
   double st[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k)
-    st[k] = sn[k] + (k < 3 ? P.K * tr : 0.0) + 2.0 * P.mu * (de[k] - (k < 3 ? tr / 3.0 : 0.0));
-  const double ptr = (st[0] + st[1] + st[2]) / 3.0;
+    st[k] = sn[k] + (k < 3 ? P.K * tr : 0.0) + 2.0 * P.mu * (de[k] - (k < 3 ? tr * kThird : 0.0));
+  const double ptr = (st[0] + st[1] + st[2]) * kThird;
   double s[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) s[k] = st[k] - (k < 3 ? ptr : 0.0);
   const double qtr = sqrt(1.5 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
                                  2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5])));
-  const double Pn = apparent_pc(P, pcn);
   if (!(yield_f(P, ptr, qtr, Pn) > 0.0)) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) so[k] = st[k];
@@ -753,6 +762,11 @@ __host__ __device__ int return_map(const DevParams& P, double dt, const double* 
   *pco = pc;
   if (!conv) return -1;
   return it > 0 ? it : 1;
+}
+
+__host__ __device__ int return_map(const DevParams& P, double dt, const double* sn, double pcn, const double* de,
+                                   double* so, double* pco) {
+  return return_map_pn(P, dt, sn, pcn, apparent_pc(P, pcn), de, so, pco);
 }
 
 __host__ __device__ __forceinline__ double det3s(double a, double b, double c, double d, double e, double f) {
@@ -846,11 +860,12 @@ __host__ __device__ void tail_forward(const DevParams& P, const double* K, const
 __host__ __device__ void rm_reverse(const DevParams& P, double dt, const double* sn, double pcn, const double* de,
                                     const double* so, double pco, int branch, const double* sgb, double pcb,
                                     double* snb, double* pcnb, double* deb, double* thb) {
+  constexpr double kThird = 1.0 / 3.0;             // as the forward trial state
   const double tr = de[0] + de[1] + de[2];
   double st[6], s[6];
   for (int k = 0; k < 6; ++k)
-    st[k] = sn[k] + (k < 3 ? P.K * tr : 0.0) + 2.0 * P.mu * (de[k] - (k < 3 ? tr / 3.0 : 0.0));
-  const double ptr = (st[0] + st[1] + st[2]) / 3.0;
+    st[k] = sn[k] + (k < 3 ? P.K * tr : 0.0) + 2.0 * P.mu * (de[k] - (k < 3 ? tr * kThird : 0.0));
+  const double ptr = (st[0] + st[1] + st[2]) * kThird;
   for (int k = 0; k < 6; ++k) s[k] = st[k] - (k < 3 ? ptr : 0.0);
   const double qtr = sqrt(1.5 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5])));
   double stb[6];
@@ -1259,6 +1274,453 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MIN_WAVES) void k_bond(Bon
       Tout[0][slot] = (TS)(a0 * zx + a1 * zy + a2 * zz);
       Tout[1][slot] = (TS)(a3 * zx + a4 * zy + a5 * zz);
       Tout[2][slot] = (TS)(a6 * zx + a7 * zy + a8 * zz);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) hs[k] = wave_sum(hs[k]);
+  hpc = wave_sum(hpc);
+  hw = wave_sum(hw);
+  n_deg = wave_sum_i(n_deg);
+  n_pl = wave_sum_i(n_pl);
+  n_nc = wave_sum_i(n_nc);
+  n_trip = wave_sum_i(n_trip);
+  mx = wave_max_i(mx);
+  __syncthreads();   // red[] is reused
+  if (lane == 0) {
+    for (int k = 0; k < 6; ++k) red[wid][k] = hs[k];
+    red[wid][6] = hpc;
+    red[wid][7] = hw;
+    redi[wid][0] = n_deg; redi[wid][1] = n_pl; redi[wid][2] = n_nc; redi[wid][3] = n_trip;
+    red[wid][8] = (double)mx;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double W = 0.0, hsum[7] = {0, 0, 0, 0, 0, 0, 0};
+    long long d = 0, pl = 0, nc = 0, tr = 0, m2 = 0;
+    for (int w = 0; w < kBondWaves; ++w) {
+      W += red[w][7];
+      for (int k = 0; k < 7; ++k) hsum[k] += red[w][k];
+      d += redi[w][0]; pl += redi[w][1]; nc += redi[w][2]; tr += redi[w][3];
+      m2 = m2 > (long long)red[w][8] ? m2 : (long long)red[w][8];
+    }
+    if (W > 0.0) {
+      for (int k = 0; k < 6; ++k) A.sig_out[k][i] = hsum[k] / W;
+      A.pc_out[i] = hsum[6] / W;
+    } else {
+      for (int k = 0; k < 6; ++k) A.sig_out[k][i] = sig_i[k];
+      A.pc_out[i] = pc_i;
+    }
+    if (d) ctr_add(A.ctr, C_DEGEN, (unsigned long long)d);
+    if (pl) ctr_add(A.ctr, C_PLASTIC, (unsigned long long)pl);
+    if (nc) ctr_add(A.ctr, C_NOCONV, (unsigned long long)nc);
+    ctr_add(A.ctr, C_TRIPLES, (unsigned long long)tr);
+    ctr_add(A.ctr, C_TESTS, (unsigned long long)((long long)nf * nf));
+    if (m2) ctr_max(A.ctr, C_MAXNEWTON, (unsigned long long)m2);
+  }
+}
+
+// ------------------------------------------------- bond kernel, MFMA sums --
+//
+// The masked sums of pass 1 (sub-horizon shape tensor, velocity-gradient
+// sum and volume, Eqs. 22-23, 25, 55, 57) and of pass 2 (force states,
+// Eqs. 27, 31, 35) are both products of the family's 0/1 membership matrix
+// B with a per-member feature matrix:
+//   pass 1: [K_j | N_j | Vs_j] = sum_k B_jk V_k [zeta_k zeta_k^T (6), ydot_k zeta_k^T (9), 1]
+//   pass 2: A_k = sum_j B_kj M_j  (9), then T_ik = A_k zeta_ik.
+// They run on the matrix cores as 16x16x4 products (rows: sub-horizons or
+// members, K: members, N: 16 features), FP64 or FP32 (mixed precision),
+// while the VALU evaluates the exact FP64 membership predicate that forms
+// the 0/1 operand.  Lane layout of the 16x16x4 products (64 lanes, checked
+// on gfx950): A[i][k] in lane i + 16 k, B[k][f] in lane f + 16 k; the result
+// D[i][f] sits in lane f + 16 (i / 4), element i % 4, for FP32 and in lane
+// f + 16 (i % 4), element i / 4, for FP64.
+//
+// Membership bits: for row r and column block c (64 members), word
+// sb[r * nw + c] holds in bit 16 q + s the membership of member 64 c + 4 s + q,
+// so that the lane that tests (r, 4 s + q) owns one 16-bit quarter.
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <class Acc>
+struct Mma;
+template <>
+struct Mma<double> {
+  using V = v4d;
+  static __device__ __forceinline__ V run(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of result element r in lane group q (lane / 16)
+  static __device__ __forceinline__ int row(int q, int r) { return 4 * r + q; }
+};
+template <>
+struct Mma<float> {
+  using V = v4f;
+  static __device__ __forceinline__ V run(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int r) { return 4 * q + r; }
+};
+
+constexpr int kTileBatch = 4;     // 16-row tiles a wave carries through one sweep over the members
+
+template <class Acc>
+__host__ __device__ constexpr size_t bond_mx_lds_bytes(int max_f) {
+  return (size_t)max_f * (sizeof(Quad<double>) + 8 * sizeof(Acc) + 16 * sizeof(Acc)) +
+         (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long);
+}
+
+// Feature f of member k (pass 1, B operand): V_k a_f b_f from the record
+// {zeta0, zeta1, zeta2, V, ydot0, ydot1, ydot2, 1}.
+__host__ __device__ constexpr int feat_a(int f) {
+  return f < 3 ? f : f == 3 ? 1 : f < 6 ? 0 : f < 15 ? 4 + (f - 6) / 3 : 7;
+}
+__host__ __device__ constexpr int feat_b(int f) {
+  return f < 3 ? f : f == 3 ? 2 : f == 4 ? 2 : f == 5 ? 1 : f < 15 ? (f - 6) % 3 : 7;
+}
+
+template <class Acc>
+__global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_mx(BondArgs A, DevParams P) {
+  using TS = Acc;
+  using MM = Mma<Acc>;
+  using V4 = typename MM::V;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t i = xcd_point(blockIdx.x, A.per);
+  if (i >= A.n) return;                           // uniform per block
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int mf = A.max_f;
+  const int64_t n = A.n;
+  const int64_t b0 = A.row[i];
+  const int nf = (int)(A.row[i + 1] - b0);
+  const int nw = (mf + 63) / 64;                   // membership words per row
+  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);        // x_k
+  Acc* sR = reinterpret_cast<Acc*>(sX + mf);                           // 8 per member: zeta, V, ydot, 1
+  Acc* sKN = sR + 8 * (size_t)mf;                                      // 16 per member: K, N, Vs, then M_j
+  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)mf);
+  unsigned short* sq = reinterpret_cast<unsigned short*>(sb);
+  TS** const Tout = reinterpret_cast<TS**>(A.T);
+  __shared__ double s_d2;
+  __shared__ double red[kBondWaves][24];
+  __shared__ double pt[4];
+  __shared__ long long redi[kBondWaves][4];
+
+  const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
+  const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
+
+  // Stage the family of i and form the full-horizon partial sums (Eqs. 5, 8).
+  Acc Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0;
+  for (int m = tid; m < nf; m += kBondThreads) {
+    const int32_t k = A.col[b0 + m];
+    const double xk0 = A.x[k], xk1 = A.x[n + k], xk2 = A.x[2 * n + k];
+    const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
+    const double y0 = A.vh[k] - vi0, y1 = A.vh[n + k] - vi1, y2 = A.vh[2 * n + k] - vi2;
+    const double V = A.vol_n[k];
+    sX[m] = Quad<double>{{xk0, xk1, xk2, 0.0}};
+    const Acc a0 = (Acc)z0, a1 = (Acc)z1, a2 = (Acc)z2, c0 = (Acc)y0, c1 = (Acc)y1, c2 = (Acc)y2, Va = (Acc)V;
+    Acc* rec = sR + 8 * (size_t)m;
+    rec[0] = a0; rec[1] = a1; rec[2] = a2; rec[3] = Va;
+    rec[4] = c0; rec[5] = c1; rec[6] = c2; rec[7] = (Acc)1;
+    const Acc w0 = Va * a0, w1 = Va * a1, w2 = Va * a2;
+    Kp[0] += w0 * a0; Kp[1] += w1 * a1; Kp[2] += w2 * a2;
+    Kp[3] += w1 * a2; Kp[4] += w0 * a2; Kp[5] += w0 * a1;
+    Np[0] += c0 * w0; Np[1] += c0 * w1; Np[2] += c0 * w2;
+    Np[3] += c1 * w0; Np[4] += c1 * w1; Np[5] += c1 * w2;
+    Np[6] += c2 * w0; Np[7] += c2 * w1; Np[8] += c2 * w2;
+    Vp += Va;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) Kp[k] = wave_sum(Kp[k]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Np[k] = wave_sum(Np[k]);
+  Vp = wave_sum(Vp);
+  if (lane == 0) {
+    for (int k = 0; k < 6; ++k) red[wid][k] = (double)Kp[k];
+    for (int k = 0; k < 9; ++k) red[wid][6 + k] = (double)Np[k];
+    red[wid][15] = (double)Vp;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    s_d2 = P.d2;
+    double Ki[6], Ni[9];
+    double Vh = 0.0;
+    for (int k = 0; k < 6; ++k) Ki[k] = 0.0;
+    for (int k = 0; k < 9; ++k) Ni[k] = 0.0;
+    for (int w = 0; w < kBondWaves; ++w) {
+      for (int k = 0; k < 6; ++k) Ki[k] += red[w][k];
+      for (int k = 0; k < 9; ++k) Ni[k] += red[w][6 + k];
+      Vh += red[w][15];
+    }
+    // Volume change of the step: with geometry at n+1 the increment F_D
+    // satisfies F_D^{-1} = I - dt L_i (Eq. 17 in updated Lagrangian form).
+    double Jd = 1.0;
+    const double dK = det3s(Ki[0], Ki[1], Ki[2], Ki[3], Ki[4], Ki[5]);
+    const double tk = (Ki[0] + Ki[1] + Ki[2]) / 3.0;
+    if (nf >= 3 && dK > 1e-12 * tk * tk * tk) {
+      const double a = Ki[0], b = Ki[1], c = Ki[2], d = Ki[3], e = Ki[4], f = Ki[5];
+      const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
+      const double ixy = (d * e - f * c) / dK, ixz = (f * d - b * e) / dK, iyz = (e * f - a * d) / dK;
+      const double Ki9[9] = {ixx, ixy, ixz, ixy, iyy, iyz, ixz, iyz, izz};
+      double B[9];
+      for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) {
+          double L = Ni[3 * r] * Ki9[cc] + Ni[3 * r + 1] * Ki9[3 + cc] + Ni[3 * r + 2] * Ki9[6 + cc];
+          B[3 * r + cc] = (r == cc ? 1.0 : 0.0) - A.dt_inc * L;
+        }
+      const double dB = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
+                        B[2] * (B[3] * B[7] - B[4] * B[6]);
+      Jd = 1.0 / dB;
+    }
+    const double Jn = A.J[i] * Jd;
+    const double Vn = A.vol_n[i] * Jd;
+    const double ph = 1.0 - (1.0 - A.phi[i]) / Jd;            // Eq. 16
+    const double Sr = swrc(P, Jn, ph, A.s[i]);                // Eq. 15
+    A.J_out[i] = Jn;
+    A.vol_out[i] = Vn;
+    A.phi_out[i] = ph;
+    A.Sr_out[i] = Sr;
+    A.mass_out[i] = (P.rho_s * (1.0 - ph) + P.rho_w * Sr * ph) * Vn;   // Eq. 48
+    pt[0] = Sr;
+    pt[1] = 1.0 / Vh;
+    pt[2] = apparent_pc(P, A.pc[i]);                          // Eq. 45, shared by the bonds of i
+  }
+  __syncthreads();
+  const double d2 = s_d2;
+  const int ntile = (nf + 15) >> 4;
+  const int nks = (nf + 3) >> 2;
+  const int nblk = (nks + 15) >> 4;               // bit words per row written by pass 1
+
+  // ---- pass 1: membership matrix x features on the matrix cores.  Tiles
+  // past the family (and rows past nf) carry zero operands; everything in
+  // the member loop is branch-free so that tests and products interleave.
+  {
+    const int fa = feat_a(r16), fb = feat_b(r16);
+    for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
+      double xj[kTileBatch][3];
+      bool jv[kTileBatch];
+      int jrow[kTileBatch];
+      V4 acc[kTileBatch];
+      unsigned piece[kTileBatch];
+#pragma unroll
+      for (int b = 0; b < kTileBatch; ++b) {
+        jrow[b] = (t0 + kBondWaves * b) * 16 + r16;
+        jv[b] = jrow[b] < nf;
+        const Quad<double> q = sX[jv[b] ? jrow[b] : 0];
+        xj[b][0] = q.v[0]; xj[b][1] = q.v[1]; xj[b][2] = q.v[2];
+        acc[b] = V4{0, 0, 0, 0};
+        piece[b] = 0u;
+      }
+      // member data of the next step is loaded one step ahead
+      bool kv = q4 < nf;
+      Quad<double> xk = sX[kv ? q4 : 0];
+      Acc ra = sR[8 * (size_t)(kv ? q4 : 0) + fa], rb = sR[8 * (size_t)(kv ? q4 : 0) + fb],
+          rv = sR[8 * (size_t)(kv ? q4 : 0) + 3];
+      for (int ks = 0; ks < nks; ++ks) {
+        const int k1 = 4 * (ks + 1) + q4;
+        const bool kv1 = k1 < nf;
+        const int kk1 = kv1 ? k1 : 0;
+        const Quad<double> xk1 = sX[kk1];
+        const Acc* rec1 = sR + 8 * (size_t)kk1;
+        const Acc ra1 = rec1[fa], rb1 = rec1[fb], rv1 = rec1[3];
+        const Acc fv = ra * rb * rv;
+        const Acc bval = kv ? fv : (Acc)0;
+        const unsigned sbit = 1u << (ks & 15);
+#pragma unroll
+        for (int b = 0; b < kTileBatch; ++b) {
+          const bool in = within(xj[b][0], xj[b][1], xj[b][2], xk.v[0], xk.v[1], xk.v[2], d2) & kv & jv[b];
+          piece[b] |= in ? sbit : 0u;
+          acc[b] = MM::run(in ? (Acc)1 : (Acc)0, bval, acc[b]);
+        }
+        if ((ks & 15) == 15 || ks == nks - 1) {
+#pragma unroll
+          for (int b = 0; b < kTileBatch; ++b) {
+            if (jv[b]) sq[((size_t)jrow[b] * nw + (ks >> 4)) * 4 + q4] = (unsigned short)piece[b];
+            piece[b] = 0u;
+          }
+        }
+        kv = kv1;
+        xk = xk1;
+        ra = ra1; rb = rb1; rv = rv1;
+      }
+#pragma unroll
+      for (int b = 0; b < kTileBatch; ++b) {
+        const int t = t0 + kBondWaves * b;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = t * 16 + MM::row(q4, r);
+          if (j < nf) sKN[16 * (size_t)j + r16] = acc[b][r];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  const double Sr_i = pt[0], iVh = pt[1], Pn_i = pt[2];
+  const double s_i = A.s[i];
+  double sig_i[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sig_i[k] = A.sig[k][i];
+  const double pc_i = A.pc[i];
+
+  // ---- per-bond tail: one lane per bond (i,j)
+  double hs[6] = {0, 0, 0, 0, 0, 0}, hpc = 0.0, hw = 0.0;
+  long long n_deg = 0, n_pl = 0, n_nc = 0, n_trip = 0, mx = 0;
+  for (int m = tid; m < nf; m += kBondThreads) {
+    Acc* kn = sKN + 16 * (size_t)m;
+    int ns = 0;
+    for (int c = 0; c < nblk; ++c) ns += __popcll(sb[(size_t)m * nw + c]);
+    n_trip += ns;
+    // FP64 from here on: inversion, gradient, return map, force state.
+    const double a = kn[0], b = kn[1], c = kn[2], d = kn[3], e = kn[4], f = kn[5];
+    const double dK = det3s(a, b, c, d, e, f);
+    const double tk = (a + b + c) / 3.0;
+    const int64_t slot = b0 + m;
+    if (ns < 3 || !(dK > 1e-12 * tk * tk * tk)) {               // degenerate: inactive bond
+      ++n_deg;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) kn[q] = (Acc)0;
+      if (P.force_mode == ULPPM_FORCE_EQ51) { Tout[0][slot] = (TS)0; Tout[1][slot] = (TS)0; Tout[2][slot] = (TS)0; }
+      continue;
+    }
+    const double idK = 1.0 / dK;
+    const double ixx = (b * c - d * d) * idK, iyy = (a * c - e * e) * idK, izz = (a * b - f * f) * idK;
+    const double ixy = (d * e - f * c) * idK, ixz = (f * d - b * e) * idK, iyz = (e * f - a * d) * idK;
+    double N[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) N[q] = (double)kn[6 + q];
+    double L[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      L[3 * r + 0] = N[3 * r] * ixx + N[3 * r + 1] * ixy + N[3 * r + 2] * ixz;
+      L[3 * r + 1] = N[3 * r] * ixy + N[3 * r + 1] * iyy + N[3 * r + 2] * iyz;
+      L[3 * r + 2] = N[3 * r] * ixz + N[3 * r + 1] * iyz + N[3 * r + 2] * izz;
+    }
+    const double varpi = (double)kn[15] * iVh;                  // Eq. 55
+    const double h = A.dt_inc;
+    const double de[6] = {h * L[0], h * L[4], h * L[8], h * 0.5 * (L[5] + L[7]), h * 0.5 * (L[2] + L[6]),
+                          h * 0.5 * (L[1] + L[3])};              // Eqs. 26, 59
+    double sgb[6], pcb;
+    if (h == 0.0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sgb[k] = sig_i[k];
+      pcb = pc_i;
+    } else {
+      int it = return_map_pn(P, h, sig_i, pc_i, Pn_i, de, sgb, &pcb);
+      if (it < 0) { ++n_nc; it = P.newton_maxit; }
+      if (it > 0) ++n_pl;
+      mx = mx > it ? mx : it;
+    }
+    // Total bond stress sigma_ij + Sr_i s_i 1 (Eq. 32 with p_w = -s) times K_ij^{-1}.
+    const double ps = Sr_i * s_i;
+    const double S00 = sgb[0] + ps, S11 = sgb[1] + ps, S22 = sgb[2] + ps;
+    const double SK[9] = {S00 * ixx + sgb[5] * ixy + sgb[4] * ixz, S00 * ixy + sgb[5] * iyy + sgb[4] * iyz,
+                          S00 * ixz + sgb[5] * iyz + sgb[4] * izz, sgb[5] * ixx + S11 * ixy + sgb[3] * ixz,
+                          sgb[5] * ixy + S11 * iyy + sgb[3] * iyz, sgb[5] * ixz + S11 * iyz + sgb[3] * izz,
+                          sgb[4] * ixx + sgb[3] * ixy + S22 * ixz, sgb[4] * ixy + sgb[3] * iyy + S22 * iyz,
+                          sgb[4] * ixz + sgb[3] * iyz + S22 * izz};
+    const double Vj = A.vol_n[A.col[slot]];
+    if (P.force_mode == ULPPM_FORCE_EQ51) {
+      // Eq. 51 as printed: T_ij = varpi (sigma_ij + Sr s 1) K_ij^{-1} zeta_ij.
+      const Quad<double> xj = sX[m];
+      const double zx = xj.v[0] - xi0, zy = xj.v[1] - xi1, zz = xj.v[2] - xi2;
+      Tout[0][slot] = (TS)(varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz));
+      Tout[1][slot] = (TS)(varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz));
+      Tout[2][slot] = (TS)(varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz));
+    } else {
+      const double wj = Vj * iVh;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) kn[q] = (Acc)(wj * SK[q]);
+    }
+    // point history: volume-weighted mean of the bond states
+#pragma unroll
+    for (int k = 0; k < 6; ++k) hs[k] += Vj * sgb[k];
+    hpc += Vj * pcb;
+    hw += Vj;
+  }
+  if (P.force_mode == ULPPM_FORCE_CONJUGATE && sizeof(Acc) == 8) {
+    // ---- pass 2 in FP64 on the VALU: one lane per member k streams the M_j
+    // of its row of the (symmetric) membership matrix.  FP64 matrix products
+    // run at the vector rate on this chip and would pad the 9 outputs to 16.
+    __syncthreads();
+    for (int m = tid; m < nf; m += kBondThreads) {
+      Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0, a8 = 0;
+      unsigned long long word = 0ull;
+      Acc r[9];                                        // M_j, loaded one member ahead
+#pragma unroll
+      for (int q = 0; q < 9; ++q) r[q] = sKN[q];
+      for (int j = 0; j < nf; ++j) {
+        if ((j & 63) == 0) word = sb[(size_t)m * nw + (j >> 6)];
+        const int jn = j + 1 < nf ? j + 1 : j;
+        Acc rn[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) rn[q] = sKN[16 * (size_t)jn + q];
+        const int jj = j & 63;
+        const Acc w = (word >> (16 * (jj & 3) + (jj >> 2))) & 1ull ? (Acc)1 : (Acc)0;
+        a0 += w * r[0]; a1 += w * r[1]; a2 += w * r[2];
+        a3 += w * r[3]; a4 += w * r[4]; a5 += w * r[5];
+        a6 += w * r[6]; a7 += w * r[7]; a8 += w * r[8];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) r[q] = rn[q];
+      }
+      const Acc* zm = sR + 8 * (size_t)m;
+      const Acc zx = zm[0], zy = zm[1], zz = zm[2];
+      const int64_t slot = b0 + m;
+      Tout[0][slot] = (TS)(a0 * zx + a1 * zy + a2 * zz);
+      Tout[1][slot] = (TS)(a3 * zx + a4 * zy + a5 * zz);
+      Tout[2][slot] = (TS)(a6 * zx + a7 * zy + a8 * zz);
+    }
+  } else if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
+    // ---- pass 2 in FP32: A_k = sum_j B_kj M_j on the matrix cores
+    // (membership is symmetric, so row k of the bit matrix is column k),
+    // then T_ik = A_k zeta_ik with the three products of a row combined
+    // across neighbouring lanes.
+    __syncthreads();
+    for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
+      V4 acc[kTileBatch];
+      unsigned piece[kTileBatch];
+      int krow[kTileBatch];
+#pragma unroll
+      for (int b = 0; b < kTileBatch; ++b) {
+        acc[b] = V4{0, 0, 0, 0};
+        piece[b] = 0u;
+        krow[b] = (t0 + kBondWaves * b) * 16 + r16;
+      }
+#pragma unroll 2
+      for (int js = 0; js < nks; ++js) {
+        const int j = 4 * js + q4;
+        const bool ok = j < nf && r16 < 9;
+        const Acc mv = sKN[16 * (size_t)(ok ? j : 0) + (r16 < 9 ? r16 : 0)];
+        const Acc bval = ok ? mv : (Acc)0;
+        const int s = js & 15;
+        if (s == 0) {
+#pragma unroll
+          for (int b = 0; b < kTileBatch; ++b) {
+            const bool kv = krow[b] < nf;
+            const unsigned pw = sq[((size_t)(kv ? krow[b] : 0) * nw + (js >> 4)) * 4 + q4];
+            piece[b] = kv ? pw : 0u;
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < kTileBatch; ++b) {
+          const Acc av = (piece[b] >> s) & 1u ? (Acc)1 : (Acc)0;
+          acc[b] = MM::run(av, bval, acc[b]);
+        }
+      }
+      const int qz = r16 % 3;
+#pragma unroll
+      for (int b = 0; b < kTileBatch; ++b) {
+        const int t = t0 + kBondWaves * b;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = t * 16 + MM::row(q4, r);
+          const bool ok = k < nf && r16 < 9;
+          const Acc zq = sR[8 * (size_t)(ok ? k : 0) + qz];
+          const Acc prod = ok ? acc[b][r] * zq : (Acc)0;
+          const Acc p1 = __shfl_down(prod, 1, 16);
+          const Acc p2 = __shfl_down(prod, 2, 16);
+          if (ok && qz == 0) Tout[r16 / 3][b0 + k] = (TS)(prod + p1 + p2);
+        }
+      }
     }
   }
 #pragma unroll
@@ -2196,6 +2658,7 @@ DevParams dev_params(const ulppm_params* p) {
   d.newton_tol = p->newton_tol;
   d.newton_maxit = p->newton_maxit;
   d.force_mode = p->force_mode;
+  d.iM2 = 1.0 / (p->M * p->M);
   return d;
 }
 
@@ -2307,7 +2770,11 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
 }
 
 size_t bond_lds(int max_f, bool mixed) {
+#if ULPPM_BOND_MFMA
+  return mixed ? bond_mx_lds_bytes<float>(max_f) : bond_mx_lds_bytes<double>(max_f);
+#else
   return mixed ? bond_lds_bytes<float>(max_f) : bond_lds_bytes<double>(max_f);
+#endif
 }
 
 // Algorithm 1 (bond pass) into outputs; mode: step (state outputs) or not.
@@ -2344,10 +2811,17 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   A.ctr = ctx->ctr;
   DevParams P = dev_params(p);
   const size_t lds = bond_lds(ctx->max_f, mixed);
+#if ULPPM_BOND_MFMA
+  if (mixed)
+    k_bond_mx<float><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
+  else
+    k_bond_mx<double><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
+#else
   if (mixed)
     k_bond<float><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
   else
     k_bond<double><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
+#endif
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
@@ -2574,10 +3048,13 @@ int ulppm_selfcheck_tail(const ulppm_params* p, int32_t seed, int32_t n_cases, d
       const double x0 = x, h = 1e-5 * fabs(x0);
       int b1, b2;
       x = x0 + h;
+      P.iM2 = 1.0 / (P.M * P.M);
       const double jp = J(P, K, N, sig, pc, Srs, w, &b1);
       x = x0 - h;
+      P.iM2 = 1.0 / (P.M * P.M);
       const double jm = J(P, K, N, sig, pc, Srs, w, &b2);
       x = x0;
+      P.iM2 = 1.0 / (P.M * P.M);
       grads[ng] = thb[k];
       fds[ng++] = (b1 == F.branch && b2 == F.branch) ? (jp - jm) / (2 * h) : (double)NAN;
     }
@@ -2604,7 +3081,7 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   if (!out) return ULPPM_E_ARG;
   *out = nullptr;
   if (n_points <= 0 || n_points > 2147483647LL) return ULPPM_E_ARG;
-  if (max_family == 0) max_family = 192;
+  if (max_family == 0) max_family = 152;
   if (max_family < 8 || max_family > 1024) return ULPPM_E_ARG;
   ctx = new ulppm_ctx();
   ctx->stream = (hipStream_t)hip_stream;
@@ -2665,10 +3142,17 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
     return ULPPM_E_HIP;
   }
   // the bond kernel's dynamic LDS may exceed the default cap for large max_family
+#if ULPPM_BOND_MFMA
+  (void)hipFuncSetAttribute((const void*)k_bond_mx<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bond_lds(max_family, false));
+  (void)hipFuncSetAttribute((const void*)k_bond_mx<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bond_lds(max_family, true));
+#else
   (void)hipFuncSetAttribute((const void*)k_bond<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bond_lds(max_family, false));
   (void)hipFuncSetAttribute((const void*)k_bond<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bond_lds(max_family, true));
+#endif
   if (hipGetLastError() != hipSuccess) {
     ulppm_destroy(ctx);
     return ULPPM_E_HIP;

@@ -206,7 +206,7 @@ class DeviceState:
 class Context:
     """One ulppm context (scratch for up to n points) on the current stream."""
 
-    def __init__(self, n_points: int, max_family: int = 192, stream=None):
+    def __init__(self, n_points: int, max_family: int = 0, stream=None):
         import torch
         self.L = load_library()
         if stream is None:
