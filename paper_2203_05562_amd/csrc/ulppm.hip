@@ -1015,6 +1015,7 @@ struct BondArgs {
   double* sig_out[6];
   double* pc_out;
   void* T[3];             // bond force states, CSR order (double, or float in mixed precision)
+  double* pk;             // 2n: apparent pre-consolidation of p_c,i and 1/V_H,i (k_point_kin)
   double dt_inc;
   int max_f;
   unsigned long long* ctr;
@@ -1319,6 +1320,76 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MIN_WAVES) void k_bond(Bon
   }
 }
 
+// ------------------------------------------------------ point kinematics --
+// Point kinematics of the step (Eqs. 5, 8, 15-17, 48), one wave per point:
+// the full-horizon shape tensor K_i, velocity-gradient sum N_i and family
+// volume V_H in FP64, then lane 0 updates J, V, phi, S_r and the mass and
+// stores the apparent pre-consolidation of p_c,i (Eq. 45) and 1/V_H, which
+// every bond of i uses.  With geometry at n+1 the step's deformation
+// increment F_D satisfies F_D^{-1} = I - dt L_i (Eq. 17 in updated
+// Lagrangian form).
+__global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t n = A.n;
+  const XcdWalk W = xcd_walk(n, 4);
+  for (int64_t i = W.first; i < W.end; i += W.stride) {
+    const int64_t b0 = A.row[i], b1 = A.row[i + 1];
+    const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
+    const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
+    double Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0.0;
+    for (int64_t s = b0 + lane; s < b1; s += kWave) {
+      const int32_t k = A.col[s];
+      const double z0 = A.x[k] - xi0, z1 = A.x[n + k] - xi1, z2 = A.x[2 * n + k] - xi2;
+      const double y0 = A.vh[k] - vi0, y1 = A.vh[n + k] - vi1, y2 = A.vh[2 * n + k] - vi2;
+      const double V = A.vol_n[k];
+      const double w0 = V * z0, w1 = V * z1, w2 = V * z2;
+      Kp[0] += w0 * z0; Kp[1] += w1 * z1; Kp[2] += w2 * z2;
+      Kp[3] += w1 * z2; Kp[4] += w0 * z2; Kp[5] += w0 * z1;
+      Np[0] += y0 * w0; Np[1] += y0 * w1; Np[2] += y0 * w2;
+      Np[3] += y1 * w0; Np[4] += y1 * w1; Np[5] += y1 * w2;
+      Np[6] += y2 * w0; Np[7] += y2 * w1; Np[8] += y2 * w2;
+      Vp += V;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Kp[k] = wave_sum(Kp[k]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Np[k] = wave_sum(Np[k]);
+    Vp = wave_sum(Vp);
+    if (lane == 0) {
+      const int nf = (int)(b1 - b0);
+      double Jd = 1.0;
+      const double dK = det3s(Kp[0], Kp[1], Kp[2], Kp[3], Kp[4], Kp[5]);
+      const double tk = (Kp[0] + Kp[1] + Kp[2]) / 3.0;
+      if (nf >= 3 && dK > 1e-12 * tk * tk * tk) {
+        const double a = Kp[0], b = Kp[1], c = Kp[2], d = Kp[3], e = Kp[4], f = Kp[5];
+        const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
+        const double ixy = (d * e - f * c) / dK, ixz = (f * d - b * e) / dK, iyz = (e * f - a * d) / dK;
+        const double Ki9[9] = {ixx, ixy, ixz, ixy, iyy, iyz, ixz, iyz, izz};
+        double B[9];
+        for (int r = 0; r < 3; ++r)
+          for (int cc = 0; cc < 3; ++cc) {
+            const double L = Np[3 * r] * Ki9[cc] + Np[3 * r + 1] * Ki9[3 + cc] + Np[3 * r + 2] * Ki9[6 + cc];
+            B[3 * r + cc] = (r == cc ? 1.0 : 0.0) - A.dt_inc * L;
+          }
+        const double dB = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
+                          B[2] * (B[3] * B[7] - B[4] * B[6]);
+        Jd = 1.0 / dB;
+      }
+      const double Jn = A.J[i] * Jd;
+      const double Vn = A.vol_n[i] * Jd;
+      const double ph = 1.0 - (1.0 - A.phi[i]) / Jd;            // Eq. 16
+      const double Sr = swrc(P, Jn, ph, A.s[i]);                // Eq. 15
+      A.J_out[i] = Jn;
+      A.vol_out[i] = Vn;
+      A.phi_out[i] = ph;
+      A.Sr_out[i] = Sr;
+      A.mass_out[i] = (P.rho_s * (1.0 - ph) + P.rho_w * Sr * ph) * Vn;   // Eq. 48
+      A.pk[i] = apparent_pc(P, A.pc[i]);
+      A.pk[n + i] = Vp > 0.0 ? 1.0 / Vp : 0.0;
+    }
+  }
+}
+
 // ------------------------------------------------- bond kernel, MFMA sums --
 //
 // The masked sums of pass 1 (sub-horizon shape tensor, velocity-gradient
@@ -1394,7 +1465,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
   const int nw = (mf + 63) / 64;                   // membership words per row
-  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);        // x_k
+  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);        // x_k, V_k
   Acc* sR = reinterpret_cast<Acc*>(sX + mf);                           // 8 per member: zeta, V, ydot, 1
   Acc* sKN = sR + 8 * (size_t)mf;                                      // 16 per member: K, N, Vs, then M_j
   unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)mf);
@@ -1402,87 +1473,32 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
   TS** const Tout = reinterpret_cast<TS**>(A.T);
   __shared__ double s_d2;
   __shared__ double red[kBondWaves][24];
-  __shared__ double pt[4];
   __shared__ long long redi[kBondWaves][4];
 
   const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
   const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
 
-  // Stage the family of i and form the full-horizon partial sums (Eqs. 5, 8).
-  Acc Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0;
+  // Per-point values of this step (k_point_kin), fetched while the family is staged.
+  const double Sr_i = A.Sr_out[i], Pn_i = A.pk[i], iVh = A.pk[n + i];
+  const double s_i = A.s[i];
+  double sig_i[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sig_i[k] = A.sig[k][i];
+  const double pc_i = A.pc[i];
+  if (tid == 0) s_d2 = P.d2;
+
+  // Stage the family of i: positions for the exact predicate, zeta_ik, V_k
+  // and ydot_ik for the feature matrix.
   for (int m = tid; m < nf; m += kBondThreads) {
     const int32_t k = A.col[b0 + m];
     const double xk0 = A.x[k], xk1 = A.x[n + k], xk2 = A.x[2 * n + k];
     const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
     const double y0 = A.vh[k] - vi0, y1 = A.vh[n + k] - vi1, y2 = A.vh[2 * n + k] - vi2;
-    const double V = A.vol_n[k];
-    sX[m] = Quad<double>{{xk0, xk1, xk2, 0.0}};
-    const Acc a0 = (Acc)z0, a1 = (Acc)z1, a2 = (Acc)z2, c0 = (Acc)y0, c1 = (Acc)y1, c2 = (Acc)y2, Va = (Acc)V;
+    const double Vk = A.vol_n[k];
+    sX[m] = Quad<double>{{xk0, xk1, xk2, Vk}};
     Acc* rec = sR + 8 * (size_t)m;
-    rec[0] = a0; rec[1] = a1; rec[2] = a2; rec[3] = Va;
-    rec[4] = c0; rec[5] = c1; rec[6] = c2; rec[7] = (Acc)1;
-    const Acc w0 = Va * a0, w1 = Va * a1, w2 = Va * a2;
-    Kp[0] += w0 * a0; Kp[1] += w1 * a1; Kp[2] += w2 * a2;
-    Kp[3] += w1 * a2; Kp[4] += w0 * a2; Kp[5] += w0 * a1;
-    Np[0] += c0 * w0; Np[1] += c0 * w1; Np[2] += c0 * w2;
-    Np[3] += c1 * w0; Np[4] += c1 * w1; Np[5] += c1 * w2;
-    Np[6] += c2 * w0; Np[7] += c2 * w1; Np[8] += c2 * w2;
-    Vp += Va;
-  }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) Kp[k] = wave_sum(Kp[k]);
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Np[k] = wave_sum(Np[k]);
-  Vp = wave_sum(Vp);
-  if (lane == 0) {
-    for (int k = 0; k < 6; ++k) red[wid][k] = (double)Kp[k];
-    for (int k = 0; k < 9; ++k) red[wid][6 + k] = (double)Np[k];
-    red[wid][15] = (double)Vp;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    s_d2 = P.d2;
-    double Ki[6], Ni[9];
-    double Vh = 0.0;
-    for (int k = 0; k < 6; ++k) Ki[k] = 0.0;
-    for (int k = 0; k < 9; ++k) Ni[k] = 0.0;
-    for (int w = 0; w < kBondWaves; ++w) {
-      for (int k = 0; k < 6; ++k) Ki[k] += red[w][k];
-      for (int k = 0; k < 9; ++k) Ni[k] += red[w][6 + k];
-      Vh += red[w][15];
-    }
-    // Volume change of the step: with geometry at n+1 the increment F_D
-    // satisfies F_D^{-1} = I - dt L_i (Eq. 17 in updated Lagrangian form).
-    double Jd = 1.0;
-    const double dK = det3s(Ki[0], Ki[1], Ki[2], Ki[3], Ki[4], Ki[5]);
-    const double tk = (Ki[0] + Ki[1] + Ki[2]) / 3.0;
-    if (nf >= 3 && dK > 1e-12 * tk * tk * tk) {
-      const double a = Ki[0], b = Ki[1], c = Ki[2], d = Ki[3], e = Ki[4], f = Ki[5];
-      const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
-      const double ixy = (d * e - f * c) / dK, ixz = (f * d - b * e) / dK, iyz = (e * f - a * d) / dK;
-      const double Ki9[9] = {ixx, ixy, ixz, ixy, iyy, iyz, ixz, iyz, izz};
-      double B[9];
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc) {
-          double L = Ni[3 * r] * Ki9[cc] + Ni[3 * r + 1] * Ki9[3 + cc] + Ni[3 * r + 2] * Ki9[6 + cc];
-          B[3 * r + cc] = (r == cc ? 1.0 : 0.0) - A.dt_inc * L;
-        }
-      const double dB = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
-                        B[2] * (B[3] * B[7] - B[4] * B[6]);
-      Jd = 1.0 / dB;
-    }
-    const double Jn = A.J[i] * Jd;
-    const double Vn = A.vol_n[i] * Jd;
-    const double ph = 1.0 - (1.0 - A.phi[i]) / Jd;            // Eq. 16
-    const double Sr = swrc(P, Jn, ph, A.s[i]);                // Eq. 15
-    A.J_out[i] = Jn;
-    A.vol_out[i] = Vn;
-    A.phi_out[i] = ph;
-    A.Sr_out[i] = Sr;
-    A.mass_out[i] = (P.rho_s * (1.0 - ph) + P.rho_w * Sr * ph) * Vn;   // Eq. 48
-    pt[0] = Sr;
-    pt[1] = 1.0 / Vh;
-    pt[2] = apparent_pc(P, A.pc[i]);                          // Eq. 45, shared by the bonds of i
+    rec[0] = (Acc)z0; rec[1] = (Acc)z1; rec[2] = (Acc)z2; rec[3] = (Acc)Vk;
+    rec[4] = (Acc)y0; rec[5] = (Acc)y1; rec[6] = (Acc)y2; rec[7] = (Acc)1;
   }
   __syncthreads();
   const double d2 = s_d2;
@@ -1555,13 +1571,6 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
   }
   __syncthreads();
 
-  const double Sr_i = pt[0], iVh = pt[1], Pn_i = pt[2];
-  const double s_i = A.s[i];
-  double sig_i[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) sig_i[k] = A.sig[k][i];
-  const double pc_i = A.pc[i];
-
   // ---- per-bond tail: one lane per bond (i,j)
   double hs[6] = {0, 0, 0, 0, 0, 0}, hpc = 0.0, hw = 0.0;
   long long n_deg = 0, n_pl = 0, n_nc = 0, n_trip = 0, mx = 0;
@@ -1618,7 +1627,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
                           sgb[5] * ixy + S11 * iyy + sgb[3] * iyz, sgb[5] * ixz + S11 * iyz + sgb[3] * izz,
                           sgb[4] * ixx + sgb[3] * ixy + S22 * ixz, sgb[4] * ixy + sgb[3] * iyy + S22 * iyz,
                           sgb[4] * ixz + sgb[3] * iyz + S22 * izz};
-    const double Vj = A.vol_n[A.col[slot]];
+    const double Vj = sX[m].v[3];
     if (P.force_mode == ULPPM_FORCE_EQ51) {
       // Eq. 51 as printed: T_ij = varpi (sigma_ij + Sr s 1) K_ij^{-1} zeta_ij.
       const Quad<double> xj = sX[m];
@@ -2592,6 +2601,7 @@ struct ulppm_ctx {
   double* vh = nullptr;     // 3n
   double* vol_n = nullptr;  // n
   double* pscr = nullptr;   // 12n point scratch for non-mutating passes
+  double* pk = nullptr;     // 2n per-point values of the bond pass
   int32_t* cellid = nullptr;
   int32_t* cnt = nullptr;
   int64_t* row = nullptr;   // n+1
@@ -2809,9 +2819,11 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   A.dt_inc = dt_inc;
   A.max_f = ctx->max_f;
   A.ctr = ctx->ctr;
+  A.pk = ctx->pk;
   DevParams P = dev_params(p);
   const size_t lds = bond_lds(ctx->max_f, mixed);
 #if ULPPM_BOND_MFMA
+  k_point_kin<<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
   if (mixed)
     k_bond_mx<float><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
   else
@@ -3105,6 +3117,7 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   A((void**)&ctx->vh, sizeof(double) * 3 * n);
   A((void**)&ctx->vol_n, sizeof(double) * n);
   A((void**)&ctx->pscr, sizeof(double) * 12 * n);
+  A((void**)&ctx->pk, sizeof(double) * 2 * n);
   A((void**)&ctx->cellid, sizeof(int32_t) * n);
   A((void**)&ctx->cnt, sizeof(int32_t) * n);
   A((void**)&ctx->row, sizeof(int64_t) * (n + 1));
@@ -3165,7 +3178,7 @@ int ulppm_destroy(ulppm_ctx* ctx) {
   if (!ctx) return ULPPM_E_ARG;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
-  void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->cellid, ctx->cnt, ctx->row, ctx->cand,
+  void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->pk, ctx->cellid, ctx->cnt, ctx->row, ctx->cand,
                   ctx->ccnt, ctx->crev, ctx->posmap, ctx->xref, ctx->gate,
                   ctx->ccount, ctx->ccursor, ctx->cstart, ctx->cpts, ctx->col, ctx->rev, ctx->T,
                   ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->ctr_sum, ctx->E, ctx->adj,
