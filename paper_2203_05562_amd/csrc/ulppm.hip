@@ -41,12 +41,6 @@ namespace {
 #ifndef ULPPM_BOND_THREADS
 #define ULPPM_BOND_THREADS 128
 #endif
-#ifndef ULPPM_BOND_MIN_WAVES
-#define ULPPM_BOND_MIN_WAVES 1
-#endif
-#ifndef ULPPM_BOND_MFMA
-#define ULPPM_BOND_MFMA 1       // masked sums of the bond kernel on the matrix cores
-#endif
 #ifndef ULPPM_BOND_MX_MIN_WAVES
 #define ULPPM_BOND_MX_MIN_WAVES 2
 #endif
@@ -123,31 +117,69 @@ __device__ __forceinline__ XcdWalk xcd_walk(int64_t n, int wpb) {
   return w;
 }
 
+// Wave reductions with DPP lane exchanges (no LDS traffic): butterflies
+// within each row of 16 lanes (quad_perm xor 1 and 2, half-row and row
+// mirrors), then row_bcast15 and row_bcast31 carry the row totals into the
+// last row; lane 63 holds the wave's total, which is read back uniformly.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, Ctrl, RowMask, 0xF, false);
+}
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<Ctrl, RowMask>((int)b);
+  const int hi = dpp_i<Ctrl, RowMask>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<Ctrl, RowMask>(__float_as_int(v)));
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140,
+              kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_d<kDppXor1, 0xF>(v);
+  v += dpp_d<kDppXor2, 0xF>(v);
+  v += dpp_d<kDppHalfMirror, 0xF>(v);
+  v += dpp_d<kDppMirror, 0xF>(v);
+  v += dpp_d<kDppBcast15, 0xA>(v);
+  v += dpp_d<kDppBcast31, 0xC>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_f<kDppXor1, 0xF>(v);
+  v += dpp_f<kDppXor2, 0xF>(v);
+  v += dpp_f<kDppHalfMirror, 0xF>(v);
+  v += dpp_f<kDppMirror, 0xF>(v);
+  v += dpp_f<kDppBcast15, 0xA>(v);
+  v += dpp_f<kDppBcast31, 0xC>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-__device__ __forceinline__ long long wave_sum_i(long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+__device__ __forceinline__ int wave_sum_i(int v) {
+  v += dpp_i<kDppXor1, 0xF>(v);
+  v += dpp_i<kDppXor2, 0xF>(v);
+  v += dpp_i<kDppHalfMirror, 0xF>(v);
+  v += dpp_i<kDppMirror, 0xF>(v);
+  v += dpp_i<kDppBcast15, 0xA>(v);
+  v += dpp_i<kDppBcast31, 0xC>(v);
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
-__device__ __forceinline__ long long wave_max_i(long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    long long w = __shfl_xor(v, o, kWave);
-    v = v > w ? v : w;
-  }
-  return v;
+// maximum of non-negative values (masked rows contribute 0)
+__device__ __forceinline__ int wave_max_i(int v) {
+  v = max(v, dpp_i<kDppXor1, 0xF>(v));
+  v = max(v, dpp_i<kDppXor2, 0xF>(v));
+  v = max(v, dpp_i<kDppHalfMirror, 0xF>(v));
+  v = max(v, dpp_i<kDppMirror, 0xF>(v));
+  v = max(v, dpp_i<kDppBcast15, 0xA>(v));
+  v = max(v, dpp_i<kDppBcast31, 0xC>(v));
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Exact squared distance, rounded as ((dx^2 + dy^2) + dz^2) with no fused
@@ -1016,15 +1048,16 @@ struct BondArgs {
   double* pc_out;
   void* T[3];             // bond force states, CSR order (double, or float in mixed precision)
   double* pk;             // 2n: apparent pre-consolidation of p_c,i and 1/V_H,i (k_point_kin)
+  const double* xv;       // 8n: x (3), V^n, v_half (3), 0 per point
   double dt_inc;
   int max_f;
   unsigned long long* ctr;
 };
 
-// LDS records of one family member k of point i, 16-byte aligned so that
-// each is read with ds_read_b128: positions (FP64, for the exact predicate),
-// zeta_ik with V_k, and ydot_ik.  The sub-horizon force-state factors of
-// pass 2 are 9 values per bond, padded to a 16-byte multiple.
+// LDS records of one family member, 16-byte aligned so that each is read
+// with ds_read_b128 (the adjoint's bond kernel): positions, zeta_ik with V_k,
+// ydot_ik; the sub-horizon force-state factors are 9 values per bond, padded
+// to a 16-byte multiple.
 template <class T>
 struct alignas(16) Quad {
   T v[4];
@@ -1034,293 +1067,18 @@ struct alignas(16) MRec {
   Acc v[sizeof(Acc) == 8 ? 10 : 12];
 };
 
-template <class Acc>
-__host__ __device__ constexpr size_t bond_lds_bytes(int max_f) {
-  return (size_t)max_f * (sizeof(Quad<double>) + 2 * sizeof(Quad<Acc>) + sizeof(MRec<Acc>)) +
-         (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long);
-}
-
-// One workgroup per point i, one lane per bond (i,j).
-// Acc: type of the sub-horizon, full-horizon and force-state sums (and of
-// the force states written); double, or float for mixed precision.
-template <class Acc>
-__global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MIN_WAVES) void k_bond(BondArgs A, DevParams P) {
-  using TS = Acc;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int64_t i = xcd_point(blockIdx.x, A.per);
-  if (i >= A.n) return;                           // uniform per block
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  const int mf = A.max_f;
-  const int64_t n = A.n;
-  const int64_t b0 = A.row[i];
-  const int nf = (int)(A.row[i + 1] - b0);
-  const int nw = (mf + 63) / 64;                   // membership words per row
-  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);        // x_k
-  Quad<Acc>* sZ = reinterpret_cast<Quad<Acc>*>(sX + mf);               // zeta_ik, V_k
-  Quad<Acc>* sY = sZ + mf;                                              // ydot_ik
-  MRec<Acc>* sM = reinterpret_cast<MRec<Acc>*>(sY + mf);               // (V_j/V_H)(sigma_ij + S_r s 1) K_ij^{-1}
-  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sM + mf);  // mf*nw S_ij rows
-  TS** const Tout = reinterpret_cast<TS**>(A.T);
-  __shared__ double s_d2;
-  __shared__ double red[kBondWaves][24];
-  __shared__ double pt[4];                         // Sr_new, Vh, sum-of-family-volumes
-  __shared__ long long redi[kBondWaves][4];
-
-  const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
-  const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
-
-  // Stage the family of i and form the full-horizon partial sums (Eqs. 5, 8).
-  Acc Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0;
-  for (int m = tid; m < nf; m += kBondThreads) {
-    const int32_t k = A.col[b0 + m];
-    const double xk0 = A.x[k], xk1 = A.x[n + k], xk2 = A.x[2 * n + k];
-    const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
-    const double y0 = A.vh[k] - vi0, y1 = A.vh[n + k] - vi1, y2 = A.vh[2 * n + k] - vi2;
-    const double V = A.vol_n[k];
-    sX[m] = Quad<double>{{xk0, xk1, xk2, 0.0}};
-    sZ[m] = Quad<Acc>{{(Acc)z0, (Acc)z1, (Acc)z2, (Acc)V}};
-    sY[m] = Quad<Acc>{{(Acc)y0, (Acc)y1, (Acc)y2, (Acc)0}};
-    const Acc a0 = (Acc)z0, a1 = (Acc)z1, a2 = (Acc)z2, c0 = (Acc)y0, c1 = (Acc)y1, c2 = (Acc)y2, Va = (Acc)V;
-    const Acc w0 = Va * a0, w1 = Va * a1, w2 = Va * a2;
-    Kp[0] += w0 * a0; Kp[1] += w1 * a1; Kp[2] += w2 * a2;
-    Kp[3] += w1 * a2; Kp[4] += w0 * a2; Kp[5] += w0 * a1;
-    Np[0] += c0 * w0; Np[1] += c0 * w1; Np[2] += c0 * w2;
-    Np[3] += c1 * w0; Np[4] += c1 * w1; Np[5] += c1 * w2;
-    Np[6] += c2 * w0; Np[7] += c2 * w1; Np[8] += c2 * w2;
-    Vp += Va;
-  }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) Kp[k] = wave_sum(Kp[k]);
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Np[k] = wave_sum(Np[k]);
-  Vp = wave_sum(Vp);
-  if (lane == 0) {
-    for (int k = 0; k < 6; ++k) red[wid][k] = (double)Kp[k];
-    for (int k = 0; k < 9; ++k) red[wid][6 + k] = (double)Np[k];
-    red[wid][15] = (double)Vp;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    s_d2 = P.d2;
-    double Ki[6], Ni[9];
-    double Vh = 0.0;
-    for (int k = 0; k < 6; ++k) Ki[k] = 0.0;
-    for (int k = 0; k < 9; ++k) Ni[k] = 0.0;
-    for (int w = 0; w < kBondWaves; ++w) {
-      for (int k = 0; k < 6; ++k) Ki[k] += red[w][k];
-      for (int k = 0; k < 9; ++k) Ni[k] += red[w][6 + k];
-      Vh += red[w][15];
-    }
-    // Volume change of the step: with geometry at n+1 the increment F_D
-    // satisfies F_D^{-1} = I - dt L_i (Eq. 17 in updated Lagrangian form).
-    double Jd = 1.0;
-    const double dK = det3s(Ki[0], Ki[1], Ki[2], Ki[3], Ki[4], Ki[5]);
-    const double tk = (Ki[0] + Ki[1] + Ki[2]) / 3.0;
-    if (nf >= 3 && dK > 1e-12 * tk * tk * tk) {
-      const double a = Ki[0], b = Ki[1], c = Ki[2], d = Ki[3], e = Ki[4], f = Ki[5];
-      const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
-      const double ixy = (d * e - f * c) / dK, ixz = (f * d - b * e) / dK, iyz = (e * f - a * d) / dK;
-      const double Ki9[9] = {ixx, ixy, ixz, ixy, iyy, iyz, ixz, iyz, izz};
-      double B[9];
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc) {
-          double L = Ni[3 * r] * Ki9[cc] + Ni[3 * r + 1] * Ki9[3 + cc] + Ni[3 * r + 2] * Ki9[6 + cc];
-          B[3 * r + cc] = (r == cc ? 1.0 : 0.0) - A.dt_inc * L;
-        }
-      const double dB = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
-                        B[2] * (B[3] * B[7] - B[4] * B[6]);
-      Jd = 1.0 / dB;
-    }
-    const double Jn = A.J[i] * Jd;
-    const double Vn = A.vol_n[i] * Jd;
-    const double ph = 1.0 - (1.0 - A.phi[i]) / Jd;            // Eq. 16
-    const double Sr = swrc(P, Jn, ph, A.s[i]);                // Eq. 15
-    A.J_out[i] = Jn;
-    A.vol_out[i] = Vn;
-    A.phi_out[i] = ph;
-    A.Sr_out[i] = Sr;
-    A.mass_out[i] = (P.rho_s * (1.0 - ph) + P.rho_w * Sr * ph) * Vn;   // Eq. 48
-    pt[0] = Sr;
-    pt[1] = Vh;
-  }
-  __syncthreads();
-  const double Sr_i = pt[0], Vh = pt[1];
-  const double s_i = A.s[i];
-  double sig_i[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) sig_i[k] = A.sig[k][i];
-  const double pc_i = A.pc[i];
-  const double d2 = s_d2;                          // from LDS: a VGPR, not a reloaded kernel argument
-
-  double hs[6] = {0, 0, 0, 0, 0, 0}, hpc = 0.0, hw = 0.0;
-  long long n_deg = 0, n_pl = 0, n_nc = 0, n_trip = 0, mx = 0;
-  for (int m = tid; m < nf; m += kBondThreads) {
-    const Quad<double> xj = sX[m];
-    const double xj0 = xj.v[0], xj1 = xj.v[1], xj2 = xj.v[2];
-    Acc K0 = 0, K1 = 0, K2 = 0, K3 = 0, K4 = 0, K5 = 0;
-    Acc N00 = 0, N01 = 0, N02 = 0, N10 = 0, N11 = 0, N12 = 0, N20 = 0, N21 = 0, N22 = 0, Vs = 0;
-    int ns = 0;
-    for (int t0 = 0; t0 < nf; t0 += 64) {
-      const int tn = nf - t0 < 64 ? nf - t0 : 64;
-      unsigned long long word = 0ull;
-      for (int u = 0; u < tn; ++u) {
-        const int t = t0 + u;
-        const Quad<double> xk = sX[t];
-        const Quad<Acc> zk = sZ[t];
-        const Quad<Acc> yk = sY[t];
-        const bool in = within(xj0, xj1, xj2, xk.v[0], xk.v[1], xk.v[2], d2);
-        const Acc w = in ? zk.v[3] : (Acc)0;
-        ns += in ? 1 : 0;
-        word |= (unsigned long long)in << u;
-        const Acc z0 = zk.v[0], z1 = zk.v[1], z2 = zk.v[2];
-        const Acc w0 = w * z0, w1 = w * z1, w2 = w * z2;
-        K0 += w0 * z0; K1 += w1 * z1; K2 += w2 * z2;
-        K3 += w1 * z2; K4 += w0 * z2; K5 += w0 * z1;
-        const Acc y0 = yk.v[0], y1 = yk.v[1], y2 = yk.v[2];
-        N00 += y0 * w0; N01 += y0 * w1; N02 += y0 * w2;
-        N10 += y1 * w0; N11 += y1 * w1; N12 += y1 * w2;
-        N20 += y2 * w0; N21 += y2 * w1; N22 += y2 * w2;
-        Vs += w;
-      }
-      sb[(size_t)m * nw + (t0 >> 6)] = word;
-    }
-    n_trip += ns;
-    // FP64 from here on: inversion, gradient, return map, force state.
-    const double a = K0, b = K1, c = K2, d = K3, e = K4, f = K5;
-    const double dK = det3s(a, b, c, d, e, f);
-    const double tk = (a + b + c) / 3.0;
-    const int64_t slot = b0 + m;
-    if (ns < 3 || !(dK > 1e-12 * tk * tk * tk)) {               // degenerate: inactive bond
-      ++n_deg;
-      sM[m] = MRec<Acc>{};
-      if (P.force_mode == ULPPM_FORCE_EQ51) { Tout[0][slot] = (TS)0; Tout[1][slot] = (TS)0; Tout[2][slot] = (TS)0; }
-      continue;
-    }
-    const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
-    const double ixy = (d * e - f * c) / dK, ixz = (f * d - b * e) / dK, iyz = (e * f - a * d) / dK;
-    const double N[9] = {(double)N00, (double)N01, (double)N02, (double)N10, (double)N11,
-                         (double)N12, (double)N20, (double)N21, (double)N22};
-    double L[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      L[3 * r + 0] = N[3 * r] * ixx + N[3 * r + 1] * ixy + N[3 * r + 2] * ixz;
-      L[3 * r + 1] = N[3 * r] * ixy + N[3 * r + 1] * iyy + N[3 * r + 2] * iyz;
-      L[3 * r + 2] = N[3 * r] * ixz + N[3 * r + 1] * iyz + N[3 * r + 2] * izz;
-    }
-    const double varpi = (double)Vs / Vh;                       // Eq. 55
-    const double h = A.dt_inc;
-    const double de[6] = {h * L[0], h * L[4], h * L[8], h * 0.5 * (L[5] + L[7]), h * 0.5 * (L[2] + L[6]),
-                          h * 0.5 * (L[1] + L[3])};              // Eqs. 26, 59
-    double sgb[6], pcb;
-    if (h == 0.0) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) sgb[k] = sig_i[k];
-      pcb = pc_i;
-    } else {
-      int it = return_map(P, h, sig_i, pc_i, de, sgb, &pcb);
-      if (it < 0) { ++n_nc; it = P.newton_maxit; }
-      if (it > 0) ++n_pl;
-      mx = mx > it ? mx : it;
-    }
-    // Total bond stress sigma_ij + Sr_i s_i 1 (Eq. 32 with p_w = -s) times K_ij^{-1}.
-    const double ps = Sr_i * s_i;
-    const double S00 = sgb[0] + ps, S11 = sgb[1] + ps, S22 = sgb[2] + ps;
-    const double SK[9] = {S00 * ixx + sgb[5] * ixy + sgb[4] * ixz, S00 * ixy + sgb[5] * iyy + sgb[4] * iyz,
-                          S00 * ixz + sgb[5] * iyz + sgb[4] * izz, sgb[5] * ixx + S11 * ixy + sgb[3] * ixz,
-                          sgb[5] * ixy + S11 * iyy + sgb[3] * iyz, sgb[5] * ixz + S11 * iyz + sgb[3] * izz,
-                          sgb[4] * ixx + sgb[3] * ixy + S22 * ixz, sgb[4] * ixy + sgb[3] * iyy + S22 * iyz,
-                          sgb[4] * ixz + sgb[3] * iyz + S22 * izz};
-    const double Vj = A.vol_n[A.col[slot]];
-    if (P.force_mode == ULPPM_FORCE_EQ51) {
-      // Eq. 51 as printed: T_ij = varpi (sigma_ij + Sr s 1) K_ij^{-1} zeta_ij.
-      const double zx = xj0 - xi0, zy = xj1 - xi1, zz = xj2 - xi2;
-      Tout[0][slot] = (TS)(varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz));
-      Tout[1][slot] = (TS)(varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz));
-      Tout[2][slot] = (TS)(varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz));
-    } else {
-      const double wj = Vj / Vh;
-      MRec<Acc> r{};
-#pragma unroll
-      for (int q = 0; q < 9; ++q) r.v[q] = (Acc)(wj * SK[q]);
-      sM[m] = r;
-    }
-    // point history: volume-weighted mean of the bond states
-#pragma unroll
-    for (int k = 0; k < 6; ++k) hs[k] += Vj * sgb[k];
-    hpc += Vj * pcb;
-    hw += Vj;
-  }
-  if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
-    // Force state of bond (i,k): the sub-horizon force state of every
-    // sub-horizon S_ij holding k, evaluated on bond ik (Eqs. 27, 31), summed
-    // as in the double integral of Eq. 35.  Membership is symmetric, so lane
-    // k reads row k of the bit matrix written in the first pass.
-    __syncthreads();
-    for (int m = tid; m < nf; m += kBondThreads) {
-      Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0, a8 = 0;
-      for (int j0 = 0; j0 < nf; j0 += 64) {
-        unsigned long long word = sb[(size_t)m * nw + (j0 >> 6)];
-        const int jn = nf - j0 < 64 ? nf - j0 : 64;
-        for (int jj = 0; jj < jn; ++jj) {
-          const Acc w = (word >> jj) & 1ull ? (Acc)1 : (Acc)0;
-          const MRec<Acc> r = sM[j0 + jj];
-          a0 += w * r.v[0]; a1 += w * r.v[1]; a2 += w * r.v[2];
-          a3 += w * r.v[3]; a4 += w * r.v[4]; a5 += w * r.v[5];
-          a6 += w * r.v[6]; a7 += w * r.v[7]; a8 += w * r.v[8];
-        }
-      }
-      const Quad<Acc> zm = sZ[m];
-      const Acc zx = zm.v[0], zy = zm.v[1], zz = zm.v[2];
-      const int64_t slot = b0 + m;
-      Tout[0][slot] = (TS)(a0 * zx + a1 * zy + a2 * zz);
-      Tout[1][slot] = (TS)(a3 * zx + a4 * zy + a5 * zz);
-      Tout[2][slot] = (TS)(a6 * zx + a7 * zy + a8 * zz);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) hs[k] = wave_sum(hs[k]);
-  hpc = wave_sum(hpc);
-  hw = wave_sum(hw);
-  n_deg = wave_sum_i(n_deg);
-  n_pl = wave_sum_i(n_pl);
-  n_nc = wave_sum_i(n_nc);
-  n_trip = wave_sum_i(n_trip);
-  mx = wave_max_i(mx);
-  __syncthreads();   // red[] is reused
-  if (lane == 0) {
-    for (int k = 0; k < 6; ++k) red[wid][k] = hs[k];
-    red[wid][6] = hpc;
-    red[wid][7] = hw;
-    redi[wid][0] = n_deg; redi[wid][1] = n_pl; redi[wid][2] = n_nc; redi[wid][3] = n_trip;
-    red[wid][8] = (double)mx;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double W = 0.0, hsum[7] = {0, 0, 0, 0, 0, 0, 0};
-    long long d = 0, pl = 0, nc = 0, tr = 0, m2 = 0;
-    for (int w = 0; w < kBondWaves; ++w) {
-      W += red[w][7];
-      for (int k = 0; k < 7; ++k) hsum[k] += red[w][k];
-      d += redi[w][0]; pl += redi[w][1]; nc += redi[w][2]; tr += redi[w][3];
-      m2 = m2 > (long long)red[w][8] ? m2 : (long long)red[w][8];
-    }
-    if (W > 0.0) {
-      for (int k = 0; k < 6; ++k) A.sig_out[k][i] = hsum[k] / W;
-      A.pc_out[i] = hsum[6] / W;
-    } else {
-      for (int k = 0; k < 6; ++k) A.sig_out[k][i] = sig_i[k];
-      A.pc_out[i] = pc_i;
-    }
-    if (d) ctr_add(A.ctr, C_DEGEN, (unsigned long long)d);
-    if (pl) ctr_add(A.ctr, C_PLASTIC, (unsigned long long)pl);
-    if (nc) ctr_add(A.ctr, C_NOCONV, (unsigned long long)nc);
-    ctr_add(A.ctr, C_TRIPLES, (unsigned long long)tr);
-    ctr_add(A.ctr, C_TESTS, (unsigned long long)((long long)nf * nf));
-    if (m2) ctr_max(A.ctr, C_MAXNEWTON, (unsigned long long)m2);
-  }
-}
-
 // ------------------------------------------------------ point kinematics --
+// One 64-byte record per point for the bond pass's gathers of neighbour
+// data: x (3), V^n, v_half (3), 0.
+__global__ void k_pack(int64_t n, const double* __restrict__ x, const double* __restrict__ vh,
+                       const double* __restrict__ vol_n, double* __restrict__ xv) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double4* r = reinterpret_cast<double4*>(xv + 8 * i);
+    r[0] = make_double4(x[i], x[n + i], x[2 * n + i], vol_n[i]);
+    r[1] = make_double4(vh[i], vh[n + i], vh[2 * n + i], 0.0);
+  }
+}
+
 // Point kinematics of the step (Eqs. 5, 8, 15-17, 48), one wave per point:
 // the full-horizon shape tensor K_i, velocity-gradient sum N_i and family
 // volume V_H in FP64, then lane 0 updates J, V, phi, S_r and the mass and
@@ -1339,9 +1097,11 @@ __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
     double Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0.0;
     for (int64_t s = b0 + lane; s < b1; s += kWave) {
       const int32_t k = A.col[s];
-      const double z0 = A.x[k] - xi0, z1 = A.x[n + k] - xi1, z2 = A.x[2 * n + k] - xi2;
-      const double y0 = A.vh[k] - vi0, y1 = A.vh[n + k] - vi1, y2 = A.vh[2 * n + k] - vi2;
-      const double V = A.vol_n[k];
+      const double4 pa = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k];
+      const double4 pb = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k + 1];
+      const double z0 = pa.x - xi0, z1 = pa.y - xi1, z2 = pa.z - xi2;
+      const double y0 = pb.x - vi0, y1 = pb.y - vi1, y2 = pb.z - vi2;
+      const double V = pa.w;
       const double w0 = V * z0, w1 = V * z1, w2 = V * z2;
       Kp[0] += w0 * z0; Kp[1] += w1 * z1; Kp[2] += w2 * z2;
       Kp[3] += w1 * z2; Kp[4] += w0 * z2; Kp[5] += w0 * z1;
@@ -1473,7 +1233,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
   TS** const Tout = reinterpret_cast<TS**>(A.T);
   __shared__ double s_d2;
   __shared__ double red[kBondWaves][24];
-  __shared__ long long redi[kBondWaves][4];
+  __shared__ int redi[kBondWaves][4];
 
   const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
   const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
@@ -1491,10 +1251,11 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
   // and ydot_ik for the feature matrix.
   for (int m = tid; m < nf; m += kBondThreads) {
     const int32_t k = A.col[b0 + m];
-    const double xk0 = A.x[k], xk1 = A.x[n + k], xk2 = A.x[2 * n + k];
+    const double4 pa = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k];
+    const double4 pb = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k + 1];
+    const double xk0 = pa.x, xk1 = pa.y, xk2 = pa.z, Vk = pa.w;
     const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
-    const double y0 = A.vh[k] - vi0, y1 = A.vh[n + k] - vi1, y2 = A.vh[2 * n + k] - vi2;
-    const double Vk = A.vol_n[k];
+    const double y0 = pb.x - vi0, y1 = pb.y - vi1, y2 = pb.z - vi2;
     sX[m] = Quad<double>{{xk0, xk1, xk2, Vk}};
     Acc* rec = sR + 8 * (size_t)m;
     rec[0] = (Acc)z0; rec[1] = (Acc)z1; rec[2] = (Acc)z2; rec[3] = (Acc)Vk;
@@ -1573,7 +1334,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
 
   // ---- per-bond tail: one lane per bond (i,j)
   double hs[6] = {0, 0, 0, 0, 0, 0}, hpc = 0.0, hw = 0.0;
-  long long n_deg = 0, n_pl = 0, n_nc = 0, n_trip = 0, mx = 0;
+  int n_deg = 0, n_pl = 0, n_nc = 0, n_trip = 0, mx = 0;
   for (int m = tid; m < nf; m += kBondThreads) {
     Acc* kn = sKN + 16 * (size_t)m;
     int ns = 0;
@@ -2602,6 +2363,7 @@ struct ulppm_ctx {
   double* vol_n = nullptr;  // n
   double* pscr = nullptr;   // 12n point scratch for non-mutating passes
   double* pk = nullptr;     // 2n per-point values of the bond pass
+  double* xv = nullptr;     // 8n packed x, V^n, v_half per point (bond-pass gathers)
   int32_t* cellid = nullptr;
   int32_t* cnt = nullptr;
   int64_t* row = nullptr;   // n+1
@@ -2780,11 +2542,7 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
 }
 
 size_t bond_lds(int max_f, bool mixed) {
-#if ULPPM_BOND_MFMA
   return mixed ? bond_mx_lds_bytes<float>(max_f) : bond_mx_lds_bytes<double>(max_f);
-#else
-  return mixed ? bond_lds_bytes<float>(max_f) : bond_lds_bytes<double>(max_f);
-#endif
 }
 
 // Algorithm 1 (bond pass) into outputs; mode: step (state outputs) or not.
@@ -2820,20 +2578,15 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   A.max_f = ctx->max_f;
   A.ctr = ctx->ctr;
   A.pk = ctx->pk;
+  A.xv = ctx->xv;
   DevParams P = dev_params(p);
   const size_t lds = bond_lds(ctx->max_f, mixed);
-#if ULPPM_BOND_MFMA
+  k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
   k_point_kin<<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
   if (mixed)
     k_bond_mx<float><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
   else
     k_bond_mx<double><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
-#else
-  if (mixed)
-    k_bond<float><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
-  else
-    k_bond<double><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
-#endif
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
@@ -3118,6 +2871,7 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   A((void**)&ctx->vol_n, sizeof(double) * n);
   A((void**)&ctx->pscr, sizeof(double) * 12 * n);
   A((void**)&ctx->pk, sizeof(double) * 2 * n);
+  A((void**)&ctx->xv, sizeof(double) * 8 * n);
   A((void**)&ctx->cellid, sizeof(int32_t) * n);
   A((void**)&ctx->cnt, sizeof(int32_t) * n);
   A((void**)&ctx->row, sizeof(int64_t) * (n + 1));
@@ -3155,17 +2909,10 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
     return ULPPM_E_HIP;
   }
   // the bond kernel's dynamic LDS may exceed the default cap for large max_family
-#if ULPPM_BOND_MFMA
   (void)hipFuncSetAttribute((const void*)k_bond_mx<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bond_lds(max_family, false));
   (void)hipFuncSetAttribute((const void*)k_bond_mx<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bond_lds(max_family, true));
-#else
-  (void)hipFuncSetAttribute((const void*)k_bond<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)bond_lds(max_family, false));
-  (void)hipFuncSetAttribute((const void*)k_bond<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)bond_lds(max_family, true));
-#endif
   if (hipGetLastError() != hipSuccess) {
     ulppm_destroy(ctx);
     return ULPPM_E_HIP;
@@ -3178,7 +2925,7 @@ int ulppm_destroy(ulppm_ctx* ctx) {
   if (!ctx) return ULPPM_E_ARG;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
-  void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->pk, ctx->cellid, ctx->cnt, ctx->row, ctx->cand,
+  void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->pk, ctx->xv, ctx->cellid, ctx->cnt, ctx->row, ctx->cand,
                   ctx->ccnt, ctx->crev, ctx->posmap, ctx->xref, ctx->gate,
                   ctx->ccount, ctx->ccursor, ctx->cstart, ctx->cpts, ctx->col, ctx->rev, ctx->T,
                   ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->ctr_sum, ctx->E, ctx->adj,
