@@ -110,8 +110,9 @@ typedef struct {
   int64_t timed_steps;          /* steps covered by the phase timings (p->timing) */
   double t_predict_ms;          /* summed HIP-event durations per phase over timed steps */
   double t_family_ms;
-  double t_bond_ms;
+  double t_bond_ms;             /* the bond kernel alone */
   double t_gather_ms;
+  double t_kin_ms;              /* point kinematics before the bond kernel */
 } ulppm_report;
 
 /* Create a context for up to n_points points and max_family members per family

@@ -27,6 +27,7 @@
 // create; the state lives in caller-owned SoA device arrays.
 
 #include <hip/hip_runtime.h>
+#include <functional>
 
 #include <cmath>
 #include <cstdint>
@@ -64,7 +65,7 @@ enum Ctr {
 constexpr int kStripes = 256;       // each device counter is striped over this many addresses
 constexpr int kTimedSteps = 256;    // steps per call covered by phase timings
 constexpr double kSkin = 0.1;       // candidate-list skin, as a fraction of delta
-constexpr int kPhases = 4;          // predict, family, bond, gather
+constexpr int kPhases = 5;          // predict, family, bond, gather, point kinematics
 
 struct DevParams {
   double delta, d2;
@@ -2546,7 +2547,9 @@ size_t bond_lds(int max_f, bool mixed) {
 }
 
 // Algorithm 1 (bond pass) into outputs; mode: step (state outputs) or not.
-int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, double dt_inc, bool commit) {
+// mark(0) / mark(1) bracket the point-kinematics kernels when timing.
+int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, double dt_inc, bool commit,
+              const std::function<void(int)>& mark = nullptr) {
   const int64_t n = S->n;
   BondArgs A;
   A.n = n;
@@ -2580,9 +2583,11 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   A.pk = ctx->pk;
   A.xv = ctx->xv;
   DevParams P = dev_params(p);
+  if (mark) mark(0);
   const size_t lds = bond_lds(ctx->max_f, mixed);
   k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
   k_point_kin<<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
+  if (mark) mark(1);
   if (mixed)
     k_bond_mx<float><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
   else
@@ -2667,13 +2672,13 @@ void fill_report(ulppm_ctx* ctx, int64_t n, ulppm_report* rep, int64_t steps) {
   rep->steps = steps;
   rep->n_bond_updates = (int64_t)ctx->h_ctr[C_BONDSUM];
   rep->timed_steps = 0;
-  rep->t_predict_ms = rep->t_family_ms = rep->t_bond_ms = rep->t_gather_ms = 0.0;
+  rep->t_predict_ms = rep->t_family_ms = rep->t_bond_ms = rep->t_gather_ms = rep->t_kin_ms = 0.0;
 }
 
 // Sum the phase durations of the timed steps of the last ulppm_step call.
 void add_timings(ulppm_ctx* ctx, int64_t timed, ulppm_report* rep) {
   if (!rep || timed <= 0) return;
-  double t[kPhases] = {0, 0, 0, 0};
+  double t[kPhases] = {0, 0, 0, 0, 0};
   for (int64_t k = 0; k < timed; ++k)
     for (int ph = 0; ph < kPhases; ++ph) {
       float ms = 0.f;
@@ -2684,6 +2689,7 @@ void add_timings(ulppm_ctx* ctx, int64_t timed, ulppm_report* rep) {
   rep->t_family_ms = t[1];
   rep->t_bond_ms = t[2];
   rep->t_gather_ms = t[3];
+  rep->t_kin_ms = t[4];
 }
 
 }  // namespace
@@ -3262,8 +3268,13 @@ int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_
     mark(k, 1, 0);
     if ((rc = build_families(ctx, n, p->delta, k == 0))) return rc;
     mark(k, 1, 1);
-    mark(k, 2, 0);
-    if ((rc = bond_pass(ctx, S, p, p->dt, true))) return rc;
+    mark(k, 4, 0);
+    if ((rc = bond_pass(ctx, S, p, p->dt, true, [&](int b) {
+           if (b == 0) return;
+           mark(k, 4, 1);
+           mark(k, 2, 0);
+         })))
+      return rc;
     mark(k, 2, 1);
     mark(k, 3, 0);
     if ((rc = gather_pass(ctx, S, p, G_STEP, S->mass, nullptr))) return rc;

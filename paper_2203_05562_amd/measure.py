@@ -11,6 +11,10 @@ one JSON line.
         Checkpointed forward and backward of the differentiable column
         (objective: runout + settlement): time per forward step, per reverse
         step and their ratio.
+
+    python -m paper_2203_05562_amd.measure copy [--mib 1024]
+        One device-to-device copy of a known size (a float64 tensor), the
+        reference that scales the HBM byte counters of a profiler run.
 """
 import argparse
 import json
@@ -108,11 +112,21 @@ def main(argv=None):
     b.add_argument("--steps", type=int, default=50)
     b.add_argument("--every", type=int, default=25)
     b.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    c = sub.add_parser("copy")
+    c.add_argument("--mib", type=int, default=1024)
     args = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available(), "measurements need a GPU"
     torch.cuda.set_device(0)
-    if args.what == "mixed-error":
+    if args.what == "copy":
+        nbytes = args.mib << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out = dict(kind="copy", bytes_read=nbytes, bytes_written=nbytes)
+    elif args.what == "mixed-error":
         out = mixed_error(args.config, [int(x) for x in args.at.split(",")])
     else:
         out = adjoint_cost(args.config, args.steps, args.every, args.precision)
