@@ -868,8 +868,9 @@ __host__ __device__ __forceinline__ void tail_kinematics(const double* K, const 
   F.de[3] = dt * 0.5 * (L[5] + L[7]); F.de[4] = dt * 0.5 * (L[2] + L[6]); F.de[5] = dt * 0.5 * (L[1] + L[3]);
 }
 
-__host__ __device__ void tail_forward(const DevParams& P, const double* K, const double* N, const double* sig,
-                                      double pc, double Srs, double w, double dt, TailFwd& F) {
+// Pn: apparent pre-consolidation of pc (Eq. 45).
+__host__ __device__ void tail_forward_pn(const DevParams& P, const double* K, const double* N, const double* sig,
+                                         double pc, double Pn, double Srs, double w, double dt, TailFwd& F) {
   tail_kinematics(K, N, dt, F);
   double KiF[9];
   sym_full(F.Ki, KiF);
@@ -878,13 +879,18 @@ __host__ __device__ void tail_forward(const DevParams& P, const double* K, const
     F.pc = pc;
     F.branch = 0;
   } else {
-    F.branch = return_map(P, dt, sig, pc, F.de, F.sg, &F.pc);
+    F.branch = return_map_pn(P, dt, sig, pc, Pn, F.de, F.sg, &F.pc);
   }
   double Q[6] = {F.sg[0] + Srs, F.sg[1] + Srs, F.sg[2] + Srs, F.sg[3], F.sg[4], F.sg[5]};
   double QF[9], SK[9];
   sym_full(Q, QF);
   mat3_mul(QF, KiF, SK);
   for (int k = 0; k < 9; ++k) F.M[k] = w * SK[k];
+}
+
+__host__ __device__ void tail_forward(const DevParams& P, const double* K, const double* N, const double* sig,
+                                      double pc, double Srs, double w, double dt, TailFwd& F) {
+  tail_forward_pn(P, K, N, sig, pc, apparent_pc(P, pc), Srs, w, dt, F);
 }
 
 // Adjoint of the return map at fixed branch: given the adjoints of the
@@ -1566,6 +1572,7 @@ struct AdjArgs {
   const double* x;        // x^{n+1} (3n)
   const double* vh;       // v_half (3n)
   const double* vol_n;    // V^n
+  const double* xv;       // 8n packed x^{n+1}, V^n, v_half
   const double* J;        // state n
   const double* phi;
   const double* s;
@@ -1660,7 +1667,11 @@ __global__ __launch_bounds__(256) void k_adj_point1(int64_t n, const uint8_t* __
 }
 
 // One workgroup per point i: re-run the bond pass of i, then reverse it.
+// The masked sums of the re-run pass 1 and of the reverse of the sums are
+// membership-matrix products on the matrix cores (16x16x4 FP64, the lane
+// layout of the forward bond kernel); the 9-column sums stay on the VALU.
 __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(AdjArgs A, DevParams P) {
+  using MM = Mma<double>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t i = xcd_point(blockIdx.x, A.per);
   if (i >= A.n) {                                 // idle block: its parameter partials are zero
@@ -1668,6 +1679,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     return;
   }
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int r16 = lane & 15, q4 = lane >> 4;
   const int mf = A.max_f;
   const int64_t n = A.n;
   const int64_t b0 = A.row[i];
@@ -1676,14 +1688,16 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);   // x_k (pass 1), then Tbar_ik
   Quad<double>* sTb = sX;
   Quad<double>* sZ = sX + mf;                                     // zeta_ik, V_k
-  Quad<double>* sY = sZ + mf;                                     // ydot_ik
+  Quad<double>* sY = sZ + mf;                                     // ydot_ik, 1
   Quad<double>* sZb = sY + mf;                                    // zeta_bar_ik, slot Vbar_k
   MRec<double>* sM = reinterpret_cast<MRec<double>*>(sZb + mf);   // M_j
   double* sKN = reinterpret_cast<double*>(sM + mf);               // 16 per bond: K(6) N(9) active | Ks(6) Nb(9)
   double* sR = sKN + 16 * (size_t)mf;                             // 8 per bond: sigma_ij (6), p_c,ij, branch
   unsigned long long* sb = reinterpret_cast<unsigned long long*>(sR + 8 * (size_t)mf);
+  unsigned short* sq = reinterpret_cast<unsigned short*>(sb);     // membership quarters, as the forward
   __shared__ double red[kBondWaves][32];
   __shared__ double pt[32];
+  __shared__ double s_Pn;
 
   const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
   const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
@@ -1694,13 +1708,14 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   double Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0.0;
   for (int m = tid; m < nf; m += kBondThreads) {
     const int32_t k = A.col[b0 + m];
-    const double xk0 = A.x[k], xk1 = A.x[n + k], xk2 = A.x[2 * n + k];
+    const double4 pa = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k];
+    const double4 pb = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k + 1];
+    const double xk0 = pa.x, xk1 = pa.y, xk2 = pa.z, V = pa.w;
     const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
-    const double y0 = A.vh[k] - vi0, y1 = A.vh[n + k] - vi1, y2 = A.vh[2 * n + k] - vi2;
-    const double V = A.vol_n[k];
+    const double y0 = pb.x - vi0, y1 = pb.y - vi1, y2 = pb.z - vi2;
     sX[m] = Quad<double>{{xk0, xk1, xk2, 0.0}};
     sZ[m] = Quad<double>{{z0, z1, z2, V}};
-    sY[m] = Quad<double>{{y0, y1, y2, 0.0}};
+    sY[m] = Quad<double>{{y0, y1, y2, 1.0}};
     sZb[m] = Quad<double>{{0.0, 0.0, 0.0, 0.0}};
     const double w0 = V * z0, w1 = V * z1, w2 = V * z2;
     Kp[0] += w0 * z0; Kp[1] += w1 * z1; Kp[2] += w2 * z2;
@@ -1726,6 +1741,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
       pt[k] = a;                                   // K_i (6), N_i (9), Vh
     }
   }
+  if (tid == kWave) s_Pn = apparent_pc(P, A.pc[i]);   // Eq. 45, shared by the bonds of i
   __syncthreads();
   const double Vh = pt[15];
   const double Sr1 = A.Sr1[i], s_i = A.s[i];
@@ -1736,45 +1752,86 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   const double d2 = P.d2;
   const double dt = A.dt;
 
-  // ---- pass 1 (re-run): sub-horizon sums, membership rows, tail forward
+  const double Pn_i = s_Pn;
+  const int ntile = (nf + 15) >> 4;
+  const int nks = (nf + 3) >> 2;
+  const int nblk = (nks + 15) >> 4;
+
+  // ---- pass 1 (re-run): [K_j | N_j | count] = B [V zeta zeta^T | V ydot zeta^T | 1]
+  {
+    // feature f of member k is V a b from {zeta0, zeta1, zeta2, V, ydot0, ydot1, ydot2, 1}
+    // (sZ and sY are adjacent); feature 15 counts the members
+    const int fa = feat_a(r16), fb = feat_b(r16), fv = r16 == 15 ? 7 : 3;
+    const double* rz = &sZ[0].v[0];
+    const int oa = fa < 4 ? fa : 4 * mf + fa - 4, ob = fb < 4 ? fb : 4 * mf + fb - 4,
+              ov = fv < 4 ? fv : 4 * mf + fv - 4;
+    for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
+      double xj[kTileBatch][3];
+      bool jv[kTileBatch];
+      int jrow[kTileBatch];
+      v4d acc[kTileBatch];
+      unsigned piece[kTileBatch];
+#pragma unroll
+      for (int b = 0; b < kTileBatch; ++b) {
+        jrow[b] = (t0 + kBondWaves * b) * 16 + r16;
+        jv[b] = jrow[b] < nf;
+        const Quad<double> q = sX[jv[b] ? jrow[b] : 0];
+        xj[b][0] = q.v[0]; xj[b][1] = q.v[1]; xj[b][2] = q.v[2];
+        acc[b] = v4d{0, 0, 0, 0};
+        piece[b] = 0u;
+      }
+      for (int ks = 0; ks < nks; ++ks) {
+        const int kk0 = 4 * ks + q4;
+        const bool kv = kk0 < nf;
+        const int kk = kv ? kk0 : 0;
+        const Quad<double> xk = sX[kk];
+        const double fvv = rz[4 * kk + oa] * rz[4 * kk + ob] * rz[4 * kk + ov];
+        const double bval = kv ? fvv : 0.0;
+        const unsigned sbit = 1u << (ks & 15);
+#pragma unroll
+        for (int b = 0; b < kTileBatch; ++b) {
+          const bool in = within(xj[b][0], xj[b][1], xj[b][2], xk.v[0], xk.v[1], xk.v[2], d2) & kv & jv[b];
+          piece[b] |= in ? sbit : 0u;
+          acc[b] = MM::run(in ? 1.0 : 0.0, bval, acc[b]);
+        }
+        if ((ks & 15) == 15 || ks == nks - 1) {
+#pragma unroll
+          for (int b = 0; b < kTileBatch; ++b) {
+            if (jv[b]) sq[((size_t)jrow[b] * nw + (ks >> 4)) * 4 + q4] = (unsigned short)piece[b];
+            piece[b] = 0u;
+          }
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < kTileBatch; ++b) {
+        const int t = t0 + kBondWaves * b;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = t * 16 + MM::row(q4, r);
+          if (j < nf) sKN[16 * (size_t)j + r16] = acc[b][r];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- tail forward, one lane per bond
   double Wp = 0.0;
   for (int m = tid; m < nf; m += kBondThreads) {
-    const Quad<double> xj = sX[m];
-    double Kq[6] = {0, 0, 0, 0, 0, 0}, Nq[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    int ns = 0;
-    for (int t0 = 0; t0 < nf; t0 += 64) {
-      const int tn = nf - t0 < 64 ? nf - t0 : 64;
-      unsigned long long word = 0ull;
-      for (int u = 0; u < tn; ++u) {
-        const int t = t0 + u;
-        const Quad<double> xk = sX[t];
-        const Quad<double> zk = sZ[t];
-        const Quad<double> yk = sY[t];
-        const bool in = within(xj.v[0], xj.v[1], xj.v[2], xk.v[0], xk.v[1], xk.v[2], d2);
-        const double w = in ? zk.v[3] : 0.0;
-        ns += in ? 1 : 0;
-        word |= (unsigned long long)in << u;
-        const double w0 = w * zk.v[0], w1 = w * zk.v[1], w2 = w * zk.v[2];
-        Kq[0] += w0 * zk.v[0]; Kq[1] += w1 * zk.v[1]; Kq[2] += w2 * zk.v[2];
-        Kq[3] += w1 * zk.v[2]; Kq[4] += w0 * zk.v[2]; Kq[5] += w0 * zk.v[1];
-        Nq[0] += yk.v[0] * w0; Nq[1] += yk.v[0] * w1; Nq[2] += yk.v[0] * w2;
-        Nq[3] += yk.v[1] * w0; Nq[4] += yk.v[1] * w1; Nq[5] += yk.v[1] * w2;
-        Nq[6] += yk.v[2] * w0; Nq[7] += yk.v[2] * w1; Nq[8] += yk.v[2] * w2;
-      }
-      sb[(size_t)m * nw + (t0 >> 6)] = word;
-    }
     double* kn = sKN + 16 * (size_t)m;
+    double Kq[6], Nq[9];
+    for (int k = 0; k < 6; ++k) Kq[k] = kn[k];
+    for (int k = 0; k < 9; ++k) Nq[k] = kn[6 + k];
+    const int ns = (int)kn[15];
     const double dK = det3s(Kq[0], Kq[1], Kq[2], Kq[3], Kq[4], Kq[5]);
     const double tk = (Kq[0] + Kq[1] + Kq[2]) / 3.0;
     const bool active = ns >= 3 && dK > 1e-12 * tk * tk * tk;
-    for (int k = 0; k < 6; ++k) kn[k] = Kq[k];
-    for (int k = 0; k < 9; ++k) kn[6 + k] = Nq[k];
     kn[15] = active ? 1.0 : 0.0;
     MRec<double> r{};
     if (active) {
       const double Vj = sZ[m].v[3];
       TailFwd F;
-      tail_forward(P, Kq, Nq, sig_i, pc_i, Srs, Vj / Vh, dt, F);
+      tail_forward_pn(P, Kq, Nq, sig_i, pc_i, Pn_i, Srs, Vj / Vh, dt, F);
       for (int q = 0; q < 9; ++q) r.v[q] = F.M[q];
       double* rr = sR + 8 * (size_t)m;
       for (int k = 0; k < 6; ++k) rr[k] = F.sg[k];
@@ -1796,14 +1853,15 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   double ownV = 0.0;
   for (int m = tid; m < nf; m += kBondThreads) {
     double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int j0 = 0; j0 < nf; j0 += 64) {
-      const unsigned long long word = sb[(size_t)m * nw + (j0 >> 6)];
-      const int jn = nf - j0 < 64 ? nf - j0 : 64;
-      for (int jj = 0; jj < jn; ++jj) {
-        const double w = (word >> jj) & 1ull ? 1.0 : 0.0;
-        const MRec<double> r = sM[j0 + jj];
-        for (int q = 0; q < 9; ++q) a[q] += w * r.v[q];
-      }
+    unsigned long long word = 0ull;
+    MRec<double> r = sM[0];                          // M_j, loaded one member ahead
+    for (int j = 0; j < nf; ++j) {
+      if ((j & 63) == 0) word = sb[(size_t)m * nw + (j >> 6)];
+      const MRec<double> rn = sM[j + 1 < nf ? j + 1 : j];
+      const int jj = j & 63;
+      const double w = (word >> (16 * (jj & 3) + (jj >> 2))) & 1ull ? 1.0 : 0.0;
+      for (int q = 0; q < 9; ++q) a[q] += w * r.v[q];
+      r = rn;
     }
     const int64_t slot = b0 + m;
     const int32_t k = A.col[slot];
@@ -1843,20 +1901,22 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     if (active) {
       // Mbar_j = sum_k B_jk Tbar_ik zeta_ik^T
       double mb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      for (int t0 = 0; t0 < nf; t0 += 64) {
-        const unsigned long long word = sb[(size_t)m * nw + (t0 >> 6)];
-        const int tn = nf - t0 < 64 ? nf - t0 : 64;
-        for (int u = 0; u < tn; ++u) {
-          const double w = (word >> u) & 1ull ? 1.0 : 0.0;
-          const Quad<double> tbk = sTb[t0 + u];
-          const Quad<double> zk = sZ[t0 + u];
-          for (int r = 0; r < 3; ++r) {
-            const double wt = w * tbk.v[r];
-            mb[3 * r] += wt * zk.v[0];
-            mb[3 * r + 1] += wt * zk.v[1];
-            mb[3 * r + 2] += wt * zk.v[2];
-          }
+      unsigned long long word = 0ull;
+      Quad<double> tbk = sTb[0], zk = sZ[0];         // loaded one member ahead
+      for (int t = 0; t < nf; ++t) {
+        if ((t & 63) == 0) word = sb[(size_t)m * nw + (t >> 6)];
+        const int tn = t + 1 < nf ? t + 1 : t;
+        const Quad<double> tbn = sTb[tn], zn = sZ[tn];
+        const int u = t & 63;
+        const double w = (word >> (16 * (u & 3) + (u >> 2))) & 1ull ? 1.0 : 0.0;
+        for (int r = 0; r < 3; ++r) {
+          const double wt = w * tbk.v[r];
+          mb[3 * r] += wt * zk.v[0];
+          mb[3 * r + 1] += wt * zk.v[1];
+          mb[3 * r + 2] += wt * zk.v[2];
         }
+        tbk = tbn;
+        zk = zn;
       }
       double Kq[6], Nq[9];
       for (int k = 0; k < 6; ++k) Kq[k] = kn[k];
@@ -1972,23 +2032,59 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   }
   __syncthreads();
 
-  // ---- reverse of the sums (R3): G_k = Ks_i + sum_j B_kj Ks_j, H_k = Nb_i + sum_j B_kj Nb_j
+  // ---- reverse of the sums (R3): G_k = Ks_i + sum_j B_kj Ks_j, H_k = Nb_i + sum_j B_kj Nb_j.
+  // The 15 columns [Ks_j | Nb_j] run on the matrix cores; rows k land in
+  // sM (columns 0-9) and sR (columns 10-14), both free by now.
+  for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
+    v4d acc[kTileBatch];
+    unsigned piece[kTileBatch];
+    int krow[kTileBatch];
+#pragma unroll
+    for (int b = 0; b < kTileBatch; ++b) {
+      acc[b] = v4d{0, 0, 0, 0};
+      piece[b] = 0u;
+      krow[b] = (t0 + kBondWaves * b) * 16 + r16;
+    }
+    for (int js = 0; js < nks; ++js) {
+      const int j = 4 * js + q4;
+      const bool ok = j < nf && r16 < 15;
+      const double kv = sKN[16 * (size_t)(ok ? j : 0) + (r16 < 15 ? r16 : 0)];
+      const double bval = ok ? kv : 0.0;
+      const int s = js & 15;
+      if (s == 0) {
+#pragma unroll
+        for (int b = 0; b < kTileBatch; ++b) {
+          const bool rv = krow[b] < nf;
+          const unsigned pw = sq[((size_t)(rv ? krow[b] : 0) * nw + (js >> 4)) * 4 + q4];
+          piece[b] = rv ? pw : 0u;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < kTileBatch; ++b) acc[b] = MM::run((piece[b] >> s) & 1u ? 1.0 : 0.0, bval, acc[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < kTileBatch; ++b) {
+      const int t = t0 + kBondWaves * b;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int kr = t * 16 + MM::row(q4, r);
+        if (kr < nf && r16 < 15) {
+          if (r16 < 10) sM[kr].v[r16] = acc[b][r];
+          else sR[8 * (size_t)kr + r16 - 10] = acc[b][r];
+        }
+      }
+    }
+  }
+  __syncthreads();
   double ox[3] = {0, 0, 0}, oy[3] = {0, 0, 0};
   const double Vhb = pt[31];
   for (int m = tid; m < nf; m += kBondThreads) {
     double G[6], H[9];
-    for (int k = 0; k < 6; ++k) G[k] = pt[16 + k];
-    for (int k = 0; k < 9; ++k) H[k] = pt[22 + k];
-    for (int j0 = 0; j0 < nf; j0 += 64) {
-      const unsigned long long word = sb[(size_t)m * nw + (j0 >> 6)];
-      const int jn = nf - j0 < 64 ? nf - j0 : 64;
-      for (int jj = 0; jj < jn; ++jj) {
-        const double w = (word >> jj) & 1ull ? 1.0 : 0.0;
-        const double* kn = sKN + 16 * (size_t)(j0 + jj);
-        for (int k = 0; k < 6; ++k) G[k] += w * kn[k];
-        for (int k = 0; k < 9; ++k) H[k] += w * kn[6 + k];
-      }
-    }
+    const MRec<double> g10 = sM[m];
+    const double* g5 = sR + 8 * (size_t)m;
+    for (int k = 0; k < 6; ++k) G[k] = pt[16 + k] + g10.v[k];
+    for (int k = 0; k < 4; ++k) H[k] = pt[22 + k] + g10.v[6 + k];
+    for (int k = 0; k < 5; ++k) H[4 + k] = pt[26 + k] + g5[k];
     const Quad<double> zq = sZ[m];
     const Quad<double> yq = sY[m];
     const double z[3] = {zq.v[0], zq.v[1], zq.v[2]}, y[3] = {yq.v[0], yq.v[1], yq.v[2]};
@@ -3182,7 +3278,9 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
     // state n+1 given: positions, half-step velocities and families only
     k_adj_kin<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, *S1, P, ctx->x, ctx->vh, ctx->vol_n);
     HIPCHK(hipGetLastError());
-    if ((rc = build_families(ctx, n, p->delta, true))) return rc;
+    // the candidate lists are rebuilt only when a point has left half the
+    // skin since they were built (either direction in time)
+    if ((rc = build_families(ctx, n, p->delta, false))) return rc;
   } else if ((rc = adjoint_rerun(ctx, S, p, P, F))) {
     return rc;
   }
@@ -3209,7 +3307,7 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
   A.n = n;
   A.per = (n + 7) / 8;
   A.row = ctx->row; A.col = ctx->col; A.rev = ctx->rev;
-  A.x = ctx->x; A.vh = ctx->vh; A.vol_n = ctx->vol_n;
+  A.x = ctx->x; A.vh = ctx->vh; A.vol_n = ctx->vol_n; A.xv = ctx->xv;
   A.J = S->J; A.phi = S->phi; A.s = S->s;
   for (int k = 0; k < 6; ++k) { A.sig[k] = S->sig[k]; A.sig1[k] = F.sig[k]; A.sigb1[k] = adj1->sig[k]; }
   A.pc = S->pc;
@@ -3233,6 +3331,7 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
     return fail(ctx, ULPPM_E_CAPACITY, "adjoint: a family of " + std::to_string(A.max_f) +
                                            " members exceeds the workgroup's LDS");
   const unsigned grid = (unsigned)(8 * A.per);
+  k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
   k_adj_bond<<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   HIPCHK(hipGetLastError());
   k_adj_point2<<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->row, ctx->rev, S->fixed, own_x, own_vh, own_V,
