@@ -2472,6 +2472,8 @@ struct ulppm_ctx {
   int32_t* posmap = nullptr;  // n*max_c, slot of the candidate in the family row, or -1
   double* xref = nullptr;     // 3n positions at the last candidate build
   int32_t* gate = nullptr;    // 1: rebuild candidates in this step
+  int64_t built_n = -1;       // point count and horizon of the last candidate build
+  double built_delta = 0.0;
   // cells
   int32_t* ccount = nullptr;
   int32_t* ccursor = nullptr;
@@ -2595,10 +2597,15 @@ int scan_counts(ulppm_ctx* ctx, const int32_t* cnt, int64_t m, int64_t* out, con
 // point moved more than skin/2 since the last build); every step then
 // filters the candidates with the exact predicate, so the families are
 // exactly those of the current positions.  Then CSR offsets and rev[].
+// Candidate lists are rebuilt when forced, when the point count or horizon
+// changed since the last build, or when a point has left half the skin.
 int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
   const double skin = kSkin * delta;
   const double rc = delta + skin;
   const int32_t* gate = ctx->gate;
+  force = force || ctx->built_n != n || ctx->built_delta != delta;
+  ctx->built_n = n;
+  ctx->built_delta = delta;
   if (force) {
     k_fill<int32_t><<<1, 64, 0, ctx->stream>>>(ctx->gate, 1, 1);
   } else {
@@ -3365,7 +3372,7 @@ int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_
     HIPCHK(hipGetLastError());
     mark(k, 0, 1);
     mark(k, 1, 0);
-    if ((rc = build_families(ctx, n, p->delta, k == 0))) return rc;
+    if ((rc = build_families(ctx, n, p->delta, false))) return rc;
     mark(k, 1, 1);
     mark(k, 4, 0);
     if ((rc = bond_pass(ctx, S, p, p->dt, true, [&](int b) {
