@@ -56,8 +56,13 @@ enum { ULPPM_FP64 = 0, ULPPM_MIXED = 1 };
  *   that also updates the point history.
  * ULPPM_FORCE_EQ51: Eq. 51 as printed, T_ij = varpi_ij (sigma_ij + S_r s 1)
  *   K_ij^{-1} zeta_ij, the bond's own term only.  With history stored on the
- *   points this form is linearly unstable (flutter); kept for comparison. */
-enum { ULPPM_FORCE_CONJUGATE = 0, ULPPM_FORCE_EQ51 = 1 };
+ *   points this form is linearly unstable (flutter); kept for comparison.
+ * ULPPM_FORCE_STANDARD: the standard, unstabilised correspondence model of
+ *   Eqs. 12-14: one stress per point, updated from the full-horizon gradient
+ *   L_i, and T_ij = (sigma_i + S_r s 1) K_i^{-1} zeta_ij.  It has the
+ *   zero-energy modes the sub-horizons remove (Eqs. 20-21); kept as the
+ *   comparison model.  No sub-horizons are formed (n_tests = n_triples = 0). */
+enum { ULPPM_FORCE_CONJUGATE = 0, ULPPM_FORCE_EQ51 = 1, ULPPM_FORCE_STANDARD = 2 };
 
 /* Material and integration parameters, copied by value on every call. */
 typedef struct {

@@ -88,7 +88,8 @@ struct Params {             // mirrors OracleParams below, in scalar type R
   double dt;
   double newton_tol;
   int newton_maxit;
-  int force_mode;           // 0: conjugate force states (default), 1: Eq. 51 as printed
+  int force_mode;           // 0: conjugate force states (default), 1: Eq. 51 as printed,
+                            // 2: standard full-horizon correspondence (Eq. 14)
 };
 
 template <class R>
@@ -555,7 +556,7 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
   // gradient (Eq. 8) and the volume change of the step (Eq. 17 in updated
   // Lagrangian form: the increment F_D satisfies F_D^{-1} = I - dt L_i), then
   // porosity (Eq. 16), degree of saturation (Eq. 15) and mass (Eq. 48).
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : n_deg, n_pl, n_nc) reduction(max : maxit)
   for (int64_t i = 0; i < n; ++i) {
     R Ki[6] = {0, 0, 0, 0, 0, 0}, Ni[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t nfam = F.row[i + 1] - F.row[i];
@@ -577,8 +578,10 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
     sym_to_full(Ki, KF);
     R dK = det3(KF);
     double trk = val(Ki[0] + Ki[1] + Ki[2]) / 3.0;
-    if (nfam >= 3 && val(dK) > 1e-12 * trk * trk * trk) {
-      R Kinv[9], Li[9], B[9];
+    const bool full_ok = nfam >= 3 && val(dK) > 1e-12 * trk * trk * trk;
+    R Kinv[9], Li[9];
+    if (full_ok) {
+      R B[9];
       inv3(KF, dK, Kinv);
       matmul3(Ni, Kinv, Li);
       for (int k = 0; k < 9; ++k) B[k] = (k % 4 == 0 ? R(1.0) : R(0.0)) - dt_inc * Li[k];
@@ -590,6 +593,42 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
     O.phi_new[i] = 1.0 - (1.0 - S.phi[i]) / Jd;
     O.Sr_new[i] = swrc(m, O.J_new[i], O.phi_new[i], S.s[i]);
     O.mass_new[i] = (m.rho_s * (1.0 - O.phi_new[i]) + m.rho_w * O.Sr_new[i] * O.phi_new[i]) * O.vol_new[i];
+    if (P.force_mode == 2) {
+      // Standard correspondence (Eqs. 12-14): one stress per point, updated
+      // from the full-horizon gradient L_i, and force states
+      // T_ik = (sigma_i + S_r s 1) K_i^{-1} zeta_ik on every bond of i.
+      const R* sig_i = &S.sig[6 * i];
+      R sb[6], pcb;
+      if (full_ok && val(dt_inc) != 0.0) {
+        R deps[6] = {dt_inc * Li[0], dt_inc * Li[4], dt_inc * Li[8], dt_inc * 0.5 * (Li[5] + Li[7]),
+                     dt_inc * 0.5 * (Li[2] + Li[6]), dt_inc * 0.5 * (Li[1] + Li[3])};
+        int it = return_map(m, P, dt_inc, sig_i, S.pc[i], deps, sb, &pcb);
+        if (it < 0) { ++n_nc; it = P.newton_maxit; }
+        if (it > 0) ++n_pl;
+        if (it > maxit) maxit = it;
+      } else {
+        for (int k = 0; k < 6; ++k) sb[k] = sig_i[k];
+        pcb = S.pc[i];
+      }
+      for (int k = 0; k < 6; ++k) O.sig_new[6 * i + k] = sb[k];
+      O.pc_new[i] = pcb;
+      if (full_ok) {
+        R sF[9], SK[9];
+        sym_to_full(sb, sF);
+        R ps = O.Sr_new[i] * S.s[i];
+        for (int k = 0; k < 3; ++k) sF[4 * k] += ps;
+        matmul3(sF, Kinv, SK);
+        for (int64_t t = F.row[i]; t < F.row[i + 1]; ++t) {
+          const int64_t k = F.col[t];
+          R z[3];
+          for (int c = 0; c < 3; ++c) z[c] = x[3 * k + c] - x[3 * i + c];
+          for (int r = 0; r < 3; ++r)
+            O.T[3 * t + r] = SK[3 * r] * z[0] + SK[3 * r + 1] * z[1] + SK[3 * r + 2] * z[2];
+        }
+      } else {
+        n_deg += nfam;
+      }
+    }
   }
 
   // Loops 1-3 of Algorithm 1, bond part.  For each bond (i,j): the
@@ -600,7 +639,7 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
   // T = varpi (sigma - S_r p_w 1) K^{-1} zeta with p_w = -s (Eqs. 32, 51, 53).
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : n_deg, n_pl, n_nc, n_tests, n_trip) \
     reduction(max : maxit)
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t i = 0; i < (P.force_mode == 2 ? 0 : n); ++i) {
     const int64_t b0 = F.row[i], b1 = F.row[i + 1];
     R Vh = 0.0;
     for (int64_t s = b0; s < b1; ++s) Vh += S.vol[F.col[s]];

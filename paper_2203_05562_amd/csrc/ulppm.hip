@@ -1093,10 +1093,18 @@ __global__ void k_pack(int64_t n, const double* __restrict__ x, const double* __
 // every bond of i uses.  With geometry at n+1 the step's deformation
 // increment F_D satisfies F_D^{-1} = I - dt L_i (Eq. 17 in updated
 // Lagrangian form).
+//
+// In the standard correspondence mode (Eq. 14) the same wave also updates
+// the point's stress from L_i by the return map and writes the force states
+// T_ik = (sigma_i + S_r s 1) K_i^{-1} zeta_ik of all its bonds; the bond
+// kernel does not run.  TS: storage type of the force states.
+template <class TS>
 __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t n = A.n;
   const XcdWalk W = xcd_walk(n, 4);
+  const bool standard = P.force_mode == ULPPM_FORCE_STANDARD;
+  int c_deg = 0, c_pl = 0, c_nc = 0, c_mx = 0;          // standard mode, lane 0
   for (int64_t i = W.first; i < W.end; i += W.stride) {
     const int64_t b0 = A.row[i], b1 = A.row[i + 1];
     const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
@@ -1154,6 +1162,67 @@ __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
       A.pk[i] = apparent_pc(P, A.pc[i]);
       A.pk[n + i] = Vp > 0.0 ? 1.0 / Vp : 0.0;
     }
+    if (standard) {
+      // every lane holds the wave totals and forms the point update itself
+      const int nf = (int)(b1 - b0);
+      const double dK = det3s(Kp[0], Kp[1], Kp[2], Kp[3], Kp[4], Kp[5]);
+      const double tk = (Kp[0] + Kp[1] + Kp[2]) / 3.0;
+      const bool ok = nf >= 3 && dK > 1e-12 * tk * tk * tk;
+      double sg[6], pcn = A.pc[i], pco = pcn;
+      for (int k = 0; k < 6; ++k) sg[k] = A.sig[k][i];
+      double so[6] = {sg[0], sg[1], sg[2], sg[3], sg[4], sg[5]};
+      double Ki[6] = {0, 0, 0, 0, 0, 0};
+      if (ok) {
+        sym_inverse(Kp, Ki);
+        double KiF[9], L[9];
+        sym_full(Ki, KiF);
+        mat3_mul(Np, KiF, L);
+        const double h = A.dt_inc;
+        if (h != 0.0) {
+          const double de[6] = {h * L[0], h * L[4], h * L[8], h * 0.5 * (L[5] + L[7]), h * 0.5 * (L[2] + L[6]),
+                                h * 0.5 * (L[1] + L[3])};
+          int it = return_map(P, h, sg, pcn, de, so, &pco);
+          if (lane == 0) {
+            if (it < 0) { ++c_nc; it = P.newton_maxit; }
+            if (it > 0) ++c_pl;
+            c_mx = c_mx > it ? c_mx : it;
+          }
+        }
+      } else if (lane == 0) {
+        c_deg += nf;
+      }
+      if (lane == 0) {
+        for (int k = 0; k < 6; ++k) A.sig_out[k][i] = so[k];
+        A.pc_out[i] = pco;
+      }
+      // total stress sigma_i + S_r s 1 (Eq. 14 with p_w = -s) times K_i^{-1}
+      double SK[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      if (ok) {
+        const double ps = A.Sr_out[i] * A.s[i];
+        const double Q[6] = {so[0] + ps, so[1] + ps, so[2] + ps, so[3], so[4], so[5]};
+        double QF[9], KiF[9];
+        sym_full(Q, QF);
+        sym_full(Ki, KiF);
+        mat3_mul(QF, KiF, SK);
+      }
+      TS* T0 = reinterpret_cast<TS*>(A.T[0]);
+      TS* T1 = reinterpret_cast<TS*>(A.T[1]);
+      TS* T2 = reinterpret_cast<TS*>(A.T[2]);
+      for (int64_t s = b0 + lane; s < b1; s += kWave) {
+        const int32_t k = A.col[s];
+        const double4 pa = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k];
+        const double z0 = pa.x - xi0, z1 = pa.y - xi1, z2 = pa.z - xi2;
+        T0[s] = (TS)(SK[0] * z0 + SK[1] * z1 + SK[2] * z2);
+        T1[s] = (TS)(SK[3] * z0 + SK[4] * z1 + SK[5] * z2);
+        T2[s] = (TS)(SK[6] * z0 + SK[7] * z1 + SK[8] * z2);
+      }
+    }
+  }
+  if (standard && lane == 0) {
+    if (c_deg) ctr_add(A.ctr, C_DEGEN, (unsigned long long)c_deg);
+    if (c_pl) ctr_add(A.ctr, C_PLASTIC, (unsigned long long)c_pl);
+    if (c_nc) ctr_add(A.ctr, C_NOCONV, (unsigned long long)c_nc);
+    if (c_mx) ctr_max(A.ctr, C_MAXNEWTON, (unsigned long long)c_mx);
   }
 }
 
@@ -1755,7 +1824,6 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   const double Pn_i = s_Pn;
   const int ntile = (nf + 15) >> 4;
   const int nks = (nf + 3) >> 2;
-  const int nblk = (nks + 15) >> 4;
 
   // ---- pass 1 (re-run): [K_j | N_j | count] = B [V zeta zeta^T | V ydot zeta^T | 1]
   {
@@ -2552,7 +2620,8 @@ int check_params(ulppm_ctx* ctx, const ulppm_params* p) {
     return fail(ctx, ULPPM_E_ARG, "material constants out of range");
   if (p->newton_maxit < 1 || p->newton_maxit > 1000) return fail(ctx, ULPPM_E_ARG, "newton_maxit out of range");
   if (p->precision != ULPPM_FP64 && p->precision != ULPPM_MIXED) return fail(ctx, ULPPM_E_ARG, "bad precision");
-  if (p->force_mode != ULPPM_FORCE_CONJUGATE && p->force_mode != ULPPM_FORCE_EQ51)
+  if (p->force_mode != ULPPM_FORCE_CONJUGATE && p->force_mode != ULPPM_FORCE_EQ51 &&
+      p->force_mode != ULPPM_FORCE_STANDARD)
     return fail(ctx, ULPPM_E_ARG, "bad force_mode");
   return ULPPM_OK;
 }
@@ -2689,8 +2758,15 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   if (mark) mark(0);
   const size_t lds = bond_lds(ctx->max_f, mixed);
   k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
-  k_point_kin<<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
+  if (mixed)
+    k_point_kin<float><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
+  else
+    k_point_kin<double><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
   if (mark) mark(1);
+  if (p->force_mode == ULPPM_FORCE_STANDARD) {
+    HIPCHK(hipGetLastError());
+    return ULPPM_OK;
+  }
   if (mixed)
     k_bond_mx<float><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
   else

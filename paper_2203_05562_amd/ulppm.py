@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("ULPPM_LIB") or os.path.join(HERE, "libulppm.so")
 
 ULPPM_FP64, ULPPM_MIXED = 0, 1
+ULPPM_FORCE_CONJUGATE, ULPPM_FORCE_EQ51, ULPPM_FORCE_STANDARD = 0, 1, 2
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_CAPACITY", -4: "E_NOCONV", -5: "E_NONFINITE", -6: "E_ENERGY",
           -7: "E_HIP"}
 

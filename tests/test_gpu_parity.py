@@ -347,3 +347,62 @@ def test_C2_full_size_one_step_subsample(olib, gpu):
         rep = ctx.step(G, gprm, 1)
         assert rep["n_bonds"] == st["n_bonds"]
         compare_states(sub(G.to_arrays()), sub(S), tol, label=f"C2 precision {prec}")
+
+
+def test_standard_force_mode_parity(olib, gpu):
+    """The standard, unstabilised correspondence model (Eq. 14, force mode
+    2): force states against the oracle and a 50-step trajectory, FP64 at the
+    parity bar, mixed precision at 1e-4 over 20 steps."""
+    say("standard correspondence mode")
+    col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, (8, 8, 12), seed=1, vscale=0.1)
+    oprm.force_mode = 2
+    gprm.force_mode = 2
+    out = olib.bond_fields(S, oprm, oprm.dt)
+    f, T, rep = ctx.forces(G, gprm, oprm.dt, want_T=True)
+    assert rep["n_tests"] == 0 and rep["n_triples"] == 0
+    assert np.abs(T.cpu().numpy().T - out["T"]).max() <= 1e-11 * np.abs(out["T"]).max()
+    assert np.abs(f.cpu().numpy().T - out["f"]).max() <= 1e-11 * np.abs(out["f"]).max()
+    S0 = olib.copy_state(S)
+    G0 = G.clone()
+    rc, E, st = olib.step(S, oprm, 50)
+    assert rc == 0
+    ctx.step(G, gprm, 50)
+    compare_states(G.to_arrays(), S, 1e-10, fields=("u", "v", "sig", "pc", "J"), label="standard 50 steps")
+    gm = gpu.make_params(olib.params_dict(oprm), precision=gpu.ULPPM_MIXED)
+    gm.force_mode = 2
+    S1 = olib.copy_state(S0)
+    olib.step(S1, oprm, 20)
+    ctx.step(G0, gm, 20)
+    compare_states(G0.to_arrays(), S1, 1e-4, fields=("u", "v", "sig", "pc", "J"), label="standard mixed 20 steps")
+
+
+def test_zero_energy_mode_at_scale(gpu):
+    """Eqs. 20-21 at the 40^3 size (64,000 points, unjittered): the
+    checkerboard velocity changes no interior nodal force under the standard
+    model, while the sub-horizon model resists it.  Interior = at least two
+    horizons from every face."""
+    import torch
+    say("zero-energy mode, 40^3")
+    from paper_2203_05562_amd import ulppm
+    dims = (40, 40, 40)
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=0, jitter=0.0, dims=dims)
+    lat = col["lattice"]
+    sgn = np.where(lat.sum(axis=1) % 2 == 0, 1.0, -1.0)
+    v = np.zeros((col["n"], 3))
+    v[:, 0] = 0.05 * sgn
+    interior = np.all((lat >= 7) & (lat <= 32), axis=1)
+    ctx = gpu.Context(col["n"])
+    df = {}
+    for mode in (gpu.ULPPM_FORCE_CONJUGATE, gpu.ULPPM_FORCE_STANDARD):
+        fs = []
+        for vel in (np.zeros_like(v), v):
+            G = ulppm.column_state(col, "cuda:0", v0=vel)
+            p = gpu.make_params(col["params"], force_mode=mode)
+            ctx.init_state(G, p, col["params"]["ocr"])
+            p.dt = 0.5 * ctx.dt_crit(G, p)
+            f, _, _ = ctx.forces(G, p, p.dt)
+            fs.append(f.cpu().numpy().T)
+        df[mode] = np.abs(fs[1] - fs[0])[interior].max()
+        say("mode", mode, "max interior force change", df[mode])
+    assert df[gpu.ULPPM_FORCE_CONJUGATE] > 1e-3
+    assert df[gpu.ULPPM_FORCE_STANDARD] <= 1e-9 * df[gpu.ULPPM_FORCE_CONJUGATE]

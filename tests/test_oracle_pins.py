@@ -612,3 +612,58 @@ def test_conjugate_forces_stable_eq51_flutters(olib):
         res[mode] = np.array(ek)
     assert res[0].max() <= 1.5 * res[0][0]
     assert res[1][-1] > 1e3 * res[1][0]
+
+
+def test_zero_energy_mode_standard_vs_sub_horizon(olib):
+    """Eqs. 20-21 on the unjittered lattice: the checkerboard velocity
+    v_i = eps (-1)^(ix+iy+iz) e_x has a zero full-horizon velocity gradient
+    at interior points (odd-parity neighbours come in +/- pairs).  The
+    standard correspondence model (Eq. 14, force mode 2) therefore gives the
+    centre of a 13^3 block the same nodal force with and without the mode:
+    no restoring force.  The bond-associated sub-horizons see the mode and
+    the centre's force changes."""
+    dims = (13, 13, 13)
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=0, jitter=0.0, dims=dims)
+    lat = col["lattice"]
+    centre = int(np.nonzero((lat[:, 0] == 6) & (lat[:, 1] == 6) & (lat[:, 2] == 6))[0][0])
+    par = (lat[:, 0] + lat[:, 1] + lat[:, 2]) % 2
+    v = np.zeros((col["n"], 3))
+    v[:, 0] = 0.05 * np.where(par == 0, 1.0, -1.0)
+    df = {}
+    for mode in (0, 2):
+        f = []
+        for vel in (np.zeros_like(v), v):
+            prm = olib.make_params(col["params"], force_mode=mode)
+            S = olib.init_column(col, prm, col["params"]["ocr"], vel)
+            prm.dt = 0.5 * olib.dt_crit(S, prm)
+            out = olib.bond_fields(S, prm, prm.dt)
+            f.append(out["f"][centre])
+            if mode == 2:
+                assert out["stats"]["n_tests"] == 0 and out["stats"]["n_triples"] == 0
+        df[mode] = np.abs(f[1] - f[0]).max()
+    assert df[0] > 1e-6 * np.abs(f[0]).max() + 1e-30
+    assert df[2] <= 1e-9 * df[0]
+
+
+def test_standard_mode_linear_field_and_force_balance(olib):
+    """Force mode 2 on a linear velocity field: interior points update their
+    stress from the exact gradient (the same increment the sub-horizon model
+    gives there), and the internal forces sum to zero."""
+    dims = (9, 9, 9)
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=1, dims=dims)
+    lat = col["lattice"]
+    interior = np.nonzero(np.all((lat >= 3) & (lat <= 5), axis=1))[0]
+    G = np.array([[0.3, -0.1, 0.05], [0.2, -0.4, 0.1], [0.0, 0.15, 0.25]])
+    v = col["x0"] @ G.T
+    res = {}
+    for mode in (0, 2):
+        prm = olib.make_params(col["params"], force_mode=mode)
+        S = olib.init_column(col, prm, col["params"]["ocr"], v)
+        prm.dt = 0.5 * olib.dt_crit(S, prm)
+        res[mode] = (olib.bond_fields(S, prm, prm.dt), S)
+    o0, o2 = res[0][0], res[2][0]
+    s0 = res[0][1]["sig"]
+    d0 = o0["sig_pt"][interior] - s0[interior]
+    d2 = o2["sig_pt"][interior] - s0[interior]
+    assert np.max(np.abs(d2 - d0)) <= 1e-9 * np.max(np.abs(d0))
+    assert np.max(np.abs(o2["f"].sum(axis=0))) <= 1e-12 * np.max(np.abs(o2["f"]))
