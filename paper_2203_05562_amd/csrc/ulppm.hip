@@ -597,30 +597,33 @@ __global__ __launch_bounds__(256) void k_filter(const double* __restrict__ x, in
   if (lane == 0 && wmax > 0) ctr_max(ctr, C_MAXFAM, (unsigned long long)wmax);
 }
 
-// One thread per candidate slot that is a family member: CSR column and the
-// reverse-bond slot rev[(i,j)] = slot of (j,i), read through the reverse
-// candidate index (no search).
+// One wave per point, lanes over its candidate slots: for every member, the
+// CSR column and the reverse-bond slot rev[(i,j)] = slot of (j,i), read
+// through the reverse candidate index (no search).
 __global__ __launch_bounds__(256) void k_compact(int64_t n, int max_c, int max_f, const int32_t* __restrict__ cand,
                                                  const int32_t* __restrict__ ccnt, const int32_t* __restrict__ crev,
                                                  const int32_t* __restrict__ posmap, const int64_t* __restrict__ row,
                                                  int32_t* __restrict__ col, int32_t* __restrict__ rev,
                                                  unsigned long long* __restrict__ ctr) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * max_c;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / max_c;
-    const int m = (int)(e - i * max_c);
-    if (m >= ccnt[i]) continue;
-    const int pm = posmap[e];
-    if (pm < 0 || pm >= max_f) continue;
-    const int64_t s = row[i] + pm;
-    const int32_t j = cand[e];
-    col[s] = j;
-    const int cr = crev[e];
-    const int pr = cr >= 0 ? posmap[(int64_t)j * max_c + cr] : -1;
-    // The exact predicate is symmetric, so (j,i) is a member of row j.
-    const bool ok = pr >= 0 && pr < max_f;
-    rev[s] = (int32_t)(ok ? row[j] + pr : s);
-    if (!ok) ctr_add(ctr, C_OVERFLOW, 1ull);
+  const int lane = threadIdx.x & (kWave - 1);
+  const XcdWalk W = xcd_walk(n, 4);
+  for (int64_t i = W.first; i < W.end; i += W.stride) {
+    const int nc = ccnt[i];
+    const int64_t r0 = row[i];
+    const int64_t e0 = i * (int64_t)max_c;
+    for (int c = lane; c < nc; c += kWave) {
+      const int pm = posmap[e0 + c];
+      if (pm < 0 || pm >= max_f) continue;
+      const int64_t s = r0 + pm;
+      const int32_t j = cand[e0 + c];
+      col[s] = j;
+      const int cr = crev[e0 + c];
+      const int pr = cr >= 0 ? posmap[(int64_t)j * max_c + cr] : -1;
+      // The exact predicate is symmetric, so (j,i) is a member of row j.
+      const bool ok = pr >= 0 && pr < max_f;
+      rev[s] = (int32_t)(ok ? row[j] + pr : s);
+      if (!ok) ctr_add(ctr, C_OVERFLOW, 1ull);
+    }
   }
 }
 
@@ -1098,12 +1101,12 @@ __global__ void k_pack(int64_t n, const double* __restrict__ x, const double* __
 // the point's stress from L_i by the return map and writes the force states
 // T_ik = (sigma_i + S_r s 1) K_i^{-1} zeta_ik of all its bonds; the bond
 // kernel does not run.  TS: storage type of the force states.
-template <class TS>
+template <class TS, bool Standard>
 __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t n = A.n;
   const XcdWalk W = xcd_walk(n, 4);
-  const bool standard = P.force_mode == ULPPM_FORCE_STANDARD;
+  constexpr bool standard = Standard;
   int c_deg = 0, c_pl = 0, c_nc = 0, c_mx = 0;          // standard mode, lane 0
   for (int64_t i = W.first; i < W.end; i += W.stride) {
     const int64_t b0 = A.row[i], b1 = A.row[i + 1];
@@ -1162,7 +1165,7 @@ __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
       A.pk[i] = apparent_pc(P, A.pc[i]);
       A.pk[n + i] = Vp > 0.0 ? 1.0 / Vp : 0.0;
     }
-    if (standard) {
+    if constexpr (standard) {
       // every lane holds the wave totals and forms the point update itself
       const int nf = (int)(b1 - b0);
       const double dK = det3s(Kp[0], Kp[1], Kp[2], Kp[3], Kp[4], Kp[5]);
@@ -2692,12 +2695,14 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
   if (rc2) return rc2;
   k_cell_fill<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, ctx->cellid, ctx->cstart, ctx->ccursor, ctx->cpts, gate);
   const int64_t per = (n + 7) / 8;
-  const unsigned fgrid = (unsigned)std::min<int64_t>(8 * per, 16384);
+  // capped grids: most steps the gate is clear and every block returns at once,
+  // so the launch cost is that of dispatching the blocks
+  const unsigned fgrid = (unsigned)std::min<int64_t>(8 * per, 4096);
   k_family<<<fgrid, kWave, ctx->max_c * sizeof(int32_t), ctx->stream>>>(
       ctx->x, n, per, ctx->grid, ctx->cellid, ctx->cstart, ctx->cpts, rc * rc, ctx->max_c, ctx->cand, ctx->ccnt,
       ctx->ctr, gate);
   const unsigned cgrid = (unsigned)((n * ctx->max_c + 255) / 256);
-  k_cand_rev<<<std::min<unsigned>(cgrid, 8192u), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->cand, ctx->ccnt,
+  k_cand_rev<<<std::min<unsigned>(cgrid, 2048u), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->cand, ctx->ccnt,
                                                                        ctx->crev, ctx->ctr, gate);
   k_save_ref<<<blocks_for(3 * n, 256, 4096), 256, 0, ctx->stream>>>(ctx->x, ctx->xref, 3 * n, gate);
   k_fill<int32_t><<<1, 64, 0, ctx->stream>>>(ctx->gate, 1, 0);
@@ -2707,9 +2712,8 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
   HIPCHK(hipGetLastError());
   rc2 = scan_counts(ctx, ctx->cnt, n, ctx->row);
   if (rc2) return rc2;
-  k_compact<<<std::min<unsigned>(cgrid, 16384u), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand,
-                                                                        ctx->ccnt, ctx->crev, ctx->posmap, ctx->row,
-                                                                        ctx->col, ctx->rev, ctx->ctr);
+  k_compact<<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt, ctx->crev,
+                                                    ctx->posmap, ctx->row, ctx->col, ctx->rev, ctx->ctr);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
@@ -2758,10 +2762,15 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   if (mark) mark(0);
   const size_t lds = bond_lds(ctx->max_f, mixed);
   k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
-  if (mixed)
-    k_point_kin<float><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
+  // the standard model's return map lives in its own instance so that the
+  // plain kinematics keep their small register footprint
+  const bool standard = p->force_mode == ULPPM_FORCE_STANDARD;
+  if (mixed && standard)
+    k_point_kin<float, true><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
+  else if (standard)
+    k_point_kin<double, true><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
   else
-    k_point_kin<double><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
+    k_point_kin<double, false><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
   if (mark) mark(1);
   if (p->force_mode == ULPPM_FORCE_STANDARD) {
     HIPCHK(hipGetLastError());
