@@ -1056,7 +1056,8 @@ struct BondArgs {
   double* mass_out;
   double* sig_out[6];
   double* pc_out;
-  void* T[3];             // bond force states, CSR order (double, or float in mixed precision)
+  void* T;                // bond force states, CSR order, one (x, y, z, 0) record per bond
+                          // (double, or float in mixed precision)
   double* pk;             // 2n: apparent pre-consolidation of p_c,i and 1/V_H,i (k_point_kin)
   const double* xv;       // 8n: x (3), V^n, v_half (3), 0 per point
   double dt_inc;
@@ -1208,16 +1209,13 @@ __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
         sym_full(Ki, KiF);
         mat3_mul(QF, KiF, SK);
       }
-      TS* T0 = reinterpret_cast<TS*>(A.T[0]);
-      TS* T1 = reinterpret_cast<TS*>(A.T[1]);
-      TS* T2 = reinterpret_cast<TS*>(A.T[2]);
+      Quad<TS>* T4 = reinterpret_cast<Quad<TS>*>(A.T);
       for (int64_t s = b0 + lane; s < b1; s += kWave) {
         const int32_t k = A.col[s];
         const double4 pa = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k];
         const double z0 = pa.x - xi0, z1 = pa.y - xi1, z2 = pa.z - xi2;
-        T0[s] = (TS)(SK[0] * z0 + SK[1] * z1 + SK[2] * z2);
-        T1[s] = (TS)(SK[3] * z0 + SK[4] * z1 + SK[5] * z2);
-        T2[s] = (TS)(SK[6] * z0 + SK[7] * z1 + SK[8] * z2);
+        T4[s] = Quad<TS>{{(TS)(SK[0] * z0 + SK[1] * z1 + SK[2] * z2), (TS)(SK[3] * z0 + SK[4] * z1 + SK[5] * z2),
+                          (TS)(SK[6] * z0 + SK[7] * z1 + SK[8] * z2), (TS)0}};
       }
     }
   }
@@ -1309,7 +1307,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
   Acc* sKN = sR + 8 * (size_t)mf;                                      // 16 per member: K, N, Vs, then M_j
   unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)mf);
   unsigned short* sq = reinterpret_cast<unsigned short*>(sb);
-  TS** const Tout = reinterpret_cast<TS**>(A.T);
+  Quad<TS>* const T4 = reinterpret_cast<Quad<TS>*>(A.T);
   __shared__ double s_d2;
   __shared__ double red[kBondWaves][24];
   __shared__ int redi[kBondWaves][4];
@@ -1428,7 +1426,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
       ++n_deg;
 #pragma unroll
       for (int q = 0; q < 9; ++q) kn[q] = (Acc)0;
-      if (P.force_mode == ULPPM_FORCE_EQ51) { Tout[0][slot] = (TS)0; Tout[1][slot] = (TS)0; Tout[2][slot] = (TS)0; }
+      if (P.force_mode == ULPPM_FORCE_EQ51) T4[slot] = Quad<TS>{{(TS)0, (TS)0, (TS)0, (TS)0}};
       continue;
     }
     const double idK = 1.0 / dK;
@@ -1472,9 +1470,9 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
       // Eq. 51 as printed: T_ij = varpi (sigma_ij + Sr s 1) K_ij^{-1} zeta_ij.
       const Quad<double> xj = sX[m];
       const double zx = xj.v[0] - xi0, zy = xj.v[1] - xi1, zz = xj.v[2] - xi2;
-      Tout[0][slot] = (TS)(varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz));
-      Tout[1][slot] = (TS)(varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz));
-      Tout[2][slot] = (TS)(varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz));
+      T4[slot] = Quad<TS>{{(TS)(varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz)),
+                           (TS)(varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz)),
+                           (TS)(varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz)), (TS)0}};
     } else {
       const double wj = Vj * iVh;
 #pragma unroll
@@ -1514,9 +1512,8 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
       const Acc* zm = sR + 8 * (size_t)m;
       const Acc zx = zm[0], zy = zm[1], zz = zm[2];
       const int64_t slot = b0 + m;
-      Tout[0][slot] = (TS)(a0 * zx + a1 * zy + a2 * zz);
-      Tout[1][slot] = (TS)(a3 * zx + a4 * zy + a5 * zz);
-      Tout[2][slot] = (TS)(a6 * zx + a7 * zy + a8 * zz);
+      T4[slot] = Quad<TS>{{(TS)(a0 * zx + a1 * zy + a2 * zz), (TS)(a3 * zx + a4 * zy + a5 * zz),
+                           (TS)(a6 * zx + a7 * zy + a8 * zz), (TS)0}};
     }
   } else if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
     // ---- pass 2 in FP32: A_k = sum_j B_kj M_j on the matrix cores
@@ -1567,7 +1564,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
           const Acc prod = ok ? acc[b][r] * zq : (Acc)0;
           const Acc p1 = __shfl_down(prod, 1, 16);
           const Acc p2 = __shfl_down(prod, 2, 16);
-          if (ok && qz == 0) Tout[r16 / 3][b0 + k] = (TS)(prod + p1 + p2);
+          if (ok && qz == 0) T4[b0 + k].v[r16 / 3] = (TS)(prod + p1 + p2);
         }
       }
     }
@@ -2326,7 +2323,7 @@ struct GatherArgs {
   const int64_t* row;
   const int32_t* col;
   const int32_t* rev;
-  const void* T[3];       // double, or float in mixed precision
+  const void* T;          // (x, y, z, 0) per bond: double, or float in mixed precision
   const double* vol_n;
   const double* mass;     // M^{n+1}
   const double* vh;       // 3n (G_STEP)
@@ -2348,9 +2345,7 @@ struct GatherArgs {
 template <class TS>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const TS* T0 = reinterpret_cast<const TS*>(G.T[0]);
-  const TS* T1 = reinterpret_cast<const TS*>(G.T[1]);
-  const TS* T2 = reinterpret_cast<const TS*>(G.T[2]);
+  const Quad<TS>* T4 = reinterpret_cast<const Quad<TS>*>(G.T);
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;
   const XcdWalk W = xcd_walk(G.n, 4);
   for (int64_t i = W.first; i < W.end; i += W.stride) {
@@ -2359,9 +2354,10 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
     for (int64_t s = b0 + lane; s < b1; s += kWave) {
       const int32_t j = G.col[s], r = G.rev[s];
       const TS wv = (TS)G.vol_n[j];
-      f0 += (T0[s] - T0[r]) * wv;
-      f1 += (T1[s] - T1[r]) * wv;
-      f2 += (T2[s] - T2[r]) * wv;
+      const Quad<TS> ts = T4[s], tr = T4[r];
+      f0 += (ts.v[0] - tr.v[0]) * wv;
+      f1 += (ts.v[1] - tr.v[1]) * wv;
+      f2 += (ts.v[2] - tr.v[2]) * wv;
     }
     f0 = wave_sum(f0);
     f1 = wave_sum(f1);
@@ -2505,9 +2501,11 @@ __global__ void k_copy_i32(const int32_t* __restrict__ a, int32_t* __restrict__ 
     b[e] = a[e];
 }
 
-__global__ void k_widen(const float* __restrict__ a, double* __restrict__ b, int64_t m) {
+// One component of the per-bond force-state records, widened to double.
+template <class TS>
+__global__ void k_unpack_T(const Quad<TS>* __restrict__ T, int c, double* __restrict__ b, int64_t m) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
-    b[e] = (double)a[e];
+    b[e] = (double)T[e].v[c];
 }
 
 __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t m) {
@@ -2553,7 +2551,7 @@ struct ulppm_ctx {
   // bonds
   int32_t* col = nullptr;
   int32_t* rev = nullptr;
-  double* T = nullptr;        // 3*bond_cap
+  double* T = nullptr;        // 4*bond_cap: (x, y, z, 0) per bond, double or float
   // reductions
   double* part = nullptr;     // partials
   int64_t part_cap = 0;
@@ -2751,8 +2749,7 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
     A.pc_out = q + 11 * n;
   }
   const bool mixed = p->precision == ULPPM_MIXED;
-  for (int c = 0; c < 3; ++c)
-    A.T[c] = mixed ? (void*)(reinterpret_cast<float*>(ctx->T) + c * ctx->bond_cap) : (void*)(ctx->T + c * ctx->bond_cap);
+  A.T = ctx->T;
   A.dt_inc = dt_inc;
   A.max_f = ctx->max_f;
   A.ctr = ctx->ctr;
@@ -2794,9 +2791,7 @@ int gather_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int
   G.col = ctx->col;
   G.rev = ctx->rev;
   const bool mixed = p->precision == ULPPM_MIXED;
-  for (int c = 0; c < 3; ++c)
-    G.T[c] = mixed ? (const void*)(reinterpret_cast<const float*>(ctx->T) + c * ctx->bond_cap)
-                   : (const void*)(ctx->T + c * ctx->bond_cap);
+  G.T = ctx->T;
   G.vol_n = ctx->vol_n;
   G.mass = mass;
   G.vh = ctx->vh;
@@ -3081,7 +3076,7 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   A((void**)&ctx->cpts, sizeof(int32_t) * n);
   A((void**)&ctx->col, sizeof(int32_t) * ctx->bond_cap);
   A((void**)&ctx->rev, sizeof(int32_t) * ctx->bond_cap);
-  A((void**)&ctx->T, sizeof(double) * 3 * ctx->bond_cap);
+  A((void**)&ctx->T, sizeof(double) * 4 * ctx->bond_cap);
   A((void**)&ctx->part, sizeof(double) * ctx->part_cap);
   A((void**)&ctx->scan_bsum, sizeof(int64_t) * ctx->scan_cap);
   A((void**)&ctx->grid, sizeof(Grid));
@@ -3202,10 +3197,11 @@ int ulppm_forces(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, do
     for (int c = 0; c < 3; ++c)
       if (T_out[c]) {
         if (mixed)
-          k_widen<<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(reinterpret_cast<const float*>(ctx->T) + c * ctx->bond_cap,
-                                                                 T_out[c], nb);
+          k_unpack_T<float><<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(
+              reinterpret_cast<const Quad<float>*>(ctx->T), c, T_out[c], nb);
         else
-          k_copy_f64<<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(ctx->T + c * ctx->bond_cap, T_out[c], nb);
+          k_unpack_T<double><<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(
+              reinterpret_cast<const Quad<double>*>(ctx->T), c, T_out[c], nb);
       }
     HIPCHK(hipGetLastError());
   }
