@@ -42,8 +42,14 @@ namespace {
 #ifndef ULPPM_BOND_THREADS
 #define ULPPM_BOND_THREADS 128
 #endif
+// Waves per SIMD the bond kernel is compiled for: FP64 issue saturates at two
+// (the FP64 matrix products and vector ops share one pipe), while the mixed
+// instance, whose FP32 products are cheaper, gains from a third wave.
 #ifndef ULPPM_BOND_MX_MIN_WAVES
 #define ULPPM_BOND_MX_MIN_WAVES 2
+#endif
+#ifndef ULPPM_BOND_MX_MIN_WAVES_MIXED
+#define ULPPM_BOND_MX_MIN_WAVES_MIXED 3
 #endif
 #ifndef ULPPM_ADJ_MIN_WAVES
 #define ULPPM_ADJ_MIN_WAVES 2
@@ -1274,8 +1280,13 @@ constexpr int kTileBatch = 4;     // 16-row tiles a wave carries through one swe
 
 template <class Acc>
 __host__ __device__ constexpr size_t bond_mx_lds_bytes(int max_f) {
+  // the family's working set; the closing reduction reuses it for 8 doubles per thread
   return (size_t)max_f * (sizeof(Quad<double>) + 8 * sizeof(Acc) + 16 * sizeof(Acc)) +
-         (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long);
+                 (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long) >
+             8 * kBondThreads * sizeof(double)
+         ? (size_t)max_f * (sizeof(Quad<double>) + 8 * sizeof(Acc) + 16 * sizeof(Acc)) +
+               (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long)
+         : 8 * kBondThreads * sizeof(double);
 }
 
 // Feature f of member k (pass 1, B operand): V_k a_f b_f from the record
@@ -1288,7 +1299,8 @@ __host__ __device__ constexpr int feat_b(int f) {
 }
 
 template <class Acc>
-__global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_mx(BondArgs A, DevParams P) {
+__global__ __launch_bounds__(kBondThreads, sizeof(Acc) == 8 ? ULPPM_BOND_MX_MIN_WAVES : ULPPM_BOND_MX_MIN_WAVES_MIXED)
+void k_bond_mx(BondArgs A, DevParams P) {
   using TS = Acc;
   using MM = Mma<Acc>;
   using V4 = typename MM::V;
@@ -1491,23 +1503,31 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
     __syncthreads();
     for (int m = tid; m < nf; m += kBondThreads) {
       Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0, a8 = 0;
-      unsigned long long word = 0ull;
-      Acc r[9];                                        // M_j, loaded one member ahead
+      for (int c = 0; c < nblk; ++c) {
+        const unsigned long long word = sb[(size_t)m * nw + c];
+        const unsigned lo = (unsigned)word, hi = (unsigned)(word >> 32);
+        // members 64 c + 4 s + q in order; their bits are 16 q + s of the
+        // word.  Bits of members past the family are clear, so their rows
+        // (clamped to the last member) enter with weight 0.
+        for (int s4 = 0; s4 < 16; ++s4) {
+          const int j0 = 64 * c + 4 * s4;
+          if (j0 >= nf) break;
+          Acc r[4][9];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) r[q] = sKN[q];
-      for (int j = 0; j < nf; ++j) {
-        if ((j & 63) == 0) word = sb[(size_t)m * nw + (j >> 6)];
-        const int jn = j + 1 < nf ? j + 1 : j;
-        Acc rn[9];
+          for (int q = 0; q < 4; ++q) {
+            const Acc* rq = sKN + 16 * (size_t)(j0 + q < nf ? j0 + q : nf - 1);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) rn[q] = sKN[16 * (size_t)jn + q];
-        const int jj = j & 63;
-        const Acc w = (word >> (16 * (jj & 3) + (jj >> 2))) & 1ull ? (Acc)1 : (Acc)0;
-        a0 += w * r[0]; a1 += w * r[1]; a2 += w * r[2];
-        a3 += w * r[3]; a4 += w * r[4]; a5 += w * r[5];
-        a6 += w * r[6]; a7 += w * r[7]; a8 += w * r[8];
+            for (int t = 0; t < 9; ++t) r[q][t] = rq[t];
+          }
 #pragma unroll
-        for (int q = 0; q < 9; ++q) r[q] = rn[q];
+          for (int q = 0; q < 4; ++q) {
+            const unsigned half = q < 2 ? lo : hi;
+            const Acc w = (Acc)((half >> (16 * (q & 1) + s4)) & 1u);
+            a0 += w * r[q][0]; a1 += w * r[q][1]; a2 += w * r[q][2];
+            a3 += w * r[q][3]; a4 += w * r[q][4]; a5 += w * r[q][5];
+            a6 += w * r[q][6]; a7 += w * r[q][7]; a8 += w * r[q][8];
+          }
+        }
       }
       const Acc* zm = sR + 8 * (size_t)m;
       const Acc zx = zm[0], zy = zm[1], zz = zm[2];
@@ -1569,30 +1589,44 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_BOND_MX_MIN_WAVES) void k_bond_
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) hs[k] = wave_sum(hs[k]);
-  hpc = wave_sum(hpc);
-  hw = wave_sum(hw);
   n_deg = wave_sum_i(n_deg);
   n_pl = wave_sum_i(n_pl);
   n_nc = wave_sum_i(n_nc);
   n_trip = wave_sum_i(n_trip);
   mx = wave_max_i(mx);
-  __syncthreads();   // red[] is reused
+  // The eight history sums go through LDS: one wave adds 16 entries per lane
+  // and combines groups of 8 lanes, instead of eight full-wave reductions
+  // per wave.
+  __syncthreads();   // the family's working set is no longer read
+  double* hred = reinterpret_cast<double*>(smem_raw);              // [8][kBondThreads]
+#pragma unroll
+  for (int k = 0; k < 6; ++k) hred[k * kBondThreads + tid] = hs[k];
+  hred[6 * kBondThreads + tid] = hpc;
+  hred[7 * kBondThreads + tid] = hw;
   if (lane == 0) {
-    for (int k = 0; k < 6; ++k) red[wid][k] = hs[k];
-    red[wid][6] = hpc;
-    red[wid][7] = hw;
     redi[wid][0] = n_deg; redi[wid][1] = n_pl; redi[wid][2] = n_nc; redi[wid][3] = n_trip;
     red[wid][8] = (double)mx;
   }
   __syncthreads();
-  if (tid == 0) {
-    double W = 0.0, hsum[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (wid == 0) {
+    constexpr int kPer = kBondThreads / 8;
+    const double* src = hred + (lane >> 3) * kBondThreads + (lane & 7) * kPer;
+    double v = 0.0;
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) v += src[e];
+    v += dpp_d<kDppXor1, 0xF>(v);
+    v += dpp_d<kDppXor2, 0xF>(v);
+    v += dpp_d<kDppHalfMirror, 0xF>(v);
+    const long long vb = __double_as_longlong(v);
+    double hsum[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      hsum[k] = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(vb >> 32), 8 * k) << 32) |
+                                     (unsigned)__builtin_amdgcn_readlane((int)vb, 8 * k));
+    if (lane != 0) return;
+    const double W = hsum[7];
     long long d = 0, pl = 0, nc = 0, tr = 0, m2 = 0;
     for (int w = 0; w < kBondWaves; ++w) {
-      W += red[w][7];
-      for (int k = 0; k < 7; ++k) hsum[k] += red[w][k];
       d += redi[w][0]; pl += redi[w][1]; nc += redi[w][2]; tr += redi[w][3];
       m2 = m2 > (long long)red[w][8] ? m2 : (long long)red[w][8];
     }
