@@ -1108,6 +1108,85 @@ __global__ void k_pack(int64_t n, const double* __restrict__ x, const double* __
 // the point's stress from L_i by the return map and writes the force states
 // T_ik = (sigma_i + S_r s 1) K_i^{-1} zeta_ik of all its bonds; the bond
 // kernel does not run.  TS: storage type of the force states.
+// Point update from the full-horizon sums K_i, N_i and V_H,i: volume ratio
+// of the step from L_i (Eqs. 16-17), porosity, saturation (Eq. 15), mass
+// (Eq. 48), and the per-point factors the bond kernel reads (apparent
+// pre-consolidation of p_c,i, Eq. 45, and 1/V_H,i).
+__device__ __forceinline__ void point_update(const BondArgs& A, const DevParams& P, int64_t i, int nf,
+                                             const double* Kp, const double* Np, double Vp) {
+  const int64_t n = A.n;
+  double Jd = 1.0;
+  const double dK = det3s(Kp[0], Kp[1], Kp[2], Kp[3], Kp[4], Kp[5]);
+  const double tk = (Kp[0] + Kp[1] + Kp[2]) / 3.0;
+  if (nf >= 3 && dK > 1e-12 * tk * tk * tk) {
+    const double a = Kp[0], b = Kp[1], c = Kp[2], d = Kp[3], e = Kp[4], f = Kp[5];
+    const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
+    const double ixy = (d * e - f * c) / dK, ixz = (f * d - b * e) / dK, iyz = (e * f - a * d) / dK;
+    const double Ki9[9] = {ixx, ixy, ixz, ixy, iyy, iyz, ixz, iyz, izz};
+    double B[9];
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) {
+        const double L = Np[3 * r] * Ki9[cc] + Np[3 * r + 1] * Ki9[3 + cc] + Np[3 * r + 2] * Ki9[6 + cc];
+        B[3 * r + cc] = (r == cc ? 1.0 : 0.0) - A.dt_inc * L;
+      }
+    const double dB = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
+                      B[2] * (B[3] * B[7] - B[4] * B[6]);
+    Jd = 1.0 / dB;
+  }
+  const double Jn = A.J[i] * Jd;
+  const double Vn = A.vol_n[i] * Jd;
+  const double ph = 1.0 - (1.0 - A.phi[i]) / Jd;            // Eq. 16
+  const double Sr = swrc(P, Jn, ph, A.s[i]);                // Eq. 15
+  A.J_out[i] = Jn;
+  A.vol_out[i] = Vn;
+  A.phi_out[i] = ph;
+  A.Sr_out[i] = Sr;
+  A.mass_out[i] = (P.rho_s * (1.0 - ph) + P.rho_w * Sr * ph) * Vn;   // Eq. 48
+  A.pk[i] = apparent_pc(P, A.pc[i]);
+  A.pk[n + i] = Vp > 0.0 ? 1.0 / Vp : 0.0;
+}
+
+// Point kinematics with one lane per point: each lane walks its own family
+// (the loads of four members in flight at once) and updates its point.  A
+// workgroup holds 256 consecutive points; the workgroups of one XCD take a
+// contiguous range of them.
+__global__ __launch_bounds__(256) void k_point_kin_lane(BondArgs A, DevParams P, int64_t per) {
+  const int64_t blk = xcd_point(blockIdx.x, per);
+  const int64_t i = blk * 256 + threadIdx.x;
+  if (i >= A.n) return;
+  const int64_t n = A.n;
+  const int64_t b0 = A.row[i], b1 = A.row[i + 1];
+  const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
+  const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
+  double Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0.0;
+  const double4* xv = reinterpret_cast<const double4*>(A.xv);
+  for (int64_t s0 = b0; s0 < b1; s0 += 4) {
+    double4 pa[4], pb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t s = s0 + u < b1 ? s0 + u : b1 - 1;
+      const int32_t k = A.col[s];
+      pa[u] = xv[2 * (int64_t)k];
+      pb[u] = xv[2 * (int64_t)k + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (s0 + u >= b1) break;
+      const double z0 = pa[u].x - xi0, z1 = pa[u].y - xi1, z2 = pa[u].z - xi2;
+      const double y0 = pb[u].x - vi0, y1 = pb[u].y - vi1, y2 = pb[u].z - vi2;
+      const double V = pa[u].w;
+      const double w0 = V * z0, w1 = V * z1, w2 = V * z2;
+      Kp[0] += w0 * z0; Kp[1] += w1 * z1; Kp[2] += w2 * z2;
+      Kp[3] += w1 * z2; Kp[4] += w0 * z2; Kp[5] += w0 * z1;
+      Np[0] += y0 * w0; Np[1] += y0 * w1; Np[2] += y0 * w2;
+      Np[3] += y1 * w0; Np[4] += y1 * w1; Np[5] += y1 * w2;
+      Np[6] += y2 * w0; Np[7] += y2 * w1; Np[8] += y2 * w2;
+      Vp += V;
+    }
+  }
+  point_update(A, P, i, (int)(b1 - b0), Kp, Np, Vp);
+}
+
 template <class TS, bool Standard>
 __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -1140,38 +1219,7 @@ __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) Np[k] = wave_sum(Np[k]);
     Vp = wave_sum(Vp);
-    if (lane == 0) {
-      const int nf = (int)(b1 - b0);
-      double Jd = 1.0;
-      const double dK = det3s(Kp[0], Kp[1], Kp[2], Kp[3], Kp[4], Kp[5]);
-      const double tk = (Kp[0] + Kp[1] + Kp[2]) / 3.0;
-      if (nf >= 3 && dK > 1e-12 * tk * tk * tk) {
-        const double a = Kp[0], b = Kp[1], c = Kp[2], d = Kp[3], e = Kp[4], f = Kp[5];
-        const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
-        const double ixy = (d * e - f * c) / dK, ixz = (f * d - b * e) / dK, iyz = (e * f - a * d) / dK;
-        const double Ki9[9] = {ixx, ixy, ixz, ixy, iyy, iyz, ixz, iyz, izz};
-        double B[9];
-        for (int r = 0; r < 3; ++r)
-          for (int cc = 0; cc < 3; ++cc) {
-            const double L = Np[3 * r] * Ki9[cc] + Np[3 * r + 1] * Ki9[3 + cc] + Np[3 * r + 2] * Ki9[6 + cc];
-            B[3 * r + cc] = (r == cc ? 1.0 : 0.0) - A.dt_inc * L;
-          }
-        const double dB = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
-                          B[2] * (B[3] * B[7] - B[4] * B[6]);
-        Jd = 1.0 / dB;
-      }
-      const double Jn = A.J[i] * Jd;
-      const double Vn = A.vol_n[i] * Jd;
-      const double ph = 1.0 - (1.0 - A.phi[i]) / Jd;            // Eq. 16
-      const double Sr = swrc(P, Jn, ph, A.s[i]);                // Eq. 15
-      A.J_out[i] = Jn;
-      A.vol_out[i] = Vn;
-      A.phi_out[i] = ph;
-      A.Sr_out[i] = Sr;
-      A.mass_out[i] = (P.rho_s * (1.0 - ph) + P.rho_w * Sr * ph) * Vn;   // Eq. 48
-      A.pk[i] = apparent_pc(P, A.pc[i]);
-      A.pk[n + i] = Vp > 0.0 ? 1.0 / Vp : 0.0;
-    }
+    if (lane == 0) point_update(A, P, i, (int)(b1 - b0), Kp, Np, Vp);
     if constexpr (standard) {
       // every lane holds the wave totals and forms the point update itself
       const int nf = (int)(b1 - b0);
@@ -2800,8 +2848,10 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
     k_point_kin<float, true><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
   else if (standard)
     k_point_kin<double, true><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
-  else
-    k_point_kin<double, false><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
+  else {
+    const int64_t per = ((n + 255) / 256 + 7) / 8;
+    k_point_kin_lane<<<(unsigned)(8 * per), 256, 0, ctx->stream>>>(A, P, per);
+  }
   if (mark) mark(1);
   if (p->force_mode == ULPPM_FORCE_STANDARD) {
     HIPCHK(hipGetLastError());
