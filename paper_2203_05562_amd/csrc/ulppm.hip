@@ -28,6 +28,7 @@
 
 #include <hip/hip_runtime.h>
 #include <functional>
+#include <type_traits>
 
 #include <cmath>
 #include <cstdint>
@@ -1409,14 +1410,16 @@ void k_bond_mx(BondArgs A, DevParams P) {
   // the member loop is branch-free so that tests and products interleave.
   {
     const int fa = feat_a(r16), fb = feat_b(r16);
-    for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
-      double xj[kTileBatch][3];
-      bool jv[kTileBatch];
-      int jrow[kTileBatch];
-      V4 acc[kTileBatch];
-      unsigned piece[kTileBatch];
+    // NB tile slots t0, t0 + kBondWaves, ... of one wave, all inside the family
+    auto tiles = [&](int t0, auto nbc) {
+      constexpr int NB = decltype(nbc)::value;
+      double xj[NB][3];
+      bool jv[NB];
+      int jrow[NB];
+      V4 acc[NB];
+      unsigned piece[NB];
 #pragma unroll
-      for (int b = 0; b < kTileBatch; ++b) {
+      for (int b = 0; b < NB; ++b) {
         jrow[b] = (t0 + kBondWaves * b) * 16 + r16;
         jv[b] = jrow[b] < nf;
         const Quad<double> q = sX[jv[b] ? jrow[b] : 0];
@@ -1440,14 +1443,14 @@ void k_bond_mx(BondArgs A, DevParams P) {
         const Acc bval = kv ? fv : (Acc)0;
         const unsigned sbit = 1u << (ks & 15);
 #pragma unroll
-        for (int b = 0; b < kTileBatch; ++b) {
+        for (int b = 0; b < NB; ++b) {
           const bool in = within(xj[b][0], xj[b][1], xj[b][2], xk.v[0], xk.v[1], xk.v[2], d2) & kv & jv[b];
           piece[b] |= in ? sbit : 0u;
           acc[b] = MM::run(in ? (Acc)1 : (Acc)0, bval, acc[b]);
         }
         if ((ks & 15) == 15 || ks == nks - 1) {
 #pragma unroll
-          for (int b = 0; b < kTileBatch; ++b) {
+          for (int b = 0; b < NB; ++b) {
             if (jv[b]) sq[((size_t)jrow[b] * nw + (ks >> 4)) * 4 + q4] = (unsigned short)piece[b];
             piece[b] = 0u;
           }
@@ -1457,7 +1460,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
         ra = ra1; rb = rb1; rv = rv1;
       }
 #pragma unroll
-      for (int b = 0; b < kTileBatch; ++b) {
+      for (int b = 0; b < NB; ++b) {
         const int t = t0 + kBondWaves * b;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -1465,6 +1468,14 @@ void k_bond_mx(BondArgs A, DevParams P) {
           if (j < nf) sKN[16 * (size_t)j + r16] = acc[b][r];
         }
       }
+    };
+    for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
+      const int nb = (ntile - t0 + kBondWaves - 1) / kBondWaves;     // slots left for this wave
+      static_assert(kTileBatch == 4, "slot dispatch below");
+      if (nb >= 4) tiles(t0, std::integral_constant<int, 4>{});
+      else if (nb == 3) tiles(t0, std::integral_constant<int, 3>{});
+      else if (nb == 2) tiles(t0, std::integral_constant<int, 2>{});
+      else tiles(t0, std::integral_constant<int, 1>{});
     }
   }
   __syncthreads();
@@ -1589,12 +1600,13 @@ void k_bond_mx(BondArgs A, DevParams P) {
     // then T_ik = A_k zeta_ik with the three products of a row combined
     // across neighbouring lanes.
     __syncthreads();
-    for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
-      V4 acc[kTileBatch];
-      unsigned piece[kTileBatch];
-      int krow[kTileBatch];
+    auto tiles2 = [&](int t0, auto nbc) {
+      constexpr int NB = decltype(nbc)::value;
+      V4 acc[NB];
+      unsigned piece[NB];
+      int krow[NB];
 #pragma unroll
-      for (int b = 0; b < kTileBatch; ++b) {
+      for (int b = 0; b < NB; ++b) {
         acc[b] = V4{0, 0, 0, 0};
         piece[b] = 0u;
         krow[b] = (t0 + kBondWaves * b) * 16 + r16;
@@ -1608,21 +1620,21 @@ void k_bond_mx(BondArgs A, DevParams P) {
         const int s = js & 15;
         if (s == 0) {
 #pragma unroll
-          for (int b = 0; b < kTileBatch; ++b) {
+          for (int b = 0; b < NB; ++b) {
             const bool kv = krow[b] < nf;
             const unsigned pw = sq[((size_t)(kv ? krow[b] : 0) * nw + (js >> 4)) * 4 + q4];
             piece[b] = kv ? pw : 0u;
           }
         }
 #pragma unroll
-        for (int b = 0; b < kTileBatch; ++b) {
+        for (int b = 0; b < NB; ++b) {
           const Acc av = (piece[b] >> s) & 1u ? (Acc)1 : (Acc)0;
           acc[b] = MM::run(av, bval, acc[b]);
         }
       }
       const int qz = r16 % 3;
 #pragma unroll
-      for (int b = 0; b < kTileBatch; ++b) {
+      for (int b = 0; b < NB; ++b) {
         const int t = t0 + kBondWaves * b;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -1635,6 +1647,13 @@ void k_bond_mx(BondArgs A, DevParams P) {
           if (ok && qz == 0) T4[b0 + k].v[r16 / 3] = (TS)(prod + p1 + p2);
         }
       }
+    };
+    for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
+      const int nb = (ntile - t0 + kBondWaves - 1) / kBondWaves;
+      if (nb >= 4) tiles2(t0, std::integral_constant<int, 4>{});
+      else if (nb == 3) tiles2(t0, std::integral_constant<int, 3>{});
+      else if (nb == 2) tiles2(t0, std::integral_constant<int, 2>{});
+      else tiles2(t0, std::integral_constant<int, 1>{});
     }
   }
   n_deg = wave_sum_i(n_deg);
