@@ -31,7 +31,9 @@ class OracleParams(C.Structure):
                 ("lam", C.c_double), ("kap", C.c_double), ("eta", C.c_double), ("b1", C.c_double),
                 ("b2", C.c_double), ("rho_s", C.c_double), ("rho_w", C.c_double), ("a1", C.c_double),
                 ("a2", C.c_double), ("n_vg", C.c_double), ("g", C.c_double * 3), ("dt", C.c_double),
-                ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("force_mode", C.c_int32)]
+                ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("force_mode", C.c_int32),
+                ("cs", C.c_double), ("mu_f", C.c_double), ("delta_c", C.c_double),
+                ("sub_origin", C.c_double * 3), ("sub_dx", C.c_double), ("sub_n", C.c_int32 * 3)]
 
 
 class OracleState(C.Structure):
@@ -101,12 +103,22 @@ def make_params(prm: dict, **over) -> OracleParams:
     p.g[:] = [float(c) for c in d["g"]]
     p.newton_maxit = int(d.get("newton_maxit", 50))
     p.force_mode = int(d.get("force_mode", 0))
+    c = d.get("contact")
+    if c:
+        p.cs, p.mu_f, p.delta_c = float(c["cs"]), float(c["mu_f"]), float(c["delta_c"])
+        p.sub_origin[:] = [float(v) for v in c["origin"]]
+        p.sub_dx = float(c["spacing"])
+        p.sub_n[:] = [int(v) for v in c["n"]]
     return p
 
 
 def params_dict(p: OracleParams) -> dict:
-    d = {k: getattr(p, k) for k, _ in OracleParams._fields_ if k != "g"}
+    d = {k: getattr(p, k) for k, _ in OracleParams._fields_
+         if k not in ("g", "cs", "mu_f", "delta_c", "sub_origin", "sub_dx", "sub_n")}
     d["g"] = list(p.g)
+    if p.cs > 0.0:
+        d["contact"] = dict(cs=p.cs, mu_f=p.mu_f, delta_c=p.delta_c, origin=list(p.sub_origin),
+                            spacing=p.sub_dx, n=list(p.sub_n))
     return d
 
 

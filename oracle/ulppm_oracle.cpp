@@ -31,7 +31,10 @@
 //   1/det(I - dt L_i); EOM sign of Eq. 33; the force state of bond (i,k)
 //   collects the sub-horizon force states of all sub-horizons holding k
 //   (Eqs. 27, 31, 35), since keeping only the bond's own term (Eq. 51) with
-//   point-stored history is linearly unstable (flutter).
+//   point-stored history is linearly unstable (flutter); contact (Eqs. 91-93)
+//   with a rigid substrate of lattice sites, the pair integrand of Eq. 93
+//   equal to 2 (T_c + T_f), and the friction term of Eq. 92 as printed, along
+//   the pair direction.
 
 #include <algorithm>
 #include <cmath>
@@ -90,6 +93,10 @@ struct Params {             // mirrors OracleParams below, in scalar type R
   int newton_maxit;
   int force_mode;           // 0: conjugate force states (default), 1: Eq. 51 as printed,
                             // 2: standard full-horizon correspondence (Eq. 14)
+  // contact with a rigid substrate (Eqs. 91-93); cs == 0 turns it off
+  double cs, mu_f, delta_c;
+  double sub_origin[3], sub_dx;
+  int sub_n[3];
 };
 
 template <class R>
@@ -524,6 +531,48 @@ struct BondOut {
   std::vector<R> f;      // n*3 internal nodal force (Eqs. 49-50)
 };
 
+// Contact with a rigid substrate (Eqs. 91-93).  The substrate is a lattice of
+// fixed sites origin + dx (a, b, -c), each of volume dx^3.  For point i and a
+// site s with Y = x_s - x_i closer than delta_c:
+//   T_c = -C_s (delta_c - |Y|) Y/|Y|                      (Eq. 91)
+//   T_f = -mu_f sign(d|Y|/dt) T_c, d|Y|/dt = -Y.v_i/|Y|   (Eq. 92 as printed;
+//                                                           the site is at rest)
+// The reverse pair has Y' = -Y, so T_c' = -T_c and T_f' = -T_f, and the
+// contact integrand of Eq. 93 is 2 (T_c + T_f); with the volumes as
+// quadrature weights the nodal force gains V_i sum_s 2 (T_c + T_f) V_s.
+// Every site is visited (no search), so the neighbourhood is exactly the set
+// of sites with |Y|^2 < delta_c^2, the squared length rounded as
+// ((Y0^2 + Y1^2) + Y2^2).
+template <class R>
+void contact_forces(const Params& P, int64_t n, const R* x, const R* v, const std::vector<R>& vol,
+                    std::vector<R>& f) {
+  if (!(P.cs > 0.0)) return;
+  const double dc2 = P.delta_c * P.delta_c;
+  const double Vs = P.sub_dx * P.sub_dx * P.sub_dx;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    R acc[3] = {R(0.0), R(0.0), R(0.0)};
+    for (int c = 0; c < P.sub_n[2]; ++c)
+      for (int b = 0; b < P.sub_n[1]; ++b)
+        for (int a = 0; a < P.sub_n[0]; ++a) {
+          const double xs[3] = {P.sub_origin[0] + (double)a * P.sub_dx, P.sub_origin[1] + (double)b * P.sub_dx,
+                                P.sub_origin[2] - (double)c * P.sub_dx};
+          R Y[3];
+          for (int q = 0; q < 3; ++q) Y[q] = xs[q] - x[3 * i + q];
+          const double yv[3] = {val(Y[0]), val(Y[1]), val(Y[2])};
+          const double r2 = (yv[0] * yv[0] + yv[1] * yv[1]) + yv[2] * yv[2];
+          if (!(r2 < dc2) || r2 == 0.0) continue;
+          const R r = sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]);
+          const R tc = -P.cs * (P.delta_c - r) / r;                 // T_c = tc Y
+          const double rate = -(yv[0] * val(v[3 * i]) + yv[1] * val(v[3 * i + 1]) + yv[2] * val(v[3 * i + 2]));
+          const double sg = rate > 0.0 ? 1.0 : (rate < 0.0 ? -1.0 : 0.0);
+          const R w = 2.0 * Vs * tc * (1.0 - P.mu_f * sg);          // 2 (T_c + T_f) V_s = w Y
+          for (int q = 0; q < 3; ++q) acc[q] += w * Y[q];
+        }
+    for (int q = 0; q < 3; ++q) f[3 * i + q] += vol[i] * acc[q];
+  }
+}
+
 // Algorithm 1 at positions x (current configuration) with relative velocities
 // taken from vh, strain increment dt_inc * D_ij.  dt_inc = 0 gives the bond
 // stress equal to the point stress (used for the initial acceleration).
@@ -763,6 +812,7 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
     }
     for (int c = 0; c < 3; ++c) O.f[3 * i + c] = fi[c];
   }
+  contact_forces(P, n, x, vh, S.vol, O.f);
   st.n_bonds += nb;
   st.n_degenerate += n_deg;
   st.n_plastic += n_pl;
@@ -864,6 +914,9 @@ typedef struct {
   double newton_tol;
   int32_t newton_maxit;
   int32_t force_mode;
+  double cs, mu_f, delta_c;        // contact: stiffness C_s, friction mu_f, cut-off delta_c
+  double sub_origin[3], sub_dx;    // substrate sites origin + sub_dx (a, b, -c)
+  int32_t sub_n[3];                // a < sub_n[0], b < sub_n[1], c < sub_n[2]
 } OracleParams;
 
 typedef struct {             // host arrays, caller order
@@ -890,6 +943,14 @@ static Params to_params(const OracleParams* p) {
   P.newton_tol = p->newton_tol;
   P.newton_maxit = p->newton_maxit;
   P.force_mode = p->force_mode;
+  P.cs = p->cs;
+  P.mu_f = p->mu_f;
+  P.delta_c = p->delta_c;
+  for (int c = 0; c < 3; ++c) {
+    P.sub_origin[c] = p->sub_origin[c];
+    P.sub_n[c] = p->sub_n[c];
+  }
+  P.sub_dx = p->sub_dx;
   return P;
 }
 

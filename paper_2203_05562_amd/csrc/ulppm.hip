@@ -1934,14 +1934,15 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     const double* rz = &sZ[0].v[0];
     const int oa = fa < 4 ? fa : 4 * mf + fa - 4, ob = fb < 4 ? fb : 4 * mf + fb - 4,
               ov = fv < 4 ? fv : 4 * mf + fv - 4;
-    for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
-      double xj[kTileBatch][3];
-      bool jv[kTileBatch];
-      int jrow[kTileBatch];
-      v4d acc[kTileBatch];
-      unsigned piece[kTileBatch];
+    auto tiles = [&](int t0, auto nbc) {
+      constexpr int NB = decltype(nbc)::value;
+      double xj[NB][3];
+      bool jv[NB];
+      int jrow[NB];
+      v4d acc[NB];
+      unsigned piece[NB];
 #pragma unroll
-      for (int b = 0; b < kTileBatch; ++b) {
+      for (int b = 0; b < NB; ++b) {
         jrow[b] = (t0 + kBondWaves * b) * 16 + r16;
         jv[b] = jrow[b] < nf;
         const Quad<double> q = sX[jv[b] ? jrow[b] : 0];
@@ -1958,21 +1959,21 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         const double bval = kv ? fvv : 0.0;
         const unsigned sbit = 1u << (ks & 15);
 #pragma unroll
-        for (int b = 0; b < kTileBatch; ++b) {
+        for (int b = 0; b < NB; ++b) {
           const bool in = within(xj[b][0], xj[b][1], xj[b][2], xk.v[0], xk.v[1], xk.v[2], d2) & kv & jv[b];
           piece[b] |= in ? sbit : 0u;
           acc[b] = MM::run(in ? 1.0 : 0.0, bval, acc[b]);
         }
         if ((ks & 15) == 15 || ks == nks - 1) {
 #pragma unroll
-          for (int b = 0; b < kTileBatch; ++b) {
+          for (int b = 0; b < NB; ++b) {
             if (jv[b]) sq[((size_t)jrow[b] * nw + (ks >> 4)) * 4 + q4] = (unsigned short)piece[b];
             piece[b] = 0u;
           }
         }
       }
 #pragma unroll
-      for (int b = 0; b < kTileBatch; ++b) {
+      for (int b = 0; b < NB; ++b) {
         const int t = t0 + kBondWaves * b;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -1980,6 +1981,13 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
           if (j < nf) sKN[16 * (size_t)j + r16] = acc[b][r];
         }
       }
+    };
+    for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
+      const int nb = (ntile - t0 + kBondWaves - 1) / kBondWaves;     // slots left for this wave
+      if (nb >= 4) tiles(t0, std::integral_constant<int, 4>{});
+      else if (nb == 3) tiles(t0, std::integral_constant<int, 3>{});
+      else if (nb == 2) tiles(t0, std::integral_constant<int, 2>{});
+      else tiles(t0, std::integral_constant<int, 1>{});
     }
   }
   __syncthreads();
@@ -2204,12 +2212,13 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   // ---- reverse of the sums (R3): G_k = Ks_i + sum_j B_kj Ks_j, H_k = Nb_i + sum_j B_kj Nb_j.
   // The 15 columns [Ks_j | Nb_j] run on the matrix cores; rows k land in
   // sM (columns 0-9) and sR (columns 10-14), both free by now.
-  for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
-    v4d acc[kTileBatch];
-    unsigned piece[kTileBatch];
-    int krow[kTileBatch];
+  auto tiles2 = [&](int t0, auto nbc) {
+    constexpr int NB = decltype(nbc)::value;
+    v4d acc[NB];
+    unsigned piece[NB];
+    int krow[NB];
 #pragma unroll
-    for (int b = 0; b < kTileBatch; ++b) {
+    for (int b = 0; b < NB; ++b) {
       acc[b] = v4d{0, 0, 0, 0};
       piece[b] = 0u;
       krow[b] = (t0 + kBondWaves * b) * 16 + r16;
@@ -2222,17 +2231,17 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
       const int s = js & 15;
       if (s == 0) {
 #pragma unroll
-        for (int b = 0; b < kTileBatch; ++b) {
+        for (int b = 0; b < NB; ++b) {
           const bool rv = krow[b] < nf;
           const unsigned pw = sq[((size_t)(rv ? krow[b] : 0) * nw + (js >> 4)) * 4 + q4];
           piece[b] = rv ? pw : 0u;
         }
       }
 #pragma unroll
-      for (int b = 0; b < kTileBatch; ++b) acc[b] = MM::run((piece[b] >> s) & 1u ? 1.0 : 0.0, bval, acc[b]);
+      for (int b = 0; b < NB; ++b) acc[b] = MM::run((piece[b] >> s) & 1u ? 1.0 : 0.0, bval, acc[b]);
     }
 #pragma unroll
-    for (int b = 0; b < kTileBatch; ++b) {
+    for (int b = 0; b < NB; ++b) {
       const int t = t0 + kBondWaves * b;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -2243,6 +2252,13 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         }
       }
     }
+  };
+  for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
+    const int nb = (ntile - t0 + kBondWaves - 1) / kBondWaves;
+    if (nb >= 4) tiles2(t0, std::integral_constant<int, 4>{});
+    else if (nb == 3) tiles2(t0, std::integral_constant<int, 3>{});
+    else if (nb == 2) tiles2(t0, std::integral_constant<int, 2>{});
+    else tiles2(t0, std::integral_constant<int, 1>{});
   }
   __syncthreads();
   double ox[3] = {0, 0, 0}, oy[3] = {0, 0, 0};

@@ -112,13 +112,14 @@ def default_params(cfg: ColumnConfig, suction_pa: float, **over) -> dict:
 
 def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
                 suction_kpa: Optional[float] = None, jitter: float = 0.05,
-                dims=None) -> dict:
+                dims=None, fixed_base: bool = True) -> dict:
     """Return the seeded column: arrays in caller (lattice) order plus params.
 
     Arrays (float64 unless stated):
       x0 (N,3), v0 (N,3) zeros, vol0 (N,), phi0 (N,), suction (N,) [Pa],
       fixed (N,) uint8, sig_geo (N,6) total K0 geostatic stress in Voigt
       order (xx, yy, zz, yz, xz, xy), tension positive.
+    fixed_base=False frees the bottom layer (a column resting on a substrate).
     """
     nx, ny, nz = dims if dims is not None else (cfg.nx, cfg.ny, cfg.nz)
     seed = cfg.seed if seed is None else seed
@@ -153,7 +154,7 @@ def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
         vol0=np.full(n, DX ** 3),
         phi0=np.full(n, phi0),
         suction=np.full(n, s),
-        fixed=(lat[:, 2] == 0).astype(np.uint8),
+        fixed=((lat[:, 2] == 0) & fixed_base).astype(np.uint8),
         sig_geo=sig,
         params=prm,
         suction_kpa=suction_kpa,
@@ -177,3 +178,42 @@ def runout_objective_weights(lattice: np.ndarray, dims) -> dict:
     top = np.nonzero(lattice[:, 2] == nz - 1)[0]
     axis = np.array([(nx - 1) * 0.5 * DX, (ny - 1) * 0.5 * DX])
     return dict(top=top, axis=axis, height=(nz - 0.5) * DX)
+
+
+# Substrate set-up for contact (Section 4.2: C_s, mu_f, delta_c = 0.8 dx).
+CONTACT = dict(mu_f=0.25, delta_c_over_dx=0.8, cs_ratio=15.0)
+
+
+def make_substrate(col: dict, extent: float = 1.0, layers: int = 1, mu_f: Optional[float] = None,
+                   cs_ratio: Optional[float] = None, delta_c_over_dx: Optional[float] = None) -> dict:
+    """Rigid substrate lattice under a column, as a contact description.
+
+    Sites at origin + dx (a, b, -c) for a < n[0], b < n[1], c < n[2] =
+    layers, spacing dx: the column footprint plus `extent` times its larger
+    width on every side.  The top layer lies 0.9 delta_c below the lowest
+    point, so no point starts within the cut-off.
+
+    Set-up readings (not the method):
+      * C_s: the paper's value is for a 2D model; here T_c is a force per
+        volume squared, so C_s carries N/m^7, set to cs_ratio times the
+        micromodulus 18 K / (pi delta^4) of a bond-based material with the
+        column's bulk modulus and horizon.
+      * delta_c = 0.8 dx and mu_f = 0.25 as stated for the collapse examples.
+    """
+    c = dict(CONTACT)
+    if mu_f is not None:
+        c["mu_f"] = mu_f
+    if cs_ratio is not None:
+        c["cs_ratio"] = cs_ratio
+    if delta_c_over_dx is not None:
+        c["delta_c_over_dx"] = delta_c_over_dx
+    prm = col["params"]
+    x0 = col["x0"]
+    lo, hi = x0.min(axis=0), x0.max(axis=0)
+    width = float(max(hi[0] - lo[0], hi[1] - lo[1]))
+    ox, oy = float(lo[0] - extent * width), float(lo[1] - extent * width)
+    nx = int(math.ceil((hi[0] + extent * width - ox) / DX)) + 1
+    ny = int(math.ceil((hi[1] + extent * width - oy) / DX)) + 1
+    dc = c["delta_c_over_dx"] * DX
+    return dict(cs=c["cs_ratio"] * 18.0 * prm["K"] / (math.pi * prm["delta"] ** 4), mu_f=c["mu_f"],
+                delta_c=dc, origin=[ox, oy, float(lo[2] - 0.9 * dc)], spacing=DX, n=[nx, ny, int(layers)])

@@ -667,3 +667,82 @@ def test_standard_mode_linear_field_and_force_balance(olib):
     d2 = o2["sig_pt"][interior] - s0[interior]
     assert np.max(np.abs(d2 - d0)) <= 1e-9 * np.max(np.abs(d0))
     assert np.max(np.abs(o2["f"].sum(axis=0))) <= 1e-12 * np.max(np.abs(o2["f"]))
+
+
+# ---------------------------------------------------------------- contact --
+
+def contact_desc(olib, cs=2.6e15, mu_f=0.0, delta_c=0.8 * DX, origin=(0.0, 0.0, 0.0), n=(1, 1, 1)):
+    return dict(cs=cs, mu_f=mu_f, delta_c=delta_c, origin=list(origin), spacing=DX, n=list(n))
+
+
+def lone_point(olib, z, vz, g=0.0, **cont):
+    """One point (empty family) above a substrate site; returns S, prm."""
+    S = olib.empty_state(1)
+    S["x0"][0] = (0.0, 0.0, z)
+    S["v"][0] = (0.0, 0.0, vz)
+    S["vol"][:] = DX ** 3
+    S["phi"][:] = 0.4
+    S["J"][:] = 1.0
+    S["Sr"][:] = 1.0
+    S["mass"][:] = 2000 * DX ** 3
+    S["pc"][:] = -1e4
+    prm = mat_params(olib, contact=contact_desc(olib, **cont))
+    prm.g[:] = [0.0, 0.0, -g]
+    return S, prm
+
+
+def test_contact_force_closed_form(olib):
+    """Eqs. 91-93 for one site below the point: f = 2 C_s (delta_c - r) V_i V_s
+    along the pair, raised by (1 + mu_f) while the gap closes (Eq. 92) and
+    absent beyond delta_c; four sites symmetric about the point cancel
+    sideways."""
+    cs, dc, Vs = 2.6e15, 0.8 * DX, DX ** 3
+    for h, vz, mu in ((0.5 * DX, 0.0, 0.25), (0.3 * DX, -0.1, 0.25), (0.3 * DX, 0.1, 0.25), (0.9 * DX, -0.1, 0.25)):
+        S, prm = lone_point(olib, h, vz, cs=cs, mu_f=mu, delta_c=dc)
+        f = olib.bond_fields(S, prm, 0.0)["f"][0]
+        sg = 0.0 if vz == 0 else (1.0 if vz > 0 else -1.0)       # d|Y|/dt has the sign of vz here
+        expect = 2 * cs * max(dc - h, 0.0) * DX ** 3 * Vs * (1.0 - mu * sg)
+        assert abs(f[0]) == 0.0 and abs(f[1]) == 0.0
+        assert f[2] == pytest.approx(expect, rel=1e-14, abs=0.0)
+    # 2 x 2 sites at (+-dx/2, +-dx/2, 0) around the point's vertical
+    S, prm = lone_point(olib, 0.2 * DX, 0.0, cs=cs, delta_c=dc, origin=(-0.5 * DX, -0.5 * DX, 0.0), n=(2, 2, 1))
+    f = olib.bond_fields(S, prm, 0.0)["f"][0]
+    r = math.sqrt(0.2 ** 2 + 0.5) * DX
+    assert abs(f[0]) < 1e-12 * abs(f[2]) and abs(f[1]) < 1e-12 * abs(f[2])
+    assert f[2] == pytest.approx(4 * 2 * cs * (dc - r) * DX ** 3 * Vs * (0.2 * DX / r), rel=1e-13)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.25, 0.5])
+def test_contact_bounce_restitution(olib, mu):
+    """A point thrown at one site without gravity: the contact is a linear
+    spring of stiffness k (1 + mu_f) while the gap closes and k (1 - mu_f)
+    while it opens (Eqs. 91-92), so it leaves at v0 sqrt((1 - mu)/(1 + mu))
+    and the work it stored in W_int is the kinetic energy lost."""
+    v0 = 0.05
+    S, prm = lone_point(olib, 0.85 * DX, -v0, mu_f=mu)
+    prm.dt = 2e-6
+    k_over_m = 2 * 2.6e15 * DX ** 3 / 2000.0
+    t_contact = math.pi / math.sqrt(k_over_m) * 0.5 * (1 / math.sqrt(1 + mu) + 1 / math.sqrt(max(1 - mu, 1e-9)))
+    nsteps = int((2 * 0.05 * DX / v0 + t_contact) / prm.dt) + 200
+    rc, E, _ = olib.step(S, prm, nsteps)
+    assert rc == 0
+    assert S["x0"][0, 2] + S["u"][0, 2] > 0.8 * DX               # out of contact again
+    v1 = S["v"][0, 2]
+    assert v1 == pytest.approx(v0 * math.sqrt((1 - mu) / (1 + mu)), rel=2e-3)
+    m = S["mass"][0]
+    assert E[0] == pytest.approx(0.5 * m * (v0 * v0 - v1 * v1), rel=1e-6, abs=1e-9 * m * v0 * v0)
+    assert E[2] == pytest.approx(0.5 * m * v1 * v1, rel=1e-12)
+
+
+def test_contact_rest_under_gravity(olib):
+    """Eq. 93 with gravity: a point dropped onto one site settles (mu_f > 0
+    dissipates) towards the gap where 2 C_s (delta_c - r) V_i V_s = m g."""
+    S, prm = lone_point(olib, 0.79 * DX, 0.0, g=9.81, mu_f=0.5)
+    prm.dt = 2e-6
+    rc, E, _ = olib.step(S, prm, 60000)
+    assert rc == 0
+    m = S["mass"][0]
+    r_eq = 0.8 * DX - m * 9.81 / (2 * 2.6e15 * DX ** 3 * DX ** 3)
+    z = S["x0"][0, 2] + S["u"][0, 2]
+    assert z == pytest.approx(r_eq, rel=1e-4)
+    assert abs(E[0] + E[2] - E[1]) < 1e-6 * abs(E[1])          # Eq. 69 with contact work in W_int
