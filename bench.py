@@ -29,6 +29,9 @@ its throughput, speed-up and relative L2 errors of u, sigma and v against
 the FP64 run after warmup + steps steps.  "adjoint": the checkpointed
 differentiable column (24x24x48 by default, 1000 steps, checkpoint every 50),
 time per forward step, per reverse step (ulppm_adjoint_step) and their ratio.
+"contact": the same column standing free on a rigid substrate lattice
+(Eqs. 91-93, the substrate one column width wider on every side), its
+throughput and gather phase, the kernel that adds the contact forces.
 """
 import argparse
 import hashlib
@@ -95,13 +98,16 @@ def cpu_baseline(cfg_name, steps, dt):
                 seconds=round(el, 3))
 
 
-def run_column(ulppm, col, precision, warmup, steps, timed=True):
+def run_column(ulppm, col, precision, warmup, steps, timed=True, contact=None):
     """Initial conditions, dt = dt_c / 2, `warmup` untimed steps, then
-    `steps` steps timed with HIP events on the library's stream."""
+    `steps` steps timed with HIP events on the library's stream.  `contact`
+    attaches a substrate (Eqs. 91-93) first."""
     import torch
     G = ulppm.column_state(col, "cuda:0")
     prm = ulppm.make_params(col["params"], precision=precision)
     ctx = ulppm.Context(col["n"])
+    if contact:
+        ctx.set_contact(contact)
     ctx.init_state(G, prm, col["params"]["ocr"])
     prm.dt = 0.5 * ctx.dt_crit(G, prm)
     if warmup:
@@ -138,6 +144,7 @@ def main():
     ap.add_argument("--adjoint-config", default="C3", help="configuration of the adjoint cost line ('' skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--adjoint-every", type=int, default=50)
+    ap.add_argument("--no-contact", action="store_true", help="skip the substrate-contact companion run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -189,6 +196,20 @@ def main():
         del Gm
     del G
     torch.cuda.empty_cache()
+    if not args.no_contact:
+        colc = inputs.make_column(cfg, fixed_base=False)
+        sub = inputs.make_substrate(colc)
+        Gc, repc, msc, _ = run_column(ulppm, colc, prec, args.warmup, args.steps, contact=sub)
+        vc = repc["n_bond_updates"] / (msc * 1e-3)
+        lc = max(repc["timed_steps"], 1)
+        out["contact"] = dict(value=vc, ms_per_step=msc / args.steps,
+                              sites=int(sub["n"][0] * sub["n"][1] * sub["n"][2]), mu_f=sub["mu_f"],
+                              delta_c=sub["delta_c"], cs=sub["cs"],
+                              gather_ms=round(repc["t_gather_ms"] / lc, 4),
+                              gather_ms_without=phases["gather"])
+        log(f"[gpu] contact: {out['contact']}")
+        del Gc
+        torch.cuda.empty_cache()
     if args.adjoint_config:
         from paper_2203_05562_amd.measure import adjoint_cost
         out["adjoint"] = adjoint_cost(args.adjoint_config, args.adjoint_steps, args.adjoint_every, "fp64")

@@ -135,6 +135,39 @@ int ulppm_destroy(ulppm_ctx *ctx);
 /* Text of the last error on this context (static storage inside the context). */
 const char *ulppm_last_error(const ulppm_ctx *ctx);
 
+/* Contact with a rigid substrate (Eqs. 91-93), held by the context.
+ * The substrate is a lattice of fixed sites origin + spacing (a, b, -c),
+ * a < n[0], b < n[1], c < n[2] (layers go down from origin), each of volume
+ * spacing^3; it carries contact only (no bonds with the points).  For point i
+ * and a site s with Y = x_s - x_i and |Y|^2 < delta_c^2 (rounded as
+ * ((Y0^2 + Y1^2) + Y2^2)):
+ *   T_c = -cs (delta_c - |Y|) Y/|Y|                       (Eq. 91)
+ *   T_f = -mu_f sign(d|Y|/dt) T_c, d|Y|/dt = -Y.v_i/|Y|    (Eq. 92 as printed)
+ * and the nodal force gains V_i sum_s 2 (T_c + T_f) V_s: the contact integrand
+ * of Eq. 93, with the reverse pair's states T_c' = -T_c, T_f' = -T_f.  v_i is
+ * the step's velocity predictor in ulppm_step and the state velocity in
+ * ulppm_forces / ulppm_init_state; V_i the point volume of step n.  cs is a
+ * force per volume squared per length [N/m^7].  The work of contact forces is
+ * booked in W_int (the substrate is at rest and does no work), so the energy
+ * balance of Eq. 69 is unchanged.  ulppm_dt_crit ignores contact. */
+typedef struct {
+  double cs;                    /* contact stiffness C_s of Eq. 91 [N/m^7]; <= 0 turns contact off */
+  double mu_f;                  /* friction coefficient of Eq. 92 */
+  double delta_c;               /* cut-off distance of the repulsion [m] */
+  double origin[3];             /* position of site (0, 0, 0) [m] */
+  double spacing;               /* lattice spacing [m] */
+  int32_t n[3];                 /* sites along x, y and layers downward */
+  int32_t pad;
+} ulppm_contact;
+
+/* Attach (or, with c == NULL or c->cs <= 0, detach) the substrate; the
+ * description is copied into the context and used by every later
+ * ulppm_init_state, ulppm_forces and ulppm_step.  The adjoint entry points
+ * return ULPPM_E_ARG while contact is on (contact is not differentiated).
+ * Errors: ULPPM_E_ARG (spacing or delta_c <= 0, a count < 1, or more than
+ * 2^31-1 sites). */
+int ulppm_set_contact(ulppm_ctx *ctx, const ulppm_contact *c);
+
 /* Initial conditions of the explicit scheme (Algorithm 2, set-up and initial
  * acceleration).  On entry sig holds the TOTAL stress, phi the initial
  * porosity, vol the initial volume, s the suction, v the initial velocity.
@@ -174,6 +207,7 @@ int ulppm_build_families(ulppm_ctx *ctx, const ulppm_state *state, const ulppm_p
  * written to f[3] (device, length n each).  T_out, if non-NULL, receives the
  * bond force states as three device arrays of length n_bonds (x, y, z), in the
  * CSR order of ulppm_build_families.  rep (host) may be NULL.
+ * With a substrate attached (ulppm_set_contact) f includes the contact forces.
  * Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_NOCONV, ULPPM_E_HIP. */
 int ulppm_forces(ulppm_ctx *ctx, const ulppm_state *state, const ulppm_params *p, double dt_inc,
                  double *f[3], double *T_out[3], ulppm_report *rep);

@@ -33,7 +33,8 @@ class OracleParams(C.Structure):
                 ("a2", C.c_double), ("n_vg", C.c_double), ("g", C.c_double * 3), ("dt", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("force_mode", C.c_int32),
                 ("cs", C.c_double), ("mu_f", C.c_double), ("delta_c", C.c_double),
-                ("sub_origin", C.c_double * 3), ("sub_dx", C.c_double), ("sub_n", C.c_int32 * 3)]
+                ("sub_origin", C.c_double * 3), ("sub_dx", C.c_double), ("sub_n", C.c_int32 * 3),
+                ("plane", C.c_int32)]
 
 
 class OracleState(C.Structure):
@@ -103,6 +104,7 @@ def make_params(prm: dict, **over) -> OracleParams:
     p.g[:] = [float(c) for c in d["g"]]
     p.newton_maxit = int(d.get("newton_maxit", 50))
     p.force_mode = int(d.get("force_mode", 0))
+    p.plane = int(d.get("plane", 0))
     c = d.get("contact")
     if c:
         p.cs, p.mu_f, p.delta_c = float(c["cs"]), float(c["mu_f"]), float(c["delta_c"])

@@ -34,7 +34,9 @@
 //   point-stored history is linearly unstable (flutter); contact (Eqs. 91-93)
 //   with a rigid substrate of lattice sites, the pair integrand of Eq. 93
 //   equal to 2 (T_c + T_f), and the friction term of Eq. 92 as printed, along
-//   the pair direction.
+//   the pair direction; plane strain as the x-z plane with unit thickness, the
+//   shape tensors inverted on their x-z block and the bond micromodulus
+//   72 K / (5 pi delta^3) in the time-step bound.
 
 #include <algorithm>
 #include <cmath>
@@ -97,6 +99,7 @@ struct Params {             // mirrors OracleParams below, in scalar type R
   double cs, mu_f, delta_c;
   double sub_origin[3], sub_dx;
   int sub_n[3];
+  int plane;                // 1: plane strain in x-z (y out of plane, unit thickness)
 };
 
 template <class R>
@@ -144,6 +147,35 @@ void matmul3(const R* A, const R* B, R* C) {
       C[3 * r + c] = s;
     }
 }
+
+// Inverse of a shape tensor K (Voigt xx, yy, zz, yz, xz, xy) built from
+// `count` members, or false when it is degenerate: fewer members than
+// dimensions, or det K <= 1e-12 (tr K / d)^d.  In plane strain (x-z plane, y
+// out of plane) only the x-z block is inverted; the y row and column of the
+// inverse are zero, so no gradient or force state gains a y component.
+template <class R>
+bool shape_inverse(const Params& P, const R* K6, int64_t count, R* Kinv) {
+  if (!P.plane) {
+    R KF[9];
+    sym_to_full(K6, KF);
+    const R dK = det3(KF);
+    const double trk = val(K6[0] + K6[1] + K6[2]) / 3.0;
+    if (count < 3 || !(val(dK) > 1e-12 * trk * trk * trk)) return false;
+    inv3(KF, dK, Kinv);
+    return true;
+  }
+  const R a = K6[0], c = K6[2], e = K6[4];
+  const R d2 = a * c - e * e;
+  const double tr = val(a + c) / 2.0;
+  if (count < 2 || !(val(d2) > 1e-12 * tr * tr)) return false;
+  for (int k = 0; k < 9; ++k) Kinv[k] = R(0.0);
+  Kinv[0] = c / d2;
+  Kinv[2] = -e / d2;
+  Kinv[6] = -e / d2;
+  Kinv[8] = a / d2;
+  return true;
+}
+
 
 // Canonical squared distance |b - a|^2: each difference and product rounded,
 // summed as ((dx^2 + dy^2) + dz^2).  Families (Eq. 1) and sub-horizons
@@ -548,7 +580,7 @@ void contact_forces(const Params& P, int64_t n, const R* x, const R* v, const st
                     std::vector<R>& f) {
   if (!(P.cs > 0.0)) return;
   const double dc2 = P.delta_c * P.delta_c;
-  const double Vs = P.sub_dx * P.sub_dx * P.sub_dx;
+  const double Vs = P.plane ? P.sub_dx * P.sub_dx : P.sub_dx * P.sub_dx * P.sub_dx;   // unit thickness in plane strain
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     R acc[3] = {R(0.0), R(0.0), R(0.0)};
@@ -623,15 +655,10 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
         for (int b = 0; b < 3; ++b) Ni[3 * a + b] += V * y[a] * z[b];
     }
     R Jd = 1.0;
-    R KF[9];
-    sym_to_full(Ki, KF);
-    R dK = det3(KF);
-    double trk = val(Ki[0] + Ki[1] + Ki[2]) / 3.0;
-    const bool full_ok = nfam >= 3 && val(dK) > 1e-12 * trk * trk * trk;
     R Kinv[9], Li[9];
+    const bool full_ok = shape_inverse(P, Ki, nfam, Kinv);
     if (full_ok) {
       R B[9];
-      inv3(KF, dK, Kinv);
       matmul3(Ni, Kinv, Li);
       for (int k = 0; k < 9; ++k) B[k] = (k % 4 == 0 ? R(1.0) : R(0.0)) - dt_inc * Li[k];
       Jd = 1.0 / det3(B);
@@ -719,17 +746,12 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
       n_trip += nsub;
       O.nsub[s] = nsub;
       for (int k = 0; k < 6; ++k) O.K[6 * s + k] = Kij[k];
-      R KF[9];
-      sym_to_full(Kij, KF);
-      R dK = det3(KF);
-      double trk = val(Kij[0] + Kij[1] + Kij[2]) / 3.0;
-      if (nsub < 3 || !(val(dK) > 1e-12 * trk * trk * trk)) {   // degenerate bond: inactive
+      R Kinv[9], L[9];
+      if (!shape_inverse(P, Kij, nsub, Kinv)) {                 // degenerate bond: inactive
         ++n_deg;
         continue;
       }
       O.active[s] = 1;
-      R Kinv[9], L[9];
-      inv3(KF, dK, Kinv);
       matmul3(Nij, Kinv, L);
       for (int k = 0; k < 9; ++k) O.L[9 * s + k] = L[k];
       R varpi = Vs / Vh;
@@ -917,6 +939,7 @@ typedef struct {
   double cs, mu_f, delta_c;        // contact: stiffness C_s, friction mu_f, cut-off delta_c
   double sub_origin[3], sub_dx;    // substrate sites origin + sub_dx (a, b, -c)
   int32_t sub_n[3];                // a < sub_n[0], b < sub_n[1], c < sub_n[2]
+  int32_t plane;                   // 1: plane strain in the x-z plane
 } OracleParams;
 
 typedef struct {             // host arrays, caller order
@@ -951,6 +974,7 @@ static Params to_params(const OracleParams* p) {
     P.sub_n[c] = p->sub_n[c];
   }
   P.sub_dx = p->sub_dx;
+  P.plane = p->plane;
   return P;
 }
 
@@ -1129,7 +1153,9 @@ double oracle_dt_crit(const OracleParams* op, const OracleState* os) {
   for (int64_t k = 0; k < 3 * n; ++k) x[k] = os->x0[k] + os->u[k];
   Families F;
   build_families_cells(n, x.data(), P.delta, F);
-  const double C = 18.0 * P.K / (M_PI * std::pow(P.delta, 4));
+  // bond micromodulus: 3D, or plane strain per unit thickness (Poisson 1/4)
+  const double C = P.plane ? 72.0 * P.K / (5.0 * M_PI * std::pow(P.delta, 3))
+                           : 18.0 * P.K / (M_PI * std::pow(P.delta, 4));
   double best = INFINITY;
   for (int64_t i = 0; i < n; ++i) {
     double sum = 0.0;

@@ -2435,6 +2435,12 @@ __global__ void k_adj_init(ulppm_state S, ulppm_state B, DevParams P, double ocr
 
 enum { G_FORCES = 0, G_INIT = 1, G_STEP = 2 };
 
+// Substrate of the contact model, as the kernels read it.
+struct ContactDev {
+  double cs, mu_f, dc, dc2, ox, oy, oz, h, Vs;
+  int32_t nx, ny, nz, on;
+};
+
 struct GatherArgs {
   int64_t n, per;
   const int64_t* row;
@@ -2452,7 +2458,52 @@ struct GatherArgs {
   unsigned long long* ctr;
   double hdt, g0, g1, g2;
   int mode;
+  const double* x;        // 3n current positions (contact)
+  ContactDev c;
 };
+
+// Inclusive index range of lattice sites whose coordinate lies within
+// (t_lo, t_hi) in units of the spacing, widened by one site on each side and
+// clipped to [0, n); empty when lo > hi.
+__device__ __forceinline__ void site_range(double t_lo, double t_hi, int n, int* lo, int* hi) {
+  const double a = floor(t_lo) - 1.0, b = ceil(t_hi) + 1.0;
+  if (!(b >= 0.0) || !(a <= (double)(n - 1))) { *lo = 0; *hi = -1; return; }
+  *lo = a < 0.0 ? 0 : (int)a;
+  *hi = b > (double)(n - 1) ? n - 1 : (int)b;
+}
+
+// Contact force density on point i from the substrate sites within delta_c
+// (Eqs. 91-93): sum_s 2 (T_c + T_f) V_s with T_c = -C_s (delta_c - |Y|) Y/|Y|,
+// T_f = -mu_f sign(d|Y|/dt) T_c, Y = x_s - x_i, d|Y|/dt = -Y.v_i/|Y|.  Lanes
+// take the sites of the candidate box; the caller reduces over the wave.
+__device__ void contact_density(const ContactDev& C, double xi, double yi, double zi, double vx, double vy,
+                                double vz, int lane, double* out) {
+#pragma clang fp contract(off)
+  out[0] = out[1] = out[2] = 0.0;
+  int a0, a1, b0, b1, k0, k1;
+  site_range((xi - C.dc - C.ox) / C.h, (xi + C.dc - C.ox) / C.h, C.nx, &a0, &a1);
+  site_range((yi - C.dc - C.oy) / C.h, (yi + C.dc - C.oy) / C.h, C.ny, &b0, &b1);
+  site_range((C.oz - zi - C.dc) / C.h, (C.oz - zi + C.dc) / C.h, C.nz, &k0, &k1);
+  if (a1 < a0 || b1 < b0 || k1 < k0) return;
+  const int na = a1 - a0 + 1, nb = b1 - b0 + 1;
+  const int64_t total = (int64_t)na * nb * (k1 - k0 + 1);
+  for (int64_t e = lane; e < total; e += kWave) {
+    const int a = a0 + (int)(e % na), b = b0 + (int)((e / na) % nb), k = k0 + (int)(e / ((int64_t)na * nb));
+    const double Y0 = (C.ox + (double)a * C.h) - xi;
+    const double Y1 = (C.oy + (double)b * C.h) - yi;
+    const double Y2 = (C.oz - (double)k * C.h) - zi;
+    const double r2 = (Y0 * Y0 + Y1 * Y1) + Y2 * Y2;
+    if (!(r2 < C.dc2) || r2 == 0.0) continue;
+    const double r = sqrt(r2);
+    const double tc = -C.cs * (C.dc - r) / r;                  // T_c = tc Y
+    const double rate = -(Y0 * vx + Y1 * vy + Y2 * vz);         // |Y| d|Y|/dt
+    const double sg = rate > 0.0 ? 1.0 : (rate < 0.0 ? -1.0 : 0.0);
+    const double w = 2.0 * C.Vs * tc * (1.0 - C.mu_f * sg);    // 2 (T_c + T_f) V_s = w Y
+    out[0] += w * Y0;
+    out[1] += w * Y1;
+    out[2] += w * Y2;
+  }
+}
 
 // One wave per point: f_i = V_i sum_j (T_ij - T_ji) V_j (Eqs. 49-50, sign of
 // Eq. 33), gathering T_ji through rev[] instead of scattering with atomics;
@@ -2479,9 +2530,18 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
     f0 = wave_sum(f0);
     f1 = wave_sum(f1);
     f2 = wave_sum(f2);
+    double fc[3] = {0.0, 0.0, 0.0};
+    if (G.c.on) {
+      contact_density(G.c, G.x[i], G.x[G.n + i], G.x[2 * G.n + i], G.vh[i], G.vh[G.n + i], G.vh[2 * G.n + i],
+                      lane, fc);
+      fc[0] = wave_sum(fc[0]);
+      fc[1] = wave_sum(fc[1]);
+      fc[2] = wave_sum(fc[2]);
+    }
     if (lane == 0) {
       const double Vi = G.vol_n[i];
-      const double f[3] = {(double)f0 * Vi, (double)f1 * Vi, (double)f2 * Vi};
+      const double f[3] = {(double)f0 * Vi + Vi * fc[0], (double)f1 * Vi + Vi * fc[1],
+                           (double)f2 * Vi + Vi * fc[2]};
       if (G.mode == G_FORCES) {
         for (int c = 0; c < 3; ++c) G.f[c][i] = f[c];
       } else {
@@ -2678,6 +2738,7 @@ struct ulppm_ctx {
   unsigned long long* ctr = nullptr;      // C_NCOUNT x kStripes
   unsigned long long* ctr_sum = nullptr;  // C_NCOUNT, folded
   double* E = nullptr;        // 3
+  ContactDev contact = {};    // substrate (ulppm_set_contact); off by default
   // adjoint scratch (ulppm_adjoint_reserve)
   double* adj = nullptr;      // 24n forward copy + 21n point adjoints + 4(n+8) partials
   double* adj_slot = nullptr; // 7 x bond_cap
@@ -2925,6 +2986,8 @@ int gather_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int
   G.hdt = 0.5 * p->dt;
   G.g0 = p->g[0]; G.g1 = p->g[1]; G.g2 = p->g[2];
   G.mode = mode;
+  G.x = ctx->x;
+  G.c = ctx->contact;
   const unsigned grid = walk_grid(n);
   if (mode == G_STEP && (int64_t)grid * 3 + kPartGather > ctx->part_cap) return fail(ctx, ULPPM_E_ARG, "partials too small");
   if (mixed)
@@ -3382,6 +3445,35 @@ size_t adj_lds(int max_f) {
                           (size_t)((max_f + 63) / 64) * sizeof(unsigned long long));
 }
 
+int ulppm_set_contact(ulppm_ctx* ctx, const ulppm_contact* c) {
+  if (!ctx) return ULPPM_E_ARG;
+  if (!c || !(c->cs > 0.0)) {
+    ctx->contact = ContactDev{};
+    return ULPPM_OK;
+  }
+  if (!(c->spacing > 0.0) || !(c->delta_c > 0.0) || !(c->mu_f >= 0.0) || !std::isfinite(c->cs) ||
+      !std::isfinite(c->origin[0]) || !std::isfinite(c->origin[1]) || !std::isfinite(c->origin[2]))
+    return fail(ctx, ULPPM_E_ARG, "contact: spacing and delta_c must be > 0, mu_f >= 0, values finite");
+  if (c->n[0] < 1 || c->n[1] < 1 || c->n[2] < 1 || (int64_t)c->n[0] * c->n[1] * c->n[2] > 2147483647LL)
+    return fail(ctx, ULPPM_E_ARG, "contact: site counts must be >= 1 with at most 2^31-1 sites");
+  ContactDev d;
+  d.cs = c->cs;
+  d.mu_f = c->mu_f;
+  d.dc = c->delta_c;
+  d.dc2 = c->delta_c * c->delta_c;
+  d.ox = c->origin[0];
+  d.oy = c->origin[1];
+  d.oz = c->origin[2];
+  d.h = c->spacing;
+  d.Vs = c->spacing * c->spacing * c->spacing;
+  d.nx = c->n[0];
+  d.ny = c->n[1];
+  d.nz = c->n[2];
+  d.on = 1;
+  ctx->contact = d;
+  return ULPPM_OK;
+}
+
 int ulppm_adjoint_reserve(ulppm_ctx* ctx) {
   if (!ctx) return ULPPM_E_ARG;
   if (ctx->adj) return ULPPM_OK;
@@ -3408,6 +3500,7 @@ int ulppm_adjoint_init(ulppm_ctx* ctx, const ulppm_state* S0, const ulppm_params
   if ((rc = check_params(ctx, p))) return rc;
   if (!s_bar || !theta_bar) return fail(ctx, ULPPM_E_ARG, "s_bar or theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
+  if (ctx->contact.on) return fail(ctx, ULPPM_E_ARG, "the adjoint does not include contact forces");
   if (!(ocr >= 1.0)) return fail(ctx, ULPPM_E_ARG, "ocr must be >= 1");
   const int64_t n = S0->n;
   if (adj0->n != n) return fail(ctx, ULPPM_E_ARG, "adjoint state must match the state size");
@@ -3471,6 +3564,7 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
   if ((rc = check_params(ctx, p))) return rc;
   if (!theta_bar) return fail(ctx, ULPPM_E_ARG, "theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
+  if (ctx->contact.on) return fail(ctx, ULPPM_E_ARG, "the adjoint does not include contact forces");
   if (p->precision != ULPPM_FP64 || p->force_mode != ULPPM_FORCE_CONJUGATE)
     return fail(ctx, ULPPM_E_ARG, "the adjoint supports FP64 with conjugate force states");
   if (!(p->dt > 0.0)) return fail(ctx, ULPPM_E_ARG, "dt must be > 0");

@@ -16,6 +16,12 @@ available, so every input here is synthetic):
     C2  80 x 80 x 160  = 1,024,000 points, seed 2, suction 20 kPa, mixed precision
     C3  24 x 24 x 48   =    27,648 points, seed 3, suction 20 kPa, adjoint
     C4  128 x 128 x 256 = 4,194,304 points, seed 4, suction 20 kPa, mixed + adjoint
+    P0  24 x 48 plane strain   =   1,152 points, seed 10, suction 20 kPa, FP64
+    P1  512 x 1024 plane strain = 524,288 points, seed 11, suction 20 kPa, FP64
+
+Plane-strain columns (the paper's examples are 2D) lie in the x-z plane at
+y = 0 with jitter in x and z only; each point's volume is dx^2 times a unit
+thickness.
 
 Lattice: index = ix + nx*(iy + ny*iz), z vertical, spacing dx = 0.01 m,
 x = (ix, iy, iz)*dx + U(-0.05, 0.05)*dx per component (drawn first from
@@ -45,6 +51,7 @@ class ColumnConfig:
     steps: int
     precision: str                  # "fp64" or "mixed"
     checkpoint_every: int = 0
+    plane: bool = False             # plane strain in the x-z plane (ny = 1)
 
     @property
     def n_points(self) -> int:
@@ -57,6 +64,8 @@ CONFIGS: Dict[str, ColumnConfig] = {
     "C2": ColumnConfig("C2", 80, 80, 160, 2, 20.0, 1000, "mixed"),
     "C3": ColumnConfig("C3", 24, 24, 48, 3, 20.0, 1000, "fp64", checkpoint_every=50),
     "C4": ColumnConfig("C4", 128, 128, 256, 4, 20.0, 500, "mixed", checkpoint_every=25),
+    "P0": ColumnConfig("P0", 24, 1, 48, 10, 20.0, 200, "fp64", plane=True),
+    "P1": ColumnConfig("P1", 512, 1, 1024, 11, 20.0, 1000, "fp64", plane=True),
 }
 
 # Material constants.  Critical-state values (M, lambda, kappa, e0, tau,
@@ -122,12 +131,16 @@ def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
     fixed_base=False frees the bottom layer (a column resting on a substrate).
     """
     nx, ny, nz = dims if dims is not None else (cfg.nx, cfg.ny, cfg.nz)
+    if cfg.plane and ny != 1:
+        raise ValueError("a plane-strain column has ny = 1")
     seed = cfg.seed if seed is None else seed
     rng = np.random.default_rng(seed)
     n = nx * ny * nz
     iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     lat = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
     jit = rng.uniform(-jitter, jitter, (n, 3)) if jitter > 0 else np.zeros((n, 3))
+    if cfg.plane:
+        jit[:, 1] = 0.0
     x0 = (lat + jit) * DX
     if suction_kpa is None:
         suction_kpa = cfg.suction_kpa
@@ -135,6 +148,7 @@ def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
         suction_kpa = float(rng.uniform(10.0, 40.0))
     s = suction_kpa * 1e3
     prm = default_params(cfg, s)
+    prm["plane"] = 1 if cfg.plane else 0
     m = MATERIAL
     phi0 = m["e0"] / (1.0 + m["e0"])
     # K0 geostatic total stress: sigma_zz = -rho g depth, sigma_h = K0 sigma_zz,
@@ -151,7 +165,7 @@ def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
         n=n, dims=(nx, ny, nz), lattice=lat.astype(np.int64),
         x0=np.ascontiguousarray(x0),
         v0=np.zeros((n, 3)),
-        vol0=np.full(n, DX ** 3),
+        vol0=np.full(n, DX ** 2 if cfg.plane else DX ** 3),
         phi0=np.full(n, phi0),
         suction=np.full(n, s),
         fixed=((lat[:, 2] == 0) & fixed_base).astype(np.uint8),
@@ -211,9 +225,13 @@ def make_substrate(col: dict, extent: float = 1.0, layers: int = 1, mu_f: Option
     x0 = col["x0"]
     lo, hi = x0.min(axis=0), x0.max(axis=0)
     width = float(max(hi[0] - lo[0], hi[1] - lo[1]))
-    ox, oy = float(lo[0] - extent * width), float(lo[1] - extent * width)
+    ox = float(lo[0] - extent * width)
     nx = int(math.ceil((hi[0] + extent * width - ox) / DX)) + 1
-    ny = int(math.ceil((hi[1] + extent * width - oy) / DX)) + 1
+    if prm.get("plane"):
+        oy, ny = float(lo[1]), 1                  # one row of sites in the plane
+    else:
+        oy = float(lo[1] - extent * width)
+        ny = int(math.ceil((hi[1] + extent * width - oy) / DX)) + 1
     dc = c["delta_c_over_dx"] * DX
     return dict(cs=c["cs_ratio"] * 18.0 * prm["K"] / (math.pi * prm["delta"] ** 4), mu_f=c["mu_f"],
                 delta_c=dc, origin=[ox, oy, float(lo[2] - 0.9 * dc)], spacing=DX, n=[nx, ny, int(layers)])

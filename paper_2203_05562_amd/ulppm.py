@@ -53,9 +53,14 @@ class Report(C.Structure):
                 for k, t in self._fields_}
 
 
+class Contact(C.Structure):
+    _fields_ = [("cs", C.c_double), ("mu_f", C.c_double), ("delta_c", C.c_double), ("origin", C.c_double * 3),
+                ("spacing", C.c_double), ("n", C.c_int32 * 3), ("pad", C.c_int32)]
+
+
 EXPORTS = ["ulppm_create", "ulppm_destroy", "ulppm_last_error", "ulppm_init_state", "ulppm_dt_crit",
            "ulppm_build_families", "ulppm_forces", "ulppm_step", "ulppm_reset_energy", "ulppm_adjoint_reserve",
-           "ulppm_adjoint_step", "ulppm_adjoint_init", "ulppm_selfcheck_tail"]
+           "ulppm_adjoint_step", "ulppm_adjoint_init", "ulppm_selfcheck_tail", "ulppm_set_contact"]
 
 _lib = None
 
@@ -94,6 +99,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                      C.c_void_p, C.c_void_p]
     L.ulppm_selfcheck_tail.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32)]
+    L.ulppm_set_contact.argtypes = [vp, C.POINTER(Contact)]
     for name in EXPORTS:
         if name != "ulppm_last_error":
             getattr(L, name).restype = C.c_int
@@ -236,6 +242,19 @@ class Context:
         if rc != 0:
             msg = self.L.ulppm_last_error(self.h)
             raise UlppmError(rc, msg.decode() if msg else "")
+
+    def set_contact(self, desc=None):
+        """Attach the substrate described by `desc` (keys cs, mu_f, delta_c,
+        origin, spacing, n), or detach it with None."""
+        if not desc:
+            self._check(self.L.ulppm_set_contact(self.h, None))
+            return
+        c = Contact()
+        c.cs, c.mu_f, c.delta_c = float(desc["cs"]), float(desc["mu_f"]), float(desc["delta_c"])
+        c.origin[:] = [float(v) for v in desc["origin"]]
+        c.spacing = float(desc["spacing"])
+        c.n[:] = [int(v) for v in desc["n"]]
+        self._check(self.L.ulppm_set_contact(self.h, C.byref(c)))
 
     def init_state(self, S: DeviceState, p: Params, ocr: float):
         cs = S.cstruct()

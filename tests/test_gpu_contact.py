@@ -1,0 +1,179 @@
+"""Parity of the contact model (Eqs. 91-93, a rigid substrate lattice) between
+the HIP library and the CPU oracle, plus closed-form checks on the GPU.
+
+Bars: FP64 forces within 1e-12 of the largest force; frictionless
+trajectories within 1e-10 relative L2; the bounce of an isolated point at
+the restitution v0 sqrt((1 - mu_f)/(1 + mu_f)) of the piecewise-linear
+contact spring; mixed precision within 1e-5.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2203_05562_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DX = inputs.DX
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2203_05562_amd import ulppm
+    ulppm.load_library()
+    return ulppm
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, float).ravel()
+    b = np.asarray(b, float).ravel()
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def column_on_substrate(olib, gpu, dims, seed=0, vscale=0.0, mu_f=0.25, lift=0.5, layers=2,
+                        precision=None):
+    """A free-standing column (no fixed base) with the substrate raised by
+    lift * delta_c, so that its bottom layer starts inside the cut-off."""
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=seed, dims=dims, fixed_base=False)
+    sub = inputs.make_substrate(col, extent=0.5, layers=layers, mu_f=mu_f)
+    sub["origin"][2] += lift * sub["delta_c"]
+    oprm = olib.make_params(col["params"], contact=sub)
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    if vscale > 0:
+        S["v"][:] = inputs.random_velocity(col["n"], seed + 100, vscale)
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    over = {} if precision is None else dict(precision=precision)
+    gprm = gpu.make_params(olib.params_dict(oprm), **over)
+    ctx = gpu.Context(col["n"])
+    ctx.set_contact(sub)
+    G = gpu.DeviceState.from_arrays(S)
+    return col, sub, oprm, gprm, S, G, ctx
+
+
+@pytest.mark.parametrize("vscale,dtmul,layers", [(0.0, 0.0, 1), (0.05, 1.0, 2), (0.5, 1.0, 2)])
+def test_contact_forces_parity(olib, gpu, vscale, dtmul, layers):
+    say("contact forces", vscale, dtmul, layers)
+    col, sub, oprm, gprm, S, G, ctx = column_on_substrate(olib, gpu, (8, 8, 12), seed=2, vscale=vscale,
+                                                          layers=layers)
+    dt_inc = dtmul * oprm.dt
+    out = olib.bond_fields(S, oprm, dt_inc)
+    f, _, _ = ctx.forces(G, gprm, dt_inc)
+    fg = f.cpu().numpy().T
+    # the contact forces are a real part of the result
+    free = olib.bond_fields(S, olib.make_params(olib.params_dict(oprm) | {"contact": None}), dt_inc)["f"]
+    fscale = np.abs(out["f"]).max()
+    say("contact share", np.abs(out["f"] - free).max() / fscale, "maxerr", np.abs(fg - out["f"]).max() / fscale)
+    assert np.abs(out["f"] - free).max() > 1e-2 * fscale
+    assert np.abs(fg - out["f"]).max() <= 1e-12 * fscale
+
+
+def test_contact_init_and_frictionless_trajectory(olib, gpu):
+    """Initial acceleration with contact, then 300 steps of a column settling
+    on the substrate with mu_f = 0 (the contact force is continuous)."""
+    say("contact trajectory mu 0")
+    col, sub, oprm, gprm, S, G, ctx = column_on_substrate(olib, gpu, (6, 6, 10), seed=5, mu_f=0.0, lift=0.2)
+    Gi = gpu.column_state(col)
+    ctx.init_state(Gi, gprm, col["params"]["ocr"])
+    a_g = Gi.to_arrays()["a"]
+    assert np.abs(a_g - S["a"]).max() <= 1e-12 * np.abs(S["a"]).max()
+    E = np.zeros(3)
+    rc, E, st = olib.step(S, oprm, 300, E)
+    assert rc == 0
+    rep = ctx.step(G, gprm, 300)
+    Sg = G.to_arrays()
+    errs = {k: rel_l2(Sg[k], S[k]) for k in ("u", "v", "a", "sig", "pc", "J")}
+    say("300 steps", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert all(v <= 1e-10 for v in errs.values()), errs
+    assert abs(rep["W_int"] - E[0]) <= 1e-9 * abs(E[1])
+    # the base rests on the substrate: no point passed through it
+    z = (S["x0"] + S["u"])[:, 2]
+    assert z.min() > sub["origin"][2]
+
+
+def test_contact_friction_short_run(olib, gpu):
+    """mu_f = 0.25 over 40 steps: the friction sign is taken in FP64 on both
+    sides from the same predictor velocity."""
+    say("contact friction run")
+    col, sub, oprm, gprm, S, G, ctx = column_on_substrate(olib, gpu, (6, 6, 10), seed=6, mu_f=0.25,
+                                                          vscale=0.02)
+    rc, E, st = olib.step(S, oprm, 40)
+    assert rc == 0
+    ctx.step(G, gprm, 40)
+    Sg = G.to_arrays()
+    errs = {k: rel_l2(Sg[k], S[k]) for k in ("u", "v", "sig")}
+    say("40 steps", errs)
+    assert all(v <= 1e-10 for v in errs.values()), errs
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.25])
+def test_contact_bounce_closed_form(olib, gpu, mu):
+    """Isolated points thrown at the substrate without gravity rebound at
+    v0 sqrt((1 - mu)/(1 + mu)) (Eqs. 91-92), on both sides."""
+    say("bounce", mu)
+    n, v0 = 4, 0.05
+    S = olib.empty_state(n)
+    S["x0"][:] = [[10 * k * DX, 0.0, 0.81 * DX] for k in range(n)]
+    S["v"][:, 2] = -v0
+    S["vol"][:] = DX ** 3
+    S["phi"][:] = 0.4
+    S["J"][:] = 1.0
+    S["Sr"][:] = 1.0
+    S["mass"][:] = 2000 * DX ** 3
+    S["pc"][:] = -1e4
+    S["s"][:] = 2e4
+    col = inputs.make_column(inputs.CONFIGS["C0"], dims=(2, 2, 2))
+    sub = dict(cs=2.6e15, mu_f=mu, delta_c=0.8 * DX, origin=[0.0, 0.0, 0.0], spacing=DX, n=[32, 1, 1])
+    oprm = olib.make_params(col["params"], contact=sub)
+    oprm.g[:] = [0.0, 0.0, 0.0]
+    oprm.dt = 2e-6
+    gprm = gpu.make_params(olib.params_dict(oprm))
+    ctx = gpu.Context(n)
+    ctx.set_contact(sub)
+    G = gpu.DeviceState.from_arrays(S)
+    nsteps = 3000
+    rc, E, _ = olib.step(S, oprm, nsteps)
+    assert rc == 0
+    ctx.step(G, gprm, nsteps)
+    vz = G.to_arrays()["v"][:, 2]
+    say("rebound", vz / v0, math.sqrt((1 - mu) / (1 + mu)))
+    assert np.all(np.abs(vz - v0 * math.sqrt((1 - mu) / (1 + mu))) <= 2e-3 * v0)
+    assert np.abs(vz - S["v"][:, 2]).max() <= 1e-12 * v0
+
+
+def test_contact_mixed_precision_forces(olib, gpu):
+    say("contact mixed")
+    col, sub, oprm, gprm, S, G, ctx = column_on_substrate(olib, gpu, (8, 8, 12), seed=3, vscale=0.05,
+                                                          precision=gpu.ULPPM_MIXED)
+    out = olib.bond_fields(S, oprm, oprm.dt)
+    f, _, _ = ctx.forces(G, gprm, oprm.dt)
+    fg = f.cpu().numpy().T
+    e = np.abs(fg - out["f"]).max() / np.abs(out["f"]).max()
+    say("mixed maxerr", e)
+    assert e <= 1e-5
+
+
+def test_contact_off_and_adjoint_rejected(olib, gpu):
+    import torch
+    say("contact off / adjoint")
+    col, sub, oprm, gprm, S, G, ctx = column_on_substrate(olib, gpu, (6, 6, 8), seed=1, vscale=0.05)
+    ctx.adjoint_reserve()
+    theta_bar = torch.zeros(4, dtype=torch.float64, device="cuda")
+    A1 = gpu.DeviceState.from_arrays(olib.empty_state(col["n"]))
+    A0 = gpu.DeviceState.from_arrays(olib.empty_state(col["n"]))
+    with pytest.raises(gpu.UlppmError) as ei:
+        ctx.adjoint_step(G, gprm, A1, A0, theta_bar)
+    assert ei.value.code == -1
+    f_on, _, _ = ctx.forces(G, gprm, 0.0)
+    ctx.set_contact(None)
+    f_off, _, _ = ctx.forces(G, gprm, 0.0)
+    free = olib.bond_fields(S, olib.make_params(olib.params_dict(oprm) | {"contact": None}), 0.0)["f"]
+    assert np.abs(f_off.cpu().numpy().T - free).max() <= 1e-12 * np.abs(free).max()
+    assert not torch.equal(f_on, f_off)

@@ -746,3 +746,83 @@ def test_contact_rest_under_gravity(olib):
     z = S["x0"][0, 2] + S["u"][0, 2]
     assert z == pytest.approx(r_eq, rel=1e-4)
     assert abs(E[0] + E[2] - E[1]) < 1e-6 * abs(E[1])          # Eq. 69 with contact work in W_int
+
+
+# ------------------------------------------------------------ plane strain --
+
+def plane_state(olib, dims=(16, 1, 20), seed=10, jitter=0.05):
+    cfg = inputs.CONFIGS["P0"]
+    col = inputs.make_column(cfg, seed=seed, jitter=jitter, dims=dims)
+    prm = olib.make_params(col["params"])
+    S = olib.init_column(col, prm, col["params"]["ocr"])
+    return col, prm, S
+
+
+def test_plane_linear_field_reproduced_exactly(olib):
+    """Plane strain (x-z plane): for v = A x + c with A acting in the plane,
+    every non-degenerate gradient L_ij equals A, nothing leaves the plane, and
+    the volume increment is 1/det(I - dt A) of the in-plane block."""
+    col, prm, S = plane_state(olib)
+    rng = np.random.default_rng(5)
+    A = np.zeros((3, 3))
+    A[np.ix_([0, 2], [0, 2])] = rng.normal(size=(2, 2))
+    c = np.array([rng.normal(), 0.0, rng.normal()])
+    x = S["x0"] + S["u"]
+    S["v"][:] = x @ A.T + c
+    dt = 1e-3
+    out = olib.bond_fields(S, prm, dt)
+    act = out["active"] == 1
+    assert act.mean() > 0.99
+    L = out["L"][act].reshape(-1, 3, 3)
+    assert np.abs(L - A).max() <= 1e-11 * np.abs(A).max()
+    B = np.eye(2) - dt * A[np.ix_([0, 2], [0, 2])]
+    assert np.allclose(out["Jd"], 1.0 / np.linalg.det(B), rtol=1e-12, atol=0)
+    assert np.all(out["T"][:, 1] == 0.0) and np.all(out["f"][:, 1] == 0.0)
+
+
+def test_plane_dt_crit_closed_form(olib):
+    """Eq. 65 in plane strain with the 2D micromodulus C = 72K/(5 pi delta^3)
+    per unit thickness: interior points of the unjittered lattice hold the
+    disc family |n| <= 3.015 of Z^2 and set the minimum."""
+    col, prm, S = plane_state(olib, dims=(14, 1, 14), jitter=0.0)
+    disc = [n for n in itertools.product(range(-4, 5), repeat=2)
+            if n != (0, 0) and n[0] ** 2 + n[1] ** 2 <= D2_LATTICE]
+    assert len(disc) == 28
+    s_inv = sum(1.0 / math.hypot(*n) for n in disc)
+    C = 72 * prm.K / (5 * math.pi * prm.delta ** 3)
+    exp = math.sqrt(2 * (1 - S["phi"][0]) * prm.rho_s * DX / (DX ** 2 * C * s_inv))
+    assert abs(olib.dt_crit(S, prm) - exp) <= 1e-12 * exp
+
+
+def test_plane_strain_elastic_step(olib):
+    """An in-plane extension rate v_x = alpha x on a stress state inside the
+    yield surface: the out-of-plane strain stays zero, so one step adds
+    (K + 4mu/3) dt alpha to sigma_xx and (K - 2mu/3) dt alpha to sigma_yy and
+    sigma_zz (Hooke's law in plane strain)."""
+    col, prm, S = plane_state(olib, jitter=0.0)
+    set_uniform_stress(S, [-40e3, -40e3, -40e3, 0.0, 0.0, 0.0], -200e3, 0.0)
+    alpha, dt = 1e-2, 1e-4
+    x = S["x0"] + S["u"]
+    S["v"][:] = 0.0
+    S["v"][:, 0] = alpha * x[:, 0]
+    out = olib.bond_fields(S, prm, dt)
+    lat = col["lattice"]
+    interior = np.all((lat[:, [0, 2]] >= 4) & (lat[:, [0, 2]] <= np.array([11, 15])), axis=1)
+    d = out["sig_pt"][interior] - np.array([-40e3, -40e3, -40e3, 0, 0, 0])
+    de = alpha * dt
+    assert np.allclose(d[:, 0], (prm.K + 4 * prm.mu / 3) * de, rtol=1e-9)
+    assert np.allclose(d[:, 1], (prm.K - 2 * prm.mu / 3) * de, rtol=1e-9)
+    assert np.allclose(d[:, 2], (prm.K - 2 * prm.mu / 3) * de, rtol=1e-9)
+    assert np.abs(d[:, 3:]).max() <= 1e-9 * (prm.K * de)
+
+
+def test_plane_column_stays_in_plane(olib):
+    """A plane-strain column under gravity: no displacement, velocity or
+    acceleration leaves the x-z plane over 100 steps, and Eq. 69 holds."""
+    col, prm, S = plane_state(olib, dims=(12, 1, 24))
+    prm.dt = 0.5 * olib.dt_crit(S, prm)
+    E = np.zeros(3)
+    rc, E, st = olib.step(S, prm, 100, E)
+    assert rc == 0
+    assert np.all(S["u"][:, 1] == 0.0) and np.all(S["v"][:, 1] == 0.0) and np.all(S["a"][:, 1] == 0.0)
+    assert abs(E[0] + E[2] - E[1]) <= 1e-2 * max(abs(E[0]), abs(E[1]), abs(E[2]))
