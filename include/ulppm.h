@@ -83,8 +83,17 @@ typedef struct {
   int32_t force_mode;           /* ULPPM_FORCE_CONJUGATE or ULPPM_FORCE_EQ51 */
   double energy_tol;            /* epsilon of Eq. 69 (the paper uses ~1e-2) */
   int32_t timing;               /* nonzero: time each phase of ulppm_step with HIP events */
-  int32_t pad;
+  int32_t plane;                /* 1: plane strain in the x-z plane (see below); 0: 3D */
 } ulppm_params;
+
+/* Plane strain (plane = 1).  All points lie in one x-z plane (equal y) with
+ * v_y = 0, and every volume is an area times a unit thickness.  Shape tensors
+ * are inverted on their x-z block (a bond is inactive with fewer than two
+ * sub-horizon members or det <= 1e-12 (tr/2)^2), so gradients, force states
+ * and forces have no y component, while the stress keeps all six components
+ * (sigma_yy from the zero out-of-plane strain).  ulppm_dt_crit uses the plane
+ * bond micromodulus C = 72K/(5 pi delta^3) per unit thickness, and contact
+ * sites weigh spacing^2.  The adjoint entry points require plane = 0. */
 
 /* Point state: caller-owned device arrays of length n (SoA). */
 typedef struct {

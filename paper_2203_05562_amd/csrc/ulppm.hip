@@ -84,6 +84,7 @@ struct DevParams {
   int newton_maxit;
   int force_mode;
   double iM2;                 // 1 / M^2
+  int plane;                  // 1: plane strain in the x-z plane, unit thickness
 };
 
 struct Grid {                 // cell grid over the current bounding box
@@ -849,6 +850,28 @@ __host__ __device__ __forceinline__ double sym_inverse(const double* K, double* 
   return det;
 }
 
+// Inverse of a shape tensor (Voigt xx, yy, zz, yz, xz, xy) summed over
+// `count` members, or false when it is degenerate: fewer members than
+// dimensions, or det K <= 1e-12 (tr K / d)^d.  In plane strain (x-z plane)
+// only the x-z block is inverted and the y row and column of the inverse are
+// zero.
+__host__ __device__ __forceinline__ bool shape_inverse(bool plane, const double* K, int count, double* Ki) {
+  if (!plane) {
+    const double dK = det3s(K[0], K[1], K[2], K[3], K[4], K[5]);
+    const double tk = (K[0] + K[1] + K[2]) / 3.0;
+    if (count < 3 || !(dK > 1e-12 * tk * tk * tk)) return false;
+    sym_inverse(K, Ki);
+    return true;
+  }
+  const double a = K[0], c = K[2], e = K[4];
+  const double d2 = a * c - e * e;
+  const double tr = (a + c) / 2.0;
+  if (count < 2 || !(d2 > 1e-12 * tr * tr)) return false;
+  const double id = 1.0 / d2;
+  Ki[0] = c * id; Ki[1] = 0.0; Ki[2] = a * id; Ki[3] = 0.0; Ki[4] = -e * id; Ki[5] = 0.0;
+  return true;
+}
+
 __host__ __device__ __forceinline__ void sym_full(const double* v, double* A) {
   A[0] = v[0]; A[1] = v[5]; A[2] = v[4];
   A[3] = v[5]; A[4] = v[1]; A[5] = v[3];
@@ -1117,13 +1140,9 @@ __device__ __forceinline__ void point_update(const BondArgs& A, const DevParams&
                                              const double* Kp, const double* Np, double Vp) {
   const int64_t n = A.n;
   double Jd = 1.0;
-  const double dK = det3s(Kp[0], Kp[1], Kp[2], Kp[3], Kp[4], Kp[5]);
-  const double tk = (Kp[0] + Kp[1] + Kp[2]) / 3.0;
-  if (nf >= 3 && dK > 1e-12 * tk * tk * tk) {
-    const double a = Kp[0], b = Kp[1], c = Kp[2], d = Kp[3], e = Kp[4], f = Kp[5];
-    const double ixx = (b * c - d * d) / dK, iyy = (a * c - e * e) / dK, izz = (a * b - f * f) / dK;
-    const double ixy = (d * e - f * c) / dK, ixz = (f * d - b * e) / dK, iyz = (e * f - a * d) / dK;
-    const double Ki9[9] = {ixx, ixy, ixz, ixy, iyy, iyz, ixz, iyz, izz};
+  double Ki[6];
+  if (shape_inverse(P.plane != 0, Kp, nf, Ki)) {
+    const double Ki9[9] = {Ki[0], Ki[5], Ki[4], Ki[5], Ki[1], Ki[3], Ki[4], Ki[3], Ki[2]};
     double B[9];
     for (int r = 0; r < 3; ++r)
       for (int cc = 0; cc < 3; ++cc) {
@@ -1224,15 +1243,12 @@ __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
     if constexpr (standard) {
       // every lane holds the wave totals and forms the point update itself
       const int nf = (int)(b1 - b0);
-      const double dK = det3s(Kp[0], Kp[1], Kp[2], Kp[3], Kp[4], Kp[5]);
-      const double tk = (Kp[0] + Kp[1] + Kp[2]) / 3.0;
-      const bool ok = nf >= 3 && dK > 1e-12 * tk * tk * tk;
+      double Ki[6] = {0, 0, 0, 0, 0, 0};
+      const bool ok = shape_inverse(P.plane != 0, Kp, nf, Ki);
       double sg[6], pcn = A.pc[i], pco = pcn;
       for (int k = 0; k < 6; ++k) sg[k] = A.sig[k][i];
       double so[6] = {sg[0], sg[1], sg[2], sg[3], sg[4], sg[5]};
-      double Ki[6] = {0, 0, 0, 0, 0, 0};
       if (ok) {
-        sym_inverse(Kp, Ki);
         double KiF[9], L[9];
         sym_full(Ki, KiF);
         mat3_mul(Np, KiF, L);
@@ -1490,19 +1506,30 @@ void k_bond_mx(BondArgs A, DevParams P) {
     n_trip += ns;
     // FP64 from here on: inversion, gradient, return map, force state.
     const double a = kn[0], b = kn[1], c = kn[2], d = kn[3], e = kn[4], f = kn[5];
-    const double dK = det3s(a, b, c, d, e, f);
-    const double tk = (a + b + c) / 3.0;
     const int64_t slot = b0 + m;
-    if (ns < 3 || !(dK > 1e-12 * tk * tk * tk)) {               // degenerate: inactive bond
+    double ixx, iyy, izz, ixy, ixz, iyz;
+    bool ok;
+    if (P.plane) {                                              // x-z block (plane strain)
+      const double d2 = a * c - e * e, tr = (a + c) / 2.0;
+      ok = ns >= 2 && d2 > 1e-12 * tr * tr;
+      const double id = 1.0 / d2;
+      ixx = c * id; izz = a * id; ixz = -e * id;
+      iyy = ixy = iyz = 0.0;
+    } else {
+      const double dK = det3s(a, b, c, d, e, f);
+      const double tk = (a + b + c) / 3.0;
+      ok = ns >= 3 && dK > 1e-12 * tk * tk * tk;
+      const double idK = 1.0 / dK;
+      ixx = (b * c - d * d) * idK; iyy = (a * c - e * e) * idK; izz = (a * b - f * f) * idK;
+      ixy = (d * e - f * c) * idK; ixz = (f * d - b * e) * idK; iyz = (e * f - a * d) * idK;
+    }
+    if (!ok) {                                                  // degenerate: inactive bond
       ++n_deg;
 #pragma unroll
       for (int q = 0; q < 9; ++q) kn[q] = (Acc)0;
       if (P.force_mode == ULPPM_FORCE_EQ51) T4[slot] = Quad<TS>{{(TS)0, (TS)0, (TS)0, (TS)0}};
       continue;
     }
-    const double idK = 1.0 / dK;
-    const double ixx = (b * c - d * d) * idK, iyy = (a * c - e * e) * idK, izz = (a * b - f * f) * idK;
-    const double ixy = (d * e - f * c) * idK, ixz = (f * d - b * e) * idK, iyz = (e * f - a * d) * idK;
     double N[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) N[q] = (double)kn[6 + q];
@@ -2460,6 +2487,7 @@ struct GatherArgs {
   int mode;
   const double* x;        // 3n current positions (contact)
   ContactDev c;
+  int plane;
 };
 
 // Inclusive index range of lattice sites whose coordinate lies within
@@ -2476,10 +2504,11 @@ __device__ __forceinline__ void site_range(double t_lo, double t_hi, int n, int*
 // (Eqs. 91-93): sum_s 2 (T_c + T_f) V_s with T_c = -C_s (delta_c - |Y|) Y/|Y|,
 // T_f = -mu_f sign(d|Y|/dt) T_c, Y = x_s - x_i, d|Y|/dt = -Y.v_i/|Y|.  Lanes
 // take the sites of the candidate box; the caller reduces over the wave.
-__device__ void contact_density(const ContactDev& C, double xi, double yi, double zi, double vx, double vy,
-                                double vz, int lane, double* out) {
+__device__ void contact_density(const ContactDev& C, bool plane, double xi, double yi, double zi, double vx,
+                                double vy, double vz, int lane, double* out) {
 #pragma clang fp contract(off)
   out[0] = out[1] = out[2] = 0.0;
+  const double Vs = plane ? C.h * C.h : C.Vs;                  // unit thickness in plane strain
   int a0, a1, b0, b1, k0, k1;
   site_range((xi - C.dc - C.ox) / C.h, (xi + C.dc - C.ox) / C.h, C.nx, &a0, &a1);
   site_range((yi - C.dc - C.oy) / C.h, (yi + C.dc - C.oy) / C.h, C.ny, &b0, &b1);
@@ -2498,7 +2527,7 @@ __device__ void contact_density(const ContactDev& C, double xi, double yi, doubl
     const double tc = -C.cs * (C.dc - r) / r;                  // T_c = tc Y
     const double rate = -(Y0 * vx + Y1 * vy + Y2 * vz);         // |Y| d|Y|/dt
     const double sg = rate > 0.0 ? 1.0 : (rate < 0.0 ? -1.0 : 0.0);
-    const double w = 2.0 * C.Vs * tc * (1.0 - C.mu_f * sg);    // 2 (T_c + T_f) V_s = w Y
+    const double w = 2.0 * Vs * tc * (1.0 - C.mu_f * sg);      // 2 (T_c + T_f) V_s = w Y
     out[0] += w * Y0;
     out[1] += w * Y1;
     out[2] += w * Y2;
@@ -2532,8 +2561,8 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
     f2 = wave_sum(f2);
     double fc[3] = {0.0, 0.0, 0.0};
     if (G.c.on) {
-      contact_density(G.c, G.x[i], G.x[G.n + i], G.x[2 * G.n + i], G.vh[i], G.vh[G.n + i], G.vh[2 * G.n + i],
-                      lane, fc);
+      contact_density(G.c, G.plane != 0, G.x[i], G.x[G.n + i], G.x[2 * G.n + i], G.vh[i], G.vh[G.n + i],
+                      G.vh[2 * G.n + i], lane, fc);
       fc[0] = wave_sum(fc[0]);
       fc[1] = wave_sum(fc[1]);
       fc[2] = wave_sum(fc[2]);
@@ -2777,6 +2806,7 @@ DevParams dev_params(const ulppm_params* p) {
   d.newton_maxit = p->newton_maxit;
   d.force_mode = p->force_mode;
   d.iM2 = 1.0 / (p->M * p->M);
+  d.plane = p->plane;
   return d;
 }
 
@@ -2802,6 +2832,7 @@ int check_params(ulppm_ctx* ctx, const ulppm_params* p) {
   if (p->force_mode != ULPPM_FORCE_CONJUGATE && p->force_mode != ULPPM_FORCE_EQ51 &&
       p->force_mode != ULPPM_FORCE_STANDARD)
     return fail(ctx, ULPPM_E_ARG, "bad force_mode");
+  if (p->plane != 0 && p->plane != 1) return fail(ctx, ULPPM_E_ARG, "plane must be 0 or 1");
   return ULPPM_OK;
 }
 
@@ -2988,6 +3019,7 @@ int gather_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int
   G.mode = mode;
   G.x = ctx->x;
   G.c = ctx->contact;
+  G.plane = p->plane;
   const unsigned grid = walk_grid(n);
   if (mode == G_STEP && (int64_t)grid * 3 + kPartGather > ctx->part_cap) return fail(ctx, ULPPM_E_ARG, "partials too small");
   if (mixed)
@@ -3424,7 +3456,9 @@ int ulppm_dt_crit(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, d
   HIPCHK(hipGetLastError());
   if ((rc = build_families(ctx, n, p->delta, true))) return rc;
   const int nb = blocks_for(n, 256, 1024);
-  const double C = 18.0 * p->K / (M_PI * std::pow(p->delta, 4));
+  // bond micromodulus: 3D, or plane strain per unit thickness (Poisson 1/4)
+  const double C = p->plane ? 72.0 * p->K / (5.0 * M_PI * std::pow(p->delta, 3))
+                            : 18.0 * p->K / (M_PI * std::pow(p->delta, 4));
   k_dtcrit<<<nb, 256, 0, ctx->stream>>>(n, ctx->row, ctx->col, ctx->x, S->vol, S->phi, C, p->rho_s,
                                          ctx->part + kPartRed);
   HIPCHK(hipGetLastError());
@@ -3501,6 +3535,7 @@ int ulppm_adjoint_init(ulppm_ctx* ctx, const ulppm_state* S0, const ulppm_params
   if (!s_bar || !theta_bar) return fail(ctx, ULPPM_E_ARG, "s_bar or theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
   if (ctx->contact.on) return fail(ctx, ULPPM_E_ARG, "the adjoint does not include contact forces");
+  if (p->plane) return fail(ctx, ULPPM_E_ARG, "the adjoint is three-dimensional only");
   if (!(ocr >= 1.0)) return fail(ctx, ULPPM_E_ARG, "ocr must be >= 1");
   const int64_t n = S0->n;
   if (adj0->n != n) return fail(ctx, ULPPM_E_ARG, "adjoint state must match the state size");
@@ -3565,6 +3600,7 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
   if (!theta_bar) return fail(ctx, ULPPM_E_ARG, "theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
   if (ctx->contact.on) return fail(ctx, ULPPM_E_ARG, "the adjoint does not include contact forces");
+  if (p->plane) return fail(ctx, ULPPM_E_ARG, "the adjoint is three-dimensional only");
   if (p->precision != ULPPM_FP64 || p->force_mode != ULPPM_FORCE_CONJUGATE)
     return fail(ctx, ULPPM_E_ARG, "the adjoint supports FP64 with conjugate force states");
   if (!(p->dt > 0.0)) return fail(ctx, ULPPM_E_ARG, "dt must be > 0");

@@ -195,7 +195,7 @@ def runout_objective_weights(lattice: np.ndarray, dims) -> dict:
 
 
 # Substrate set-up for contact (Section 4.2: C_s, mu_f, delta_c = 0.8 dx).
-CONTACT = dict(mu_f=0.25, delta_c_over_dx=0.8, cs_ratio=15.0)
+CONTACT = dict(mu_f=0.25, delta_c_over_dx=0.8, cs_ratio=1.0)
 
 
 def make_substrate(col: dict, extent: float = 1.0, layers: int = 1, mu_f: Optional[float] = None,
@@ -208,10 +208,11 @@ def make_substrate(col: dict, extent: float = 1.0, layers: int = 1, mu_f: Option
     point, so no point starts within the cut-off.
 
     Set-up readings (not the method):
-      * C_s: the paper's value is for a 2D model; here T_c is a force per
-        volume squared, so C_s carries N/m^7, set to cs_ratio times the
-        micromodulus 18 K / (pi delta^4) of a bond-based material with the
-        column's bulk modulus and horizon.
+      * C_s: the paper's value belongs to its 2D model.  Here T_c is a force
+        per volume squared, so C_s carries N/m^7 (N/m^6 per unit thickness
+        in plane strain).  It is set so that one site's contact stiffness
+        2 C_s V_i V_s equals cs_ratio times K dx, the axial stiffness of a
+        point's cell: C_s = cs_ratio K / (2 dx^(d+2)), d = 3 or 2.
       * delta_c = 0.8 dx and mu_f = 0.25 as stated for the collapse examples.
     """
     c = dict(CONTACT)
@@ -233,5 +234,6 @@ def make_substrate(col: dict, extent: float = 1.0, layers: int = 1, mu_f: Option
         oy = float(lo[1] - extent * width)
         ny = int(math.ceil((hi[1] + extent * width - oy) / DX)) + 1
     dc = c["delta_c_over_dx"] * DX
-    return dict(cs=c["cs_ratio"] * 18.0 * prm["K"] / (math.pi * prm["delta"] ** 4), mu_f=c["mu_f"],
+    d = 2 if prm.get("plane") else 3
+    return dict(cs=c["cs_ratio"] * prm["K"] / (2.0 * DX ** (d + 2)), mu_f=c["mu_f"],
                 delta_c=dc, origin=[ox, oy, float(lo[2] - 0.9 * dc)], spacing=DX, n=[nx, ny, int(layers)])

@@ -30,7 +30,7 @@ class Params(C.Structure):
                 ("a2", C.c_double), ("n_vg", C.c_double), ("g", C.c_double * 3), ("dt", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("precision", C.c_int32),
                 ("energy_check", C.c_int32), ("force_mode", C.c_int32), ("energy_tol", C.c_double),
-                ("timing", C.c_int32), ("pad", C.c_int32)]
+                ("timing", C.c_int32), ("plane", C.c_int32)]
 
 
 class State(C.Structure):
@@ -121,6 +121,7 @@ def make_params(prm: dict, precision: int = ULPPM_FP64, **over) -> Params:
     p.energy_tol = float(d.get("energy_tol", 1e-2))
     p.force_mode = int(d.get("force_mode", 0))
     p.timing = int(d.get("timing", 0))
+    p.plane = int(d.get("plane", 0))
     return p
 
 

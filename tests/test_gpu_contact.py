@@ -79,7 +79,7 @@ def test_contact_init_and_frictionless_trajectory(olib, gpu):
     """Initial acceleration with contact, then 300 steps of a column settling
     on the substrate with mu_f = 0 (the contact force is continuous)."""
     say("contact trajectory mu 0")
-    col, sub, oprm, gprm, S, G, ctx = column_on_substrate(olib, gpu, (6, 6, 10), seed=5, mu_f=0.0, lift=0.2)
+    col, sub, oprm, gprm, S, G, ctx = column_on_substrate(olib, gpu, (6, 6, 10), seed=5, mu_f=0.0, lift=0.0)
     Gi = gpu.column_state(col)
     ctx.init_state(Gi, gprm, col["params"]["ocr"])
     a_g = Gi.to_arrays()["a"]
@@ -103,7 +103,7 @@ def test_contact_friction_short_run(olib, gpu):
     sides from the same predictor velocity."""
     say("contact friction run")
     col, sub, oprm, gprm, S, G, ctx = column_on_substrate(olib, gpu, (6, 6, 10), seed=6, mu_f=0.25,
-                                                          vscale=0.02)
+                                                          vscale=0.02, lift=0.1)
     rc, E, st = olib.step(S, oprm, 40)
     assert rc == 0
     ctx.step(G, gprm, 40)

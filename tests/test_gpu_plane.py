@@ -1,0 +1,142 @@
+"""Parity of the plane-strain variant (x-z plane, unit thickness) between the
+HIP library and the CPU oracle.
+
+Bars: families bit-exact; FP64 forces within 1e-11 of the largest force;
+FP64 trajectories within 1e-10 relative L2; mixed precision within 1e-4;
+nothing leaves the plane (y components exactly zero on the GPU).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2203_05562_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2203_05562_amd import ulppm
+    ulppm.load_library()
+    return ulppm
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, float).ravel()
+    b = np.asarray(b, float).ravel()
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def plane_pair(olib, gpu, dims=(24, 1, 48), seed=10, vscale=0.0, precision=None, contact=False):
+    col = inputs.make_column(inputs.CONFIGS["P0"], seed=seed, dims=dims, fixed_base=not contact)
+    sub = None
+    over = {}
+    if contact:
+        sub = inputs.make_substrate(col, extent=0.5, layers=2, mu_f=0.0)
+        over["contact"] = sub
+    oprm = olib.make_params(col["params"], **over)
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    if vscale > 0:
+        v = inputs.random_velocity(col["n"], seed + 100, vscale)
+        v[:, 1] = 0.0
+        v[col["fixed"] == 1] = 0.0
+        S["v"][:] = v
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    gover = {} if precision is None else dict(precision=precision)
+    gprm = gpu.make_params(olib.params_dict(oprm), **gover)
+    ctx = gpu.Context(col["n"])
+    if sub:
+        ctx.set_contact(sub)
+    G = gpu.DeviceState.from_arrays(S)
+    return col, oprm, gprm, S, G, ctx
+
+
+def test_plane_families_init_and_dt_crit(olib, gpu):
+    say("plane families / init / dt")
+    col, oprm, gprm, S, G, ctx = plane_pair(olib, gpu)
+    row_o, col_o = olib.families(S["x0"], oprm.delta)
+    row_g, col_g = ctx.build_families(G, gprm)
+    assert np.array_equal(row_g.cpu().numpy(), row_o) and np.array_equal(col_g.cpu().numpy(), col_o)
+    dto, dtg = olib.dt_crit(S, oprm), ctx.dt_crit(G, gprm)
+    say("dt", dto, dtg)
+    assert abs(dto - dtg) <= 1e-14 * dto
+    Gi = gpu.column_state(col)
+    ctx.init_state(Gi, gprm, col["params"]["ocr"])
+    Si = Gi.to_arrays()
+    for k in ("a", "sig", "pc", "mass", "Sr"):
+        assert rel_l2(Si[k], S[k]) <= 1e-13, k
+
+
+@pytest.mark.parametrize("vscale,dtmul", [(0.0, 0.0), (0.05, 1.0)])
+def test_plane_forces(olib, gpu, vscale, dtmul):
+    say("plane forces", vscale, dtmul)
+    col, oprm, gprm, S, G, ctx = plane_pair(olib, gpu, seed=12, vscale=vscale)
+    dt_inc = dtmul * oprm.dt
+    out = olib.bond_fields(S, oprm, dt_inc)
+    f, T, rep = ctx.forces(G, gprm, dt_inc, want_T=True)
+    assert rep["n_bonds"] == out["row"][-1] and rep["n_degenerate"] == out["stats"]["n_degenerate"]
+    fg, Tg = f.cpu().numpy().T, T.cpu().numpy().T
+    assert np.all(fg[:, 1] == 0.0) and np.all(Tg[:, 1] == 0.0)
+    fs, ts = np.abs(out["f"]).max(), np.abs(out["T"]).max()
+    say("maxerr f", np.abs(fg - out["f"]).max() / fs, "T", np.abs(Tg - out["T"]).max() / ts)
+    assert np.abs(Tg - out["T"]).max() <= 1e-11 * ts
+    assert np.abs(fg - out["f"]).max() <= 1e-11 * fs
+
+
+def test_plane_trajectory(olib, gpu):
+    say("plane trajectory")
+    col, oprm, gprm, S, G, ctx = plane_pair(olib, gpu, seed=10)
+    E = np.zeros(3)
+    rc, E, st = olib.step(S, oprm, 200, E)
+    assert rc == 0
+    rep = ctx.step(G, gprm, 200)
+    Sg = G.to_arrays()
+    errs = {k: rel_l2(Sg[k], S[k]) for k in ("u", "v", "a", "sig", "pc", "J", "mass")}
+    say("200 steps", {k: f"{v:.2e}" for k, v in errs.items()}, "plastic", st["n_plastic"], rep["n_plastic"])
+    assert all(v <= 1e-10 for v in errs.values()), errs
+    assert np.all(Sg["u"][:, 1] == 0.0) and np.all(Sg["v"][:, 1] == 0.0)
+    assert abs(rep["W_ext"] - E[1]) <= 1e-9 * abs(E[1])
+
+
+def test_plane_with_contact(olib, gpu):
+    """A free plane-strain column settling on a row of substrate sites."""
+    say("plane + contact")
+    col, oprm, gprm, S, G, ctx = plane_pair(olib, gpu, dims=(16, 1, 24), seed=13, contact=True)
+    rc, E, st = olib.step(S, oprm, 200)
+    assert rc == 0
+    ctx.step(G, gprm, 200)
+    Sg = G.to_arrays()
+    errs = {k: rel_l2(Sg[k], S[k]) for k in ("u", "v", "sig")}
+    say("200 steps", errs)
+    assert all(v <= 1e-10 for v in errs.values()), errs
+
+
+def test_plane_mixed_precision(olib, gpu):
+    say("plane mixed")
+    col, oprm, gprm, S, G, ctx = plane_pair(olib, gpu, seed=14, precision=gpu.ULPPM_MIXED)
+    rc, E, st = olib.step(S, oprm, 200)
+    assert rc == 0
+    ctx.step(G, gprm, 200)
+    Sg = G.to_arrays()
+    errs = {k: rel_l2(Sg[k], S[k]) for k in ("u", "v", "sig")}
+    say("mixed 200 steps", errs)
+    assert all(v <= 1e-4 for v in errs.values()), errs
+
+
+def test_plane_adjoint_rejected(olib, gpu):
+    import torch
+    col, oprm, gprm, S, G, ctx = plane_pair(olib, gpu, dims=(8, 1, 8))
+    ctx.adjoint_reserve()
+    A1 = gpu.DeviceState.from_arrays(olib.empty_state(col["n"]))
+    A0 = gpu.DeviceState.from_arrays(olib.empty_state(col["n"]))
+    with pytest.raises(gpu.UlppmError) as ei:
+        ctx.adjoint_step(G, gprm, A1, A0, torch.zeros(4, dtype=torch.float64, device="cuda"))
+    assert ei.value.code == -1
