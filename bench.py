@@ -32,6 +32,8 @@ time per forward step, per reverse step (ulppm_adjoint_step) and their ratio.
 "contact": the same column standing free on a rigid substrate lattice
 (Eqs. 91-93, the substrate one column width wider on every side), its
 throughput and gather phase, the kernel that adds the contact forces.
+"plane": the plane-strain column P1 (512 x 1024 points in the x-z plane,
+families of ~28), its throughput and bond-kernel time.
 """
 import argparse
 import hashlib
@@ -145,6 +147,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--no-contact", action="store_true", help="skip the substrate-contact companion run")
+    ap.add_argument("--no-plane", action="store_true", help="skip the plane-strain companion run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -209,6 +212,18 @@ def main():
                               gather_ms_without=phases["gather"])
         log(f"[gpu] contact: {out['contact']}")
         del Gc
+        torch.cuda.empty_cache()
+    if not args.no_plane:
+        colp = inputs.make_column(inputs.CONFIGS["P1"])
+        Gp, repp, msp, _ = run_column(ulppm, colp, prec, args.warmup, args.steps)
+        lp = max(repp["timed_steps"], 1)
+        out["plane"] = dict(workload="P1: plane-strain column 512x1024", points=colp["n"],
+                            value=repp["n_bond_updates"] / (msp * 1e-3), ms_per_step=msp / args.steps,
+                            bonds_per_step=repp["n_bond_updates"] / args.steps,
+                            phase_ms={k: round(repp[f"t_{k}_ms"] / lp, 4)
+                                      for k in ("predict", "family", "kin", "bond", "gather")})
+        log(f"[gpu] plane: {out['plane']}")
+        del Gp
         torch.cuda.empty_cache()
     if args.adjoint_config:
         from paper_2203_05562_amd.measure import adjoint_cost
