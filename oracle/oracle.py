@@ -16,7 +16,7 @@ import numpy as np
 from .build import LIB, build
 
 __all__ = ["OracleParams", "lib", "make_params", "init_column", "families", "bond_fields",
-           "step", "step_dual", "dt_crit", "return_map", "rm_residual", "swrc", "copy_state",
+           "step", "step_dual", "step_bond_history", "BondHistory", "dt_crit", "return_map", "rm_residual", "swrc", "copy_state",
            "empty_state", "params_dict", "STATE_FIELDS"]
 
 _dp = C.POINTER(C.c_double)
@@ -41,6 +41,11 @@ class OracleState(C.Structure):
     _fields_ = [("n", C.c_int64), ("x0", _dp), ("u", _dp), ("uc", _dp), ("v", _dp), ("a", _dp),
                 ("vol", _dp), ("phi", _dp), ("J", _dp), ("Sr", _dp), ("mass", _dp), ("s", _dp),
                 ("sig", _dp), ("pc", _dp), ("fixed", _u8p)]
+
+
+class OracleBondHistory(C.Structure):
+    _fields_ = [("n", C.c_int64), ("cap", C.c_int64), ("nb", C.c_int64), ("row", _i64p), ("col", _i32p),
+                ("st", _dp)]
 
 
 class OracleStats(C.Structure):
@@ -72,6 +77,10 @@ def lib():
         L.oracle_step.restype = C.c_int
         L.oracle_step.argtypes = [C.POINTER(OracleParams), C.POINTER(OracleState), C.c_int32, _dp,
                                   C.POINTER(OracleStats)]
+        L.oracle_step_bond_history.restype = C.c_int
+        L.oracle_step_bond_history.argtypes = [C.POINTER(OracleParams), C.POINTER(OracleState),
+                                               C.POINTER(OracleBondHistory), C.c_int32, _dp,
+                                               C.POINTER(OracleStats)]
         L.oracle_step_dual.restype = C.c_int
         L.oracle_step_dual.argtypes = [C.POINTER(OracleParams), _dp, C.POINTER(OracleState),
                                        C.POINTER(OracleState), C.c_int32, _dp, C.POINTER(OracleStats)]
@@ -206,6 +215,31 @@ def step(S: dict, prm: OracleParams, n_steps: int = 1, energy=None):
     cs = _cstate(S)
     st = OracleStats()
     rc = lib().oracle_step(C.byref(prm), C.byref(cs), int(n_steps), _p(e), C.byref(st))
+    return rc, e, st.as_dict()
+
+
+class BondHistory:
+    """History carried on the bonds between oracle_step_bond_history calls:
+    families (row, col) and 8 values per bond (sigma Voigt, p_c, unused)."""
+
+    def __init__(self, n: int, cap: int):
+        self.row = np.zeros(n + 1, np.int64)
+        self.col = np.zeros(max(cap, 1), np.int32)
+        self.st = np.zeros((max(cap, 1), 8))
+        self.c = OracleBondHistory(0, cap, 0, _p(self.row, _i64p), _p(self.col, _i32p), _p(self.st))
+
+    @property
+    def nb(self) -> int:
+        return int(self.c.nb)
+
+
+def step_bond_history(S: dict, prm: OracleParams, H: BondHistory, n_steps: int = 1, energy=None):
+    """Advance with the history on the bonds; H carries it between calls."""
+    e = np.zeros(3) if energy is None else energy
+    cs = _cstate(S)
+    st = OracleStats()
+    rc = lib().oracle_step_bond_history(C.byref(prm), C.byref(cs), C.byref(H.c), int(n_steps), _p(e),
+                                        C.byref(st))
     return rc, e, st.as_dict()
 
 

@@ -611,7 +611,7 @@ void contact_forces(const Params& P, int64_t n, const R* x, const R* v, const st
 template <class R>
 void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval, const R* x,
                 const R* vh, const PointState<R>& S, const Families& F, R dt_inc, BondOut<R>& O,
-                Stats& st) {
+                Stats& st, const std::vector<double>* bond_in = nullptr) {
   const double d2 = P.delta * P.delta;
   const int64_t nb = F.row[n];
   O.K.assign(6 * nb, R(0.0));
@@ -760,11 +760,16 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
       R deps[6] = {dt_inc * L[0], dt_inc * L[4], dt_inc * L[8], dt_inc * 0.5 * (L[5] + L[7]),
                    dt_inc * 0.5 * (L[2] + L[6]), dt_inc * 0.5 * (L[1] + L[3])};
       R sb[6], pcb;
+      // state the bond starts from: the point history, or the bond's own
+      // history when it is carried on the bonds
+      R sig_b[6], pc_b;
+      for (int k = 0; k < 6; ++k) sig_b[k] = bond_in ? R((*bond_in)[8 * s + k]) : sig_i[k];
+      pc_b = bond_in ? R((*bond_in)[8 * s + 6]) : S.pc[i];
       if (val(dt_inc) == 0.0) {
-        for (int k = 0; k < 6; ++k) sb[k] = sig_i[k];
-        pcb = S.pc[i];
+        for (int k = 0; k < 6; ++k) sb[k] = sig_b[k];
+        pcb = pc_b;
       } else {
-        int it = return_map(m, P, dt_inc, sig_i, S.pc[i], deps, sb, &pcb);
+        int it = return_map(m, P, dt_inc, sig_b, pc_b, deps, sb, &pcb);
         if (it < 0) { ++n_nc; it = P.newton_maxit; }
         if (it > 0) ++n_pl;
         if (it > maxit) maxit = it;
@@ -858,11 +863,55 @@ std::vector<double> values(const std::vector<R>& a) {
   return v;
 }
 
+// History carried on the bonds instead of the points (the alternative to the
+// point history; the paper stores internal variables on material points but
+// does not say how bond stresses relate to them across steps).  Every bond
+// keeps its own (sigma_ij, p_c,ij) from one step to the next while it stays in
+// the family; a bond that enters a family starts from its point's history
+// (the volume-weighted mean of the point's bond states, as before).
+struct BondHistory {
+  std::vector<int64_t> row;   // families the states belong to (empty: none yet)
+  std::vector<int32_t> col;
+  std::vector<double> st;     // 8 per bond: sigma (6), p_c, unused
+};
+
+// Bond states in the order of the new families F: a bond found in the
+// previous families of its point keeps its state; a new bond takes the point's.
+inline void carry_bond_history(const BondHistory& H, const Families& F, const std::vector<double>& sig,
+                               const std::vector<double>& pc, std::vector<double>& in) {
+  const int64_t n = (int64_t)F.row.size() - 1;
+  in.assign(8 * F.row[n], 0.0);
+  const bool have = (int64_t)H.row.size() == n + 1;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t s = F.row[i]; s < F.row[i + 1]; ++s) {
+      int64_t found = -1;
+      if (have)
+        for (int64_t t = H.row[i]; t < H.row[i + 1]; ++t)
+          if (H.col[t] == F.col[s]) { found = t; break; }
+      for (int k = 0; k < 6; ++k) in[8 * s + k] = found >= 0 ? H.st[8 * found + k] : sig[6 * i + k];
+      in[8 * s + 6] = found >= 0 ? H.st[8 * found + 6] : pc[i];
+    }
+}
+
+// Updated bond states after Algorithm 1; a degenerate (inactive) bond keeps
+// the state it started from.
+template <class R>
+void store_bond_history(BondHistory& H, const Families& F, const BondOut<R>& O, const std::vector<double>& in) {
+  const int64_t nb = F.row.back();
+  H.row = F.row;
+  H.col = F.col;
+  H.st.assign(8 * nb, 0.0);
+  for (int64_t s = 0; s < nb; ++s) {
+    for (int k = 0; k < 6; ++k) H.st[8 * s + k] = O.active[s] ? val(O.sig[6 * s + k]) : in[8 * s + k];
+    H.st[8 * s + 6] = O.active[s] ? val(O.pc[s]) : in[8 * s + 6];
+  }
+}
+
 // Algorithm 2, one step n -> n+1, central differences (beta1 = 1/2,
 // beta2 = 0; Eqs. 60-64), with energies of Eqs. 66-68 accumulated in E.
 template <class R>
 int newmark_step(const Params& P, const Mat<R>& m, PointState<R>& S, R* E, Stats& st,
-                 Families* Fout = nullptr) {
+                 Families* Fout = nullptr, BondHistory* H = nullptr) {
   const int64_t n = S.n;
   const R dt = P.dt;
   const R hdt = 0.5 * P.dt;
@@ -892,7 +941,10 @@ int newmark_step(const Params& P, const Mat<R>& m, PointState<R>& S, R* E, Stats
   build_families_cells(n, xv.data(), P.delta, F);
   build_reverse(n, F);
   BondOut<R> O;
-  algorithm1(P, m, n, xv.data(), x.data(), vh.data(), S, F, dt, O, st);
+  std::vector<double> bond_in;
+  if (H) carry_bond_history(*H, F, values(S.sig), values(S.pc), bond_in);
+  algorithm1(P, m, n, xv.data(), x.data(), vh.data(), S, F, dt, O, st, H ? &bond_in : nullptr);
+  if (H) store_bond_history(*H, F, O, bond_in);
   // Acceleration (Eq. 62 with the sign of Eq. 33) and velocity corrector (Eq. 63).
   R ekin = 0.0;
   for (int64_t i = 0; i < n; ++i) {
@@ -1099,6 +1151,46 @@ int oracle_step(const OracleParams* op, OracleState* os, int32_t n_steps, double
   for (int k = 0; k < n_steps && rc == 0; ++k) rc = newmark_step(P, m, S, energy, st);
   store_state(S, os);
   store_stats(st, ost);
+  return rc;
+}
+
+// Algorithm 2 with the history carried on the bonds (see BondHistory):
+// bh holds the families and bond states of the last step (bh->nb = 0 or
+// bh->n != n: none yet, every bond starts from its point) and receives those
+// of the last step taken.  Returns -2 when bh->cap is too small.
+typedef struct {
+  int64_t n, cap, nb;
+  int64_t* row;   // n+1
+  int32_t* col;   // cap
+  double* st;     // 8 per bond: sigma (6, Voigt), p_c, unused
+} OracleBondHistory;
+
+int oracle_step_bond_history(const OracleParams* op, OracleState* os, OracleBondHistory* bh, int32_t n_steps,
+                             double* energy, OracleStats* ost) {
+  Params P = to_params(op);
+  Mat<double> m = to_mat<double>(P);
+  PointState<double> S;
+  load_state(os, S);
+  BondHistory H;
+  if (bh->nb > 0 && bh->n == S.n) {
+    H.row.assign(bh->row, bh->row + S.n + 1);
+    H.col.assign(bh->col, bh->col + bh->nb);
+    H.st.assign(bh->st, bh->st + 8 * bh->nb);
+  }
+  Stats st;
+  int rc = 0;
+  for (int k = 0; k < n_steps && rc == 0; ++k) rc = newmark_step(P, m, S, energy, st, nullptr, &H);
+  store_state(S, os);
+  store_stats(st, ost);
+  const int64_t nb = H.row.empty() ? 0 : H.row.back();
+  if (nb > bh->cap) return -2;
+  bh->n = S.n;
+  bh->nb = nb;
+  if (nb > 0) {
+    std::copy(H.row.begin(), H.row.end(), bh->row);
+    std::copy(H.col.begin(), H.col.end(), bh->col);
+    std::copy(H.st.begin(), H.st.end(), bh->st);
+  }
   return rc;
 }
 

@@ -826,3 +826,114 @@ def test_plane_column_stays_in_plane(olib):
     assert rc == 0
     assert np.all(S["u"][:, 1] == 0.0) and np.all(S["v"][:, 1] == 0.0) and np.all(S["a"][:, 1] == 0.0)
     assert abs(E[0] + E[2] - E[1]) <= 1e-2 * max(abs(E[0]), abs(E[1]), abs(E[2]))
+
+
+# ------------------------------------------------------------ bond history --
+
+def predictor_state(S, prm):
+    """The state whose positions and velocities are the ones a step uses:
+    x^{n+1} from the Kahan-compensated predictor and v = v_half."""
+    T = olib_copy(S)
+    dt = prm.dt
+    g = np.array(prm.g[:])
+    vh = S["v"] + 0.5 * dt * S["a"]
+    vh[S["fixed"] == 1] = 0.0
+    y = dt * vh - S["uc"]
+    t = S["u"] + y
+    T["uc"] = (t - S["u"]) - y
+    T["u"] = t
+    T["v"] = vh
+    del g
+    return T
+
+
+def olib_copy(S):
+    return {k: v.copy() for k, v in S.items()}
+
+
+def hooke(prm, de):
+    lam = prm.K - 2.0 * prm.mu / 3.0
+    out = 2.0 * prm.mu * de
+    out[:, :3] += lam * de[:, :3].sum(axis=1, keepdims=True)
+    return out
+
+
+def test_bond_history_carries_each_bond_state(olib):
+    """History on the bonds: in the elastic range a bond that stays in its
+    family gains exactly Hooke's increment of its own strain increment, from
+    its own previous state (not from the point mean), step after step; and
+    splitting the steps over calls changes nothing."""
+    col, prm, S = column_state(olib, (6, 6, 8), seed=4, jitter=0.0)
+    set_uniform_stress(S, [-40e3, -38e3, -42e3, 1e3, 0.0, -500.0], -400e3, 0.0)
+    prm.g[:] = [0.0, 0.0, 0.0]
+    S["fixed"][:] = 0
+    S["v"][:] = inputs.random_velocity(col["n"], 3, 1e-3)
+    S["a"][:] = 0.0
+    prm.dt = 0.5 * olib.dt_crit(S, prm)
+    H = olib.BondHistory(col["n"], 200 * col["n"])
+    rc, _, _ = olib.step_bond_history(S, prm, H, 2)            # bonds now differ from the point mean
+    assert rc == 0
+    for _ in range(2):
+        before = H.st[:H.nb].copy()
+        row0, col0 = H.row.copy(), H.col[:H.nb].copy()
+        pre = predictor_state(S, prm)
+        out = olib.bond_fields(pre, prm, prm.dt)
+        rc, _, st = olib.step_bond_history(S, prm, H, 1)
+        assert rc == 0 and st["n_plastic"] == 0
+        assert np.array_equal(H.row, row0) and np.array_equal(H.col[:H.nb], col0)
+        L = out["L"].reshape(-1, 3, 3)
+        D = 0.5 * (L + L.transpose(0, 2, 1))
+        de = prm.dt * np.stack([D[:, 0, 0], D[:, 1, 1], D[:, 2, 2], D[:, 1, 2], D[:, 0, 2], D[:, 0, 1]], axis=1)
+        act = out["active"] == 1
+        inc = H.st[:H.nb, :6] - before[:, :6]
+        spread = np.abs(before[:, :6] - before[:, :6].mean(axis=0)).max()
+        assert spread > 1e-3 * np.abs(hooke(prm, de)[act]).max()      # bonds really differ
+        assert np.abs(inc[act] - hooke(prm, de)[act]).max() <= 1e-9 * np.abs(before[:, :6]).max()
+        assert np.array_equal(H.st[:H.nb, 6], before[:, 6])            # elastic: p_c unchanged
+    S2 = olib_copy(S)
+    H2 = olib.BondHistory(col["n"], 200 * col["n"])
+    H2.row[:], H2.col[:], H2.st[:] = H.row, H.col, H.st
+    H2.c.nb, H2.c.n = H.c.nb, H.c.n
+    olib.step_bond_history(S, prm, H, 4)
+    olib.step_bond_history(S2, prm, H2, 2)
+    olib.step_bond_history(S2, prm, H2, 2)
+    assert np.array_equal(S["u"], S2["u"]) and np.array_equal(H.st, H2.st)
+
+
+def test_bond_history_new_bond_starts_from_point(olib):
+    """A bond that enters a family starts from its point's history: a point
+    moving into a neighbour's horizon brings a new bond whose stored state is
+    the point's stress of the previous step plus Hooke's increment."""
+    col, prm, S = column_state(olib, (5, 5, 5), seed=0, jitter=0.0)
+    set_uniform_stress(S, [-40e3, -40e3, -40e3, 0.0, 0.0, 0.0], -400e3, 0.0)
+    prm.g[:] = [0.0, 0.0, 0.0]
+    S["fixed"][:] = 0
+    lat = col["lattice"]
+    mover = int(np.nonzero((lat == [4, 2, 2]).all(axis=1))[0][0])
+    target = int(np.nonzero((lat == [0, 2, 2]).all(axis=1))[0][0])
+    # start outside the horizon of `target` (3.025 dx > 3.015 dx) and move
+    # 0.007 dx per step towards it: outside after one step, inside after two
+    S["u"][mover, 0] = -(4.0 - 3.025) * DX
+    prm.dt = 1e-5
+    S["v"][mover, 0] = -0.007 * DX / prm.dt
+    S["a"][:] = 0.0
+    H = olib.BondHistory(col["n"], 200 * col["n"])
+    rc, _, _ = olib.step_bond_history(S, prm, H, 1)
+    assert rc == 0
+    r1 = H.row.copy()
+    sig_pt = S["sig"].copy()
+    pre = predictor_state(S, prm)
+    out = olib.bond_fields(pre, prm, prm.dt)
+    rc, _, _ = olib.step_bond_history(S, prm, H, 1)
+    assert rc == 0
+    fam = H.col[H.row[target]:H.row[target + 1]]
+    assert mover in fam and (r1[target + 1] - r1[target]) < (H.row[target + 1] - H.row[target])
+    s = H.row[target] + int(np.nonzero(fam == mover)[0][0])
+    L = out["L"][s].reshape(3, 3)
+    D = 0.5 * (L + L.T)
+    de = prm.dt * np.array([[D[0, 0], D[1, 1], D[2, 2], D[1, 2], D[0, 2], D[0, 1]]])
+    if out["active"][s]:
+        exp = sig_pt[target] + hooke(prm, de)[0]
+    else:
+        exp = sig_pt[target]
+    assert np.allclose(H.st[s, :6], exp, rtol=0, atol=1e-9 * 40e3)
