@@ -100,14 +100,14 @@ def cpu_baseline(cfg_name, steps, dt):
                 seconds=round(el, 3))
 
 
-def run_column(ulppm, col, precision, warmup, steps, timed=True, contact=None):
+def run_column(ulppm, col, precision, warmup, steps, timed=True, contact=None, max_family=0):
     """Initial conditions, dt = dt_c / 2, `warmup` untimed steps, then
     `steps` steps timed with HIP events on the library's stream.  `contact`
     attaches a substrate (Eqs. 91-93) first."""
     import torch
     G = ulppm.column_state(col, "cuda:0")
     prm = ulppm.make_params(col["params"], precision=precision)
-    ctx = ulppm.Context(col["n"])
+    ctx = ulppm.Context(col["n"], max_family=max_family)
     if contact:
         ctx.set_contact(contact)
     ctx.init_state(G, prm, col["params"]["ocr"])
@@ -215,7 +215,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_plane:
         colp = inputs.make_column(inputs.CONFIGS["P1"])
-        Gp, repp, msp, _ = run_column(ulppm, colp, prec, args.warmup, args.steps)
+        # plane families hold at most ~30 members: a context sized for 64 runs one wave per point
+        Gp, repp, msp, _ = run_column(ulppm, colp, prec, args.warmup, args.steps, max_family=64)
         lp = max(repp["timed_steps"], 1)
         out["plane"] = dict(workload="P1: plane-strain column 512x1024", points=colp["n"],
                             value=repp["n_bond_updates"] / (msp * 1e-3), ms_per_step=msp / args.steps,

@@ -64,6 +64,18 @@ enum { ULPPM_FP64 = 0, ULPPM_MIXED = 1 };
  *   comparison model.  No sub-horizons are formed (n_tests = n_triples = 0). */
 enum { ULPPM_FORCE_CONJUGATE = 0, ULPPM_FORCE_EQ51 = 1, ULPPM_FORCE_STANDARD = 2 };
 
+/* Where the history (effective stress, p_c) lives between steps.
+ * ULPPM_HISTORY_POINT (default): on the points; every bond starts each step
+ *   from its point's history, and the point's new history is the
+ *   volume-weighted mean of its bonds' updated states.
+ * ULPPM_HISTORY_BOND: on the bonds; a bond keeps its own state from step to
+ *   step while it stays in the family, a bond that enters a family starts
+ *   from its point's history, and the points still receive the mean (for
+ *   output and for new bonds).  The states live in the context
+ *   (ulppm_history_reserve), ulppm_init_state clears them, and only
+ *   ulppm_step uses them (ulppm_forces starts every bond from its point). */
+enum { ULPPM_HISTORY_POINT = 0, ULPPM_HISTORY_BOND = 1 };
+
 /* Material and integration parameters, copied by value on every call. */
 typedef struct {
   double delta;                 /* horizon, constant in the current configuration (Eq. 1) [m] */
@@ -84,6 +96,8 @@ typedef struct {
   double energy_tol;            /* epsilon of Eq. 69 (the paper uses ~1e-2) */
   int32_t timing;               /* nonzero: time each phase of ulppm_step with HIP events */
   int32_t plane;                /* 1: plane strain in the x-z plane (see below); 0: 3D */
+  int32_t history;              /* ULPPM_HISTORY_POINT or ULPPM_HISTORY_BOND */
+  int32_t pad;
 } ulppm_params;
 
 /* Plane strain (plane = 1).  All points lie in one x-z plane (equal y) with
@@ -234,6 +248,20 @@ int ulppm_forces(ulppm_ctx *ctx, const ulppm_state *state, const ulppm_params *p
  * ULPPM_E_ENERGY, ULPPM_E_HIP. */
 int ulppm_step(ulppm_ctx *ctx, ulppm_state *state, const ulppm_params *p, int32_t n_steps,
                ulppm_report *rep);
+
+/* Allocate the bond states of ULPPM_HISTORY_BOND: two buffers of 8 doubles
+ * per bond slot (n_points * max_family) and a copy of the families they
+ * follow.  Call once before the first ulppm_step with history =
+ * ULPPM_HISTORY_BOND.  Errors: ULPPM_E_ARG, ULPPM_E_HIP. */
+int ulppm_history_reserve(ulppm_ctx *ctx);
+
+/* Copy the bond history of the last step to caller device memory: row_out
+ * (n+1 int64), col_out (int32) and st_out (8 doubles per bond: sigma in Voigt
+ * order, p_c, 0), each may be NULL; *nb_out (host) receives the bond count.
+ * With all three NULL only the count is returned.  Errors: ULPPM_E_ARG (no
+ * history held), ULPPM_E_CAPACITY (cap < bonds), ULPPM_E_HIP. */
+int ulppm_history_export(ulppm_ctx *ctx, int64_t *row_out, int32_t *col_out, double *st_out, int64_t cap,
+                         int64_t *nb_out);
 
 /* Allocate the scratch of ulppm_adjoint_step (a copy of one state, the point
  * adjoints and 7 doubles per bond slot).  Call once, before the first adjoint

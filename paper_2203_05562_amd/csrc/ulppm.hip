@@ -1090,6 +1090,7 @@ struct BondArgs {
                           // (double, or float in mixed precision)
   double* pk;             // 2n: apparent pre-consolidation of p_c,i and 1/V_H,i (k_point_kin)
   const double* xv;       // 8n: x (3), V^n, v_half (3), 0 per point
+  double* hist;           // history on the bonds: 8 per bond (sigma, p_c, 0), updated in place; or null
   double dt_inc;
   int max_f;
   unsigned long long* ctr;
@@ -1298,6 +1299,52 @@ __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
   }
 }
 
+// History carried on the bonds: the states of the new families' bonds.  One
+// wave per point, lanes over its bonds; a bond found (binary search) in the
+// point's row of the previous families keeps its state, a new bond starts
+// from the point history (sigma_i, p_c,i).  Rows of both are ascending.
+__global__ __launch_bounds__(256) void k_hist_carry(int64_t n, const int64_t* __restrict__ row,
+                                                    const int32_t* __restrict__ col,
+                                                    const int64_t* __restrict__ hrow,
+                                                    const int32_t* __restrict__ hcol, int have,
+                                                    const double* __restrict__ hold, double* __restrict__ hcur,
+                                                    ulppm_state S) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const XcdWalk W = xcd_walk(n, 4);
+  const double4* ho = reinterpret_cast<const double4*>(hold);
+  double4* hc = reinterpret_cast<double4*>(hcur);
+  for (int64_t i = W.first; i < W.end; i += W.stride) {
+    const int64_t b0 = row[i], b1 = row[i + 1];
+    const int64_t h0 = have ? hrow[i] : 0, h1 = have ? hrow[i + 1] : 0;
+    for (int64_t s = b0 + lane; s < b1; s += kWave) {
+      const int32_t j = col[s];
+      int64_t lo = h0, hi = h1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (hcol[mid] < j) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < h1 && hcol[lo] == j) {
+        hc[2 * s] = ho[2 * lo];
+        hc[2 * s + 1] = ho[2 * lo + 1];
+      } else {
+        hc[2 * s] = double4{S.sig[0][i], S.sig[1][i], S.sig[2][i], S.sig[3][i]};
+        hc[2 * s + 1] = double4{S.sig[4][i], S.sig[5][i], S.pc[i], 0.0};
+      }
+    }
+  }
+}
+
+// Families of the last step, kept with the bond states they order.
+__global__ void k_hist_keep(int64_t n, const int64_t* __restrict__ row, const int32_t* __restrict__ col,
+                            int64_t* __restrict__ hrow, int32_t* __restrict__ hcol) {
+  const int64_t nb = row[n];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e <= n; e += (int64_t)gridDim.x * blockDim.x)
+    hrow[e] = row[e];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nb; e += (int64_t)gridDim.x * blockDim.x)
+    hcol[e] = col[e];
+}
+
 // ------------------------------------------------- bond kernel, MFMA sums --
 //
 // The masked sums of pass 1 (sub-horizon shape tensor, velocity-gradient
@@ -1363,9 +1410,12 @@ __host__ __device__ constexpr int feat_b(int f) {
   return f < 3 ? f : f == 3 ? 2 : f == 4 ? 2 : f == 5 ? 1 : f < 15 ? (f - 6) % 3 : 7;
 }
 
-template <class Acc>
-__global__ __launch_bounds__(kBondThreads, sizeof(Acc) == 8 ? ULPPM_BOND_MX_MIN_WAVES : ULPPM_BOND_MX_MIN_WAVES_MIXED)
+// NT threads per workgroup (one point): 128 for 3D families of ~100, 64 when
+// every family fits one wave (plane strain).
+template <class Acc, bool Hist, int NT>
+__global__ __launch_bounds__(NT, sizeof(Acc) == 8 ? ULPPM_BOND_MX_MIN_WAVES : ULPPM_BOND_MX_MIN_WAVES_MIXED)
 void k_bond_mx(BondArgs A, DevParams P) {
+  constexpr int kBondThreads = NT, kBondWaves = NT / kWave;
   using TS = Acc;
   using MM = Mma<Acc>;
   using V4 = typename MM::V;
@@ -1545,15 +1595,34 @@ void k_bond_mx(BondArgs A, DevParams P) {
     const double de[6] = {h * L[0], h * L[4], h * L[8], h * 0.5 * (L[5] + L[7]), h * 0.5 * (L[2] + L[6]),
                           h * 0.5 * (L[1] + L[3])};              // Eqs. 26, 59
     double sgb[6], pcb;
-    if (h == 0.0) {
+    if constexpr (!Hist) {                                      // bonds start from the point history
+      if (h == 0.0) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) sgb[k] = sig_i[k];
-      pcb = pc_i;
-    } else {
-      int it = return_map_pn(P, h, sig_i, pc_i, Pn_i, de, sgb, &pcb);
-      if (it < 0) { ++n_nc; it = P.newton_maxit; }
-      if (it > 0) ++n_pl;
-      mx = mx > it ? mx : it;
+        for (int k = 0; k < 6; ++k) sgb[k] = sig_i[k];
+        pcb = pc_i;
+      } else {
+        int it = return_map_pn(P, h, sig_i, pc_i, Pn_i, de, sgb, &pcb);
+        if (it < 0) { ++n_nc; it = P.newton_maxit; }
+        if (it > 0) ++n_pl;
+        mx = mx > it ? mx : it;
+      }
+    } else {                                                    // each bond starts from its own state
+      const double4 ha = reinterpret_cast<const double4*>(A.hist)[2 * slot];
+      const double4 hb = reinterpret_cast<const double4*>(A.hist)[2 * slot + 1];
+      const double sg0[6] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y};
+      const double pc0 = hb.z;
+      if (h == 0.0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sgb[k] = sg0[k];
+        pcb = pc0;
+      } else {
+        int it = return_map_pn(P, h, sg0, pc0, apparent_pc(P, pc0), de, sgb, &pcb);
+        if (it < 0) { ++n_nc; it = P.newton_maxit; }
+        if (it > 0) ++n_pl;
+        mx = mx > it ? mx : it;
+      }
+      reinterpret_cast<double4*>(A.hist)[2 * slot] = double4{sgb[0], sgb[1], sgb[2], sgb[3]};
+      reinterpret_cast<double4*>(A.hist)[2 * slot + 1] = double4{sgb[4], sgb[5], pcb, 0.0};
     }
     // Total bond stress sigma_ij + Sr_i s_i 1 (Eq. 32 with p_w = -s) times K_ij^{-1}.
     const double ps = Sr_i * s_i;
@@ -2768,6 +2837,13 @@ struct ulppm_ctx {
   unsigned long long* ctr_sum = nullptr;  // C_NCOUNT, folded
   double* E = nullptr;        // 3
   ContactDev contact = {};    // substrate (ulppm_set_contact); off by default
+  // history on the bonds (ulppm_history_reserve): hist[last] holds the states
+  // of the last step in the order of hist_row/hist_col, 8 doubles per bond
+  double* hist[2] = {nullptr, nullptr};
+  int64_t* hist_row = nullptr;
+  int32_t* hist_col = nullptr;
+  int hist_last = 0;
+  int64_t hist_n = 0;         // points of the held history; 0: none
   // adjoint scratch (ulppm_adjoint_reserve)
   double* adj = nullptr;      // 24n forward copy + 21n point adjoints + 4(n+8) partials
   double* adj_slot = nullptr; // 7 x bond_cap
@@ -2833,6 +2909,10 @@ int check_params(ulppm_ctx* ctx, const ulppm_params* p) {
       p->force_mode != ULPPM_FORCE_STANDARD)
     return fail(ctx, ULPPM_E_ARG, "bad force_mode");
   if (p->plane != 0 && p->plane != 1) return fail(ctx, ULPPM_E_ARG, "plane must be 0 or 1");
+  if (p->history != ULPPM_HISTORY_POINT && p->history != ULPPM_HISTORY_BOND)
+    return fail(ctx, ULPPM_E_ARG, "bad history");
+  if (p->history == ULPPM_HISTORY_BOND && p->force_mode == ULPPM_FORCE_STANDARD)
+    return fail(ctx, ULPPM_E_ARG, "the standard model has no bond stresses to carry");
   return ULPPM_OK;
 }
 
@@ -2932,7 +3012,7 @@ size_t bond_lds(int max_f, bool mixed) {
 // Algorithm 1 (bond pass) into outputs; mode: step (state outputs) or not.
 // mark(0) / mark(1) bracket the point-kinematics kernels when timing.
 int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, double dt_inc, bool commit,
-              const std::function<void(int)>& mark = nullptr) {
+              const std::function<void(int)>& mark = nullptr, double* hist = nullptr) {
   const int64_t n = S->n;
   BondArgs A;
   A.n = n;
@@ -2959,6 +3039,7 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   }
   const bool mixed = p->precision == ULPPM_MIXED;
   A.T = ctx->T;
+  A.hist = hist;
   A.dt_inc = dt_inc;
   A.max_f = ctx->max_f;
   A.ctr = ctx->ctr;
@@ -2984,10 +3065,20 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
     HIPCHK(hipGetLastError());
     return ULPPM_OK;
   }
-  if (mixed)
-    k_bond_mx<float><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
+  const unsigned grid = (unsigned)(8 * A.per);
+  const bool one_wave = ctx->max_f <= kWave;             // every family fits one wave
+  if (mixed && hist)
+    k_bond_mx<float, true, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  else if (mixed && one_wave)
+    k_bond_mx<float, false, kWave><<<grid, kWave, lds, ctx->stream>>>(A, P);
+  else if (mixed)
+    k_bond_mx<float, false, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  else if (hist)
+    k_bond_mx<double, true, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  else if (one_wave)
+    k_bond_mx<double, false, kWave><<<grid, kWave, lds, ctx->stream>>>(A, P);
   else
-    k_bond_mx<double><<<(unsigned)(8 * A.per), kBondThreads, lds, ctx->stream>>>(A, P);
+    k_bond_mx<double, false, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
@@ -3312,10 +3403,14 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
     return ULPPM_E_HIP;
   }
   // the bond kernel's dynamic LDS may exceed the default cap for large max_family
-  (void)hipFuncSetAttribute((const void*)k_bond_mx<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)bond_lds(max_family, false));
-  (void)hipFuncSetAttribute((const void*)k_bond_mx<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)bond_lds(max_family, true));
+  for (const void* k : {(const void*)k_bond_mx<double, false, kBondThreads>,
+                        (const void*)k_bond_mx<double, true, kBondThreads>,
+                        (const void*)k_bond_mx<double, false, kWave>})
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, false));
+  for (const void* k : {(const void*)k_bond_mx<float, false, kBondThreads>,
+                        (const void*)k_bond_mx<float, true, kBondThreads>,
+                        (const void*)k_bond_mx<float, false, kWave>})
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, true));
   if (hipGetLastError() != hipSuccess) {
     ulppm_destroy(ctx);
     return ULPPM_E_HIP;
@@ -3332,7 +3427,7 @@ int ulppm_destroy(ulppm_ctx* ctx) {
                   ctx->ccnt, ctx->crev, ctx->posmap, ctx->xref, ctx->gate,
                   ctx->ccount, ctx->ccursor, ctx->cstart, ctx->cpts, ctx->col, ctx->rev, ctx->T,
                   ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->ctr_sum, ctx->E, ctx->adj,
-                  ctx->adj_slot};
+                  ctx->adj_slot, ctx->hist[0], ctx->hist[1], ctx->hist_row, ctx->hist_col};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ctx->have_events)
@@ -3430,6 +3525,7 @@ int ulppm_init_state(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, doub
   if ((rc = check_params(ctx, p))) return rc;
   if (!(ocr >= 1.0)) return fail(ctx, ULPPM_E_ARG, "ocr must be >= 1");
   const int64_t n = S->n;
+  ctx->hist_n = 0;                        // a new state: no bond history yet
   if ((rc = zero_counters(ctx))) return rc;
   DevParams P = dev_params(p);
   k_init_points<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(*S, P, ocr);
@@ -3508,6 +3604,55 @@ int ulppm_set_contact(ulppm_ctx* ctx, const ulppm_contact* c) {
   return ULPPM_OK;
 }
 
+int ulppm_history_reserve(ulppm_ctx* ctx) {
+  if (!ctx) return ULPPM_E_ARG;
+  if (ctx->hist[0]) return ULPPM_OK;
+  const size_t st = sizeof(double) * 8 * (size_t)ctx->bond_cap;
+  void* a = nullptr;
+  void* b = nullptr;
+  void* r = nullptr;
+  void* c = nullptr;
+  hipError_t e = hipMalloc(&a, st);
+  if (e == hipSuccess) e = hipMalloc(&b, st);
+  if (e == hipSuccess) e = hipMalloc(&r, sizeof(int64_t) * (size_t)(ctx->cap_n + 1));
+  if (e == hipSuccess) e = hipMalloc(&c, sizeof(int32_t) * (size_t)ctx->bond_cap);
+  if (e != hipSuccess) {
+    for (void* q : {a, b, r, c})
+      if (q) (void)hipFree(q);
+    return fail(ctx, ULPPM_E_HIP, std::string("bond history: ") + hipGetErrorString(e));
+  }
+  ctx->hist[0] = static_cast<double*>(a);
+  ctx->hist[1] = static_cast<double*>(b);
+  ctx->hist_row = static_cast<int64_t*>(r);
+  ctx->hist_col = static_cast<int32_t*>(c);
+  ctx->hist_last = 0;
+  ctx->hist_n = 0;
+  return ULPPM_OK;
+}
+
+int ulppm_history_export(ulppm_ctx* ctx, int64_t* row_out, int32_t* col_out, double* st_out, int64_t cap,
+                         int64_t* nb_out) {
+  if (!ctx) return ULPPM_E_ARG;
+  if (!nb_out) return fail(ctx, ULPPM_E_ARG, "nb_out is NULL");
+  if (!ctx->hist[0] || ctx->hist_n == 0) return fail(ctx, ULPPM_E_ARG, "no bond history is held");
+  const int64_t n = ctx->hist_n;
+  int64_t nb = 0;
+  HIPCHK(hipMemcpyAsync(&nb, ctx->hist_row + n, sizeof(nb), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *nb_out = nb;
+  if (!row_out && !col_out && !st_out) return ULPPM_OK;
+  if (cap < nb) return fail(ctx, ULPPM_E_CAPACITY, "cap is smaller than the bond count");
+  if (row_out)
+    HIPCHK(hipMemcpyAsync(row_out, ctx->hist_row, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, ctx->stream));
+  if (col_out)
+    HIPCHK(hipMemcpyAsync(col_out, ctx->hist_col, sizeof(int32_t) * nb, hipMemcpyDeviceToDevice, ctx->stream));
+  if (st_out)
+    HIPCHK(hipMemcpyAsync(st_out, ctx->hist[ctx->hist_last], sizeof(double) * 8 * nb, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ULPPM_OK;
+}
+
 int ulppm_adjoint_reserve(ulppm_ctx* ctx) {
   if (!ctx) return ULPPM_E_ARG;
   if (ctx->adj) return ULPPM_OK;
@@ -3536,6 +3681,7 @@ int ulppm_adjoint_init(ulppm_ctx* ctx, const ulppm_state* S0, const ulppm_params
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
   if (ctx->contact.on) return fail(ctx, ULPPM_E_ARG, "the adjoint does not include contact forces");
   if (p->plane) return fail(ctx, ULPPM_E_ARG, "the adjoint is three-dimensional only");
+  if (p->history) return fail(ctx, ULPPM_E_ARG, "the adjoint carries the history on the points only");
   if (!(ocr >= 1.0)) return fail(ctx, ULPPM_E_ARG, "ocr must be >= 1");
   const int64_t n = S0->n;
   if (adj0->n != n) return fail(ctx, ULPPM_E_ARG, "adjoint state must match the state size");
@@ -3601,6 +3747,7 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
   if (ctx->contact.on) return fail(ctx, ULPPM_E_ARG, "the adjoint does not include contact forces");
   if (p->plane) return fail(ctx, ULPPM_E_ARG, "the adjoint is three-dimensional only");
+  if (p->history) return fail(ctx, ULPPM_E_ARG, "the adjoint carries the history on the points only");
   if (p->precision != ULPPM_FP64 || p->force_mode != ULPPM_FORCE_CONJUGATE)
     return fail(ctx, ULPPM_E_ARG, "the adjoint supports FP64 with conjugate force states");
   if (!(p->dt > 0.0)) return fail(ctx, ULPPM_E_ARG, "dt must be > 0");
@@ -3693,6 +3840,8 @@ int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_
   DevParams P = dev_params(p);
   const int npb = blocks_for(n, 256, 2048);
   const int64_t timed = p->timing ? std::min<int64_t>(n_steps, kTimedSteps) : 0;
+  const bool bond_history = p->history == ULPPM_HISTORY_BOND;
+  if (bond_history && !ctx->hist[0]) return fail(ctx, ULPPM_E_ARG, "call ulppm_history_reserve first");
   auto mark = [&](int64_t k, int ph, int b) {
     if (k < timed) (void)hipEventRecord(ctx->ev[k][ph][b], ctx->stream);
   };
@@ -3705,12 +3854,27 @@ int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_
     if ((rc = build_families(ctx, n, p->delta, false))) return rc;
     mark(k, 1, 1);
     mark(k, 4, 0);
+    double* hist = nullptr;
+    if (bond_history) {
+      const int have = ctx->hist_n == n ? 1 : 0;
+      hist = ctx->hist[ctx->hist_last ^ 1];
+      k_hist_carry<<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->row, ctx->col, ctx->hist_row, ctx->hist_col, have,
+                                                          ctx->hist[ctx->hist_last], hist, *S);
+      HIPCHK(hipGetLastError());
+    }
     if ((rc = bond_pass(ctx, S, p, p->dt, true, [&](int b) {
            if (b == 0) return;
            mark(k, 4, 1);
            mark(k, 2, 0);
-         })))
+         }, hist)))
       return rc;
+    if (bond_history) {
+      k_hist_keep<<<blocks_for(ctx->bond_cap, 256, 4096), 256, 0, ctx->stream>>>(n, ctx->row, ctx->col, ctx->hist_row,
+                                                                                 ctx->hist_col);
+      HIPCHK(hipGetLastError());
+      ctx->hist_last ^= 1;
+      ctx->hist_n = n;
+    }
     mark(k, 2, 1);
     mark(k, 3, 0);
     if ((rc = gather_pass(ctx, S, p, G_STEP, S->mass, nullptr))) return rc;

@@ -17,6 +17,7 @@ LIB_PATH = os.environ.get("ULPPM_LIB") or os.path.join(HERE, "libulppm.so")
 
 ULPPM_FP64, ULPPM_MIXED = 0, 1
 ULPPM_FORCE_CONJUGATE, ULPPM_FORCE_EQ51, ULPPM_FORCE_STANDARD = 0, 1, 2
+ULPPM_HISTORY_POINT, ULPPM_HISTORY_BOND = 0, 1
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_CAPACITY", -4: "E_NOCONV", -5: "E_NONFINITE", -6: "E_ENERGY",
           -7: "E_HIP"}
 
@@ -30,7 +31,7 @@ class Params(C.Structure):
                 ("a2", C.c_double), ("n_vg", C.c_double), ("g", C.c_double * 3), ("dt", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("precision", C.c_int32),
                 ("energy_check", C.c_int32), ("force_mode", C.c_int32), ("energy_tol", C.c_double),
-                ("timing", C.c_int32), ("plane", C.c_int32)]
+                ("timing", C.c_int32), ("plane", C.c_int32), ("history", C.c_int32), ("pad", C.c_int32)]
 
 
 class State(C.Structure):
@@ -60,7 +61,8 @@ class Contact(C.Structure):
 
 EXPORTS = ["ulppm_create", "ulppm_destroy", "ulppm_last_error", "ulppm_init_state", "ulppm_dt_crit",
            "ulppm_build_families", "ulppm_forces", "ulppm_step", "ulppm_reset_energy", "ulppm_adjoint_reserve",
-           "ulppm_adjoint_step", "ulppm_adjoint_init", "ulppm_selfcheck_tail", "ulppm_set_contact"]
+           "ulppm_adjoint_step", "ulppm_adjoint_init", "ulppm_selfcheck_tail", "ulppm_set_contact",
+           "ulppm_history_reserve", "ulppm_history_export"]
 
 _lib = None
 
@@ -100,6 +102,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.ulppm_selfcheck_tail.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32)]
     L.ulppm_set_contact.argtypes = [vp, C.POINTER(Contact)]
+    L.ulppm_history_reserve.argtypes = [vp]
+    L.ulppm_history_export.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
     for name in EXPORTS:
         if name != "ulppm_last_error":
             getattr(L, name).restype = C.c_int
@@ -122,6 +126,7 @@ def make_params(prm: dict, precision: int = ULPPM_FP64, **over) -> Params:
     p.force_mode = int(d.get("force_mode", 0))
     p.timing = int(d.get("timing", 0))
     p.plane = int(d.get("plane", 0))
+    p.history = int(d.get("history", 0))
     return p
 
 
@@ -256,6 +261,22 @@ class Context:
         c.spacing = float(desc["spacing"])
         c.n[:] = [int(v) for v in desc["n"]]
         self._check(self.L.ulppm_set_contact(self.h, C.byref(c)))
+
+    def history_reserve(self):
+        self._check(self.L.ulppm_history_reserve(self.h))
+
+    def history_export(self, device="cuda"):
+        """(row, col, states (nb, 8)) of the bond history of the last step."""
+        import torch
+        nb = C.c_int64()
+        self._check(self.L.ulppm_history_export(self.h, None, None, None, 0, C.byref(nb)))
+        m = int(nb.value)
+        row = torch.empty(self.n_points + 1, dtype=torch.int64, device=device)
+        col = torch.empty(max(m, 1), dtype=torch.int32, device=device)
+        st = torch.empty((max(m, 1), 8), dtype=torch.float64, device=device)
+        self._check(self.L.ulppm_history_export(self.h, C.c_void_p(row.data_ptr()), C.c_void_p(col.data_ptr()),
+                                                C.c_void_p(st.data_ptr()), m, C.byref(nb)))
+        return row, col[:m], st[:m]
 
     def init_state(self, S: DeviceState, p: Params, ocr: float):
         cs = S.cstruct()

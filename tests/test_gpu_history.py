@@ -1,0 +1,125 @@
+"""Parity of the history carried on the bonds (ULPPM_HISTORY_BOND) between
+the HIP library and the CPU oracle.
+
+Bars: the exported bond families bit-exact; point fields and bond states
+within 1e-10 relative L2 over 200 steps in FP64, 1e-4 in mixed precision.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2203_05562_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2203_05562_amd import ulppm
+    ulppm.load_library()
+    return ulppm
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, float).ravel()
+    b = np.asarray(b, float).ravel()
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def history_pair(olib, gpu, dims=(8, 8, 16), seed=0, precision=None, vscale=0.0):
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=seed, dims=dims)
+    oprm = olib.make_params(col["params"])
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    if vscale > 0:
+        v = inputs.random_velocity(col["n"], seed + 100, vscale)
+        v[col["fixed"] == 1] = 0.0
+        S["v"][:] = v
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    over = dict(history=gpu.ULPPM_HISTORY_BOND)
+    if precision is not None:
+        over["precision"] = precision
+    gprm = gpu.make_params(olib.params_dict(oprm), **over)
+    ctx = gpu.Context(col["n"])
+    ctx.history_reserve()
+    G = gpu.DeviceState.from_arrays(S)
+    H = olib.BondHistory(col["n"], 200 * col["n"])
+    return col, oprm, gprm, S, G, ctx, H
+
+
+@pytest.mark.parametrize("nsteps,calls", [(1, 1), (200, 1), (200, 4)])
+def test_bond_history_trajectory(olib, gpu, nsteps, calls):
+    """200 steps of the 8 x 8 x 16 column with the history on the bonds, in
+    one call or spread over several (the states persist in the context)."""
+    say("bond history", nsteps, calls)
+    col, oprm, gprm, S, G, ctx, H = history_pair(olib, gpu, seed=0, vscale=0.05)
+    E = np.zeros(3)
+    rc, E, st = olib.step_bond_history(S, oprm, H, nsteps, E)
+    assert rc == 0
+    rep = None
+    for _ in range(calls):
+        rep = ctx.step(G, gprm, nsteps // calls)
+    Sg = G.to_arrays()
+    errs = {k: rel_l2(Sg[k], S[k]) for k in ("u", "v", "a", "sig", "pc", "J")}
+    row, colx, st_g = ctx.history_export()
+    n = col["n"]
+    assert np.array_equal(row.cpu().numpy()[:n + 1], H.row) and np.array_equal(colx.cpu().numpy(), H.col[:H.nb])
+    e_st = rel_l2(st_g.cpu().numpy()[:, :7], H.st[:H.nb, :7])
+    say(f"{nsteps} steps", {k: f"{v:.2e}" for k, v in errs.items()}, "bond states", f"{e_st:.2e}",
+        "plastic", st["n_plastic"], rep["n_plastic"])
+    assert all(v <= 1e-10 for v in errs.values()), errs
+    assert e_st <= 1e-10
+
+
+def test_bond_history_differs_from_point_history(olib, gpu):
+    """The two history rules give different columns (the point rule resets
+    every bond to the point mean each step); both match their oracle."""
+    say("bond vs point history")
+    col, oprm, gprm, S, G, ctx, H = history_pair(olib, gpu, seed=3)
+    Sp = {k: v.copy() for k, v in S.items()}
+    rc, _, _ = olib.step_bond_history(S, oprm, H, 100)
+    assert rc == 0
+    rc, _, _ = olib.step(Sp, oprm, 100)
+    assert rc == 0
+    ctx.step(G, gprm, 100)
+    d = rel_l2(S["sig"], Sp["sig"])
+    say("sigma bond vs point", d)
+    assert d > 1e-3
+    assert rel_l2(G.to_arrays()["sig"], S["sig"]) <= 1e-10
+
+
+def test_bond_history_mixed(olib, gpu):
+    say("bond history mixed")
+    col, oprm, gprm, S, G, ctx, H = history_pair(olib, gpu, seed=1, precision=gpu.ULPPM_MIXED)
+    rc, _, _ = olib.step_bond_history(S, oprm, H, 200)
+    assert rc == 0
+    ctx.step(G, gprm, 200)
+    Sg = G.to_arrays()
+    errs = {k: rel_l2(Sg[k], S[k]) for k in ("u", "v", "sig")}
+    say("mixed", errs)
+    assert all(v <= 1e-4 for v in errs.values()), errs
+
+
+def test_bond_history_errors(olib, gpu):
+    import torch
+    col, oprm, gprm, S, G, ctx, H = history_pair(olib, gpu, dims=(6, 6, 6))
+    ctx2 = gpu.Context(col["n"])
+    with pytest.raises(gpu.UlppmError) as ei:          # not reserved
+        ctx2.step(G, gprm, 1)
+    assert ei.value.code == -1
+    with pytest.raises(gpu.UlppmError) as ei:          # nothing held yet
+        ctx.history_export()
+    assert ei.value.code == -1
+    ctx.adjoint_reserve()
+    A1 = gpu.DeviceState.from_arrays(olib.empty_state(col["n"]))
+    A0 = gpu.DeviceState.from_arrays(olib.empty_state(col["n"]))
+    with pytest.raises(gpu.UlppmError) as ei:
+        ctx.adjoint_step(G, gprm, A1, A0, torch.zeros(4, dtype=torch.float64, device="cuda"))
+    assert ei.value.code == -1

@@ -406,3 +406,26 @@ def test_zero_energy_mode_at_scale(gpu):
         say("mode", mode, "max interior force change", df[mode])
     assert df[gpu.ULPPM_FORCE_CONJUGATE] > 1e-3
     assert df[gpu.ULPPM_FORCE_STANDARD] <= 1e-9 * df[gpu.ULPPM_FORCE_CONJUGATE]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_wave_bond_kernel_small_horizon(olib, gpu, precision):
+    """delta = 2 dx (families of ~32) with max_family = 64: the bond kernel
+    runs one wave per point; 100 steps against the oracle."""
+    say("one-wave bond kernel", precision)
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=6, dims=(10, 10, 14))
+    prm = dict(col["params"], delta=2.0 * inputs.DX)
+    oprm = olib.make_params(prm)
+    S = olib.init_column(col, oprm, prm["ocr"])
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    over = {} if precision == "fp64" else dict(precision=gpu.ULPPM_MIXED)
+    gprm = gpu.make_params(olib.params_dict(oprm), **over)
+    ctx = gpu.Context(col["n"], max_family=64)
+    G = gpu.DeviceState.from_arrays(S)
+    rc, E, st = olib.step(S, oprm, 100)
+    assert rc == 0
+    rep = ctx.step(G, gprm, 100)
+    assert rep["max_family"] <= 64
+    Sg = G.to_arrays()
+    compare_states(Sg, S, 1e-10 if precision == "fp64" else 1e-4, fields=("u", "v", "sig", "pc", "J"),
+                   label=f"one wave {precision}")

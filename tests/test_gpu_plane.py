@@ -35,7 +35,7 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def plane_pair(olib, gpu, dims=(24, 1, 48), seed=10, vscale=0.0, precision=None, contact=False):
+def plane_pair(olib, gpu, dims=(24, 1, 48), seed=10, vscale=0.0, precision=None, contact=False, max_family=64):
     col = inputs.make_column(inputs.CONFIGS["P0"], seed=seed, dims=dims, fixed_base=not contact)
     sub = None
     over = {}
@@ -52,7 +52,7 @@ def plane_pair(olib, gpu, dims=(24, 1, 48), seed=10, vscale=0.0, precision=None,
     oprm.dt = 0.5 * olib.dt_crit(S, oprm)
     gover = {} if precision is None else dict(precision=precision)
     gprm = gpu.make_params(olib.params_dict(oprm), **gover)
-    ctx = gpu.Context(col["n"])
+    ctx = gpu.Context(col["n"], max_family=max_family)
     if sub:
         ctx.set_contact(sub)
     G = gpu.DeviceState.from_arrays(S)
@@ -91,9 +91,12 @@ def test_plane_forces(olib, gpu, vscale, dtmul):
     assert np.abs(fg - out["f"]).max() <= 1e-11 * fs
 
 
-def test_plane_trajectory(olib, gpu):
-    say("plane trajectory")
-    col, oprm, gprm, S, G, ctx = plane_pair(olib, gpu, seed=10)
+@pytest.mark.parametrize("max_family", [64, 0])
+def test_plane_trajectory(olib, gpu, max_family):
+    """200 steps; max_family 64 runs the one-wave bond kernel, 0 (152) the
+    two-wave one."""
+    say("plane trajectory", max_family)
+    col, oprm, gprm, S, G, ctx = plane_pair(olib, gpu, seed=10, max_family=max_family)
     E = np.zeros(3)
     rc, E, st = olib.step(S, oprm, 200, E)
     assert rc == 0
