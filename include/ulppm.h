@@ -172,7 +172,9 @@ const char *ulppm_last_error(const ulppm_ctx *ctx);
  * ulppm_forces / ulppm_init_state; V_i the point volume of step n.  cs is a
  * force per volume squared per length [N/m^7].  The work of contact forces is
  * booked in W_int (the substrate is at rest and does no work), so the energy
- * balance of Eq. 69 is unchanged.  ulppm_dt_crit ignores contact. */
+ * balance of Eq. 69 is unchanged.  ulppm_dt_crit ignores contact.  The
+ * adjoint entry points include the contact forces, with the sign of Eq. 92
+ * frozen like the other branches of the step. */
 typedef struct {
   double cs;                    /* contact stiffness C_s of Eq. 91 [N/m^7]; <= 0 turns contact off */
   double mu_f;                  /* friction coefficient of Eq. 92 */
@@ -185,8 +187,7 @@ typedef struct {
 
 /* Attach (or, with c == NULL or c->cs <= 0, detach) the substrate; the
  * description is copied into the context and used by every later
- * ulppm_init_state, ulppm_forces and ulppm_step.  The adjoint entry points
- * return ULPPM_E_ARG while contact is on (contact is not differentiated).
+ * ulppm_init_state, ulppm_forces, ulppm_step and ulppm_adjoint_step.
  * Errors: ULPPM_E_ARG (spacing or delta_c <= 0, a count < 1, or more than
  * 2^31-1 sites). */
 int ulppm_set_contact(ulppm_ctx *ctx, const ulppm_contact *c);

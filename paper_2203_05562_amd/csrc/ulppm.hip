@@ -92,6 +92,97 @@ struct Grid {                 // cell grid over the current bounding box
   int64_t d0, d1, d2, ncell;
 };
 
+// Substrate of the contact model, as the kernels read it.
+struct ContactDev {
+  double cs, mu_f, dc, dc2, ox, oy, oz, h, Vs;
+  int32_t nx, ny, nz, on;
+};
+
+// Inclusive index range of lattice sites whose coordinate lies within
+// (t_lo, t_hi) in units of the spacing, widened by one site on each side and
+// clipped to [0, n); empty when lo > hi.
+__device__ __forceinline__ void site_range(double t_lo, double t_hi, int n, int* lo, int* hi) {
+  const double a = floor(t_lo) - 1.0, b = ceil(t_hi) + 1.0;
+  if (!(b >= 0.0) || !(a <= (double)(n - 1))) { *lo = 0; *hi = -1; return; }
+  *lo = a < 0.0 ? 0 : (int)a;
+  *hi = b > (double)(n - 1) ? n - 1 : (int)b;
+}
+
+// Contact force density on point i from the substrate sites within delta_c
+// (Eqs. 91-93): sum_s 2 (T_c + T_f) V_s with T_c = -C_s (delta_c - |Y|) Y/|Y|,
+// T_f = -mu_f sign(d|Y|/dt) T_c, Y = x_s - x_i, d|Y|/dt = -Y.v_i/|Y|.  Lanes
+// take the sites of the candidate box; the caller reduces over the wave.
+__device__ void contact_density(const ContactDev& C, bool plane, double xi, double yi, double zi, double vx,
+                                double vy, double vz, int lane, double* out) {
+#pragma clang fp contract(off)
+  out[0] = out[1] = out[2] = 0.0;
+  const double Vs = plane ? C.h * C.h : C.Vs;                  // unit thickness in plane strain
+  int a0, a1, b0, b1, k0, k1;
+  site_range((xi - C.dc - C.ox) / C.h, (xi + C.dc - C.ox) / C.h, C.nx, &a0, &a1);
+  site_range((yi - C.dc - C.oy) / C.h, (yi + C.dc - C.oy) / C.h, C.ny, &b0, &b1);
+  site_range((C.oz - zi - C.dc) / C.h, (C.oz - zi + C.dc) / C.h, C.nz, &k0, &k1);
+  if (a1 < a0 || b1 < b0 || k1 < k0) return;
+  const int na = a1 - a0 + 1, nb = b1 - b0 + 1;
+  const int64_t total = (int64_t)na * nb * (k1 - k0 + 1);
+  for (int64_t e = lane; e < total; e += kWave) {
+    const int a = a0 + (int)(e % na), b = b0 + (int)((e / na) % nb), k = k0 + (int)(e / ((int64_t)na * nb));
+    const double Y0 = (C.ox + (double)a * C.h) - xi;
+    const double Y1 = (C.oy + (double)b * C.h) - yi;
+    const double Y2 = (C.oz - (double)k * C.h) - zi;
+    const double r2 = (Y0 * Y0 + Y1 * Y1) + Y2 * Y2;
+    if (!(r2 < C.dc2) || r2 == 0.0) continue;
+    const double r = sqrt(r2);
+    const double tc = -C.cs * (C.dc - r) / r;                  // T_c = tc Y
+    const double rate = -(Y0 * vx + Y1 * vy + Y2 * vz);         // |Y| d|Y|/dt
+    const double sg = rate > 0.0 ? 1.0 : (rate < 0.0 ? -1.0 : 0.0);
+    const double w = 2.0 * Vs * tc * (1.0 - C.mu_f * sg);      // 2 (T_c + T_f) V_s = w Y
+    out[0] += w * Y0;
+    out[1] += w * Y1;
+    out[2] += w * Y2;
+  }
+}
+
+// Reverse of the contact force of point i (frictional branch frozen):
+// with f_i = V_i sum_s c(r) Y, c = -2 V_s (1 - mu_f sg) C_s (delta_c - r)/r
+// and Y = x_s - x_i, the adjoint fbar of f_i adds
+//   xbar_i -= V_i sum_s [c fbar + (dc/dr)/r (Y . fbar) Y],  dc/dr = 2 V_s (1 - mu_f sg) C_s delta_c / r^2,
+//   Vbar_i += sum_s c (Y . fbar).
+// Lanes take the sites of the candidate box; the caller reduces over the wave.
+__device__ void contact_adjoint(const ContactDev& C, bool plane, double xi, double yi, double zi, double vx,
+                                double vy, double vz, double Vi, const double* fb, int lane, double* xbar,
+                                double* Vbar) {
+#pragma clang fp contract(off)
+  xbar[0] = xbar[1] = xbar[2] = 0.0;
+  *Vbar = 0.0;
+  const double Vs = plane ? C.h * C.h : C.Vs;
+  int a0, a1, b0, b1, k0, k1;
+  site_range((xi - C.dc - C.ox) / C.h, (xi + C.dc - C.ox) / C.h, C.nx, &a0, &a1);
+  site_range((yi - C.dc - C.oy) / C.h, (yi + C.dc - C.oy) / C.h, C.ny, &b0, &b1);
+  site_range((C.oz - zi - C.dc) / C.h, (C.oz - zi + C.dc) / C.h, C.nz, &k0, &k1);
+  if (a1 < a0 || b1 < b0 || k1 < k0) return;
+  const int na = a1 - a0 + 1, nb = b1 - b0 + 1;
+  const int64_t total = (int64_t)na * nb * (k1 - k0 + 1);
+  for (int64_t e = lane; e < total; e += kWave) {
+    const int a = a0 + (int)(e % na), b = b0 + (int)((e / na) % nb), k = k0 + (int)(e / ((int64_t)na * nb));
+    const double Y0 = (C.ox + (double)a * C.h) - xi;
+    const double Y1 = (C.oy + (double)b * C.h) - yi;
+    const double Y2 = (C.oz - (double)k * C.h) - zi;
+    const double r2 = (Y0 * Y0 + Y1 * Y1) + Y2 * Y2;
+    if (!(r2 < C.dc2) || r2 == 0.0) continue;
+    const double r = sqrt(r2);
+    const double rate = -(Y0 * vx + Y1 * vy + Y2 * vz);
+    const double sg = rate > 0.0 ? 1.0 : (rate < 0.0 ? -1.0 : 0.0);
+    const double k2 = 2.0 * Vs * (1.0 - C.mu_f * sg) * C.cs;
+    const double c = -k2 * (C.dc - r) / r;
+    const double dcr = k2 * C.dc / (r2 * r);                    // (dc/dr) / r
+    const double yf = Y0 * fb[0] + Y1 * fb[1] + Y2 * fb[2];
+    xbar[0] -= Vi * (c * fb[0] + dcr * yf * Y0);
+    xbar[1] -= Vi * (c * fb[1] + dcr * yf * Y1);
+    xbar[2] -= Vi * (c * fb[2] + dcr * yf * Y2);
+    *Vbar += c * yf;
+  }
+}
+
 // Device counters are striped by block so that concurrent blocks rarely hit
 // the same address; k_reduce_counters folds the stripes once per call.
 __device__ __forceinline__ void ctr_add(unsigned long long* ctr, int k, unsigned long long v) {
@@ -2421,7 +2512,9 @@ __global__ __launch_bounds__(256) void k_adj_point2(int64_t n, const int64_t* __
                                                     const double* __restrict__ sigb, const double* __restrict__ pcb,
                                                     const double* __restrict__ Jb, const double* __restrict__ phib,
                                                     const double* __restrict__ sb, ulppm_state In, ulppm_state Out,
-                                                    double dt) {
+                                                    double dt, ContactDev C, const double* __restrict__ fbar,
+                                                    const double* __restrict__ xp, const double* __restrict__ vhp,
+                                                    const double* __restrict__ voln) {
   const int lane = threadIdx.x & (kWave - 1);
   const XcdWalk W = xcd_walk(n, 4);
   for (int64_t k = W.first; k < W.end; k += W.stride) {
@@ -2439,10 +2532,18 @@ __global__ __launch_bounds__(256) void k_adj_point2(int64_t n, const int64_t* __
       av[c] = wave_sum(av[c]);
     }
     aV = wave_sum(aV);
+    double cx[3] = {0.0, 0.0, 0.0}, cV = 0.0;
+    if (C.on) {                                             // contact forces on k (Eqs. 91-93)
+      const double fb[3] = {fbar[k], fbar[n + k], fbar[2 * n + k]};
+      contact_adjoint(C, false, xp[k], xp[n + k], xp[2 * n + k], vhp[k], vhp[n + k], vhp[2 * n + k], voln[k], fb,
+                      lane, cx, &cV);
+      for (int c = 0; c < 3; ++c) cx[c] = wave_sum(cx[c]);
+      cV = wave_sum(cV);
+    }
     if (lane == 0) {
       const bool fx = fixed[k] != 0;
       for (int c = 0; c < 3; ++c) {
-        const double xb = own_x[c * n + k] + ax[c];
+        const double xb = own_x[c * n + k] + ax[c] + cx[c];
         const double ub = In.u[c][k] + xb;                   // u^{n+1} = u^n + dt v_half, x = x0 + u^{n+1}
         const double vhb = In.v[c][k] + own_vh[c * n + k] + av[c] + dt * ub;
         Out.x0[c][k] = In.x0[c][k] + xb;
@@ -2451,7 +2552,7 @@ __global__ __launch_bounds__(256) void k_adj_point2(int64_t n, const int64_t* __
         Out.v[c][k] = fx ? 0.0 : vhb;
         Out.a[c][k] = fx ? 0.0 : 0.5 * dt * vhb;
       }
-      Out.vol[k] = own_V[k] + aV;
+      Out.vol[k] = own_V[k] + aV + cV;
       Out.phi[k] = phib[k];
       Out.J[k] = Jb[k];
       Out.Sr[k] = 0.0;
@@ -2531,11 +2632,6 @@ __global__ void k_adj_init(ulppm_state S, ulppm_state B, DevParams P, double ocr
 
 enum { G_FORCES = 0, G_INIT = 1, G_STEP = 2 };
 
-// Substrate of the contact model, as the kernels read it.
-struct ContactDev {
-  double cs, mu_f, dc, dc2, ox, oy, oz, h, Vs;
-  int32_t nx, ny, nz, on;
-};
 
 struct GatherArgs {
   int64_t n, per;
@@ -2558,50 +2654,6 @@ struct GatherArgs {
   ContactDev c;
   int plane;
 };
-
-// Inclusive index range of lattice sites whose coordinate lies within
-// (t_lo, t_hi) in units of the spacing, widened by one site on each side and
-// clipped to [0, n); empty when lo > hi.
-__device__ __forceinline__ void site_range(double t_lo, double t_hi, int n, int* lo, int* hi) {
-  const double a = floor(t_lo) - 1.0, b = ceil(t_hi) + 1.0;
-  if (!(b >= 0.0) || !(a <= (double)(n - 1))) { *lo = 0; *hi = -1; return; }
-  *lo = a < 0.0 ? 0 : (int)a;
-  *hi = b > (double)(n - 1) ? n - 1 : (int)b;
-}
-
-// Contact force density on point i from the substrate sites within delta_c
-// (Eqs. 91-93): sum_s 2 (T_c + T_f) V_s with T_c = -C_s (delta_c - |Y|) Y/|Y|,
-// T_f = -mu_f sign(d|Y|/dt) T_c, Y = x_s - x_i, d|Y|/dt = -Y.v_i/|Y|.  Lanes
-// take the sites of the candidate box; the caller reduces over the wave.
-__device__ void contact_density(const ContactDev& C, bool plane, double xi, double yi, double zi, double vx,
-                                double vy, double vz, int lane, double* out) {
-#pragma clang fp contract(off)
-  out[0] = out[1] = out[2] = 0.0;
-  const double Vs = plane ? C.h * C.h : C.Vs;                  // unit thickness in plane strain
-  int a0, a1, b0, b1, k0, k1;
-  site_range((xi - C.dc - C.ox) / C.h, (xi + C.dc - C.ox) / C.h, C.nx, &a0, &a1);
-  site_range((yi - C.dc - C.oy) / C.h, (yi + C.dc - C.oy) / C.h, C.ny, &b0, &b1);
-  site_range((C.oz - zi - C.dc) / C.h, (C.oz - zi + C.dc) / C.h, C.nz, &k0, &k1);
-  if (a1 < a0 || b1 < b0 || k1 < k0) return;
-  const int na = a1 - a0 + 1, nb = b1 - b0 + 1;
-  const int64_t total = (int64_t)na * nb * (k1 - k0 + 1);
-  for (int64_t e = lane; e < total; e += kWave) {
-    const int a = a0 + (int)(e % na), b = b0 + (int)((e / na) % nb), k = k0 + (int)(e / ((int64_t)na * nb));
-    const double Y0 = (C.ox + (double)a * C.h) - xi;
-    const double Y1 = (C.oy + (double)b * C.h) - yi;
-    const double Y2 = (C.oz - (double)k * C.h) - zi;
-    const double r2 = (Y0 * Y0 + Y1 * Y1) + Y2 * Y2;
-    if (!(r2 < C.dc2) || r2 == 0.0) continue;
-    const double r = sqrt(r2);
-    const double tc = -C.cs * (C.dc - r) / r;                  // T_c = tc Y
-    const double rate = -(Y0 * vx + Y1 * vy + Y2 * vz);         // |Y| d|Y|/dt
-    const double sg = rate > 0.0 ? 1.0 : (rate < 0.0 ? -1.0 : 0.0);
-    const double w = 2.0 * Vs * tc * (1.0 - C.mu_f * sg);      // 2 (T_c + T_f) V_s = w Y
-    out[0] += w * Y0;
-    out[1] += w * Y1;
-    out[2] += w * Y2;
-  }
-}
 
 // One wave per point: f_i = V_i sum_j (T_ij - T_ji) V_j (Eqs. 49-50, sign of
 // Eq. 33), gathering T_ji through rev[] instead of scattering with atomics;
@@ -3679,7 +3731,6 @@ int ulppm_adjoint_init(ulppm_ctx* ctx, const ulppm_state* S0, const ulppm_params
   if ((rc = check_params(ctx, p))) return rc;
   if (!s_bar || !theta_bar) return fail(ctx, ULPPM_E_ARG, "s_bar or theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
-  if (ctx->contact.on) return fail(ctx, ULPPM_E_ARG, "the adjoint does not include contact forces");
   if (p->plane) return fail(ctx, ULPPM_E_ARG, "the adjoint is three-dimensional only");
   if (p->history) return fail(ctx, ULPPM_E_ARG, "the adjoint carries the history on the points only");
   if (!(ocr >= 1.0)) return fail(ctx, ULPPM_E_ARG, "ocr must be >= 1");
@@ -3745,7 +3796,6 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
   if ((rc = check_params(ctx, p))) return rc;
   if (!theta_bar) return fail(ctx, ULPPM_E_ARG, "theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
-  if (ctx->contact.on) return fail(ctx, ULPPM_E_ARG, "the adjoint does not include contact forces");
   if (p->plane) return fail(ctx, ULPPM_E_ARG, "the adjoint is three-dimensional only");
   if (p->history) return fail(ctx, ULPPM_E_ARG, "the adjoint carries the history on the points only");
   if (p->precision != ULPPM_FP64 || p->force_mode != ULPPM_FORCE_CONJUGATE)
@@ -3820,7 +3870,8 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
   HIPCHK(hipGetLastError());
   k_adj_point2<<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->row, ctx->rev, S->fixed, own_x, own_vh, own_V,
                                                       A.slot_x, A.slot_vh, A.slot_V, ctx->bond_cap, sigb, pcb, Jb,
-                                                      phib, sb, *adj1, *adj0, p->dt);
+                                                      phib, sb, *adj1, *adj0, p->dt, ctx->contact, fbar, ctx->x,
+                                                      ctx->vh, ctx->vol_n);
   k_adj_theta<<<1, 256, 0, ctx->stream>>>(thpart, (int64_t)grid, theta_bar);
   HIPCHK(hipGetLastError());
   if ((rc = read_counters(ctx))) return rc;

@@ -28,9 +28,17 @@ def gpu():
     return ulppm
 
 
-def start(olib, gpu, dims=(6, 6, 8), seed=3, vscale=0.3):
-    col = inputs.make_column(inputs.CONFIGS["C0"], seed=seed, dims=dims)
-    oprm = olib.make_params(col["params"])
+def start(olib, gpu, dims=(6, 6, 8), seed=3, vscale=0.3, contact=False):
+    """A small column; with contact it stands free on a substrate raised into
+    the cut-off, so that its base starts in contact."""
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=seed, dims=dims, fixed_base=not contact)
+    over = {}
+    sub = None
+    if contact:
+        sub = inputs.make_substrate(col, extent=0.5, layers=2, mu_f=0.25)
+        sub["origin"][2] += 0.3 * sub["delta_c"]
+        over["contact"] = sub
+    oprm = olib.make_params(col["params"], **over)
     S = olib.init_column(col, oprm, col["params"]["ocr"])
     v = inputs.random_velocity(col["n"], seed + 50, vscale)
     v[col["fixed"] == 1] = 0.0
@@ -38,6 +46,8 @@ def start(olib, gpu, dims=(6, 6, 8), seed=3, vscale=0.3):
     oprm.dt = 0.5 * olib.dt_crit(S, oprm)
     gprm = gpu.make_params(olib.params_dict(oprm))
     ctx = gpu.Context(col["n"])
+    if sub:
+        ctx.set_contact(sub)
     ctx.adjoint_reserve()
     return col, oprm, gprm, S, ctx
 
@@ -110,14 +120,15 @@ def test_one_step_adjoint_identity(olib, gpu):
     assert abs(lhs - rhs) <= 1e-8 * max(abs(lhs), abs(rhs))
 
 
-@pytest.mark.parametrize("nsteps", [1, 8])
-def test_adjoint_matches_dual_numbers(olib, gpu, nsteps):
+@pytest.mark.parametrize("nsteps,contact", [(1, False), (8, False), (8, True)])
+def test_adjoint_matches_dual_numbers(olib, gpu, nsteps, contact):
     """Gradient of J = sum c . u^N through N plastic steps: the GPU adjoint
     dotted with directions in (M, lam, kap, eta), the initial velocity,
     stress, pre-consolidation and suction equals the oracle's directional
-    derivatives."""
-    say("adjoint vs dual", nsteps)
-    col, oprm, gprm, S, ctx = start(olib, gpu)
+    derivatives; with contact, through a base in contact with the substrate
+    (Eqs. 91-93, friction branch frozen)."""
+    say("adjoint vs dual", nsteps, "contact" if contact else "")
+    col, oprm, gprm, S, ctx = start(olib, gpu, contact=contact)
     n = col["n"]
     rng = np.random.default_rng(11)
     c = rng.normal(size=(n, 3))
