@@ -33,7 +33,8 @@ time per forward step, per reverse step (ulppm_adjoint_step) and their ratio.
 (Eqs. 91-93, the substrate one column width wider on every side), its
 throughput and gather phase, the kernel that adds the contact forces.
 "plane": the plane-strain column P1 (512 x 1024 points in the x-z plane,
-families of ~28), its throughput and bond-kernel time.
+families of ~28), its throughput and bond-kernel time.  "history": the
+workload with the history carried on the bonds (ULPPM_HISTORY_BOND).
 """
 import argparse
 import hashlib
@@ -100,14 +101,16 @@ def cpu_baseline(cfg_name, steps, dt):
                 seconds=round(el, 3))
 
 
-def run_column(ulppm, col, precision, warmup, steps, timed=True, contact=None, max_family=0):
+def run_column(ulppm, col, precision, warmup, steps, timed=True, contact=None, max_family=0, history=0):
     """Initial conditions, dt = dt_c / 2, `warmup` untimed steps, then
     `steps` steps timed with HIP events on the library's stream.  `contact`
     attaches a substrate (Eqs. 91-93) first."""
     import torch
     G = ulppm.column_state(col, "cuda:0")
-    prm = ulppm.make_params(col["params"], precision=precision)
+    prm = ulppm.make_params(col["params"], precision=precision, history=history)
     ctx = ulppm.Context(col["n"], max_family=max_family)
+    if history:
+        ctx.history_reserve()
     if contact:
         ctx.set_contact(contact)
     ctx.init_state(G, prm, col["params"]["ocr"])
@@ -148,6 +151,7 @@ def main():
     ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--no-contact", action="store_true", help="skip the substrate-contact companion run")
     ap.add_argument("--no-plane", action="store_true", help="skip the plane-strain companion run")
+    ap.add_argument("--no-history", action="store_true", help="skip the bond-history companion run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -225,6 +229,15 @@ def main():
                                       for k in ("predict", "family", "kin", "bond", "gather")})
         log(f"[gpu] plane: {out['plane']}")
         del Gp
+        torch.cuda.empty_cache()
+    if not args.no_history:
+        Gh, reph, msh, _ = run_column(ulppm, col, prec, args.warmup, args.steps, history=ulppm.ULPPM_HISTORY_BOND)
+        lh = max(reph["timed_steps"], 1)
+        out["history"] = dict(value=reph["n_bond_updates"] / (msh * 1e-3), ms_per_step=msh / args.steps,
+                              phase_ms={k: round(reph[f"t_{k}_ms"] / lh, 4)
+                                        for k in ("predict", "family", "kin", "bond", "gather")})
+        log(f"[gpu] history: {out['history']}")
+        del Gh
         torch.cuda.empty_cache()
     if args.adjoint_config:
         from paper_2203_05562_amd.measure import adjoint_cost
