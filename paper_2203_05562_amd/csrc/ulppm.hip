@@ -2217,15 +2217,24 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   double ownV = 0.0;
   for (int m = tid; m < nf; m += kBondThreads) {
     double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    unsigned long long word = 0ull;
-    MRec<double> r = sM[0];                          // M_j, loaded one member ahead
-    for (int j = 0; j < nf; ++j) {
-      if ((j & 63) == 0) word = sb[(size_t)m * nw + (j >> 6)];
-      const MRec<double> rn = sM[j + 1 < nf ? j + 1 : j];
-      const int jj = j & 63;
-      const double w = (word >> (16 * (jj & 3) + (jj >> 2))) & 1ull ? 1.0 : 0.0;
-      for (int q = 0; q < 9; ++q) a[q] += w * r.v[q];
-      r = rn;
+    // members 64 c + 4 s + q in groups of four (bits 16 q + s of word c);
+    // rows past the family are clamped and enter with weight 0
+    for (int c = 0; 64 * c < nf; ++c) {
+      const unsigned long long word = sb[(size_t)m * nw + c];
+      const unsigned lo = (unsigned)word, hi = (unsigned)(word >> 32);
+      for (int s4 = 0; s4 < 16; ++s4) {
+        const int j0 = 64 * c + 4 * s4;
+        if (j0 >= nf) break;
+        MRec<double> r4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r4[q] = sM[j0 + q < nf ? j0 + q : nf - 1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double w = (double)(((q < 2 ? lo : hi) >> (16 * (q & 1) + s4)) & 1u);
+#pragma unroll
+          for (int e = 0; e < 9; ++e) a[e] += w * r4[q].v[e];
+        }
+      }
     }
     const int64_t slot = b0 + m;
     const int32_t k = A.col[slot];
@@ -2265,22 +2274,31 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     if (active) {
       // Mbar_j = sum_k B_jk Tbar_ik zeta_ik^T
       double mb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      unsigned long long word = 0ull;
-      Quad<double> tbk = sTb[0], zk = sZ[0];         // loaded one member ahead
-      for (int t = 0; t < nf; ++t) {
-        if ((t & 63) == 0) word = sb[(size_t)m * nw + (t >> 6)];
-        const int tn = t + 1 < nf ? t + 1 : t;
-        const Quad<double> tbn = sTb[tn], zn = sZ[tn];
-        const int u = t & 63;
-        const double w = (word >> (16 * (u & 3) + (u >> 2))) & 1ull ? 1.0 : 0.0;
-        for (int r = 0; r < 3; ++r) {
-          const double wt = w * tbk.v[r];
-          mb[3 * r] += wt * zk.v[0];
-          mb[3 * r + 1] += wt * zk.v[1];
-          mb[3 * r + 2] += wt * zk.v[2];
+      for (int c = 0; 64 * c < nf; ++c) {             // members in groups of four, as above
+        const unsigned long long word = sb[(size_t)m * nw + c];
+        const unsigned lo = (unsigned)word, hi = (unsigned)(word >> 32);
+        for (int s4 = 0; s4 < 16; ++s4) {
+          const int t0 = 64 * c + 4 * s4;
+          if (t0 >= nf) break;
+          Quad<double> tb4[4], z4[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int t = t0 + q < nf ? t0 + q : nf - 1;
+            tb4[q] = sTb[t];
+            z4[q] = sZ[t];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double w = (double)(((q < 2 ? lo : hi) >> (16 * (q & 1) + s4)) & 1u);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+              const double wt = w * tb4[q].v[r];
+              mb[3 * r] += wt * z4[q].v[0];
+              mb[3 * r + 1] += wt * z4[q].v[1];
+              mb[3 * r + 2] += wt * z4[q].v[2];
+            }
+          }
         }
-        tbk = tbn;
-        zk = zn;
       }
       double Kq[6], Nq[9];
       for (int k = 0; k < 6; ++k) Kq[k] = kn[k];
