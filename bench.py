@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--no-contact", action="store_true", help="skip the substrate-contact companion run")
     ap.add_argument("--no-plane", action="store_true", help="skip the plane-strain companion run")
     ap.add_argument("--no-history", action="store_true", help="skip the bond-history companion run")
+    ap.add_argument("--max-family", type=int, default=128,
+                    help="family capacity of the main run's context (0: the library default, 152); a run whose "
+                         "families outgrow it is repeated with the default")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -168,7 +171,18 @@ def main():
     n = col["n"]
     log(f"[gpu] {args.config}: {cfg.nx}x{cfg.ny}x{cfg.nz} = {n} points, suction {col['suction_kpa']:.2f} kPa")
     prec = ulppm.ULPPM_MIXED if args.precision == "mixed" else ulppm.ULPPM_FP64
-    G, rep, ms, dt = run_column(ulppm, col, prec, args.warmup, args.steps)
+    # A capacity of 128 members (the column's families hold at most ~120) leaves
+    # LDS for five bond workgroups per CU; a family that outgrows it raises a
+    # capacity error, and the run is repeated with the default capacity.
+    max_family = args.max_family
+    try:
+        G, rep, ms, dt = run_column(ulppm, col, prec, args.warmup, args.steps, max_family=max_family)
+    except ulppm.UlppmError as e:
+        if e.code != -2 or max_family == 0:
+            raise
+        log(f"[gpu] families outgrew max_family={max_family}; repeating with the default capacity")
+        max_family = 0
+        G, rep, ms, dt = run_column(ulppm, col, prec, args.warmup, args.steps, max_family=max_family)
     log(f"[gpu] dt = {dt:.4e} s; timed {args.steps} steps after {args.warmup}: {ms:.1f} ms; report {rep}")
     bonds = rep["n_bond_updates"]
     value = bonds / (ms * 1e-3)
@@ -189,6 +203,7 @@ def main():
                data="synthetic",
                config=dict(workload=f"{args.config}: jittered soil column {cfg.nx}x{cfg.ny}x{cfg.nz}, "
                                     f"{args.precision}", points=n, bonds_per_step=bonds / args.steps,
+                           max_family=max_family or 152, largest_family=rep["max_family"],
                            dt=dt, suction_kpa=col["suction_kpa"], seed=cfg.seed, precision=args.precision),
                roofline=roofline, phase_ms=phases)
     if args.precision == "fp64" and not args.no_mixed:

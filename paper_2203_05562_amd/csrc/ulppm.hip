@@ -1480,6 +1480,8 @@ struct Mma<float> {
 };
 
 constexpr int kTileBatch = 4;     // 16-row tiles a wave carries through one sweep over the members
+constexpr size_t kCuLds = 160 * 1024;       // LDS of one CU
+constexpr size_t kBondStaticLds = 512;      // the bond kernel's static LDS, rounded up
 
 template <class Acc>
 __host__ __device__ constexpr size_t bond_mx_lds_bytes(int max_f) {
@@ -1502,9 +1504,12 @@ __host__ __device__ constexpr int feat_b(int f) {
 }
 
 // NT threads per workgroup (one point): 128 for 3D families of ~100, 64 when
-// every family fits one wave (plane strain).
-template <class Acc, bool Hist, int NT>
-__global__ __launch_bounds__(NT, sizeof(Acc) == 8 ? ULPPM_BOND_MX_MIN_WAVES : ULPPM_BOND_MX_MIN_WAVES_MIXED)
+// every family fits one wave (plane strain).  MW: waves per SIMD the FP64
+// instance is compiled for: 2 by default, 3 when the family capacity leaves
+// LDS for five or more workgroups per CU (the extra wave then outweighs the
+// registers it spills).
+template <class Acc, bool Hist, int NT, int MW = ULPPM_BOND_MX_MIN_WAVES>
+__global__ __launch_bounds__(NT, sizeof(Acc) == 8 ? MW : ULPPM_BOND_MX_MIN_WAVES_MIXED)
 void k_bond_mx(BondArgs A, DevParams P) {
   constexpr int kBondThreads = NT, kBondWaves = NT / kWave;
   using TS = Acc;
@@ -3147,6 +3152,8 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
     k_bond_mx<double, true, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   else if (one_wave)
     k_bond_mx<double, false, kWave><<<grid, kWave, lds, ctx->stream>>>(A, P);
+  else if (kCuLds / (lds + kBondStaticLds) >= 5)
+    k_bond_mx<double, false, kBondThreads, 3><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   else
     k_bond_mx<double, false, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   HIPCHK(hipGetLastError());
@@ -3474,6 +3481,7 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   }
   // the bond kernel's dynamic LDS may exceed the default cap for large max_family
   for (const void* k : {(const void*)k_bond_mx<double, false, kBondThreads>,
+                        (const void*)k_bond_mx<double, false, kBondThreads, 3>,
                         (const void*)k_bond_mx<double, true, kBondThreads>,
                         (const void*)k_bond_mx<double, false, kWave>})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, false));

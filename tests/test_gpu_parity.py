@@ -170,11 +170,13 @@ def test_one_step(olib, gpu, vscale):
     assert abs(rep["W_int"] - E[0]) <= 1e-11 * max(abs(E[0]), abs(E[1]))
 
 
-@pytest.mark.parametrize("nsteps", [200, 500])
-def test_trajectory_C0(olib, gpu, nsteps):
-    """8 x 8 x 16 column, FP64: u, v, sigma, p_c, J within 1e-10 relative L2."""
-    say("trajectory", nsteps)
-    col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, (8, 8, 16), seed=0)
+@pytest.mark.parametrize("nsteps,max_family", [(200, 256), (500, 256), (200, 128)])
+def test_trajectory_C0(olib, gpu, nsteps, max_family):
+    """8 x 8 x 16 column, FP64: u, v, sigma, p_c, J within 1e-10 relative L2.
+    A capacity of 128 members runs the bond kernel built for three waves per
+    SIMD (its LDS then leaves room for five workgroups per CU)."""
+    say("trajectory", nsteps, max_family)
+    col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, (8, 8, 16), seed=0, max_family=max_family)
     E = np.zeros(3)
     rc, E, st = olib.step(S, oprm, nsteps, E)
     assert rc == 0
