@@ -1506,8 +1506,8 @@ __host__ __device__ constexpr int feat_b(int f) {
 // NT threads per workgroup (one point): 128 for 3D families of ~100, 64 when
 // every family fits one wave (plane strain).  MW: waves per SIMD the FP64
 // instance is compiled for: 2 by default, 3 when the family capacity leaves
-// LDS for five or more workgroups per CU (the extra wave then outweighs the
-// registers it spills).
+// LDS for more than two waves per SIMD (five two-wave or ten one-wave
+// workgroups per CU; the extra wave then outweighs the registers it spills).
 template <class Acc, bool Hist, int NT, int MW = ULPPM_BOND_MX_MIN_WAVES>
 __global__ __launch_bounds__(NT, sizeof(Acc) == 8 ? MW : ULPPM_BOND_MX_MIN_WAVES_MIXED)
 void k_bond_mx(BondArgs A, DevParams P) {
@@ -3150,6 +3150,8 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
     k_bond_mx<float, false, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   else if (hist)
     k_bond_mx<double, true, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  else if (one_wave && kCuLds / (lds + kBondStaticLds) >= 10)
+    k_bond_mx<double, false, kWave, 3><<<grid, kWave, lds, ctx->stream>>>(A, P);
   else if (one_wave)
     k_bond_mx<double, false, kWave><<<grid, kWave, lds, ctx->stream>>>(A, P);
   else if (kCuLds / (lds + kBondStaticLds) >= 5)
@@ -3483,7 +3485,8 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   for (const void* k : {(const void*)k_bond_mx<double, false, kBondThreads>,
                         (const void*)k_bond_mx<double, false, kBondThreads, 3>,
                         (const void*)k_bond_mx<double, true, kBondThreads>,
-                        (const void*)k_bond_mx<double, false, kWave>})
+                        (const void*)k_bond_mx<double, false, kWave>,
+                        (const void*)k_bond_mx<double, false, kWave, 3>})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, false));
   for (const void* k : {(const void*)k_bond_mx<float, false, kBondThreads>,
                         (const void*)k_bond_mx<float, true, kBondThreads>,
