@@ -1484,12 +1484,19 @@ constexpr size_t kCuLds = 160 * 1024;       // LDS of one CU
 constexpr size_t kBondStaticLds = 512;      // the bond kernel's static LDS, rounded up
 
 template <class Acc>
+__host__ __device__ constexpr size_t bond_mx_member_bytes() {
+  // FP64 member records begin with (zeta, V) in FP64 and serve the exact
+  // membership test directly; the mixed records are FP32, so (zeta, V) is
+  // kept in FP64 beside them
+  return (sizeof(Acc) == 8 ? 0 : sizeof(Quad<double>)) + 8 * sizeof(Acc) + 16 * sizeof(Acc);
+}
+template <class Acc>
 __host__ __device__ constexpr size_t bond_mx_lds_bytes(int max_f) {
   // the family's working set; the closing reduction reuses it for 8 doubles per thread
-  return (size_t)max_f * (sizeof(Quad<double>) + 8 * sizeof(Acc) + 16 * sizeof(Acc)) +
+  return (size_t)max_f * bond_mx_member_bytes<Acc>() +
                  (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long) >
              8 * kBondThreads * sizeof(double)
-         ? (size_t)max_f * (sizeof(Quad<double>) + 8 * sizeof(Acc) + 16 * sizeof(Acc)) +
+         ? (size_t)max_f * bond_mx_member_bytes<Acc>() +
                (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long)
          : 8 * kBondThreads * sizeof(double);
 }
@@ -1525,8 +1532,13 @@ void k_bond_mx(BondArgs A, DevParams P) {
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
   const int nw = (mf + 63) / 64;                   // membership words per row
-  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);        // x_k, V_k
-  Acc* sR = reinterpret_cast<Acc*>(sX + mf);                           // 8 per member: zeta, V, ydot, 1
+  // (zeta_ik, V_k) in FP64 for the exact membership test: the head of the
+  // FP64 member record, or an array of its own beside the FP32 records
+  constexpr bool kF64 = sizeof(Acc) == 8;
+  constexpr int kZs = kF64 ? 2 : 1;                                    // Quad stride of (zeta, V)
+  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);
+  Acc* sR = kF64 ? reinterpret_cast<Acc*>(smem_raw)
+                 : reinterpret_cast<Acc*>(sX + mf);                    // 8 per member: zeta, V, ydot, 1
   Acc* sKN = sR + 8 * (size_t)mf;                                      // 16 per member: K, N, Vs, then M_j
   unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)mf);
   unsigned short* sq = reinterpret_cast<unsigned short*>(sb);
@@ -1547,16 +1559,16 @@ void k_bond_mx(BondArgs A, DevParams P) {
   const double pc_i = A.pc[i];
   if (tid == 0) s_d2 = P.d2;
 
-  // Stage the family of i: positions for the exact predicate, zeta_ik, V_k
-  // and ydot_ik for the feature matrix.
+  // Stage the family of i: zeta_ik and V_k (FP64, for the exact predicate
+  // and the feature matrix) and ydot_ik.
   for (int m = tid; m < nf; m += kBondThreads) {
     const int32_t k = A.col[b0 + m];
     const double4 pa = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k];
     const double4 pb = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k + 1];
-    const double xk0 = pa.x, xk1 = pa.y, xk2 = pa.z, Vk = pa.w;
-    const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
+    const double Vk = pa.w;
+    const double z0 = pa.x - xi0, z1 = pa.y - xi1, z2 = pa.z - xi2;
     const double y0 = pb.x - vi0, y1 = pb.y - vi1, y2 = pb.z - vi2;
-    sX[m] = Quad<double>{{xk0, xk1, xk2, Vk}};
+    if constexpr (!kF64) sX[m] = Quad<double>{{z0, z1, z2, Vk}};
     Acc* rec = sR + 8 * (size_t)m;
     rec[0] = (Acc)z0; rec[1] = (Acc)z1; rec[2] = (Acc)z2; rec[3] = (Acc)Vk;
     rec[4] = (Acc)y0; rec[5] = (Acc)y1; rec[6] = (Acc)y2; rec[7] = (Acc)1;
@@ -1584,21 +1596,21 @@ void k_bond_mx(BondArgs A, DevParams P) {
       for (int b = 0; b < NB; ++b) {
         jrow[b] = (t0 + kBondWaves * b) * 16 + r16;
         jv[b] = jrow[b] < nf;
-        const Quad<double> q = sX[jv[b] ? jrow[b] : 0];
+        const Quad<double> q = sX[kZs * (jv[b] ? jrow[b] : 0)];
         xj[b][0] = q.v[0]; xj[b][1] = q.v[1]; xj[b][2] = q.v[2];
         acc[b] = V4{0, 0, 0, 0};
         piece[b] = 0u;
       }
       // member data of the next step is loaded one step ahead
       bool kv = q4 < nf;
-      Quad<double> xk = sX[kv ? q4 : 0];
+      Quad<double> xk = sX[kZs * (kv ? q4 : 0)];
       Acc ra = sR[8 * (size_t)(kv ? q4 : 0) + fa], rb = sR[8 * (size_t)(kv ? q4 : 0) + fb],
           rv = sR[8 * (size_t)(kv ? q4 : 0) + 3];
       for (int ks = 0; ks < nks; ++ks) {
         const int k1 = 4 * (ks + 1) + q4;
         const bool kv1 = k1 < nf;
         const int kk1 = kv1 ? k1 : 0;
-        const Quad<double> xk1 = sX[kk1];
+        const Quad<double> xk1 = sX[kZs * kk1];
         const Acc* rec1 = sR + 8 * (size_t)kk1;
         const Acc ra1 = rec1[fa], rb1 = rec1[fb], rv1 = rec1[3];
         const Acc fv = ra * rb * rv;
@@ -1728,11 +1740,11 @@ void k_bond_mx(BondArgs A, DevParams P) {
                           sgb[5] * ixy + S11 * iyy + sgb[3] * iyz, sgb[5] * ixz + S11 * iyz + sgb[3] * izz,
                           sgb[4] * ixx + sgb[3] * ixy + S22 * ixz, sgb[4] * ixy + sgb[3] * iyy + S22 * iyz,
                           sgb[4] * ixz + sgb[3] * iyz + S22 * izz};
-    const double Vj = sX[m].v[3];
+    const Quad<double> zj = sX[kZs * m];
+    const double Vj = zj.v[3];
     if (P.force_mode == ULPPM_FORCE_EQ51) {
       // Eq. 51 as printed: T_ij = varpi (sigma_ij + Sr s 1) K_ij^{-1} zeta_ij.
-      const Quad<double> xj = sX[m];
-      const double zx = xj.v[0] - xi0, zy = xj.v[1] - xi1, zz = xj.v[2] - xi2;
+      const double zx = zj.v[0], zy = zj.v[1], zz = zj.v[2];
       T4[slot] = Quad<TS>{{(TS)(varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz)),
                            (TS)(varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz)),
                            (TS)(varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz)), (TS)0}};
@@ -2047,7 +2059,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
   const int nw = (mf + 63) / 64;
-  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);   // x_k (pass 1), then Tbar_ik
+  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);   // Tbar_ik (after pass 1)
   Quad<double>* sTb = sX;
   Quad<double>* sZ = sX + mf;                                     // zeta_ik, V_k
   Quad<double>* sY = sZ + mf;                                     // ydot_ik, 1
@@ -2075,7 +2087,6 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     const double xk0 = pa.x, xk1 = pa.y, xk2 = pa.z, V = pa.w;
     const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
     const double y0 = pb.x - vi0, y1 = pb.y - vi1, y2 = pb.z - vi2;
-    sX[m] = Quad<double>{{xk0, xk1, xk2, 0.0}};
     sZ[m] = Quad<double>{{z0, z1, z2, V}};
     sY[m] = Quad<double>{{y0, y1, y2, 1.0}};
     sZb[m] = Quad<double>{{0.0, 0.0, 0.0, 0.0}};
@@ -2137,7 +2148,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
       for (int b = 0; b < NB; ++b) {
         jrow[b] = (t0 + kBondWaves * b) * 16 + r16;
         jv[b] = jrow[b] < nf;
-        const Quad<double> q = sX[jv[b] ? jrow[b] : 0];
+        const Quad<double> q = sZ[jv[b] ? jrow[b] : 0];     // relative positions: the test of Eq. 22
         xj[b][0] = q.v[0]; xj[b][1] = q.v[1]; xj[b][2] = q.v[2];
         acc[b] = v4d{0, 0, 0, 0};
         piece[b] = 0u;
@@ -2146,7 +2157,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         const int kk0 = 4 * ks + q4;
         const bool kv = kk0 < nf;
         const int kk = kv ? kk0 : 0;
-        const Quad<double> xk = sX[kk];
+        const Quad<double> xk = sZ[kk];
         const double fvv = rz[4 * kk + oa] * rz[4 * kk + ob] * rz[4 * kk + ov];
         const double bval = kv ? fvv : 0.0;
         const unsigned sbit = 1u << (ks & 15);
