@@ -144,10 +144,15 @@ typedef struct {
 } ulppm_report;
 
 /* Create a context for up to n_points points and max_family members per family
- * (0 selects 152: a jittered cubic lattice with delta = 3.015 dx has at most
- * about 125, and 152 lets four FP64 bond workgroups share a CU).  hip_stream
- * is a hipStream_t (NULL = the null stream).
- * Allocates all scratch now; afterwards only ulppm_adjoint_reserve allocates.
+ * (0 selects 152: a jittered cubic lattice with delta = 3.015 dx starts with
+ * at most about 121, and compression adds members).  The bond kernel's LDS is
+ * sized by max_family (about 192 bytes per member in FP64): 152 fits four
+ * FP64 bond workgroups per CU, 128 six, and a max_family of at most 64 runs
+ * the bond kernel with one wave per point.  A family larger than max_family
+ * is an error (ULPPM_E_CAPACITY), never a truncation.  hip_stream is a
+ * hipStream_t (NULL = the null stream).
+ * Allocates all scratch now; afterwards only ulppm_adjoint_reserve and
+ * ulppm_history_reserve allocate.
  * Errors: ULPPM_E_ARG (n_points <= 0 or > 2^31-1, max_family > 1024),
  * ULPPM_E_HIP (allocation failed). */
 int ulppm_create(ulppm_ctx **out, int64_t n_points, int32_t max_family, void *hip_stream);

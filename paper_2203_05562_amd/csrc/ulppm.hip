@@ -1179,7 +1179,7 @@ struct BondArgs {
   double* pc_out;
   void* T;                // bond force states, CSR order, one (x, y, z, 0) record per bond
                           // (double, or float in mixed precision)
-  double* pk;             // 2n: apparent pre-consolidation of p_c,i and 1/V_H,i (k_point_kin)
+  double* pk;             // 2n: apparent pre-consolidation of p_c,i and 1/V_H,i (point kinematics)
   const double* xv;       // 8n: x (3), V^n, v_half (3), 0 per point
   double* hist;           // history on the bonds: 8 per bond (sigma, p_c, 0), updated in place; or null
   double dt_inc;
@@ -1299,13 +1299,16 @@ __global__ __launch_bounds__(256) void k_point_kin_lane(BondArgs A, DevParams P,
   point_update(A, P, i, (int)(b1 - b0), Kp, Np, Vp);
 }
 
-template <class TS, bool Standard>
-__global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
+// The standard correspondence model (Eqs. 12-14): one wave per point forms
+// the full-horizon sums and the point update, then every lane updates the
+// point stress from L_i by the return map and writes T_ij = (sigma_i + S_r s 1)
+// K_i^{-1} zeta_ij for its bonds of the point.
+template <class TS>
+__global__ __launch_bounds__(256) void k_point_kin_standard(BondArgs A, DevParams P) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t n = A.n;
   const XcdWalk W = xcd_walk(n, 4);
-  constexpr bool standard = Standard;
-  int c_deg = 0, c_pl = 0, c_nc = 0, c_mx = 0;          // standard mode, lane 0
+  int c_deg = 0, c_pl = 0, c_nc = 0, c_mx = 0;          // lane 0
   for (int64_t i = W.first; i < W.end; i += W.stride) {
     const int64_t b0 = A.row[i], b1 = A.row[i + 1];
     const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
@@ -1332,7 +1335,7 @@ __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
     for (int k = 0; k < 9; ++k) Np[k] = wave_sum(Np[k]);
     Vp = wave_sum(Vp);
     if (lane == 0) point_update(A, P, i, (int)(b1 - b0), Kp, Np, Vp);
-    if constexpr (standard) {
+    {
       // every lane holds the wave totals and forms the point update itself
       const int nf = (int)(b1 - b0);
       double Ki[6] = {0, 0, 0, 0, 0, 0};
@@ -1382,7 +1385,7 @@ __global__ __launch_bounds__(256) void k_point_kin(BondArgs A, DevParams P) {
       }
     }
   }
-  if (standard && lane == 0) {
+  if (lane == 0) {
     if (c_deg) ctr_add(A.ctr, C_DEGEN, (unsigned long long)c_deg);
     if (c_pl) ctr_add(A.ctr, C_PLASTIC, (unsigned long long)c_pl);
     if (c_nc) ctr_add(A.ctr, C_NOCONV, (unsigned long long)c_nc);
@@ -1550,7 +1553,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
   const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
   const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
 
-  // Per-point values of this step (k_point_kin), fetched while the family is staged.
+  // Per-point values of this step (point kinematics), fetched while the family is staged.
   const double Sr_i = A.Sr_out[i], Pn_i = A.pk[i], iVh = A.pk[n + i];
   const double s_i = A.s[i];
   double sig_i[6];
@@ -1815,7 +1818,6 @@ void k_bond_mx(BondArgs A, DevParams P) {
         piece[b] = 0u;
         krow[b] = (t0 + kBondWaves * b) * 16 + r16;
       }
-#pragma unroll 2
       for (int js = 0; js < nks; ++js) {
         const int j = 4 * js + q4;
         const bool ok = j < nf && r16 < 9;
@@ -3139,9 +3141,9 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   // plain kinematics keep their small register footprint
   const bool standard = p->force_mode == ULPPM_FORCE_STANDARD;
   if (mixed && standard)
-    k_point_kin<float, true><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
+    k_point_kin_standard<float><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
   else if (standard)
-    k_point_kin<double, true><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
+    k_point_kin_standard<double><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
   else {
     const int64_t per = ((n + 255) / 256 + 7) / 8;
     k_point_kin_lane<<<(unsigned)(8 * per), 256, 0, ctx->stream>>>(A, P, per);
