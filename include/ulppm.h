@@ -107,7 +107,8 @@ typedef struct {
  * and forces have no y component, while the stress keeps all six components
  * (sigma_yy from the zero out-of-plane strain).  ulppm_dt_crit uses the plane
  * bond micromodulus C = 72K/(5 pi delta^3) per unit thickness, and contact
- * sites weigh spacing^2.  The adjoint entry points require plane = 0. */
+ * sites weigh spacing^2.  The adjoint entry points differentiate the same
+ * block inversion (its derivative has no y row or column). */
 
 /* Point state: caller-owned device arrays of length n (SoA). */
 typedef struct {

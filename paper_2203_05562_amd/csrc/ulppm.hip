@@ -941,25 +941,36 @@ __host__ __device__ __forceinline__ double sym_inverse(const double* K, double* 
   return det;
 }
 
-// Inverse of a shape tensor (Voigt xx, yy, zz, yz, xz, xy) summed over
-// `count` members, or false when it is degenerate: fewer members than
-// dimensions, or det K <= 1e-12 (tr K / d)^d.  In plane strain (x-z plane)
+// Whether a shape tensor (Voigt xx, yy, zz, yz, xz, xy) summed over `count`
+// members can be inverted: not when it is degenerate, with fewer members than
+// dimensions or det K <= 1e-12 (tr K / d)^d.  In plane strain (x-z plane)
 // only the x-z block is inverted and the y row and column of the inverse are
-// zero.
-__host__ __device__ __forceinline__ bool shape_inverse(bool plane, const double* K, int count, double* Ki) {
+// zero; shape_inverse tests and inverts.
+__host__ __device__ __forceinline__ bool shape_regular(bool plane, const double* K, int count) {
   if (!plane) {
     const double dK = det3s(K[0], K[1], K[2], K[3], K[4], K[5]);
     const double tk = (K[0] + K[1] + K[2]) / 3.0;
-    if (count < 3 || !(dK > 1e-12 * tk * tk * tk)) return false;
+    return count >= 3 && dK > 1e-12 * tk * tk * tk;
+  }
+  const double d2 = K[0] * K[2] - K[4] * K[4];
+  const double tr = (K[0] + K[2]) / 2.0;
+  return count >= 2 && d2 > 1e-12 * tr * tr;
+}
+
+// The inverse itself, for a tensor shape_regular accepts.
+__host__ __device__ __forceinline__ void shape_inverse_of(bool plane, const double* K, double* Ki) {
+  if (!plane) {
     sym_inverse(K, Ki);
-    return true;
+    return;
   }
   const double a = K[0], c = K[2], e = K[4];
-  const double d2 = a * c - e * e;
-  const double tr = (a + c) / 2.0;
-  if (count < 2 || !(d2 > 1e-12 * tr * tr)) return false;
-  const double id = 1.0 / d2;
+  const double id = 1.0 / (a * c - e * e);
   Ki[0] = c * id; Ki[1] = 0.0; Ki[2] = a * id; Ki[3] = 0.0; Ki[4] = -e * id; Ki[5] = 0.0;
+}
+
+__host__ __device__ __forceinline__ bool shape_inverse(bool plane, const double* K, int count, double* Ki) {
+  if (!shape_regular(plane, K, count)) return false;
+  shape_inverse_of(plane, K, Ki);
   return true;
 }
 
@@ -983,8 +994,9 @@ __host__ __device__ __forceinline__ void unique_grad(const double* G, double* g)
 }
 
 // K^{-1} and the strain increment dt sym(N K^{-1}) of a bond (Eqs. 25-26, 59).
-__host__ __device__ __forceinline__ void tail_kinematics(const double* K, const double* N, double dt, TailFwd& F) {
-  sym_inverse(K, F.Ki);
+__host__ __device__ __forceinline__ void tail_kinematics(bool plane, const double* K, const double* N, double dt,
+                                                         TailFwd& F) {
+  shape_inverse_of(plane, K, F.Ki);
   double KiF[9], L[9];
   sym_full(F.Ki, KiF);
   mat3_mul(N, KiF, L);
@@ -995,7 +1007,7 @@ __host__ __device__ __forceinline__ void tail_kinematics(const double* K, const 
 // Pn: apparent pre-consolidation of pc (Eq. 45).
 __host__ __device__ void tail_forward_pn(const DevParams& P, const double* K, const double* N, const double* sig,
                                          double pc, double Pn, double Srs, double w, double dt, TailFwd& F) {
-  tail_kinematics(K, N, dt, F);
+  tail_kinematics(P.plane != 0, K, N, dt, F);
   double KiF[9];
   sym_full(F.Ki, KiF);
   if (dt == 0.0) {
@@ -2205,9 +2217,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     for (int k = 0; k < 6; ++k) Kq[k] = kn[k];
     for (int k = 0; k < 9; ++k) Nq[k] = kn[6 + k];
     const int ns = (int)kn[15];
-    const double dK = det3s(Kq[0], Kq[1], Kq[2], Kq[3], Kq[4], Kq[5]);
-    const double tk = (Kq[0] + Kq[1] + Kq[2]) / 3.0;
-    const bool active = ns >= 3 && dK > 1e-12 * tk * tk * tk;
+    const bool active = shape_regular(P.plane != 0, Kq, ns);
     kn[15] = active ? 1.0 : 0.0;
     MRec<double> r{};
     if (active) {
@@ -2323,7 +2333,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
       for (int k = 0; k < 9; ++k) Nq[k] = kn[6 + k];
       const double Vj = sZ[m].v[3];
       TailFwd F;                                   // the return map's solution from pass 1
-      tail_kinematics(Kq, Nq, dt, F);
+      tail_kinematics(P.plane != 0, Kq, Nq, dt, F);
       const double* rr = sR + 8 * (size_t)m;
       for (int k = 0; k < 6; ++k) F.sg[k] = rr[k];
       F.pc = rr[6];
@@ -2395,11 +2405,9 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     Vb_own += V1b * Jd;
     // Jd = 1/det(B), B = I - dt L_i, L_i = N_i K_i^{-1}
     double Ks_i[6] = {0, 0, 0, 0, 0, 0}, Nb_i[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const double dKi = det3s(pt[0], pt[1], pt[2], pt[3], pt[4], pt[5]);
-    const double tki = (pt[0] + pt[1] + pt[2]) / 3.0;
-    if (nf >= 3 && dKi > 1e-12 * tki * tki * tki && dt != 0.0) {
+    if (shape_regular(P.plane != 0, pt, nf) && dt != 0.0) {
       double Ki[6], KiF[9], Li[9], B[9], Bi[9];
-      sym_inverse(pt, Ki);
+      shape_inverse_of(P.plane != 0, pt, Ki);
       sym_full(Ki, KiF);
       mat3_mul(pt + 6, KiF, Li);
       for (int k = 0; k < 9; ++k) B[k] = (k % 4 == 0 ? 1.0 : 0.0) - dt * Li[k];
@@ -2548,7 +2556,8 @@ __global__ __launch_bounds__(256) void k_adj_point2(int64_t n, const int64_t* __
                                                     const double* __restrict__ sigb, const double* __restrict__ pcb,
                                                     const double* __restrict__ Jb, const double* __restrict__ phib,
                                                     const double* __restrict__ sb, ulppm_state In, ulppm_state Out,
-                                                    double dt, ContactDev C, const double* __restrict__ fbar,
+                                                    double dt, ContactDev C, bool plane,
+                                                    const double* __restrict__ fbar,
                                                     const double* __restrict__ xp, const double* __restrict__ vhp,
                                                     const double* __restrict__ voln) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -2571,7 +2580,7 @@ __global__ __launch_bounds__(256) void k_adj_point2(int64_t n, const int64_t* __
     double cx[3] = {0.0, 0.0, 0.0}, cV = 0.0;
     if (C.on) {                                             // contact forces on k (Eqs. 91-93)
       const double fb[3] = {fbar[k], fbar[n + k], fbar[2 * n + k]};
-      contact_adjoint(C, false, xp[k], xp[n + k], xp[2 * n + k], vhp[k], vhp[n + k], vhp[2 * n + k], voln[k], fb,
+      contact_adjoint(C, plane, xp[k], xp[n + k], xp[2 * n + k], vhp[k], vhp[n + k], vhp[2 * n + k], voln[k], fb,
                       lane, cx, &cV);
       for (int c = 0; c < 3; ++c) cx[c] = wave_sum(cx[c]);
       cV = wave_sum(cV);
@@ -3773,7 +3782,6 @@ int ulppm_adjoint_init(ulppm_ctx* ctx, const ulppm_state* S0, const ulppm_params
   if ((rc = check_params(ctx, p))) return rc;
   if (!s_bar || !theta_bar) return fail(ctx, ULPPM_E_ARG, "s_bar or theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
-  if (p->plane) return fail(ctx, ULPPM_E_ARG, "the adjoint is three-dimensional only");
   if (p->history) return fail(ctx, ULPPM_E_ARG, "the adjoint carries the history on the points only");
   if (!(ocr >= 1.0)) return fail(ctx, ULPPM_E_ARG, "ocr must be >= 1");
   const int64_t n = S0->n;
@@ -3838,7 +3846,6 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
   if ((rc = check_params(ctx, p))) return rc;
   if (!theta_bar) return fail(ctx, ULPPM_E_ARG, "theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
-  if (p->plane) return fail(ctx, ULPPM_E_ARG, "the adjoint is three-dimensional only");
   if (p->history) return fail(ctx, ULPPM_E_ARG, "the adjoint carries the history on the points only");
   if (p->precision != ULPPM_FP64 || p->force_mode != ULPPM_FORCE_CONJUGATE)
     return fail(ctx, ULPPM_E_ARG, "the adjoint supports FP64 with conjugate force states");
@@ -3912,7 +3919,7 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
   HIPCHK(hipGetLastError());
   k_adj_point2<<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->row, ctx->rev, S->fixed, own_x, own_vh, own_V,
                                                       A.slot_x, A.slot_vh, A.slot_V, ctx->bond_cap, sigb, pcb, Jb,
-                                                      phib, sb, *adj1, *adj0, p->dt, ctx->contact, fbar, ctx->x,
+                                                      phib, sb, *adj1, *adj0, p->dt, ctx->contact, p->plane != 0, fbar, ctx->x,
                                                       ctx->vh, ctx->vol_n);
   k_adj_theta<<<1, 256, 0, ctx->stream>>>(thpart, (int64_t)grid, theta_bar);
   HIPCHK(hipGetLastError());

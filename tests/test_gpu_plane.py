@@ -3,7 +3,8 @@ HIP library and the CPU oracle.
 
 Bars: families bit-exact; FP64 forces within 1e-11 of the largest force;
 FP64 trajectories within 1e-10 relative L2; mixed precision within 1e-4;
-nothing leaves the plane (y components exactly zero on the GPU).
+nothing leaves the plane (y components exactly zero on the GPU); the plane-strain
+adjoint matches the oracle's dual numbers within 1e-7.
 """
 import sys
 
@@ -134,12 +135,82 @@ def test_plane_mixed_precision(olib, gpu):
     assert all(v <= 1e-4 for v in errs.values()), errs
 
 
-def test_plane_adjoint_rejected(olib, gpu):
+@pytest.mark.parametrize("contact", [False, True])
+def test_plane_adjoint_matches_dual_numbers(olib, gpu, contact):
+    """Gradient of J = sum c . u^N through 8 plastic plane-strain steps: the
+    GPU adjoint (reverse of the x-z block inversion) dotted with directions in
+    (M, lam, kap, eta), the in-plane initial velocity, stress,
+    pre-consolidation and suction equals the oracle's directional derivatives
+    (dual numbers); with contact, a free base pressed into the substrate."""
     import torch
-    col, oprm, gprm, S, G, ctx = plane_pair(olib, gpu, dims=(8, 1, 8))
+    say("plane adjoint vs dual", "contact" if contact else "")
+    col = inputs.make_column(inputs.CONFIGS["P0"], seed=1, dims=(8, 1, 10), fixed_base=not contact)
+    over = {}
+    sub = None
+    if contact:
+        sub = inputs.make_substrate(col, extent=0.5, layers=2, mu_f=0.25)
+        sub["origin"][2] += 0.3 * sub["delta_c"]
+        over["contact"] = sub
+    oprm = olib.make_params(col["params"], **over)
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    n = col["n"]
+    fixed = col["fixed"] == 1
+    v = inputs.random_velocity(n, 51, 0.1)
+    v[:, 1] = 0.0
+    v[fixed] = 0.0
+    S["v"][:] = v
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    gprm = gpu.make_params(olib.params_dict(oprm))
+    ctx = gpu.Context(n, max_family=64)
+    if sub:
+        ctx.set_contact(sub)
     ctx.adjoint_reserve()
-    A1 = gpu.DeviceState.from_arrays(olib.empty_state(col["n"]))
-    A0 = gpu.DeviceState.from_arrays(olib.empty_state(col["n"]))
-    with pytest.raises(gpu.UlppmError) as ei:
-        ctx.adjoint_step(G, gprm, A1, A0, torch.zeros(4, dtype=torch.float64, device="cuda"))
-    assert ei.value.code == -1
+    nsteps = 8
+    G = gpu.DeviceState.from_arrays(S)
+    states = [G.clone()]
+    for _ in range(nsteps):
+        ctx.step(G, gprm, 1)
+        states.append(G.clone())
+    assert np.all(G.to_arrays()["u"][:, 1] == 0.0)
+    rng = np.random.default_rng(11)
+    c = rng.normal(size=(n, 3))
+    c[:, 1] = 0.0
+    lamN = {k: np.zeros_like(S[k]) for k in ("u", "uc", "v", "a", "vol", "phi", "J", "Sr", "mass", "s", "sig", "pc")}
+    lamN["u"] = c
+    lam = gpu.DeviceState.from_arrays({**lamN, "x0": np.zeros((n, 3))})
+    th = torch.zeros(4, dtype=torch.float64, device="cuda")
+    plastic = []
+    for k in range(nsteps - 1, -1, -1):
+        out = gpu.DeviceState(n)
+        plastic.append(ctx.adjoint_step(states[k], gprm, lam, out, th)["n_plastic"])
+        lam = out
+    lam0 = lam.to_arrays()
+    th = th.cpu().numpy()
+    say("theta_bar", th, "plastic/step", plastic)
+    assert sum(plastic) > 0
+    vin = rng.normal(size=(n, 3))
+    vin[:, 1] = 0.0
+    vin[fixed] = 0.0
+    dirs = {
+        "M": (np.array([1.0, 0, 0, 0]), {}),
+        "lam": (np.array([0, 1.0, 0, 0]), {}),
+        "kap": (np.array([0, 0, 1.0, 0]), {}),
+        "eta": (np.array([0, 0, 0, oprm.eta]), {}),
+        "v0": (np.zeros(4), {"v": vin}),
+        "sig0": (np.zeros(4), {"sig": rng.normal(size=(n, 6)) * 1e3}),
+        "pc0": (np.zeros(4), {"pc": rng.normal(size=n) * 1e3}),
+        "s": (np.zeros(4), {"s": np.full(n, 1e3)}),
+    }
+    for name, (dpar, dfields) in dirs.items():
+        dS = olib.empty_state(n)
+        for k, val in dfields.items():
+            dS[k][:] = val
+        S1 = olib.copy_state(S)
+        rc, _, st = olib.step_dual(S1, dS, oprm, dpar, nsteps)
+        assert rc == 0 and st["n_plastic"] > 0
+        dJ = float(np.sum(c * dS["u"]))
+        g = float(np.dot(th, dpar))
+        for k, val in dfields.items():
+            g += float(np.sum(lam0[k] * val))
+        say(name, dJ, g)
+        assert abs(g - dJ) <= 1e-7 * max(abs(dJ), 1e-300), (name, g, dJ)

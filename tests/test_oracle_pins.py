@@ -500,17 +500,26 @@ def test_initial_state_on_scaled_yield_surface(olib):
 
 # ------------------------------------------------------- dual numbers --
 
-def test_dual_tangent_matches_central_differences(olib):
+@pytest.mark.parametrize("plane", [False, True])
+def test_dual_tangent_matches_central_differences(olib, plane):
     """The forward-mode (dual number) oracle is the derivative of the oracle:
     central differences of 8 steps in M, eta and the initial velocity, taken
     only where both perturbed runs keep identical families, sub-horizons and
-    elastic/plastic branches (the step map is piecewise smooth)."""
-    col, prm, S = column_state(olib, (6, 6, 8), seed=1)
+    elastic/plastic branches (the step map is piecewise smooth); in 3D and in
+    plane strain, where only the x-z block of each shape tensor is inverted."""
+    if plane:
+        col, prm, S = plane_state(olib, dims=(8, 1, 10), seed=1)
+    else:
+        col, prm, S = column_state(olib, (6, 6, 8), seed=1)
     prm.dt = 0.5 * olib.dt_crit(S, prm)
     rng = np.random.default_rng(2)
-    S["v"][:] = rng.uniform(-0.02, 0.02, S["v"].shape)
-    S["v"][S["fixed"] == 1] = 0.0
+    vs = 0.05 if plane else 0.02         # both plastic over the 8 steps
+    S["v"][:] = rng.uniform(-vs, vs, S["v"].shape)
     dv = rng.normal(size=S["v"].shape)
+    if plane:
+        S["v"][:, 1] = 0.0
+        dv[:, 1] = 0.0
+    S["v"][S["fixed"] == 1] = 0.0
     dv[S["fixed"] == 1] = 0.0
     # (name, dparam tangent, velocity tangent, relative step)
     cases = [("M", np.array([1.0, 0, 0, 0]), None, 1e-4),
@@ -523,7 +532,7 @@ def test_dual_tangent_matches_central_differences(olib):
             dS["v"][:] = dvel
         S1 = olib.copy_state(S)
         rc, _, st0 = olib.step_dual(S1, dS, prm, dpar, nst)
-        assert rc == 0
+        assert rc == 0 and st0["n_plastic"] > 0
         res, sts = [], []
         for sgn in (+1, -1):
             S2 = olib.copy_state(S)
