@@ -101,13 +101,14 @@ def cpu_baseline(cfg_name, steps, dt):
                 seconds=round(el, 3))
 
 
-def run_column(ulppm, col, precision, warmup, steps, timed=True, contact=None, max_family=0, history=0):
+def run_column(ulppm, col, precision, warmup, steps, timed=True, contact=None, max_family=0, history=0,
+               force_mode=0):
     """Initial conditions, dt = dt_c / 2, `warmup` untimed steps, then
     `steps` steps timed with HIP events on the library's stream.  `contact`
     attaches a substrate (Eqs. 91-93) first."""
     import torch
     G = ulppm.column_state(col, "cuda:0")
-    prm = ulppm.make_params(col["params"], precision=precision, history=history)
+    prm = ulppm.make_params(col["params"], precision=precision, history=history, force_mode=force_mode)
     ctx = ulppm.Context(col["n"], max_family=max_family)
     if history:
         ctx.history_reserve()
@@ -152,6 +153,8 @@ def main():
     ap.add_argument("--no-contact", action="store_true", help="skip the substrate-contact companion run")
     ap.add_argument("--no-plane", action="store_true", help="skip the plane-strain companion run")
     ap.add_argument("--no-history", action="store_true", help="skip the bond-history companion run")
+    ap.add_argument("--no-standard", action="store_true",
+                    help="skip the companion run of the standard (full-horizon) correspondence model")
     ap.add_argument("--max-family", type=int, default=128,
                     help="family capacity of the main run's context (0: the library default, 152); a run whose "
                          "families outgrow it is repeated with the default")
@@ -253,6 +256,17 @@ def main():
                                         for k in ("predict", "family", "kin", "bond", "gather")})
         log(f"[gpu] history: {out['history']}")
         del Gh
+        torch.cuda.empty_cache()
+    if not args.no_standard:
+        # the standard correspondence model (Eqs. 12-14): one full-horizon K_i^{-1} per point
+        Gs, reps, mss, _ = run_column(ulppm, col, prec, args.warmup, args.steps, max_family=max_family,
+                                      force_mode=ulppm.ULPPM_FORCE_STANDARD)
+        ls = max(reps["timed_steps"], 1)
+        out["standard"] = dict(value=reps["n_bond_updates"] / (mss * 1e-3), ms_per_step=mss / args.steps,
+                               phase_ms={k: round(reps[f"t_{k}_ms"] / ls, 4)
+                                         for k in ("predict", "family", "kin", "bond", "gather")})
+        log(f"[gpu] standard: {out['standard']}")
+        del Gs
         torch.cuda.empty_cache()
     if args.adjoint_config:
         from paper_2203_05562_amd.measure import adjoint_cost
