@@ -351,6 +351,33 @@ def test_C2_full_size_one_step_subsample(olib, gpu):
         compare_states(sub(G.to_arrays()), sub(S), tol, label=f"C2 precision {prec}")
 
 
+def test_C1_bench_configuration(olib, gpu):
+    """The timed workload in its timed launch configuration: the 40 x 40 x 80
+    column (128,000 points) in a context of family capacity 128, so that the
+    bond kernel runs its three-wave FP64 instance (six workgroups per CU), for
+    three steps from the initial state; every point against the oracle, FP64
+    at 1e-11 and mixed precision at 1e-4."""
+    import time
+    say("C1 bench configuration, capacity 128, 3 steps")
+    cfg = inputs.CONFIGS["C1"]
+    col = inputs.make_column(cfg)
+    oprm = olib.make_params(col["params"])
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    S0 = olib.copy_state(S)
+    t0 = time.time()
+    rc, _, st = olib.step(S, oprm, 3)
+    assert rc == 0
+    say(f"oracle 3 steps {time.time() - t0:.1f}s, bonds {st['n_bonds']}, plastic {st['n_plastic']}")
+    ctx = gpu.Context(col["n"], max_family=128)
+    for prec, tol in ((gpu.ULPPM_FP64, 1e-11), (gpu.ULPPM_MIXED, 1e-4)):
+        gprm = gpu.make_params(olib.params_dict(oprm), precision=prec)
+        G = gpu.DeviceState.from_arrays(S0)
+        rep = ctx.step(G, gprm, 3)
+        assert rep["n_bond_updates"] == st["n_bonds"] and rep["max_family"] <= 128
+        compare_states(G.to_arrays(), S, tol, label=f"C1 precision {prec}")
+
+
 def test_standard_force_mode_parity(olib, gpu):
     """The standard, unstabilised correspondence model (Eq. 14, force mode
     2): force states against the oracle and a 50-step trajectory, FP64 at the
