@@ -4,23 +4,34 @@
 // One explicit central-difference step (Algorithm 2 driving Algorithm 1):
 //   k_predict   velocity predictor, boundary conditions, Kahan-compensated
 //               displacement, positions (Eqs. 60-61, 64)
-//   family build cell list -> one wave per point tests the 27 neighbour cells
-//               with the exact FP64 distance predicate, sorts its row, then a
-//               scan turns rows into CSR and a binary search builds rev[]
+//   families    Verlet candidates within delta plus a skin, rebuilt from a
+//               cell list only when a point has moved half the skin
+//               (k_check_skin, k_family, k_cand_rev); every step k_filter
+//               applies the exact FP64 distance predicate to the candidates,
+//               a scan turns the counts into CSR rows and k_compact writes
+//               the columns and rev[] through the reverse candidate index
 //               (Eq. 1; Algorithm 1, neighbour search)
-//   k_bond      one workgroup per point i: the family of i is staged in LDS;
-//               the full-horizon sums give the volume change, porosity,
-//               saturation and mass of i (Eqs. 5, 8, 15-17, 48); then one lane
-//               per bond (i,j) streams every k in H_i from LDS (broadcast
-//               reads), tests k in S_ij exactly and accumulates the
-//               sub-horizon shape tensor, velocity-gradient numerator and
-//               volume (Eqs. 22-23, 25, 55, 57); inverts K_ij in FP64, forms
-//               the strain increment, runs the Perzyna return map
-//               (Section 3.2.1) and writes the force state T_ij (Eqs. 32, 51,
-//               53); wave reductions give the point history average.
+//   k_point_kin_lane  one lane per point: full-horizon sums, volume change,
+//               porosity, saturation and mass (Eqs. 5, 8, 15-17, 48)
+//   k_bond_mx   one workgroup per point i, its family staged in LDS: pass 1
+//               forms the sub-horizon sums (shape tensor, velocity-gradient
+//               numerator, volume; Eqs. 22-23, 25, 55, 57) as the 0/1
+//               membership matrix times a feature matrix on the matrix cores,
+//               membership decided by the exact FP64 predicate; the tail (one
+//               lane per bond) inverts K_ij in FP64, forms the strain
+//               increment, runs the Perzyna return map (Section 3.2.1) and
+//               the bond's factor M_j; pass 2 sums the M_j of the sub-horizons
+//               holding each member into the force states T_ij (Eqs. 27, 31-32,
+//               35; Eqs. 51, 53 as an option); the point history is the
+//               volume-weighted mean of the bond states.
 //   k_gather    one wave per point: f_i = sum_j (T_ij - T_ji) V_i V_j through
-//               rev[] (no atomics), acceleration, velocity corrector, energy
-//               partials (Eqs. 49-50, 62-63, 66-68)
+//               rev[] (no atomics), contact with a rigid substrate (Eqs.
+//               91-93), acceleration, velocity corrector, energy partials
+//               (Eqs. 49-50, 62-63, 66-68)
+// The standard correspondence model (Eqs. 12-14) replaces the bond kernel by
+// k_point_kin_standard; the history carried on the bonds adds k_hist_carry
+// and k_hist_keep around it; the k_adj_* kernels run the reverse mode of a
+// step.
 //
 // Every kernel is stream-ordered on the context's stream.  No kernel traps;
 // failures raise device counters.  Memory: all scratch is allocated at
@@ -43,9 +54,10 @@ namespace {
 #ifndef ULPPM_BOND_THREADS
 #define ULPPM_BOND_THREADS 128
 #endif
-// Waves per SIMD the bond kernel is compiled for: FP64 issue saturates at two
-// (the FP64 matrix products and vector ops share one pipe), while the mixed
-// instance, whose FP32 products are cheaper, gains from a third wave.
+// Waves per SIMD the bond kernel is compiled for: two by default (no spills);
+// the mixed instance, and the FP64 one when the family capacity leaves LDS
+// for five or more workgroups per CU, are compiled for three, which gains
+// more from the extra wave than it loses to spilled registers.
 #ifndef ULPPM_BOND_MX_MIN_WAVES
 #define ULPPM_BOND_MX_MIN_WAVES 2
 #endif
