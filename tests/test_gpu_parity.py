@@ -378,6 +378,48 @@ def test_C1_bench_configuration(olib, gpu):
         compare_states(G.to_arrays(), S, tol, label=f"C1 precision {prec}")
 
 
+def test_C4_full_size_balance(gpu):
+    """128 x 128 x 256 = 4,194,304 points (about 4.6e8 bonds) from the GPU's
+    initial state, FP64, where no oracle run fits: properties that hold at any
+    size.  The internal forces f_i = sum_j (T_ij - T_ji) V_i V_j (Eqs. 49-50)
+    sum to zero (pairwise antisymmetric terms) and have no net moment about
+    the origin (each point's conjugate force states give sum_k V_k zeta_ik x
+    T_ik = 0 because the bond stresses are symmetric and K_j^{-1} multiplies
+    the K_j its members sum to), at zero strain increment and through the
+    return map; then one FP64 and one mixed step agree to 1e-4."""
+    import torch
+    say("C4 full size, balance and one step")
+    cfg = inputs.CONFIGS["C4"]
+    col = inputs.make_column(cfg)
+    n = col["n"]
+    G = gpu.column_state(col, "cuda:0")
+    prm = gpu.make_params(col["params"])
+    ctx = gpu.Context(n)
+    ctx.init_state(G, prm, col["params"]["ocr"])
+    prm.dt = 0.5 * ctx.dt_crit(G, prm)
+    G["v"].copy_(torch.from_numpy(inputs.random_velocity(n, 40, 0.05).T.copy()))
+    G["v"][:, G["fixed"] == 1] = 0.0
+    x = G["x0"] + G["u"]
+    for dt_inc in (0.0, prm.dt):
+        f, _, rep = ctx.forces(G, prm, dt_inc)
+        net = f.sum(dim=1)
+        mom = torch.linalg.cross(x.T, f.T).sum(dim=0)
+        fs = f.abs().sum()
+        ms = (torch.linalg.vector_norm(x, dim=0) * torch.linalg.vector_norm(f, dim=0)).sum()
+        say("dt_inc", dt_inc, "bonds", rep["n_bonds"], "plastic", rep["n_plastic"], "net", net.tolist(),
+            "sum|f|", float(fs), "moment", mom.tolist(), "sum|x||f|", float(ms))
+        assert rep["n_bonds"] > 4.0e8
+        assert float(net.abs().max()) <= 1e-10 * float(fs)
+        assert float(mom.abs().max()) <= 1e-10 * float(ms)
+    Gm = G.clone()
+    ctx.step(G, prm, 1)
+    ctx.step(Gm, gpu.make_params(col["params"], precision=gpu.ULPPM_MIXED, dt=prm.dt), 1)
+    for k in ("u", "v", "sig"):
+        e = float(torch.linalg.vector_norm(Gm[k] - G[k]) / torch.linalg.vector_norm(G[k]))
+        say("C4 mixed vs fp64", k, e)
+        assert e <= 1e-4, (k, e)
+
+
 def test_standard_force_mode_parity(olib, gpu):
     """The standard, unstabilised correspondence model (Eq. 14, force mode
     2): force states against the oracle and a 50-step trajectory, FP64 at the
