@@ -221,13 +221,22 @@ def main():
         del Gm
     del G
     torch.cuda.empty_cache()
+    def run_cap(c, **kw):
+        # the main run's family capacity, or the default where a family outgrows it
+        try:
+            return run_column(ulppm, c, prec, args.warmup, args.steps, max_family=max_family, **kw) + (max_family,)
+        except ulppm.UlppmError as e:
+            if e.code != -2 or max_family == 0:
+                raise
+            return run_column(ulppm, c, prec, args.warmup, args.steps, **kw) + (0,)
+
     if not args.no_contact:
         colc = inputs.make_column(cfg, fixed_base=False)
         sub = inputs.make_substrate(colc)
-        Gc, repc, msc, _ = run_column(ulppm, colc, prec, args.warmup, args.steps, contact=sub)
+        Gc, repc, msc, _, capc = run_cap(colc, contact=sub)
         vc = repc["n_bond_updates"] / (msc * 1e-3)
         lc = max(repc["timed_steps"], 1)
-        out["contact"] = dict(value=vc, ms_per_step=msc / args.steps,
+        out["contact"] = dict(value=vc, ms_per_step=msc / args.steps, max_family=capc or 152,
                               sites=int(sub["n"][0] * sub["n"][1] * sub["n"][2]), mu_f=sub["mu_f"],
                               delta_c=sub["delta_c"], cs=sub["cs"],
                               gather_ms=round(repc["t_gather_ms"] / lc, 4),
@@ -249,9 +258,10 @@ def main():
         del Gp
         torch.cuda.empty_cache()
     if not args.no_history:
-        Gh, reph, msh, _ = run_column(ulppm, col, prec, args.warmup, args.steps, history=ulppm.ULPPM_HISTORY_BOND)
+        Gh, reph, msh, _, caph = run_cap(col, history=ulppm.ULPPM_HISTORY_BOND)
         lh = max(reph["timed_steps"], 1)
         out["history"] = dict(value=reph["n_bond_updates"] / (msh * 1e-3), ms_per_step=msh / args.steps,
+                              max_family=caph or 152,
                               phase_ms={k: round(reph[f"t_{k}_ms"] / lh, 4)
                                         for k in ("predict", "family", "kin", "bond", "gather")})
         log(f"[gpu] history: {out['history']}")

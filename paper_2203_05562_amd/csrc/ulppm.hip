@@ -3182,6 +3182,8 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
     k_bond_mx<float, false, kWave><<<grid, kWave, lds, ctx->stream>>>(A, P);
   else if (mixed)
     k_bond_mx<float, false, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  else if (hist && kCuLds / (lds + kBondStaticLds) >= 5)
+    k_bond_mx<double, true, kBondThreads, 3><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   else if (hist)
     k_bond_mx<double, true, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   else if (one_wave && kCuLds / (lds + kBondStaticLds) >= 10)

@@ -34,7 +34,7 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def history_pair(olib, gpu, dims=(8, 8, 16), seed=0, precision=None, vscale=0.0):
+def history_pair(olib, gpu, dims=(8, 8, 16), seed=0, precision=None, vscale=0.0, max_family=0):
     col = inputs.make_column(inputs.CONFIGS["C0"], seed=seed, dims=dims)
     oprm = olib.make_params(col["params"])
     S = olib.init_column(col, oprm, col["params"]["ocr"])
@@ -47,19 +47,20 @@ def history_pair(olib, gpu, dims=(8, 8, 16), seed=0, precision=None, vscale=0.0)
     if precision is not None:
         over["precision"] = precision
     gprm = gpu.make_params(olib.params_dict(oprm), **over)
-    ctx = gpu.Context(col["n"])
+    ctx = gpu.Context(col["n"], max_family=max_family)
     ctx.history_reserve()
     G = gpu.DeviceState.from_arrays(S)
     H = olib.BondHistory(col["n"], 200 * col["n"])
     return col, oprm, gprm, S, G, ctx, H
 
 
-@pytest.mark.parametrize("nsteps,calls", [(1, 1), (200, 1), (200, 4)])
-def test_bond_history_trajectory(olib, gpu, nsteps, calls):
+@pytest.mark.parametrize("nsteps,calls,max_family", [(1, 1, 0), (200, 1, 0), (200, 4, 0), (200, 1, 128)])
+def test_bond_history_trajectory(olib, gpu, nsteps, calls, max_family):
     """200 steps of the 8 x 8 x 16 column with the history on the bonds, in
-    one call or spread over several (the states persist in the context)."""
-    say("bond history", nsteps, calls)
-    col, oprm, gprm, S, G, ctx, H = history_pair(olib, gpu, seed=0, vscale=0.05)
+    one call or spread over several (the states persist in the context); a
+    family capacity of 128 runs the bond kernel's three-wave instance."""
+    say("bond history", nsteps, calls, max_family)
+    col, oprm, gprm, S, G, ctx, H = history_pair(olib, gpu, seed=0, vscale=0.05, max_family=max_family)
     E = np.zeros(3)
     rc, E, st = olib.step_bond_history(S, oprm, H, nsteps, E)
     assert rc == 0
