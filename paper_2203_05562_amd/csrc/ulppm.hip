@@ -1424,32 +1424,40 @@ __global__ __launch_bounds__(256) void k_point_kin_standard(BondArgs A, DevParam
 __global__ __launch_bounds__(256) void k_hist_carry(int64_t n, const int64_t* __restrict__ row,
                                                     const int32_t* __restrict__ col,
                                                     const int64_t* __restrict__ hrow,
-                                                    const int32_t* __restrict__ hcol, int have,
+                                                    const int32_t* __restrict__ hcol, int have, int max_f,
                                                     const double* __restrict__ hold, double* __restrict__ hcur,
                                                     ulppm_state S) {
+  // one wave per point: the point's previous row is staged in LDS (at most
+  // max_f sorted columns) and every new bond binary-searches it there
+  extern __shared__ int32_t s_hcol[];
+  int32_t* rowc = s_hcol + (threadIdx.x / kWave) * (size_t)max_f;
   const int lane = threadIdx.x & (kWave - 1);
   const XcdWalk W = xcd_walk(n, 4);
   const double4* ho = reinterpret_cast<const double4*>(hold);
   double4* hc = reinterpret_cast<double4*>(hcur);
   for (int64_t i = W.first; i < W.end; i += W.stride) {
     const int64_t b0 = row[i], b1 = row[i + 1];
-    const int64_t h0 = have ? hrow[i] : 0, h1 = have ? hrow[i + 1] : 0;
+    const int64_t h0 = have ? hrow[i] : 0;
+    const int nh = have ? (int)min<int64_t>(hrow[i + 1] - h0, max_f) : 0;
+    for (int t = lane; t < nh; t += kWave) rowc[t] = hcol[h0 + t];
+    __builtin_amdgcn_wave_barrier();               // this wave's row is in place (LDS is in order per wave)
     for (int64_t s = b0 + lane; s < b1; s += kWave) {
       const int32_t j = col[s];
-      int64_t lo = h0, hi = h1;
+      int lo = 0, hi = nh;
       while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (hcol[mid] < j) lo = mid + 1;
+        const int mid = (lo + hi) >> 1;
+        if (rowc[mid] < j) lo = mid + 1;
         else hi = mid;
       }
-      if (lo < h1 && hcol[lo] == j) {
-        hc[2 * s] = ho[2 * lo];
-        hc[2 * s + 1] = ho[2 * lo + 1];
+      if (lo < nh && rowc[lo] == j) {
+        hc[2 * s] = ho[2 * (h0 + lo)];
+        hc[2 * s + 1] = ho[2 * (h0 + lo) + 1];
       } else {
         hc[2 * s] = double4{S.sig[0][i], S.sig[1][i], S.sig[2][i], S.sig[3][i]};
         hc[2 * s + 1] = double4{S.sig[4][i], S.sig[5][i], S.pc[i], 0.0};
       }
     }
+    __builtin_amdgcn_wave_barrier();               // every lane is done with the row before the next
   }
 }
 
@@ -3972,8 +3980,8 @@ int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_
     if (bond_history) {
       const int have = ctx->hist_n == n ? 1 : 0;
       hist = ctx->hist[ctx->hist_last ^ 1];
-      k_hist_carry<<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->row, ctx->col, ctx->hist_row, ctx->hist_col, have,
-                                                          ctx->hist[ctx->hist_last], hist, *S);
+      k_hist_carry<<<walk_grid(n), 256, 4 * sizeof(int32_t) * (size_t)ctx->max_f, ctx->stream>>>(
+          n, ctx->row, ctx->col, ctx->hist_row, ctx->hist_col, have, ctx->max_f, ctx->hist[ctx->hist_last], hist, *S);
       HIPCHK(hipGetLastError());
     }
     if ((rc = bond_pass(ctx, S, p, p->dt, true, [&](int b) {
