@@ -202,7 +202,11 @@ def test_frame_indifference_lattice_rotation(olib):
 
 def test_internal_forces_sum_to_zero(olib):
     """Eqs. 49-50: the assembled internal force is a pair sum antisymmetric in
-    (i, j), so its total vanishes for any state."""
+    (i, j), so its total vanishes for any state.  Its moment vanishes too:
+    every point's conjugate force states give sum_k V_k zeta_ik x T_ik =
+    sum_j w_j eps : (Q_j K_j^{-1} K_j) with a symmetric bond stress Q_j, so a
+    transposed K^{-1}, a member missing from K_j or a non-symmetric stress
+    update shows up as a net moment."""
     col, prm, S = column_state(olib, (8, 8, 12), seed=2)
     rng = np.random.default_rng(5)
     S["v"][:] = rng.uniform(-0.1, 0.1, S["v"].shape)
@@ -210,6 +214,9 @@ def test_internal_forces_sum_to_zero(olib):
     out = olib.bond_fields(S, prm, 2e-5)
     f = out["f"]
     assert np.abs(f.sum(axis=0)).max() <= 1e-13 * np.abs(f).sum()
+    x = S["x0"] + S["u"]
+    mom = np.cross(x, f).sum(axis=0)
+    assert np.abs(mom).max() <= 1e-13 * (np.linalg.norm(x, axis=1) * np.linalg.norm(f, axis=1)).sum()
 
 
 def test_interior_patch_uniform_stress(olib):
