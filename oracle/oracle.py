@@ -16,7 +16,7 @@ import numpy as np
 from .build import LIB, build
 
 __all__ = ["OracleParams", "lib", "make_params", "init_column", "families", "bond_fields",
-           "step", "step_dual", "step_bond_history", "BondHistory", "dt_crit", "return_map", "rm_residual", "swrc", "copy_state",
+           "step", "step_dual", "step_bond_history", "step_dual_bond_history", "BondHistory", "dt_crit", "return_map", "rm_residual", "swrc", "copy_state",
            "empty_state", "params_dict", "STATE_FIELDS"]
 
 _dp = C.POINTER(C.c_double)
@@ -84,6 +84,10 @@ def lib():
         L.oracle_step_dual.restype = C.c_int
         L.oracle_step_dual.argtypes = [C.POINTER(OracleParams), _dp, C.POINTER(OracleState),
                                        C.POINTER(OracleState), C.c_int32, _dp, C.POINTER(OracleStats)]
+        L.oracle_step_dual_bond_history.restype = C.c_int
+        L.oracle_step_dual_bond_history.argtypes = [C.POINTER(OracleParams), _dp, C.POINTER(OracleState),
+                                                    C.POINTER(OracleState), C.POINTER(OracleBondHistory), _dp,
+                                                    C.c_int32, _dp, C.POINTER(OracleStats)]
         L.oracle_init_state.restype = C.c_int
         L.oracle_init_state.argtypes = [C.POINTER(OracleParams), C.POINTER(OracleState), C.c_double]
         L.oracle_dt_crit.restype = C.c_double
@@ -226,6 +230,7 @@ class BondHistory:
         self.row = np.zeros(n + 1, np.int64)
         self.col = np.zeros(max(cap, 1), np.int32)
         self.st = np.zeros((max(cap, 1), 8))
+        self.dst = np.zeros((max(cap, 1), 8))      # tangents of st (dual-number runs)
         self.c = OracleBondHistory(0, cap, 0, _p(self.row, _i64p), _p(self.col, _i32p), _p(self.st))
 
     @property
@@ -252,6 +257,19 @@ def step_dual(S: dict, dS: dict, prm: OracleParams, dparam, n_steps: int = 1, en
     st = OracleStats()
     rc = lib().oracle_step_dual(C.byref(prm), _p(dp), C.byref(cs), C.byref(cd), int(n_steps), _p(e),
                                 C.byref(st))
+    return rc, e, st.as_dict()
+
+
+def step_dual_bond_history(S: dict, dS: dict, prm: OracleParams, dparam, H: BondHistory, n_steps: int = 1,
+                           energy=None):
+    """step_dual with the history on the bonds: H.st and its tangents H.dst
+    are carried between calls like S and dS."""
+    e = np.zeros(3) if energy is None else energy
+    dp = np.ascontiguousarray(np.asarray(dparam, np.float64))
+    cs, cd = _cstate(S), _cstate(dS)
+    st = OracleStats()
+    rc = lib().oracle_step_dual_bond_history(C.byref(prm), _p(dp), C.byref(cs), C.byref(cd), C.byref(H.c),
+                                             _p(H.dst), int(n_steps), _p(e), C.byref(st))
     return rc, e, st.as_dict()
 
 

@@ -623,7 +623,7 @@ void contact_forces(const Params& P, int64_t n, const R* x, const R* v, const st
 template <class R>
 void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval, const R* x,
                 const R* vh, const PointState<R>& S, const Families& F, R dt_inc, BondOut<R>& O,
-                Stats& st, const std::vector<double>* bond_in = nullptr) {
+                Stats& st, const std::vector<R>* bond_in = nullptr) {
   const double d2 = P.delta * P.delta;
   const int64_t nb = F.row[n];
   O.K.assign(6 * nb, R(0.0));
@@ -775,8 +775,8 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
       // state the bond starts from: the point history, or the bond's own
       // history when it is carried on the bonds
       R sig_b[6], pc_b;
-      for (int k = 0; k < 6; ++k) sig_b[k] = bond_in ? R((*bond_in)[8 * s + k]) : sig_i[k];
-      pc_b = bond_in ? R((*bond_in)[8 * s + 6]) : S.pc[i];
+      for (int k = 0; k < 6; ++k) sig_b[k] = bond_in ? (*bond_in)[8 * s + k] : sig_i[k];
+      pc_b = bond_in ? (*bond_in)[8 * s + 6] : S.pc[i];
       if (val(dt_inc) == 0.0) {
         for (int k = 0; k < 6; ++k) sb[k] = sig_b[k];
         pcb = pc_b;
@@ -881,18 +881,20 @@ std::vector<double> values(const std::vector<R>& a) {
 // keeps its own (sigma_ij, p_c,ij) from one step to the next while it stays in
 // the family; a bond that enters a family starts from its point's history
 // (the volume-weighted mean of the point's bond states, as before).
+template <class R>
 struct BondHistory {
   std::vector<int64_t> row;   // families the states belong to (empty: none yet)
   std::vector<int32_t> col;
-  std::vector<double> st;     // 8 per bond: sigma (6), p_c, unused
+  std::vector<R> st;          // 8 per bond: sigma (6), p_c, unused
 };
 
 // Bond states in the order of the new families F: a bond found in the
 // previous families of its point keeps its state; a new bond takes the point's.
-inline void carry_bond_history(const BondHistory& H, const Families& F, const std::vector<double>& sig,
-                               const std::vector<double>& pc, std::vector<double>& in) {
+template <class R>
+void carry_bond_history(const BondHistory<R>& H, const Families& F, const std::vector<R>& sig,
+                        const std::vector<R>& pc, std::vector<R>& in) {
   const int64_t n = (int64_t)F.row.size() - 1;
-  in.assign(8 * F.row[n], 0.0);
+  in.assign(8 * F.row[n], R(0.0));
   const bool have = (int64_t)H.row.size() == n + 1;
   for (int64_t i = 0; i < n; ++i)
     for (int64_t s = F.row[i]; s < F.row[i + 1]; ++s) {
@@ -908,14 +910,14 @@ inline void carry_bond_history(const BondHistory& H, const Families& F, const st
 // Updated bond states after Algorithm 1; a degenerate (inactive) bond keeps
 // the state it started from.
 template <class R>
-void store_bond_history(BondHistory& H, const Families& F, const BondOut<R>& O, const std::vector<double>& in) {
+void store_bond_history(BondHistory<R>& H, const Families& F, const BondOut<R>& O, const std::vector<R>& in) {
   const int64_t nb = F.row.back();
   H.row = F.row;
   H.col = F.col;
-  H.st.assign(8 * nb, 0.0);
+  H.st.assign(8 * nb, R(0.0));
   for (int64_t s = 0; s < nb; ++s) {
-    for (int k = 0; k < 6; ++k) H.st[8 * s + k] = O.active[s] ? val(O.sig[6 * s + k]) : in[8 * s + k];
-    H.st[8 * s + 6] = O.active[s] ? val(O.pc[s]) : in[8 * s + 6];
+    for (int k = 0; k < 6; ++k) H.st[8 * s + k] = O.active[s] ? O.sig[6 * s + k] : in[8 * s + k];
+    H.st[8 * s + 6] = O.active[s] ? O.pc[s] : in[8 * s + 6];
   }
 }
 
@@ -923,7 +925,7 @@ void store_bond_history(BondHistory& H, const Families& F, const BondOut<R>& O, 
 // beta2 = 0; Eqs. 60-64), with energies of Eqs. 66-68 accumulated in E.
 template <class R>
 int newmark_step(const Params& P, const Mat<R>& m, PointState<R>& S, R* E, Stats& st,
-                 Families* Fout = nullptr, BondHistory* H = nullptr) {
+                 Families* Fout = nullptr, BondHistory<R>* H = nullptr) {
   const int64_t n = S.n;
   const R dt = P.dt;
   const R hdt = 0.5 * P.dt;
@@ -953,8 +955,8 @@ int newmark_step(const Params& P, const Mat<R>& m, PointState<R>& S, R* E, Stats
   build_families_cells(n, xv.data(), P.delta, F);
   build_reverse(n, F);
   BondOut<R> O;
-  std::vector<double> bond_in;
-  if (H) carry_bond_history(*H, F, values(S.sig), values(S.pc), bond_in);
+  std::vector<R> bond_in;
+  if (H) carry_bond_history(*H, F, S.sig, S.pc, bond_in);
   algorithm1(P, m, n, xv.data(), x.data(), vh.data(), S, F, dt, O, st, H ? &bond_in : nullptr);
   if (H) store_bond_history(*H, F, O, bond_in);
   // Acceleration (Eq. 62 with the sign of Eq. 33) and velocity corrector (Eq. 63).
@@ -1183,7 +1185,7 @@ int oracle_step_bond_history(const OracleParams* op, OracleState* os, OracleBond
   Mat<double> m = to_mat<double>(P);
   PointState<double> S;
   load_state(os, S);
-  BondHistory H;
+  BondHistory<double> H;
   if (bh->nb > 0 && bh->n == S.n) {
     H.row.assign(bh->row, bh->row + S.n + 1);
     H.col.assign(bh->col, bh->col + bh->nb);
@@ -1299,8 +1301,8 @@ double oracle_swrc(const OracleParams* op, double J, double phi, double s) {
 // Forward-mode directional derivative of n_steps steps.  dstate holds the
 // tangents of the state fields (x0 and fixed ignored); dparam[4] the tangents
 // of (M, lam, kap, eta); the suction tangent is taken from dstate->s.  On return the state and its tangent are advanced.
-int oracle_step_dual(const OracleParams* op, const double* dparam, OracleState* os, OracleState* ds,
-                     int32_t n_steps, double* energy, OracleStats* ost) {
+static int step_dual_run(const OracleParams* op, const double* dparam, OracleState* os, OracleState* ds,
+                         int32_t n_steps, double* energy, OracleStats* ost, BondHistory<Dual>* H) {
   Params P = to_params(op);
   Mat<Dual> m = to_mat<Dual>(P);
   m.M.d = dparam[0];
@@ -1331,7 +1333,7 @@ int oracle_step_dual(const OracleParams* op, const double* dparam, OracleState* 
   Stats st;
   Dual E[3] = {Dual(energy[0]), Dual(energy[1]), Dual(energy[2])};
   int rc = 0;
-  for (int k = 0; k < n_steps && rc == 0; ++k) rc = newmark_step(P, m, S, E, st);
+  for (int k = 0; k < n_steps && rc == 0; ++k) rc = newmark_step(P, m, S, E, st, nullptr, H);
   auto st_back = [&](const std::vector<Dual>& d, double* v, double* t) {
     for (size_t k = 0; k < d.size(); ++k) { v[k] = d[k].v; t[k] = d[k].d; }
   };
@@ -1348,6 +1350,37 @@ int oracle_step_dual(const OracleParams* op, const double* dparam, OracleState* 
   st_back(S.pc, os->pc, ds->pc);
   for (int c = 0; c < 3; ++c) energy[c] = E[c].v;
   store_stats(st, ost);
+  return rc;
+}
+
+
+int oracle_step_dual(const OracleParams* op, const double* dparam, OracleState* os, OracleState* ds,
+                     int32_t n_steps, double* energy, OracleStats* ost) {
+  return step_dual_run(op, dparam, os, ds, n_steps, energy, ost, nullptr);
+}
+
+// Forward-mode derivatives with the history on the bonds: dst holds the
+// tangents of bh->st (8 per bond), read and written like bh.
+int oracle_step_dual_bond_history(const OracleParams* op, const double* dparam, OracleState* os, OracleState* ds,
+                                  OracleBondHistory* bh, double* dst, int32_t n_steps, double* energy,
+                                  OracleStats* ost) {
+  BondHistory<Dual> H;
+  if (bh->nb > 0 && bh->n == os->n) {
+    H.row.assign(bh->row, bh->row + os->n + 1);
+    H.col.assign(bh->col, bh->col + bh->nb);
+    H.st.resize(8 * bh->nb);
+    for (int64_t k = 0; k < 8 * bh->nb; ++k) H.st[k] = Dual(bh->st[k], dst[k]);
+  }
+  const int rc = step_dual_run(op, dparam, os, ds, n_steps, energy, ost, &H);
+  const int64_t nb = H.row.empty() ? 0 : H.row.back();
+  if (nb > bh->cap) return -2;
+  bh->n = os->n;
+  bh->nb = nb;
+  if (nb > 0) {
+    std::copy(H.row.begin(), H.row.end(), bh->row);
+    std::copy(H.col.begin(), H.col.end(), bh->col);
+    for (int64_t k = 0; k < 8 * nb; ++k) { bh->st[k] = H.st[k].v; dst[k] = H.st[k].d; }
+  }
   return rc;
 }
 

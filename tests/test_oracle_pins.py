@@ -953,3 +953,56 @@ def test_bond_history_new_bond_starts_from_point(olib):
     else:
         exp = sig_pt[target]
     assert np.allclose(H.st[s, :6], exp, rtol=0, atol=1e-9 * 40e3)
+
+
+def test_bond_history_dual_matches_central_differences(olib):
+    """The dual-number oracle with the history on the bonds is the derivative
+    of the oracle with the history on the bonds: central differences of 8
+    plastic steps in eta, the initial velocity and the initial stress (the
+    stress reaches the bonds through the carry, every bond starting from its
+    point at the first step), for the point fields and for the carried bond
+    states, where both perturbed runs keep the same sets and branches."""
+    col, prm, S = column_state(olib, (6, 6, 8), seed=1)
+    prm.dt = 0.5 * olib.dt_crit(S, prm)
+    rng = np.random.default_rng(2)
+    S["v"][:] = rng.uniform(-0.05, 0.05, S["v"].shape)
+    S["v"][S["fixed"] == 1] = 0.0
+    n = col["n"]
+    dv = rng.normal(size=S["v"].shape)
+    dv[S["fixed"] == 1] = 0.0
+    dsig = rng.normal(size=S["sig"].shape) * 1e3
+    cases = [("eta", np.array([0, 0, 0, prm.eta]), {}, 1e-4),
+             ("v0", np.zeros(4), {"v": dv}, 1e-6),
+             ("sig0", np.zeros(4), {"sig": dsig}, 1e-5)]
+    for name, dpar, dfl, hs in cases:
+        dS = olib.empty_state(n)
+        for k, v in dfl.items():
+            dS[k][:] = v
+        S1 = olib.copy_state(S)
+        H = olib.BondHistory(n, 200 * n)
+        rc, _, st0 = olib.step_dual_bond_history(S1, dS, prm, dpar, H, 8)
+        assert rc == 0 and st0["n_plastic"] > 0
+        runs, sts = [], []
+        for sgn in (+1, -1):
+            S2 = olib.copy_state(S)
+            p2 = olib.make_params(olib.params_dict(prm))
+            H2 = olib.BondHistory(n, 200 * n)
+            if name == "eta":
+                p2.eta += sgn * hs * prm.eta
+            for k, v in dfl.items():
+                S2[k] += sgn * hs * v
+            rc, _, st = olib.step_bond_history(S2, p2, H2, 8)
+            assert rc == 0
+            runs.append((S2, H2))
+            sts.append(st)
+        for key in ("n_bonds", "n_triples", "n_plastic"):
+            assert sts[0][key] == sts[1][key] == st0[key], (name, key)
+        for fld, tol in (("u", 1e-7), ("v", 1e-7), ("sig", 1e-7), ("pc", 1e-5)):
+            fd = (runs[0][0][fld] - runs[1][0][fld]) / (2 * hs)
+            err = np.linalg.norm(fd - dS[fld]) / np.linalg.norm(dS[fld])
+            assert err < tol, (name, fld, err)
+        nb = H.nb
+        assert runs[0][1].nb == runs[1][1].nb == nb
+        fdh = (runs[0][1].st[:nb, :6] - runs[1][1].st[:nb, :6]) / (2 * hs)
+        err = np.linalg.norm(fdh - H.dst[:nb, :6]) / np.linalg.norm(H.dst[:nb, :6])
+        assert err < 1e-7, (name, "bond states", err)
