@@ -73,7 +73,8 @@ enum { ULPPM_FORCE_CONJUGATE = 0, ULPPM_FORCE_EQ51 = 1, ULPPM_FORCE_STANDARD = 2
  *   from its point's history, and the points still receive the mean (for
  *   output and for new bonds).  The states live in the context
  *   (ulppm_history_reserve), ulppm_init_state clears them, and only
- *   ulppm_step uses them (ulppm_forces starts every bond from its point). */
+ *   ulppm_step uses them (ulppm_forces starts every bond from its point);
+ *   its reverse is ulppm_adjoint_step_bond_history. */
 enum { ULPPM_HISTORY_POINT = 0, ULPPM_HISTORY_BOND = 1 };
 
 /* Material and integration parameters, copied by value on every call. */
@@ -299,6 +300,28 @@ int ulppm_adjoint_reserve(ulppm_ctx *ctx);
 int ulppm_adjoint_step(ulppm_ctx *ctx, const ulppm_state *state_n, const ulppm_state *state_np1,
                        const ulppm_params *p, const ulppm_state *adj_np1, ulppm_state *adj_n,
                        double *theta_bar, ulppm_report *rep);
+
+/* Reverse mode of one step n -> n+1 with the history on the bonds
+ * (p->history = ULPPM_HISTORY_BOND; an alternative reading of the paper's
+ * history, see ULPPM_HISTORY_BOND), otherwise as ulppm_adjoint_step.
+ * state_np1 is required.  row_n (n+1 int64), col_n (n_bonds_n int32) and
+ * hist_n (8 doubles per bond: sigma in Voigt order, p_c, 0) are the families
+ * and bond states after step n, as ulppm_history_export returned them after
+ * the step that produced state_n (device arrays; n_bonds_n = 0 and NULLs
+ * when step n is the first: every bond then starts from its point).
+ * hist_bar_np1 is the adjoint of the bond states after step n+1, in the
+ * order of the families of state_np1 (the order ulppm_history_export gives
+ * after step n+1).  Writes hist_bar_n, the adjoint of hist_n (same layout,
+ * zero for bonds not carried into step n+1); a bond that enters a family
+ * hands its start-state adjoint to its point's history (adj_n->sig, pc).
+ * Needs ulppm_history_reserve and ulppm_adjoint_reserve (the second of them
+ * reserves 16 doubles per bond slot for this call); allocates nothing itself.
+ * Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_NOCONV, ULPPM_E_HIP. */
+int ulppm_adjoint_step_bond_history(ulppm_ctx *ctx, const ulppm_state *state_n, const ulppm_state *state_np1,
+                                    const ulppm_params *p, int64_t n_bonds_n, const int64_t *row_n,
+                                    const int32_t *col_n, const double *hist_n, const double *hist_bar_np1,
+                                    const ulppm_state *adj_np1, ulppm_state *adj_n, double *hist_bar_n,
+                                    double *theta_bar, ulppm_report *rep);
 
 /* Reverse of ulppm_init_state (the initial conditions of Algorithm 2) at the
  * state state0 it produced with the same p and ocr.  adj0 is the adjoint of

@@ -1471,6 +1471,52 @@ __global__ void k_hist_keep(int64_t n, const int64_t* __restrict__ row, const in
     hcol[e] = col[e];
 }
 
+// Reverse of k_hist_carry: a carried bond hands the adjoint of its start
+// state back to the bond it came from (hbar0, in the previous families'
+// order, zero elsewhere); a new bond, which started from its point, adds it
+// to the adjoint of the point's history (sigb, pcb).  One wave per point.
+__global__ __launch_bounds__(256) void k_adj_hist_carry(int64_t n, const int64_t* __restrict__ row,
+                                                        const int32_t* __restrict__ col,
+                                                        const int64_t* __restrict__ hrow,
+                                                        const int32_t* __restrict__ hcol, int have, int max_f,
+                                                        const double* __restrict__ hb0s, double* __restrict__ hbar0,
+                                                        double* __restrict__ sigb, double* __restrict__ pcb) {
+  extern __shared__ int32_t s_hcol[];
+  int32_t* rowc = s_hcol + (threadIdx.x / kWave) * (size_t)max_f;
+  const int lane = threadIdx.x & (kWave - 1);
+  const XcdWalk W = xcd_walk(n, 4);
+  for (int64_t i = W.first; i < W.end; i += W.stride) {
+    const int64_t b0 = row[i], b1 = row[i + 1];
+    const int64_t h0 = have ? hrow[i] : 0;
+    const int nh = have ? (int)min<int64_t>(hrow[i + 1] - h0, max_f) : 0;
+    for (int t = lane; t < nh; t += kWave) rowc[t] = hcol[h0 + t];
+    __builtin_amdgcn_wave_barrier();
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t s = b0 + lane; s < b1; s += kWave) {
+      const int32_t j = col[s];
+      int lo = 0, hi = nh;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rowc[mid] < j) lo = mid + 1;
+        else hi = mid;
+      }
+      const double* src = hb0s + 8 * s;
+      if (lo < nh && rowc[lo] == j) {
+        double* dst = hbar0 + 8 * (h0 + lo);
+        for (int k = 0; k < 7; ++k) dst[k] = src[k];
+      } else {
+        for (int k = 0; k < 7; ++k) acc[k] += src[k];
+      }
+    }
+    for (int k = 0; k < 7; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+      for (int k = 0; k < 6; ++k) sigb[k * n + i] += acc[k];
+      pcb[i] += acc[6];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // ------------------------------------------------- bond kernel, MFMA sums --
 //
 // The masked sums of pass 1 (sub-horizon shape tensor, velocity-gradient
@@ -2012,6 +2058,12 @@ struct AdjArgs {
   double* slot_vh;        // 3 x cap
   double* slot_V;         // cap
   double* thpart;         // 4 per block
+  // history on the bonds: start states of this step's bonds (8 per slot),
+  // adjoints of their updated states (8 per slot), adjoints of the start
+  // states (8 per slot, written)
+  const double* hstart = nullptr;
+  const double* hbar1 = nullptr;
+  double* hbar0s = nullptr;
   int64_t cap;
   double dt;
   int max_f;
@@ -2078,6 +2130,10 @@ __global__ __launch_bounds__(256) void k_adj_point1(int64_t n, const uint8_t* __
 // The masked sums of the re-run pass 1 and of the reverse of the sums are
 // membership-matrix products on the matrix cores (16x16x4 FP64, the lane
 // layout of the forward bond kernel); the 9-column sums stay on the VALU.
+// Hist: the history on the bonds; each bond starts from its carried state
+// (A.hstart), its updated state also receives A.hbar1, and the adjoint of
+// its start state goes to A.hbar0s instead of the point's history.
+template <bool Hist>
 __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(AdjArgs A, DevParams P) {
   using MM = Mma<double>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -2243,7 +2299,12 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     if (active) {
       const double Vj = sZ[m].v[3];
       TailFwd F;
-      tail_forward_pn(P, Kq, Nq, sig_i, pc_i, Pn_i, Srs, Vj / Vh, dt, F);
+      if constexpr (Hist) {
+        const double* h0 = A.hstart + 8 * (b0 + m);
+        tail_forward_pn(P, Kq, Nq, h0, h0[6], apparent_pc(P, h0[6]), Srs, Vj / Vh, dt, F);
+      } else {
+        tail_forward_pn(P, Kq, Nq, sig_i, pc_i, Pn_i, Srs, Vj / Vh, dt, F);
+      }
       for (int q = 0; q < 9; ++q) r.v[q] = F.M[q];
       double* rr = sR + 8 * (size_t)m;
       for (int k = 0; k < 6; ++k) rr[k] = F.sg[k];
@@ -2366,13 +2427,35 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         vh_hist += sgb1[k] * (F.sg[k] - sig1[k]);
       }
       vh_hist += pcb1 * (F.pc - pc1);
-      const double pcx = pcb1 * Vj / W;
+      double pcx = pcb1 * Vj / W;
       double wb = 0.0;
-      tail_reverse(P, Kq, Nq, sig_i, pc_i, Srs, Vj / Vh, dt, F, mb, sgx, pcx, Kb, Nb, acc_sig, &acc_pc, &acc_Srs,
-                   &wb, acc_th);
+      if constexpr (Hist) {
+        // the bond's own updated state is also carried to the next step
+        const double* hb = A.hbar1 + 8 * (b0 + m);
+        for (int k = 0; k < 6; ++k) sgx[k] += hb[k];
+        pcx += hb[6];
+        const double* h0 = A.hstart + 8 * (b0 + m);
+        double s0b[6] = {0, 0, 0, 0, 0, 0}, p0b = 0.0;
+        tail_reverse(P, Kq, Nq, h0, h0[6], Srs, Vj / Vh, dt, F, mb, sgx, pcx, Kb, Nb, s0b, &p0b, &acc_Srs,
+                     &wb, acc_th);
+        double* ho = A.hbar0s + 8 * (b0 + m);
+        for (int k = 0; k < 6; ++k) ho[k] = s0b[k];
+        ho[6] = p0b;
+        ho[7] = 0.0;
+      } else {
+        tail_reverse(P, Kq, Nq, sig_i, pc_i, Srs, Vj / Vh, dt, F, mb, sgx, pcx, Kb, Nb, acc_sig, &acc_pc,
+                     &acc_Srs, &wb, acc_th);
+      }
       // w_j = V_j / Vh
       sZb[m].v[3] += wb / Vh + vh_hist / W;
       acc_Vh -= wb * Vj / (Vh * Vh);
+    }
+    if constexpr (Hist) {
+      if (!active) {                               // an inactive bond keeps its start state
+        const double* hb = A.hbar1 + 8 * (b0 + m);
+        double* ho = A.hbar0s + 8 * (b0 + m);
+        for (int k = 0; k < 8; ++k) ho[k] = hb[k];
+      }
     }
     double Ks[6];
     sym_full_grad<double>(Kb, Ks);
@@ -2964,6 +3047,7 @@ struct ulppm_ctx {
   // adjoint scratch (ulppm_adjoint_reserve)
   double* adj = nullptr;      // 24n forward copy + 21n point adjoints + 4(n+8) partials
   double* adj_slot = nullptr; // 7 x bond_cap
+  double* adj_hist = nullptr; // 16 x bond_cap: carried start states and their adjoints (history on the bonds)
   // phase timing events, [step][phase][start/stop]
   hipEvent_t ev[kTimedSteps][kPhases][2] = {};
   bool have_events = false;
@@ -3552,7 +3636,7 @@ int ulppm_destroy(ulppm_ctx* ctx) {
                   ctx->ccnt, ctx->crev, ctx->posmap, ctx->xref, ctx->gate,
                   ctx->ccount, ctx->ccursor, ctx->cstart, ctx->cpts, ctx->col, ctx->rev, ctx->T,
                   ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->ctr_sum, ctx->E, ctx->adj,
-                  ctx->adj_slot, ctx->hist[0], ctx->hist[1], ctx->hist_row, ctx->hist_col};
+                  ctx->adj_slot, ctx->adj_hist, ctx->hist[0], ctx->hist[1], ctx->hist_row, ctx->hist_col};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ctx->have_events)
@@ -3729,6 +3813,18 @@ int ulppm_set_contact(ulppm_ctx* ctx, const ulppm_contact* c) {
   return ULPPM_OK;
 }
 
+// Scratch of the bond-history adjoint, once both the adjoint scratch and the
+// bond states are reserved (whichever reservation comes second allocates it).
+static int reserve_adj_hist(ulppm_ctx* ctx) {
+  if (ctx->adj_hist || !ctx->adj || !ctx->hist[0]) return ULPPM_OK;
+  const hipError_t e = hipMalloc((void**)&ctx->adj_hist, sizeof(double) * 16 * (size_t)ctx->bond_cap);
+  if (e != hipSuccess) {
+    ctx->adj_hist = nullptr;
+    return fail(ctx, ULPPM_E_HIP, std::string("bond-history adjoint scratch: ") + hipGetErrorString(e));
+  }
+  return ULPPM_OK;
+}
+
 int ulppm_history_reserve(ulppm_ctx* ctx) {
   if (!ctx) return ULPPM_E_ARG;
   if (ctx->hist[0]) return ULPPM_OK;
@@ -3752,7 +3848,7 @@ int ulppm_history_reserve(ulppm_ctx* ctx) {
   ctx->hist_col = static_cast<int32_t*>(c);
   ctx->hist_last = 0;
   ctx->hist_n = 0;
-  return ULPPM_OK;
+  return reserve_adj_hist(ctx);
 }
 
 int ulppm_history_export(ulppm_ctx* ctx, int64_t* row_out, int32_t* col_out, double* st_out, int64_t cap,
@@ -3790,9 +3886,11 @@ int ulppm_adjoint_reserve(ulppm_ctx* ctx) {
     ctx->adj = nullptr;
     return fail(ctx, ULPPM_E_HIP, std::string("adjoint scratch: ") + hipGetErrorString(e));
   }
-  HIPCHK(hipFuncSetAttribute((const void*)k_adj_bond, hipFuncAttributeMaxDynamicSharedMemorySize,
+  HIPCHK(hipFuncSetAttribute((const void*)k_adj_bond<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)std::min(adj_lds(ctx->max_f), kMaxLds)));
-  return ULPPM_OK;
+  HIPCHK(hipFuncSetAttribute((const void*)k_adj_bond<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)std::min(adj_lds(ctx->max_f), kMaxLds)));
+  return reserve_adj_hist(ctx);
 }
 
 int ulppm_adjoint_init(ulppm_ctx* ctx, const ulppm_state* S0, const ulppm_params* p, double ocr,
@@ -3804,7 +3902,6 @@ int ulppm_adjoint_init(ulppm_ctx* ctx, const ulppm_state* S0, const ulppm_params
   if ((rc = check_params(ctx, p))) return rc;
   if (!s_bar || !theta_bar) return fail(ctx, ULPPM_E_ARG, "s_bar or theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
-  if (p->history) return fail(ctx, ULPPM_E_ARG, "the adjoint carries the history on the points only");
   if (!(ocr >= 1.0)) return fail(ctx, ULPPM_E_ARG, "ocr must be >= 1");
   const int64_t n = S0->n;
   if (adj0->n != n) return fail(ctx, ULPPM_E_ARG, "adjoint state must match the state size");
@@ -3857,8 +3954,22 @@ static int adjoint_rerun(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_param
   return ULPPM_OK;
 }
 
-int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* S1, const ulppm_params* p,
-                       const ulppm_state* adj1, ulppm_state* adj0, double* theta_bar, ulppm_report* rep) {
+// Bond states of the bond-history adjoint: those after step n (in the
+// order of the families row_n / col_n, none when nb_n == 0), the adjoint of
+// those after step n+1 (order of the families of state n+1) and the adjoint
+// of those after step n (written).
+struct HistAdj {
+  int64_t nb_n;
+  const int64_t* row_n;
+  const int32_t* col_n;
+  const double* hist_n;
+  const double* hist_bar1;
+  double* hist_bar0;
+};
+
+static int adjoint_step_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* S1, const ulppm_params* p,
+                             const ulppm_state* adj1, ulppm_state* adj0, double* theta_bar, ulppm_report* rep,
+                             const HistAdj* H) {
   if (!ctx) return ULPPM_E_ARG;
   int rc = check_state(ctx, S);
   if (rc) return rc;
@@ -3868,7 +3979,17 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
   if ((rc = check_params(ctx, p))) return rc;
   if (!theta_bar) return fail(ctx, ULPPM_E_ARG, "theta_bar is NULL");
   if (!ctx->adj) return fail(ctx, ULPPM_E_ARG, "call ulppm_adjoint_reserve first");
-  if (p->history) return fail(ctx, ULPPM_E_ARG, "the adjoint carries the history on the points only");
+  if (!H && p->history)
+    return fail(ctx, ULPPM_E_ARG, "with the history on the bonds use ulppm_adjoint_step_bond_history");
+  if (H) {
+    if (p->history != ULPPM_HISTORY_BOND) return fail(ctx, ULPPM_E_ARG, "p->history must be ULPPM_HISTORY_BOND");
+    if (!S1) return fail(ctx, ULPPM_E_ARG, "the bond-history adjoint needs state n+1");
+    if (!ctx->adj_hist) return fail(ctx, ULPPM_E_ARG, "call ulppm_history_reserve and ulppm_adjoint_reserve first");
+    if (!H->hist_bar1) return fail(ctx, ULPPM_E_ARG, "hist_bar_np1 is NULL");
+    if (H->nb_n < 0 || H->nb_n > ctx->bond_cap) return fail(ctx, ULPPM_E_ARG, "n_bonds_n out of range");
+    if (H->nb_n > 0 && (!H->row_n || !H->col_n || !H->hist_n || !H->hist_bar0))
+      return fail(ctx, ULPPM_E_ARG, "row_n, col_n, hist_n and hist_bar_n are needed when n_bonds_n > 0");
+  }
   if (p->precision != ULPPM_FP64 || p->force_mode != ULPPM_FORCE_CONJUGATE)
     return fail(ctx, ULPPM_E_ARG, "the adjoint supports FP64 with conjugate force states");
   if (!(p->dt > 0.0)) return fail(ctx, ULPPM_E_ARG, "dt must be > 0");
@@ -3936,9 +4057,33 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
     return fail(ctx, ULPPM_E_CAPACITY, "adjoint: a family of " + std::to_string(A.max_f) +
                                            " members exceeds the workgroup's LDS");
   const unsigned grid = (unsigned)(8 * A.per);
+  const size_t carry_lds = 4 * sizeof(int32_t) * (size_t)ctx->max_f;
+  const int have = H && H->nb_n > 0 ? 1 : 0;
+  if (H) {
+    // the start states of this step's bonds, carried from the bonds after step n
+    A.hstart = ctx->adj_hist;
+    A.hbar1 = H->hist_bar1;
+    A.hbar0s = ctx->adj_hist + 8 * ctx->bond_cap;
+    k_hist_carry<<<walk_grid(n), 256, carry_lds, ctx->stream>>>(n, ctx->row, ctx->col, H->row_n, H->col_n, have,
+                                                                ctx->max_f, H->hist_n, ctx->adj_hist, *S);
+    HIPCHK(hipGetLastError());
+  }
   k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
-  k_adj_bond<<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  if (H)
+    k_adj_bond<true><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  else
+    k_adj_bond<false><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   HIPCHK(hipGetLastError());
+  if (H) {
+    if (have) {
+      const int64_t len = 8 * H->nb_n;
+      k_fill<double><<<blocks_for(len, 256, 4096), 256, 0, ctx->stream>>>(H->hist_bar0, len, 0.0);
+    }
+    k_adj_hist_carry<<<walk_grid(n), 256, carry_lds, ctx->stream>>>(n, ctx->row, ctx->col, H->row_n, H->col_n,
+                                                                    have, ctx->max_f, A.hbar0s, H->hist_bar0, sigb,
+                                                                    pcb);
+    HIPCHK(hipGetLastError());
+  }
   k_adj_point2<<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->row, ctx->rev, S->fixed, own_x, own_vh, own_V,
                                                       A.slot_x, A.slot_vh, A.slot_V, ctx->bond_cap, sigb, pcb, Jb,
                                                       phib, sb, *adj1, *adj0, p->dt, ctx->contact, p->plane != 0, fbar, ctx->x,
@@ -3948,6 +4093,20 @@ int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* 
   if ((rc = read_counters(ctx))) return rc;
   fill_report(ctx, n, rep, 1);
   return counters_to_status(ctx);
+}
+
+int ulppm_adjoint_step(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* S1, const ulppm_params* p,
+                       const ulppm_state* adj1, ulppm_state* adj0, double* theta_bar, ulppm_report* rep) {
+  return adjoint_step_impl(ctx, S, S1, p, adj1, adj0, theta_bar, rep, nullptr);
+}
+
+int ulppm_adjoint_step_bond_history(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_state* S1,
+                                    const ulppm_params* p, int64_t n_bonds_n, const int64_t* row_n,
+                                    const int32_t* col_n, const double* hist_n, const double* hist_bar_np1,
+                                    const ulppm_state* adj1, ulppm_state* adj0, double* hist_bar_n,
+                                    double* theta_bar, ulppm_report* rep) {
+  const HistAdj H{n_bonds_n, row_n, col_n, hist_n, hist_bar_np1, hist_bar_n};
+  return adjoint_step_impl(ctx, S, S1, p, adj1, adj0, theta_bar, rep, &H);
 }
 
 int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_steps, ulppm_report* rep) {

@@ -62,7 +62,7 @@ class Contact(C.Structure):
 EXPORTS = ["ulppm_create", "ulppm_destroy", "ulppm_last_error", "ulppm_init_state", "ulppm_dt_crit",
            "ulppm_build_families", "ulppm_forces", "ulppm_step", "ulppm_reset_energy", "ulppm_adjoint_reserve",
            "ulppm_adjoint_step", "ulppm_adjoint_init", "ulppm_selfcheck_tail", "ulppm_set_contact",
-           "ulppm_history_reserve", "ulppm_history_export"]
+           "ulppm_history_reserve", "ulppm_history_export", "ulppm_adjoint_step_bond_history"]
 
 _lib = None
 
@@ -104,6 +104,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.ulppm_set_contact.argtypes = [vp, C.POINTER(Contact)]
     L.ulppm_history_reserve.argtypes = [vp]
     L.ulppm_history_export.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
+    L.ulppm_adjoint_step_bond_history.argtypes = [vp, C.POINTER(State), C.POINTER(State), C.POINTER(Params),
+                                                  C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                  C.POINTER(State), C.POINTER(State), C.c_void_p, C.c_void_p,
+                                                  C.POINTER(Report)]
     for name in EXPORTS:
         if name != "ulppm_last_error":
             getattr(L, name).restype = C.c_int
@@ -339,6 +343,30 @@ class Context:
         self._check(self.L.ulppm_adjoint_step(self.h, C.byref(cs), n1, C.byref(p), C.byref(c1), C.byref(c0),
                                               C.c_void_p(theta_bar.data_ptr()), C.byref(rep)))
         return rep.as_dict()
+
+    def adjoint_step_bond_history(self, S: "DeviceState", S1: "DeviceState", p: Params, hist_n, hist_bar1,
+                                  adj1: "DeviceState", adj0: "DeviceState", theta_bar) -> tuple:
+        """One reverse step with the history on the bonds.  hist_n = (row, col,
+        states) after step n as history_export returned them (None at the
+        first step); hist_bar1 = adjoint of the states after step n+1 (device
+        float64 (nb_{n+1}, 8)).  Returns (adjoint of hist_n's states, report)."""
+        import torch
+        rep = Report()
+        cs, c1s, c1, c0 = S.cstruct(), S1.cstruct(), adj1.cstruct(), adj0.cstruct()
+        if hist_n is None:
+            nb, rp, cp, hp, hbar0 = 0, None, None, None, None
+            out = None
+        else:
+            row, col, st = hist_n
+            nb = int(col.shape[0])
+            out = torch.zeros((max(nb, 1), 8), dtype=torch.float64, device=st.device)
+            rp, cp, hp = (C.c_void_p(t.data_ptr()) for t in (row, col, st))
+            hbar0 = C.c_void_p(out.data_ptr())
+        hb1 = hist_bar1.contiguous()
+        self._check(self.L.ulppm_adjoint_step_bond_history(
+            self.h, C.byref(cs), C.byref(c1s), C.byref(p), nb, rp, cp, hp, C.c_void_p(hb1.data_ptr()),
+            C.byref(c1), C.byref(c0), hbar0, C.c_void_p(theta_bar.data_ptr()), C.byref(rep)))
+        return (out[:nb] if out is not None else None), rep.as_dict()
 
     def adjoint_init(self, S0: "DeviceState", p: Params, ocr: float, adj0: "DeviceState", s_bar, theta_bar):
         """Reverse of init_state at its output S0: s_bar (device float64 (n,))

@@ -121,6 +121,86 @@ def test_bond_history_errors(olib, gpu):
     ctx.adjoint_reserve()
     A1 = gpu.DeviceState.from_arrays(olib.empty_state(col["n"]))
     A0 = gpu.DeviceState.from_arrays(olib.empty_state(col["n"]))
-    with pytest.raises(gpu.UlppmError) as ei:
+    with pytest.raises(gpu.UlppmError) as ei:          # the bond history has its own reverse entry point
         ctx.adjoint_step(G, gprm, A1, A0, torch.zeros(4, dtype=torch.float64, device="cuda"))
     assert ei.value.code == -1
+    ctx2.adjoint_reserve()                             # no bond states reserved: no scratch for the reverse
+    hb = torch.zeros((1, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu.UlppmError) as ei:
+        ctx2.adjoint_step_bond_history(G, G, gprm, None, hb, A1, A0, torch.zeros(4, dtype=torch.float64,
+                                                                                 device="cuda"))
+    assert ei.value.code == -1
+
+
+FIELDS_ADJ = ("u", "uc", "v", "a", "vol", "phi", "J", "Sr", "mass", "s", "sig", "pc")
+
+
+def test_bond_history_adjoint_matches_dual_numbers(olib, gpu):
+    """Gradient of J = sum c . u^N through 8 plastic steps with the history on
+    the bonds: the GPU reverse sweep (ulppm_adjoint_step_bond_history, the
+    bond states' adjoints carried between steps through the families each
+    step exported) dotted with directions in (M, lam, kap, eta), the initial
+    velocity, stress, pre-consolidation and suction equals the oracle's
+    directional derivatives with the history on the bonds (dual numbers)."""
+    import torch
+    say("bond history adjoint vs dual")
+    nsteps = 8
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=1, dims=(6, 6, 8))
+    n = col["n"]
+    oprm = olib.make_params(col["params"])
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    rng = np.random.default_rng(2)
+    fixed = col["fixed"] == 1
+    S["v"][:] = rng.uniform(-0.05, 0.05, S["v"].shape)
+    S["v"][fixed] = 0.0
+    gprm = gpu.make_params(olib.params_dict(oprm), history=gpu.ULPPM_HISTORY_BOND)
+    ctx = gpu.Context(n)
+    ctx.history_reserve()
+    ctx.adjoint_reserve()
+    G = gpu.DeviceState.from_arrays(S)
+    states, hists = [G.clone()], [None]
+    for _ in range(nsteps):
+        ctx.step(G, gprm, 1)
+        states.append(G.clone())
+        hists.append(ctx.history_export())
+    c = rng.normal(size=(n, 3))
+    lamN = {k: np.zeros_like(S[k]) for k in FIELDS_ADJ}
+    lamN["u"] = c
+    lam = gpu.DeviceState.from_arrays({**lamN, "x0": np.zeros((n, 3))})
+    hbar = torch.zeros((hists[-1][1].shape[0], 8), dtype=torch.float64, device="cuda")
+    th = torch.zeros(4, dtype=torch.float64, device="cuda")
+    for k in range(nsteps - 1, -1, -1):
+        out = gpu.DeviceState(n)
+        hbar, _ = ctx.adjoint_step_bond_history(states[k], states[k + 1], gprm, hists[k], hbar, lam, out, th)
+        lam = out
+    assert hbar is None                              # the first step carried no bond states
+    lam0 = lam.to_arrays()
+    th = th.cpu().numpy()
+    say("theta_bar", th)
+    vin = rng.normal(size=(n, 3))
+    vin[fixed] = 0.0
+    dirs = {
+        "M": (np.array([1.0, 0, 0, 0]), {}),
+        "lam": (np.array([0, 1.0, 0, 0]), {}),
+        "kap": (np.array([0, 0, 1.0, 0]), {}),
+        "eta": (np.array([0, 0, 0, oprm.eta]), {}),
+        "v0": (np.zeros(4), {"v": vin}),
+        "sig0": (np.zeros(4), {"sig": rng.normal(size=(n, 6)) * 1e3}),
+        "pc0": (np.zeros(4), {"pc": rng.normal(size=n) * 1e3}),
+        "s": (np.zeros(4), {"s": np.full(n, 1e3)}),
+    }
+    for name, (dpar, dfields) in dirs.items():
+        dS = olib.empty_state(n)
+        for k, val in dfields.items():
+            dS[k][:] = val
+        S1 = olib.copy_state(S)
+        H = olib.BondHistory(n, 200 * n)
+        rc, _, st = olib.step_dual_bond_history(S1, dS, oprm, dpar, H, nsteps)
+        assert rc == 0 and st["n_plastic"] > 0
+        dJ = float(np.sum(c * dS["u"]))
+        g = float(np.dot(th, dpar))
+        for k, val in dfields.items():
+            g += float(np.sum(lam0[k] * val))
+        say(name, dJ, g)
+        assert abs(g - dJ) <= 1e-7 * max(abs(dJ), 1e-300), (name, g, dJ)
