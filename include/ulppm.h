@@ -271,6 +271,17 @@ int ulppm_history_reserve(ulppm_ctx *ctx);
 int ulppm_history_export(ulppm_ctx *ctx, int64_t *row_out, int32_t *col_out, double *st_out, int64_t cap,
                          int64_t *nb_out);
 
+/* Load a bond history into the context, as ulppm_history_export wrote it
+ * after some step (device arrays: row n+1 int64, col n_bonds int32, st 8
+ * doubles per bond), so that the next ulppm_step with history =
+ * ULPPM_HISTORY_BOND carries these states; restarting from a checkpoint
+ * needs it.  n_bonds = 0 clears the history (every bond then starts from its
+ * point, as after ulppm_init_state).  The row must have been built for the
+ * same n and family capacity.  Errors: ULPPM_E_ARG (not reserved, sizes out of
+ * range), ULPPM_E_HIP. */
+int ulppm_history_import(ulppm_ctx *ctx, int64_t n, const int64_t *row, const int32_t *col, const double *st,
+                         int64_t n_bonds);
+
 /* Allocate the scratch of ulppm_adjoint_step (a copy of one state, the point
  * adjoints and 7 doubles per bond slot).  Call once, before the first adjoint
  * step; ulppm_adjoint_step itself never allocates.  Errors: ULPPM_E_ARG, ULPPM_E_HIP. */

@@ -63,7 +63,8 @@ class ColumnSpec:
     precision.  Holds one library context with its adjoint scratch."""
 
     def __init__(self, col: dict, n_steps: int, checkpoint_every: int, dt: Optional[float] = None,
-                 precision: int = ulppm.ULPPM_FP64, device="cuda", ctx: Optional["ulppm.Context"] = None):
+                 precision: int = ulppm.ULPPM_FP64, device="cuda", ctx: Optional["ulppm.Context"] = None,
+                 history: int = ulppm.ULPPM_HISTORY_POINT):
         if n_steps < 0 or checkpoint_every < 1:
             raise ValueError("n_steps >= 0 and checkpoint_every >= 1 required")
         self.n = col["n"]
@@ -72,9 +73,12 @@ class ColumnSpec:
         self.n_steps = int(n_steps)
         self.k = int(checkpoint_every)
         self.precision = precision
+        self.history = int(history)
         self.device = torch.device(device)
         self.base = ulppm.column_state(col, device)        # pre-initialisation state
         self.ctx = ctx if ctx is not None else ulppm.Context(self.n)
+        if self.history == ulppm.ULPPM_HISTORY_BOND:
+            self.ctx.history_reserve()
         self.ctx.adjoint_reserve()
         if dt is None:
             S = self.base.clone()
@@ -95,6 +99,7 @@ class ColumnSpec:
         for k, v in zip(THETA, [float(t) for t in theta]):
             d[k] = v
         d["dt"] = self.dt
+        d["history"] = self.history
         return ulppm.make_params(d, precision=self.precision if precision is None else precision)
 
     def initial_state(self, theta, s, v0):
@@ -110,14 +115,19 @@ class ColumnRun(torch.autograd.Function):
     device, s (n,) and v0 (n, 3) float64 on the spec's device.  Returns u^N as
     an (n, 3) float64 device tensor.  Backward: per segment from the last,
     recompute the segment's states from its checkpoint, then reverse its steps
-    one by one; finally reverse the initial conditions."""
+    one by one; finally reverse the initial conditions.  With the history on
+    the bonds each checkpoint also keeps the bond states and their families,
+    a recomputed segment starts from them, and the reverse carries their
+    adjoints from step to step."""
 
     @staticmethod
     def forward(ctx, theta, s, v0, spec):
         th = theta.detach().cpu()
         S = spec.initial_state(th, s.detach(), v0.detach())
         p = spec.params_for(th)
+        bond = spec.history == ulppm.ULPPM_HISTORY_BOND
         ckpts = [S.snapshot()]
+        hists = [None]                                     # init_state leaves no bond states
         reps = []
         done = 0
         while done < spec.n_steps:
@@ -125,9 +135,11 @@ class ColumnRun(torch.autograd.Function):
             reps.append(spec.ctx.step(S, p, m))
             done += m
             ckpts.append(S.snapshot())
+            hists.append(spec.ctx.history_export() if bond else None)
         ctx.spec = spec
         ctx.theta = th
         ctx.ckpts = ckpts
+        ctx.hists = hists
         ctx.theta_device = theta.device
         spec.last_forward = reps
         return S.t["u"].t().clone()
@@ -142,20 +154,34 @@ class ColumnRun(torch.autograd.Function):
         tb = torch.zeros(4, dtype=torch.float64, device=spec.device)
         reps = []
         clock = _Clock(spec.timing)
+        bond = spec.history == ulppm.ULPPM_HISTORY_BOND
+        hbar = None
+        if bond and spec.n_steps > 0:                      # nothing depends on the final bond states
+            hbar = torch.zeros_like(ctx.hists[-1][2])
         starts = list(range(0, spec.n_steps, spec.k))
         for seg in range(len(starts) - 1, -1, -1):
             m = min(spec.k, spec.n_steps - starts[seg])
             clock.start("recompute")
             states = [ctx.ckpts[seg]]
+            hists = [ctx.hists[seg]]
             S = ctx.ckpts[seg].snapshot()
+            if bond:
+                spec.ctx.history_import(ctx.hists[seg])
             for _ in range(m - 1):
                 spec.ctx.step(S, p, 1)
                 states.append(S.snapshot())
+                if bond:
+                    hists.append(spec.ctx.history_export())
             clock.stop("recompute")
             clock.start("reverse")
             states.append(ctx.ckpts[seg + 1])
             for n in range(m - 1, -1, -1):
-                reps.append(spec.ctx.adjoint_step(states[n], p64, lam, lam, tb, S1=states[n + 1]))
+                if bond:
+                    hbar, rep = spec.ctx.adjoint_step_bond_history(states[n], states[n + 1], p64, hists[n], hbar,
+                                                                   lam, lam, tb)
+                    reps.append(rep)
+                else:
+                    reps.append(spec.ctx.adjoint_step(states[n], p64, lam, lam, tb, S1=states[n + 1]))
             clock.stop("reverse")
             del states, S
         sbar = torch.empty(spec.n, dtype=torch.float64, device=spec.device)

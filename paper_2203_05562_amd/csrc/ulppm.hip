@@ -3874,6 +3874,26 @@ int ulppm_history_export(ulppm_ctx* ctx, int64_t* row_out, int32_t* col_out, dou
   return ULPPM_OK;
 }
 
+int ulppm_history_import(ulppm_ctx* ctx, int64_t n, const int64_t* row, const int32_t* col, const double* st,
+                         int64_t n_bonds) {
+  if (!ctx) return ULPPM_E_ARG;
+  if (!ctx->hist[0]) return fail(ctx, ULPPM_E_ARG, "call ulppm_history_reserve first");
+  if (n < 1 || n > ctx->cap_n) return fail(ctx, ULPPM_E_ARG, "n out of range");
+  if (n_bonds < 0 || n_bonds > ctx->bond_cap) return fail(ctx, ULPPM_E_ARG, "n_bonds out of range");
+  if (n_bonds == 0) {
+    ctx->hist_n = 0;                               // none held: every bond starts from its point
+    return ULPPM_OK;
+  }
+  if (!row || !col || !st) return fail(ctx, ULPPM_E_ARG, "row, col and st are needed when n_bonds > 0");
+  HIPCHK(hipMemcpyAsync(ctx->hist_row, row, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->hist_col, col, sizeof(int32_t) * n_bonds, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->hist[ctx->hist_last], st, sizeof(double) * 8 * n_bonds, hipMemcpyDeviceToDevice,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->hist_n = n;
+  return ULPPM_OK;
+}
+
 int ulppm_adjoint_reserve(ulppm_ctx* ctx) {
   if (!ctx) return ULPPM_E_ARG;
   if (ctx->adj) return ULPPM_OK;

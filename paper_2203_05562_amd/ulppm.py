@@ -62,7 +62,8 @@ class Contact(C.Structure):
 EXPORTS = ["ulppm_create", "ulppm_destroy", "ulppm_last_error", "ulppm_init_state", "ulppm_dt_crit",
            "ulppm_build_families", "ulppm_forces", "ulppm_step", "ulppm_reset_energy", "ulppm_adjoint_reserve",
            "ulppm_adjoint_step", "ulppm_adjoint_init", "ulppm_selfcheck_tail", "ulppm_set_contact",
-           "ulppm_history_reserve", "ulppm_history_export", "ulppm_adjoint_step_bond_history"]
+           "ulppm_history_reserve", "ulppm_history_export", "ulppm_history_import",
+           "ulppm_adjoint_step_bond_history"]
 
 _lib = None
 
@@ -104,6 +105,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.ulppm_set_contact.argtypes = [vp, C.POINTER(Contact)]
     L.ulppm_history_reserve.argtypes = [vp]
     L.ulppm_history_export.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
+    L.ulppm_history_import.argtypes = [vp, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
     L.ulppm_adjoint_step_bond_history.argtypes = [vp, C.POINTER(State), C.POINTER(State), C.POINTER(Params),
                                                   C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                                   C.POINTER(State), C.POINTER(State), C.c_void_p, C.c_void_p,
@@ -281,6 +283,18 @@ class Context:
         self._check(self.L.ulppm_history_export(self.h, C.c_void_p(row.data_ptr()), C.c_void_p(col.data_ptr()),
                                                 C.c_void_p(st.data_ptr()), m, C.byref(nb)))
         return row, col[:m], st[:m]
+
+    def history_import(self, hist):
+        """Load (row, col, states) as history_export returned them; None clears
+        the held history."""
+        if hist is None:
+            self._check(self.L.ulppm_history_import(self.h, self.n_points, None, None, None, 0))
+            return
+        row, col, st = hist
+        nb = int(col.shape[0])
+        st = st.contiguous()
+        self._check(self.L.ulppm_history_import(self.h, int(row.shape[0]) - 1, C.c_void_p(row.data_ptr()),
+                                                C.c_void_p(col.data_ptr()), C.c_void_p(st.data_ptr()), nb))
 
     def init_state(self, S: DeviceState, p: Params, ocr: float):
         cs = S.cstruct()

@@ -204,3 +204,53 @@ def test_bond_history_adjoint_matches_dual_numbers(olib, gpu):
             g += float(np.sum(lam0[k] * val))
         say(name, dJ, g)
         assert abs(g - dJ) <= 1e-7 * max(abs(dJ), 1e-300), (name, g, dJ)
+
+
+def test_bond_history_checkpointed_gradient(olib, gpu):
+    """The checkpointed differentiable column with the history on the bonds:
+    checkpoints every 1, 4 (ragged last segment) and 10 steps give the same
+    gradient (a recomputed segment starts from the bond states its checkpoint
+    kept), and its initial-velocity gradient of J = sum c . u^N over 10 steps
+    equals the oracle's directional derivative with the history on the bonds."""
+    import torch
+    from paper_2203_05562_amd import adjoint
+    say("bond history, checkpointed gradient")
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=1, dims=(6, 6, 8))
+    n = col["n"]
+    fixed = col["fixed"] == 1
+    rng = np.random.default_rng(4)
+    v0 = rng.uniform(-0.05, 0.05, (n, 3))
+    v0[fixed] = 0.0
+    oprm = olib.make_params(col["params"])
+    S = olib.init_column(col, oprm, col["params"]["ocr"], v0)
+    dt = 0.5 * olib.dt_crit(S, oprm)
+    c = rng.normal(size=(n, 3))
+
+    def grad(k):
+        spec = adjoint.ColumnSpec(col, 10, k, dt=dt, history=gpu.ULPPM_HISTORY_BOND)
+        theta = spec.theta0().requires_grad_(True)
+        s = torch.tensor(col["suction"], dtype=torch.float64, device="cuda", requires_grad=True)
+        v = torch.tensor(v0, dtype=torch.float64, device="cuda", requires_grad=True)
+        u = adjoint.ColumnRun.apply(theta, s, v, spec)
+        J = (u * torch.tensor(c, device="cuda")).sum()
+        J.backward()
+        return theta.grad.numpy().copy(), s.grad.cpu().numpy(), v.grad.cpu().numpy()
+
+    ref = grad(1)
+    for k in (4, 10):
+        got = grad(k)
+        say("k", k, got[0], ref[0])
+        for a, b in zip(got, ref):
+            assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+    dv = rng.normal(size=(n, 3))
+    dv[fixed] = 0.0
+    dS = olib.empty_state(n)
+    dS["v"][:] = dv
+    oprm.dt = dt
+    H = olib.BondHistory(n, 200 * n)
+    rc, _, st = olib.step_dual_bond_history(olib.copy_state(S), dS, oprm, np.zeros(4), H, 10)
+    assert rc == 0 and st["n_plastic"] > 0
+    dJ = float(np.sum(c * dS["u"]))
+    g = float(np.sum(ref[2] * dv))
+    say("v0 direction", dJ, g)
+    assert abs(g - dJ) <= 1e-7 * abs(dJ)
