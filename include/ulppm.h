@@ -259,8 +259,10 @@ int ulppm_step(ulppm_ctx *ctx, ulppm_state *state, const ulppm_params *p, int32_
 
 /* Allocate the bond states of ULPPM_HISTORY_BOND: two buffers of 8 doubles
  * per bond slot (n_points * max_family) and a copy of the families they
- * follow.  Call once before the first ulppm_step with history =
- * ULPPM_HISTORY_BOND.  Errors: ULPPM_E_ARG, ULPPM_E_HIP. */
+ * follow; if ulppm_adjoint_reserve has run, also the 16 doubles per bond
+ * slot of ulppm_adjoint_step_bond_history.  Call once before the first
+ * ulppm_step with history = ULPPM_HISTORY_BOND.  Errors: ULPPM_E_ARG,
+ * ULPPM_E_HIP. */
 int ulppm_history_reserve(ulppm_ctx *ctx);
 
 /* Copy the bond history of the last step to caller device memory: row_out
@@ -283,8 +285,10 @@ int ulppm_history_import(ulppm_ctx *ctx, int64_t n, const int64_t *row, const in
                          int64_t n_bonds);
 
 /* Allocate the scratch of ulppm_adjoint_step (a copy of one state, the point
- * adjoints and 7 doubles per bond slot).  Call once, before the first adjoint
- * step; ulppm_adjoint_step itself never allocates.  Errors: ULPPM_E_ARG, ULPPM_E_HIP. */
+ * adjoints and 7 doubles per bond slot) and, if ulppm_history_reserve has
+ * run, the 16 doubles per bond slot of ulppm_adjoint_step_bond_history.  Call
+ * once, before the first adjoint step; the adjoint steps themselves never
+ * allocate.  Errors: ULPPM_E_ARG, ULPPM_E_HIP. */
 int ulppm_adjoint_reserve(ulppm_ctx *ctx);
 
 /* Reverse mode of one step n -> n+1 (the workload's hand-written adjoint of
