@@ -1206,6 +1206,7 @@ struct BondArgs {
   double* pk;             // 2n: apparent pre-consolidation of p_c,i and 1/V_H,i (point kinematics)
   const double* xv;       // 8n: x (3), V^n, v_half (3), 0 per point
   double* hist;           // history on the bonds: 8 per bond (sigma, p_c, 0), updated in place; or null
+  double* fown;           // 3n: sum_k T_ik V_k of each point's own force states (FP64 conjugate); or null
   double dt_inc;
   int max_f;
   unsigned long long* ctr;
@@ -1840,6 +1841,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
     hpc += Vj * pcb;
     hw += Vj;
   }
+  double own[3] = {0.0, 0.0, 0.0};
   if (P.force_mode == ULPPM_FORCE_CONJUGATE && sizeof(Acc) == 8) {
     // ---- pass 2 in FP64 on the VALU: one lane per member k streams the M_j
     // of its row of the (symmetric) membership matrix.  FP64 matrix products
@@ -1876,8 +1878,11 @@ void k_bond_mx(BondArgs A, DevParams P) {
       const Acc* zm = sR + 8 * (size_t)m;
       const Acc zx = zm[0], zy = zm[1], zz = zm[2];
       const int64_t slot = b0 + m;
-      T4[slot] = Quad<TS>{{(TS)(a0 * zx + a1 * zy + a2 * zz), (TS)(a3 * zx + a4 * zy + a5 * zz),
-                           (TS)(a6 * zx + a7 * zy + a8 * zz), (TS)0}};
+      const Acc t0 = a0 * zx + a1 * zy + a2 * zz, t1 = a3 * zx + a4 * zy + a5 * zz, t2 = a6 * zx + a7 * zy + a8 * zz;
+      T4[slot] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
+      own[0] += t0 * zm[3];                                        // sum_k T_ik V_k
+      own[1] += t1 * zm[3];
+      own[2] += t2 * zm[3];
     }
   } else if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
     // ---- pass 2 in FP32: A_k = sum_j B_kj M_j on the matrix cores
@@ -1954,9 +1959,11 @@ void k_bond_mx(BondArgs A, DevParams P) {
   for (int k = 0; k < 6; ++k) hred[k * kBondThreads + tid] = hs[k];
   hred[6 * kBondThreads + tid] = hpc;
   hred[7 * kBondThreads + tid] = hw;
+  for (int c = 0; c < 3; ++c) own[c] = wave_sum(own[c]);
   if (lane == 0) {
     redi[wid][0] = n_deg; redi[wid][1] = n_pl; redi[wid][2] = n_nc; redi[wid][3] = n_trip;
     red[wid][8] = (double)mx;
+    red[wid][9] = own[0]; red[wid][10] = own[1]; red[wid][11] = own[2];
   }
   __syncthreads();
   if (wid == 0) {
@@ -1987,6 +1994,12 @@ void k_bond_mx(BondArgs A, DevParams P) {
     } else {
       for (int k = 0; k < 6; ++k) A.sig_out[k][i] = sig_i[k];
       A.pc_out[i] = pc_i;
+    }
+    if (A.fown) {
+      double o[3] = {0.0, 0.0, 0.0};
+      for (int w = 0; w < kBondWaves; ++w)
+        for (int c = 0; c < 3; ++c) o[c] += red[w][9 + c];
+      for (int c = 0; c < 3; ++c) A.fown[c * n + i] = o[c];
     }
     if (d) ctr_add(A.ctr, C_DEGEN, (unsigned long long)d);
     if (pl) ctr_add(A.ctr, C_PLASTIC, (unsigned long long)pl);
@@ -2801,6 +2814,7 @@ struct GatherArgs {
   const double* x;        // 3n current positions (contact)
   ContactDev c;
   int plane;
+  const double* fown;     // 3n: sum_j T_ij V_j from the bond kernel, or null (gathered here)
 };
 
 // One wave per point: f_i = V_i sum_j (T_ij - T_ji) V_j (Eqs. 49-50, sign of
@@ -2817,17 +2831,34 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
   for (int64_t i = W.first; i < W.end; i += W.stride) {
     const int64_t b0 = G.row[i], b1 = G.row[i + 1];
     TS f0 = 0, f1 = 0, f2 = 0;
-    for (int64_t s = b0 + lane; s < b1; s += kWave) {
-      const int32_t j = G.col[s], r = G.rev[s];
-      const TS wv = (TS)G.vol_n[j];
-      const Quad<TS> ts = T4[s], tr = T4[r];
-      f0 += (ts.v[0] - tr.v[0]) * wv;
-      f1 += (ts.v[1] - tr.v[1]) * wv;
-      f2 += (ts.v[2] - tr.v[2]) * wv;
+    if (G.fown) {
+      // the bond kernel summed the point's own force states; only T_ji is gathered
+      for (int64_t s = b0 + lane; s < b1; s += kWave) {
+        const int32_t j = G.col[s], r = G.rev[s];
+        const TS wv = (TS)G.vol_n[j];
+        const Quad<TS> tr = T4[r];
+        f0 -= tr.v[0] * wv;
+        f1 -= tr.v[1] * wv;
+        f2 -= tr.v[2] * wv;
+      }
+    } else {
+      for (int64_t s = b0 + lane; s < b1; s += kWave) {
+        const int32_t j = G.col[s], r = G.rev[s];
+        const TS wv = (TS)G.vol_n[j];
+        const Quad<TS> ts = T4[s], tr = T4[r];
+        f0 += (ts.v[0] - tr.v[0]) * wv;
+        f1 += (ts.v[1] - tr.v[1]) * wv;
+        f2 += (ts.v[2] - tr.v[2]) * wv;
+      }
     }
     f0 = wave_sum(f0);
     f1 = wave_sum(f1);
     f2 = wave_sum(f2);
+    if (G.fown) {
+      f0 += (TS)G.fown[i];
+      f1 += (TS)G.fown[G.n + i];
+      f2 += (TS)G.fown[2 * G.n + i];
+    }
     double fc[3] = {0.0, 0.0, 0.0};
     if (G.c.on) {
       contact_density(G.c, G.plane != 0, G.x[i], G.x[G.n + i], G.x[2 * G.n + i], G.vh[i], G.vh[G.n + i],
@@ -3005,6 +3036,7 @@ struct ulppm_ctx {
   double* pscr = nullptr;   // 12n point scratch for non-mutating passes
   double* pk = nullptr;     // 2n per-point values of the bond pass
   double* xv = nullptr;     // 8n packed x, V^n, v_half per point (bond-pass gathers)
+  double* fown = nullptr;   // 3n own-row force sums of the bond kernel (FP64 conjugate)
   int32_t* cellid = nullptr;
   int32_t* cnt = nullptr;
   int64_t* row = nullptr;   // n+1
@@ -3241,6 +3273,7 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   const bool mixed = p->precision == ULPPM_MIXED;
   A.T = ctx->T;
   A.hist = hist;
+  A.fown = (p->precision != ULPPM_MIXED && p->force_mode == ULPPM_FORCE_CONJUGATE) ? ctx->fown : nullptr;
   A.dt_inc = dt_inc;
   A.max_f = ctx->max_f;
   A.ctr = ctx->ctr;
@@ -3318,6 +3351,7 @@ int gather_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int
   G.x = ctx->x;
   G.c = ctx->contact;
   G.plane = p->plane;
+  G.fown = (!mixed && p->force_mode == ULPPM_FORCE_CONJUGATE) ? ctx->fown : nullptr;
   const unsigned grid = walk_grid(n);
   if (mode == G_STEP && (int64_t)grid * 3 + kPartGather > ctx->part_cap) return fail(ctx, ULPPM_E_ARG, "partials too small");
   if (mixed)
@@ -3573,6 +3607,7 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   A((void**)&ctx->pscr, sizeof(double) * 12 * n);
   A((void**)&ctx->pk, sizeof(double) * 2 * n);
   A((void**)&ctx->xv, sizeof(double) * 8 * n);
+  A((void**)&ctx->fown, sizeof(double) * 3 * n);
   A((void**)&ctx->cellid, sizeof(int32_t) * n);
   A((void**)&ctx->cnt, sizeof(int32_t) * n);
   A((void**)&ctx->row, sizeof(int64_t) * (n + 1));
@@ -3632,7 +3667,7 @@ int ulppm_destroy(ulppm_ctx* ctx) {
   if (!ctx) return ULPPM_E_ARG;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
-  void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->pk, ctx->xv, ctx->cellid, ctx->cnt, ctx->row, ctx->cand,
+  void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->pk, ctx->xv, ctx->fown, ctx->cellid, ctx->cnt, ctx->row, ctx->cand,
                   ctx->ccnt, ctx->crev, ctx->posmap, ctx->xref, ctx->gate,
                   ctx->ccount, ctx->ccursor, ctx->cstart, ctx->cpts, ctx->col, ctx->rev, ctx->T,
                   ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->ctr_sum, ctx->E, ctx->adj,
