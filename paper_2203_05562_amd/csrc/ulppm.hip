@@ -2821,8 +2821,9 @@ struct GatherArgs {
 // Eq. 33), gathering T_ji through rev[] instead of scattering with atomics;
 // then a = f/M + g (Eq. 62), v = v_half + (dt/2) a (Eq. 63), energy partials.
 // TS: storage and accumulation type of the force gather (float in mixed
-// precision); the Newmark update is FP64.
-template <class TS>
+// precision); the Newmark update is FP64.  Own: the bond kernel has summed
+// each point's own force states (G.fown), so only T_ji is gathered.
+template <class TS, bool Own>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const Quad<TS>* T4 = reinterpret_cast<const Quad<TS>*>(G.T);
@@ -2831,8 +2832,12 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
   for (int64_t i = W.first; i < W.end; i += W.stride) {
     const int64_t b0 = G.row[i], b1 = G.row[i + 1];
     TS f0 = 0, f1 = 0, f2 = 0;
-    if (G.fown) {
-      // the bond kernel summed the point's own force states; only T_ji is gathered
+    if constexpr (Own) {
+      // loaded before the bond loop so that the latency overlaps it
+      f0 = (TS)G.fown[i];
+      f1 = (TS)G.fown[G.n + i];
+      f2 = (TS)G.fown[2 * G.n + i];
+      if (lane != 0) f0 = f1 = f2 = (TS)0;          // added once by the wave sum
       for (int64_t s = b0 + lane; s < b1; s += kWave) {
         const int32_t j = G.col[s], r = G.rev[s];
         const TS wv = (TS)G.vol_n[j];
@@ -2854,11 +2859,6 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
     f0 = wave_sum(f0);
     f1 = wave_sum(f1);
     f2 = wave_sum(f2);
-    if (G.fown) {
-      f0 += (TS)G.fown[i];
-      f1 += (TS)G.fown[G.n + i];
-      f2 += (TS)G.fown[2 * G.n + i];
-    }
     double fc[3] = {0.0, 0.0, 0.0};
     if (G.c.on) {
       contact_density(G.c, G.plane != 0, G.x[i], G.x[G.n + i], G.x[2 * G.n + i], G.vh[i], G.vh[G.n + i],
@@ -3238,6 +3238,14 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
   return ULPPM_OK;
 }
 
+// Whether the bond kernel sums each point's own force states for the gather:
+// the FP64 conjugate path with families of more than one wave (with small
+// families the gather's per-point work is dominated by latency, not by the
+// records this saves).
+static bool own_sums(const ulppm_ctx* ctx, const ulppm_params* p) {
+  return p->precision != ULPPM_MIXED && p->force_mode == ULPPM_FORCE_CONJUGATE && ctx->max_f > kWave;
+}
+
 size_t bond_lds(int max_f, bool mixed) {
   return mixed ? bond_mx_lds_bytes<float>(max_f) : bond_mx_lds_bytes<double>(max_f);
 }
@@ -3273,7 +3281,7 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   const bool mixed = p->precision == ULPPM_MIXED;
   A.T = ctx->T;
   A.hist = hist;
-  A.fown = (p->precision != ULPPM_MIXED && p->force_mode == ULPPM_FORCE_CONJUGATE) ? ctx->fown : nullptr;
+  A.fown = own_sums(ctx, p) ? ctx->fown : nullptr;
   A.dt_inc = dt_inc;
   A.max_f = ctx->max_f;
   A.ctr = ctx->ctr;
@@ -3351,13 +3359,16 @@ int gather_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int
   G.x = ctx->x;
   G.c = ctx->contact;
   G.plane = p->plane;
-  G.fown = (!mixed && p->force_mode == ULPPM_FORCE_CONJUGATE) ? ctx->fown : nullptr;
+  G.fown = own_sums(ctx, p) ? ctx->fown : nullptr;
   const unsigned grid = walk_grid(n);
   if (mode == G_STEP && (int64_t)grid * 3 + kPartGather > ctx->part_cap) return fail(ctx, ULPPM_E_ARG, "partials too small");
   if (mixed)
-    k_gather<float><<<grid, 256, 0, ctx->stream>>>(G);
+    k_gather<float, false><<<grid, 256, 0, ctx->stream>>>(G);
   else
-    k_gather<double><<<grid, 256, 0, ctx->stream>>>(G);
+    if (G.fown)
+      k_gather<double, true><<<grid, 256, 0, ctx->stream>>>(G);
+    else
+      k_gather<double, false><<<grid, 256, 0, ctx->stream>>>(G);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
