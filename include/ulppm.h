@@ -313,7 +313,7 @@ int ulppm_adjoint_reserve(ulppm_ctx *ctx);
  * mixed-precision run (the reverse is then taken about that run's states).
  * rep (host) may be NULL; it receives the step's family counts and, when the
  * step is re-run from state_n, the re-run's counters (with state_np1 given
- * the return map is not re-run and its counters stay zero).
+ * only the families are rebuilt, and the return-map counters stay zero).
  * Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_NOCONV, ULPPM_E_HIP. */
 int ulppm_adjoint_step(ulppm_ctx *ctx, const ulppm_state *state_n, const ulppm_state *state_np1,
                        const ulppm_params *p, const ulppm_state *adj_np1, ulppm_state *adj_n,
