@@ -676,15 +676,17 @@ __global__ void k_check_skin(const double* __restrict__ x, const double* __restr
 // Family of every point in the current configuration (Eq. 1): one wave per
 // point filters its candidate row with the exact predicate; the ballot
 // prefix gives each member its slot in the row, so rows stay ascending.
-__global__ __launch_bounds__(256) void k_filter(const double* __restrict__ x, int64_t n, int max_c, int max_f,
+__global__ __launch_bounds__(256) void k_filter(const double* __restrict__ xv, int64_t n, int max_c, int max_f,
                                                 const int32_t* __restrict__ cand, const int32_t* __restrict__ ccnt,
                                                 double d2, int32_t* __restrict__ posmap, int32_t* __restrict__ cnt,
                                                 unsigned long long* __restrict__ ctr) {
   const int lane = threadIdx.x & (kWave - 1);
   const XcdWalk W = xcd_walk(n, 4);
   int wmax = 0;
+  const double4* P4 = reinterpret_cast<const double4*>(xv);     // packed records: x, y, z, V first
   for (int64_t i = W.first; i < W.end; i += W.stride) {
-    const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
+    const double4 pi = P4[2 * i];
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
     const int nc = ccnt[i];
     int count = 0;
     for (int base = 0; base < nc; base += kWave) {
@@ -692,7 +694,8 @@ __global__ __launch_bounds__(256) void k_filter(const double* __restrict__ x, in
       bool hit = false;
       if (c < nc) {
         const int32_t j = cand[i * (int64_t)max_c + c];
-        hit = within(xi, yi, zi, x[j], x[n + j], x[2 * n + j], d2);
+        const double4 pj = P4[2 * (int64_t)j];                     // one 32-byte read per candidate
+        hit = within(xi, yi, zi, pj.x, pj.y, pj.z, d2);
       }
       const unsigned long long mask = __ballot(hit);
       const int off = __popcll(mask & ((1ull << lane) - 1ull));
@@ -3227,7 +3230,9 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
   k_save_ref<<<blocks_for(3 * n, 256, 4096), 256, 0, ctx->stream>>>(ctx->x, ctx->xref, 3 * n, gate);
   k_fill<int32_t><<<1, 64, 0, ctx->stream>>>(ctx->gate, 1, 0);
   HIPCHK(hipGetLastError());
-  k_filter<<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->x, n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
+  // the packed point records carry the positions the filter reads
+  k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
+  k_filter<<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->xv, n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
                                                    delta * delta, ctx->posmap, ctx->cnt, ctx->ctr);
   HIPCHK(hipGetLastError());
   rc2 = scan_counts(ctx, ctx->cnt, n, ctx->row);
