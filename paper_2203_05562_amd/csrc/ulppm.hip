@@ -1208,7 +1208,9 @@ struct BondArgs {
                           // (double, or float in mixed precision)
   double* pk;             // 2n: apparent pre-consolidation of p_c,i and 1/V_H,i (point kinematics)
   const double* xv;       // 8n: x (3), V^n, v_half (3), 0 per point
-  double* hist;           // history on the bonds: 8 per bond (sigma, p_c, 0), updated in place; or null
+  double* hist;           // history on the bonds: 8 per bond (sigma, p_c, 0), written; or null
+  const double* hist_old; // the bond states of the previous step (8 per bond)
+  const int64_t* hmap;    // per bond: its slot in hist_old, or -1 (a new bond starts from its point)
   double* fown;           // 3n: sum_k T_ik V_k of each point's own force states (FP64 conjugate); or null
   double dt_inc;
   int max_f;
@@ -1462,6 +1464,37 @@ __global__ __launch_bounds__(256) void k_hist_carry(int64_t n, const int64_t* __
       }
     }
     __builtin_amdgcn_wave_barrier();               // every lane is done with the row before the next
+  }
+}
+
+// The forward's carry as a map: for every bond of the new families its slot
+// in the previous families (-1 for a bond that enters), so that the bond
+// kernel reads the old states directly.  One wave per point, as k_hist_carry.
+__global__ __launch_bounds__(256) void k_hist_map(int64_t n, const int64_t* __restrict__ row,
+                                                  const int32_t* __restrict__ col, const int64_t* __restrict__ hrow,
+                                                  const int32_t* __restrict__ hcol, int have, int max_f,
+                                                  int64_t* __restrict__ hmap) {
+  extern __shared__ int32_t s_hcol[];
+  int32_t* rowc = s_hcol + (threadIdx.x / kWave) * (size_t)max_f;
+  const int lane = threadIdx.x & (kWave - 1);
+  const XcdWalk W = xcd_walk(n, 4);
+  for (int64_t i = W.first; i < W.end; i += W.stride) {
+    const int64_t b0 = row[i], b1 = row[i + 1];
+    const int64_t h0 = have ? hrow[i] : 0;
+    const int nh = have ? (int)min<int64_t>(hrow[i + 1] - h0, max_f) : 0;
+    for (int t = lane; t < nh; t += kWave) rowc[t] = hcol[h0 + t];
+    __builtin_amdgcn_wave_barrier();
+    for (int64_t s = b0 + lane; s < b1; s += kWave) {
+      const int32_t j = col[s];
+      int lo = 0, hi = nh;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rowc[mid] < j) lo = mid + 1;
+        else hi = mid;
+      }
+      hmap[s] = (lo < nh && rowc[lo] == j) ? h0 + lo : -1;
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -1766,11 +1799,30 @@ void k_bond_mx(BondArgs A, DevParams P) {
       ixx = (b * c - d * d) * idK; iyy = (a * c - e * e) * idK; izz = (a * b - f * f) * idK;
       ixy = (d * e - f * c) * idK; ixz = (f * d - b * e) * idK; iyz = (e * f - a * d) * idK;
     }
+    // history on the bonds: the state the bond starts from
+    double sg0[6] = {0, 0, 0, 0, 0, 0}, pc0 = 0.0;
+    if constexpr (Hist) {
+      const int64_t src = A.hmap[slot];
+      if (src >= 0) {
+        const double4 ha = reinterpret_cast<const double4*>(A.hist_old)[2 * src];
+        const double4 hb = reinterpret_cast<const double4*>(A.hist_old)[2 * src + 1];
+        sg0[0] = ha.x; sg0[1] = ha.y; sg0[2] = ha.z; sg0[3] = ha.w; sg0[4] = hb.x; sg0[5] = hb.y;
+        pc0 = hb.z;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sg0[k] = sig_i[k];
+        pc0 = pc_i;
+      }
+    }
     if (!ok) {                                                  // degenerate: inactive bond
       ++n_deg;
 #pragma unroll
       for (int q = 0; q < 9; ++q) kn[q] = (Acc)0;
       if (P.force_mode == ULPPM_FORCE_EQ51) T4[slot] = Quad<TS>{{(TS)0, (TS)0, (TS)0, (TS)0}};
+      if constexpr (Hist) {                                     // an inactive bond keeps its state
+        reinterpret_cast<double4*>(A.hist)[2 * slot] = double4{sg0[0], sg0[1], sg0[2], sg0[3]};
+        reinterpret_cast<double4*>(A.hist)[2 * slot + 1] = double4{sg0[4], sg0[5], pc0, 0.0};
+      }
       continue;
     }
     double N[9];
@@ -1800,10 +1852,6 @@ void k_bond_mx(BondArgs A, DevParams P) {
         mx = mx > it ? mx : it;
       }
     } else {                                                    // each bond starts from its own state
-      const double4 ha = reinterpret_cast<const double4*>(A.hist)[2 * slot];
-      const double4 hb = reinterpret_cast<const double4*>(A.hist)[2 * slot + 1];
-      const double sg0[6] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y};
-      const double pc0 = hb.z;
       if (h == 0.0) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) sgb[k] = sg0[k];
@@ -3077,6 +3125,7 @@ struct ulppm_ctx {
   double* hist[2] = {nullptr, nullptr};
   int64_t* hist_row = nullptr;
   int32_t* hist_col = nullptr;
+  int64_t* hist_map = nullptr; // per bond slot: slot of the same bond in the previous families, or -1
   int hist_last = 0;
   int64_t hist_n = 0;         // points of the held history; 0: none
   // adjoint scratch (ulppm_adjoint_reserve)
@@ -3286,6 +3335,8 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   const bool mixed = p->precision == ULPPM_MIXED;
   A.T = ctx->T;
   A.hist = hist;
+  A.hist_old = hist ? ctx->hist[ctx->hist_last] : nullptr;
+  A.hmap = hist ? ctx->hist_map : nullptr;
   A.fown = own_sums(ctx, p) ? ctx->fown : nullptr;
   A.dt_inc = dt_inc;
   A.max_f = ctx->max_f;
@@ -3687,7 +3738,8 @@ int ulppm_destroy(ulppm_ctx* ctx) {
                   ctx->ccnt, ctx->crev, ctx->posmap, ctx->xref, ctx->gate,
                   ctx->ccount, ctx->ccursor, ctx->cstart, ctx->cpts, ctx->col, ctx->rev, ctx->T,
                   ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->ctr_sum, ctx->E, ctx->adj,
-                  ctx->adj_slot, ctx->adj_hist, ctx->hist[0], ctx->hist[1], ctx->hist_row, ctx->hist_col};
+                  ctx->adj_slot, ctx->adj_hist, ctx->hist[0], ctx->hist[1], ctx->hist_row, ctx->hist_col,
+                  ctx->hist_map};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ctx->have_events)
@@ -3884,12 +3936,14 @@ int ulppm_history_reserve(ulppm_ctx* ctx) {
   void* b = nullptr;
   void* r = nullptr;
   void* c = nullptr;
+  void* m = nullptr;
   hipError_t e = hipMalloc(&a, st);
   if (e == hipSuccess) e = hipMalloc(&b, st);
   if (e == hipSuccess) e = hipMalloc(&r, sizeof(int64_t) * (size_t)(ctx->cap_n + 1));
   if (e == hipSuccess) e = hipMalloc(&c, sizeof(int32_t) * (size_t)ctx->bond_cap);
+  if (e == hipSuccess) e = hipMalloc(&m, sizeof(int64_t) * (size_t)ctx->bond_cap);
   if (e != hipSuccess) {
-    for (void* q : {a, b, r, c})
+    for (void* q : {a, b, r, c, m})
       if (q) (void)hipFree(q);
     return fail(ctx, ULPPM_E_HIP, std::string("bond history: ") + hipGetErrorString(e));
   }
@@ -3897,6 +3951,7 @@ int ulppm_history_reserve(ulppm_ctx* ctx) {
   ctx->hist[1] = static_cast<double*>(b);
   ctx->hist_row = static_cast<int64_t*>(r);
   ctx->hist_col = static_cast<int32_t*>(c);
+  ctx->hist_map = static_cast<int64_t*>(m);
   ctx->hist_last = 0;
   ctx->hist_n = 0;
   return reserve_adj_hist(ctx);
@@ -4210,8 +4265,8 @@ int ulppm_step(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, int32_t n_
     if (bond_history) {
       const int have = ctx->hist_n == n ? 1 : 0;
       hist = ctx->hist[ctx->hist_last ^ 1];
-      k_hist_carry<<<walk_grid(n), 256, 4 * sizeof(int32_t) * (size_t)ctx->max_f, ctx->stream>>>(
-          n, ctx->row, ctx->col, ctx->hist_row, ctx->hist_col, have, ctx->max_f, ctx->hist[ctx->hist_last], hist, *S);
+      k_hist_map<<<walk_grid(n), 256, 4 * sizeof(int32_t) * (size_t)ctx->max_f, ctx->stream>>>(
+          n, ctx->row, ctx->col, ctx->hist_row, ctx->hist_col, have, ctx->max_f, ctx->hist_map);
       HIPCHK(hipGetLastError());
     }
     if ((rc = bond_pass(ctx, S, p, p->dt, true, [&](int b) {
