@@ -29,9 +29,9 @@
 //               91-93), acceleration, velocity corrector, energy partials
 //               (Eqs. 49-50, 62-63, 66-68)
 // The standard correspondence model (Eqs. 12-14) replaces the bond kernel by
-// k_point_kin_standard; the history carried on the bonds adds k_hist_carry
+// k_point_kin_standard; the history carried on the bonds adds k_hist_map
 // and k_hist_keep around it; the k_adj_* kernels run the reverse mode of a
-// step.
+// step (with the bond history, k_hist_carry and k_adj_hist_carry).
 //
 // Every kernel is stream-ordered on the context's stream.  No kernel traps;
 // failures raise device counters.  Memory: all scratch is allocated at
@@ -1423,10 +1423,11 @@ __global__ __launch_bounds__(256) void k_point_kin_standard(BondArgs A, DevParam
   }
 }
 
-// History carried on the bonds: the states of the new families' bonds.  One
-// wave per point, lanes over its bonds; a bond found (binary search) in the
-// point's row of the previous families keeps its state, a new bond starts
-// from the point history (sigma_i, p_c,i).  Rows of both are ascending.
+// History carried on the bonds: the start states of the new families' bonds,
+// copied (the reverse step's input).  One wave per point, lanes over its
+// bonds; a bond found (binary search) in the point's row of the previous
+// families keeps its state, a new bond starts from the point history
+// (sigma_i, p_c,i).  Rows of both are ascending.
 __global__ __launch_bounds__(256) void k_hist_carry(int64_t n, const int64_t* __restrict__ row,
                                                     const int32_t* __restrict__ col,
                                                     const int64_t* __restrict__ hrow,
