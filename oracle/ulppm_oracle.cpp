@@ -186,18 +186,6 @@ inline double r2(const double* a, const double* b) {
   return (xx + yy) + zz;
 }
 
-// The sub-horizon test of Eq. 22 for members j and k of the family of i:
-// the squared length of zeta_ik - zeta_ij, each relative position
-// zeta = x - x_i rounded first.
-inline double r2_rel(const double* xi, const double* xj, const double* xk) {
-  double zj[3], zk[3];
-  for (int c = 0; c < 3; ++c) {
-    zj[c] = xj[c] - xi[c];
-    zk[c] = xk[c] - xi[c];
-  }
-  return r2(zj, zk);
-}
-
 // ----------------------------------------------------------- families --
 
 struct Families {
@@ -741,7 +729,7 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
       for (int64_t t = b0; t < b1; ++t) {
         const int64_t k = F.col[t];
         ++n_tests;
-        if (!(r2_rel(&xval[3 * i], &xval[3 * j], &xval[3 * k]) <= d2)) continue;
+        if (!(r2(&xval[3 * j], &xval[3 * k]) <= d2)) continue;
         ++nsub;
         R z[3], y[3];
         for (int c = 0; c < 3; ++c) {
@@ -822,7 +810,7 @@ void algorithm1(const Params& P, const Mat<R>& m, int64_t n, const double* xval,
         R acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int64_t s = b0; s < b1; ++s) {
           const int64_t j = F.col[s];
-          if (!(r2_rel(&xval[3 * i], &xval[3 * j], &xval[3 * k]) <= d2)) continue;
+          if (!(r2(&xval[3 * j], &xval[3 * k]) <= d2)) continue;
           for (int q = 0; q < 9; ++q) acc[q] += SKb[9 * (s - b0) + q];
         }
         R z[3];

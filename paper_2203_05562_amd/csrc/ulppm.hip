@@ -1651,13 +1651,15 @@ void k_bond_mx(BondArgs A, DevParams P) {
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
   const int nw = (mf + 63) / 64;                   // membership words per row
-  // (zeta_ik, V_k) in FP64 for the exact membership test: the head of the
-  // FP64 member record, or an array of its own beside the FP32 records
+  // (x_k, V_k) in FP64 for the membership test of Eq. 22, which compares
+  // |x_k - x_j| from the absolute positions: the head of the FP64 member
+  // record (whose features take zeta_ik = x_k - x_i on the fly), or an array
+  // of its own beside the FP32 records (which hold zeta_ik)
   constexpr bool kF64 = sizeof(Acc) == 8;
-  constexpr int kZs = kF64 ? 2 : 1;                                    // Quad stride of (zeta, V)
+  constexpr int kZs = kF64 ? 2 : 1;                                    // Quad stride of (x, V)
   Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);
   Acc* sR = kF64 ? reinterpret_cast<Acc*>(smem_raw)
-                 : reinterpret_cast<Acc*>(sX + mf);                    // 8 per member: zeta, V, ydot, 1
+                 : reinterpret_cast<Acc*>(sX + mf);                    // 8 per member: x or zeta, V, ydot, 1
   Acc* sKN = sR + 8 * (size_t)mf;                                      // 16 per member: K, N, Vs, then M_j
   unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)mf);
   unsigned short* sq = reinterpret_cast<unsigned short*>(sb);
@@ -1678,18 +1680,23 @@ void k_bond_mx(BondArgs A, DevParams P) {
   const double pc_i = A.pc[i];
   if (tid == 0) s_d2 = P.d2;
 
-  // Stage the family of i: zeta_ik and V_k (FP64, for the exact predicate
-  // and the feature matrix) and ydot_ik.
+  // Stage the family of i: x_k and V_k (FP64, for the exact predicate; the
+  // FP64 feature matrix subtracts x_i), ydot_ik, and in mixed precision
+  // zeta_ik formed in FP64 before rounding.
   for (int m = tid; m < nf; m += kBondThreads) {
     const int32_t k = A.col[b0 + m];
     const double4 pa = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k];
     const double4 pb = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k + 1];
     const double Vk = pa.w;
-    const double z0 = pa.x - xi0, z1 = pa.y - xi1, z2 = pa.z - xi2;
     const double y0 = pb.x - vi0, y1 = pb.y - vi1, y2 = pb.z - vi2;
-    if constexpr (!kF64) sX[m] = Quad<double>{{z0, z1, z2, Vk}};
     Acc* rec = sR + 8 * (size_t)m;
-    rec[0] = (Acc)z0; rec[1] = (Acc)z1; rec[2] = (Acc)z2; rec[3] = (Acc)Vk;
+    if constexpr (kF64) {
+      rec[0] = pa.x; rec[1] = pa.y; rec[2] = pa.z;
+    } else {
+      sX[m] = Quad<double>{{pa.x, pa.y, pa.z, Vk}};
+      rec[0] = (Acc)(pa.x - xi0); rec[1] = (Acc)(pa.y - xi1); rec[2] = (Acc)(pa.z - xi2);
+    }
+    rec[3] = (Acc)Vk;
     rec[4] = (Acc)y0; rec[5] = (Acc)y1; rec[6] = (Acc)y2; rec[7] = (Acc)1;
   }
   __syncthreads();
@@ -1703,6 +1710,10 @@ void k_bond_mx(BondArgs A, DevParams P) {
   // the member loop is branch-free so that tests and products interleave.
   {
     const int fa = feat_a(r16), fb = feat_b(r16);
+    // the FP64 records hold x_k: a position feature is x_k - x_i, rounded as
+    // the relative position zeta_ik everywhere else
+    const double oa = kF64 && fa < 3 ? (fa == 0 ? xi0 : fa == 1 ? xi1 : xi2) : 0.0;
+    const double ob = kF64 && fb < 3 ? (fb == 0 ? xi0 : fb == 1 ? xi1 : xi2) : 0.0;
     // NB tile slots t0, t0 + kBondWaves, ... of one wave, all inside the family
     auto tiles = [&](int t0, auto nbc) {
       constexpr int NB = decltype(nbc)::value;
@@ -1723,7 +1734,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
       // member data of the next step is loaded one step ahead
       bool kv = q4 < nf;
       Quad<double> xk = sX[kZs * (kv ? q4 : 0)];
-      Acc ra = sR[8 * (size_t)(kv ? q4 : 0) + fa], rb = sR[8 * (size_t)(kv ? q4 : 0) + fb],
+      Acc ra = sR[8 * (size_t)(kv ? q4 : 0) + fa] - (Acc)oa, rb = sR[8 * (size_t)(kv ? q4 : 0) + fb] - (Acc)ob,
           rv = sR[8 * (size_t)(kv ? q4 : 0) + 3];
       for (int ks = 0; ks < nks; ++ks) {
         const int k1 = 4 * (ks + 1) + q4;
@@ -1731,7 +1742,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
         const int kk1 = kv1 ? k1 : 0;
         const Quad<double> xk1 = sX[kZs * kk1];
         const Acc* rec1 = sR + 8 * (size_t)kk1;
-        const Acc ra1 = rec1[fa], rb1 = rec1[fb], rv1 = rec1[3];
+        const Acc ra1 = rec1[fa] - (Acc)oa, rb1 = rec1[fb] - (Acc)ob, rv1 = rec1[3];
         const Acc fv = ra * rb * rv;
         const Acc bval = kv ? fv : (Acc)0;
         const unsigned sbit = 1u << (ks & 15);
@@ -1878,7 +1889,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
     const double Vj = zj.v[3];
     if (P.force_mode == ULPPM_FORCE_EQ51) {
       // Eq. 51 as printed: T_ij = varpi (sigma_ij + Sr s 1) K_ij^{-1} zeta_ij.
-      const double zx = zj.v[0], zy = zj.v[1], zz = zj.v[2];
+      const double zx = zj.v[0] - xi0, zy = zj.v[1] - xi1, zz = zj.v[2] - xi2;
       T4[slot] = Quad<TS>{{(TS)(varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz)),
                            (TS)(varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz)),
                            (TS)(varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz)), (TS)0}};
@@ -1894,7 +1905,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
     hw += Vj;
   }
   double own[3] = {0.0, 0.0, 0.0};
-  if (P.force_mode == ULPPM_FORCE_CONJUGATE && sizeof(Acc) == 8) {
+  if constexpr (kF64) if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
     // ---- pass 2 in FP64 on the VALU: one lane per member k streams the M_j
     // of its row of the (symmetric) membership matrix.  FP64 matrix products
     // run at the vector rate on this chip and would pad the 9 outputs to 16.
@@ -1927,8 +1938,8 @@ void k_bond_mx(BondArgs A, DevParams P) {
           }
         }
       }
-      const Acc* zm = sR + 8 * (size_t)m;
-      const Acc zx = zm[0], zy = zm[1], zz = zm[2];
+      const Acc* zm = sR + 8 * (size_t)m;                          // x_k, V_k (FP64 record)
+      const Acc zx = zm[0] - xi0, zy = zm[1] - xi1, zz = zm[2] - xi2;
       const int64_t slot = b0 + m;
       const Acc t0 = a0 * zx + a1 * zy + a2 * zz, t1 = a3 * zx + a4 * zy + a5 * zz, t2 = a6 * zx + a7 * zy + a8 * zz;
       T4[slot] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
@@ -1936,7 +1947,8 @@ void k_bond_mx(BondArgs A, DevParams P) {
       own[1] += t1 * zm[3];
       own[2] += t2 * zm[3];
     }
-  } else if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
+  }
+  if constexpr (!kF64) if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
     // ---- pass 2 in FP32: A_k = sum_j B_kj M_j on the matrix cores
     // (membership is symmetric, so row k of the bit matrix is column k),
     // then T_ik = A_k zeta_ik with the three products of a row combined
@@ -2214,7 +2226,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
   const int nw = (mf + 63) / 64;
-  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);   // Tbar_ik (after pass 1)
+  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);   // x_k (pass 1), then Tbar_ik
   Quad<double>* sTb = sX;
   Quad<double>* sZ = sX + mf;                                     // zeta_ik, V_k
   Quad<double>* sY = sZ + mf;                                     // ydot_ik, 1
@@ -2242,6 +2254,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     const double xk0 = pa.x, xk1 = pa.y, xk2 = pa.z, V = pa.w;
     const double z0 = xk0 - xi0, z1 = xk1 - xi1, z2 = xk2 - xi2;
     const double y0 = pb.x - vi0, y1 = pb.y - vi1, y2 = pb.z - vi2;
+    sX[m] = Quad<double>{{xk0, xk1, xk2, V}};
     sZ[m] = Quad<double>{{z0, z1, z2, V}};
     sY[m] = Quad<double>{{y0, y1, y2, 1.0}};
     sZb[m] = Quad<double>{{0.0, 0.0, 0.0, 0.0}};
@@ -2303,7 +2316,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
       for (int b = 0; b < NB; ++b) {
         jrow[b] = (t0 + kBondWaves * b) * 16 + r16;
         jv[b] = jrow[b] < nf;
-        const Quad<double> q = sZ[jv[b] ? jrow[b] : 0];     // relative positions: the test of Eq. 22
+        const Quad<double> q = sX[jv[b] ? jrow[b] : 0];     // positions: the test of Eq. 22
         xj[b][0] = q.v[0]; xj[b][1] = q.v[1]; xj[b][2] = q.v[2];
         acc[b] = v4d{0, 0, 0, 0};
         piece[b] = 0u;
@@ -2312,7 +2325,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         const int kk0 = 4 * ks + q4;
         const bool kv = kk0 < nf;
         const int kk = kv ? kk0 : 0;
-        const Quad<double> xk = sZ[kk];
+        const Quad<double> xk = sX[kk];
         const double fvv = rz[4 * kk + oa] * rz[4 * kk + ob] * rz[4 * kk + ov];
         const double bval = kv ? fvv : 0.0;
         const unsigned sbit = 1u << (ks & 15);

@@ -153,6 +153,71 @@ def test_forces_and_bond_states(olib, gpu, vscale, dtmul):
     assert rel_l2(fg, out["f"]) <= 1e-11
 
 
+def _boundary_column(olib, seed):
+    """A 6 x 6 x 6 column with sub-horizon members placed one ulp around the
+    boundary |x_k - x_j| = delta, where the squared distance from the
+    positions (Eq. 22) and the one from the relative positions
+    (x_k - x_i) - (x_j - x_i) fall on different sides of delta^2.  Near the
+    x = 0 face the relative positions round, so such placements exist.
+    Returns the column with x0 moved, and the number of placements."""
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=seed, dims=(6, 6, 6))
+    lat = col["lattice"]
+    idx = {tuple(map(int, l)): n for n, l in enumerate(lat)}
+    x = col["x0"]
+    delta = col["params"]["delta"]
+    d2 = delta * delta
+    placed = 0
+    for ci, cj, ck in (((1, 3, 3), (0, 3, 3), (3, 3, 3)), ((1, 2, 3), (0, 2, 3), (3, 2, 3)),
+                       ((1, 3, 1), (0, 3, 1), (3, 3, 1))):
+        i, j, k = idx[ci], idx[cj], idx[ck]
+        for m in (1, -1, 2, -2, 3, -3):
+            d = delta
+            for _ in range(abs(m)):
+                d = float(np.nextafter(d, np.inf if m > 0 else -np.inf))
+            xk = [x[j][0] + d, x[j][1], x[j][2]]
+            dx = [xk[c] - x[j][c] for c in range(3)]
+            plain = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2]
+            dd = [(xk[c] - x[i][c]) - (x[j][c] - x[i][c]) for c in range(3)]
+            rel = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]
+            if (plain <= d2) != (rel <= d2):
+                x[k] = xk
+                placed += 1
+                break
+    return col, placed
+
+
+def test_subhorizon_boundary_members(olib, gpu):
+    """Members placed one ulp around the sub-horizon boundary: the GPU takes
+    the same set decisions as the oracle (Eq. 22 from the positions), so
+    the counts are equal and the forces agree at the FP64 bar."""
+    for seed in (0, 6, 9):
+        col, placed = _boundary_column(olib, seed)
+        say("boundary members", seed, placed)
+        assert placed >= 1
+        oprm = olib.make_params(col["params"])
+        S = olib.init_column(col, oprm, col["params"]["ocr"])
+        S["v"][:] = inputs.random_velocity(col["n"], seed + 5, 0.05)
+        oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+        out = olib.bond_fields(S, oprm, oprm.dt)
+        gprm = gpu.make_params(olib.params_dict(oprm))
+        ctx = gpu.Context(col["n"], max_family=128)
+        G = gpu.DeviceState.from_arrays(S)
+        f, T, rep = ctx.forces(G, gprm, oprm.dt, want_T=True)
+        assert rep["n_tests"] == out["stats"]["n_tests"]
+        assert rep["n_triples"] == out["stats"]["n_triples"]
+        assert rep["n_degenerate"] == out["stats"]["n_degenerate"]
+        Tg = T.cpu().numpy().T
+        tscale = np.abs(out["T"]).max()
+        assert np.abs(Tg - out["T"]).max() <= 1e-11 * tscale
+        fg = f.cpu().numpy().T
+        assert rel_l2(fg, out["f"]) <= 1e-11
+        rc, E, st = olib.step(S, oprm, 3)
+        assert rc == 0
+        rep = ctx.step(G, gprm, 3)
+        assert rep["n_triples"] == st["n_triples"]
+        compare_states(G.to_arrays(), S, 1e-11, label="boundary 3 steps")
+
+
 # --------------------------------------------------------------- stepping --
 
 @pytest.mark.parametrize("vscale", [0.0, 0.3])

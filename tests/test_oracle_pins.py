@@ -115,6 +115,159 @@ def test_subhorizon_sizes_and_shape_tensor_on_lattice(olib):
     assert shells[5] == {59} and shells[6] == {51} and shells[8] == {44} and shells[9] == {37, 43}
 
 
+def _ulp_steps(x, m):
+    """The double m representable steps from x (m may be negative)."""
+    for _ in range(abs(m)):
+        x = np.nextafter(x, np.inf if m > 0 else -np.inf)
+    return float(x)
+
+
+def test_subhorizon_boundary_follows_positions(olib):
+    """Eq. 22, S_ij = {k in H_i : |x_k - x_j| <= delta}, decided at the
+    boundary.  Member k of an interior family is put on the x-axis through
+    x_j at x_j + d, with d a few ulps inside or outside delta; x_k - x_j is
+    then exact (Sterbenz), so exact rational arithmetic decides membership.
+    |S_ij| of the oracle follows that decision at every placement, and k
+    enters exactly when d <= delta."""
+    from fractions import Fraction as Fr
+    col, prm, S = column_state(olib, (10, 6, 6), seed=4)
+    lat = col["lattice"]
+    idx = {tuple(map(int, l)): n for n, l in enumerate(lat)}
+    i, j, k = idx[(6, 3, 3)], idx[(5, 3, 3)], idx[(8, 3, 3)]
+    delta = prm.delta
+    counts = {}
+    for m in (-6, -4, -3, 3, 4, 6):
+        d = _ulp_steps(delta, m)
+        S2 = olib.copy_state(S)
+        S2["x0"][k] = [S["x0"][j][0] + d, S["x0"][j][1], S["x0"][j][2]]
+        xk, xj = S2["x0"][k], S2["x0"][j]
+        assert Fr(xk[0]) - Fr(xj[0]) == Fr(xk[0] - xj[0])         # the difference is exact
+        out = olib.bond_fields(S2, prm, 0.0)
+        row, colx = out["row"], out["col"]
+        fam = colx[row[i]:row[i + 1]]
+        assert k in fam
+        s = row[i] + int(np.nonzero(fam == j)[0][0])
+        x = S2["x0"]
+        exact = 0
+        for kk in fam:
+            r2 = sum((Fr(x[kk][c]) - Fr(x[j][c])) ** 2 for c in range(3))
+            if kk != k:      # the other members sit far from the boundary
+                assert abs(r2 - Fr(delta) ** 2) > Fr(1, 10 ** 12) * Fr(delta) ** 2
+            exact += r2 <= Fr(delta) ** 2
+        assert out["nsub"][s] == exact, (m, out["nsub"][s], exact)
+        counts[m] = exact
+    assert counts[-3] == counts[-6] == counts[3] + 1 == counts[6] + 1
+
+
+def test_eq51_varpi_and_force_states_on_lattice(olib):
+    """Eqs. 51, 53, 55 on the unjittered lattice.  varpi_ij = V_s / V_H, the
+    sub-horizon's volume over the family's, with the members taken from
+    the integer-lattice enumeration and random point volumes; at a uniform
+    stress the Eq. 51 force state of each interior bond equals
+    varpi_ij (sigma + S_r s 1) K_ij^{-1} zeta_ij with K_ij from the lattice
+    sums V n n^T of the enumerated members."""
+    col, prm, S = column_state(olib, (16, 16, 16), jitter=0.0)
+    prm.force_mode = 1
+    rng = np.random.default_rng(21)
+    S["vol"][:] = DX ** 3 * rng.uniform(0.5, 1.5, col["n"])
+    sig6 = [-20e3, -15e3, -25e3, 3e3, -2e3, 1e3]
+    set_uniform_stress(S, sig6, -60e3, 20e3)
+    out = olib.bond_fields(S, prm, 0.0)
+    lat = col["lattice"]
+    idx = {tuple(map(int, l)): n for n, l in enumerate(lat)}
+    fam = lattice_family()
+    sig = np.array([[sig6[0], sig6[5], sig6[4]], [sig6[5], sig6[1], sig6[3]], [sig6[4], sig6[3], sig6[2]]])
+    for centre in ((8, 8, 8), (7, 9, 8)):
+        i = idx[centre]
+        ci = np.array(centre)
+        VH = sum(S["vol"][idx[tuple(ci + n)]] for n in fam)
+        ps = out["Sr_new"][i] * S["s"][i]
+        for s in range(out["row"][i], out["row"][i + 1]):
+            j = int(out["col"][s])
+            nj = lat[j] - ci
+            members = [n for n in fam if sum((a - b) ** 2 for a, b in zip(n, nj)) <= D2_LATTICE]
+            Vk = np.array([S["vol"][idx[tuple(ci + n)]] for n in members])
+            varpi = Vk.sum() / VH
+            assert abs(out["varpi"][s] - varpi) <= 1e-14 * varpi
+            K = sum(v * DX * DX * np.outer(n, n) for v, n in zip(Vk, members))
+            T = varpi * (sig + ps * np.eye(3)) @ np.linalg.solve(K, nj * DX)
+            assert np.abs(out["T"][s] - T).max() <= 1e-10 * np.abs(T).max(), (centre, tuple(nj))
+    # a transposed zeta (zeta_ji) or an unweighted varpi would fail: the
+    # volumes are not uniform and varpi differs between shells
+    assert len(set(np.round(out["varpi"], 12))) > 8
+
+
+def test_history_mean_is_volume_weighted(olib):
+    """Point history (Section 1; R8): the new point stress and p_c are the
+    mean of the bond states weighted by the step-n volumes V_j of the bonds'
+    far ends.  Volumes and bond stresses both vary here, so an unweighted
+    mean, weights V_k of the sub-horizon members or the updated volumes
+    V^{n+1} all fail."""
+    col, prm, S = column_state(olib, (8, 8, 8), seed=6)
+    rng = np.random.default_rng(33)
+    S["vol"][:] = DX ** 3 * rng.uniform(0.4, 1.6, col["n"])
+    S["v"][:] = rng.uniform(-0.5, 0.5, S["v"].shape)
+    dt = 1e-4
+    out = olib.bond_fields(S, prm, dt)
+    row, colx = out["row"], out["col"]
+    worst = 0.0
+    gaps = []
+    for i in range(0, col["n"], 5):
+        sl = slice(row[i], row[i + 1])
+        act = out["active"][sl] == 1
+        js = colx[sl][act]
+        w = S["vol"][js]
+        bs = out["sig"][sl][act]
+        exp = (w[:, None] * bs).sum(0) / w.sum()
+        exp_pc = (w * out["pc"][sl][act]).sum() / w.sum()
+        scale = np.abs(bs).max()
+        worst = max(worst, np.abs(out["sig_pt"][i] - exp).max() / scale,
+                    abs(out["pc_pt"][i] - exp_pc) / abs(exp_pc))
+        w1 = w * out["Jd"][js]
+        gaps.append((np.abs(bs.mean(0) - exp).max() / scale,
+                     np.abs((w1[:, None] * bs).sum(0) / w1.sum() - exp).max() / scale))
+    assert worst <= 1e-13
+    gaps = np.array(gaps)
+    assert gaps[:, 0].max() > 1e-4 and gaps[:, 1].max() > 1e-9
+
+
+def test_force_state_virial_is_the_point_stress(olib):
+    """Why the conjugate force state weighs each sub-horizon by V_j / V_H.
+    For T_ik = sum_{j: k in S_ij} (V_j/V_H) (sigma_ij + S_r s 1) K_ij^{-1}
+    zeta_ik, the nonlocal virial sum_k V_k T_ik (x) zeta_ik collapses through
+    K_ij^{-1} K_ij to sum_j (V_j/V_H)(sigma_ij + S_r s 1): the step's new
+    point stress (the V_j-weighted mean of the bond stresses) plus S_r s 1.
+    The standard correspondence force state (Eq. 14) has the same property
+    with the point stress, sum_k V_k T_ik (x) zeta_ik = sigma_i + S_r s 1, so
+    this weight makes the sub-horizon model carry the point history's
+    stress exactly as the standard model does."""
+    for mode in (0, 2):
+        col, prm, S = column_state(olib, (8, 8, 8), seed=12)
+        prm.force_mode = mode
+        rng = np.random.default_rng(8)
+        S["vol"][:] = DX ** 3 * rng.uniform(0.5, 1.5, col["n"])
+        S["v"][:] = rng.uniform(-0.3, 0.3, S["v"].shape)
+        out = olib.bond_fields(S, prm, 1e-4)
+        assert out["stats"]["n_plastic"] > 0
+        x = S["x0"] + S["u"]
+        row, colx = out["row"], out["col"]
+        worst, checked = 0.0, 0
+        for i in range(col["n"]):
+            sl = slice(row[i], row[i + 1])
+            if mode == 0 and not np.all(out["active"][sl] == 1):
+                continue
+            ks = colx[sl]
+            z = x[ks] - x[i]
+            vir = np.einsum("k,ka,kb->ab", S["vol"][ks], out["T"][sl], z)
+            sv = out["sig_pt"][i]
+            exp = np.array([[sv[0], sv[5], sv[4]], [sv[5], sv[1], sv[3]], [sv[4], sv[3], sv[2]]])
+            exp += out["Sr_new"][i] * S["s"][i] * np.eye(3)
+            worst = max(worst, np.abs(vir - exp).max() / np.abs(exp).max())
+            checked += 1
+        assert checked > col["n"] // 2
+        assert worst <= 1e-11, (mode, worst)
+
+
 # ---------------------------------------------------------- velocity gradient --
 
 def test_linear_field_reproduced_exactly(olib):
@@ -200,7 +353,8 @@ def test_frame_indifference_lattice_rotation(olib):
 
 # ------------------------------------------------------------------ forces --
 
-def test_internal_forces_sum_to_zero(olib):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_internal_forces_sum_to_zero(olib, mode):
     """Eqs. 49-50: the assembled internal force is a pair sum antisymmetric in
     (i, j), so its total vanishes for any state.  Its moment vanishes too:
     every point's conjugate force states give sum_k V_k zeta_ik x T_ik =
@@ -208,22 +362,30 @@ def test_internal_forces_sum_to_zero(olib):
     transposed K^{-1}, a member missing from K_j or a non-symmetric stress
     update shows up as a net moment."""
     col, prm, S = column_state(olib, (8, 8, 12), seed=2)
+    prm.force_mode = mode
     rng = np.random.default_rng(5)
     S["v"][:] = rng.uniform(-0.1, 0.1, S["v"].shape)
     S["sig"][:] += rng.uniform(-2e3, 2e3, S["sig"].shape)
     out = olib.bond_fields(S, prm, 2e-5)
     f = out["f"]
     assert np.abs(f.sum(axis=0)).max() <= 1e-13 * np.abs(f).sum()
+    if mode == 1:
+        # Eq. 51 keeps only the bond's own term: sum_k V_k zeta_ik x T_ik is
+        # then no symmetric contraction and the moment does not vanish
+        return
     x = S["x0"] + S["u"]
     mom = np.cross(x, f).sum(axis=0)
     assert np.abs(mom).max() <= 1e-13 * (np.linalg.norm(x, axis=1) * np.linalg.norm(f, axis=1)).sum()
 
 
-def test_interior_patch_uniform_stress(olib):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_interior_patch_uniform_stress(olib, mode):
     """A uniform stress on the unjittered lattice leaves points at least
     2 delta inside the body force-free: sub-horizons of bonds n and -n are
-    point reflections of each other (Eq. 33 with central symmetry)."""
+    point reflections of each other (Eq. 33 with central symmetry), for the
+    conjugate force states and for Eq. 51 as printed."""
     col, prm, S = column_state(olib, (16, 16, 16), jitter=0.0)
+    prm.force_mode = mode
     set_uniform_stress(S, [-20e3, -15e3, -25e3, 3e3, -2e3, 1e3], -60e3, 20e3)
     out = olib.bond_fields(S, prm, 0.0)
     lat = col["lattice"]
