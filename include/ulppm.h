@@ -23,7 +23,8 @@
  *   device counters that the host turns into codes, with text available from
  *   ulppm_last_error.  After an error the state is finite or flagged but
  *   otherwise unspecified; restore it from a copy.
- * - One context per host thread / stream; no global state.
+ * - One context per host thread / stream.  The only global state is the
+ *   static scratch of ulppm_forces_static, one array per device.
  */
 #ifndef ULPPM_H
 #define ULPPM_H
@@ -242,6 +243,26 @@ int ulppm_build_families(ulppm_ctx *ctx, const ulppm_state *state, const ulppm_p
  * Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_NOCONV, ULPPM_E_HIP. */
 int ulppm_forces(ulppm_ctx *ctx, const ulppm_state *state, const ulppm_params *p, double dt_inc,
                  double *f[3], double *T_out[3], ulppm_report *rep);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ulppm_forces
+ * without a context.  The scratch it needs lives in a file-scope device
+ * array of the library, 16 MiB on each GPU the library runs on, held until
+ * the process ends; it serves at most ULPPM_STATIC_MAX_POINTS points and
+ * ULPPM_STATIC_MAX_FAMILY members per family.  The first call on a device
+ * (with that device current) looks the array up; no call allocates device
+ * memory.  Arguments and results are those of ulppm_forces (no substrate is
+ * attached); hip_stream is a hipStream_t (NULL = the null stream).  Every call
+ * on one device shares that device's array, which keeps the last call's
+ * contents (each call clears what must start at zero): calls that overlap on
+ * one device, on any streams or host threads, race and must not be issued.
+ * Errors: ULPPM_E_ARG (state NULL, n < 1 or n > ULPPM_STATIC_MAX_POINTS,
+ * other arguments as ulppm_forces), ULPPM_E_CAPACITY (a family larger than
+ * ULPPM_STATIC_MAX_FAMILY), ULPPM_E_NOCONV, ULPPM_E_HIP. */
+#define ULPPM_STATIC_MAX_POINTS 2048
+#define ULPPM_STATIC_MAX_FAMILY 128
+int ulppm_forces_static(const ulppm_state *state, const ulppm_params *p, double dt_inc, double *f[3],
+                        double *T_out[3], ulppm_report *rep, void *hip_stream);
 
 /* Algorithm 2, n_steps explicit central-difference Newmark steps (beta1 = 1/2,
  * beta2 = 0, Eqs. 60-64), state updated in place.  Each step: velocity

@@ -39,6 +39,7 @@
 
 #include <hip/hip_runtime.h>
 #include <functional>
+#include <mutex>
 #include <type_traits>
 
 #include <cmath>
@@ -3657,31 +3658,29 @@ int ulppm_selfcheck_tail(const ulppm_params* p, int32_t seed, int32_t n_cases, d
   return ULPPM_OK;
 }
 
-int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hip_stream) {
-  ulppm_ctx* ctx = nullptr;
-  if (!out) return ULPPM_E_ARG;
-  *out = nullptr;
-  if (n_points <= 0 || n_points > 2147483647LL) return ULPPM_E_ARG;
-  if (max_family == 0) max_family = 152;
-  if (max_family < 8 || max_family > 1024) return ULPPM_E_ARG;
-  ctx = new ulppm_ctx();
-  ctx->stream = (hipStream_t)hip_stream;
+}  // extern "C"
+
+namespace {
+
+// Capacities of a context for n points and max_family members per family.
+// Returns false where a bond or candidate slot would not fit an int32.
+bool size_context(ulppm_ctx* ctx, int64_t n_points, int max_family) {
   ctx->cap_n = n_points;
   ctx->max_f = max_family;
   ctx->max_cells = n_points * 2 + 4096;
   ctx->bond_cap = n_points * (int64_t)max_family;
   ctx->max_c = ((max_family * 3 / 2) + 63) / 64 * 64;
-  if (ctx->bond_cap > 2147483647LL || n_points * (int64_t)ctx->max_c > 2147483647LL) {
-    delete ctx;
-    return ULPPM_E_ARG;   // bond slots are int32
-  }
-  const int64_t n = n_points;
   ctx->part_cap = kPartGather + 3 * 4096 + 64;
-  ctx->scan_cap = (std::max<int64_t>(n + 1, ctx->max_cells) + kScanChunk - 1) / kScanChunk + 1;
-  hipError_t e = hipSuccess;
-  auto A = [&](void** p, size_t bytes) {
-    if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 8);
-  };
+  ctx->scan_cap = (std::max<int64_t>(n_points + 1, ctx->max_cells) + kScanChunk - 1) / kScanChunk + 1;
+  return ctx->bond_cap <= 2147483647LL && n_points * (int64_t)ctx->max_c <= 2147483647LL;
+}
+
+// Every scratch buffer of a context, in order: A(&pointer, bytes) places it
+// (hipMalloc for ulppm_create, slices of the static array for
+// ulppm_forces_static).
+template <class Alloc>
+void context_buffers(ulppm_ctx* ctx, Alloc&& A) {
+  const int64_t n = ctx->cap_n;
   A((void**)&ctx->x, sizeof(double) * 3 * n);
   A((void**)&ctx->vh, sizeof(double) * 3 * n);
   A((void**)&ctx->vol_n, sizeof(double) * n);
@@ -3711,6 +3710,43 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
   A((void**)&ctx->ctr, sizeof(unsigned long long) * C_NCOUNT * kStripes);
   A((void**)&ctx->ctr_sum, sizeof(unsigned long long) * C_NCOUNT);
   A((void**)&ctx->E, sizeof(double) * 3);
+}
+
+// The bond kernel's dynamic LDS may exceed the default cap for large max_family.
+void set_bond_lds_limits(int max_family) {
+  for (const void* k : {(const void*)k_bond_mx<double, false, kBondThreads>,
+                        (const void*)k_bond_mx<double, false, kBondThreads, 3>,
+                        (const void*)k_bond_mx<double, true, kBondThreads>,
+                        (const void*)k_bond_mx<double, false, kWave>,
+                        (const void*)k_bond_mx<double, false, kWave, 3>})
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, false));
+  for (const void* k : {(const void*)k_bond_mx<float, false, kBondThreads>,
+                        (const void*)k_bond_mx<float, true, kBondThreads>,
+                        (const void*)k_bond_mx<float, false, kWave>})
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, true));
+}
+
+}  // namespace
+
+extern "C" {
+
+int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hip_stream) {
+  ulppm_ctx* ctx = nullptr;
+  if (!out) return ULPPM_E_ARG;
+  *out = nullptr;
+  if (n_points <= 0 || n_points > 2147483647LL) return ULPPM_E_ARG;
+  if (max_family == 0) max_family = 152;
+  if (max_family < 8 || max_family > 1024) return ULPPM_E_ARG;
+  ctx = new ulppm_ctx();
+  ctx->stream = (hipStream_t)hip_stream;
+  if (!size_context(ctx, n_points, max_family)) {
+    delete ctx;
+    return ULPPM_E_ARG;   // bond slots are int32
+  }
+  hipError_t e = hipSuccess;
+  context_buffers(ctx, [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 8);
+  });
   if (e != hipSuccess) {
     ulppm_destroy(ctx);
     return ULPPM_E_HIP;
@@ -3725,17 +3761,7 @@ int ulppm_create(ulppm_ctx** out, int64_t n_points, int32_t max_family, void* hi
     ulppm_destroy(ctx);
     return ULPPM_E_HIP;
   }
-  // the bond kernel's dynamic LDS may exceed the default cap for large max_family
-  for (const void* k : {(const void*)k_bond_mx<double, false, kBondThreads>,
-                        (const void*)k_bond_mx<double, false, kBondThreads, 3>,
-                        (const void*)k_bond_mx<double, true, kBondThreads>,
-                        (const void*)k_bond_mx<double, false, kWave>,
-                        (const void*)k_bond_mx<double, false, kWave, 3>})
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, false));
-  for (const void* k : {(const void*)k_bond_mx<float, false, kBondThreads>,
-                        (const void*)k_bond_mx<float, true, kBondThreads>,
-                        (const void*)k_bond_mx<float, false, kWave>})
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, true));
+  set_bond_lds_limits(max_family);
   if (hipGetLastError() != hipSuccess) {
     ulppm_destroy(ctx);
     return ULPPM_E_HIP;
@@ -3806,9 +3832,13 @@ int ulppm_build_families(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_param
   return ULPPM_OK;
 }
 
-int ulppm_forces(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, double dt_inc, double* f[3],
-                 double* T_out[3], ulppm_report* rep) {
-  if (!ctx) return ULPPM_E_ARG;
+}  // extern "C"
+
+namespace {
+
+// Algorithm 1 alone at the current state (ulppm_forces, ulppm_forces_static).
+int forces_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, double dt_inc, double* f[3],
+                double* T_out[3], ulppm_report* rep) {
   int rc = check_state(ctx, S);
   if (rc) return rc;
   if ((rc = check_params(ctx, p))) return rc;
@@ -3842,6 +3872,98 @@ int ulppm_forces(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, do
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return ULPPM_OK;
+}
+
+// Scratch of ulppm_forces_static: one file-scope array per device, holding
+// the buffers of a context for kStaticPoints points and kStaticFamily
+// members per family.  Host code never uses the array's name (a host-side
+// stand-in); it uses the device address hipGetSymbolAddress returns.
+constexpr int64_t kStaticPoints = ULPPM_STATIC_MAX_POINTS;
+constexpr int kStaticFamily = ULPPM_STATIC_MAX_FAMILY;
+constexpr size_t kStaticAlign = 256;
+constexpr size_t kStaticBytes = 16u << 20;   // 16 MiB (15.4 MiB used); checked against the buffer list at set-up
+constexpr int kStaticDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+struct StaticSlot {
+  ulppm_ctx ctx;          // buffers sliced from this device's scratch array
+  bool ready = false;
+};
+StaticSlot g_static[kStaticDevices];
+std::mutex g_static_mu;
+
+// Set-up on the current device, once: the array's device address, the
+// context's buffers sliced from it (256-byte aligned), the bond kernel's LDS
+// limits and zeroed energies.  Returns the context or null (code in *rc).
+ulppm_ctx* static_context(hipStream_t stream, int* rc) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kStaticDevices) {
+    *rc = dev >= kStaticDevices ? ULPPM_E_ARG : ULPPM_E_HIP;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticSlot& sl = g_static[dev];
+  ulppm_ctx* ctx = &sl.ctx;
+  if (!sl.ready) {
+    unsigned char* base = nullptr;
+    if (hipGetSymbolAddress((void**)&base, HIP_SYMBOL(scratch)) != hipSuccess || !base) {
+      *rc = ULPPM_E_HIP;
+      return nullptr;
+    }
+    if (!size_context(ctx, kStaticPoints, kStaticFamily)) {
+      *rc = ULPPM_E_ARG;
+      return nullptr;
+    }
+    size_t off = 0;
+    bool fits = true;
+    context_buffers(ctx, [&](void** p, size_t bytes) {
+      off = (off + kStaticAlign - 1) / kStaticAlign * kStaticAlign;
+      if (off + bytes > kStaticBytes) fits = false;
+      *p = fits ? (void*)(base + off) : nullptr;
+      off += bytes;
+    });
+    if (!fits) {
+      *rc = ULPPM_E_HIP;      // the array is smaller than the buffer list: a build error
+      return nullptr;
+    }
+    ctx->have_events = false;
+    set_bond_lds_limits(kStaticFamily);
+    k_fill<double><<<1, 64, 0, stream>>>(ctx->E, 3, 0.0);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
+      *rc = ULPPM_E_HIP;
+      return nullptr;
+    }
+    sl.ready = true;
+  }
+  ctx->stream = stream;
+  ctx->contact = ContactDev{};
+  ctx->hist_n = 0;
+  *rc = ULPPM_OK;
+  return ctx;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ulppm_forces(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, double dt_inc, double* f[3],
+                 double* T_out[3], ulppm_report* rep) {
+  if (!ctx) return ULPPM_E_ARG;
+  return forces_impl(ctx, S, p, dt_inc, f, T_out, rep);
+}
+
+int ulppm_forces_static(const ulppm_state* S, const ulppm_params* p, double dt_inc, double* f[3],
+                        double* T_out[3], ulppm_report* rep, void* hip_stream) {
+  if (!S || S->n <= 0 || S->n > kStaticPoints) return ULPPM_E_ARG;
+  int rc = ULPPM_OK;
+  ulppm_ctx* ctx = static_context((hipStream_t)hip_stream, &rc);
+  if (!ctx) return rc;
+  return forces_impl(ctx, S, p, dt_inc, f, T_out, rep);
 }
 
 int ulppm_init_state(ulppm_ctx* ctx, ulppm_state* S, const ulppm_params* p, double ocr) {

@@ -63,7 +63,7 @@ EXPORTS = ["ulppm_create", "ulppm_destroy", "ulppm_last_error", "ulppm_init_stat
            "ulppm_build_families", "ulppm_forces", "ulppm_step", "ulppm_reset_energy", "ulppm_adjoint_reserve",
            "ulppm_adjoint_step", "ulppm_adjoint_init", "ulppm_selfcheck_tail", "ulppm_set_contact",
            "ulppm_history_reserve", "ulppm_history_export", "ulppm_history_import",
-           "ulppm_adjoint_step_bond_history"]
+           "ulppm_adjoint_step_bond_history", "ulppm_forces_static"]
 
 _lib = None
 
@@ -93,6 +93,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                        C.c_int64, C.POINTER(C.c_int64)]
     L.ulppm_forces.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.c_double, C.POINTER(_dp),
                                C.POINTER(_dp), C.POINTER(Report)]
+    L.ulppm_forces_static.argtypes = [C.POINTER(State), C.POINTER(Params), C.c_double, C.POINTER(_dp),
+                                      C.POINTER(_dp), C.POINTER(Report), vp]
     L.ulppm_step.argtypes = [vp, C.POINTER(State), C.POINTER(Params), C.c_int32, C.POINTER(Report)]
     L.ulppm_reset_energy.argtypes = [vp]
     L.ulppm_adjoint_reserve.argtypes = [vp]
@@ -388,6 +390,28 @@ class Context:
         c0, ca = S0.cstruct(), adj0.cstruct()
         self._check(self.L.ulppm_adjoint_init(self.h, C.byref(c0), C.byref(p), float(ocr), C.byref(ca),
                                               C.c_void_p(s_bar.data_ptr()), C.c_void_p(theta_bar.data_ptr())))
+
+
+STATIC_MAX_POINTS, STATIC_MAX_FAMILY = 2048, 128
+
+
+def forces_static(S: DeviceState, p: Params, dt_inc: float, f, T=None, stream=None) -> dict:
+    """ulppm_forces_static: Algorithm 1 with no context and no device
+    allocation.  f (3, n) and, if given, T (3, >= n_bonds) are caller-owned
+    float64 device tensors that receive the nodal forces and force states."""
+    import torch
+    L = load_library()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    fp = (_dp * 3)(*[C.cast(f[c].data_ptr(), _dp) for c in range(3)])
+    Tp = (_dp * 3)(*[C.cast(T[c].data_ptr(), _dp) for c in range(3)]) if T is not None else None
+    rep = Report()
+    cs = S.cstruct()
+    rc = L.ulppm_forces_static(C.byref(cs), C.byref(p), float(dt_inc), fp, Tp, C.byref(rep),
+                               C.c_void_p(stream.cuda_stream))
+    if rc != 0:
+        raise UlppmError(rc, "ulppm_forces_static failed")
+    return rep.as_dict()
 
 
 def selfcheck_tail(p: Params, seed: int = 0, n_cases: int = 40):
