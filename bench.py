@@ -35,6 +35,16 @@ throughput and gather phase, the kernel that adds the contact forces.
 "plane": the plane-strain column P1 (512 x 1024 points in the x-z plane,
 families of ~28), its throughput and bond-kernel time.  "history": the
 workload with the history carried on the bonds (ULPPM_HISTORY_BOND).
+"eq51": the workload with the force state of Eq. 51 as printed.
+"full_run": the workload as defined, 2000 steps from rest for seeds 1, 2 and
+3 (suction drawn per seed), with the energy balance of Eq. 69 checked after
+every 100 steps: time per step over the run and in windows, candidate
+rebuilds, plastic fraction, largest family and the final energy residual.
+
+The roofline object also carries the HBM side of the same kernel:
+achieved_gbs = traffic / average launch duration and hbm_frac = that over
+8 TB/s, where traffic is the counter-measured byte count of the committed
+profile (null when the kernel source changed since).
 """
 import argparse
 import hashlib
@@ -48,7 +58,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FLOPS_PER_TEST = 8.0
-FLOPS_PER_MEMBER = 43.0
+FLOPS_PER_MEMBER_SUMS = 34.0      # shape tensor, gradient numerator, volume (Eqs. 23, 25, 55, 57)
+FLOPS_PER_MEMBER_CONJ = 9.0       # the conjugate force-state sum (pass 2)
+FLOPS_PER_MEMBER = FLOPS_PER_MEMBER_SUMS + FLOPS_PER_MEMBER_CONJ
 FLOPS_PER_BOND = 250.0
 PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64 (and FP32 without packing)
 PEAK_HBM_GBS = 8000.0
@@ -132,6 +144,76 @@ def run_column(ulppm, col, precision, warmup, steps, timed=True, contact=None, m
     return G, rep, ms, prm.dt
 
 
+def full_run(ulppm, cfg_name, seeds, nsteps, chunk, max_family):
+    """The workload as defined: `nsteps` steps from rest per seed, in calls of
+    `chunk` steps with the energy balance of Eq. 69 checked after each call
+    (from the first call's end, past step 40).  A family that outgrows
+    `max_family` restarts the seed at the default capacity."""
+    import torch
+    from paper_2203_05562_amd import inputs
+    cfg = inputs.CONFIGS[cfg_name]
+    runs = []
+    tot_bonds, tot_ms = 0, 0.0
+    for seed in seeds:
+        col = inputs.make_column(cfg, seed=seed)
+        cap = max_family
+        while True:
+            G = ulppm.column_state(col, "cuda:0")
+            prm = ulppm.make_params(col["params"], energy_check=1, energy_tol=1e-2, timing=1)
+            ctx = ulppm.Context(col["n"], max_family=cap)
+            ctx.init_state(G, prm, col["params"]["ocr"])
+            prm.dt = 0.5 * ctx.dt_crit(G, prm)
+            stream = torch.cuda.current_stream()
+            chunks, status = [], "ok"
+            try:
+                for c in range(nsteps // chunk):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    rep = ctx.step(G, prm, chunk)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    chunks.append((e0.elapsed_time(e1), rep))
+            except ulppm.UlppmError as e:
+                if e.code == -2 and cap != 0:
+                    log(f"[gpu] full run seed {seed}: families outgrew {cap}; restarting at the default capacity")
+                    cap = 0
+                    del ctx, G
+                    continue
+                status = str(e)
+            break
+        ms = [c[0] for c in chunks]
+        reps = [c[1] for c in chunks]
+        bonds = sum(r["n_bond_updates"] for r in reps)
+        last = reps[-1] if reps else {}
+        E = (last.get("W_int", 0.0), last.get("W_ext", 0.0), last.get("W_kin", 0.0))
+        emax = max(abs(v) for v in E) or 1.0
+
+        def window(k):
+            return round(ms[k] / chunk, 4) if k < len(ms) else None
+
+        done = len(ms) * chunk
+        runs.append(dict(seed=seed, suction_kpa=round(col["suction_kpa"], 3), steps=done, status=status,
+                         ms_per_step=round(sum(ms) / max(done, 1), 4),
+                         window_ms_per_step={f"{k * chunk}-{(k + 1) * chunk}": window(k)
+                                             for k in (0, nsteps // chunk // 2 - 1, nsteps // chunk - 1)},
+                         bond_ms_per_step=round(sum(r["t_bond_ms"] for r in reps) / max(done, 1), 4),
+                         bond_updates_per_s=bonds / (sum(ms) * 1e-3) if ms else None,
+                         rebuilds=sum(r["n_rebuilds"] for r in reps),
+                         plastic_fraction=sum(r["n_plastic"] for r in reps) / max(bonds, 1),
+                         largest_family=max((r["max_family"] for r in reps), default=0),
+                         max_family=cap or 152,
+                         energy_residual=abs(E[0] + E[2] - E[1]) / emax, W=E))
+        log(f"[gpu] full run: {runs[-1]}")
+        tot_bonds += bonds
+        tot_ms += sum(ms)
+        del ctx, G
+        torch.cuda.empty_cache()
+    return dict(workload=f"{cfg_name}: {cfg.nx}x{cfg.ny}x{cfg.nz} column, {nsteps} steps from rest per seed, "
+                         f"Eq. 69 checked every {chunk} steps", seeds=list(seeds),
+                value=tot_bonds / (tot_ms * 1e-3) if tot_ms else None, unit="bond-updates/s", runs=runs)
+
+
 def rel_l2(a, b):
     import torch
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
@@ -156,6 +238,10 @@ def main():
     ap.add_argument("--no-history", action="store_true", help="skip the bond-history companion run")
     ap.add_argument("--no-standard", action="store_true",
                     help="skip the companion run of the standard (full-horizon) correspondence model")
+    ap.add_argument("--full-steps", type=int, default=2000,
+                    help="steps per seed of the full-run companion (0 skips it)")
+    ap.add_argument("--full-seeds", default="1,2,3")
+    ap.add_argument("--no-eq51", action="store_true", help="skip the Eq. 51 companion run")
     ap.add_argument("--max-family", type=int, default=128,
                     help="family capacity of the main run's context (0: the library default, 152); a run whose "
                          "families outgrow it is repeated with the default")
@@ -196,10 +282,18 @@ def main():
                         FLOPS_PER_BOND * bonds) / args.steps
     achieved = flops_per_launch / t_bond / 1e12
     traffic = measured_traffic(args.config, args.precision)
+    gbs = traffic / t_bond / 1e9 if traffic else None
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_VALU_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP64_VALU_TFLOPS, 4), traffic=traffic,
                     kernel="k_bond_mx", avg_launch_ms=round(t_bond * 1e3, 4),
-                    flops_per_launch=flops_per_launch)
+                    flops_per_launch=flops_per_launch,
+                    flops_per_unit=dict(test=FLOPS_PER_TEST, member_sums=FLOPS_PER_MEMBER_SUMS,
+                                        member_conjugate_sum=FLOPS_PER_MEMBER_CONJ, bond=FLOPS_PER_BOND),
+                    frac_without_conjugate_sum=round(
+                        (flops_per_launch - FLOPS_PER_MEMBER_CONJ * rep["n_triples"] / args.steps) / t_bond / 1e12
+                        / PEAK_FP64_VALU_TFLOPS, 4),
+                    achieved_gbs=round(gbs, 1) if gbs else None,
+                    hbm_frac=round(gbs / PEAK_HBM_GBS, 4) if gbs else None)
     phases = {k: round(rep[f"t_{k}_ms"] / max(launches, 1), 4) for k in ("predict", "family", "kin", "bond", "gather")}
     out = dict(metric="bond-updates/s per Newmark step", value=value, unit="bond-updates/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps, higher_is_better=True,
@@ -241,7 +335,10 @@ def main():
                               sites=int(sub["n"][0] * sub["n"][1] * sub["n"][2]), mu_f=sub["mu_f"],
                               delta_c=sub["delta_c"], cs=sub["cs"],
                               gather_ms=round(repc["t_gather_ms"] / lc, 4),
-                              gather_ms_without=phases["gather"])
+                              gather_ms_without=phases["gather"],
+                              phase_ms={k: round(repc[f"t_{k}_ms"] / lc, 4)
+                                        for k in ("predict", "family", "kin", "bond", "gather")},
+                              rebuilds=repc["n_rebuilds"], largest_family=repc["max_family"])
         log(f"[gpu] contact: {out['contact']}")
         del Gc
         torch.cuda.empty_cache()
@@ -279,6 +376,20 @@ def main():
         log(f"[gpu] standard: {out['standard']}")
         del Gs
         torch.cuda.empty_cache()
+    if not args.no_eq51:
+        # the force state of Eq. 51 as printed (stable over this short window from rest)
+        Ge, repe, mse, _, cape = run_cap(col, force_mode=ulppm.ULPPM_FORCE_EQ51)
+        le = max(repe["timed_steps"], 1)
+        out["eq51"] = dict(value=repe["n_bond_updates"] / (mse * 1e-3), ms_per_step=mse / args.steps,
+                           max_family=cape or 152,
+                           phase_ms={k: round(repe[f"t_{k}_ms"] / le, 4)
+                                     for k in ("predict", "family", "kin", "bond", "gather")})
+        log(f"[gpu] eq51: {out['eq51']}")
+        del Ge
+        torch.cuda.empty_cache()
+    if args.full_steps > 0 and args.precision == "fp64":
+        out["full_run"] = full_run(ulppm, args.config, [int(v) for v in args.full_seeds.split(",")],
+                                   args.full_steps, 100, max_family)
     if args.adjoint_config:
         from paper_2203_05562_amd.measure import adjoint_cost
         out["adjoint"] = adjoint_cost(args.adjoint_config, args.adjoint_steps, args.adjoint_every, "fp64")

@@ -144,6 +144,7 @@ typedef struct {
   double t_bond_ms;             /* the bond kernel alone */
   double t_gather_ms;
   double t_kin_ms;              /* point kinematics before the bond kernel */
+  int64_t n_rebuilds;           /* candidate-list rebuilds (a point moved half the skin), summed */
 } ulppm_report;
 
 /* Create a context for up to n_points points and max_family members per family

@@ -80,7 +80,7 @@ constexpr int64_t kPartGather = 10240;  // gather energy partials, 3 per block
 // Device counters, zeroed at the start of every API call.
 enum Ctr {
   C_DEGEN = 0, C_PLASTIC, C_MAXNEWTON, C_NOCONV, C_TESTS, C_TRIPLES, C_OVERFLOW,
-  C_NONFINITE, C_MAXFAM, C_BONDSUM, C_NCOUNT = 16
+  C_NONFINITE, C_MAXFAM, C_BONDSUM, C_REBUILD, C_NCOUNT = 16
 };
 constexpr int kStripes = 256;       // each device counter is striped over this many addresses
 constexpr int kTimedSteps = 256;    // steps per call covered by phase timings
@@ -657,8 +657,9 @@ __global__ __launch_bounds__(256) void k_cand_rev(int64_t n, int max_c, const in
 }
 
 __global__ void k_save_ref(const double* __restrict__ x, double* __restrict__ xref, int64_t m,
-                           const int32_t* __restrict__ gate) {
+                           unsigned long long* __restrict__ ctr, const int32_t* __restrict__ gate) {
   if (*gate == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr_add(ctr, C_REBUILD, 1ull);   // one candidate rebuild
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
     xref[e] = x[e];
 }
@@ -1599,25 +1600,39 @@ struct Mma<float> {
   static __device__ __forceinline__ int row(int q, int r) { return 4 * q + r; }
 };
 
-constexpr int kTileBatch = 4;     // 16-row tiles a wave carries through one sweep over the members
+#ifndef ULPPM_TILE_BATCH
+#define ULPPM_TILE_BATCH 4
+#endif
+constexpr int kTileBatch = ULPPM_TILE_BATCH;   // 16-row tiles a wave carries through one sweep over the members
+static_assert(kTileBatch >= 1 && kTileBatch <= 4, "tile_slots dispatches 1 to 4 tiles");
+
+// Run f(t0, NB) for the NB = min(nb, kTileBatch) tile slots t0, t0 + waves, ...
+// left to one wave, NB a compile-time constant.
+template <class F>
+__device__ __forceinline__ void tile_slots(int nb, int t0, F&& f) {
+  if (kTileBatch >= 4 && nb >= 4) f(t0, std::integral_constant<int, 4>{});
+  else if (kTileBatch >= 3 && nb >= 3) f(t0, std::integral_constant<int, 3>{});
+  else if (kTileBatch >= 2 && nb >= 2) f(t0, std::integral_constant<int, 2>{});
+  else f(t0, std::integral_constant<int, 1>{});
+}
 constexpr size_t kCuLds = 160 * 1024;       // LDS of one CU
 constexpr size_t kBondStaticLds = 512;      // the bond kernel's static LDS, rounded up
 
-template <class Acc>
-__host__ __device__ constexpr size_t bond_mx_member_bytes() {
-  // FP64 member records begin with (zeta, V) in FP64 and serve the exact
-  // membership test directly; the mixed records are FP32, so (zeta, V) is
-  // kept in FP64 beside them
-  return (sizeof(Acc) == 8 ? 0 : sizeof(Quad<double>)) + 8 * sizeof(Acc) + 16 * sizeof(Acc);
-}
+// Member slots of the staged records: the family padded to whole 16-row
+// tiles plus the quad the member loop loads one step ahead.  Padding slots
+// hold positions at infinity (no membership) and zero features.
+__host__ __device__ constexpr int bond_mx_slots(int max_f) { return ((max_f + 15) & ~15) + 4; }
 template <class Acc>
 __host__ __device__ constexpr size_t bond_mx_lds_bytes(int max_f) {
-  // the family's working set; the closing reduction reuses it for 8 doubles per thread
-  return (size_t)max_f * bond_mx_member_bytes<Acc>() +
-                 (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long) >
+  // (x_k, V_k) in FP64 for the membership test and the member record (zeta_ik,
+  // V_k, ydot_ik, 1) in the sum type per slot; the 16 sums and the membership
+  // bits per member.  The closing reduction reuses the space for 8 doubles
+  // per thread.
+  return (size_t)bond_mx_slots(max_f) * (sizeof(Quad<double>) + 8 * sizeof(Acc)) +
+                 (size_t)max_f * (16 * sizeof(Acc) + ((max_f + 63) / 64) * sizeof(unsigned long long)) >
              8 * kBondThreads * sizeof(double)
-         ? (size_t)max_f * bond_mx_member_bytes<Acc>() +
-               (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long)
+         ? (size_t)bond_mx_slots(max_f) * (sizeof(Quad<double>) + 8 * sizeof(Acc)) +
+               (size_t)max_f * (16 * sizeof(Acc) + ((max_f + 63) / 64) * sizeof(unsigned long long))
          : 8 * kBondThreads * sizeof(double);
 }
 
@@ -1653,15 +1668,13 @@ void k_bond_mx(BondArgs A, DevParams P) {
   const int nf = (int)(A.row[i + 1] - b0);
   const int nw = (mf + 63) / 64;                   // membership words per row
   // (x_k, V_k) in FP64 for the membership test of Eq. 22, which compares
-  // |x_k - x_j| from the absolute positions: the head of the FP64 member
-  // record (whose features take zeta_ik = x_k - x_i on the fly), or an array
-  // of its own beside the FP32 records (which hold zeta_ik)
+  // |x_k - x_j| from the positions, beside the member records that hold
+  // zeta_ik (formed in FP64, then rounded to the sum type)
   constexpr bool kF64 = sizeof(Acc) == 8;
-  constexpr int kZs = kF64 ? 2 : 1;                                    // Quad stride of (x, V)
+  const int mfp = bond_mx_slots(mf);
   Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);
-  Acc* sR = kF64 ? reinterpret_cast<Acc*>(smem_raw)
-                 : reinterpret_cast<Acc*>(sX + mf);                    // 8 per member: x or zeta, V, ydot, 1
-  Acc* sKN = sR + 8 * (size_t)mf;                                      // 16 per member: K, N, Vs, then M_j
+  Acc* sR = reinterpret_cast<Acc*>(sX + mfp);                          // 8 per slot: zeta, V, ydot, 1
+  Acc* sKN = sR + 8 * (size_t)mfp;                                     // 16 per member: K, N, Vs, then M_j
   unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)mf);
   unsigned short* sq = reinterpret_cast<unsigned short*>(sb);
   Quad<TS>* const T4 = reinterpret_cast<Quad<TS>*>(A.T);
@@ -1672,13 +1685,6 @@ void k_bond_mx(BondArgs A, DevParams P) {
   const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
   const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
 
-  // Per-point values of this step (point kinematics), fetched while the family is staged.
-  const double Sr_i = A.Sr_out[i], Pn_i = A.pk[i], iVh = A.pk[n + i];
-  const double s_i = A.s[i];
-  double sig_i[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) sig_i[k] = A.sig[k][i];
-  const double pc_i = A.pc[i];
   if (tid == 0) s_d2 = P.d2;
 
   // Stage the family of i: x_k and V_k (FP64, for the exact predicate; the
@@ -1691,30 +1697,31 @@ void k_bond_mx(BondArgs A, DevParams P) {
     const double Vk = pa.w;
     const double y0 = pb.x - vi0, y1 = pb.y - vi1, y2 = pb.z - vi2;
     Acc* rec = sR + 8 * (size_t)m;
-    if constexpr (kF64) {
-      rec[0] = pa.x; rec[1] = pa.y; rec[2] = pa.z;
-    } else {
-      sX[m] = Quad<double>{{pa.x, pa.y, pa.z, Vk}};
-      rec[0] = (Acc)(pa.x - xi0); rec[1] = (Acc)(pa.y - xi1); rec[2] = (Acc)(pa.z - xi2);
-    }
+    sX[m] = Quad<double>{{pa.x, pa.y, pa.z, Vk}};
+    rec[0] = (Acc)(pa.x - xi0); rec[1] = (Acc)(pa.y - xi1); rec[2] = (Acc)(pa.z - xi2);
     rec[3] = (Acc)Vk;
     rec[4] = (Acc)y0; rec[5] = (Acc)y1; rec[6] = (Acc)y2; rec[7] = (Acc)1;
   }
-  __syncthreads();
-  const double d2 = s_d2;
   const int ntile = (nf + 15) >> 4;
   const int nks = (nf + 3) >> 2;
   const int nblk = (nks + 15) >> 4;               // bit words per row written by pass 1
+  // padding slots up to whole tiles and the look-ahead quad: positions at
+  // infinity fail every membership test (inf - x = inf, inf - inf = NaN), and
+  // zero features add nothing, so the member loop needs no range checks
+  for (int m = nf + tid; m < max(16 * ntile, 4 * nks + 4); m += kBondThreads) {
+    sX[m] = Quad<double>{{INFINITY, INFINITY, INFINITY, 0.0}};
+    Acc* rec = sR + 8 * (size_t)m;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rec[q] = (Acc)0;
+  }
+  __syncthreads();
+  const double d2 = s_d2;
 
   // ---- pass 1: membership matrix x features on the matrix cores.  Tiles
   // past the family (and rows past nf) carry zero operands; everything in
   // the member loop is branch-free so that tests and products interleave.
   {
     const int fa = feat_a(r16), fb = feat_b(r16);
-    // the FP64 records hold x_k: a position feature is x_k - x_i, rounded as
-    // the relative position zeta_ik everywhere else
-    const double oa = kF64 && fa < 3 ? (fa == 0 ? xi0 : fa == 1 ? xi1 : xi2) : 0.0;
-    const double ob = kF64 && fb < 3 ? (fb == 0 ? xi0 : fb == 1 ? xi1 : xi2) : 0.0;
     // NB tile slots t0, t0 + kBondWaves, ... of one wave, all inside the family
     auto tiles = [&](int t0, auto nbc) {
       constexpr int NB = decltype(nbc)::value;
@@ -1727,29 +1734,24 @@ void k_bond_mx(BondArgs A, DevParams P) {
       for (int b = 0; b < NB; ++b) {
         jrow[b] = (t0 + kBondWaves * b) * 16 + r16;
         jv[b] = jrow[b] < nf;
-        const Quad<double> q = sX[kZs * (jv[b] ? jrow[b] : 0)];
+        const Quad<double> q = sX[jrow[b]];          // a padding slot past the family
         xj[b][0] = q.v[0]; xj[b][1] = q.v[1]; xj[b][2] = q.v[2];
         acc[b] = V4{0, 0, 0, 0};
         piece[b] = 0u;
       }
       // member data of the next step is loaded one step ahead
-      bool kv = q4 < nf;
-      Quad<double> xk = sX[kZs * (kv ? q4 : 0)];
-      Acc ra = sR[8 * (size_t)(kv ? q4 : 0) + fa] - (Acc)oa, rb = sR[8 * (size_t)(kv ? q4 : 0) + fb] - (Acc)ob,
-          rv = sR[8 * (size_t)(kv ? q4 : 0) + 3];
+      Quad<double> xk = sX[q4];
+      Acc ra = sR[8 * (size_t)q4 + fa], rb = sR[8 * (size_t)q4 + fb], rv = sR[8 * (size_t)q4 + 3];
       for (int ks = 0; ks < nks; ++ks) {
         const int k1 = 4 * (ks + 1) + q4;
-        const bool kv1 = k1 < nf;
-        const int kk1 = kv1 ? k1 : 0;
-        const Quad<double> xk1 = sX[kZs * kk1];
-        const Acc* rec1 = sR + 8 * (size_t)kk1;
-        const Acc ra1 = rec1[fa] - (Acc)oa, rb1 = rec1[fb] - (Acc)ob, rv1 = rec1[3];
-        const Acc fv = ra * rb * rv;
-        const Acc bval = kv ? fv : (Acc)0;
+        const Quad<double> xk1 = sX[k1];
+        const Acc* rec1 = sR + 8 * (size_t)k1;
+        const Acc ra1 = rec1[fa], rb1 = rec1[fb], rv1 = rec1[3];
+        const Acc bval = ra * rb * rv;
         const unsigned sbit = 1u << (ks & 15);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          const bool in = within(xj[b][0], xj[b][1], xj[b][2], xk.v[0], xk.v[1], xk.v[2], d2) & kv & jv[b];
+          const bool in = within(xj[b][0], xj[b][1], xj[b][2], xk.v[0], xk.v[1], xk.v[2], d2);
           piece[b] |= in ? sbit : 0u;
           acc[b] = MM::run(in ? (Acc)1 : (Acc)0, bval, acc[b]);
         }
@@ -1760,7 +1762,6 @@ void k_bond_mx(BondArgs A, DevParams P) {
             piece[b] = 0u;
           }
         }
-        kv = kv1;
         xk = xk1;
         ra = ra1; rb = rb1; rv = rv1;
       }
@@ -1776,16 +1777,19 @@ void k_bond_mx(BondArgs A, DevParams P) {
     };
     for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
       const int nb = (ntile - t0 + kBondWaves - 1) / kBondWaves;     // slots left for this wave
-      static_assert(kTileBatch == 4, "slot dispatch below");
-      if (nb >= 4) tiles(t0, std::integral_constant<int, 4>{});
-      else if (nb == 3) tiles(t0, std::integral_constant<int, 3>{});
-      else if (nb == 2) tiles(t0, std::integral_constant<int, 2>{});
-      else tiles(t0, std::integral_constant<int, 1>{});
+      tile_slots(nb, t0, tiles);
     }
   }
   __syncthreads();
 
-  // ---- per-bond tail: one lane per bond (i,j)
+  // ---- per-bond tail: one lane per bond (i,j); the per-point values of
+  // this step (point kinematics) are loaded here, not kept through pass 1
+  const double Sr_i = A.Sr_out[i], Pn_i = A.pk[i], iVh = A.pk[n + i];
+  const double s_i = A.s[i];
+  double sig_i[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sig_i[k] = A.sig[k][i];
+  const double pc_i = A.pc[i];
   double hs[6] = {0, 0, 0, 0, 0, 0}, hpc = 0.0, hw = 0.0;
   int n_deg = 0, n_pl = 0, n_nc = 0, n_trip = 0, mx = 0;
   for (int m = tid; m < nf; m += kBondThreads) {
@@ -1886,11 +1890,10 @@ void k_bond_mx(BondArgs A, DevParams P) {
                           sgb[5] * ixy + S11 * iyy + sgb[3] * iyz, sgb[5] * ixz + S11 * iyz + sgb[3] * izz,
                           sgb[4] * ixx + sgb[3] * ixy + S22 * ixz, sgb[4] * ixy + sgb[3] * iyy + S22 * iyz,
                           sgb[4] * ixz + sgb[3] * iyz + S22 * izz};
-    const Quad<double> zj = sX[kZs * m];
-    const double Vj = zj.v[3];
+    const double Vj = sX[m].v[3];
     if (P.force_mode == ULPPM_FORCE_EQ51) {
       // Eq. 51 as printed: T_ij = varpi (sigma_ij + Sr s 1) K_ij^{-1} zeta_ij.
-      const double zx = zj.v[0] - xi0, zy = zj.v[1] - xi1, zz = zj.v[2] - xi2;
+      const double zx = sR[8 * (size_t)m], zy = sR[8 * (size_t)m + 1], zz = sR[8 * (size_t)m + 2];
       T4[slot] = Quad<TS>{{(TS)(varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz)),
                            (TS)(varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz)),
                            (TS)(varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz)), (TS)0}};
@@ -1939,8 +1942,8 @@ void k_bond_mx(BondArgs A, DevParams P) {
           }
         }
       }
-      const Acc* zm = sR + 8 * (size_t)m;                          // x_k, V_k (FP64 record)
-      const Acc zx = zm[0] - xi0, zy = zm[1] - xi1, zz = zm[2] - xi2;
+      const Acc* zm = sR + 8 * (size_t)m;
+      const Acc zx = zm[0], zy = zm[1], zz = zm[2];
       const int64_t slot = b0 + m;
       const Acc t0 = a0 * zx + a1 * zy + a2 * zz, t1 = a3 * zx + a4 * zy + a5 * zz, t2 = a6 * zx + a7 * zy + a8 * zz;
       T4[slot] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
@@ -2004,10 +2007,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
     };
     for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
       const int nb = (ntile - t0 + kBondWaves - 1) / kBondWaves;
-      if (nb >= 4) tiles2(t0, std::integral_constant<int, 4>{});
-      else if (nb == 3) tiles2(t0, std::integral_constant<int, 3>{});
-      else if (nb == 2) tiles2(t0, std::integral_constant<int, 2>{});
-      else tiles2(t0, std::integral_constant<int, 1>{});
+      tile_slots(nb, t0, tiles2);
     }
   }
   n_deg = wave_sum_i(n_deg);
@@ -2356,10 +2356,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     };
     for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
       const int nb = (ntile - t0 + kBondWaves - 1) / kBondWaves;     // slots left for this wave
-      if (nb >= 4) tiles(t0, std::integral_constant<int, 4>{});
-      else if (nb == 3) tiles(t0, std::integral_constant<int, 3>{});
-      else if (nb == 2) tiles(t0, std::integral_constant<int, 2>{});
-      else tiles(t0, std::integral_constant<int, 1>{});
+      tile_slots(nb, t0, tiles);
     }
   }
   __syncthreads();
@@ -2668,10 +2665,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   };
   for (int t0 = wid; t0 < ntile; t0 += kBondWaves * kTileBatch) {
     const int nb = (ntile - t0 + kBondWaves - 1) / kBondWaves;
-    if (nb >= 4) tiles2(t0, std::integral_constant<int, 4>{});
-    else if (nb == 3) tiles2(t0, std::integral_constant<int, 3>{});
-    else if (nb == 2) tiles2(t0, std::integral_constant<int, 2>{});
-    else tiles2(t0, std::integral_constant<int, 1>{});
+    tile_slots(nb, t0, tiles2);
   }
   __syncthreads();
   double ox[3] = {0, 0, 0}, oy[3] = {0, 0, 0};
@@ -3291,7 +3285,7 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
   const unsigned cgrid = (unsigned)((n * ctx->max_c + 255) / 256);
   k_cand_rev<<<std::min<unsigned>(cgrid, 2048u), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->cand, ctx->ccnt,
                                                                        ctx->crev, ctx->ctr, gate);
-  k_save_ref<<<blocks_for(3 * n, 256, 4096), 256, 0, ctx->stream>>>(ctx->x, ctx->xref, 3 * n, gate);
+  k_save_ref<<<blocks_for(3 * n, 256, 4096), 256, 0, ctx->stream>>>(ctx->x, ctx->xref, 3 * n, ctx->ctr, gate);
   k_fill<int32_t><<<1, 64, 0, ctx->stream>>>(ctx->gate, 1, 0);
   HIPCHK(hipGetLastError());
   // the packed point records carry the positions the filter reads
@@ -3482,6 +3476,7 @@ void fill_report(ulppm_ctx* ctx, int64_t n, ulppm_report* rep, int64_t steps) {
   rep->max_family = (int64_t)ctx->h_ctr[C_MAXFAM];
   rep->steps = steps;
   rep->n_bond_updates = (int64_t)ctx->h_ctr[C_BONDSUM];
+  rep->n_rebuilds = (int64_t)ctx->h_ctr[C_REBUILD];
   rep->timed_steps = 0;
   rep->t_predict_ms = rep->t_family_ms = rep->t_bond_ms = rep->t_gather_ms = rep->t_kin_ms = 0.0;
 }

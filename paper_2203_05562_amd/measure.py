@@ -1,10 +1,12 @@
 """Accuracy and cost measurements of the library on one GPU, each printing
 one JSON line.
 
-    python -m paper_2203_05562_amd.measure mixed-error [--config C2] [--at 100,500,1000]
+    python -m paper_2203_05562_amd.measure mixed-error [--config C2] [--at 100,500,1000] [--no-floor]
         Mixed-precision run against the FP64 run of the same column from the
         same initial state: relative L2 errors of u, sigma and v at the given
-        step counts, and the time per step of each.
+        step counts, and the time per step of each; beside it the floor, an
+        FP64 run from initial positions moved by one ulp against the same
+        FP64 run.
 
     python -m paper_2203_05562_amd.measure adjoint-cost [--config C4] [--steps 50] [--every 25]
                                                         [--precision mixed]
@@ -22,6 +24,14 @@ one JSON line.
     python -m paper_2203_05562_amd.measure copy [--mib 1024]
         One device-to-device copy of a known size (a float64 tensor), the
         reference that scales the HBM byte counters of a profiler run.
+
+    python -m paper_2203_05562_amd.measure profile-summary --dir D [--kernel REGEX] [--skip-first]
+        Reads the database a rocprofv3 run wrote under D (kernel dispatches
+        of --kernel-trace, and/or the per-dispatch counters of --pmc) and
+        prints it as a JSON line: per kernel name the calls and the average /
+        min / max duration, and per counter the mean value per dispatch of
+        the kernels matching REGEX (the first dispatch left out with
+        --skip-first).  No GPU is used.
 """
 import argparse
 import json
@@ -38,17 +48,36 @@ def rel_l2(a, b):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
-def mixed_error(cfg_name: str, at):
+def mixed_error(cfg_name: str, at, floor: bool = True, max_family: int = 0):
+    """Mixed precision against FP64 from the same initial state, and (floor)
+    FP64 against FP64 from perturbed initial positions: moved by one FP64 ulp
+    in every coordinate (seeded signs), and rounded to FP32.  The first shows
+    the smooth sensitivity of the trajectory; the second also lets pairs near
+    |x_k - x_j| = delta change sides, as the positions of a mixed run do, and
+    so measures the floor that the discontinuous set decisions put under any
+    run perturbed at FP32 size."""
+    import numpy as np
     import torch
     from . import inputs, ulppm
     cfg = inputs.CONFIGS[cfg_name]
     col = inputs.make_column(cfg)
     n = col["n"]
     runs = {}
-    for name, prec in (("fp64", ulppm.ULPPM_FP64), ("mixed", ulppm.ULPPM_MIXED)):
-        G = ulppm.column_state(col, "cuda:0")
+    names = [("fp64", ulppm.ULPPM_FP64), ("mixed", ulppm.ULPPM_MIXED)]
+    if floor:
+        names += [("fp64_ulp", ulppm.ULPPM_FP64), ("fp64_x0f32", ulppm.ULPPM_FP64)]
+    for name, prec in names:
+        c = col
+        if name == "fp64_ulp":
+            sgn = np.random.default_rng(cfg.seed + 1000).choice([-1.0, 1.0], col["x0"].shape)
+            c = dict(col, x0=np.nextafter(col["x0"], col["x0"] + sgn))
+        elif name == "fp64_x0f32":
+            # the initial positions rounded to FP32: a perturbation of the size
+            # that FP32 arithmetic makes, taken once at the start
+            c = dict(col, x0=col["x0"].astype(np.float32).astype(np.float64))
+        G = ulppm.column_state(c, "cuda:0")
         prm = ulppm.make_params(col["params"], precision=prec)
-        ctx = ulppm.Context(n)
+        ctx = ulppm.Context(n, max_family=max_family)
         ctx.init_state(G, prm, col["params"]["ocr"])
         runs[name] = [G, prm, ctx, 0.0]
     dt = 0.5 * runs["fp64"][2].dt_crit(runs["fp64"][0], runs["fp64"][1])
@@ -63,9 +92,14 @@ def mixed_error(cfg_name: str, at):
             torch.cuda.synchronize()
             r[3] += time.perf_counter() - t0
         done = target
-        a, b = runs["mixed"][0], runs["fp64"][0]
-        row = dict(step=target, u_rel_l2=rel_l2(a["u"], b["u"]), sig_rel_l2=rel_l2(a["sig"], b["sig"]),
-                   v_rel_l2=rel_l2(a["v"], b["v"]), pc_rel_l2=rel_l2(a["pc"], b["pc"]))
+        b = runs["fp64"][0]
+        row = dict(step=target)
+        for name in runs:
+            if name == "fp64":
+                continue
+            a = runs[name][0]
+            row[name] = dict(u_rel_l2=rel_l2(a["u"], b["u"]), sig_rel_l2=rel_l2(a["sig"], b["sig"]),
+                             v_rel_l2=rel_l2(a["v"], b["v"]), pc_rel_l2=rel_l2(a["pc"], b["pc"]))
         log(row)
         out.append(row)
     return dict(kind="mixed-error", workload=f"{cfg_name}: {cfg.nx}x{cfg.ny}x{cfg.nz} column", points=n, dt=dt,
@@ -180,12 +214,51 @@ def adjoint_check(cfg_name: str, steps: int, every: int, precision: str = "fp64"
                 points=n, objective=float(J.detach()), seconds_forward_backward=round(t_adj, 2), checks=rows)
 
 
+def profile_summary(d: str, kernel: str, skip_first: bool):
+    """Kernel durations and per-dispatch counters from the SQLite database
+    (rocpd) that rocprofv3 writes by default under d."""
+    import glob
+    import os
+    import re
+    import sqlite3
+    out = dict(kind="profile-summary", dir=os.path.basename(os.path.normpath(d)), kernels={}, counters={})
+    rx = re.compile(kernel)
+    per = {}
+    for f in glob.glob(os.path.join(d, "**", "*.db"), recursive=True):
+        con = sqlite3.connect(f)
+        durs = {}
+        for name, dur, did in con.execute("select name, duration, dispatch_id from kernels"):
+            durs.setdefault(name, []).append((did, dur * 1e-6))
+        for name, v in durs.items():
+            ms = [x for _, x in sorted(v)]
+            out["kernels"][name] = dict(calls=len(ms), total_ms=sum(ms), avg_ms=sum(ms) / len(ms), min_ms=min(ms),
+                                        max_ms=max(ms))
+        q = ("select kernel_name, counter_name, dispatch_id, value, vgpr_count, accum_vgpr_count, sgpr_count, "
+             "lds_block_size, scratch_size from counters_collection")
+        for kn, cn, did, val, vg, ag, sg, lds, scr in con.execute(q):
+            if not rx.search(kn):
+                continue
+            e = per.setdefault((kn, cn), {}).setdefault(did, [0.0, (vg, ag, sg, lds, scr)])
+            e[0] += val
+    for (kn, cn), disp in per.items():
+        ids = sorted(disp)
+        if skip_first and len(ids) > 1:
+            ids = ids[1:]
+        vals = [disp[i][0] for i in ids]
+        vg, ag, sg, lds, scr = disp[ids[0]][1]
+        out["counters"].setdefault(kn, {})[cn] = dict(mean=sum(vals) / len(vals), dispatches=len(vals))
+        out["counters"][kn]["_resources"] = dict(vgpr=vg, agpr=ag, sgpr=sg, lds=lds, scratch=scr)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
     a = sub.add_parser("mixed-error")
     a.add_argument("--config", default="C2")
     a.add_argument("--at", default="100,500,1000")
+    a.add_argument("--no-floor", action="store_true", help="skip the FP64 run from one-ulp moved positions")
+    a.add_argument("--max-family", type=int, default=0)
     b = sub.add_parser("adjoint-cost")
     b.add_argument("--config", default="C4")
     b.add_argument("--steps", type=int, default=50)
@@ -198,7 +271,14 @@ def main(argv=None):
     d.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=1024)
+    e = sub.add_parser("profile-summary")
+    e.add_argument("--dir", required=True)
+    e.add_argument("--kernel", default=".")
+    e.add_argument("--skip-first", action="store_true")
     args = ap.parse_args(argv)
+    if args.what == "profile-summary":
+        print(json.dumps(profile_summary(args.dir, args.kernel, args.skip_first)), flush=True)
+        return
     import torch
     assert torch.cuda.is_available(), "measurements need a GPU"
     torch.cuda.set_device(0)
@@ -213,7 +293,7 @@ def main(argv=None):
     elif args.what == "adjoint-check":
         out = adjoint_check(args.config, args.steps, args.every, args.precision)
     elif args.what == "mixed-error":
-        out = mixed_error(args.config, [int(x) for x in args.at.split(",")])
+        out = mixed_error(args.config, [int(x) for x in args.at.split(",")], not args.no_floor, args.max_family)
     else:
         out = adjoint_cost(args.config, args.steps, args.every, args.precision)
     print(json.dumps(out), flush=True)

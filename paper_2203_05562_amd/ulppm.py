@@ -47,7 +47,7 @@ class Report(C.Structure):
                 ("n_triples", C.c_int64), ("max_family", C.c_int64), ("steps", C.c_int64),
                 ("n_bond_updates", C.c_int64), ("timed_steps", C.c_int64), ("t_predict_ms", C.c_double),
                 ("t_family_ms", C.c_double), ("t_bond_ms", C.c_double), ("t_gather_ms", C.c_double),
-                ("t_kin_ms", C.c_double)]
+                ("t_kin_ms", C.c_double), ("n_rebuilds", C.c_int64)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))

@@ -56,7 +56,7 @@ int main(void) {
          offsetof(ulppm_params, energy_tol), offsetof(ulppm_state, sig));
   printf("%zu %zu %zu %zu\n", offsetof(ulppm_state, fixed), offsetof(ulppm_report, steps),
          offsetof(ulppm_params, timing), offsetof(ulppm_report, t_gather_ms));
-  printf("%zu\n", offsetof(ulppm_report, t_kin_ms));
+  printf("%zu %zu\n", offsetof(ulppm_report, t_kin_ms), offsetof(ulppm_report, n_rebuilds));
   printf("%zu %zu %zu\n", sizeof(ulppm_contact), offsetof(ulppm_contact, spacing), offsetof(ulppm_contact, n));
   return 0;
 }
@@ -72,7 +72,7 @@ int main(void) {
            ulppm.Params.g.offset, ulppm.Params.newton_maxit.offset, ulppm.Params.energy_tol.offset,
            ulppm.State.sig.offset, ulppm.State.fixed.offset, ulppm.Report.steps.offset,
            ulppm.Params.timing.offset, ulppm.Report.t_gather_ms.offset, ulppm.Report.t_kin_ms.offset,
-           C.sizeof(ulppm.Contact), ulppm.Contact.spacing.offset, ulppm.Contact.n.offset]
+           ulppm.Report.n_rebuilds.offset, C.sizeof(ulppm.Contact), ulppm.Contact.spacing.offset, ulppm.Contact.n.offset]
     assert vals == exp
 
 

@@ -342,6 +342,35 @@ def test_single_plane_blows_up_on_both_sides(olib, gpu):
     assert ei.value.code == -5
 
 
+def test_energy_check_trips_at_five_critical_steps(olib, gpu):
+    """Eq. 69 checked by ulppm_step (energy_check): 40 steps at half the
+    critical step of Eq. 65 keep |W_int + W_kin - W_ext| within 1e-2 of the
+    largest energy on both sides, and the call returns OK; five more steps at
+    five times the critical step break the balance while the motion is still
+    finite, and the call returns ULPPM_E_ENERGY where the oracle's energies
+    break it the same way."""
+    say("energy check")
+    col, oprm, gprm, S, G, ctx = make_pair(olib, gpu, (8, 8, 16), seed=0)
+    gprm.energy_check = 1
+    gprm.energy_tol = 1e-2
+    E = np.zeros(3)
+    rc, E, st = olib.step(S, oprm, 40, E)
+    assert rc == 0 and abs(E[0] + E[2] - E[1]) <= 1e-2 * np.abs(E).max()
+    rep = ctx.step(G, gprm, 40)
+    assert abs(rep["W_int"] + rep["W_kin"] - rep["W_ext"]) <= 1e-2 * max(abs(rep["W_int"]), abs(rep["W_ext"]),
+                                                                         abs(rep["W_kin"]))
+    dtc = olib.dt_crit(S, oprm)
+    oprm.dt = 5.0 * dtc
+    gprm.dt = 5.0 * dtc
+    rc, E, st = olib.step(S, oprm, 5, E)
+    assert rc == 0 and np.all(np.isfinite(E))
+    assert abs(E[0] + E[2] - E[1]) > 1e-2 * np.abs(E).max()
+    with pytest.raises(gpu.UlppmError) as ei:
+        ctx.step(G, gprm, 5)
+    assert ei.value.code == -6
+    assert np.all(np.isfinite(G.to_arrays()["v"]))
+
+
 def test_candidate_rebuilds_inside_a_call(olib, gpu):
     """A column translating at several m/s moves more than half the candidate
     skin every few steps, so the candidate lists are rebuilt inside one
@@ -441,6 +470,32 @@ def test_C1_bench_configuration(olib, gpu):
         rep = ctx.step(G, gprm, 3)
         assert rep["n_bond_updates"] == st["n_bonds"] and rep["max_family"] <= 128
         compare_states(G.to_arrays(), S, tol, label=f"C1 precision {prec}")
+
+
+def test_C1_mixed_against_fp64_200_steps(gpu):
+    """Mixed precision on the 40 x 40 x 80 column (128,000 points, capacity
+    128) against the FP64 run from the same initial state after 200 steps:
+    u and sigma within 1e-4, v within 1e-3 relative L2.  The bars sit below
+    the floor that FP32-size perturbations of the input put under any run:
+    an FP64 run from initial positions rounded to FP32 differs from the FP64
+    run by u 2e-4, sigma 8e-5, v 1e-3 at step 200, because sub-horizon and
+    family sets (Eqs. 1, 22) change with the positions."""
+    say("C1 mixed against FP64, 200 steps")
+    col = inputs.make_column(inputs.CONFIGS["C1"])
+    out = {}
+    for prec in (gpu.ULPPM_FP64, gpu.ULPPM_MIXED):
+        G = gpu.column_state(col, "cuda:0")
+        prm = gpu.make_params(col["params"], precision=prec)
+        ctx = gpu.Context(col["n"], max_family=128)
+        ctx.init_state(G, prm, col["params"]["ocr"])
+        prm.dt = 0.5 * ctx.dt_crit(G, prm)
+        ctx.step(G, prm, 200)
+        out[prec] = G.to_arrays()
+        del ctx, G
+    a, b = out[gpu.ULPPM_MIXED], out[gpu.ULPPM_FP64]
+    errs = {k: rel_l2(a[k], b[k]) for k in ("u", "sig", "v", "pc")}
+    say("mixed vs fp64 after 200 steps", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert errs["u"] <= 1e-4 and errs["sig"] <= 1e-4 and errs["v"] <= 1e-3
 
 
 def test_C4_full_size_balance(gpu):
