@@ -122,7 +122,10 @@ typedef struct {
   double *Sr, *mass, *s;        /* degree of saturation, lumped mass, suction [Pa] (read only) */
   double *sig[6];               /* effective stress (Voigt), the point history */
   double *pc;                   /* saturated pre-consolidation pressure p_c < 0, point history */
-  const uint8_t *fixed;         /* nonzero = fixed point (v = a = 0) */
+  const uint8_t *fixed;         /* boundary code: 0 free; 1 fixed (v = a = 0); 2 driven: the point keeps
+                                   its velocity v (a = 0), a prescribed-velocity boundary.  The work
+                                   done by fixed and driven points is not booked in the energies, so
+                                   Eq. 69 is meaningful only without driven points. */
 } ulppm_state;
 
 /* Host-side report of the last ulppm_step / ulppm_forces call. */

@@ -924,7 +924,8 @@ int newmark_step(const Params& P, const Mat<R>& m, PointState<R>& S, R* E, Stats
   // summed with Kahan compensation.
   for (int64_t i = 0; i < n; ++i)
     for (int c = 0; c < 3; ++c) {
-      R vhalf = S.fixed[i] ? R(0.0) : R(S.v[3 * i + c] + hdt * S.a[3 * i + c]);
+      // fixed points (code 1) stand still, driven points (code 2) keep their velocity
+      R vhalf = S.fixed[i] == 2 ? S.v[3 * i + c] : S.fixed[i] ? R(0.0) : R(S.v[3 * i + c] + hdt * S.a[3 * i + c]);
       vh[3 * i + c] = vhalf;
       R y = dt * vhalf - S.uc[3 * i + c];
       R t = S.u[3 * i + c] + y;

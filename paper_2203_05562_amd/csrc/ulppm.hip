@@ -392,7 +392,8 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T v, const int32_t* __restr
 // ------------------------------------------------------------ predictor --
 
 // Velocity predictor v_half = v + (dt/2) a (Eq. 60, beta1 = 1/2, with the step
-// size restored), fixed points v_half = 0 (boundary conditions), displacement
+// size restored); boundary conditions: fixed points (code 1) v_half = 0,
+// driven points (code 2) v_half = v, the velocity they keep; displacement
 // u += dt v_half (Eqs. 61/64 with beta2 = 0) with Kahan compensation, and
 // positions x = x0 + u.  Rounded exactly as written (no contraction), so a
 // state gives bit-identical positions on every device.  Also saves V^n and
@@ -406,11 +407,12 @@ __global__ void k_predict(ulppm_state S, DevParams P, double* __restrict__ x, do
   double eint = 0.0, eext = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const bool fx = S.fixed[i] != 0;
+    const bool drv = S.fixed[i] == 2;
     const double m = S.mass[i];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double a = S.a[c][i];
-      const double vhalf = fx ? 0.0 : S.v[c][i] + hdt * a;
+      const double vhalf = drv ? S.v[c][i] : fx ? 0.0 : S.v[c][i] + hdt * a;
       vh[c * n + i] = vhalf;
       const double u = S.u[c][i], uc = S.uc[c][i];
       const double y = dt * vhalf - uc;
@@ -2168,10 +2170,10 @@ __global__ void k_adj_kin(ulppm_state S, ulppm_state S1, DevParams P, double* __
   const int64_t n = S.n;
   const double hdt = 0.5 * P.dt;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const bool fx = S.fixed[i] != 0;
+    const bool fx = S.fixed[i] != 0, drv = S.fixed[i] == 2;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      vh[c * n + i] = fx ? 0.0 : S.v[c][i] + hdt * S.a[c][i];
+      vh[c * n + i] = drv ? S.v[c][i] : fx ? 0.0 : S.v[c][i] + hdt * S.a[c][i];
       x[c * n + i] = S1.x0[c][i] + S1.u[c][i];
     }
     vol_n[i] = S.vol[i];
@@ -2762,7 +2764,7 @@ __global__ __launch_bounds__(256) void k_adj_point2(int64_t n, const int64_t* __
       cV = wave_sum(cV);
     }
     if (lane == 0) {
-      const bool fx = fixed[k] != 0;
+      const bool fx = fixed[k] != 0, drv = fixed[k] == 2;
       for (int c = 0; c < 3; ++c) {
         const double xb = own_x[c * n + k] + ax[c] + cx[c];
         const double ub = In.u[c][k] + xb;                   // u^{n+1} = u^n + dt v_half, x = x0 + u^{n+1}
@@ -2770,7 +2772,8 @@ __global__ __launch_bounds__(256) void k_adj_point2(int64_t n, const int64_t* __
         Out.x0[c][k] = In.x0[c][k] + xb;
         Out.u[c][k] = ub;
         Out.uc[c][k] = -ub;
-        Out.v[c][k] = fx ? 0.0 : vhb;
+        // fixed: v_half = 0; driven: v_half = v^n, a = 0; free: v_half = v^n + (dt/2) a^n
+        Out.v[c][k] = drv ? vhb : fx ? 0.0 : vhb;
         Out.a[c][k] = fx ? 0.0 : 0.5 * dt * vhb;
       }
       Out.vol[k] = own_V[k] + aV + cV;

@@ -18,6 +18,8 @@ available, so every input here is synthetic):
     C4  128 x 128 x 256 = 4,194,304 points, seed 4, suction 20 kPa, mixed + adjoint
     P0  24 x 48 plane strain   =   1,152 points, seed 10, suction 20 kPa, FP64
     P1  512 x 1024 plane strain = 524,288 points, seed 11, suction 20 kPa, FP64
+    U2, U3  uniaxial compression bar 40 x 12 x 12 (Section 4.1), horizon 2 and
+        3 spacings, unjittered, elastic, one end driven (make_uniaxial_block)
 
 Plane-strain columns (the paper's examples are 2D) lie in the x-z plane at
 y = 0 with jitter in x and z only; each point's volume is dx^2 times a unit
@@ -178,6 +180,57 @@ def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
 def random_velocity(n: int, seed: int, scale: float = 1e-2) -> np.ndarray:
     """Seeded velocity field U(-scale, scale) [m/s] for one-step checks."""
     return np.random.default_rng(seed).uniform(-scale, scale, (n, 3))
+
+
+# Uniaxial compression (Section 4.1): an elastic specimen at zero suction
+# pressed along x.  The paper's specimen is 2D (12,000 points, geometry in a
+# figure that is not available); this is a synthetic 3D bar with its stated
+# constants.
+UNIAXIAL = dict(
+    spacing=0.005,     # distance between adjacent points [m]
+    K=25.0e6, mu=15.0e6,
+    rho_s=2200.0,      # solid skeleton density [kg/m^3]
+    phi0=0.2,          # initial porosity
+    u_total=0.5e-3,    # applied displacement [m]
+    t_load=0.1,        # loading time [s]
+    dt_dynamic=3.0e-6, # time step of the dynamic case [s]
+)
+
+
+def make_uniaxial_block(m: int, dims=(40, 12, 12), sigma0: float = -1.0) -> dict:
+    """Bar of nx x ny x nz points on the unjittered cubic lattice of spacing
+    0.005 m, horizon delta = m * spacing (m = 2 or 3; families of 32 and 122
+    in the interior), zero suction, no
+    gravity, isotropic elastic range only: the initial effective stress is a
+    negligible isotropic sigma0 [Pa] and the over-consolidation ratio is huge
+    (1e12), so the critical-state yield surface is never reached.  Boundary
+    codes: the face ix = 0 fixed (1); the face ix = nx - 1 driven (2) at the
+    constant velocity -u_total / t_load along x; other faces free.  Arrays in
+    the layout of make_column."""
+    u = UNIAXIAL
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    h = u["spacing"]
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    lat = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)
+    x0 = lat.astype(np.float64) * h
+    fixed = np.zeros(n, np.uint8)
+    fixed[lat[:, 0] == 0] = 1
+    fixed[lat[:, 0] == nx - 1] = 2
+    v0 = np.zeros((n, 3))
+    v0[lat[:, 0] == nx - 1, 0] = -u["u_total"] / u["t_load"]
+    sig = np.zeros((n, 6))
+    sig[:, :3] = sigma0
+    m_ = MATERIAL
+    # delta a hair above m * spacing: on the unjittered lattice the points at
+    # exactly m spacings would otherwise enter or not by rounding
+    prm = dict(delta=m * h * (1.0 + 1e-9), K=u["K"], mu=u["mu"], M=m_["M"], lam=m_["lam"], kap=m_["kap"],
+               eta=1.0e30, b1=m_["b1"], b2=m_["b2"], rho_s=u["rho_s"], rho_w=m_["rho_w"], a1=m_["a1"],
+               a2=m_["a2"], n_vg=m_["n_vg"], g=(0.0, 0.0, 0.0), dt=0.0, newton_tol=1e-13, newton_maxit=50,
+               ocr=1.0e12, plane=0)
+    return dict(n=n, dims=tuple(dims), lattice=lat.astype(np.int64), x0=np.ascontiguousarray(x0), v0=v0,
+                vol0=np.full(n, h ** 3), phi0=np.full(n, u["phi0"]), suction=np.zeros(n), fixed=fixed,
+                sig_geo=sig, params=prm, suction_kpa=0.0, m=m)
 
 
 def subsample_ids(n: int, every: int = 64) -> np.ndarray:

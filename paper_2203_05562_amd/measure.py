@@ -21,6 +21,12 @@ one JSON line.
         a seeded initial-velocity direction, each marked valid only when the
         two perturbed runs visit the same family and sub-horizon counts.
 
+    python -m paper_2203_05562_amd.measure uniaxial [--m 2,3] [--t-end 0.1] [--dt 3e-6]
+        Dynamic uniaxial compression of an elastic bar (Section 4.1), standard
+        correspondence against sub-horizons: the non-affine and checkerboard
+        parts of the velocity field and the sigma_xx oscillation along the
+        axis over time.
+
     python -m paper_2203_05562_amd.measure copy [--mib 1024]
         One device-to-device copy of a known size (a float64 tensor), the
         reference that scales the HBM byte counters of a profiler run.
@@ -105,6 +111,65 @@ def mixed_error(cfg_name: str, at, floor: bool = True, max_family: int = 0):
     return dict(kind="mixed-error", workload=f"{cfg_name}: {cfg.nx}x{cfg.ny}x{cfg.nz} column", points=n, dt=dt,
                 errors=out, ms_per_step={k: 1e3 * r[3] / done for k, r in runs.items()},
                 speedup=runs["fp64"][3] / runs["mixed"][3])
+
+
+def uniaxial(ms, t_end: float, dt: float, sample_every: int, dims=(40, 12, 12)):
+    """Dynamic uniaxial compression (Section 4.1) of the elastic bar, with the
+    standard correspondence model (Eqs. 12-14) and with the bond-associated
+    sub-horizons, for each horizon ratio m.  Every `sample_every` steps:
+    the RMS velocity, the part of the velocity field that no affine field
+    A x + b explains (least squares over all points) and its checkerboard
+    component sum_i (-1)^(ix+iy+iz) v_i / n, both relative to the RMS
+    velocity, and the oscillation of sigma_xx along the bar's axis (RMS of its
+    second difference over the mean |sigma_xx| of the axis points)."""
+    import numpy as np
+    import torch
+    from . import inputs, ulppm
+    out = []
+    for m in ms:
+        blk = inputs.make_uniaxial_block(m, dims)
+        lat = blk["lattice"]
+        nx, ny, nz = blk["dims"]
+        sgn = torch.tensor((-1.0) ** lat.sum(axis=1), dtype=torch.float64, device="cuda")
+        axis = np.nonzero((lat[:, 1] == ny // 2) & (lat[:, 2] == nz // 2))[0]
+        axis = torch.tensor(axis[np.argsort(lat[axis, 0])], device="cuda")
+        X = torch.tensor(np.concatenate([blk["x0"], np.ones((blk["n"], 1))], axis=1), device="cuda")
+        for name, mode in (("standard", ulppm.ULPPM_FORCE_STANDARD), ("sub-horizon", ulppm.ULPPM_FORCE_CONJUGATE)):
+            G = ulppm.column_state(blk, "cuda:0", v0=blk["v0"])
+            prm = ulppm.make_params(blk["params"], force_mode=mode)
+            ctx = ulppm.Context(blk["n"], max_family=0 if m > 2 else 64)
+            ctx.init_state(G, prm, blk["params"]["ocr"])
+            dtc = ctx.dt_crit(G, prm)
+            prm.dt = dt
+            nsteps = int(round(t_end / dt))
+            rows, done = [], 0
+            t0 = time.perf_counter()
+            while done < nsteps:
+                k = min(sample_every, nsteps - done)
+                ctx.step(G, prm, k)
+                done += k
+                v = G["v"].t()
+                vr = float(torch.sqrt((v * v).sum(1).mean()))
+                coef = torch.linalg.lstsq(X, v).solution
+                na = v - X @ coef
+                cb = (sgn[:, None] * v).mean(0)
+                sx = G["sig"][0][axis]
+                d2 = sx[2:] - 2.0 * sx[1:-1] + sx[:-2]
+                na_rms = float(torch.sqrt((na * na).sum(1).mean()))
+                rows.append(dict(step=done, t=done * dt, v_rms=vr, nonaffine_rms=na_rms, nonaffine=na_rms / vr,
+                                 checkerboard_abs=float(torch.linalg.vector_norm(cb)),
+                                 checkerboard=float(torch.linalg.vector_norm(cb)) / vr,
+                                 sigxx_osc=float(torch.sqrt((d2 * d2).mean()) / sx.abs().mean()),
+                                 sigxx_axis_mean=float(sx.mean())))
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            log(dict(m=m, model=name, last=rows[-1], seconds=round(el, 2)))
+            out.append(dict(m=m, model=name, delta=blk["params"]["delta"], dt=dt, dt_crit=dtc, steps=nsteps,
+                            seconds=round(el, 2), samples=rows))
+            del ctx, G
+    return dict(kind="uniaxial", workload=f"uniaxial compression bar {dims[0]}x{dims[1]}x{dims[2]}, spacing "
+                                          f"{inputs.UNIAXIAL['spacing']} m, u_x = {inputs.UNIAXIAL['u_total']} m "
+                                          f"over {t_end} s", runs=out)
 
 
 def adjoint_cost(cfg_name: str, steps: int, every: int, precision: str):
@@ -269,6 +334,11 @@ def main(argv=None):
     d.add_argument("--steps", type=int, default=1000)
     d.add_argument("--every", type=int, default=50)
     d.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    f = sub.add_parser("uniaxial")
+    f.add_argument("--m", default="2,3")
+    f.add_argument("--t-end", type=float, default=0.1)
+    f.add_argument("--dt", type=float, default=3.0e-6)
+    f.add_argument("--sample-every", type=int, default=1000)
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=1024)
     e = sub.add_parser("profile-summary")
@@ -292,6 +362,8 @@ def main(argv=None):
         out = dict(kind="copy", bytes_read=nbytes, bytes_written=nbytes)
     elif args.what == "adjoint-check":
         out = adjoint_check(args.config, args.steps, args.every, args.precision)
+    elif args.what == "uniaxial":
+        out = uniaxial([int(v) for v in args.m.split(",")], args.t_end, args.dt, args.sample_every)
     elif args.what == "mixed-error":
         out = mixed_error(args.config, [int(x) for x in args.at.split(",")], not args.no_floor, args.max_family)
     else:

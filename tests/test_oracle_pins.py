@@ -1168,3 +1168,32 @@ def test_bond_history_dual_matches_central_differences(olib):
         fdh = (runs[0][1].st[:nb, :6] - runs[1][1].st[:nb, :6]) / (2 * hs)
         err = np.linalg.norm(fdh - H.dst[:nb, :6]) / np.linalg.norm(H.dst[:nb, :6])
         assert err < 1e-7, (name, "bond states", err)
+
+
+# -------------------------------------------------- uniaxial compression bar --
+
+def test_driven_and_fixed_boundaries_are_exact(olib):
+    """Boundary codes of the point state (Algorithm 2 with prescribed
+    velocities): a driven point (code 2) keeps its velocity and moves by
+    exactly dt v per step, a fixed point (code 1) does not move, and both
+    carry zero acceleration.  Uniaxial bar of Section 4.1 with horizon
+    2 spacings, whose interior families hold the 32 lattice points within
+    2 spacings."""
+    blk = inputs.make_uniaxial_block(2, dims=(10, 5, 5))
+    prm = olib.make_params(blk["params"])
+    S = olib.init_column(blk, prm, blk["params"]["ocr"], v0=blk["v0"])
+    row, _ = olib.families(S["x0"], prm.delta)
+    lat = blk["lattice"]
+    interior = np.all((lat >= 2) & (lat <= np.array(blk["dims"]) - 3), axis=1)
+    assert np.all(np.diff(row)[interior] == 32)
+    prm.dt = 3e-6
+    rc, E, st = olib.step(S, prm, 40)
+    assert rc == 0
+    drv, fix = blk["fixed"] == 2, blk["fixed"] == 1
+    vx = blk["v0"][drv, 0][0]
+    assert np.all(S["v"][drv] == blk["v0"][drv]) and np.all(S["a"][drv] == 0.0)
+    assert np.abs(S["u"][drv, 0] - 40 * 3e-6 * vx).max() <= 1e-15 * abs(40 * 3e-6 * vx)
+    assert np.all(S["u"][drv, 1:] == 0.0)
+    assert np.all(S["u"][fix] == 0.0) and np.all(S["v"][fix] == 0.0)
+    free = blk["fixed"] == 0
+    assert np.abs(S["v"][free, 0]).max() > 0.0          # the compression wave has left the driven face
