@@ -392,7 +392,13 @@ def main():
                                    args.full_steps, 100, max_family)
     if args.adjoint_config:
         from paper_2203_05562_amd.measure import adjoint_cost
-        out["adjoint"] = adjoint_cost(args.adjoint_config, args.adjoint_steps, args.adjoint_every, "fp64")
+        try:
+            out["adjoint"] = adjoint_cost(args.adjoint_config, args.adjoint_steps, args.adjoint_every, "fp64",
+                                          max_family)
+        except ulppm.UlppmError as e:
+            if e.code != -2 or max_family == 0:
+                raise
+            out["adjoint"] = adjoint_cost(args.adjoint_config, args.adjoint_steps, args.adjoint_every, "fp64")
         log(f"[gpu] adjoint: {out['adjoint']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps, dt)

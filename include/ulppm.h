@@ -310,7 +310,7 @@ int ulppm_history_import(ulppm_ctx *ctx, int64_t n, const int64_t *row, const in
                          int64_t n_bonds);
 
 /* Allocate the scratch of ulppm_adjoint_step (a copy of one state, the point
- * adjoints and 7 doubles per bond slot) and, if ulppm_history_reserve has
+ * adjoints and 15 doubles per bond slot) and, if ulppm_history_reserve has
  * run, the 16 doubles per bond slot of ulppm_adjoint_step_bond_history.  Call
  * once, before the first adjoint step; the adjoint steps themselves never
  * allocate.  Errors: ULPPM_E_ARG, ULPPM_E_HIP. */
@@ -333,9 +333,13 @@ int ulppm_adjoint_reserve(ulppm_ctx *ctx);
  * adj_n->x0 receives adj_np1->x0 plus the adjoint of x0, so both accumulate
  * over a backward sweep; adj_n->Sr and adj_n->mass are zero (the step
  * recomputes them).  theta_bar (device, 4 doubles) accumulates the adjoints of
- * (M, lam, kap, eta).  adj_n may alias adj_np1.  p must be FP64 with
- * conjugate force states; state_n and state_np1 may come from a
- * mixed-precision run (the reverse is then taken about that run's states).
+ * (M, lam, kap, eta).  adj_n may alias adj_np1.  p must have conjugate
+ * force states.  With p->precision = ULPPM_FP64 the reverse is FP64
+ * throughout; with ULPPM_MIXED its two membership-matrix sweeps (the re-run
+ * of the sub-horizon sums and the reverse of those sums) run on FP32 matrix
+ * cores with FP32 accumulation, and everything else stays FP64.  state_n and
+ * state_np1 may come from a mixed-precision run (the reverse is then taken
+ * about that run's states).
  * rep (host) may be NULL; it receives the step's family counts and, when the
  * step is re-run from state_n, the re-run's counters (with state_np1 given
  * only the families are rebuilt, and the return-map counters stay zero).

@@ -15,8 +15,10 @@ device.  Each reverse step is handed the recomputed state n+1 as well, so
 the library rebuilds only positions and families instead of re-running the
 step.
 
-A mixed-precision forward is reversed in FP64 about the mixed run's own
-states (the recomputed segment is mixed as well, so it reproduces them).
+A mixed-precision forward is reversed about the mixed run's own states (the
+recomputed segment is mixed as well, so it reproduces them), in FP64 by
+default, or with reverse_precision = ULPPM_MIXED with the two
+membership-matrix sweeps of each reverse step on FP32 matrix cores.
 """
 from typing import Optional, Sequence
 
@@ -64,7 +66,8 @@ class ColumnSpec:
 
     def __init__(self, col: dict, n_steps: int, checkpoint_every: int, dt: Optional[float] = None,
                  precision: int = ulppm.ULPPM_FP64, device="cuda", ctx: Optional["ulppm.Context"] = None,
-                 history: int = ulppm.ULPPM_HISTORY_POINT):
+                 history: int = ulppm.ULPPM_HISTORY_POINT, max_family: int = 0,
+                 reverse_precision: int = ulppm.ULPPM_FP64):
         if n_steps < 0 or checkpoint_every < 1:
             raise ValueError("n_steps >= 0 and checkpoint_every >= 1 required")
         self.n = col["n"]
@@ -73,10 +76,11 @@ class ColumnSpec:
         self.n_steps = int(n_steps)
         self.k = int(checkpoint_every)
         self.precision = precision
+        self.reverse_precision = int(reverse_precision)
         self.history = int(history)
         self.device = torch.device(device)
         self.base = ulppm.column_state(col, device)        # pre-initialisation state
-        self.ctx = ctx if ctx is not None else ulppm.Context(self.n)
+        self.ctx = ctx if ctx is not None else ulppm.Context(self.n, max_family=max_family)
         if self.history == ulppm.ULPPM_HISTORY_BOND:
             self.ctx.history_reserve()
         self.ctx.adjoint_reserve()
@@ -148,7 +152,7 @@ class ColumnRun(torch.autograd.Function):
     def backward(ctx, gu):
         spec = ctx.spec
         p = spec.params_for(ctx.theta)
-        p64 = spec.params_for(ctx.theta, precision=ulppm.ULPPM_FP64)
+        p64 = spec.params_for(ctx.theta, precision=spec.reverse_precision)
         lam = ulppm.DeviceState(spec.n, spec.device)
         lam.t["u"].copy_(gu.t())
         tb = torch.zeros(4, dtype=torch.float64, device=spec.device)

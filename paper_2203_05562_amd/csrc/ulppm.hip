@@ -2137,6 +2137,7 @@ struct AdjArgs {
   double* slot_x;         // 3 x cap: contribution to xbar_k from point i at slot (i,k)
   double* slot_vh;        // 3 x cap
   double* slot_V;         // cap
+  double* fwd;            // 8 x cap: the bond tail's forward solution per slot (sigma 6, p_c, branch)
   double* thpart;         // 4 per block
   // history on the bonds: start states of this step's bonds (8 per slot),
   // adjoints of their updated states (8 per slot), adjoints of the start
@@ -2213,9 +2214,10 @@ __global__ __launch_bounds__(256) void k_adj_point1(int64_t n, const uint8_t* __
 // Hist: the history on the bonds; each bond starts from its carried state
 // (A.hstart), its updated state also receives A.hbar1, and the adjoint of
 // its start state goes to A.hbar0s instead of the point's history.
-template <bool Hist>
+template <bool Hist, class Acc>
 __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(AdjArgs A, DevParams P) {
-  using MM = Mma<double>;
+  using MM = Mma<Acc>;            // the two membership-matrix sweeps: FP64, or FP32 in mixed precision
+  using V4 = typename MM::V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t i = xcd_point(blockIdx.x, A.per);
   if (i >= A.n) {                                 // idle block: its parameter partials are zero
@@ -2229,15 +2231,18 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
   const int nw = (mf + 63) / 64;
-  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);   // x_k (pass 1), then Tbar_ik
+  // LDS per member: 3 quads, the 10-value record and the 16 sums (320 B with
+  // two membership words), so that four workgroups fit a CU for families of
+  // up to ~124.  The per-bond adjoint partials of zeta and V live in their
+  // output slots (A.slot_x, A.slot_V) and the tail's forward solution in
+  // A.fwd, both in HBM, read back by the thread that wrote them.
+  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);   // x_k (pass 1), Tbar_ik, then H columns 10-13
   Quad<double>* sTb = sX;
   Quad<double>* sZ = sX + mf;                                     // zeta_ik, V_k
-  Quad<double>* sY = sZ + mf;                                     // ydot_ik, 1
-  Quad<double>* sZb = sY + mf;                                    // zeta_bar_ik, slot Vbar_k
-  MRec<double>* sM = reinterpret_cast<MRec<double>*>(sZb + mf);   // M_j
+  Quad<double>* sY = sZ + mf;                                     // ydot_ik, 1 (then H column 14)
+  MRec<double>* sM = reinterpret_cast<MRec<double>*>(sY + mf);    // M_j, then G and H columns 0-9
   double* sKN = reinterpret_cast<double*>(sM + mf);               // 16 per bond: K(6) N(9) active | Ks(6) Nb(9)
-  double* sR = sKN + 16 * (size_t)mf;                             // 8 per bond: sigma_ij (6), p_c,ij, branch
-  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sR + 8 * (size_t)mf);
+  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)mf);
   unsigned short* sq = reinterpret_cast<unsigned short*>(sb);     // membership quarters, as the forward
   __shared__ double red[kBondWaves][32];
   __shared__ double pt[32];
@@ -2260,7 +2265,6 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     sX[m] = Quad<double>{{xk0, xk1, xk2, V}};
     sZ[m] = Quad<double>{{z0, z1, z2, V}};
     sY[m] = Quad<double>{{y0, y1, y2, 1.0}};
-    sZb[m] = Quad<double>{{0.0, 0.0, 0.0, 0.0}};
     const double w0 = V * z0, w1 = V * z1, w2 = V * z2;
     Kp[0] += w0 * z0; Kp[1] += w1 * z1; Kp[2] += w2 * z2;
     Kp[3] += w1 * z2; Kp[4] += w0 * z2; Kp[5] += w0 * z1;
@@ -2313,7 +2317,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
       double xj[NB][3];
       bool jv[NB];
       int jrow[NB];
-      v4d acc[NB];
+      V4 acc[NB];
       unsigned piece[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
@@ -2321,7 +2325,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         jv[b] = jrow[b] < nf;
         const Quad<double> q = sX[jv[b] ? jrow[b] : 0];     // positions: the test of Eq. 22
         xj[b][0] = q.v[0]; xj[b][1] = q.v[1]; xj[b][2] = q.v[2];
-        acc[b] = v4d{0, 0, 0, 0};
+        acc[b] = V4{0, 0, 0, 0};
         piece[b] = 0u;
       }
       for (int ks = 0; ks < nks; ++ks) {
@@ -2330,13 +2334,13 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         const int kk = kv ? kk0 : 0;
         const Quad<double> xk = sX[kk];
         const double fvv = rz[4 * kk + oa] * rz[4 * kk + ob] * rz[4 * kk + ov];
-        const double bval = kv ? fvv : 0.0;
+        const Acc bval = kv ? (Acc)fvv : (Acc)0;
         const unsigned sbit = 1u << (ks & 15);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const bool in = within(xj[b][0], xj[b][1], xj[b][2], xk.v[0], xk.v[1], xk.v[2], d2) & kv & jv[b];
           piece[b] |= in ? sbit : 0u;
-          acc[b] = MM::run(in ? 1.0 : 0.0, bval, acc[b]);
+          acc[b] = MM::run(in ? (Acc)1 : (Acc)0, bval, acc[b]);
         }
         if ((ks & 15) == 15 || ks == nks - 1) {
 #pragma unroll
@@ -2384,7 +2388,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         tail_forward_pn(P, Kq, Nq, sig_i, pc_i, Pn_i, Srs, Vj / Vh, dt, F);
       }
       for (int q = 0; q < 9; ++q) r.v[q] = F.M[q];
-      double* rr = sR + 8 * (size_t)m;
+      double* rr = A.fwd + 8 * (b0 + m);
       for (int k = 0; k < 6; ++k) rr[k] = F.sg[k];
       rr[6] = F.pc;
       rr[7] = (double)F.branch;
@@ -2443,7 +2447,8 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     for (int c = 0; c < 3; ++c) e += (a[3 * c] * zq.v[0] + a[3 * c + 1] * zq.v[1] + a[3 * c + 2] * zq.v[2]) * df[c];
     ownV += Vk * e;
     zb.v[3] = Vi * e;                               // to Vbar_k
-    sZb[m] = zb;
+    for (int c = 0; c < 3; ++c) A.slot_x[c * A.cap + slot] = zb.v[c];
+    A.slot_V[slot] = zb.v[3];
   }
   __syncthreads();
 
@@ -2493,7 +2498,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
       const double Vj = sZ[m].v[3];
       TailFwd F;                                   // the return map's solution from pass 1
       tail_kinematics(P.plane != 0, Kq, Nq, dt, F);
-      const double* rr = sR + 8 * (size_t)m;
+      const double* rr = A.fwd + 8 * (b0 + m);
       for (int k = 0; k < 6; ++k) F.sg[k] = rr[k];
       F.pc = rr[6];
       F.branch = (int)rr[7];
@@ -2525,7 +2530,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
                      &acc_Srs, &wb, acc_th);
       }
       // w_j = V_j / Vh
-      sZb[m].v[3] += wb / Vh + vh_hist / W;
+      A.slot_V[b0 + m] += wb / Vh + vh_hist / W;
       acc_Vh -= wb * Vj / (Vh * Vh);
     }
     if constexpr (Hist) {
@@ -2623,15 +2628,16 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
 
   // ---- reverse of the sums (R3): G_k = Ks_i + sum_j B_kj Ks_j, H_k = Nb_i + sum_j B_kj Nb_j.
   // The 15 columns [Ks_j | Nb_j] run on the matrix cores; rows k land in
-  // sM (columns 0-9) and sR (columns 10-14), both free by now.
+  // sM (columns 0-9), sTb (columns 10-13) and the last slot of sY (column
+  // 14), all free by now.
   auto tiles2 = [&](int t0, auto nbc) {
     constexpr int NB = decltype(nbc)::value;
-    v4d acc[NB];
+    V4 acc[NB];
     unsigned piece[NB];
     int krow[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      acc[b] = v4d{0, 0, 0, 0};
+      acc[b] = V4{0, 0, 0, 0};
       piece[b] = 0u;
       krow[b] = (t0 + kBondWaves * b) * 16 + r16;
     }
@@ -2639,7 +2645,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
       const int j = 4 * js + q4;
       const bool ok = j < nf && r16 < 15;
       const double kv = sKN[16 * (size_t)(ok ? j : 0) + (r16 < 15 ? r16 : 0)];
-      const double bval = ok ? kv : 0.0;
+      const Acc bval = ok ? (Acc)kv : (Acc)0;
       const int s = js & 15;
       if (s == 0) {
 #pragma unroll
@@ -2650,7 +2656,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         }
       }
 #pragma unroll
-      for (int b = 0; b < NB; ++b) acc[b] = MM::run((piece[b] >> s) & 1u ? 1.0 : 0.0, bval, acc[b]);
+      for (int b = 0; b < NB; ++b) acc[b] = MM::run((piece[b] >> s) & 1u ? (Acc)1 : (Acc)0, bval, acc[b]);
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -2660,7 +2666,8 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         const int kr = t * 16 + MM::row(q4, r);
         if (kr < nf && r16 < 15) {
           if (r16 < 10) sM[kr].v[r16] = acc[b][r];
-          else sR[8 * (size_t)kr + r16 - 10] = acc[b][r];
+          else if (r16 < 14) sTb[kr].v[r16 - 10] = acc[b][r];
+          else sY[kr].v[3] = acc[b][r];
         }
       }
     }
@@ -2675,27 +2682,27 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   for (int m = tid; m < nf; m += kBondThreads) {
     double G[6], H[9];
     const MRec<double> g10 = sM[m];
-    const double* g5 = sR + 8 * (size_t)m;
+    const Quad<double> g4 = sTb[m];
     for (int k = 0; k < 6; ++k) G[k] = pt[16 + k] + g10.v[k];
     for (int k = 0; k < 4; ++k) H[k] = pt[22 + k] + g10.v[6 + k];
-    for (int k = 0; k < 5; ++k) H[4 + k] = pt[26 + k] + g5[k];
+    for (int k = 0; k < 4; ++k) H[4 + k] = pt[26 + k] + g4.v[k];
     const Quad<double> zq = sZ[m];
     const Quad<double> yq = sY[m];
+    H[8] = pt[30] + yq.v[3];
     const double z[3] = {zq.v[0], zq.v[1], zq.v[2]}, y[3] = {yq.v[0], yq.v[1], yq.v[2]};
     const double Vk = zq.v[3];
     double Gz[3], Hz[3], HTy[3];
     symv(G, z, Gz);
     for (int r = 0; r < 3; ++r) Hz[r] = H[3 * r] * z[0] + H[3 * r + 1] * z[1] + H[3 * r + 2] * z[2];
     for (int c = 0; c < 3; ++c) HTy[c] = H[c] * y[0] + H[3 + c] * y[1] + H[6 + c] * y[2];
-    Quad<double> zb = sZb[m];
+    const int64_t slot = b0 + m;
     double zbar[3], ybar[3];
     for (int c = 0; c < 3; ++c) {
-      zbar[c] = zb.v[c] + Vk * (Gz[c] + HTy[c]);
+      zbar[c] = A.slot_x[c * A.cap + slot] + Vk * (Gz[c] + HTy[c]);
       ybar[c] = Vk * Hz[c];
     }
-    const double Vbar = zb.v[3] + 0.5 * (z[0] * Gz[0] + z[1] * Gz[1] + z[2] * Gz[2]) +
+    const double Vbar = A.slot_V[slot] + 0.5 * (z[0] * Gz[0] + z[1] * Gz[1] + z[2] * Gz[2]) +
                         (y[0] * Hz[0] + y[1] * Hz[1] + y[2] * Hz[2]) + Vhb;
-    const int64_t slot = b0 + m;
     for (int c = 0; c < 3; ++c) {
       A.slot_x[c * A.cap + slot] = zbar[c];
       A.slot_vh[c * A.cap + slot] = ybar[c];
@@ -3142,7 +3149,7 @@ struct ulppm_ctx {
   int64_t hist_n = 0;         // points of the held history; 0: none
   // adjoint scratch (ulppm_adjoint_reserve)
   double* adj = nullptr;      // 24n forward copy + 21n point adjoints + 4(n+8) partials
-  double* adj_slot = nullptr; // 7 x bond_cap
+  double* adj_slot = nullptr; // 15 x bond_cap: adjoint slot contributions (7), bond tail forward solutions (8)
   double* adj_hist = nullptr; // 16 x bond_cap: carried start states and their adjoints (history on the bonds)
   // phase timing events, [step][phase][start/stop]
   hipEvent_t ev[kTimedSteps][kPhases][2] = {};
@@ -4017,7 +4024,7 @@ int ulppm_dt_crit(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, d
 constexpr size_t kMaxLds = 160 * 1024 - 1024;   // dynamic LDS of one workgroup (CDNA4: 160 KB per CU)
 
 size_t adj_lds(int max_f) {
-  return (size_t)max_f * (4 * sizeof(Quad<double>) + sizeof(MRec<double>) + 24 * sizeof(double) +
+  return (size_t)max_f * (3 * sizeof(Quad<double>) + sizeof(MRec<double>) + 16 * sizeof(double) +
                           (size_t)((max_f + 63) / 64) * sizeof(unsigned long long));
 }
 
@@ -4140,16 +4147,18 @@ int ulppm_adjoint_reserve(ulppm_ctx* ctx) {
   const int64_t n = ctx->cap_n;
   const size_t pts = sizeof(double) * (size_t)(45 * n + 4 * (n + 8));
   HIPCHK(hipMalloc((void**)&ctx->adj, pts));
-  const hipError_t e = hipMalloc((void**)&ctx->adj_slot, sizeof(double) * 7 * (size_t)ctx->bond_cap);
+  // per bond slot: the adjoint contributions (x 3, v_half 3, V 1) and the
+  // bond tail's forward solution (8)
+  const hipError_t e = hipMalloc((void**)&ctx->adj_slot, sizeof(double) * 15 * (size_t)ctx->bond_cap);
   if (e != hipSuccess) {
     (void)hipFree(ctx->adj);
     ctx->adj = nullptr;
     return fail(ctx, ULPPM_E_HIP, std::string("adjoint scratch: ") + hipGetErrorString(e));
   }
-  HIPCHK(hipFuncSetAttribute((const void*)k_adj_bond<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)std::min(adj_lds(ctx->max_f), kMaxLds)));
-  HIPCHK(hipFuncSetAttribute((const void*)k_adj_bond<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)std::min(adj_lds(ctx->max_f), kMaxLds)));
+  for (const void* k : {(const void*)k_adj_bond<false, double>, (const void*)k_adj_bond<true, double>,
+                        (const void*)k_adj_bond<false, float>, (const void*)k_adj_bond<true, float>})
+    HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)std::min(adj_lds(ctx->max_f), kMaxLds)));
   return reserve_adj_hist(ctx);
 }
 
@@ -4250,8 +4259,8 @@ static int adjoint_step_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_s
     if (H->nb_n > 0 && (!H->row_n || !H->col_n || !H->hist_n || !H->hist_bar0))
       return fail(ctx, ULPPM_E_ARG, "row_n, col_n, hist_n and hist_bar_n are needed when n_bonds_n > 0");
   }
-  if (p->precision != ULPPM_FP64 || p->force_mode != ULPPM_FORCE_CONJUGATE)
-    return fail(ctx, ULPPM_E_ARG, "the adjoint supports FP64 with conjugate force states");
+  if (p->force_mode != ULPPM_FORCE_CONJUGATE)
+    return fail(ctx, ULPPM_E_ARG, "the adjoint supports conjugate force states");
   if (!(p->dt > 0.0)) return fail(ctx, ULPPM_E_ARG, "dt must be > 0");
   const int64_t n = S->n;
   if (adj1->n != n || adj0->n != n || (S1 && S1->n != n))
@@ -4305,6 +4314,7 @@ static int adjoint_step_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_s
   A.slot_x = ctx->adj_slot;
   A.slot_vh = ctx->adj_slot + 3 * ctx->bond_cap;
   A.slot_V = ctx->adj_slot + 6 * ctx->bond_cap;
+  A.fwd = ctx->adj_slot + 7 * ctx->bond_cap;
   A.thpart = thpart;
   A.cap = ctx->bond_cap;
   A.dt = p->dt;
@@ -4329,10 +4339,15 @@ static int adjoint_step_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_s
     HIPCHK(hipGetLastError());
   }
   k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
-  if (H)
-    k_adj_bond<true><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  const bool mixed = p->precision == ULPPM_MIXED;
+  if (H && mixed)
+    k_adj_bond<true, float><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  else if (H)
+    k_adj_bond<true, double><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  else if (mixed)
+    k_adj_bond<false, float><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   else
-    k_adj_bond<false><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+    k_adj_bond<false, double><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
   HIPCHK(hipGetLastError());
   if (H) {
     if (have) {

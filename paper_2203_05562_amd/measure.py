@@ -172,13 +172,15 @@ def uniaxial(ms, t_end: float, dt: float, sample_every: int, dims=(40, 12, 12)):
                                           f"over {t_end} s", runs=out)
 
 
-def adjoint_cost(cfg_name: str, steps: int, every: int, precision: str):
+def adjoint_cost(cfg_name: str, steps: int, every: int, precision: str, max_family: int = 0,
+                 reverse: str = "fp64"):
     import torch
     from . import adjoint, inputs, ulppm
     cfg = inputs.CONFIGS[cfg_name]
     col = inputs.make_column(cfg)
     prec = ulppm.ULPPM_MIXED if precision == "mixed" else ulppm.ULPPM_FP64
-    spec = adjoint.ColumnSpec(col, steps, every, precision=prec)
+    rprec = ulppm.ULPPM_MIXED if reverse == "mixed" else ulppm.ULPPM_FP64
+    spec = adjoint.ColumnSpec(col, steps, every, precision=prec, max_family=max_family, reverse_precision=rprec)
     spec.timing = True
     w = inputs.runout_objective_weights(col["lattice"], col["dims"])
     theta = spec.theta0().requires_grad_(True)
@@ -198,8 +200,8 @@ def adjoint_cost(cfg_name: str, steps: int, every: int, precision: str):
     t = spec.last_timing
     return dict(kind="adjoint-cost",
                 workload=f"{cfg_name}: {cfg.nx}x{cfg.ny}x{cfg.nz} column, {steps} steps, checkpoint every {every}, "
-                         f"{precision} forward, objective runout + settlement",
-                points=col["n"], forward_ms=round(fwd, 2), backward_ms=round(bwd, 2),
+                         f"{precision} forward, {reverse} reverse, objective runout + settlement",
+                points=col["n"], max_family=max_family or 152, forward_ms=round(fwd, 2), backward_ms=round(bwd, 2),
                 recompute_ms=round(t["recompute"], 2), reverse_ms=round(t["reverse"], 2),
                 forward_ms_per_step=round(fwd / steps, 4), adjoint_ms_per_step=round(t["reverse"] / steps, 4),
                 adjoint_to_forward_step=round(t["reverse"] / fwd, 3), backward_to_forward=round(bwd / fwd, 3),
@@ -329,6 +331,9 @@ def main(argv=None):
     b.add_argument("--steps", type=int, default=50)
     b.add_argument("--every", type=int, default=25)
     b.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    b.add_argument("--max-family", type=int, default=0, help="family capacity of the context (0: 152)")
+    b.add_argument("--reverse", default="fp64", choices=["fp64", "mixed"],
+                   help="precision of the reverse steps' membership-matrix sweeps")
     d = sub.add_parser("adjoint-check")
     d.add_argument("--config", default="C3")
     d.add_argument("--steps", type=int, default=1000)
@@ -367,7 +372,7 @@ def main(argv=None):
     elif args.what == "mixed-error":
         out = mixed_error(args.config, [int(x) for x in args.at.split(",")], not args.no_floor, args.max_family)
     else:
-        out = adjoint_cost(args.config, args.steps, args.every, args.precision)
+        out = adjoint_cost(args.config, args.steps, args.every, args.precision, args.max_family, args.reverse)
     print(json.dumps(out), flush=True)
 
 

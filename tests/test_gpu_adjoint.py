@@ -251,10 +251,12 @@ def oracle_run(olib, col, dt, nsteps, theta=None, s=None, v0=None):
     return S["u"], st
 
 
-def gpu_gradient(gpu, col, v0, dt, w, tau, nsteps, k, precision=None):
+def gpu_gradient(gpu, col, v0, dt, w, tau, nsteps, k, precision=None, reverse_precision=None):
     import torch
     from paper_2203_05562_amd import adjoint
     kw = {} if precision is None else {"precision": precision}
+    if reverse_precision is not None:
+        kw["reverse_precision"] = reverse_precision
     spec = adjoint.ColumnSpec(col, nsteps, k, dt=dt, **kw)
     theta = spec.theta0().requires_grad_(True)
     s = torch.tensor(col["suction"], dtype=torch.float64, device="cuda", requires_grad=True)
@@ -346,6 +348,52 @@ def test_mixed_precision_gradient_error(olib, gpu):
     assert errs["J"] <= 1e-5
     for name in ("theta", "s", "v0"):
         assert errs[name] <= 1e-2, (name, errs)
+
+
+def test_mixed_reverse_against_fp64_reverse(olib, gpu):
+    """The reverse steps in mixed precision (their two membership-matrix
+    sweeps on FP32 matrix cores) about a mixed forward, against the FP64
+    reverse about the same forward: the gradients in theta, s and v0 agree to
+    1e-4 relative, and the one-step adjoint identity against the oracle's
+    dual numbers holds to 1e-5."""
+    import torch
+    from paper_2203_05562_amd import ulppm
+    say("mixed reverse")
+    col, v0, dt, w = column_case(olib)
+    tau = 0.1 * inputs.DX
+    ref = gpu_gradient(gpu, col, v0, dt, w, tau, 12, 5, precision=ulppm.ULPPM_MIXED)
+    got = gpu_gradient(gpu, col, v0, dt, w, tau, 12, 5, precision=ulppm.ULPPM_MIXED,
+                       reverse_precision=ulppm.ULPPM_MIXED)
+    assert got[0] == ref[0]
+    errs = {name: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            for name, a, b in zip(("theta", "s", "v0"), got[1:4], ref[1:4])}
+    say("mixed reverse vs fp64 reverse", errs)
+    assert all(e <= 1e-4 for e in errs.values()), errs
+    # one-step identity, the reverse taken about the FP64 step's state n+1
+    col2, oprm, gprm, S, ctx = start(olib, gpu)
+    n = col2["n"]
+    rng = np.random.default_rng(7)
+    t0 = {"u": rng.normal(size=(n, 3)) * 1e-4, "v": rng.normal(size=(n, 3)) * 1e-2,
+          "sig": rng.normal(size=(n, 6)) * 1e2, "pc": rng.normal(size=n) * 1e2}
+    dpar = np.array([0.3, 0.02, -0.01, 0.2 * oprm.eta])
+    dS = olib.empty_state(n)
+    for k, v in t0.items():
+        dS[k][:] = v
+    S1 = olib.copy_state(S)
+    rc, _, st = olib.step_dual(S1, dS, oprm, dpar, 1)
+    assert rc == 0 and st["n_plastic"] > 0
+    lam1 = {k: rng.normal(size=S[k].shape) for k in FIELDS}
+    lam1["uc"][:] = 0.0
+    L1 = dev(gpu, {**lam1, "x0": np.zeros((n, 3))})
+    L0 = gpu.DeviceState(n)
+    th = torch.zeros(4, dtype=torch.float64, device="cuda")
+    gprm.precision = gpu.ULPPM_MIXED
+    ctx.adjoint_step(dev(gpu, S), gprm, L1, L0, th, S1=dev(gpu, S1))
+    lam0 = L0.to_arrays()
+    lhs = inner(lam1, {k: dS[k] for k in FIELDS if k != "uc"})
+    rhs = inner(lam0, t0) + float(np.dot(th.cpu().numpy(), dpar))
+    say("mixed identity", lhs, rhs)
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs))
 
 
 def test_adjoint_given_next_state_matches_rerun(olib, gpu):
