@@ -36,6 +36,9 @@ throughput and gather phase, the kernel that adds the contact forces.
 families of ~28), its throughput and bond-kernel time.  "history": the
 workload with the history carried on the bonds (ULPPM_HISTORY_BOND).
 "eq51": the workload with the force state of Eq. 51 as printed.
+"adjoint_large": the 128 x 128 x 256 column (4.2M points) with a mixed
+forward of 25 steps and its checkpointed reverse, the reverse sweeps in
+mixed precision: time per forward step, per reverse step and their ratio.
 "full_run": the workload as defined, 2000 steps from rest for seeds 1, 2 and
 3 (suction drawn per seed), with the energy balance of Eq. 69 checked after
 every 100 steps: time per step over the run and in windows, candidate
@@ -233,6 +236,10 @@ def main():
     ap.add_argument("--adjoint-config", default="C3", help="configuration of the adjoint cost line ('' skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--adjoint-every", type=int, default=50)
+    ap.add_argument("--adjoint-large-config", default="C4",
+                    help="configuration of the large mixed-precision adjoint line ('' skips it)")
+    ap.add_argument("--adjoint-large-steps", type=int, default=25)
+    ap.add_argument("--adjoint-large-every", type=int, default=25)
     ap.add_argument("--no-contact", action="store_true", help="skip the substrate-contact companion run")
     ap.add_argument("--no-plane", action="store_true", help="skip the plane-strain companion run")
     ap.add_argument("--no-history", action="store_true", help="skip the bond-history companion run")
@@ -344,10 +351,19 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_plane:
         colp = inputs.make_column(inputs.CONFIGS["P1"])
-        # plane families hold at most ~30 members: a context sized for 64 runs one wave per point
-        Gp, repp, msp, _ = run_column(ulppm, colp, prec, args.warmup, args.steps, max_family=64)
+        # plane families hold about 30 members: a context sized for at most 64
+        # runs one wave per point, and 48 leaves LDS for twelve such
+        # workgroups per CU (three waves per SIMD); 64 if a family outgrows 48
+        capp = 48
+        try:
+            Gp, repp, msp, _ = run_column(ulppm, colp, prec, args.warmup, args.steps, max_family=capp)
+        except ulppm.UlppmError as e:
+            if e.code != -2:
+                raise
+            capp = 64
+            Gp, repp, msp, _ = run_column(ulppm, colp, prec, args.warmup, args.steps, max_family=capp)
         lp = max(repp["timed_steps"], 1)
-        out["plane"] = dict(workload="P1: plane-strain column 512x1024", points=colp["n"],
+        out["plane"] = dict(workload="P1: plane-strain column 512x1024", points=colp["n"], max_family=capp,
                             value=repp["n_bond_updates"] / (msp * 1e-3), ms_per_step=msp / args.steps,
                             bonds_per_step=repp["n_bond_updates"] / args.steps,
                             phase_ms={k: round(repp[f"t_{k}_ms"] / lp, 4)
@@ -400,6 +416,20 @@ def main():
                 raise
             out["adjoint"] = adjoint_cost(args.adjoint_config, args.adjoint_steps, args.adjoint_every, "fp64")
         log(f"[gpu] adjoint: {out['adjoint']}")
+    if args.adjoint_large_config:
+        # the 4M-point column: mixed forward, reverse sweeps in mixed precision
+        from paper_2203_05562_amd.measure import adjoint_cost
+        torch.cuda.empty_cache()
+        try:
+            out["adjoint_large"] = adjoint_cost(args.adjoint_large_config, args.adjoint_large_steps,
+                                                args.adjoint_large_every, "mixed", max_family, "mixed")
+        except ulppm.UlppmError as e:
+            if e.code != -2 or max_family == 0:
+                raise
+            out["adjoint_large"] = adjoint_cost(args.adjoint_large_config, args.adjoint_large_steps,
+                                                args.adjoint_large_every, "mixed", 0, "mixed")
+        log(f"[gpu] adjoint_large: {out['adjoint_large']}")
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_steps, dt)
     else:

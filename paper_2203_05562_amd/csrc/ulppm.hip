@@ -747,8 +747,17 @@ __global__ __launch_bounds__(256) void k_compact(int64_t n, int max_c, int max_f
 
 // ----------------------------------------------------- constitutive model --
 
+// Apparent pre-consolidation P(p_c) = -exp(b1) (-p_c)^b2 (Eq. 45) and its
+// slope dP/dp_c (Eq. 89).  With b1 = 0 and b2 = 1 they are p_c and 1, taken
+// without the transcendental calls (the Newton iterations of the plastic
+// bonds evaluate both every iteration).
 __host__ __device__ __forceinline__ double apparent_pc(const DevParams& P, double pc) {
+  if (P.b1 == 0.0 && P.b2 == 1.0) return pc;
   return -exp(P.b1) * pow(-pc, P.b2);               // Eq. 45
+}
+__host__ __device__ __forceinline__ double apparent_pc_slope(const DevParams& P, double pc) {
+  if (P.b1 == 0.0 && P.b2 == 1.0) return 1.0;
+  return P.b2 * exp(P.b1) * pow(-pc, P.b2 - 1.0);   // Eq. 89
 }
 
 __host__ __device__ __forceinline__ double yield_f(const DevParams& P, double p, double q, double pcb) {
@@ -772,7 +781,10 @@ __host__ __device__ double swrc(const DevParams& P, double J, double phi, double
 // g - c f(p, q, P) on [0, inf), where it changes sign once.
 struct ConsistencySolve {
   double K, mu, M2, lk, b1, b2, c, ptr, qtr, pcn;
-  __host__ __device__ double Pb(double pc) const { return -exp(b1) * pow(-pc, b2); }
+  __host__ __device__ double Pb(double pc) const { return b1 == 0.0 && b2 == 1.0 ? pc : -exp(b1) * pow(-pc, b2); }
+  __host__ __device__ double dPb(double pc) const {
+    return b1 == 0.0 && b2 == 1.0 ? 1.0 : b2 * exp(b1) * pow(-pc, b2 - 1.0);
+  }
   __host__ __device__ double pc_for(double g) const {
     const double A = g / (lk * (1.0 + 2.0 * K * g));
     double hi = 0.0, lo = pcn;
@@ -786,7 +798,7 @@ struct ConsistencySolve {
       const double E = exp(-A * (2.0 * ptr - Pb(x)));
       const double h = x - pcn * E;
       if (h > 0.0) hi = x; else lo = x;
-      const double dh = 1.0 - pcn * E * A * b2 * exp(b1) * pow(-x, b2 - 1.0);
+      const double dh = 1.0 - pcn * E * A * dPb(x);
       double xn = x - h / dh;
       if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
       const bool done = fabs(xn - x) <= 1e-16 * fabs(x);
@@ -856,7 +868,7 @@ __host__ __device__ int return_map_pn(const DevParams& P, double dt, const doubl
   bool conv = false, stalled = false;
   for (;;) {
     const double Pb = apparent_pc(P, pc);
-    const double dP = P.b2 * exp(P.b1) * pow(-pc, P.b2 - 1.0);   // Eq. 89
+    const double dP = apparent_pc_slope(P, pc);                  // Eq. 89
     const double f = yield_f(P, p, q, Pb);
     const double fp = 2.0 * p - Pb, fq = 2.0 * q / M2, fc = -p * dP;
     const double E = exp(-c * f * fp / lk);
@@ -1083,7 +1095,7 @@ __host__ __device__ void rm_reverse(const DevParams& P, double dt, const double*
     // implicit function theorem at the solution x = (p, q, pc)
     const double c = dt / P.eta, M2 = P.M * P.M, lk = P.lam - P.kap;
     const double Pb = apparent_pc(P, pco);
-    const double dP = P.b2 * exp(P.b1) * pow(-pco, P.b2 - 1.0);
+    const double dP = apparent_pc_slope(P, pco);
     const double f = yield_f(P, p, q, Pb);
     const double fp = 2.0 * p - Pb, fq = 2.0 * q / M2, fc = -p * dP;
     const double E = exp(-c * f * fp / lk);

@@ -121,9 +121,19 @@ def default_params(cfg: ColumnConfig, suction_pa: float, **over) -> dict:
     )
 
 
+def morton_order(lat: np.ndarray) -> np.ndarray:
+    """Permutation that lists integer lattice coordinates (n, 3) in Morton
+    (Z-curve) order: the bits of x, y and z interleaved, x lowest."""
+    key = np.zeros(lat.shape[0], np.uint64)
+    for b in range(21):
+        for c in range(3):
+            key |= ((lat[:, c].astype(np.uint64) >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + c)
+    return np.argsort(key, kind="stable")
+
+
 def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
                 suction_kpa: Optional[float] = None, jitter: float = 0.05,
-                dims=None, fixed_base: bool = True) -> dict:
+                dims=None, fixed_base: bool = True, order: str = "lattice") -> dict:
     """Return the seeded column: arrays in caller (lattice) order plus params.
 
     Arrays (float64 unless stated):
@@ -131,6 +141,8 @@ def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
       fixed (N,) uint8, sig_geo (N,6) total K0 geostatic stress in Voigt
       order (xx, yy, zz, yz, xz, xy), tension positive.
     fixed_base=False frees the bottom layer (a column resting on a substrate).
+    order="morton" numbers the points along the Morton curve of their lattice
+    coordinates instead of lattice order (the same points and random draws).
     """
     nx, ny, nz = dims if dims is not None else (cfg.nx, cfg.ny, cfg.nz)
     if cfg.plane and ny != 1:
@@ -163,6 +175,12 @@ def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
     sig[:, 0] = k0 * szz
     sig[:, 1] = k0 * szz
     sig[:, 2] = szz
+    fixed = ((lat[:, 2] == 0) & fixed_base).astype(np.uint8)
+    if order == "morton":
+        p = morton_order(lat.astype(np.int64))
+        lat, x0, sig, fixed = lat[p], x0[p], sig[p], fixed[p]
+    elif order != "lattice":
+        raise ValueError("order is 'lattice' or 'morton'")
     return dict(
         n=n, dims=(nx, ny, nz), lattice=lat.astype(np.int64),
         x0=np.ascontiguousarray(x0),
@@ -170,10 +188,11 @@ def make_column(cfg: ColumnConfig, seed: Optional[int] = None,
         vol0=np.full(n, DX ** 2 if cfg.plane else DX ** 3),
         phi0=np.full(n, phi0),
         suction=np.full(n, s),
-        fixed=((lat[:, 2] == 0) & fixed_base).astype(np.uint8),
-        sig_geo=sig,
+        fixed=fixed,
+        sig_geo=np.ascontiguousarray(sig),
         params=prm,
         suction_kpa=suction_kpa,
+        order=order,
     )
 
 

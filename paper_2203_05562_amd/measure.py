@@ -27,6 +27,10 @@ one JSON line.
         parts of the velocity field and the sigma_xx oscillation along the
         axis over time.
 
+    python -m paper_2203_05562_amd.measure point-order [--configs C1,C4] [--warm 1000]
+        Time per step and per phase with the points numbered in lattice order
+        and in Morton order (the library processes points in id order).
+
     python -m paper_2203_05562_amd.measure copy [--mib 1024]
         One device-to-device copy of a known size (a float64 tensor), the
         reference that scales the HBM byte counters of a profiler run.
@@ -170,6 +174,43 @@ def uniaxial(ms, t_end: float, dt: float, sample_every: int, dims=(40, 12, 12)):
     return dict(kind="uniaxial", workload=f"uniaxial compression bar {dims[0]}x{dims[1]}x{dims[2]}, spacing "
                                           f"{inputs.UNIAXIAL['spacing']} m, u_x = {inputs.UNIAXIAL['u_total']} m "
                                           f"over {t_end} s", runs=out)
+
+
+def point_order(cfgs, warm: int, steps: int):
+    """Time per step and per phase of the same column with its points numbered
+    in lattice order and in Morton order, after `warm` untimed steps (the
+    late state of a collapse when warm is large), FP64 and mixed."""
+    import torch
+    from . import inputs, ulppm
+    rows = []
+    for cfg_name in cfgs:
+        cfg = inputs.CONFIGS[cfg_name]
+        w = warm if cfg.n_points < 1_000_000 else 0
+        for order in ("lattice", "morton"):
+            col = inputs.make_column(cfg, order=order)
+            for prec in ("fp64", "mixed"):
+                G = ulppm.column_state(col, "cuda:0")
+                prm = ulppm.make_params(col["params"], precision=ulppm.ULPPM_MIXED if prec == "mixed" else 0)
+                ctx = ulppm.Context(col["n"], max_family=128)
+                ctx.init_state(G, prm, col["params"]["ocr"])
+                prm.dt = 0.5 * ctx.dt_crit(G, prm)
+                if w:
+                    ctx.step(G, prm, w)
+                torch.cuda.synchronize()
+                prm.timing = 1
+                s = torch.cuda.current_stream()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                rep = ctx.step(G, prm, steps)
+                e1.record(s)
+                torch.cuda.synchronize()
+                ph = {k: round(rep[f"t_{k}_ms"] / steps, 4) for k in ("predict", "family", "kin", "bond", "gather")}
+                rows.append(dict(config=cfg_name, order=order, precision=prec, after_steps=w,
+                                 ms_per_step=round(e0.elapsed_time(e1) / steps, 4), phase_ms=ph))
+                log(rows[-1])
+                del ctx, G
+                torch.cuda.empty_cache()
+    return dict(kind="point-order", rows=rows)
 
 
 def adjoint_cost(cfg_name: str, steps: int, every: int, precision: str, max_family: int = 0,
@@ -339,6 +380,10 @@ def main(argv=None):
     d.add_argument("--steps", type=int, default=1000)
     d.add_argument("--every", type=int, default=50)
     d.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    o = sub.add_parser("point-order")
+    o.add_argument("--configs", default="C1,C4")
+    o.add_argument("--warm", type=int, default=1000)
+    o.add_argument("--steps", type=int, default=20)
     f = sub.add_parser("uniaxial")
     f.add_argument("--m", default="2,3")
     f.add_argument("--t-end", type=float, default=0.1)
@@ -367,6 +412,8 @@ def main(argv=None):
         out = dict(kind="copy", bytes_read=nbytes, bytes_written=nbytes)
     elif args.what == "adjoint-check":
         out = adjoint_check(args.config, args.steps, args.every, args.precision)
+    elif args.what == "point-order":
+        out = point_order(args.configs.split(","), args.warm, args.steps)
     elif args.what == "uniaxial":
         out = uniaxial([int(v) for v in args.m.split(",")], args.t_end, args.dt, args.sample_every)
     elif args.what == "mixed-error":
