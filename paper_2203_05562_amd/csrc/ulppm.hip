@@ -1636,6 +1636,9 @@ constexpr size_t kBondStaticLds = 512;      // the bond kernel's static LDS, rou
 // tiles plus the quad the member loop loads one step ahead.  Padding slots
 // hold positions at infinity (no membership) and zero features.
 __host__ __device__ constexpr int bond_mx_slots(int max_f) { return ((max_f + 15) & ~15) + 4; }
+// Rows of the 16 member sums: the family capacity rounded up to whole groups
+// of four, which pass 2 reads without range checks.
+__host__ __device__ constexpr int bond_mx_rows(int max_f) { return (max_f + 3) & ~3; }
 template <class Acc>
 __host__ __device__ constexpr size_t bond_mx_lds_bytes(int max_f) {
   // (x_k, V_k) in FP64 for the membership test and the member record (zeta_ik,
@@ -1643,10 +1646,12 @@ __host__ __device__ constexpr size_t bond_mx_lds_bytes(int max_f) {
   // bits per member.  The closing reduction reuses the space for 8 doubles
   // per thread.
   return (size_t)bond_mx_slots(max_f) * (sizeof(Quad<double>) + 8 * sizeof(Acc)) +
-                 (size_t)max_f * (16 * sizeof(Acc) + ((max_f + 63) / 64) * sizeof(unsigned long long)) >
+                 (size_t)bond_mx_rows(max_f) * 16 * sizeof(Acc) +
+                 (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long) >
              8 * kBondThreads * sizeof(double)
          ? (size_t)bond_mx_slots(max_f) * (sizeof(Quad<double>) + 8 * sizeof(Acc)) +
-               (size_t)max_f * (16 * sizeof(Acc) + ((max_f + 63) / 64) * sizeof(unsigned long long))
+               (size_t)bond_mx_rows(max_f) * 16 * sizeof(Acc) +
+               (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long)
          : 8 * kBondThreads * sizeof(double);
 }
 
@@ -1689,7 +1694,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
   Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);
   Acc* sR = reinterpret_cast<Acc*>(sX + mfp);                          // 8 per slot: zeta, V, ydot, 1
   Acc* sKN = sR + 8 * (size_t)mfp;                                     // 16 per member: K, N, Vs, then M_j
-  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)mf);
+  unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)bond_mx_rows(mf));
   unsigned short* sq = reinterpret_cast<unsigned short*>(sb);
   Quad<TS>* const T4 = reinterpret_cast<Quad<TS>*>(A.T);
   __shared__ double s_d2;
@@ -1924,46 +1929,126 @@ void k_bond_mx(BondArgs A, DevParams P) {
   }
   double own[3] = {0.0, 0.0, 0.0};
   if constexpr (kF64) if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
-    // ---- pass 2 in FP64 on the VALU: one lane per member k streams the M_j
-    // of its row of the (symmetric) membership matrix.  FP64 matrix products
-    // run at the vector rate on this chip and would pad the 9 outputs to 16.
+    // ---- pass 2 in FP64 on the VALU: A_k = sum_j B_kj M_j, streaming the
+    // rows M_j of the (symmetric) membership matrix in groups of four.  FP64
+    // matrix products run at the vector rate on this chip and would pad the
+    // 9 outputs to 16.  Rows past the family up to a whole group read as
+    // zeros (their membership bits are clear, and 0 * stale data could be NaN).
+    for (int m = nf + tid; m < 4 * nks; m += kBondThreads) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) sKN[16 * (size_t)m + q] = (Acc)0;
+    }
     __syncthreads();
-    for (int m = tid; m < nf; m += kBondThreads) {
-      Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0, a8 = 0;
-      for (int c = 0; c < nblk; ++c) {
-        const unsigned long long word = sb[(size_t)m * nw + c];
-        const unsigned lo = (unsigned)word, hi = (unsigned)(word >> 32);
-        // members 64 c + 4 s + q in order; their bits are 16 q + s of the
-        // word.  Bits of members past the family are clear, so their rows
-        // (clamped to the last member) enter with weight 0.
-        for (int s4 = 0; s4 < 16; ++s4) {
-          const int j0 = 64 * c + 4 * s4;
-          if (j0 >= nf) break;
-          Acc r[4][9];
+    if (kBondWaves == 2 && nf <= 2 * kWave && 16 * bond_mx_rows(mf) >= 18 * kWave) {
+      // Two members per lane (k = lane and lane + 64), the groups of rows
+      // split between the two waves: each row read from LDS serves two
+      // members, which halves the LDS traffic that bounds this loop.  The
+      // waves then hand each other the partial sums of the member the other
+      // one finishes.
+      const int gh = (nks + 1) / 2;
+      const int g0 = wid == 0 ? 0 : gh, g1 = wid == 0 ? gh : nks;
+      const int ka = lane, kb = lane + kWave;
+      const bool va = ka < nf, vb = kb < nf;
+      Acc Pa[9], Pb[9];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const Acc* rq = sKN + 16 * (size_t)(j0 + q < nf ? j0 + q : nf - 1);
+      for (int t = 0; t < 9; ++t) Pa[t] = Pb[t] = (Acc)0;
+      unsigned long long wa = 0ull, wb = 0ull;
+      for (int g = g0; g < g1; ++g) {
+        const int s4 = g & 15;
+        if (g == g0 || s4 == 0) {                  // membership words of both members
+          const unsigned long long xa = sb[(size_t)(va ? ka : 0) * nw + (g >> 4)];
+          const unsigned long long xb = sb[(size_t)(vb ? kb : 0) * nw + (g >> 4)];
+          wa = va ? xa : 0ull;
+          wb = vb ? xb : 0ull;
+        }
+        Acc r[4][9];
 #pragma unroll
-            for (int t = 0; t < 9; ++t) r[q][t] = rq[t];
-          }
+        for (int q = 0; q < 4; ++q) {
+          const Acc* rq = sKN + 16 * (size_t)(4 * g + q);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const unsigned half = q < 2 ? lo : hi;
-            const Acc w = (Acc)((half >> (16 * (q & 1) + s4)) & 1u);
-            a0 += w * r[q][0]; a1 += w * r[q][1]; a2 += w * r[q][2];
-            a3 += w * r[q][3]; a4 += w * r[q][4]; a5 += w * r[q][5];
-            a6 += w * r[q][6]; a7 += w * r[q][7]; a8 += w * r[q][8];
+          for (int t = 0; t < 9; ++t) r[q][t] = rq[t];
+        }
+        // members 4 g + q; their bits are 16 q + s4 of the word
+        const unsigned la = (unsigned)wa, ha = (unsigned)(wa >> 32);
+        const unsigned lb = (unsigned)wb, hb = (unsigned)(wb >> 32);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int sh = 16 * (q & 1) + s4;
+          const Acc w0 = (Acc)(((q < 2 ? la : ha) >> sh) & 1u);
+          const Acc w1 = (Acc)(((q < 2 ? lb : hb) >> sh) & 1u);
+#pragma unroll
+          for (int t = 0; t < 9; ++t) {
+            Pa[t] += w0 * r[q][t];
+            Pb[t] += w1 * r[q][t];
           }
         }
       }
-      const Acc* zm = sR + 8 * (size_t)m;
-      const Acc zx = zm[0], zy = zm[1], zz = zm[2];
-      const int64_t slot = b0 + m;
-      const Acc t0 = a0 * zx + a1 * zy + a2 * zz, t1 = a3 * zx + a4 * zy + a5 * zz, t2 = a6 * zx + a7 * zy + a8 * zz;
-      T4[slot] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
-      own[0] += t0 * zm[3];                                        // sum_k T_ik V_k
-      own[1] += t1 * zm[3];
-      own[2] += t2 * zm[3];
+      __syncthreads();                             // every row M_j has been read
+      Acc* xch = sKN;                              // [18][64]: the partials handed over
+      if (wid == 0) {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) xch[(size_t)(9 + t) * kWave + lane] = Pb[t];
+      } else {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) xch[(size_t)t * kWave + lane] = Pa[t];
+      }
+      __syncthreads();
+      Acc S[9];
+      if (wid == 0) {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) S[t] = Pa[t] + xch[(size_t)t * kWave + lane];
+      } else {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) S[t] = Pb[t] + xch[(size_t)(9 + t) * kWave + lane];
+      }
+      const int m = wid == 0 ? ka : kb;
+      if (m < nf) {
+        const Acc* zm = sR + 8 * (size_t)m;
+        const Acc zx = zm[0], zy = zm[1], zz = zm[2];
+        const Acc t0 = S[0] * zx + S[1] * zy + S[2] * zz, t1 = S[3] * zx + S[4] * zy + S[5] * zz,
+                  t2 = S[6] * zx + S[7] * zy + S[8] * zz;
+        T4[b0 + m] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
+        own[0] += t0 * zm[3];                                      // sum_k T_ik V_k
+        own[1] += t1 * zm[3];
+        own[2] += t2 * zm[3];
+      }
+    } else {
+      // one lane per member k (families of more than 128 members)
+      for (int m = tid; m < nf; m += kBondThreads) {
+        Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0, a8 = 0;
+        for (int c = 0; c < nblk; ++c) {
+          const unsigned long long word = sb[(size_t)m * nw + c];
+          const unsigned lo = (unsigned)word, hi = (unsigned)(word >> 32);
+          // members 64 c + 4 s + q in order; their bits are 16 q + s of the word
+          for (int s4 = 0; s4 < 16; ++s4) {
+            const int j0 = 64 * c + 4 * s4;
+            if (j0 >= nf) break;
+            Acc r[4][9];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const Acc* rq = sKN + 16 * (size_t)(j0 + q);
+#pragma unroll
+              for (int t = 0; t < 9; ++t) r[q][t] = rq[t];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const unsigned half = q < 2 ? lo : hi;
+              const Acc w = (Acc)((half >> (16 * (q & 1) + s4)) & 1u);
+              a0 += w * r[q][0]; a1 += w * r[q][1]; a2 += w * r[q][2];
+              a3 += w * r[q][3]; a4 += w * r[q][4]; a5 += w * r[q][5];
+              a6 += w * r[q][6]; a7 += w * r[q][7]; a8 += w * r[q][8];
+            }
+          }
+        }
+        const Acc* zm = sR + 8 * (size_t)m;
+        const Acc zx = zm[0], zy = zm[1], zz = zm[2];
+        const int64_t slot = b0 + m;
+        const Acc t0 = a0 * zx + a1 * zy + a2 * zz, t1 = a3 * zx + a4 * zy + a5 * zz, t2 = a6 * zx + a7 * zy + a8 * zz;
+        T4[slot] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
+        own[0] += t0 * zm[3];                                      // sum_k T_ik V_k
+        own[1] += t1 * zm[3];
+        own[2] += t2 * zm[3];
+      }
     }
   }
   if constexpr (!kF64) if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
