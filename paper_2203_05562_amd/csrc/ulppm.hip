@@ -1630,29 +1630,41 @@ __device__ __forceinline__ void tile_slots(int nb, int t0, F&& f) {
   else f(t0, std::integral_constant<int, 1>{});
 }
 constexpr size_t kCuLds = 160 * 1024;       // LDS of one CU
-constexpr size_t kBondStaticLds = 512;      // the bond kernel's static LDS, rounded up
+constexpr size_t kBondStaticLds = 512;      // headroom for static LDS in the occupancy estimate
 
 // Member slots of the staged records: the family padded to whole 16-row
-// tiles plus the quad the member loop loads one step ahead.  Padding slots
-// hold positions at infinity (no membership) and zero features.
-__host__ __device__ constexpr int bond_mx_slots(int max_f) { return ((max_f + 15) & ~15) + 4; }
+// tiles, plus (mixed precision) the quad the member loop loads one step
+// ahead; in FP64 that last, unused look-ahead load falls on the sums that
+// follow the records.  Padding slots hold positions outside every horizon
+// (no membership) and zero features.
+template <class Acc>
+__host__ __device__ constexpr int bond_mx_slots(int max_f) {
+  return ((max_f + 15) & ~15) + (sizeof(Acc) == 8 ? 0 : 4);
+}
 // Rows of the 16 member sums: the family capacity rounded up to whole groups
 // of four, which pass 2 reads without range checks.
 __host__ __device__ constexpr int bond_mx_rows(int max_f) { return (max_f + 3) & ~3; }
+// Bytes of one member slot.  FP64: the record {x_k, V_k, ydot_ik, 1}, with
+// zeta_ik = x_k - x_i formed where it is needed.  Mixed: (x_k, V_k) in FP64 for
+// the membership test beside the record {zeta_ik, V_k, ydot_ik, 1} in FP32.
+template <class Acc>
+__host__ __device__ constexpr size_t bond_mx_slot_bytes() {
+  return sizeof(Acc) == 8 ? 8 * sizeof(double) : sizeof(Quad<double>) + 8 * sizeof(Acc);
+}
 template <class Acc>
 __host__ __device__ constexpr size_t bond_mx_lds_bytes(int max_f) {
-  // (x_k, V_k) in FP64 for the membership test and the member record (zeta_ik,
-  // V_k, ydot_ik, 1) in the sum type per slot; the 16 sums and the membership
-  // bits per member.  The closing reduction reuses the space for 8 doubles
-  // per thread.
-  return (size_t)bond_mx_slots(max_f) * (sizeof(Quad<double>) + 8 * sizeof(Acc)) +
+  // the member slots, the 16 sums and the membership bits per member.  The
+  // closing reduction reuses the space for 8 doubles per thread and the
+  // per-wave partials after them.  The kernel has no static LDS: at family
+  // capacity 128 the FP64 workgroup needs 26 KB, and six fit a CU.
+  return (size_t)bond_mx_slots<Acc>(max_f) * bond_mx_slot_bytes<Acc>() +
                  (size_t)bond_mx_rows(max_f) * 16 * sizeof(Acc) +
                  (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long) >
-             8 * kBondThreads * sizeof(double)
-         ? (size_t)bond_mx_slots(max_f) * (sizeof(Quad<double>) + 8 * sizeof(Acc)) +
+             8 * kBondThreads * sizeof(double) + 128
+         ? (size_t)bond_mx_slots<Acc>(max_f) * bond_mx_slot_bytes<Acc>() +
                (size_t)bond_mx_rows(max_f) * 16 * sizeof(Acc) +
                (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long)
-         : 8 * kBondThreads * sizeof(double);
+         : 8 * kBondThreads * sizeof(double) + 128;
 }
 
 // Feature f of member k (pass 1, B operand): V_k a_f b_f from the record
@@ -1686,29 +1698,29 @@ void k_bond_mx(BondArgs A, DevParams P) {
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
   const int nw = (mf + 63) / 64;                   // membership words per row
-  // (x_k, V_k) in FP64 for the membership test of Eq. 22, which compares
-  // |x_k - x_j| from the positions, beside the member records that hold
-  // zeta_ik (formed in FP64, then rounded to the sum type)
+  // The membership test of Eq. 22 compares |x_k - x_j| from the positions.
+  // FP64: one record {x_k, V_k, ydot_ik, 1} per slot, zeta_ik = x_k - x_i
+  // formed where it is needed.  Mixed: (x_k, V_k) in FP64 beside the record
+  // {zeta_ik, V_k, ydot_ik, 1} in FP32 (zeta formed in FP64, then rounded).
   constexpr bool kF64 = sizeof(Acc) == 8;
-  const int mfp = bond_mx_slots(mf);
-  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);
-  Acc* sR = reinterpret_cast<Acc*>(sX + mfp);                          // 8 per slot: zeta, V, ydot, 1
+  const int mfp = bond_mx_slots<Acc>(mf);
+  Quad<double>* sX = reinterpret_cast<Quad<double>*>(smem_raw);        // mixed only
+  Acc* sR = kF64 ? reinterpret_cast<Acc*>(smem_raw) : reinterpret_cast<Acc*>(sX + mfp);
   Acc* sKN = sR + 8 * (size_t)mfp;                                     // 16 per member: K, N, Vs, then M_j
   unsigned long long* sb = reinterpret_cast<unsigned long long*>(sKN + 16 * (size_t)bond_mx_rows(mf));
   unsigned short* sq = reinterpret_cast<unsigned short*>(sb);
   Quad<TS>* const T4 = reinterpret_cast<Quad<TS>*>(A.T);
-  __shared__ double s_d2;
-  __shared__ double red[kBondWaves][24];
-  __shared__ int redi[kBondWaves][4];
 
   const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
   const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
+  // position of slot m for the membership test
+  auto pos = [&](int m) -> Quad<double> {
+    if constexpr (kF64) return reinterpret_cast<const Quad<double>*>(sR)[2 * m];
+    else return sX[m];
+  };
 
-  if (tid == 0) s_d2 = P.d2;
-
-  // Stage the family of i: x_k and V_k (FP64, for the exact predicate; the
-  // FP64 feature matrix subtracts x_i), ydot_ik, and in mixed precision
-  // zeta_ik formed in FP64 before rounding.
+  // Stage the family of i: x_k and V_k (FP64, for the exact predicate),
+  // ydot_ik, and in mixed precision zeta_ik formed in FP64 before rounding.
   for (int m = tid; m < nf; m += kBondThreads) {
     const int32_t k = A.col[b0 + m];
     const double4 pa = reinterpret_cast<const double4*>(A.xv)[2 * (int64_t)k];
@@ -1716,31 +1728,45 @@ void k_bond_mx(BondArgs A, DevParams P) {
     const double Vk = pa.w;
     const double y0 = pb.x - vi0, y1 = pb.y - vi1, y2 = pb.z - vi2;
     Acc* rec = sR + 8 * (size_t)m;
-    sX[m] = Quad<double>{{pa.x, pa.y, pa.z, Vk}};
-    rec[0] = (Acc)(pa.x - xi0); rec[1] = (Acc)(pa.y - xi1); rec[2] = (Acc)(pa.z - xi2);
+    if constexpr (kF64) {
+      rec[0] = pa.x; rec[1] = pa.y; rec[2] = pa.z;
+    } else {
+      sX[m] = Quad<double>{{pa.x, pa.y, pa.z, Vk}};
+      rec[0] = (Acc)(pa.x - xi0); rec[1] = (Acc)(pa.y - xi1); rec[2] = (Acc)(pa.z - xi2);
+    }
     rec[3] = (Acc)Vk;
     rec[4] = (Acc)y0; rec[5] = (Acc)y1; rec[6] = (Acc)y2; rec[7] = (Acc)1;
   }
   const int ntile = (nf + 15) >> 4;
   const int nks = (nf + 3) >> 2;
   const int nblk = (nks + 15) >> 4;               // bit words per row written by pass 1
-  // padding slots up to whole tiles and the look-ahead quad: positions at
-  // infinity fail every membership test (inf - x = inf, inf - inf = NaN), and
-  // zero features add nothing, so the member loop needs no range checks
-  for (int m = nf + tid; m < max(16 * ntile, 4 * nks + 4); m += kBondThreads) {
-    sX[m] = Quad<double>{{INFINITY, INFINITY, INFINITY, 0.0}};
+  // padding slots up to whole tiles (and the look-ahead quad in mixed
+  // precision): positions outside every horizon fail every membership test
+  // (FP64: 1e6 m away, so that the features V a b stay finite and vanish
+  // with V = 0; mixed: infinity, beside zero features), so the member loop
+  // needs no range checks
+  for (int m = nf + tid; m < (kF64 ? 16 * ntile : max(16 * ntile, 4 * nks + 4)); m += kBondThreads) {
     Acc* rec = sR + 8 * (size_t)m;
 #pragma unroll
     for (int q = 0; q < 8; ++q) rec[q] = (Acc)0;
+    if constexpr (kF64) {
+      rec[0] = xi0 + 1e6; rec[1] = xi1 + 1e6; rec[2] = xi2 + 1e6;
+    } else {
+      sX[m] = Quad<double>{{INFINITY, INFINITY, INFINITY, 0.0}};
+    }
   }
   __syncthreads();
-  const double d2 = s_d2;
+  const double d2 = P.d2;
 
   // ---- pass 1: membership matrix x features on the matrix cores.  Tiles
   // past the family (and rows past nf) carry zero operands; everything in
   // the member loop is branch-free so that tests and products interleave.
   {
     const int fa = feat_a(r16), fb = feat_b(r16);
+    // the FP64 records hold x_k: the zeta features subtract x_i
+    const double xi[3] = {xi0, xi1, xi2};
+    const Acc oa = kF64 && fa < 3 ? (Acc)xi[fa < 3 ? fa : 0] : (Acc)0;
+    const Acc ob = kF64 && fb < 3 ? (Acc)xi[fb < 3 ? fb : 0] : (Acc)0;
     // NB tile slots t0, t0 + kBondWaves, ... of one wave, all inside the family
     auto tiles = [&](int t0, auto nbc) {
       constexpr int NB = decltype(nbc)::value;
@@ -1753,19 +1779,19 @@ void k_bond_mx(BondArgs A, DevParams P) {
       for (int b = 0; b < NB; ++b) {
         jrow[b] = (t0 + kBondWaves * b) * 16 + r16;
         jv[b] = jrow[b] < nf;
-        const Quad<double> q = sX[jrow[b]];          // a padding slot past the family
+        const Quad<double> q = pos(jrow[b]);         // a padding slot past the family
         xj[b][0] = q.v[0]; xj[b][1] = q.v[1]; xj[b][2] = q.v[2];
         acc[b] = V4{0, 0, 0, 0};
         piece[b] = 0u;
       }
       // member data of the next step is loaded one step ahead
-      Quad<double> xk = sX[q4];
-      Acc ra = sR[8 * (size_t)q4 + fa], rb = sR[8 * (size_t)q4 + fb], rv = sR[8 * (size_t)q4 + 3];
+      Quad<double> xk = pos(q4);
+      Acc ra = sR[8 * (size_t)q4 + fa] - oa, rb = sR[8 * (size_t)q4 + fb] - ob, rv = sR[8 * (size_t)q4 + 3];
       for (int ks = 0; ks < nks; ++ks) {
         const int k1 = 4 * (ks + 1) + q4;
-        const Quad<double> xk1 = sX[k1];
+        const Quad<double> xk1 = pos(k1);
         const Acc* rec1 = sR + 8 * (size_t)k1;
-        const Acc ra1 = rec1[fa], rb1 = rec1[fb], rv1 = rec1[3];
+        const Acc ra1 = rec1[fa] - oa, rb1 = rec1[fb] - ob, rv1 = rec1[3];
         const Acc bval = ra * rb * rv;
         const unsigned sbit = 1u << (ks & 15);
 #pragma unroll
@@ -1909,10 +1935,12 @@ void k_bond_mx(BondArgs A, DevParams P) {
                           sgb[5] * ixy + S11 * iyy + sgb[3] * iyz, sgb[5] * ixz + S11 * iyz + sgb[3] * izz,
                           sgb[4] * ixx + sgb[3] * ixy + S22 * ixz, sgb[4] * ixy + sgb[3] * iyy + S22 * iyz,
                           sgb[4] * ixz + sgb[3] * iyz + S22 * izz};
-    const double Vj = sX[m].v[3];
+    const double Vj = kF64 ? (double)sR[8 * (size_t)m + 3] : sX[m].v[3];
     if (P.force_mode == ULPPM_FORCE_EQ51) {
       // Eq. 51 as printed: T_ij = varpi (sigma_ij + Sr s 1) K_ij^{-1} zeta_ij.
-      const double zx = sR[8 * (size_t)m], zy = sR[8 * (size_t)m + 1], zz = sR[8 * (size_t)m + 2];
+      const double zx = kF64 ? sR[8 * (size_t)m] - xi0 : (double)sR[8 * (size_t)m];
+      const double zy = kF64 ? sR[8 * (size_t)m + 1] - xi1 : (double)sR[8 * (size_t)m + 1];
+      const double zz = kF64 ? sR[8 * (size_t)m + 2] - xi2 : (double)sR[8 * (size_t)m + 2];
       T4[slot] = Quad<TS>{{(TS)(varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz)),
                            (TS)(varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz)),
                            (TS)(varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz)), (TS)0}};
@@ -2004,7 +2032,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
       const int m = wid == 0 ? ka : kb;
       if (m < nf) {
         const Acc* zm = sR + 8 * (size_t)m;
-        const Acc zx = zm[0], zy = zm[1], zz = zm[2];
+        const Acc zx = zm[0] - xi0, zy = zm[1] - xi1, zz = zm[2] - xi2;
         const Acc t0 = S[0] * zx + S[1] * zy + S[2] * zz, t1 = S[3] * zx + S[4] * zy + S[5] * zz,
                   t2 = S[6] * zx + S[7] * zy + S[8] * zz;
         T4[b0 + m] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
@@ -2041,7 +2069,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
           }
         }
         const Acc* zm = sR + 8 * (size_t)m;
-        const Acc zx = zm[0], zy = zm[1], zz = zm[2];
+        const Acc zx = zm[0] - xi0, zy = zm[1] - xi1, zz = zm[2] - xi2;
         const int64_t slot = b0 + m;
         const Acc t0 = a0 * zx + a1 * zy + a2 * zz, t1 = a3 * zx + a4 * zy + a5 * zz, t2 = a6 * zx + a7 * zy + a8 * zz;
         T4[slot] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
@@ -2119,6 +2147,8 @@ void k_bond_mx(BondArgs A, DevParams P) {
   // per wave.
   __syncthreads();   // the family's working set is no longer read
   double* hred = reinterpret_cast<double*>(smem_raw);              // [8][kBondThreads]
+  double (*red)[4] = reinterpret_cast<double (*)[4]>(hred + 8 * kBondThreads);   // [waves][4]
+  int (*redi)[4] = reinterpret_cast<int (*)[4]>(hred + 8 * kBondThreads + 4 * kBondWaves);
 #pragma unroll
   for (int k = 0; k < 6; ++k) hred[k * kBondThreads + tid] = hs[k];
   hred[6 * kBondThreads + tid] = hpc;
@@ -2126,8 +2156,8 @@ void k_bond_mx(BondArgs A, DevParams P) {
   for (int c = 0; c < 3; ++c) own[c] = wave_sum(own[c]);
   if (lane == 0) {
     redi[wid][0] = n_deg; redi[wid][1] = n_pl; redi[wid][2] = n_nc; redi[wid][3] = n_trip;
-    red[wid][8] = (double)mx;
-    red[wid][9] = own[0]; red[wid][10] = own[1]; red[wid][11] = own[2];
+    red[wid][0] = (double)mx;
+    red[wid][1] = own[0]; red[wid][2] = own[1]; red[wid][3] = own[2];
   }
   __syncthreads();
   if (wid == 0) {
@@ -2150,7 +2180,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
     long long d = 0, pl = 0, nc = 0, tr = 0, m2 = 0;
     for (int w = 0; w < kBondWaves; ++w) {
       d += redi[w][0]; pl += redi[w][1]; nc += redi[w][2]; tr += redi[w][3];
-      m2 = m2 > (long long)red[w][8] ? m2 : (long long)red[w][8];
+      m2 = m2 > (long long)red[w][0] ? m2 : (long long)red[w][0];
     }
     if (W > 0.0) {
       for (int k = 0; k < 6; ++k) A.sig_out[k][i] = hsum[k] / W;
@@ -2162,7 +2192,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
     if (A.fown) {
       double o[3] = {0.0, 0.0, 0.0};
       for (int w = 0; w < kBondWaves; ++w)
-        for (int c = 0; c < 3; ++c) o[c] += red[w][9 + c];
+        for (int c = 0; c < 3; ++c) o[c] += red[w][1 + c];
       for (int c = 0; c < 3; ++c) A.fown[c * n + i] = o[c];
     }
     if (d) ctr_add(A.ctr, C_DEGEN, (unsigned long long)d);
