@@ -56,14 +56,16 @@ namespace {
 #define ULPPM_BOND_THREADS 128
 #endif
 // Waves per SIMD the bond kernel is compiled for: two by default (no spills);
-// the mixed instance, and the FP64 one when the family capacity leaves LDS
-// for five or more workgroups per CU, are compiled for three, which gains
-// more from the extra wave than it loses to spilled registers.
+// the FP64 one is compiled for three when the family capacity leaves LDS for
+// five or more workgroups per CU, and the mixed one (whose LDS is smaller)
+// for four.  The kernel waits on LDS and on dependent FP64 chains, and each
+// extra wave gains more than it loses to spilled registers (C1, mixed: 2.18
+// ms at three waves, 2.02 ms at four with 85 spilled registers).
 #ifndef ULPPM_BOND_MX_MIN_WAVES
 #define ULPPM_BOND_MX_MIN_WAVES 2
 #endif
 #ifndef ULPPM_BOND_MX_MIN_WAVES_MIXED
-#define ULPPM_BOND_MX_MIN_WAVES_MIXED 3
+#define ULPPM_BOND_MX_MIN_WAVES_MIXED 4
 #endif
 #ifndef ULPPM_ADJ_MIN_WAVES
 #define ULPPM_ADJ_MIN_WAVES 2
