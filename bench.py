@@ -311,26 +311,30 @@ def main():
                            max_family=max_family or 152, largest_family=rep["max_family"],
                            dt=dt, suction_kpa=col["suction_kpa"], seed=cfg.seed, precision=args.precision),
                roofline=roofline, phase_ms=phases)
+    def run_cap(c, precision=prec, **kw):
+        # the main run's family capacity, or the default where a family outgrows it
+        try:
+            return run_column(ulppm, c, precision, args.warmup, args.steps, max_family=max_family, **kw) + (max_family,)
+        except ulppm.UlppmError as e:
+            if e.code != -2 or max_family == 0:
+                raise
+            return run_column(ulppm, c, precision, args.warmup, args.steps, **kw) + (0,)
+
     if args.precision == "fp64" and not args.no_mixed:
-        # the same run in mixed precision from the same initial state
-        Gm, repm, msm, _ = run_column(ulppm, col, ulppm.ULPPM_MIXED, args.warmup, args.steps)
+        # the same run in mixed precision from the same initial state, at the same family capacity
+        Gm, repm, msm, _, capm = run_cap(col, precision=ulppm.ULPPM_MIXED)
         vm = repm["n_bond_updates"] / (msm * 1e-3)
+        lm = max(repm["timed_steps"], 1)
         out["mixed"] = dict(value=vm, ms_per_step=msm / args.steps, speedup=round(vm / value, 3),
-                            steps_compared=args.warmup + args.steps,
+                            max_family=capm or 152, steps_compared=args.warmup + args.steps,
                             u_rel_l2=rel_l2(Gm["u"], G["u"]), sig_rel_l2=rel_l2(Gm["sig"], G["sig"]),
-                            v_rel_l2=rel_l2(Gm["v"], G["v"]))
+                            v_rel_l2=rel_l2(Gm["v"], G["v"]),
+                            phase_ms={k: round(repm[f"t_{k}_ms"] / lm, 4)
+                                      for k in ("predict", "family", "kin", "bond", "gather")})
         log(f"[gpu] mixed: {out['mixed']}")
         del Gm
     del G
     torch.cuda.empty_cache()
-    def run_cap(c, **kw):
-        # the main run's family capacity, or the default where a family outgrows it
-        try:
-            return run_column(ulppm, c, prec, args.warmup, args.steps, max_family=max_family, **kw) + (max_family,)
-        except ulppm.UlppmError as e:
-            if e.code != -2 or max_family == 0:
-                raise
-            return run_column(ulppm, c, prec, args.warmup, args.steps, **kw) + (0,)
 
     if not args.no_contact:
         colc = inputs.make_column(cfg, fixed_base=False)

@@ -55,18 +55,6 @@ namespace {
 #ifndef ULPPM_BOND_THREADS
 #define ULPPM_BOND_THREADS 128
 #endif
-// Waves per SIMD the bond kernel is compiled for: two by default (no spills);
-// the FP64 one is compiled for three when the family capacity leaves LDS for
-// five or more workgroups per CU, and the mixed one (whose LDS is smaller)
-// for four.  The kernel waits on LDS and on dependent FP64 chains, and each
-// extra wave gains more than it loses to spilled registers (C1, mixed: 2.18
-// ms at three waves, 2.02 ms at four with 85 spilled registers).
-#ifndef ULPPM_BOND_MX_MIN_WAVES
-#define ULPPM_BOND_MX_MIN_WAVES 2
-#endif
-#ifndef ULPPM_BOND_MX_MIN_WAVES_MIXED
-#define ULPPM_BOND_MX_MIN_WAVES_MIXED 4
-#endif
 #ifndef ULPPM_ADJ_MIN_WAVES
 #define ULPPM_ADJ_MIN_WAVES 2
 #endif
@@ -1679,12 +1667,15 @@ __host__ __device__ constexpr int feat_b(int f) {
 }
 
 // NT threads per workgroup (one point): 128 for 3D families of ~100, 64 when
-// every family fits one wave (plane strain).  MW: waves per SIMD the FP64
-// instance is compiled for: 2 by default, 3 when the family capacity leaves
-// LDS for more than two waves per SIMD (five two-wave or ten one-wave
-// workgroups per CU; the extra wave then outweighs the registers it spills).
-template <class Acc, bool Hist, int NT, int MW = ULPPM_BOND_MX_MIN_WAVES>
-__global__ __launch_bounds__(NT, sizeof(Acc) == 8 ? MW : ULPPM_BOND_MX_MIN_WAVES_MIXED)
+// every family fits one wave (plane strain).  MW: waves per SIMD the instance
+// is compiled for, chosen on the host from the workgroups the LDS of the
+// family capacity lets a CU hold (bond_waves).  The kernel waits on LDS and on
+// dependent FP64 chains, so a wave more gains more than it loses to spilled
+// registers (C1, mixed: 2.18 ms at three waves, 2.02 ms at four with 85
+// spilled registers); an instance compiled for more waves than the LDS
+// admits would only spill.
+template <class Acc, bool Hist, int NT, int MW>
+__global__ __launch_bounds__(NT, MW)
 void k_bond_mx(BondArgs A, DevParams P) {
   constexpr int kBondThreads = NT, kBondWaves = NT / kWave;
   using TS = Acc;
@@ -3451,6 +3442,16 @@ static bool own_sums(const ulppm_ctx* ctx, const ulppm_params* p) {
 size_t bond_lds(int max_f, bool mixed) {
   return mixed ? bond_mx_lds_bytes<float>(max_f) : bond_mx_lds_bytes<double>(max_f);
 }
+// Waves per SIMD the bond kernel's LDS (lds bytes per workgroup of nt
+// threads) admits, capped at the instances built: three for FP64 (reached
+// from five workgroups of two waves, 2.5 waves per SIMD on average, where the
+// third wave still pays), four for mixed precision.
+int bond_waves(size_t lds, int nt, bool mixed) {
+  const int wg = (int)(kCuLds / (lds + kBondStaticLds));       // workgroups per CU
+  const int waves = wg * (nt / kWave);                          // per CU, four SIMDs
+  if (mixed) return waves >= 16 ? 4 : 3;
+  return waves >= 10 ? 3 : 2;
+}
 
 // Algorithm 1 (bond pass) into outputs; mode: step (state outputs) or not.
 // mark(0) / mark(1) bracket the point-kinematics kernels when timing.
@@ -3513,24 +3514,32 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   }
   const unsigned grid = (unsigned)(8 * A.per);
   const bool one_wave = ctx->max_f <= kWave;             // every family fits one wave
-  if (mixed && hist)
-    k_bond_mx<float, true, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  const int nt = one_wave && !hist ? kWave : kBondThreads;  // the history instances run two waves
+  const bool more = bond_waves(lds, nt, mixed) > (mixed ? 3 : 2);
+  if (mixed && hist && more)
+    k_bond_mx<float, true, kBondThreads, 4><<<grid, nt, lds, ctx->stream>>>(A, P);
+  else if (mixed && hist)
+    k_bond_mx<float, true, kBondThreads, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
+  else if (mixed && one_wave && more)
+    k_bond_mx<float, false, kWave, 4><<<grid, nt, lds, ctx->stream>>>(A, P);
   else if (mixed && one_wave)
-    k_bond_mx<float, false, kWave><<<grid, kWave, lds, ctx->stream>>>(A, P);
+    k_bond_mx<float, false, kWave, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
+  else if (mixed && more)
+    k_bond_mx<float, false, kBondThreads, 4><<<grid, nt, lds, ctx->stream>>>(A, P);
   else if (mixed)
-    k_bond_mx<float, false, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
-  else if (hist && kCuLds / (lds + kBondStaticLds) >= 5)
-    k_bond_mx<double, true, kBondThreads, 3><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+    k_bond_mx<float, false, kBondThreads, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
+  else if (hist && more)
+    k_bond_mx<double, true, kBondThreads, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
   else if (hist)
-    k_bond_mx<double, true, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
-  else if (one_wave && kCuLds / (lds + kBondStaticLds) >= 10)
-    k_bond_mx<double, false, kWave, 3><<<grid, kWave, lds, ctx->stream>>>(A, P);
+    k_bond_mx<double, true, kBondThreads, 2><<<grid, nt, lds, ctx->stream>>>(A, P);
+  else if (one_wave && more)
+    k_bond_mx<double, false, kWave, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
   else if (one_wave)
-    k_bond_mx<double, false, kWave><<<grid, kWave, lds, ctx->stream>>>(A, P);
-  else if (kCuLds / (lds + kBondStaticLds) >= 5)
-    k_bond_mx<double, false, kBondThreads, 3><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+    k_bond_mx<double, false, kWave, 2><<<grid, nt, lds, ctx->stream>>>(A, P);
+  else if (more)
+    k_bond_mx<double, false, kBondThreads, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
   else
-    k_bond_mx<double, false, kBondThreads><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+    k_bond_mx<double, false, kBondThreads, 2><<<grid, nt, lds, ctx->stream>>>(A, P);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
@@ -3848,15 +3857,19 @@ void context_buffers(ulppm_ctx* ctx, Alloc&& A) {
 
 // The bond kernel's dynamic LDS may exceed the default cap for large max_family.
 void set_bond_lds_limits(int max_family) {
-  for (const void* k : {(const void*)k_bond_mx<double, false, kBondThreads>,
+  for (const void* k : {(const void*)k_bond_mx<double, false, kBondThreads, 2>,
                         (const void*)k_bond_mx<double, false, kBondThreads, 3>,
-                        (const void*)k_bond_mx<double, true, kBondThreads>,
-                        (const void*)k_bond_mx<double, false, kWave>,
+                        (const void*)k_bond_mx<double, true, kBondThreads, 2>,
+                        (const void*)k_bond_mx<double, true, kBondThreads, 3>,
+                        (const void*)k_bond_mx<double, false, kWave, 2>,
                         (const void*)k_bond_mx<double, false, kWave, 3>})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, false));
-  for (const void* k : {(const void*)k_bond_mx<float, false, kBondThreads>,
-                        (const void*)k_bond_mx<float, true, kBondThreads>,
-                        (const void*)k_bond_mx<float, false, kWave>})
+  for (const void* k : {(const void*)k_bond_mx<float, false, kBondThreads, 3>,
+                        (const void*)k_bond_mx<float, false, kBondThreads, 4>,
+                        (const void*)k_bond_mx<float, true, kBondThreads, 3>,
+                        (const void*)k_bond_mx<float, true, kBondThreads, 4>,
+                        (const void*)k_bond_mx<float, false, kWave, 3>,
+                        (const void*)k_bond_mx<float, false, kWave, 4>})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, true));
 }
 
