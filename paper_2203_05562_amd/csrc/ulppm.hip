@@ -2526,27 +2526,8 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   // Tbar_ik = V_i V_k (fbar_i - fbar_k); zeta_bar_ik = A_ik^T Tbar_ik with
   // A_ik = sum_j B_kj M_j; volume adjoints of the gather.
   double ownV = 0.0;
-  for (int m = tid; m < nf; m += kBondThreads) {
-    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    // members 64 c + 4 s + q in groups of four (bits 16 q + s of word c);
-    // rows past the family are clamped and enter with weight 0
-    for (int c = 0; 64 * c < nf; ++c) {
-      const unsigned long long word = sb[(size_t)m * nw + c];
-      const unsigned lo = (unsigned)word, hi = (unsigned)(word >> 32);
-      for (int s4 = 0; s4 < 16; ++s4) {
-        const int j0 = 64 * c + 4 * s4;
-        if (j0 >= nf) break;
-        MRec<double> r4[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) r4[q] = sM[j0 + q < nf ? j0 + q : nf - 1];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double w = (double)(((q < 2 ? lo : hi) >> (16 * (q & 1) + s4)) & 1u);
-#pragma unroll
-          for (int e = 0; e < 9; ++e) a[e] += w * r4[q].v[e];
-        }
-      }
-    }
+  // the reverse of the gather for member m, given A_ik
+  auto gather_reverse = [&](int m, const double* a) {
     const int64_t slot = b0 + m;
     const int32_t k = A.col[slot];
     const double Vk = sZ[m].v[3];
@@ -2569,6 +2550,89 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     zb.v[3] = Vi * e;                               // to Vbar_k
     for (int c = 0; c < 3; ++c) A.slot_x[c * A.cap + slot] = zb.v[c];
     A.slot_V[slot] = zb.v[3];
+  };
+  if (kBondWaves == 2 && nf <= 2 * kWave && (size_t)mf * sizeof(MRec<double>) >= 18 * kWave * sizeof(double)) {
+    // Two members per lane (k = lane and lane + 64), the groups of rows split
+    // between the waves, which then hand each other the partial sums of the
+    // member the other finishes (as the forward pass 2).  Rows past the family
+    // are clamped and enter with weight 0.
+    const int gh = (nks + 1) / 2;
+    const int g0 = wid == 0 ? 0 : gh, g1 = wid == 0 ? gh : nks;
+    const int ka = lane, kb = lane + kWave;
+    const bool va = ka < nf, vb = kb < nf;
+    double Pa[9], Pb[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Pa[e] = Pb[e] = 0.0;
+    unsigned long long wa = 0ull, wb = 0ull;
+    for (int g = g0; g < g1; ++g) {
+      const int s4 = g & 15, j0 = 4 * g;
+      if (g == g0 || s4 == 0) {
+        const unsigned long long xa = sb[(size_t)(va ? ka : 0) * nw + (g >> 4)];
+        const unsigned long long xb = sb[(size_t)(vb ? kb : 0) * nw + (g >> 4)];
+        wa = va ? xa : 0ull;
+        wb = vb ? xb : 0ull;
+      }
+      MRec<double> r4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r4[q] = sM[j0 + q < nf ? j0 + q : nf - 1];
+      const unsigned la = (unsigned)wa, ha = (unsigned)(wa >> 32);
+      const unsigned lb = (unsigned)wb, hb = (unsigned)(wb >> 32);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int sh = 16 * (q & 1) + s4;
+        const double w0 = (double)(((q < 2 ? la : ha) >> sh) & 1u);
+        const double w1 = (double)(((q < 2 ? lb : hb) >> sh) & 1u);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+          Pa[e] += w0 * r4[q].v[e];
+          Pb[e] += w1 * r4[q].v[e];
+        }
+      }
+    }
+    __syncthreads();                               // every row M_j has been read
+    double* xch = reinterpret_cast<double*>(sM);   // [18][64]; sM is free until the G/H sweep
+    if (wid == 0) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) xch[(size_t)(9 + e) * kWave + lane] = Pb[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) xch[(size_t)e * kWave + lane] = Pa[e];
+    }
+    __syncthreads();
+    double a[9];
+    if (wid == 0) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) a[e] = Pa[e] + xch[(size_t)e * kWave + lane];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) a[e] = Pb[e] + xch[(size_t)(9 + e) * kWave + lane];
+    }
+    const int m = wid == 0 ? ka : kb;
+    if (m < nf) gather_reverse(m, a);
+  } else {
+    for (int m = tid; m < nf; m += kBondThreads) {
+      double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      // members 64 c + 4 s + q in groups of four (bits 16 q + s of word c);
+      // rows past the family are clamped and enter with weight 0
+      for (int c = 0; 64 * c < nf; ++c) {
+        const unsigned long long word = sb[(size_t)m * nw + c];
+        const unsigned lo = (unsigned)word, hi = (unsigned)(word >> 32);
+        for (int s4 = 0; s4 < 16; ++s4) {
+          const int j0 = 64 * c + 4 * s4;
+          if (j0 >= nf) break;
+          MRec<double> r4[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) r4[q] = sM[j0 + q < nf ? j0 + q : nf - 1];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double w = (double)(((q < 2 ? lo : hi) >> (16 * (q & 1) + s4)) & 1u);
+#pragma unroll
+            for (int e = 0; e < 9; ++e) a[e] += w * r4[q].v[e];
+          }
+        }
+      }
+      gather_reverse(m, a);
+    }
   }
   __syncthreads();
 
