@@ -2636,6 +2636,83 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   }
   __syncthreads();
 
+  // ---- Mbar_j = sum_k B_jk Tbar_ik zeta_ik^T for every bond, before the
+  // tail: two members per lane with the groups split between the waves, as
+  // above; the sums land in sM (free until the G/H sweep) for the tail.
+  const bool mbar_swept = kBondWaves == 2 && nf <= 2 * kWave &&
+                          (size_t)mf * sizeof(MRec<double>) >= 18 * kWave * sizeof(double);
+  if (mbar_swept) {
+    const int gh = (nks + 1) / 2;
+    const int g0 = wid == 0 ? 0 : gh, g1 = wid == 0 ? gh : nks;
+    const int ka = lane, kb = lane + kWave;
+    const bool va = ka < nf, vb = kb < nf;
+    double Pa[9], Pb[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Pa[e] = Pb[e] = 0.0;
+    unsigned long long wa = 0ull, wb = 0ull;
+    for (int g = g0; g < g1; ++g) {
+      const int s4 = g & 15, t0 = 4 * g;
+      if (g == g0 || s4 == 0) {
+        const unsigned long long xa = sb[(size_t)(va ? ka : 0) * nw + (g >> 4)];
+        const unsigned long long xb = sb[(size_t)(vb ? kb : 0) * nw + (g >> 4)];
+        wa = va ? xa : 0ull;
+        wb = vb ? xb : 0ull;
+      }
+      Quad<double> tb4[4], z4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = t0 + q < nf ? t0 + q : nf - 1;
+        tb4[q] = sTb[t];
+        z4[q] = sZ[t];
+      }
+      const unsigned la = (unsigned)wa, ha = (unsigned)(wa >> 32);
+      const unsigned lb = (unsigned)wb, hb = (unsigned)(wb >> 32);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int sh = 16 * (q & 1) + s4;
+        const double w0 = (double)(((q < 2 ? la : ha) >> sh) & 1u);
+        const double w1 = (double)(((q < 2 ? lb : hb) >> sh) & 1u);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const double t0a = w0 * tb4[q].v[r], t0b = w1 * tb4[q].v[r];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            Pa[3 * r + c] += t0a * z4[q].v[c];
+            Pb[3 * r + c] += t0b * z4[q].v[c];
+          }
+        }
+      }
+    }
+    __syncthreads();                               // sM is free: M_j was last read by the A_k sweep
+    double* xch = reinterpret_cast<double*>(sM);   // [18][64]
+    if (wid == 0) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) xch[(size_t)(9 + e) * kWave + lane] = Pb[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) xch[(size_t)e * kWave + lane] = Pa[e];
+    }
+    __syncthreads();
+    double mbs[9];
+    if (wid == 0) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) mbs[e] = Pa[e] + xch[(size_t)e * kWave + lane];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) mbs[e] = Pb[e] + xch[(size_t)(9 + e) * kWave + lane];
+    }
+    __syncthreads();
+    const int m = wid == 0 ? ka : kb;
+    if (m < nf) {
+      MRec<double> r;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) r.v[e] = mbs[e];
+      r.v[9] = 0.0;
+      sM[m] = r;
+    }
+    __syncthreads();
+  }
+
   // ---- reverse of the force states (R5) and of the bond tail
   const double sgb1[6] = {A.sigb1[0][i], A.sigb1[1][i], A.sigb1[2][i], A.sigb1[3][i], A.sigb1[4][i], A.sigb1[5][i]};
   const double pcb1 = A.pcb1[i];
@@ -2648,9 +2725,14 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     const bool active = kn[15] != 0.0;
     double Kb[6] = {0, 0, 0, 0, 0, 0}, Nb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (active) {
-      // Mbar_j = sum_k B_jk Tbar_ik zeta_ik^T
+      // Mbar_j = sum_k B_jk Tbar_ik zeta_ik^T (swept above, or here one bond per lane)
       double mb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      for (int c = 0; 64 * c < nf; ++c) {             // members in groups of four, as above
+      if (mbar_swept) {
+        const MRec<double> r = sM[m];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) mb[e] = r.v[e];
+      }
+      for (int c = 0; !mbar_swept && 64 * c < nf; ++c) {   // members in groups of four, as above
         const unsigned long long word = sb[(size_t)m * nw + c];
         const unsigned lo = (unsigned)word, hi = (unsigned)(word >> 32);
         for (int s4 = 0; s4 < 16; ++s4) {
