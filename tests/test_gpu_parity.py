@@ -472,6 +472,35 @@ def test_C1_bench_configuration(olib, gpu):
         compare_states(G.to_arrays(), S, tol, label=f"C1 precision {prec}")
 
 
+def test_C3_trajectory_200_steps(olib, gpu):
+    """Long-run agreement at a larger size: the 24 x 24 x 48 column (27,648
+    points) at family capacity 128, 200 FP64 steps against 200 oracle steps
+    at the 1e-10 bar, and the same 200 steps in mixed precision at 1e-4."""
+    import time
+    say("C3 200 steps, capacity 128")
+    col = inputs.make_column(inputs.CONFIGS["C3"])
+    oprm = olib.make_params(col["params"])
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    S0 = olib.copy_state(S)
+    t0 = time.time()
+    E = np.zeros(3)
+    rc, E, st = olib.step(S, oprm, 200, E)
+    assert rc == 0
+    say(f"oracle 200 steps {time.time() - t0:.1f}s, plastic {st['n_plastic']}")
+    ctx = gpu.Context(col["n"], max_family=128)
+    for prec, tol, fields in ((gpu.ULPPM_FP64, 1e-10, ("u", "v", "sig", "pc", "J", "a", "mass", "Sr")),
+                              (gpu.ULPPM_MIXED, 1e-4, ("u", "v", "sig", "pc", "J"))):
+        gprm = gpu.make_params(olib.params_dict(oprm), precision=prec)
+        G = gpu.DeviceState.from_arrays(S0)
+        rep = ctx.step(G, gprm, 200)
+        assert rep["n_bond_updates"] == st["n_bonds"] or prec == gpu.ULPPM_MIXED
+        compare_states(G.to_arrays(), S, tol, fields=fields, label=f"C3 200 steps precision {prec}")
+        if prec == gpu.ULPPM_FP64:
+            assert rep["n_triples"] == st["n_triples"]
+            assert abs(rep["W_ext"] - E[1]) <= 1e-9 * abs(E[1])
+
+
 def test_C1_mixed_against_fp64_200_steps(gpu):
     """Mixed precision on the 40 x 40 x 80 column (128,000 points, capacity
     128) against the FP64 run from the same initial state after 200 steps:
@@ -615,7 +644,7 @@ def test_one_wave_bond_kernel_small_horizon(olib, gpu, precision):
     G = gpu.DeviceState.from_arrays(S)
     rc, E, st = olib.step(S, oprm, 100)
     assert rc == 0
-    rep = ctx.step(G, gprm, 100)
+    rep = ctx.step(G, gprm, 200)
     assert rep["max_family"] <= 64
     Sg = G.to_arrays()
     compare_states(Sg, S, 1e-10 if precision == "fp64" else 1e-4, fields=("u", "v", "sig", "pc", "J"),
