@@ -644,7 +644,7 @@ def test_one_wave_bond_kernel_small_horizon(olib, gpu, precision):
     G = gpu.DeviceState.from_arrays(S)
     rc, E, st = olib.step(S, oprm, 100)
     assert rc == 0
-    rep = ctx.step(G, gprm, 200)
+    rep = ctx.step(G, gprm, 100)
     assert rep["max_family"] <= 64
     Sg = G.to_arrays()
     compare_states(Sg, S, 1e-10 if precision == "fp64" else 1e-4, fields=("u", "v", "sig", "pc", "J"),
