@@ -741,12 +741,17 @@ __global__ __launch_bounds__(256) void k_compact(int64_t n, int max_c, int max_f
 // slope dP/dp_c (Eq. 89).  With b1 = 0 and b2 = 1 they are p_c and 1, taken
 // without the transcendental calls (the Newton iterations of the plastic
 // bonds evaluate both every iteration).
+// LinP: the exponents b1 = 0, b2 = 1, where the apparent pre-consolidation is
+// p_c itself.  Code compiled for that case carries none of the registers of
+// the general power (the bond kernel's return map is its register peak).
+template <bool LinP = false>
 __host__ __device__ __forceinline__ double apparent_pc(const DevParams& P, double pc) {
-  if (P.b1 == 0.0 && P.b2 == 1.0) return pc;
+  if (LinP || (P.b1 == 0.0 && P.b2 == 1.0)) return pc;
   return -exp(P.b1) * pow(-pc, P.b2);               // Eq. 45
 }
+template <bool LinP = false>
 __host__ __device__ __forceinline__ double apparent_pc_slope(const DevParams& P, double pc) {
-  if (P.b1 == 0.0 && P.b2 == 1.0) return 1.0;
+  if (LinP || (P.b1 == 0.0 && P.b2 == 1.0)) return 1.0;
   return P.b2 * exp(P.b1) * pow(-pc, P.b2 - 1.0);   // Eq. 89
 }
 
@@ -769,11 +774,14 @@ __host__ __device__ double swrc(const DevParams& P, double J, double phi, double
 // p_c solves p_c = p_c,n exp(-g (2 p_tr - P(p_c)) / ((lam - kap)(1 + 2 K g))),
 // a strictly increasing equation in p_c; g itself is the root of
 // g - c f(p, q, P) on [0, inf), where it changes sign once.
+template <bool LinP>
 struct ConsistencySolve {
   double K, mu, M2, lk, b1, b2, c, ptr, qtr, pcn;
-  __host__ __device__ double Pb(double pc) const { return b1 == 0.0 && b2 == 1.0 ? pc : -exp(b1) * pow(-pc, b2); }
+  __host__ __device__ double Pb(double pc) const {
+    return LinP || (b1 == 0.0 && b2 == 1.0) ? pc : -exp(b1) * pow(-pc, b2);
+  }
   __host__ __device__ double dPb(double pc) const {
-    return b1 == 0.0 && b2 == 1.0 ? 1.0 : b2 * exp(b1) * pow(-pc, b2 - 1.0);
+    return LinP || (b1 == 0.0 && b2 == 1.0) ? 1.0 : b2 * exp(b1) * pow(-pc, b2 - 1.0);
   }
   __host__ __device__ double pc_for(double g) const {
     const double A = g / (lk * (1.0 + 2.0 * K * g));
@@ -830,6 +838,7 @@ struct ConsistencySolve {
 // count (0 elastic) or -1.
 // Pn: the apparent pre-consolidation of pcn (Eq. 45), the same for every
 // bond of a point.
+template <bool LinP = false>
 __host__ __device__ int return_map_pn(const DevParams& P, double dt, const double* sn, double pcn, double Pn,
                                       const double* de, double* so, double* pco) {
   constexpr double kThird = 1.0 / 3.0;
@@ -857,8 +866,8 @@ __host__ __device__ int return_map_pn(const DevParams& P, double dt, const doubl
   int it = 0;
   bool conv = false, stalled = false;
   for (;;) {
-    const double Pb = apparent_pc(P, pc);
-    const double dP = apparent_pc_slope(P, pc);                  // Eq. 89
+    const double Pb = apparent_pc<LinP>(P, pc);
+    const double dP = apparent_pc_slope<LinP>(P, pc);            // Eq. 89
     const double f = yield_f(P, p, q, Pb);
     const double fp = 2.0 * p - Pb, fq = 2.0 * q / M2, fc = -p * dP;
     const double E = exp(-c * f * fp / lk);
@@ -870,13 +879,13 @@ __host__ __device__ int return_map_pn(const DevParams& P, double dt, const doubl
       break;
     }
     if (it >= P.newton_maxit || stalled) {
-      ConsistencySolve B{P.K, P.mu, M2, lk, P.b1, P.b2, c, ptr, qtr, pcn};
+      ConsistencySolve<LinP> B{P.K, P.mu, M2, lk, P.b1, P.b2, c, ptr, qtr, pcn};
       double xb[3];
       B.solve(yield_f(P, ptr, qtr, Pn), xb);
       p = xb[0];
       q = xb[1];
       pc = xb[2];
-      const double Pb2 = apparent_pc(P, pc);
+      const double Pb2 = apparent_pc<LinP>(P, pc);
       const double f2 = yield_f(P, p, q, Pb2), fp2 = 2.0 * p - Pb2;
       const double e1 = p - ptr + P.K * c * f2 * fp2;
       const double e2 = q - qtr + 3.0 * P.mu * c * f2 * 2.0 * q / M2;
@@ -903,7 +912,7 @@ __host__ __device__ int return_map_pn(const DevParams& P, double dt, const doubl
     double stp = 1.0;
     for (int h = 0; h < 60; ++h) {
       const double pt = p + stp * dx1, qt = q + stp * dx2, ct = pc + stp * dx3;
-      if (ct < 0.0 && qt >= 0.0 && yield_f(P, pt, qt, apparent_pc(P, ct)) > 0.0) break;
+      if (ct < 0.0 && qt >= 0.0 && yield_f(P, pt, qt, apparent_pc<LinP>(P, ct)) > 0.0) break;
       stp *= 0.5;
     }
     p += stp * dx1;
@@ -1671,10 +1680,11 @@ __host__ __device__ constexpr int feat_b(int f) {
 // is compiled for, chosen on the host from the workgroups the LDS of the
 // family capacity lets a CU hold (bond_waves).  The kernel waits on LDS and on
 // dependent FP64 chains, so a wave more gains more than it loses to spilled
-// registers (C1, mixed: 2.18 ms at three waves, 2.02 ms at four with 85
-// spilled registers); an instance compiled for more waves than the LDS
-// admits would only spill.
-template <class Acc, bool Hist, int NT, int MW>
+// registers; an instance compiled for more waves than the LDS admits would
+// only spill.  LinP: the run's apparent pre-consolidation is linear (Eq. 45
+// with b1 = 0, b2 = 1), which takes the general power, the register peak of
+// the return map, out of the instance.
+template <class Acc, bool Hist, bool LinP, int NT, int MW>
 __global__ __launch_bounds__(NT, MW)
 void k_bond_mx(BondArgs A, DevParams P) {
   constexpr int kBondThreads = NT, kBondWaves = NT / kWave;
@@ -1830,30 +1840,42 @@ void k_bond_mx(BondArgs A, DevParams P) {
   const double pc_i = A.pc[i];
   double hs[6] = {0, 0, 0, 0, 0, 0}, hpc = 0.0, hw = 0.0;
   int n_deg = 0, n_pl = 0, n_nc = 0, n_trip = 0, mx = 0;
-  for (int m = tid; m < nf; m += kBondThreads) {
+  // One lane per bond.  The lane's sums above start at zero for its first
+  // bond, so nothing is carried through that bond's return map (the
+  // kernel's register peak).  Families wider than the workgroup take
+  // further bonds per lane; the sums are then carried as wave totals,
+  // which are uniform, and handed back to lane 0 for the closing reduction.
+  auto tail = [&](const int m) {
     Acc* kn = sKN + 16 * (size_t)m;
     int ns = 0;
     for (int c = 0; c < nblk; ++c) ns += __popcll(sb[(size_t)m * nw + c]);
     n_trip += ns;
     // FP64 from here on: inversion, gradient, return map, force state.
-    const double a = kn[0], b = kn[1], c = kn[2], d = kn[3], e = kn[4], f = kn[5];
     const int64_t slot = b0 + m;
-    double ixx, iyy, izz, ixy, ixz, iyz;
-    bool ok;
-    if (P.plane) {                                              // x-z block (plane strain)
-      const double d2 = a * c - e * e, tr = (a + c) / 2.0;
-      ok = ns >= 2 && d2 > 1e-12 * tr * tr;
-      const double id = 1.0 / d2;
-      ixx = c * id; izz = a * id; ixz = -e * id;
-      iyy = ixy = iyz = 0.0;
-    } else {
+    // K_ij^{-1} (symmetric: xx, yy, zz, xy, xz, yz) from the sums in LDS.  The
+    // mixed-precision instances, compiled for four waves per SIMD, form it
+    // again after the return map (their register peak) rather than keep it
+    // through it; the recomputation is bit-identical, and the empty asm keeps
+    // the compiler from reusing the first reads.  The FP64 instances keep it.
+    auto kinv = [&](double* I) -> bool {
+      asm volatile("" ::: "memory");
+      const double a = kn[0], b = kn[1], c = kn[2], d = kn[3], e = kn[4], f = kn[5];
+      if (P.plane) {                                            // x-z block (plane strain)
+        const double d2 = a * c - e * e, tr = (a + c) / 2.0;
+        const double id = 1.0 / d2;
+        I[0] = c * id; I[2] = a * id; I[4] = -e * id;
+        I[1] = I[3] = I[5] = 0.0;
+        return ns >= 2 && d2 > 1e-12 * tr * tr;
+      }
       const double dK = det3s(a, b, c, d, e, f);
       const double tk = (a + b + c) / 3.0;
-      ok = ns >= 3 && dK > 1e-12 * tk * tk * tk;
       const double idK = 1.0 / dK;
-      ixx = (b * c - d * d) * idK; iyy = (a * c - e * e) * idK; izz = (a * b - f * f) * idK;
-      ixy = (d * e - f * c) * idK; ixz = (f * d - b * e) * idK; iyz = (e * f - a * d) * idK;
-    }
+      I[0] = (b * c - d * d) * idK; I[1] = (a * c - e * e) * idK; I[2] = (a * b - f * f) * idK;
+      I[3] = (d * e - f * c) * idK; I[4] = (f * d - b * e) * idK; I[5] = (e * f - a * d) * idK;
+      return ns >= 3 && dK > 1e-12 * tk * tk * tk;
+    };
+    double Ki[6];
+    const bool ok = kinv(Ki);
     // history on the bonds: the state the bond starts from
     double sg0[6] = {0, 0, 0, 0, 0, 0}, pc0 = 0.0;
     if constexpr (Hist) {
@@ -1878,7 +1900,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
         reinterpret_cast<double4*>(A.hist)[2 * slot] = double4{sg0[0], sg0[1], sg0[2], sg0[3]};
         reinterpret_cast<double4*>(A.hist)[2 * slot + 1] = double4{sg0[4], sg0[5], pc0, 0.0};
       }
-      continue;
+      return;
     }
     double N[9];
 #pragma unroll
@@ -1886,9 +1908,9 @@ void k_bond_mx(BondArgs A, DevParams P) {
     double L[9];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      L[3 * r + 0] = N[3 * r] * ixx + N[3 * r + 1] * ixy + N[3 * r + 2] * ixz;
-      L[3 * r + 1] = N[3 * r] * ixy + N[3 * r + 1] * iyy + N[3 * r + 2] * iyz;
-      L[3 * r + 2] = N[3 * r] * ixz + N[3 * r + 1] * iyz + N[3 * r + 2] * izz;
+      L[3 * r + 0] = N[3 * r] * Ki[0] + N[3 * r + 1] * Ki[3] + N[3 * r + 2] * Ki[4];
+      L[3 * r + 1] = N[3 * r] * Ki[3] + N[3 * r + 1] * Ki[1] + N[3 * r + 2] * Ki[5];
+      L[3 * r + 2] = N[3 * r] * Ki[4] + N[3 * r + 1] * Ki[5] + N[3 * r + 2] * Ki[2];
     }
     const double varpi = (double)kn[15] * iVh;                  // Eq. 55
     const double h = A.dt_inc;
@@ -1901,7 +1923,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
         for (int k = 0; k < 6; ++k) sgb[k] = sig_i[k];
         pcb = pc_i;
       } else {
-        int it = return_map_pn(P, h, sig_i, pc_i, Pn_i, de, sgb, &pcb);
+        int it = return_map_pn<LinP>(P, h, sig_i, pc_i, Pn_i, de, sgb, &pcb);
         if (it < 0) { ++n_nc; it = P.newton_maxit; }
         if (it > 0) ++n_pl;
         mx = mx > it ? mx : it;
@@ -1912,7 +1934,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
         for (int k = 0; k < 6; ++k) sgb[k] = sg0[k];
         pcb = pc0;
       } else {
-        int it = return_map_pn(P, h, sg0, pc0, apparent_pc(P, pc0), de, sgb, &pcb);
+        int it = return_map_pn<LinP>(P, h, sg0, pc0, apparent_pc<LinP>(P, pc0), de, sgb, &pcb);
         if (it < 0) { ++n_nc; it = P.newton_maxit; }
         if (it > 0) ++n_pl;
         mx = mx > it ? mx : it;
@@ -1920,6 +1942,8 @@ void k_bond_mx(BondArgs A, DevParams P) {
       reinterpret_cast<double4*>(A.hist)[2 * slot] = double4{sgb[0], sgb[1], sgb[2], sgb[3]};
       reinterpret_cast<double4*>(A.hist)[2 * slot + 1] = double4{sgb[4], sgb[5], pcb, 0.0};
     }
+    if constexpr (!kF64) kinv(Ki);
+    const double ixx = Ki[0], iyy = Ki[1], izz = Ki[2], ixy = Ki[3], ixz = Ki[4], iyz = Ki[5];
     // Total bond stress sigma_ij + Sr_i s_i 1 (Eq. 32 with p_w = -s) times K_ij^{-1}.
     const double ps = Sr_i * s_i;
     const double S00 = sgb[0] + ps, S11 = sgb[1] + ps, S22 = sgb[2] + ps;
@@ -1947,6 +1971,37 @@ void k_bond_mx(BondArgs A, DevParams P) {
     for (int k = 0; k < 6; ++k) hs[k] += Vj * sgb[k];
     hpc += Vj * pcb;
     hw += Vj;
+  };
+  if (tid < nf) tail(tid);
+  if (nf > kBondThreads) {                        // uniform per block
+    double u[8];
+    int ui[5];
+    auto fold = [&](bool first) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) u[k] = (first ? 0.0 : u[k]) + wave_sum(hs[k]);
+      u[6] = (first ? 0.0 : u[6]) + wave_sum(hpc);
+      u[7] = (first ? 0.0 : u[7]) + wave_sum(hw);
+      ui[0] = (first ? 0 : ui[0]) + wave_sum_i(n_deg);
+      ui[1] = (first ? 0 : ui[1]) + wave_sum_i(n_pl);
+      ui[2] = (first ? 0 : ui[2]) + wave_sum_i(n_nc);
+      ui[3] = (first ? 0 : ui[3]) + wave_sum_i(n_trip);
+      ui[4] = max(first ? 0 : ui[4], wave_max_i(mx));
+#pragma unroll
+      for (int k = 0; k < 6; ++k) hs[k] = 0.0;
+      hpc = hw = 0.0;
+      n_deg = n_pl = n_nc = n_trip = mx = 0;
+    };
+    fold(true);
+    for (int m0 = kBondThreads; m0 < nf; m0 += kBondThreads) {   // uniform trip count:
+      if (m0 + tid < nf) tail(m0 + tid);                          // the wave sums need
+      fold(false);                                                // every lane
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) hs[k] = u[k];
+      hpc = u[6]; hw = u[7];
+      n_deg = ui[0]; n_pl = ui[1]; n_nc = ui[2]; n_trip = ui[3]; mx = ui[4];
+    }
   }
   double own[3] = {0.0, 0.0, 0.0};
   if constexpr (kF64) if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
@@ -3599,6 +3654,44 @@ int bond_waves(size_t lds, int nt, bool mixed) {
   return waves >= 10 ? 3 : 2;
 }
 
+// Launch of the bond kernel: the instance for the precision (Acc), the
+// bond-history mode and the pre-consolidation law (LinP), at the workgroup
+// width and waves per SIMD that the family capacity admits.  The history
+// instances always run two waves.
+struct BondLaunch {
+  unsigned grid;
+  int nt;
+  size_t lds;
+  hipStream_t stream;
+  bool one_wave, more;
+};
+template <class Acc, bool Hist, bool LinP>
+void launch_bond(const BondLaunch& L, const BondArgs& A, const DevParams& P) {
+  constexpr int lo = sizeof(Acc) == 8 ? 2 : 3;                   // waves per SIMD without "more"
+  if constexpr (!Hist) {
+    if (L.one_wave) {
+      if (L.more) k_bond_mx<Acc, Hist, LinP, kWave, lo + 1><<<L.grid, L.nt, L.lds, L.stream>>>(A, P);
+      else k_bond_mx<Acc, Hist, LinP, kWave, lo><<<L.grid, L.nt, L.lds, L.stream>>>(A, P);
+      return;
+    }
+  }
+  if (L.more) k_bond_mx<Acc, Hist, LinP, kBondThreads, lo + 1><<<L.grid, L.nt, L.lds, L.stream>>>(A, P);
+  else k_bond_mx<Acc, Hist, LinP, kBondThreads, lo><<<L.grid, L.nt, L.lds, L.stream>>>(A, P);
+}
+// The dynamic LDS cap of every instance launch_bond<Acc, Hist, LinP> can pick.
+template <class Acc, bool Hist, bool LinP>
+void bond_lds_limit(int lds) {
+  constexpr int lo = sizeof(Acc) == 8 ? 2 : 3;
+  const void* ks[4] = {(const void*)k_bond_mx<Acc, Hist, LinP, kBondThreads, lo>,
+                       (const void*)k_bond_mx<Acc, Hist, LinP, kBondThreads, lo + 1>, nullptr, nullptr};
+  if constexpr (!Hist) {
+    ks[2] = (const void*)k_bond_mx<Acc, Hist, LinP, kWave, lo>;
+    ks[3] = (const void*)k_bond_mx<Acc, Hist, LinP, kWave, lo + 1>;
+  }
+  for (const void* k : ks)
+    if (k) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
 // Algorithm 1 (bond pass) into outputs; mode: step (state outputs) or not.
 // mark(0) / mark(1) bracket the point-kinematics kernels when timing.
 int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, double dt_inc, bool commit,
@@ -3662,30 +3755,12 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   const bool one_wave = ctx->max_f <= kWave;             // every family fits one wave
   const int nt = one_wave && !hist ? kWave : kBondThreads;  // the history instances run two waves
   const bool more = bond_waves(lds, nt, mixed) > (mixed ? 3 : 2);
-  if (mixed && hist && more)
-    k_bond_mx<float, true, kBondThreads, 4><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else if (mixed && hist)
-    k_bond_mx<float, true, kBondThreads, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else if (mixed && one_wave && more)
-    k_bond_mx<float, false, kWave, 4><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else if (mixed && one_wave)
-    k_bond_mx<float, false, kWave, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else if (mixed && more)
-    k_bond_mx<float, false, kBondThreads, 4><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else if (mixed)
-    k_bond_mx<float, false, kBondThreads, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else if (hist && more)
-    k_bond_mx<double, true, kBondThreads, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else if (hist)
-    k_bond_mx<double, true, kBondThreads, 2><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else if (one_wave && more)
-    k_bond_mx<double, false, kWave, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else if (one_wave)
-    k_bond_mx<double, false, kWave, 2><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else if (more)
-    k_bond_mx<double, false, kBondThreads, 3><<<grid, nt, lds, ctx->stream>>>(A, P);
-  else
-    k_bond_mx<double, false, kBondThreads, 2><<<grid, nt, lds, ctx->stream>>>(A, P);
+  const bool lin = p->b1 == 0.0 && p->b2 == 1.0;        // Eq. 45 reduces to P = p_c
+  const BondLaunch L{grid, nt, lds, ctx->stream, one_wave, more};
+  if (mixed && hist) lin ? launch_bond<float, true, true>(L, A, P) : launch_bond<float, true, false>(L, A, P);
+  else if (mixed) lin ? launch_bond<float, false, true>(L, A, P) : launch_bond<float, false, false>(L, A, P);
+  else if (hist) lin ? launch_bond<double, true, true>(L, A, P) : launch_bond<double, true, false>(L, A, P);
+  else lin ? launch_bond<double, false, true>(L, A, P) : launch_bond<double, false, false>(L, A, P);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
@@ -4003,20 +4078,15 @@ void context_buffers(ulppm_ctx* ctx, Alloc&& A) {
 
 // The bond kernel's dynamic LDS may exceed the default cap for large max_family.
 void set_bond_lds_limits(int max_family) {
-  for (const void* k : {(const void*)k_bond_mx<double, false, kBondThreads, 2>,
-                        (const void*)k_bond_mx<double, false, kBondThreads, 3>,
-                        (const void*)k_bond_mx<double, true, kBondThreads, 2>,
-                        (const void*)k_bond_mx<double, true, kBondThreads, 3>,
-                        (const void*)k_bond_mx<double, false, kWave, 2>,
-                        (const void*)k_bond_mx<double, false, kWave, 3>})
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, false));
-  for (const void* k : {(const void*)k_bond_mx<float, false, kBondThreads, 3>,
-                        (const void*)k_bond_mx<float, false, kBondThreads, 4>,
-                        (const void*)k_bond_mx<float, true, kBondThreads, 3>,
-                        (const void*)k_bond_mx<float, true, kBondThreads, 4>,
-                        (const void*)k_bond_mx<float, false, kWave, 3>,
-                        (const void*)k_bond_mx<float, false, kWave, 4>})
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bond_lds(max_family, true));
+  const int l64 = (int)bond_lds(max_family, false), l32 = (int)bond_lds(max_family, true);
+  bond_lds_limit<double, false, false>(l64);
+  bond_lds_limit<double, false, true>(l64);
+  bond_lds_limit<double, true, false>(l64);
+  bond_lds_limit<double, true, true>(l64);
+  bond_lds_limit<float, false, false>(l32);
+  bond_lds_limit<float, false, true>(l32);
+  bond_lds_limit<float, true, false>(l32);
+  bond_lds_limit<float, true, true>(l32);
 }
 
 }  // namespace

@@ -649,3 +649,33 @@ def test_one_wave_bond_kernel_small_horizon(olib, gpu, precision):
     Sg = G.to_arrays()
     compare_states(Sg, S, 1e-10 if precision == "fp64" else 1e-4, fields=("u", "v", "sig", "pc", "J"),
                    label=f"one wave {precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_nonlinear_apparent_preconsolidation(olib, gpu, precision):
+    """Eq. 45 with b1 = 0.1, b2 = 1.02: the bond kernel's general instance
+    (the power in its return map; b1 = 0, b2 = 1 runs an instance without it)
+    against the oracle over 100 steps of a shaken column with plastic bonds.
+    FP64 within 1e-10 relative L2, mixed within 1e-4."""
+    say("nonlinear Eq. 45", precision)
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=5, dims=(8, 8, 12))
+    col["params"].update(b1=0.1, b2=1.02)
+    oprm = olib.make_params(col["params"])
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    v = inputs.random_velocity(col["n"], 105, 0.3)
+    v[col["fixed"] == 1] = 0.0
+    S["v"][:] = v
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    gprm = gpu.make_params(olib.params_dict(oprm))
+    assert gprm.b1 == 0.1 and gprm.b2 == 1.02
+    if precision == "mixed":
+        gprm.precision = gpu.ULPPM_MIXED
+    ctx = gpu.Context(col["n"], max_family=128)
+    G = gpu.DeviceState.from_arrays(S)
+    rc, E, st = olib.step(S, oprm, 100)
+    assert rc == 0
+    rep = ctx.step(G, gprm, 100)
+    say("plastic", st["n_plastic"], rep["n_plastic"], "max newton", st["max_newton"], rep["max_newton"])
+    assert st["n_plastic"] > 0 and rep["n_plastic"] > 0
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    compare_states(G.to_arrays(), S, tol, fields=("u", "v", "sig", "pc", "J"), label=f"Eq. 45 {precision}")
