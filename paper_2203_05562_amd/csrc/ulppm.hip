@@ -1035,6 +1035,7 @@ __host__ __device__ __forceinline__ void tail_kinematics(bool plane, const doubl
 }
 
 // Pn: apparent pre-consolidation of pc (Eq. 45).
+template <bool LinP = false>
 __host__ __device__ void tail_forward_pn(const DevParams& P, const double* K, const double* N, const double* sig,
                                          double pc, double Pn, double Srs, double w, double dt, TailFwd& F) {
   tail_kinematics(P.plane != 0, K, N, dt, F);
@@ -1045,7 +1046,7 @@ __host__ __device__ void tail_forward_pn(const DevParams& P, const double* K, co
     F.pc = pc;
     F.branch = 0;
   } else {
-    F.branch = return_map_pn(P, dt, sig, pc, Pn, F.de, F.sg, &F.pc);
+    F.branch = return_map_pn<LinP>(P, dt, sig, pc, Pn, F.de, F.sg, &F.pc);
   }
   double Q[6] = {F.sg[0] + Srs, F.sg[1] + Srs, F.sg[2] + Srs, F.sg[3], F.sg[4], F.sg[5]};
   double QF[9], SK[9];
@@ -1062,6 +1063,7 @@ __host__ __device__ void tail_forward(const DevParams& P, const double* K, const
 // Adjoint of the return map at fixed branch: given the adjoints of the
 // updated bond stress (sgb, Voigt components) and p_c, accumulate those of
 // the point stress, p_c,n, the strain increment and (M, lam, kap, eta).
+template <bool LinP = false>
 __host__ __device__ void rm_reverse(const DevParams& P, double dt, const double* sn, double pcn, const double* de,
                                     const double* so, double pco, int branch, const double* sgb, double pcb,
                                     double* snb, double* pcnb, double* deb, double* thb) {
@@ -1093,8 +1095,8 @@ __host__ __device__ void rm_reverse(const DevParams& P, double dt, const double*
     double qtrb = qtr > 0.0 ? -ratiob * q / (qtr * qtr) : 0.0;
     // implicit function theorem at the solution x = (p, q, pc)
     const double c = dt / P.eta, M2 = P.M * P.M, lk = P.lam - P.kap;
-    const double Pb = apparent_pc(P, pco);
-    const double dP = apparent_pc_slope(P, pco);
+    const double Pb = apparent_pc<LinP>(P, pco);
+    const double dP = apparent_pc_slope<LinP>(P, pco);
     const double f = yield_f(P, p, q, Pb);
     const double fp = 2.0 * p - Pb, fq = 2.0 * q / M2, fc = -p * dP;
     const double E = exp(-c * f * fp / lk);
@@ -1144,6 +1146,7 @@ __host__ __device__ void rm_reverse(const DevParams& P, double dt, const double*
 // Adjoint of tail_forward: from the adjoints of M (9) and of the bond state
 // (sgb_ext, pcb_ext, e.g. from the history average) to those of K (unique
 // entries), N (9), the point stress and p_c, S_r s, w and the parameters.
+template <bool LinP = false>
 __host__ __device__ void tail_reverse(const DevParams& P, const double* K, const double* N, const double* sig,
                                       double pc, double Srs, double w, double dt, const TailFwd& F,
                                       const double* Mb, const double* sgb_ext, double pcb_ext, double* Kb,
@@ -1175,7 +1178,7 @@ __host__ __device__ void tail_reverse(const DevParams& P, const double* K, const
     for (int k = 0; k < 6; ++k) sigb[k] += sgb[k];
     *pcbp += pcb_ext;
   } else {
-    rm_reverse(P, dt, sig, pc, F.de, F.sg, F.pc, F.branch, sgb, pcb_ext, sigb, pcbp, deb, thb);
+    rm_reverse<LinP>(P, dt, sig, pc, F.de, F.sg, F.pc, F.branch, sgb, pcb_ext, sigb, pcbp, deb, thb);
   }
   // de = dt sym(L): Lbar
   double Lb[9] = {dt * deb[0], 0.5 * dt * deb[5], 0.5 * dt * deb[4],
@@ -2389,7 +2392,9 @@ __global__ __launch_bounds__(256) void k_adj_point1(int64_t n, const uint8_t* __
 // Hist: the history on the bonds; each bond starts from its carried state
 // (A.hstart), its updated state also receives A.hbar1, and the adjoint of
 // its start state goes to A.hbar0s instead of the point's history.
-template <bool Hist, class Acc>
+// LinP: the linear pre-consolidation law (b1 = 0, b2 = 1), as in the forward
+// bond kernel.
+template <bool Hist, class Acc, bool LinP>
 __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(AdjArgs A, DevParams P) {
   using MM = Mma<Acc>;            // the two membership-matrix sweeps: FP64, or FP32 in mixed precision
   using V4 = typename MM::V;
@@ -2464,7 +2469,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
       pt[k] = a;                                   // K_i (6), N_i (9), Vh
     }
   }
-  if (tid == kWave) s_Pn = apparent_pc(P, A.pc[i]);   // Eq. 45, shared by the bonds of i
+  if (tid == kWave) s_Pn = apparent_pc<LinP>(P, A.pc[i]);   // Eq. 45, shared by the bonds of i
   __syncthreads();
   const double Vh = pt[15];
   const double Sr1 = A.Sr1[i], s_i = A.s[i];
@@ -2558,9 +2563,9 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
       TailFwd F;
       if constexpr (Hist) {
         const double* h0 = A.hstart + 8 * (b0 + m);
-        tail_forward_pn(P, Kq, Nq, h0, h0[6], apparent_pc(P, h0[6]), Srs, Vj / Vh, dt, F);
+        tail_forward_pn<LinP>(P, Kq, Nq, h0, h0[6], apparent_pc<LinP>(P, h0[6]), Srs, Vj / Vh, dt, F);
       } else {
-        tail_forward_pn(P, Kq, Nq, sig_i, pc_i, Pn_i, Srs, Vj / Vh, dt, F);
+        tail_forward_pn<LinP>(P, Kq, Nq, sig_i, pc_i, Pn_i, Srs, Vj / Vh, dt, F);
       }
       for (int q = 0; q < 9; ++q) r.v[q] = F.M[q];
       double* rr = A.fwd + 8 * (b0 + m);
@@ -2775,7 +2780,10 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   for (int k = 0; k < 6; ++k) sig1[k] = A.sig1[k][i];
   const double pc1 = A.pc1[i];
   double acc_sig[6] = {0, 0, 0, 0, 0, 0}, acc_pc = 0.0, acc_Srs = 0.0, acc_Vh = 0.0, acc_th[4] = {0, 0, 0, 0};
-  for (int m = tid; m < nf; m += kBondThreads) {
+  // One lane per bond, the first bond of each lane with its sums starting at
+  // zero (none carried through the reverse of its return map); further bonds
+  // of a family wider than the workgroup carry them as wave totals.
+  auto rtail = [&](const int m) {
     double* kn = sKN + 16 * (size_t)m;
     const bool active = kn[15] != 0.0;
     double Kb[6] = {0, 0, 0, 0, 0, 0}, Nb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -2840,14 +2848,14 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
         pcx += hb[6];
         const double* h0 = A.hstart + 8 * (b0 + m);
         double s0b[6] = {0, 0, 0, 0, 0, 0}, p0b = 0.0;
-        tail_reverse(P, Kq, Nq, h0, h0[6], Srs, Vj / Vh, dt, F, mb, sgx, pcx, Kb, Nb, s0b, &p0b, &acc_Srs,
+        tail_reverse<LinP>(P, Kq, Nq, h0, h0[6], Srs, Vj / Vh, dt, F, mb, sgx, pcx, Kb, Nb, s0b, &p0b, &acc_Srs,
                      &wb, acc_th);
         double* ho = A.hbar0s + 8 * (b0 + m);
         for (int k = 0; k < 6; ++k) ho[k] = s0b[k];
         ho[6] = p0b;
         ho[7] = 0.0;
       } else {
-        tail_reverse(P, Kq, Nq, sig_i, pc_i, Srs, Vj / Vh, dt, F, mb, sgx, pcx, Kb, Nb, acc_sig, &acc_pc,
+        tail_reverse<LinP>(P, Kq, Nq, sig_i, pc_i, Srs, Vj / Vh, dt, F, mb, sgx, pcx, Kb, Nb, acc_sig, &acc_pc,
                      &acc_Srs, &wb, acc_th);
       }
       // w_j = V_j / Vh
@@ -2865,6 +2873,31 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     sym_full_grad<double>(Kb, Ks);
     for (int k = 0; k < 6; ++k) kn[k] = Ks[k];
     for (int k = 0; k < 9; ++k) kn[6 + k] = Nb[k];
+  };
+  if (tid < nf) rtail(tid);
+  if (nf > kBondThreads) {                        // uniform per block
+    double u[13];
+    auto fold = [&](bool first) {
+      double* acc[13] = {&acc_sig[0], &acc_sig[1], &acc_sig[2], &acc_sig[3], &acc_sig[4], &acc_sig[5], &acc_pc,
+                         &acc_Srs, &acc_Vh, &acc_th[0], &acc_th[1], &acc_th[2], &acc_th[3]};
+#pragma unroll
+      for (int k = 0; k < 13; ++k) {
+        u[k] = (first ? 0.0 : u[k]) + wave_sum(*acc[k]);
+        *acc[k] = 0.0;
+      }
+    };
+    fold(true);
+    for (int m0 = kBondThreads; m0 < nf; m0 += kBondThreads) {   // uniform trip count
+      if (m0 + tid < nf) rtail(m0 + tid);
+      fold(false);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc_sig[k] = u[k];
+      acc_pc = u[6]; acc_Srs = u[7]; acc_Vh = u[8];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc_th[k] = u[9 + k];
+    }
   }
   // block reductions: sigma_bar_i (6), pc_bar_i, Srs_bar, Vh_bar, theta (4), own V (gather)
   double vals[14] = {acc_sig[0], acc_sig[1], acc_sig[2], acc_sig[3], acc_sig[4], acc_sig[5], acc_pc, acc_Srs,
@@ -4513,8 +4546,10 @@ int ulppm_adjoint_reserve(ulppm_ctx* ctx) {
     ctx->adj = nullptr;
     return fail(ctx, ULPPM_E_HIP, std::string("adjoint scratch: ") + hipGetErrorString(e));
   }
-  for (const void* k : {(const void*)k_adj_bond<false, double>, (const void*)k_adj_bond<true, double>,
-                        (const void*)k_adj_bond<false, float>, (const void*)k_adj_bond<true, float>})
+  for (const void* k : {(const void*)k_adj_bond<false, double, false>, (const void*)k_adj_bond<true, double, false>,
+                        (const void*)k_adj_bond<false, float, false>, (const void*)k_adj_bond<true, float, false>,
+                        (const void*)k_adj_bond<false, double, true>, (const void*)k_adj_bond<true, double, true>,
+                        (const void*)k_adj_bond<false, float, true>, (const void*)k_adj_bond<true, float, true>})
     HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)std::min(adj_lds(ctx->max_f), kMaxLds)));
   return reserve_adj_hist(ctx);
@@ -4698,14 +4733,19 @@ static int adjoint_step_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_s
   }
   k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
   const bool mixed = p->precision == ULPPM_MIXED;
-  if (H && mixed)
-    k_adj_bond<true, float><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
-  else if (H)
-    k_adj_bond<true, double><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
-  else if (mixed)
-    k_adj_bond<false, float><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
-  else
-    k_adj_bond<false, double><<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  const bool lin = p->b1 == 0.0 && p->b2 == 1.0;        // Eq. 45 reduces to P = p_c
+  auto go = [&](auto hist_c, auto acc_c, auto lin_c) {
+    k_adj_bond<decltype(hist_c)::value, typename decltype(acc_c)::type, decltype(lin_c)::value>
+        <<<grid, kBondThreads, lds, ctx->stream>>>(A, P);
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  using D_ = std::common_type<double>;
+  using S_ = std::common_type<float>;
+  if (H && mixed) lin ? go(T_{}, S_{}, T_{}) : go(T_{}, S_{}, F_{});
+  else if (H) lin ? go(T_{}, D_{}, T_{}) : go(T_{}, D_{}, F_{});
+  else if (mixed) lin ? go(F_{}, S_{}, T_{}) : go(F_{}, S_{}, F_{});
+  else lin ? go(F_{}, D_{}, T_{}) : go(F_{}, D_{}, F_{});
   HIPCHK(hipGetLastError());
   if (H) {
     if (have) {

@@ -28,11 +28,12 @@ def gpu():
     return ulppm
 
 
-def start(olib, gpu, dims=(6, 6, 8), seed=3, vscale=0.3, contact=False):
+def start(olib, gpu, dims=(6, 6, 8), seed=3, vscale=0.3, contact=False, law="linear"):
     """A small column; with contact it stands free on a substrate raised into
-    the cut-off, so that its base starts in contact."""
+    the cut-off, so that its base starts in contact.  law "power": Eq. 45 with
+    b1 = 0.1, b2 = 1.02 (the general instance of the adjoint bond kernel)."""
     col = inputs.make_column(inputs.CONFIGS["C0"], seed=seed, dims=dims, fixed_base=not contact)
-    over = {}
+    over = {"b1": 0.1, "b2": 1.02} if law == "power" else {}
     sub = None
     if contact:
         sub = inputs.make_substrate(col, extent=0.5, layers=2, mu_f=0.25)
@@ -120,15 +121,17 @@ def test_one_step_adjoint_identity(olib, gpu):
     assert abs(lhs - rhs) <= 1e-8 * max(abs(lhs), abs(rhs))
 
 
-@pytest.mark.parametrize("nsteps,contact", [(1, False), (8, False), (8, True)])
-def test_adjoint_matches_dual_numbers(olib, gpu, nsteps, contact):
+@pytest.mark.parametrize("nsteps,contact,law", [(1, False, "linear"), (8, False, "linear"), (8, True, "linear"),
+                                                (8, False, "power")])
+def test_adjoint_matches_dual_numbers(olib, gpu, nsteps, contact, law):
     """Gradient of J = sum c . u^N through N plastic steps: the GPU adjoint
     dotted with directions in (M, lam, kap, eta), the initial velocity,
     stress, pre-consolidation and suction equals the oracle's directional
     derivatives; with contact, through a base in contact with the substrate
-    (Eqs. 91-93, friction branch frozen)."""
-    say("adjoint vs dual", nsteps, "contact" if contact else "")
-    col, oprm, gprm, S, ctx = start(olib, gpu, contact=contact)
+    (Eqs. 91-93, friction branch frozen); with the power law of Eq. 45."""
+    say("adjoint vs dual", nsteps, "contact" if contact else "", law)
+    col, oprm, gprm, S, ctx = start(olib, gpu, contact=contact, law=law)
+    assert (gprm.b1, gprm.b2) == ((0.1, 1.02) if law == "power" else (0.0, 1.0))
     n = col["n"]
     rng = np.random.default_rng(11)
     c = rng.normal(size=(n, 3))
