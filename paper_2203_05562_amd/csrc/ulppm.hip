@@ -1596,6 +1596,15 @@ __global__ __launch_bounds__(256) void k_adj_hist_carry(int64_t n, const int64_t
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// 2 p + (this lane's bit of the lane mask m): one add with carry, the mask
+// as the carry-in.  Written out because the compiler forms the sum from a
+// select and a shift-or.
+__device__ __forceinline__ unsigned shift_in(unsigned p, unsigned long long m) {
+  unsigned r;
+  asm("v_addc_co_u32 %0, %1, %2, %2, %1" : "=v"(r), "+s"(m) : "v"(p));
+  return r;
+}
+
 template <class Acc>
 struct Mma;
 template <>
@@ -1790,32 +1799,50 @@ void k_bond_mx(BondArgs A, DevParams P) {
         acc[b] = V4{0, 0, 0, 0};
         piece[b] = 0u;
       }
-      // member data of the next step is loaded one step ahead
-      Quad<double> xk = pos(q4);
-      Acc ra = sR[8 * (size_t)q4 + fa] - oa, rb = sR[8 * (size_t)q4 + fb] - ob, rv = sR[8 * (size_t)q4 + 3];
-      for (int ks = 0; ks < nks; ++ks) {
-        const int k1 = 4 * (ks + 1) + q4;
-        const Quad<double> xk1 = pos(k1);
-        const Acc* rec1 = sR + 8 * (size_t)k1;
-        const Acc ra1 = rec1[fa] - oa, rb1 = rec1[fb] - ob, rv1 = rec1[3];
-        const Acc bval = ra * rb * rv;
-        const unsigned sbit = 1u << (ks & 15);
+      // Member data of step ks: position and the three feature factors.
+      struct StepData {
+        Quad<double> x;
+        Acc ra, rb, rv;
+      };
+      auto load = [&](int ks) {
+        const int k = 4 * ks + q4;
+        const Acc* rec = sR + 8 * (size_t)k;
+        return StepData{pos(k), rec[fa] - oa, rec[fb] - ob, rec[3]};
+      };
+      // The bits of a piece are shifted in (2 piece + in: one add with carry),
+      // so step s of the piece's c steps sits at bit c - 1 - s; the store
+      // reverses them into bit s.
+      auto step = [&](int ks, const StepData& m) {
+        const Acc bval = m.ra * m.rb * m.rv;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          const bool in = within(xj[b][0], xj[b][1], xj[b][2], xk.v[0], xk.v[1], xk.v[2], d2);
-          piece[b] |= in ? sbit : 0u;
+          const bool in = within(xj[b][0], xj[b][1], xj[b][2], m.x.v[0], m.x.v[1], m.x.v[2], d2);
+          piece[b] = shift_in(piece[b], __ballot(in));
           acc[b] = MM::run(in ? (Acc)1 : (Acc)0, bval, acc[b]);
         }
         if ((ks & 15) == 15 || ks == nks - 1) {
+          const unsigned up = 15 - (ks & 15);         // 16 - c
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            if (jv[b]) sq[((size_t)jrow[b] * nw + (ks >> 4)) * 4 + q4] = (unsigned short)piece[b];
+            const unsigned bits = __builtin_bitreverse32(piece[b] << up) >> 16;
+            if (jv[b]) sq[((size_t)jrow[b] * nw + (ks >> 4)) * 4 + q4] = (unsigned short)bits;
             piece[b] = 0u;
           }
         }
-        xk = xk1;
-        ra = ra1; rb = rb1; rv = rv1;
+      };
+      // Two steps per iteration, each step's data loaded one step ahead into
+      // alternating registers (no copies between iterations).  The last
+      // look-ahead reads slot 4 nks + q4 at most, as the member loop always
+      // has (a padding slot, or in FP64 the sums that follow the records).
+      StepData ma = load(0);
+      int ks = 0;
+      for (; ks + 1 < nks; ks += 2) {
+        const StepData mb = load(ks + 1);
+        step(ks, ma);
+        ma = load(ks + 2);
+        step(ks + 1, mb);
       }
+      if (ks < nks) step(ks, ma);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int t = t0 + kBondWaves * b;
