@@ -853,7 +853,7 @@ __host__ __device__ int return_map_pn(const DevParams& P, double dt, const doubl
   for (int k = 0; k < 6; ++k) s[k] = st[k] - (k < 3 ? ptr : 0.0);
   const double qtr = sqrt(1.5 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
                                  2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5])));
-  if (!(yield_f(P, ptr, qtr, Pn) > 0.0)) {
+  if (__builtin_expect(!(yield_f(P, ptr, qtr, Pn) > 0.0), 1)) {   // elastic: the common case, laid out first
 #pragma unroll
     for (int k = 0; k < 6; ++k) so[k] = st[k];
     *pco = pcn;
@@ -878,7 +878,7 @@ __host__ __device__ int return_map_pn(const DevParams& P, double dt, const doubl
       conv = true;
       break;
     }
-    if (it >= P.newton_maxit || stalled) {
+    if (__builtin_expect(it >= P.newton_maxit || stalled, 0)) {
       ConsistencySolve<LinP> B{P.K, P.mu, M2, lk, P.b1, P.b2, c, ptr, qtr, pcn};
       double xb[3];
       B.solve(yield_f(P, ptr, qtr, Pn), xb);
@@ -1921,7 +1921,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
         pc0 = pc_i;
       }
     }
-    if (!ok) {                                                  // degenerate: inactive bond
+    if (__builtin_expect(!ok, 0)) {                             // degenerate: inactive bond
       ++n_deg;
 #pragma unroll
       for (int q = 0; q < 9; ++q) kn[q] = (Acc)0;
