@@ -740,10 +740,9 @@ __global__ __launch_bounds__(256) void k_compact(int64_t n, int max_c, int max_f
 // Apparent pre-consolidation P(p_c) = -exp(b1) (-p_c)^b2 (Eq. 45) and its
 // slope dP/dp_c (Eq. 89).  With b1 = 0 and b2 = 1 they are p_c and 1, taken
 // without the transcendental calls (the Newton iterations of the plastic
-// bonds evaluate both every iteration).
-// LinP: the exponents b1 = 0, b2 = 1, where the apparent pre-consolidation is
-// p_c itself.  Code compiled for that case carries none of the registers of
-// the general power (the bond kernel's return map is its register peak).
+// bonds evaluate both every iteration).  LinP = true compiles that case
+// alone: such code carries none of the registers of the general power (the
+// bond kernels' return map is their register peak).
 template <bool LinP = false>
 __host__ __device__ __forceinline__ double apparent_pc(const DevParams& P, double pc) {
   if (LinP || (P.b1 == 0.0 && P.b2 == 1.0)) return pc;
@@ -1076,7 +1075,7 @@ __host__ __device__ void rm_reverse(const DevParams& P, double dt, const double*
   for (int k = 0; k < 6; ++k) s[k] = st[k] - (k < 3 ? ptr : 0.0);
   const double qtr = sqrt(1.5 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5])));
   double stb[6];
-  if (branch == 0) {
+  if (__builtin_expect(branch == 0, 1)) {          // elastic: the common case, laid out first
     for (int k = 0; k < 6; ++k) stb[k] = sgb[k];
     *pcnb += pcb;
   } else {
