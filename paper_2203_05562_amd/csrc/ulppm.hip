@@ -11,7 +11,7 @@
 //               a scan turns the counts into CSR rows and k_compact writes
 //               the columns and rev[] through the reverse candidate index
 //               (Eq. 1; Algorithm 1, neighbour search)
-//   k_point_kin_lane  one lane per point: full-horizon sums, volume change,
+//   k_point_kin_quad  four lanes per point: full-horizon sums, volume change,
 //               porosity, saturation and mass (Eqs. 5, 8, 15-17, 48)
 //   k_bond_mx   one workgroup per point i, its family staged in LDS: pass 1
 //               forms the sub-horizon sums (shape tensor, velocity-gradient
@@ -1305,32 +1305,37 @@ __device__ __forceinline__ void point_update(const BondArgs& A, const DevParams&
   A.pk[n + i] = Vp > 0.0 ? 1.0 / Vp : 0.0;
 }
 
-// Point kinematics with one lane per point: each lane walks its own family
-// (the loads of four members in flight at once) and updates its point.  A
-// workgroup holds 256 consecutive points; the workgroups of one XCD take a
-// contiguous range of them.
-__global__ __launch_bounds__(256) void k_point_kin_lane(BondArgs A, DevParams P, int64_t per) {
+// Point kinematics with four lanes per point (a DPP quad): each lane walks
+// every fourth member of the family (the loads of four members in flight at
+// once), the quad adds its partial sums, and its first lane updates the point.
+// A workgroup holds 64 consecutive points; the workgroups of one XCD take a
+// contiguous range of them.  (One lane per point left only two waves per SIMD
+// on C1, too few to hide the gathers' latency.)
+constexpr int kKinLanes = 4;
+constexpr int kKinPoints = 256 / kKinLanes;                  // points per workgroup
+__global__ __launch_bounds__(256) void k_point_kin_quad(BondArgs A, DevParams P, int64_t per) {
   const int64_t blk = xcd_point(blockIdx.x, per);
-  const int64_t i = blk * 256 + threadIdx.x;
-  if (i >= A.n) return;
+  const int sub = threadIdx.x & (kKinLanes - 1);
+  const int64_t i = blk * kKinPoints + threadIdx.x / kKinLanes;
+  if (i >= A.n) return;                                       // whole quads
   const int64_t n = A.n;
   const int64_t b0 = A.row[i], b1 = A.row[i + 1];
   const double xi0 = A.x[i], xi1 = A.x[n + i], xi2 = A.x[2 * n + i];
   const double vi0 = A.vh[i], vi1 = A.vh[n + i], vi2 = A.vh[2 * n + i];
   double Kp[6] = {0, 0, 0, 0, 0, 0}, Np[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Vp = 0.0;
   const double4* xv = reinterpret_cast<const double4*>(A.xv);
-  for (int64_t s0 = b0; s0 < b1; s0 += 4) {
+  for (int64_t s0 = b0 + sub; s0 < b1; s0 += 4 * kKinLanes) {
     double4 pa[4], pb[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int64_t s = s0 + u < b1 ? s0 + u : b1 - 1;
+      const int64_t s = s0 + kKinLanes * u < b1 ? s0 + kKinLanes * u : s0;
       const int32_t k = A.col[s];
       pa[u] = xv[2 * (int64_t)k];
       pb[u] = xv[2 * (int64_t)k + 1];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (s0 + u >= b1) break;
+      if (s0 + kKinLanes * u >= b1) break;
       const double z0 = pa[u].x - xi0, z1 = pa[u].y - xi1, z2 = pa[u].z - xi2;
       const double y0 = pb[u].x - vi0, y1 = pb[u].y - vi1, y2 = pb[u].z - vi2;
       const double V = pa[u].w;
@@ -1343,7 +1348,17 @@ __global__ __launch_bounds__(256) void k_point_kin_lane(BondArgs A, DevParams P,
       Vp += V;
     }
   }
-  point_update(A, P, i, (int)(b1 - b0), Kp, Np, Vp);
+  // quad sums: every lane of the quad ends with the totals
+  auto quad_sum = [](double v) {
+    v += dpp_d<kDppXor1, 0xF>(v);
+    return v + dpp_d<kDppXor2, 0xF>(v);
+  };
+#pragma unroll
+  for (int k = 0; k < 6; ++k) Kp[k] = quad_sum(Kp[k]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Np[k] = quad_sum(Np[k]);
+  Vp = quad_sum(Vp);
+  if (sub == 0) point_update(A, P, i, (int)(b1 - b0), Kp, Np, Vp);
 }
 
 // The standard correspondence model (Eqs. 12-14): one wave per point forms
@@ -3802,8 +3817,8 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   else if (standard)
     k_point_kin_standard<double><<<walk_grid(n), 256, 0, ctx->stream>>>(A, P);
   else {
-    const int64_t per = ((n + 255) / 256 + 7) / 8;
-    k_point_kin_lane<<<(unsigned)(8 * per), 256, 0, ctx->stream>>>(A, P, per);
+    const int64_t per = ((n + kKinPoints - 1) / kKinPoints + 7) / 8;
+    k_point_kin_quad<<<(unsigned)(8 * per), 256, 0, ctx->stream>>>(A, P, per);
   }
   if (mark) mark(1);
   if (p->force_mode == ULPPM_FORCE_STANDARD) {
