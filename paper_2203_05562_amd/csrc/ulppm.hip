@@ -1676,20 +1676,23 @@ template <class Acc>
 __host__ __device__ constexpr size_t bond_mx_slot_bytes() {
   return sizeof(Acc) == 8 ? 8 * sizeof(double) : sizeof(Quad<double>) + 8 * sizeof(Acc);
 }
+// Rows of the closing reduction (one double per thread each): the point
+// history sums (8), the own force-state sums (3) and four counters.
+constexpr int kCloseRows = 15;
 template <class Acc>
-__host__ __device__ constexpr size_t bond_mx_lds_bytes(int max_f) {
+__host__ __device__ constexpr size_t bond_mx_lds_bytes(int max_f, int nt) {
   // the member slots, the 16 sums and the membership bits per member.  The
-  // closing reduction reuses the space for 8 doubles per thread and the
-  // per-wave partials after them.  The kernel has no static LDS: at family
-  // capacity 128 the FP64 workgroup needs 26 KB, and six fit a CU.
+  // closing reduction reuses the space for 16 rows of one double per thread
+  // and the per-wave maxima after them.  The kernel has no static LDS: at
+  // family capacity 128 the FP64 workgroup needs 26 KB, and six fit a CU.
   return (size_t)bond_mx_slots<Acc>(max_f) * bond_mx_slot_bytes<Acc>() +
                  (size_t)bond_mx_rows(max_f) * 16 * sizeof(Acc) +
                  (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long) >
-             8 * kBondThreads * sizeof(double) + 128
+             16 * (size_t)nt * sizeof(double) + 128
          ? (size_t)bond_mx_slots<Acc>(max_f) * bond_mx_slot_bytes<Acc>() +
                (size_t)bond_mx_rows(max_f) * 16 * sizeof(Acc) +
                (size_t)max_f * ((max_f + 63) / 64) * sizeof(unsigned long long)
-         : 8 * kBondThreads * sizeof(double) + 128;
+         : 16 * (size_t)nt * sizeof(double) + 128;
 }
 
 // Feature f of member k (pass 1, B operand): V_k a_f b_f from the record
@@ -2229,64 +2232,58 @@ void k_bond_mx(BondArgs A, DevParams P) {
       tile_slots(nb, t0, tiles2);
     }
   }
-  n_deg = wave_sum_i(n_deg);
-  n_pl = wave_sum_i(n_pl);
-  n_nc = wave_sum_i(n_nc);
-  n_trip = wave_sum_i(n_trip);
   mx = wave_max_i(mx);
-  // The eight history sums go through LDS: one wave adds 16 entries per lane
-  // and combines groups of 8 lanes, instead of eight full-wave reductions
-  // per wave.
+  // Closing: the point-history sums, the own force-state sums and the
+  // counters (15 rows of one double per thread) go through LDS.  Each row is
+  // added by kLpr lanes, 16 entries each, then by DPP within the lanes; with
+  // two waves, wave 0 holds rows 0-7 and writes the point history, wave 1
+  // rows 8-14 and writes the own sums and counters.
   __syncthreads();   // the family's working set is no longer read
-  double* hred = reinterpret_cast<double*>(smem_raw);              // [8][kBondThreads]
-  double (*red)[4] = reinterpret_cast<double (*)[4]>(hred + 8 * kBondThreads);   // [waves][4]
-  int (*redi)[4] = reinterpret_cast<int (*)[4]>(hred + 8 * kBondThreads + 4 * kBondWaves);
+  constexpr int kLpr = kBondThreads / 16, kRpw = kWave / kLpr;   // lanes per row, rows per wave
+  double* hred = reinterpret_cast<double*>(smem_raw);              // [16][kBondThreads]
+  int* redm = reinterpret_cast<int*>(hred + 16 * kBondThreads);    // [waves]: max Newton iterations
+  {
+    const double rv[kCloseRows] = {hs[0], hs[1], hs[2], hs[3], hs[4], hs[5], hpc, hw, own[0], own[1], own[2],
+                                   (double)n_deg, (double)n_pl, (double)n_nc, (double)n_trip};
 #pragma unroll
-  for (int k = 0; k < 6; ++k) hred[k * kBondThreads + tid] = hs[k];
-  hred[6 * kBondThreads + tid] = hpc;
-  hred[7 * kBondThreads + tid] = hw;
-  for (int c = 0; c < 3; ++c) own[c] = wave_sum(own[c]);
-  if (lane == 0) {
-    redi[wid][0] = n_deg; redi[wid][1] = n_pl; redi[wid][2] = n_nc; redi[wid][3] = n_trip;
-    red[wid][0] = (double)mx;
-    red[wid][1] = own[0]; red[wid][2] = own[1]; red[wid][3] = own[2];
+    for (int k = 0; k < kCloseRows; ++k) hred[k * kBondThreads + tid] = rv[k];
+    hred[kCloseRows * kBondThreads + tid] = 0.0;
   }
+  if (lane == 0) redm[wid] = mx;
   __syncthreads();
-  if (wid == 0) {
-    constexpr int kPer = kBondThreads / 8;
-    const double* src = hred + (lane >> 3) * kBondThreads + (lane & 7) * kPer;
-    double v = 0.0;
+  double v = 0.0;
+  {
+    const double* src = hred + (tid / kLpr) * kBondThreads + (tid % kLpr) * 16;
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) v += src[e];
-    v += dpp_d<kDppXor1, 0xF>(v);
-    v += dpp_d<kDppXor2, 0xF>(v);
-    v += dpp_d<kDppHalfMirror, 0xF>(v);
-    const long long vb = __double_as_longlong(v);
-    double hsum[8];
+    for (int e = 0; e < 16; ++e) v += src[e];
+  }
+  v += dpp_d<kDppXor1, 0xF>(v);
+  v += dpp_d<kDppXor2, 0xF>(v);
+  if constexpr (kLpr == 8) v += dpp_d<kDppHalfMirror, 0xF>(v);
+  const long long vb = __double_as_longlong(v);
+  double tot[kRpw];                                               // this wave's rows, uniform
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      hsum[k] = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(vb >> 32), 8 * k) << 32) |
-                                     (unsigned)__builtin_amdgcn_readlane((int)vb, 8 * k));
-    if (lane != 0) return;
-    const double W = hsum[7];
-    long long d = 0, pl = 0, nc = 0, tr = 0, m2 = 0;
-    for (int w = 0; w < kBondWaves; ++w) {
-      d += redi[w][0]; pl += redi[w][1]; nc += redi[w][2]; tr += redi[w][3];
-      m2 = m2 > (long long)red[w][0] ? m2 : (long long)red[w][0];
-    }
+  for (int k = 0; k < kRpw; ++k)
+    tot[k] = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(vb >> 32), k * kLpr) << 32) |
+                                  (unsigned)__builtin_amdgcn_readlane((int)vb, k * kLpr));
+  if (lane != 0) return;
+  if (wid == 0) {                                                 // rows 0-7
+    const double W = tot[7];
     if (W > 0.0) {
-      for (int k = 0; k < 6; ++k) A.sig_out[k][i] = hsum[k] / W;
-      A.pc_out[i] = hsum[6] / W;
+      for (int k = 0; k < 6; ++k) A.sig_out[k][i] = tot[k] / W;
+      A.pc_out[i] = tot[6] / W;
     } else {
       for (int k = 0; k < 6; ++k) A.sig_out[k][i] = sig_i[k];
       A.pc_out[i] = pc_i;
     }
-    if (A.fown) {
-      double o[3] = {0.0, 0.0, 0.0};
-      for (int w = 0; w < kBondWaves; ++w)
-        for (int c = 0; c < 3; ++c) o[c] += red[w][1 + c];
-      for (int c = 0; c < 3; ++c) A.fown[c * n + i] = o[c];
-    }
+  }
+  if (wid == 8 / kRpw) {                                          // rows 8-14
+    const double* t = tot + (8 - wid * kRpw);
+    if (A.fown)
+      for (int c = 0; c < 3; ++c) A.fown[c * n + i] = t[c];
+    const long long d = (long long)t[3], pl = (long long)t[4], nc = (long long)t[5], tr = (long long)t[6];
+    int m2 = 0;
+    for (int w = 0; w < kBondWaves; ++w) m2 = m2 > redm[w] ? m2 : redm[w];
     if (d) ctr_add(A.ctr, C_DEGEN, (unsigned long long)d);
     if (pl) ctr_add(A.ctr, C_PLASTIC, (unsigned long long)pl);
     if (nc) ctr_add(A.ctr, C_NOCONV, (unsigned long long)nc);
@@ -3714,8 +3711,8 @@ static bool own_sums(const ulppm_ctx* ctx, const ulppm_params* p) {
   return p->precision != ULPPM_MIXED && p->force_mode == ULPPM_FORCE_CONJUGATE && ctx->max_f > kWave;
 }
 
-size_t bond_lds(int max_f, bool mixed) {
-  return mixed ? bond_mx_lds_bytes<float>(max_f) : bond_mx_lds_bytes<double>(max_f);
+size_t bond_lds(int max_f, bool mixed, int nt) {
+  return mixed ? bond_mx_lds_bytes<float>(max_f, nt) : bond_mx_lds_bytes<double>(max_f, nt);
 }
 // Waves per SIMD the bond kernel's LDS (lds bytes per workgroup of nt
 // threads) admits, capped at the instances built: three for FP64 (reached
@@ -3807,7 +3804,9 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
   A.xv = ctx->xv;
   DevParams P = dev_params(p);
   if (mark) mark(0);
-  const size_t lds = bond_lds(ctx->max_f, mixed);
+  const bool one_wave = ctx->max_f <= kWave;             // every family fits one wave
+  const int nt = one_wave && !hist ? kWave : kBondThreads;  // the history instances run two waves
+  const size_t lds = bond_lds(ctx->max_f, mixed, nt);
   k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
   // the standard model's return map lives in its own instance so that the
   // plain kinematics keep their small register footprint
@@ -3826,8 +3825,6 @@ int bond_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, doubl
     return ULPPM_OK;
   }
   const unsigned grid = (unsigned)(8 * A.per);
-  const bool one_wave = ctx->max_f <= kWave;             // every family fits one wave
-  const int nt = one_wave && !hist ? kWave : kBondThreads;  // the history instances run two waves
   const bool more = bond_waves(lds, nt, mixed) > (mixed ? 3 : 2);
   const bool lin = p->b1 == 0.0 && p->b2 == 1.0;        // Eq. 45 reduces to P = p_c
   const BondLaunch L{grid, nt, lds, ctx->stream, one_wave, more};
@@ -4152,7 +4149,8 @@ void context_buffers(ulppm_ctx* ctx, Alloc&& A) {
 
 // The bond kernel's dynamic LDS may exceed the default cap for large max_family.
 void set_bond_lds_limits(int max_family) {
-  const int l64 = (int)bond_lds(max_family, false), l32 = (int)bond_lds(max_family, true);
+  const int l64 = (int)bond_lds(max_family, false, kBondThreads),
+            l32 = (int)bond_lds(max_family, true, kBondThreads);
   bond_lds_limit<double, false, false>(l64);
   bond_lds_limit<double, false, true>(l64);
   bond_lds_limit<double, true, false>(l64);
