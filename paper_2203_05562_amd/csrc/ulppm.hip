@@ -1222,7 +1222,7 @@ struct BondArgs {
   double* sig_out[6];
   double* pc_out;
   void* T;                // bond force states, CSR order, one (x, y, z, 0) record per bond
-                          // (double, or float in mixed precision)
+                          // (double, or float in mixed precision); V_i T_ik where fown is set
   double* pk;             // 2n: apparent pre-consolidation of p_c,i and 1/V_H,i (point kinematics)
   const double* xv;       // 8n: x (3), V^n, v_half (3), 0 per point
   double* hist;           // history on the bonds: 8 per bond (sigma, p_c, 0), written; or null
@@ -2057,6 +2057,9 @@ void k_bond_mx(BondArgs A, DevParams P) {
     // matrix products run at the vector rate on this chip and would pad the
     // 9 outputs to 16.  Rows past the family up to a whole group read as
     // zeros (their membership bits are clear, and 0 * stale data could be NaN).
+    // With the own sums kept here, the records hold V_i T_ik: the gather of
+    // point k then needs no V_i of its neighbours.
+    const double sc = A.fown ? A.vol_n[i] : 1.0;
     for (int m = nf + tid; m < 4 * nks; m += kBondThreads) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) sKN[16 * (size_t)m + q] = (Acc)0;
@@ -2130,7 +2133,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
         const Acc zx = zm[0] - xi0, zy = zm[1] - xi1, zz = zm[2] - xi2;
         const Acc t0 = S[0] * zx + S[1] * zy + S[2] * zz, t1 = S[3] * zx + S[4] * zy + S[5] * zz,
                   t2 = S[6] * zx + S[7] * zy + S[8] * zz;
-        T4[b0 + m] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
+        T4[b0 + m] = Quad<TS>{{(TS)(sc * t0), (TS)(sc * t1), (TS)(sc * t2), (TS)0}};
         own[0] += t0 * zm[3];                                      // sum_k T_ik V_k
         own[1] += t1 * zm[3];
         own[2] += t2 * zm[3];
@@ -2167,7 +2170,7 @@ void k_bond_mx(BondArgs A, DevParams P) {
         const Acc zx = zm[0] - xi0, zy = zm[1] - xi1, zz = zm[2] - xi2;
         const int64_t slot = b0 + m;
         const Acc t0 = a0 * zx + a1 * zy + a2 * zz, t1 = a3 * zx + a4 * zy + a5 * zz, t2 = a6 * zx + a7 * zy + a8 * zz;
-        T4[slot] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
+        T4[slot] = Quad<TS>{{(TS)(sc * t0), (TS)(sc * t1), (TS)(sc * t2), (TS)0}};
         own[0] += t0 * zm[3];                                      // sum_k T_ik V_k
         own[1] += t1 * zm[3];
         own[2] += t2 * zm[3];
@@ -3301,12 +3304,10 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
       f2 = (TS)G.fown[2 * G.n + i];
       if (lane != 0) f0 = f1 = f2 = (TS)0;          // added once by the wave sum
       for (int64_t s = b0 + lane; s < b1; s += kWave) {
-        const int32_t j = G.col[s], r = G.rev[s];
-        const TS wv = (TS)G.vol_n[j];
-        const Quad<TS> tr = T4[r];
-        f0 -= tr.v[0] * wv;
-        f1 -= tr.v[1] * wv;
-        f2 -= tr.v[2] * wv;
+        const Quad<TS> tr = T4[G.rev[s]];             // V_j T_ji, scaled by point j
+        f0 -= tr.v[0];
+        f1 -= tr.v[1];
+        f2 -= tr.v[2];
       }
     } else {
       for (int64_t s = b0 + lane; s < b1; s += kWave) {
@@ -3474,6 +3475,15 @@ template <class TS>
 __global__ void k_unpack_T(const Quad<TS>* __restrict__ T, int c, double* __restrict__ b, int64_t m) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
     b[e] = (double)T[e].v[c];
+}
+// The same from records that hold V_i T_ik (the FP64 path with own sums):
+// one thread per point i divides its row by V_i.
+__global__ void k_unpack_T_scaled(const Quad<double>* __restrict__ T, int c, const int64_t* __restrict__ row,
+                                  const double* __restrict__ vol, int64_t n, double* __restrict__ b) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double Vi = vol[i];
+    for (int64_t e = row[i]; e < row[i + 1]; ++e) b[e] = T[e].v[c] / Vi;
+  }
 }
 
 __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t m) {
@@ -4299,6 +4309,9 @@ int forces_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, dou
         if (mixed)
           k_unpack_T<float><<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(
               reinterpret_cast<const Quad<float>*>(ctx->T), c, T_out[c], nb);
+        else if (own_sums(ctx, p))
+          k_unpack_T_scaled<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
+              reinterpret_cast<const Quad<double>*>(ctx->T), c, ctx->row, ctx->vol_n, n, T_out[c]);
         else
           k_unpack_T<double><<<blocks_for(nb, 256), 256, 0, ctx->stream>>>(
               reinterpret_cast<const Quad<double>*>(ctx->T), c, T_out[c], nb);
