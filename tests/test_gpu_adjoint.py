@@ -28,11 +28,14 @@ def gpu():
     return ulppm
 
 
-def start(olib, gpu, dims=(6, 6, 8), seed=3, vscale=0.3, contact=False, law="linear"):
+def start(olib, gpu, dims=(6, 6, 8), seed=3, vscale=0.3, contact=False, law="linear", delta_dx=None):
     """A small column; with contact it stands free on a substrate raised into
     the cut-off, so that its base starts in contact.  law "power": Eq. 45 with
-    b1 = 0.1, b2 = 1.02 (the general instance of the adjoint bond kernel)."""
+    b1 = 0.1, b2 = 1.02 (the general instance of the adjoint bond kernel).
+    delta_dx: another horizon, in lattice spacings."""
     col = inputs.make_column(inputs.CONFIGS["C0"], seed=seed, dims=dims, fixed_base=not contact)
+    if delta_dx:
+        col["params"]["delta"] = delta_dx * inputs.DX
     over = {"b1": 0.1, "b2": 1.02} if law == "power" else {}
     sub = None
     if contact:
@@ -46,7 +49,7 @@ def start(olib, gpu, dims=(6, 6, 8), seed=3, vscale=0.3, contact=False, law="lin
     S["v"][:] = v
     oprm.dt = 0.5 * olib.dt_crit(S, oprm)
     gprm = gpu.make_params(olib.params_dict(oprm))
-    ctx = gpu.Context(col["n"])
+    ctx = gpu.Context(col["n"], max_family=256 if delta_dx else 0)
     if sub:
         ctx.set_contact(sub)
     ctx.adjoint_reserve()
@@ -121,16 +124,20 @@ def test_one_step_adjoint_identity(olib, gpu):
     assert abs(lhs - rhs) <= 1e-8 * max(abs(lhs), abs(rhs))
 
 
-@pytest.mark.parametrize("nsteps,contact,law", [(1, False, "linear"), (8, False, "linear"), (8, True, "linear"),
-                                                (8, False, "power")])
-def test_adjoint_matches_dual_numbers(olib, gpu, nsteps, contact, law):
+@pytest.mark.parametrize("nsteps,contact,law,delta_dx", [(1, False, "linear", None), (8, False, "linear", None),
+                                                         (8, True, "linear", None), (8, False, "power", None),
+                                                         (4, False, "linear", 3.6)])
+def test_adjoint_matches_dual_numbers(olib, gpu, nsteps, contact, law, delta_dx):
     """Gradient of J = sum c . u^N through N plastic steps: the GPU adjoint
     dotted with directions in (M, lam, kap, eta), the initial velocity,
     stress, pre-consolidation and suction equals the oracle's directional
     derivatives; with contact, through a base in contact with the substrate
-    (Eqs. 91-93, friction branch frozen); with the power law of Eq. 45."""
-    say("adjoint vs dual", nsteps, "contact" if contact else "", law)
-    col, oprm, gprm, S, ctx = start(olib, gpu, contact=contact, law=law)
+    (Eqs. 91-93, friction branch frozen); with the power law of Eq. 45; and
+    with a horizon of 3.6 spacings, whose families (up to ~190 members) are
+    wider than the adjoint bond kernel's 128 threads."""
+    say("adjoint vs dual", nsteps, "contact" if contact else "", law, delta_dx)
+    col, oprm, gprm, S, ctx = start(olib, gpu, contact=contact, law=law, delta_dx=delta_dx,
+                                    dims=(8, 8, 10) if delta_dx else (6, 6, 8))
     assert (gprm.b1, gprm.b2) == ((0.1, 1.02) if law == "power" else (0.0, 1.0))
     n = col["n"]
     rng = np.random.default_rng(11)

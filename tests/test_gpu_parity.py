@@ -679,3 +679,37 @@ def test_nonlinear_apparent_preconsolidation(olib, gpu, precision):
     assert st["n_plastic"] > 0 and rep["n_plastic"] > 0
     tol = 1e-10 if precision == "fp64" else 1e-4
     compare_states(G.to_arrays(), S, tol, fields=("u", "v", "sig", "pc", "J"), label=f"Eq. 45 {precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_wide_families(olib, gpu, precision):
+    """A horizon of 3.6 spacings: families of up to 194 members, wider than
+    the bond kernel's 128 threads, so lanes take a second bond (their sums
+    carried as wave totals) and FP64 pass 2 runs one lane per member.  20
+    plastic steps against the oracle: FP64 within 1e-10 with equal bond
+    update, triple and plastic counts, mixed within 1e-4."""
+    say("wide families", precision)
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=2, dims=(10, 10, 12))
+    col["params"]["delta"] = 3.6 * inputs.DX
+    oprm = olib.make_params(col["params"])
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    v = inputs.random_velocity(col["n"], 102, 0.3)
+    v[col["fixed"] == 1] = 0.0
+    S["v"][:] = v
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    gprm = gpu.make_params(olib.params_dict(oprm))
+    if precision == "mixed":
+        gprm.precision = gpu.ULPPM_MIXED
+    ctx = gpu.Context(col["n"], max_family=256)
+    G = gpu.DeviceState.from_arrays(S)
+    rc, E, st = olib.step(S, oprm, 20)
+    assert rc == 0
+    rep = ctx.step(G, gprm, 20)
+    say("max family", rep["max_family"], "plastic", st["n_plastic"], rep["n_plastic"])
+    assert rep["max_family"] > 128 and st["n_plastic"] > 0
+    if precision == "fp64":
+        # counts summed over the 20 steps on both sides
+        assert rep["n_bond_updates"] == st["n_bonds"] and rep["n_triples"] == st["n_triples"]
+        assert rep["n_plastic"] == st["n_plastic"]
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    compare_states(G.to_arrays(), S, tol, fields=("u", "v", "sig", "pc", "J", "a"), label=f"wide {precision}")
