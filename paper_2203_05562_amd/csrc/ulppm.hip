@@ -3190,14 +3190,19 @@ __global__ __launch_bounds__(256) void k_adj_point2(int64_t n, const int64_t* __
   }
 }
 
-__global__ void k_adj_theta(const double* __restrict__ part, int64_t nb, double* __restrict__ th) {
-  __shared__ double s[4][256];
+// Sum of the per-block parameter partials (4 per block) in a fixed order:
+// 1024 threads, each folding every 1024th block four at a time, then a tree.
+constexpr int kThetaThreads = 1024;
+__global__ __launch_bounds__(kThetaThreads) void k_adj_theta(const double* __restrict__ part, int64_t nb,
+                                                            double* __restrict__ th) {
+  __shared__ double s[4][kThetaThreads];
   double a[4] = {0, 0, 0, 0};
-  for (int64_t b = threadIdx.x; b < nb; b += 256)
+#pragma unroll 4
+  for (int64_t b = threadIdx.x; b < nb; b += kThetaThreads)
     for (int k = 0; k < 4; ++k) a[k] += part[4 * b + k];
   for (int k = 0; k < 4; ++k) s[k][threadIdx.x] = a[k];
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = kThetaThreads / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o)
       for (int k = 0; k < 4; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + o];
     __syncthreads();
@@ -3448,16 +3453,21 @@ __global__ void k_dtcrit(int64_t n, const int64_t* __restrict__ row, const int32
 }
 
 // Folds the counter stripes: sums, except the maxima.
-__global__ void k_reduce_counters(const unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ out) {
-  const int k = threadIdx.x;
-  if (k >= C_NCOUNT) return;
-  unsigned long long a = 0;
+// One wave per counter: each lane folds every 64th stripe, then the wave.
+__global__ __launch_bounds__(C_NCOUNT * kWave) void k_reduce_counters(const unsigned long long* __restrict__ ctr,
+                                                                     unsigned long long* __restrict__ out) {
+  const int k = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const bool is_max = k == C_MAXNEWTON || k == C_MAXFAM;
-  for (int t = 0; t < kStripes; ++t) {
+  unsigned long long a = 0;
+  for (int t = lane; t < kStripes; t += kWave) {
     const unsigned long long v = ctr[k * kStripes + t];
     a = is_max ? (a > v ? a : v) : a + v;
   }
-  out[k] = a;
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(a, off);
+    a = is_max ? (a > o ? a : o) : a + o;
+  }
+  if (lane == 0) out[k] = a;
 }
 
 __global__ void k_export_rows(int64_t n, const int64_t* __restrict__ row, int64_t* __restrict__ out) {
@@ -3889,7 +3899,7 @@ int gather_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int
 }
 
 int read_counters(ulppm_ctx* ctx) {
-  k_reduce_counters<<<1, 64, 0, ctx->stream>>>(ctx->ctr, ctx->ctr_sum);
+  k_reduce_counters<<<1, C_NCOUNT * kWave, 0, ctx->stream>>>(ctx->ctr, ctx->ctr_sum);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->ctr_sum, sizeof(ctx->h_ctr), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -4622,7 +4632,7 @@ int ulppm_adjoint_init(ulppm_ctx* ctx, const ulppm_state* S0, const ulppm_params
   const int nb = blocks_for(n, 256, 2048);
   double* part = ctx->adj + 45 * n;     // 4 (n + 8) doubles, nb <= n + 8
   k_adj_init<<<nb, 256, 0, ctx->stream>>>(*S0, *adj0, dev_params(p), ocr, s_bar, part);
-  k_adj_theta<<<1, 256, 0, ctx->stream>>>(part, (int64_t)nb, theta_bar);
+  k_adj_theta<<<1, kThetaThreads, 0, ctx->stream>>>(part, (int64_t)nb, theta_bar);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
@@ -4813,7 +4823,7 @@ static int adjoint_step_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_s
                                                       A.slot_x, A.slot_vh, A.slot_V, ctx->bond_cap, sigb, pcb, Jb,
                                                       phib, sb, *adj1, *adj0, p->dt, ctx->contact, p->plane != 0, fbar, ctx->x,
                                                       ctx->vh, ctx->vol_n);
-  k_adj_theta<<<1, 256, 0, ctx->stream>>>(thpart, (int64_t)grid, theta_bar);
+  k_adj_theta<<<1, kThetaThreads, 0, ctx->stream>>>(thpart, (int64_t)grid, theta_bar);
   HIPCHK(hipGetLastError());
   if ((rc = read_counters(ctx))) return rc;
   fill_report(ctx, n, rep, 1);
