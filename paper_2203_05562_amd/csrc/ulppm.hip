@@ -70,7 +70,7 @@ constexpr int64_t kPartGather = 10240;  // gather energy partials, 3 per block
 // Device counters, zeroed at the start of every API call.
 enum Ctr {
   C_DEGEN = 0, C_PLASTIC, C_MAXNEWTON, C_NOCONV, C_TESTS, C_TRIPLES, C_OVERFLOW,
-  C_NONFINITE, C_MAXFAM, C_BONDSUM, C_REBUILD, C_NCOUNT = 16
+  C_NONFINITE, C_MAXFAM, C_BONDSUM, C_REBUILD, C_ADJLDS, C_NCOUNT = 16
 };
 constexpr int kStripes = 256;       // each device counter is striped over this many addresses
 constexpr int kTimedSteps = 256;    // steps per call covered by phase timings
@@ -2358,6 +2358,7 @@ struct AdjArgs {
   double* slot_V;         // cap
   double* fwd;            // 8 x cap: the bond tail's forward solution per slot (sigma 6, p_c, branch)
   double* thpart;         // 4 per block
+  unsigned long long* ctr;  // striped counters (C_ADJLDS)
   // history on the bonds: start states of this step's bonds (8 per slot),
   // adjoints of their updated states (8 per slot), adjoints of the start
   // states (8 per slot, written)
@@ -2451,6 +2452,11 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
   const int64_t n = A.n;
   const int64_t b0 = A.row[i];
   const int nf = (int)(A.row[i + 1] - b0);
+  if (nf > mf) {                                  // the LDS was laid out for fewer members
+    if (tid == 0) ctr_add(A.ctr, C_ADJLDS, 1ull);
+    if (tid < 4) A.thpart[4 * blockIdx.x + tid] = 0.0;
+    return;                                       // uniform per block; the step reports an error
+  }
   const int nw = (mf + 63) / 64;
   // LDS per member: 3 quads, the 10-value record and the 16 sums (320 B with
   // two membership words), so that four workgroups fit a CU for families of
@@ -3509,6 +3515,7 @@ struct ulppm_ctx {
   hipStream_t stream = nullptr;
   int64_t cap_n = 0;
   int max_f = 0;
+  int seen_max_f = 0;       // largest family any call on this context has reported
   int64_t max_cells = 0;
   int64_t bond_cap = 0;
   // per point
@@ -3903,6 +3910,7 @@ int read_counters(ulppm_ctx* ctx) {
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->ctr_sum, sizeof(ctx->h_ctr), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->seen_max_f = std::max<int>(ctx->seen_max_f, (int)ctx->h_ctr[C_MAXFAM]);
   return ULPPM_OK;
 }
 
@@ -3911,6 +3919,8 @@ int counters_to_status(ulppm_ctx* ctx) {
     return fail(ctx, ULPPM_E_CAPACITY, "a family exceeded max_family=" + std::to_string(ctx->max_f) +
                                            " (largest " + std::to_string(ctx->h_ctr[C_MAXFAM]) + ")");
   if (ctx->h_ctr[C_NONFINITE]) return fail(ctx, ULPPM_E_NONFINITE, "non-finite positions, velocities or accelerations");
+  if (ctx->h_ctr[C_ADJLDS])
+    return fail(ctx, ULPPM_E_CAPACITY, "adjoint: a family larger than any the forward calls reported");
   if (ctx->h_ctr[C_NOCONV])
     return fail(ctx, ULPPM_E_NOCONV, std::to_string(ctx->h_ctr[C_NOCONV]) + " return-map Newton solves did not converge");
   return ULPPM_OK;
@@ -4771,12 +4781,20 @@ static int adjoint_step_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_s
   A.slot_V = ctx->adj_slot + 6 * ctx->bond_cap;
   A.fwd = ctx->adj_slot + 7 * ctx->bond_cap;
   A.thpart = thpart;
+  A.ctr = ctx->ctr;
   A.cap = ctx->bond_cap;
   A.dt = p->dt;
-  // LDS for the largest family of this step, not of the context
-  if ((rc = read_counters(ctx))) return rc;
-  if ((rc = counters_to_status(ctx))) return rc;
-  A.max_f = std::max<int>(1, (int)ctx->h_ctr[C_MAXFAM]);
+  // LDS for the largest family the forward calls on this context reported:
+  // the step's families are those of the forward step it reverses, so no
+  // wait for this step's counters is needed (a larger family would stop its
+  // block and fail the step).  Without such a report, the largest family of
+  // this step.
+  A.max_f = ctx->seen_max_f;
+  if (A.max_f <= 0 || A.max_f > ctx->max_f || adj_lds(A.max_f) > kMaxLds) {
+    if ((rc = read_counters(ctx))) return rc;
+    if ((rc = counters_to_status(ctx))) return rc;
+    A.max_f = std::max<int>(1, (int)ctx->h_ctr[C_MAXFAM]);
+  }
   const size_t lds = adj_lds(A.max_f);
   if (lds > kMaxLds)
     return fail(ctx, ULPPM_E_CAPACITY, "adjoint: a family of " + std::to_string(A.max_f) +
