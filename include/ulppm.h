@@ -343,6 +343,10 @@ int ulppm_adjoint_reserve(ulppm_ctx *ctx);
  * rep (host) may be NULL; it receives the step's family counts and, when the
  * step is re-run from state_n, the re-run's counters (with state_np1 given
  * only the families are rebuilt, and the return-map counters stay zero).
+ * The step's workgroup memory is laid out for the largest family that the
+ * forward calls on this context have reported (for this step's own largest
+ * family when none has); a family larger than that fails the step with
+ * ULPPM_E_CAPACITY, after which adj_n and theta_bar are not usable.
  * Errors: ULPPM_E_ARG, ULPPM_E_CAPACITY, ULPPM_E_NOCONV, ULPPM_E_HIP. */
 int ulppm_adjoint_step(ulppm_ctx *ctx, const ulppm_state *state_n, const ulppm_state *state_np1,
                        const ulppm_params *p, const ulppm_state *adj_np1, ulppm_state *adj_n,
