@@ -431,6 +431,37 @@ def test_adjoint_given_next_state_matches_rerun(olib, gpu):
     assert np.max(np.abs(out[1][1] - out[0][1])) <= 1e-12 * np.max(np.abs(out[0][1]))
 
 
+def test_adjoint_family_larger_than_forward_reported(olib, gpu):
+    """The adjoint step lays out its workgroup memory for the largest family
+    the calls on its context have reported.  Here the only report is of a
+    column stretched by 1.3 (smaller families), and the reverse of a step of
+    the unstretched column fails with E_CAPACITY (its blocks with larger
+    families stop before touching the layout); a fresh context, with no
+    report, sizes the step from the step's own families and succeeds."""
+    import torch
+    say("adjoint family bound")
+    col, oprm, gprm, S, ctx = start(olib, gpu)
+    n = col["n"]
+    ctxf = gpu.Context(n)
+    states = forward_states(ctxf, gprm, dev(gpu, S), 1)
+    Sx = olib.copy_state(S)
+    Sx["u"][:] = 0.3 * S["x0"] + 1.3 * S["u"]
+    row_x, _ = ctx.build_families(dev(gpu, Sx), gprm)
+    row_0, _ = ctxf.build_families(states[0], gprm)
+    fx = int(torch.diff(row_x).max())
+    f0 = int(torch.diff(row_0).max())
+    say("largest family stretched", fx, "unstretched", f0)
+    assert fx < f0
+    lam = dev(gpu, {**{k: np.zeros_like(S[k]) for k in FIELDS}, "x0": np.zeros((n, 3))})
+    th = torch.zeros(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu.UlppmError) as e:
+        ctx.adjoint_step(states[0], gprm, lam, lam, th, S1=states[1])
+    assert e.value.code == -2
+    fresh = gpu.Context(n)
+    fresh.adjoint_reserve()
+    fresh.adjoint_step(states[0], gprm, lam, lam, th, S1=states[1])
+
+
 def test_adjoint_C3_size_matches_gpu_finite_differences(gpu):
     """The 24 x 24 x 48 differentiable column (27,648 points), 30 steps with
     checkpoints every 7 from a seeded initial velocity: every gradient
