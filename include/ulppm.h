@@ -310,7 +310,7 @@ int ulppm_history_import(ulppm_ctx *ctx, int64_t n, const int64_t *row, const in
                          int64_t n_bonds);
 
 /* Allocate the scratch of ulppm_adjoint_step (a copy of one state, the point
- * adjoints and 15 doubles per bond slot) and, if ulppm_history_reserve has
+ * adjoints and 16 doubles per bond slot) and, if ulppm_history_reserve has
  * run, the 16 doubles per bond slot of ulppm_adjoint_step_bond_history.  Call
  * once, before the first adjoint step; the adjoint steps themselves never
  * allocate.  Errors: ULPPM_E_ARG, ULPPM_E_HIP. */

@@ -2353,9 +2353,12 @@ struct AdjArgs {
   double* Jb;             // n
   double* phib;           // n
   double* sb;             // n, this step's suction adjoint
-  double* slot_x;         // 3 x cap: contribution to xbar_k from point i at slot (i,k)
-  double* slot_vh;        // 3 x cap
-  double* slot_V;         // cap
+  // One 64-byte record per bond slot (i,k), the contributions of point i to
+  // the adjoints of point k: xbar_k (3), vhbar_k (3), Vbar_k (1), 0.  The
+  // three pointers address its fields; the record of slot s starts at 8 s.
+  double* slot_x;
+  double* slot_vh;
+  double* slot_V;
   double* fwd;            // 8 x cap: the bond tail's forward solution per slot (sigma 6, p_c, branch)
   double* thpart;         // 4 per block
   unsigned long long* ctr;  // striped counters (C_ADJLDS)
@@ -2655,8 +2658,8 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     for (int c = 0; c < 3; ++c) e += (a[3 * c] * zq.v[0] + a[3 * c + 1] * zq.v[1] + a[3 * c + 2] * zq.v[2]) * df[c];
     ownV += Vk * e;
     zb.v[3] = Vi * e;                               // to Vbar_k
-    for (int c = 0; c < 3; ++c) A.slot_x[c * A.cap + slot] = zb.v[c];
-    A.slot_V[slot] = zb.v[3];
+    for (int c = 0; c < 3; ++c) A.slot_x[8 * slot + c] = zb.v[c];
+    A.slot_V[8 * slot] = zb.v[3];
   };
   if (kBondWaves == 2 && nf <= 2 * kWave && (size_t)mf * sizeof(MRec<double>) >= 18 * kWave * sizeof(double)) {
     // Two members per lane (k = lane and lane + 64), the groups of rows split
@@ -2906,7 +2909,7 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
                      &acc_Srs, &wb, acc_th);
       }
       // w_j = V_j / Vh
-      A.slot_V[b0 + m] += wb / Vh + vh_hist / W;
+      A.slot_V[8 * (b0 + m)] += wb / Vh + vh_hist / W;
       acc_Vh -= wb * Vj / (Vh * Vh);
     }
     if constexpr (Hist) {
@@ -3099,18 +3102,18 @@ __global__ __launch_bounds__(kBondThreads, ULPPM_ADJ_MIN_WAVES) void k_adj_bond(
     const int64_t slot = b0 + m;
     double zbar[3], ybar[3];
     for (int c = 0; c < 3; ++c) {
-      zbar[c] = A.slot_x[c * A.cap + slot] + Vk * (Gz[c] + HTy[c]);
+      zbar[c] = A.slot_x[8 * slot + c] + Vk * (Gz[c] + HTy[c]);
       ybar[c] = Vk * Hz[c];
     }
-    const double Vbar = A.slot_V[slot] + 0.5 * (z[0] * Gz[0] + z[1] * Gz[1] + z[2] * Gz[2]) +
+    const double Vbar = A.slot_V[8 * slot] + 0.5 * (z[0] * Gz[0] + z[1] * Gz[1] + z[2] * Gz[2]) +
                         (y[0] * Hz[0] + y[1] * Hz[1] + y[2] * Hz[2]) + Vhb;
     for (int c = 0; c < 3; ++c) {
-      A.slot_x[c * A.cap + slot] = zbar[c];
-      A.slot_vh[c * A.cap + slot] = ybar[c];
+      A.slot_x[8 * slot + c] = zbar[c];
+      A.slot_vh[8 * slot + c] = ybar[c];
       ox[c] -= zbar[c];
       oy[c] -= ybar[c];
     }
-    A.slot_V[slot] = Vbar;
+    A.slot_V[8 * slot] = Vbar;
   }
   for (int c = 0; c < 3; ++c) {
     ox[c] = wave_sum(ox[c]);
@@ -3151,12 +3154,12 @@ __global__ __launch_bounds__(256) void k_adj_point2(int64_t n, const int64_t* __
   for (int64_t k = W.first; k < W.end; k += W.stride) {
     double ax[3] = {0, 0, 0}, av[3] = {0, 0, 0}, aV = 0.0;
     for (int64_t s = row[k] + lane; s < row[k + 1]; s += kWave) {
-      const int32_t r = rev[s];
+      const double* rec = slot_x + 8 * (int64_t)rev[s];   // the record of slot (k,j) for (j,k)
       for (int c = 0; c < 3; ++c) {
-        ax[c] += slot_x[c * cap + r];
-        av[c] += slot_vh[c * cap + r];
+        ax[c] += rec[c];
+        av[c] += rec[3 + c];
       }
-      aV += slot_V[r];
+      aV += rec[6];
     }
     for (int c = 0; c < 3; ++c) {
       ax[c] = wave_sum(ax[c]);
@@ -3568,7 +3571,7 @@ struct ulppm_ctx {
   int64_t hist_n = 0;         // points of the held history; 0: none
   // adjoint scratch (ulppm_adjoint_reserve)
   double* adj = nullptr;      // 24n forward copy + 21n point adjoints + 4(n+8) partials
-  double* adj_slot = nullptr; // 15 x bond_cap: adjoint slot contributions (7), bond tail forward solutions (8)
+  double* adj_slot = nullptr; // 16 x bond_cap: adjoint slot records (8), bond tail forward solutions (8)
   double* adj_hist = nullptr; // 16 x bond_cap: carried start states and their adjoints (history on the bonds)
   // phase timing events, [step][phase][start/stop]
   hipEvent_t ev[kTimedSteps][kPhases][2] = {};
@@ -4612,7 +4615,7 @@ int ulppm_adjoint_reserve(ulppm_ctx* ctx) {
   HIPCHK(hipMalloc((void**)&ctx->adj, pts));
   // per bond slot: the adjoint contributions (x 3, v_half 3, V 1) and the
   // bond tail's forward solution (8)
-  const hipError_t e = hipMalloc((void**)&ctx->adj_slot, sizeof(double) * 15 * (size_t)ctx->bond_cap);
+  const hipError_t e = hipMalloc((void**)&ctx->adj_slot, sizeof(double) * 16 * (size_t)ctx->bond_cap);
   if (e != hipSuccess) {
     (void)hipFree(ctx->adj);
     ctx->adj = nullptr;
@@ -4777,9 +4780,9 @@ static int adjoint_step_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_s
   A.own_x = own_x; A.own_vh = own_vh; A.own_V = own_V; A.sigb = sigb; A.pcb = pcb; A.Jb = Jb; A.phib = phib;
   A.sb = sb;
   A.slot_x = ctx->adj_slot;
-  A.slot_vh = ctx->adj_slot + 3 * ctx->bond_cap;
-  A.slot_V = ctx->adj_slot + 6 * ctx->bond_cap;
-  A.fwd = ctx->adj_slot + 7 * ctx->bond_cap;
+  A.slot_vh = ctx->adj_slot + 3;
+  A.slot_V = ctx->adj_slot + 6;
+  A.fwd = ctx->adj_slot + 8 * ctx->bond_cap;
   A.thpart = thpart;
   A.ctr = ctx->ctr;
   A.cap = ctx->bond_cap;
