@@ -210,6 +210,16 @@ __device__ __forceinline__ int64_t xcd_point(int64_t b, int64_t per) {
 struct XcdWalk {
   int64_t first, stride, end;
 };
+// The same walk over groups of lanes: gpb groups per block, g this thread's.
+__device__ __forceinline__ XcdWalk xcd_walk_groups(int64_t n, int gpb, int g) {
+  const int64_t per = (n + 7) / 8;
+  const int64_t x = blockIdx.x & 7, lb = blockIdx.x >> 3, nblk = gridDim.x >> 3;
+  XcdWalk w;
+  w.first = x * per + lb * gpb + g;
+  w.stride = nblk * gpb;
+  w.end = (x + 1) * per < n ? (x + 1) * per : n;
+  return w;
+}
 __device__ __forceinline__ XcdWalk xcd_walk(int64_t n, int wpb) {
   const int64_t per = (n + 7) / 8;
   const int64_t x = blockIdx.x & 7, lb = blockIdx.x >> 3, nblk = gridDim.x >> 3;
@@ -3301,13 +3311,34 @@ struct GatherArgs {
 // then a = f/M + g (Eq. 62), v = v_half + (dt/2) a (Eq. 63), energy partials.
 // TS: storage and accumulation type of the force gather (float in mixed
 // precision); the Newmark update is FP64.  Own: the bond kernel has summed
-// each point's own force states (G.fown), so only T_ji is gathered.
-template <class TS, bool Own>
+// each point's own force states (G.fown) and stored V_i T_ik, so only the
+// reverse records V_j T_ji are gathered.  LPP: lanes per point, a whole wave,
+// or one 16-lane row for families that fit a wave (four points per wave, so
+// that the lanes are not left idle by families of a few dozen bonds).
+template <class TS, bool Own, int LPP>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
+  static_assert(LPP == kWave || LPP == 16, "a point per wave or per 16-lane row");
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int sub = lane & (LPP - 1);                 // lane within the point's group
   const Quad<TS>* T4 = reinterpret_cast<const Quad<TS>*>(G.T);
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-  const XcdWalk W = xcd_walk(G.n, 4);
+  // the sum over the point's group of lanes, left in every lane of the group
+  auto group_sum = [](auto v) {
+    if constexpr (LPP == kWave) {
+      return wave_sum(v);
+    } else if constexpr (sizeof(v) == 8) {
+      v += dpp_d<kDppXor1, 0xF>(v);
+      v += dpp_d<kDppXor2, 0xF>(v);
+      v += dpp_d<kDppHalfMirror, 0xF>(v);
+      return v + dpp_d<kDppMirror, 0xF>(v);
+    } else {
+      v += dpp_f<kDppXor1, 0xF>(v);
+      v += dpp_f<kDppXor2, 0xF>(v);
+      v += dpp_f<kDppHalfMirror, 0xF>(v);
+      return v + dpp_f<kDppMirror, 0xF>(v);
+    }
+  };
+  const XcdWalk W = xcd_walk_groups(G.n, 256 / LPP, threadIdx.x / LPP);
   for (int64_t i = W.first; i < W.end; i += W.stride) {
     const int64_t b0 = G.row[i], b1 = G.row[i + 1];
     TS f0 = 0, f1 = 0, f2 = 0;
@@ -3316,15 +3347,15 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
       f0 = (TS)G.fown[i];
       f1 = (TS)G.fown[G.n + i];
       f2 = (TS)G.fown[2 * G.n + i];
-      if (lane != 0) f0 = f1 = f2 = (TS)0;          // added once by the wave sum
-      for (int64_t s = b0 + lane; s < b1; s += kWave) {
+      if (sub != 0) f0 = f1 = f2 = (TS)0;           // added once by the group sum
+      for (int64_t s = b0 + sub; s < b1; s += LPP) {
         const Quad<TS> tr = T4[G.rev[s]];             // V_j T_ji, scaled by point j
         f0 -= tr.v[0];
         f1 -= tr.v[1];
         f2 -= tr.v[2];
       }
     } else {
-      for (int64_t s = b0 + lane; s < b1; s += kWave) {
+      for (int64_t s = b0 + sub; s < b1; s += LPP) {
         const int32_t j = G.col[s], r = G.rev[s];
         const TS wv = (TS)G.vol_n[j];
         const Quad<TS> ts = T4[s], tr = T4[r];
@@ -3333,18 +3364,20 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
         f2 += (ts.v[2] - tr.v[2]) * wv;
       }
     }
-    f0 = wave_sum(f0);
-    f1 = wave_sum(f1);
-    f2 = wave_sum(f2);
+    f0 = group_sum(f0);
+    f1 = group_sum(f1);
+    f2 = group_sum(f2);
     double fc[3] = {0.0, 0.0, 0.0};
-    if (G.c.on) {
-      contact_density(G.c, G.plane != 0, G.x[i], G.x[G.n + i], G.x[2 * G.n + i], G.vh[i], G.vh[G.n + i],
-                      G.vh[2 * G.n + i], lane, fc);
-      fc[0] = wave_sum(fc[0]);
-      fc[1] = wave_sum(fc[1]);
-      fc[2] = wave_sum(fc[2]);
+    if constexpr (LPP == kWave) {                   // the host runs contact with a wave per point
+      if (G.c.on) {
+        contact_density(G.c, G.plane != 0, G.x[i], G.x[G.n + i], G.x[2 * G.n + i], G.vh[i], G.vh[G.n + i],
+                        G.vh[2 * G.n + i], lane, fc);
+        fc[0] = wave_sum(fc[0]);
+        fc[1] = wave_sum(fc[1]);
+        fc[2] = wave_sum(fc[2]);
+      }
     }
-    if (lane == 0) {
+    if (sub == 0) {
       const double Vi = G.vol_n[i];
       const double f[3] = {(double)f0 * Vi + Vi * fc[0], (double)f1 * Vi + Vi * fc[1],
                            (double)f2 * Vi + Vi * fc[2]};
@@ -3376,6 +3409,11 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs G) {
     }
   }
   if (G.mode == G_STEP) {
+    if constexpr (LPP != kWave) {                   // the groups' partials
+      e0 = wave_sum(e0);
+      e1 = wave_sum(e1);
+      e2 = wave_sum(e2);
+    }
     __shared__ double r[3][4];
     if (lane == 0) { r[0][wid] = e0; r[1][wid] = e1; r[2][wid] = e2; }
     __syncthreads();
@@ -3897,13 +3935,19 @@ int gather_pass(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, int
   G.fown = own_sums(ctx, p) ? ctx->fown : nullptr;
   const unsigned grid = walk_grid(n);
   if (mode == G_STEP && (int64_t)grid * 3 + kPartGather > ctx->part_cap) return fail(ctx, ULPPM_E_ARG, "partials too small");
-  if (mixed)
-    k_gather<float, false><<<grid, 256, 0, ctx->stream>>>(G);
+  // families that fit a wave: a 16-lane row per point (no contact: its site
+  // loop runs over a wave's lanes); the own sums come only with larger ones
+  const bool rows = ctx->max_f <= kWave && !G.c.on;
+  if (mixed && rows)
+    k_gather<float, false, 16><<<grid, 256, 0, ctx->stream>>>(G);
+  else if (mixed)
+    k_gather<float, false, kWave><<<grid, 256, 0, ctx->stream>>>(G);
+  else if (G.fown)
+    k_gather<double, true, kWave><<<grid, 256, 0, ctx->stream>>>(G);
+  else if (rows)
+    k_gather<double, false, 16><<<grid, 256, 0, ctx->stream>>>(G);
   else
-    if (G.fown)
-      k_gather<double, true><<<grid, 256, 0, ctx->stream>>>(G);
-    else
-      k_gather<double, false><<<grid, 256, 0, ctx->stream>>>(G);
+    k_gather<double, false, kWave><<<grid, 256, 0, ctx->stream>>>(G);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
