@@ -680,12 +680,18 @@ __global__ void k_check_skin(const double* __restrict__ x, const double* __restr
 // Family of every point in the current configuration (Eq. 1): one wave per
 // point filters its candidate row with the exact predicate; the ballot
 // prefix gives each member its slot in the row, so rows stay ascending.
+// LPP: lanes per point, a whole wave or one 16-lane row (four points per
+// wave, for candidate lists of a few dozen).
+template <int LPP>
 __global__ __launch_bounds__(256) void k_filter(const double* __restrict__ xv, int64_t n, int max_c, int max_f,
                                                 const int32_t* __restrict__ cand, const int32_t* __restrict__ ccnt,
                                                 double d2, int32_t* __restrict__ posmap, int32_t* __restrict__ cnt,
                                                 unsigned long long* __restrict__ ctr) {
+  static_assert(LPP == kWave || LPP == 16, "a point per wave or per 16-lane row");
   const int lane = threadIdx.x & (kWave - 1);
-  const XcdWalk W = xcd_walk(n, 4);
+  const int sub = lane & (LPP - 1), sh = lane & ~(LPP - 1);     // lane in the group, the group's first bit
+  const unsigned long long gmask = LPP == kWave ? ~0ull : 0xFFFFull << sh;
+  const XcdWalk W = xcd_walk_groups(n, 256 / LPP, threadIdx.x / LPP);
   int wmax = 0;
   const double4* P4 = reinterpret_cast<const double4*>(xv);     // packed records: x, y, z, V first
   for (int64_t i = W.first; i < W.end; i += W.stride) {
@@ -693,43 +699,45 @@ __global__ __launch_bounds__(256) void k_filter(const double* __restrict__ xv, i
     const double xi = pi.x, yi = pi.y, zi = pi.z;
     const int nc = ccnt[i];
     int count = 0;
-    for (int base = 0; base < nc; base += kWave) {
-      const int c = base + lane;
+    for (int base = 0; base < nc; base += LPP) {
+      const int c = base + sub;
       bool hit = false;
       if (c < nc) {
         const int32_t j = cand[i * (int64_t)max_c + c];
         const double4 pj = P4[2 * (int64_t)j];                     // one 32-byte read per candidate
         hit = within(xi, yi, zi, pj.x, pj.y, pj.z, d2);
       }
-      const unsigned long long mask = __ballot(hit);
+      const unsigned long long mask = __ballot(hit) & gmask;     // this group's hits
       const int off = __popcll(mask & ((1ull << lane) - 1ull));
       if (c < nc) posmap[i * (int64_t)max_c + c] = hit ? count + off : -1;
       count += __popcll(mask);
     }
-    if (lane == 0) {
+    if (sub == 0) {
       cnt[i] = count < max_f ? count : max_f;
       if (count > max_f) ctr_add(ctr, C_OVERFLOW, 1ull);
     }
     wmax = wmax > count ? wmax : count;
   }
+  wmax = wave_max_i(wmax);
   if (lane == 0 && wmax > 0) ctr_max(ctr, C_MAXFAM, (unsigned long long)wmax);
 }
 
 // One wave per point, lanes over its candidate slots: for every member, the
 // CSR column and the reverse-bond slot rev[(i,j)] = slot of (j,i), read
 // through the reverse candidate index (no search).
+template <int LPP>
 __global__ __launch_bounds__(256) void k_compact(int64_t n, int max_c, int max_f, const int32_t* __restrict__ cand,
                                                  const int32_t* __restrict__ ccnt, const int32_t* __restrict__ crev,
                                                  const int32_t* __restrict__ posmap, const int64_t* __restrict__ row,
                                                  int32_t* __restrict__ col, int32_t* __restrict__ rev,
                                                  unsigned long long* __restrict__ ctr) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const XcdWalk W = xcd_walk(n, 4);
+  const int sub = threadIdx.x & (LPP - 1);
+  const XcdWalk W = xcd_walk_groups(n, 256 / LPP, threadIdx.x / LPP);
   for (int64_t i = W.first; i < W.end; i += W.stride) {
     const int nc = ccnt[i];
     const int64_t r0 = row[i];
     const int64_t e0 = i * (int64_t)max_c;
-    for (int c = lane; c < nc; c += kWave) {
+    for (int c = sub; c < nc; c += LPP) {
       const int pm = posmap[e0 + c];
       if (pm < 0 || pm >= max_f) continue;
       const int64_t s = r0 + pm;
@@ -3760,13 +3768,26 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
   HIPCHK(hipGetLastError());
   // the packed point records carry the positions the filter reads
   k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
-  k_filter<<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->xv, n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
-                                                   delta * delta, ctx->posmap, ctx->cnt, ctx->ctr);
+  // candidate lists of a few dozen (families that fit a wave): a 16-lane row
+  // per point (P1: 2.94 -> 2.85 ms per step; with C1's ~137 candidates a
+  // whole wave per point is as fast)
+  const bool rows = ctx->max_f <= kWave;
+  if (rows)
+    k_filter<16><<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->xv, n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
+                                                        delta * delta, ctx->posmap, ctx->cnt, ctx->ctr);
+  else
+    k_filter<kWave><<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->xv, n, ctx->max_c, ctx->max_f, ctx->cand,
+                                                           ctx->ccnt, delta * delta, ctx->posmap, ctx->cnt, ctx->ctr);
   HIPCHK(hipGetLastError());
   rc2 = scan_counts(ctx, ctx->cnt, n, ctx->row);
   if (rc2) return rc2;
-  k_compact<<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt, ctx->crev,
-                                                    ctx->posmap, ctx->row, ctx->col, ctx->rev, ctx->ctr);
+  if (rows)
+    k_compact<16><<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt, ctx->crev,
+                                                         ctx->posmap, ctx->row, ctx->col, ctx->rev, ctx->ctr);
+  else
+    k_compact<kWave><<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
+                                                            ctx->crev, ctx->posmap, ctx->row, ctx->col, ctx->rev,
+                                                            ctx->ctr);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
