@@ -162,6 +162,7 @@ class DeviceState:
 
     def _bind(self, mut, ro, fixed):
         self.mut, self.ro = mut, ro
+        self._cs = None                     # the C view of the fields, built once (they never move)
         self.t: Dict[str, "torch.Tensor"] = {}
         for block, rows in ((mut, _MUT), (ro, _RO)):
             r0 = 0
@@ -211,6 +212,13 @@ class DeviceState:
         return S
 
     def cstruct(self) -> State:
+        """The ulppm_state of these fields (a copy of one built at the first
+        call: a call per C entry point adds no per-field pointer casts)."""
+        if self._cs is None:
+            self._cs = self._build_cstruct()
+        return State.from_buffer_copy(self._cs)
+
+    def _build_cstruct(self) -> State:
         s = State()
         s.n = self.n
         for k in VEC:
