@@ -1246,7 +1246,7 @@ struct BondArgs {
   double* hist;           // history on the bonds: 8 per bond (sigma, p_c, 0), written; or null
   const double* hist_old; // the bond states of the previous step (8 per bond)
   const int64_t* hmap;    // per bond: its slot in hist_old, or -1 (a new bond starts from its point)
-  double* fown;           // 3n: sum_k T_ik V_k of each point's own force states (FP64 conjugate); or null
+  double* fown;           // 3n: sum_k T_ik V_k of each point's own force states (FP64); or null
   double dt_inc;
   int max_f;
   unsigned long long* ctr;
@@ -2023,9 +2023,22 @@ void k_bond_mx(BondArgs A, DevParams P) {
       const double zx = kF64 ? sR[8 * (size_t)m] - xi0 : (double)sR[8 * (size_t)m];
       const double zy = kF64 ? sR[8 * (size_t)m + 1] - xi1 : (double)sR[8 * (size_t)m + 1];
       const double zz = kF64 ? sR[8 * (size_t)m + 2] - xi2 : (double)sR[8 * (size_t)m + 2];
-      T4[slot] = Quad<TS>{{(TS)(varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz)),
-                           (TS)(varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz)),
-                           (TS)(varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz)), (TS)0}};
+      const double t0 = varpi * (SK[0] * zx + SK[1] * zy + SK[2] * zz),
+                   t1 = varpi * (SK[3] * zx + SK[4] * zy + SK[5] * zz),
+                   t2 = varpi * (SK[6] * zx + SK[7] * zy + SK[8] * zz);
+      if constexpr (kF64) {
+        // With the own sums kept, the record holds V_i T_ij (as in the
+        // conjugate path) and the bond's row, no longer read, T_ij V_j: the
+        // lane sums its rows after the last bond, so that nothing is carried
+        // through the return maps of its further bonds.
+        const double sc = A.fown ? A.vol_n[i] : 1.0;
+        T4[slot] = Quad<TS>{{(TS)(sc * t0), (TS)(sc * t1), (TS)(sc * t2), (TS)0}};
+        kn[0] = t0 * Vj;
+        kn[1] = t1 * Vj;
+        kn[2] = t2 * Vj;
+      } else {
+        T4[slot] = Quad<TS>{{(TS)t0, (TS)t1, (TS)t2, (TS)0}};
+      }
     } else {
       const double wj = Vj * iVh;
 #pragma unroll
@@ -2069,6 +2082,14 @@ void k_bond_mx(BondArgs A, DevParams P) {
     }
   }
   double own[3] = {0.0, 0.0, 0.0};
+  if constexpr (kF64) if (P.force_mode == ULPPM_FORCE_EQ51 && A.fown) {
+    // rows of the lane's own bonds (a degenerate bond's row reads zero)
+    for (int m = tid; m < nf; m += kBondThreads) {
+      own[0] += sKN[16 * (size_t)m];
+      own[1] += sKN[16 * (size_t)m + 1];
+      own[2] += sKN[16 * (size_t)m + 2];
+    }
+  }
   if constexpr (kF64) if (P.force_mode == ULPPM_FORCE_CONJUGATE) {
     // ---- pass 2 in FP64 on the VALU: A_k = sum_j B_kj M_j, streaming the
     // rows M_j of the (symmetric) membership matrix in groups of four.  FP64
@@ -3793,11 +3814,12 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
 }
 
 // Whether the bond kernel sums each point's own force states for the gather:
-// the FP64 conjugate path with families of more than one wave (with small
+// the FP64 conjugate and Eq. 51 paths with families of more than one wave (with small
 // families the gather's per-point work is dominated by latency, not by the
 // records this saves).
 static bool own_sums(const ulppm_ctx* ctx, const ulppm_params* p) {
-  return p->precision != ULPPM_MIXED && p->force_mode == ULPPM_FORCE_CONJUGATE && ctx->max_f > kWave;
+  return p->precision != ULPPM_MIXED &&
+         (p->force_mode == ULPPM_FORCE_CONJUGATE || p->force_mode == ULPPM_FORCE_EQ51) && ctx->max_f > kWave;
 }
 
 size_t bond_lds(int max_f, bool mixed, int nt) {
