@@ -713,3 +713,34 @@ def test_wide_families(olib, gpu, precision):
         assert rep["n_plastic"] == st["n_plastic"]
     tol = 1e-10 if precision == "fp64" else 1e-4
     compare_states(G.to_arrays(), S, tol, fields=("u", "v", "sig", "pc", "J", "a"), label=f"wide {precision}")
+
+
+def test_wide_families_eq51(olib, gpu):
+    """Eq. 51 with families wider than the bond kernel's 128 threads: the
+    bond kernel sums each point's own force states (lanes taking a second
+    bond included) and stores V_i T_ij, which the export divides back.  The
+    force states of one evaluation within 1e-11, then 20 steps within
+    1e-10, against the oracle."""
+    say("wide families eq51")
+    col = inputs.make_column(inputs.CONFIGS["C0"], seed=2, dims=(10, 10, 12))
+    col["params"]["delta"] = 3.6 * inputs.DX
+    oprm = olib.make_params(col["params"])
+    oprm.force_mode = 1
+    S = olib.init_column(col, oprm, col["params"]["ocr"])
+    v = inputs.random_velocity(col["n"], 102, 0.3)
+    v[col["fixed"] == 1] = 0.0
+    S["v"][:] = v
+    oprm.dt = 0.5 * olib.dt_crit(S, oprm)
+    gprm = gpu.make_params(olib.params_dict(oprm))
+    ctx = gpu.Context(col["n"], max_family=256)
+    G = gpu.DeviceState.from_arrays(S)
+    out = olib.bond_fields(S, oprm, oprm.dt)
+    f, T, rep = ctx.forces(G, gprm, oprm.dt, want_T=True)
+    say("max family", rep["max_family"])
+    assert rep["max_family"] > 128
+    assert np.abs(T.cpu().numpy().T - out["T"]).max() <= 1e-11 * np.abs(out["T"]).max()
+    rc, E, st = olib.step(S, oprm, 20)
+    assert rc == 0
+    rep = ctx.step(G, gprm, 20)
+    assert rep["n_bond_updates"] == st["n_bonds"] and rep["n_plastic"] == st["n_plastic"]
+    compare_states(G.to_arrays(), S, 1e-10, fields=("u", "v", "sig", "pc", "J", "a"), label="wide eq51")
