@@ -2,7 +2,8 @@
 against ulppm_forces with a context of the same family capacity: two calls
 in a row on the one static scratch array, the second with a smaller input,
 each checked against the context's result at the FP64 bar (1e-11 relative;
-the kernels are the same, so the results are expected to be equal)."""
+the kernels are the same, so the results are expected to be equal): the
+conjugate force state in FP64 and mixed precision, Eq. 51 in FP64."""
 import sys
 
 import numpy as np
@@ -41,8 +42,12 @@ def test_forces_static_matches_forces():
     for dims, seed, vscale in (((8, 8, 16), 3, 0.3), ((6, 6, 9), 4, 0.1)):
         say("forces_static", dims, seed)
         G, prm, ctx = _state(gpu, dims, seed, vscale)
-        for precision in (gpu.ULPPM_FP64, gpu.ULPPM_MIXED):
+        # the conjugate force state in both precisions, and Eq. 51 in FP64,
+        # whose own force-state sums also sit in the scratch array
+        for precision, mode in ((gpu.ULPPM_FP64, gpu.ULPPM_FORCE_CONJUGATE), (gpu.ULPPM_MIXED, gpu.ULPPM_FORCE_CONJUGATE),
+                                (gpu.ULPPM_FP64, gpu.ULPPM_FORCE_EQ51)):
             prm.precision = precision
+            prm.force_mode = mode
             f_ref, T_ref, rep_ref = ctx.forces(G, prm, prm.dt, want_T=True)
             nb = rep_ref["n_bonds"]
             f = torch.full((3, G.n), np.nan, dtype=torch.float64, device="cuda")
@@ -55,7 +60,8 @@ def test_forces_static_matches_forces():
             Ta, Tr = T.cpu().numpy(), T_ref.cpu().numpy()
             ef = np.linalg.norm(fa - fr) / np.linalg.norm(fr)
             eT = np.abs(Ta - Tr).max() / np.abs(Tr).max()
-            say("  precision", precision, "f rel", ef, "T max rel", eT, "bonds", nb)
+            say("  precision", precision, "force mode", mode, "f rel", ef, "T max rel", eT, "bonds", nb,
+                "max family", rep_ref["max_family"])
             assert ef <= 1e-11 and eT <= 1e-11
         ctx.close()
 
