@@ -685,8 +685,8 @@ __global__ void k_check_skin(const double* __restrict__ x, const double* __restr
 template <int LPP>
 __global__ __launch_bounds__(256) void k_filter(const double* __restrict__ xv, int64_t n, int max_c, int max_f,
                                                 const int32_t* __restrict__ cand, const int32_t* __restrict__ ccnt,
-                                                double d2, int32_t* __restrict__ posmap, int32_t* __restrict__ cnt,
-                                                unsigned long long* __restrict__ ctr) {
+                                                double d2, unsigned long long* __restrict__ fbits,
+                                                int32_t* __restrict__ cnt, unsigned long long* __restrict__ ctr) {
   static_assert(LPP == kWave || LPP == 16, "a point per wave or per 16-lane row");
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (LPP - 1), sh = lane & ~(LPP - 1);     // lane in the group, the group's first bit
@@ -708,8 +708,14 @@ __global__ __launch_bounds__(256) void k_filter(const double* __restrict__ xv, i
         hit = within(xi, yi, zi, pj.x, pj.y, pj.z, d2);
       }
       const unsigned long long mask = __ballot(hit) & gmask;     // this group's hits
-      const int off = __popcll(mask & ((1ull << lane) - 1ull));
-      if (c < nc) posmap[i * (int64_t)max_c + c] = hit ? count + off : -1;
+      // membership bit of each candidate slot, 64 slots to a word (slots
+      // past the count read as clear)
+      if constexpr (LPP == kWave) {
+        if (lane == 0) fbits[i * (int64_t)(max_c / 64) + base / 64] = mask;
+      } else {
+        if (sub == 0)
+          reinterpret_cast<uint16_t*>(fbits)[i * (int64_t)(max_c / 16) + base / 16] = (uint16_t)(mask >> sh);
+      }
       count += __popcll(mask);
     }
     if (sub == 0) {
@@ -722,29 +728,44 @@ __global__ __launch_bounds__(256) void k_filter(const double* __restrict__ xv, i
   if (lane == 0 && wmax > 0) ctr_max(ctr, C_MAXFAM, (unsigned long long)wmax);
 }
 
+// Position in its point's family row of the member in candidate slot c (the
+// members in the slots before it), or -1 if the slot holds no member; b are
+// the point's membership words.
+__device__ __forceinline__ int member_pos(const unsigned long long* __restrict__ b, int c) {
+  const unsigned long long w = b[c >> 6];
+  if (!((w >> (c & 63)) & 1ull)) return -1;
+  int p = __popcll(w & ((1ull << (c & 63)) - 1ull));
+  for (int k = 0; k < (c >> 6); ++k) p += __popcll(b[k]);
+  return p;
+}
+
 // One wave per point, lanes over its candidate slots: for every member, the
-// CSR column and the reverse-bond slot rev[(i,j)] = slot of (j,i), read
-// through the reverse candidate index (no search).
+// CSR column and the reverse-bond slot rev[(i,j)] = slot of (j,i), found
+// through the reverse candidate index (no search) and the membership words
+// of j (a few bytes per point, which stay in L2, where a table of positions
+// per candidate slot would not).
 template <int LPP>
 __global__ __launch_bounds__(256) void k_compact(int64_t n, int max_c, int max_f, const int32_t* __restrict__ cand,
                                                  const int32_t* __restrict__ ccnt, const int32_t* __restrict__ crev,
-                                                 const int32_t* __restrict__ posmap, const int64_t* __restrict__ row,
-                                                 int32_t* __restrict__ col, int32_t* __restrict__ rev,
-                                                 unsigned long long* __restrict__ ctr) {
+                                                 const unsigned long long* __restrict__ fbits,
+                                                 const int64_t* __restrict__ row, int32_t* __restrict__ col,
+                                                 int32_t* __restrict__ rev, unsigned long long* __restrict__ ctr) {
   const int sub = threadIdx.x & (LPP - 1);
+  const int nw = max_c / 64;
   const XcdWalk W = xcd_walk_groups(n, 256 / LPP, threadIdx.x / LPP);
   for (int64_t i = W.first; i < W.end; i += W.stride) {
     const int nc = ccnt[i];
     const int64_t r0 = row[i];
     const int64_t e0 = i * (int64_t)max_c;
+    const unsigned long long* bi = fbits + i * nw;
     for (int c = sub; c < nc; c += LPP) {
-      const int pm = posmap[e0 + c];
+      const int pm = member_pos(bi, c);
       if (pm < 0 || pm >= max_f) continue;
       const int64_t s = r0 + pm;
       const int32_t j = cand[e0 + c];
       col[s] = j;
       const int cr = crev[e0 + c];
-      const int pr = cr >= 0 ? posmap[(int64_t)j * max_c + cr] : -1;
+      const int pr = cr >= 0 ? member_pos(fbits + (int64_t)j * nw, cr) : -1;
       // The exact predicate is symmetric, so (j,i) is a member of row j.
       const bool ok = pr >= 0 && pr < max_f;
       rev[s] = (int32_t)(ok ? row[j] + pr : s);
@@ -3595,7 +3616,7 @@ struct ulppm_ctx {
   double* pscr = nullptr;   // 12n point scratch for non-mutating passes
   double* pk = nullptr;     // 2n per-point values of the bond pass
   double* xv = nullptr;     // 8n packed x, V^n, v_half per point (bond-pass gathers)
-  double* fown = nullptr;   // 3n own-row force sums of the bond kernel (FP64 conjugate)
+  double* fown = nullptr;   // 3n own-row force sums of the bond kernel (FP64)
   int32_t* cellid = nullptr;
   int32_t* cnt = nullptr;
   int64_t* row = nullptr;   // n+1
@@ -3604,7 +3625,7 @@ struct ulppm_ctx {
   int32_t* cand = nullptr;    // n*max_c, rows ascending
   int32_t* ccnt = nullptr;    // n
   int32_t* crev = nullptr;    // n*max_c, position of i in the candidate row of j
-  int32_t* posmap = nullptr;  // n*max_c, slot of the candidate in the family row, or -1
+  unsigned long long* fbits = nullptr;  // n*max_c/64: membership bit of each candidate slot
   double* xref = nullptr;     // 3n positions at the last candidate build
   int32_t* gate = nullptr;    // 1: rebuild candidates in this step
   int64_t built_n = -1;       // point count and horizon of the last candidate build
@@ -3795,19 +3816,19 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
   const bool rows = ctx->max_f <= kWave;
   if (rows)
     k_filter<16><<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->xv, n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
-                                                        delta * delta, ctx->posmap, ctx->cnt, ctx->ctr);
+                                                        delta * delta, ctx->fbits, ctx->cnt, ctx->ctr);
   else
     k_filter<kWave><<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->xv, n, ctx->max_c, ctx->max_f, ctx->cand,
-                                                           ctx->ccnt, delta * delta, ctx->posmap, ctx->cnt, ctx->ctr);
+                                                           ctx->ccnt, delta * delta, ctx->fbits, ctx->cnt, ctx->ctr);
   HIPCHK(hipGetLastError());
   rc2 = scan_counts(ctx, ctx->cnt, n, ctx->row);
   if (rc2) return rc2;
   if (rows)
     k_compact<16><<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt, ctx->crev,
-                                                         ctx->posmap, ctx->row, ctx->col, ctx->rev, ctx->ctr);
+                                                         ctx->fbits, ctx->row, ctx->col, ctx->rev, ctx->ctr);
   else
     k_compact<kWave><<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
-                                                            ctx->crev, ctx->posmap, ctx->row, ctx->col, ctx->rev,
+                                                            ctx->crev, ctx->fbits, ctx->row, ctx->col, ctx->rev,
                                                             ctx->ctr);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
@@ -4249,7 +4270,7 @@ void context_buffers(ulppm_ctx* ctx, Alloc&& A) {
   A((void**)&ctx->cand, sizeof(int32_t) * n * ctx->max_c);
   A((void**)&ctx->ccnt, sizeof(int32_t) * n);
   A((void**)&ctx->crev, sizeof(int32_t) * n * ctx->max_c);
-  A((void**)&ctx->posmap, sizeof(int32_t) * n * ctx->max_c);
+  A((void**)&ctx->fbits, sizeof(unsigned long long) * n * (ctx->max_c / 64));
   A((void**)&ctx->xref, sizeof(double) * 3 * n);
   A((void**)&ctx->gate, sizeof(int32_t));
   A((void**)&ctx->ccount, sizeof(int32_t) * ctx->max_cells);
@@ -4330,7 +4351,7 @@ int ulppm_destroy(ulppm_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   void* ptrs[] = {ctx->x, ctx->vh, ctx->vol_n, ctx->pscr, ctx->pk, ctx->xv, ctx->fown, ctx->cellid, ctx->cnt, ctx->row, ctx->cand,
-                  ctx->ccnt, ctx->crev, ctx->posmap, ctx->xref, ctx->gate,
+                  ctx->ccnt, ctx->crev, ctx->fbits, ctx->xref, ctx->gate,
                   ctx->ccount, ctx->ccursor, ctx->cstart, ctx->cpts, ctx->col, ctx->rev, ctx->T,
                   ctx->part, ctx->scan_bsum, ctx->grid, ctx->ctr, ctx->ctr_sum, ctx->E, ctx->adj,
                   ctx->adj_slot, ctx->adj_hist, ctx->hist[0], ctx->hist[1], ctx->hist_row, ctx->hist_col,
@@ -4439,7 +4460,7 @@ int forces_impl(ulppm_ctx* ctx, const ulppm_state* S, const ulppm_params* p, dou
 constexpr int64_t kStaticPoints = ULPPM_STATIC_MAX_POINTS;
 constexpr int kStaticFamily = ULPPM_STATIC_MAX_FAMILY;
 constexpr size_t kStaticAlign = 256;
-constexpr size_t kStaticBytes = 16u << 20;   // 16 MiB (15.4 MiB used); checked against the buffer list at set-up
+constexpr size_t kStaticBytes = 16u << 20;   // 16 MiB (about 14 MiB used); checked against the buffer list at set-up
 constexpr int kStaticDevices = 64;
 
 }  // namespace
