@@ -677,20 +677,21 @@ __global__ void k_check_skin(const double* __restrict__ x, const double* __restr
   }
 }
 
-// Family of every point in the current configuration (Eq. 1): one wave per
-// point filters its candidate row with the exact predicate; the ballot
-// prefix gives each member its slot in the row, so rows stay ascending.
-// LPP: lanes per point, a whole wave or one 16-lane row (four points per
-// wave, for candidate lists of a few dozen).
+// Family of every point in the current configuration (Eq. 1): a group of
+// lanes per point filters its candidate row with the exact predicate; the
+// ballot bits, kept per candidate slot, give each member its slot in the row
+// (the members before it), so rows stay ascending.  LPP: lanes per point, a
+// whole wave, half a wave, or one 16-lane row (four points per wave, for
+// candidate lists of a few dozen).
 template <int LPP>
 __global__ __launch_bounds__(256) void k_filter(const double* __restrict__ xv, int64_t n, int max_c, int max_f,
                                                 const int32_t* __restrict__ cand, const int32_t* __restrict__ ccnt,
                                                 double d2, unsigned long long* __restrict__ fbits,
                                                 int32_t* __restrict__ cnt, unsigned long long* __restrict__ ctr) {
-  static_assert(LPP == kWave || LPP == 16, "a point per wave or per 16-lane row");
+  static_assert(LPP == kWave || LPP == 32 || LPP == 16, "a point per wave or per 32- or 16-lane group");
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (LPP - 1), sh = lane & ~(LPP - 1);     // lane in the group, the group's first bit
-  const unsigned long long gmask = LPP == kWave ? ~0ull : 0xFFFFull << sh;
+  const unsigned long long gmask = LPP == kWave ? ~0ull : ((1ull << LPP) - 1ull) << sh;
   const XcdWalk W = xcd_walk_groups(n, 256 / LPP, threadIdx.x / LPP);
   int wmax = 0;
   const double4* P4 = reinterpret_cast<const double4*>(xv);     // packed records: x, y, z, V first
@@ -712,6 +713,9 @@ __global__ __launch_bounds__(256) void k_filter(const double* __restrict__ xv, i
       // past the count read as clear)
       if constexpr (LPP == kWave) {
         if (lane == 0) fbits[i * (int64_t)(max_c / 64) + base / 64] = mask;
+      } else if constexpr (LPP == 32) {
+        if (sub == 0)
+          reinterpret_cast<uint32_t*>(fbits)[i * (int64_t)(max_c / 32) + base / 32] = (uint32_t)(mask >> sh);
       } else {
         if (sub == 0)
           reinterpret_cast<uint16_t*>(fbits)[i * (int64_t)(max_c / 16) + base / 16] = (uint16_t)(mask >> sh);
@@ -739,7 +743,7 @@ __device__ __forceinline__ int member_pos(const unsigned long long* __restrict__
   return p;
 }
 
-// One wave per point, lanes over its candidate slots: for every member, the
+// A group of LPP lanes per point over its candidate slots: for every member, the
 // CSR column and the reverse-bond slot rev[(i,j)] = slot of (j,i), found
 // through the reverse candidate index (no search) and the membership words
 // of j (a few bytes per point, which stay in L2, where a table of positions
@@ -3811,15 +3815,17 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
   // the packed point records carry the positions the filter reads
   k_pack<<<blocks_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, ctx->x, ctx->vh, ctx->vol_n, ctx->xv);
   // candidate lists of a few dozen (families that fit a wave): a 16-lane row
-  // per point (P1: 2.94 -> 2.85 ms per step; with C1's ~137 candidates a
-  // whole wave per point is as fast)
+  // per point (P1: 2.94 -> 2.85 ms per step against a wave); lists of about
+  // 150 (C1): half a wave per point, two points per wave, in both kernels
+  // (family phase 0.279 -> 0.246 ms against a wave, whose last pass over a
+  // list leaves most lanes idle; 16 lanes take too many passes)
   const bool rows = ctx->max_f <= kWave;
   if (rows)
     k_filter<16><<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->xv, n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
                                                         delta * delta, ctx->fbits, ctx->cnt, ctx->ctr);
   else
-    k_filter<kWave><<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->xv, n, ctx->max_c, ctx->max_f, ctx->cand,
-                                                           ctx->ccnt, delta * delta, ctx->fbits, ctx->cnt, ctx->ctr);
+    k_filter<32><<<walk_grid(n), 256, 0, ctx->stream>>>(ctx->xv, n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
+                                                        delta * delta, ctx->fbits, ctx->cnt, ctx->ctr);
   HIPCHK(hipGetLastError());
   rc2 = scan_counts(ctx, ctx->cnt, n, ctx->row);
   if (rc2) return rc2;
@@ -3827,9 +3833,8 @@ int build_families(ulppm_ctx* ctx, int64_t n, double delta, bool force) {
     k_compact<16><<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt, ctx->crev,
                                                          ctx->fbits, ctx->row, ctx->col, ctx->rev, ctx->ctr);
   else
-    k_compact<kWave><<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt,
-                                                            ctx->crev, ctx->fbits, ctx->row, ctx->col, ctx->rev,
-                                                            ctx->ctr);
+    k_compact<32><<<walk_grid(n), 256, 0, ctx->stream>>>(n, ctx->max_c, ctx->max_f, ctx->cand, ctx->ccnt, ctx->crev,
+                                                         ctx->fbits, ctx->row, ctx->col, ctx->rev, ctx->ctr);
   HIPCHK(hipGetLastError());
   return ULPPM_OK;
 }
